@@ -1,0 +1,404 @@
+"""FP64 CPU oracle: the frequency/time hybrid method, step by step.
+
+TEST INFRASTRUCTURE ONLY -- imported by tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library.
+
+Each function follows one step of Anderson, Bruno & Lyon, "High-order,
+dispersionless Fast-Hybrid wave equation solver, Part I" (arXiv 1807.02718),
+cited by section and equation label.  Bessel functions come from
+scipy.special, LU from LAPACK (scipy.linalg), the DFT is a direct O(M^2) sum
+and the sinc is numpy.sinc.  Nothing is blocked, fused or reordered beyond
+what the cited definitions state.
+
+Readings of passages the paper leaves open (all documented in the design doc):
+  * frequencies omega_j = j W / F, j = 1..F; DFT grid of 2F points on [-W, W)
+  * coupling eta = max(kappa, 1); wave speed c = 1 unless given
+  * incident field u_inc = f(t - p.r/c), so the boundary signal is a = -f
+  * V(r, 0) := 1 for plane-wave data (low-frequency limit), 0 for point sources
+  * window centers s_k = 1.5 H (k - 1) for all integers k
+  * active windows A(t) = {k : |t - s_k - tau0| <= pi / d_omega}
+  * extra recentering shift tau0 (tau0 = 0 is the paper's choice)
+  * sinc is the normalized sinc sin(pi x)/(pi x)
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+from scipy import special, linalg
+
+__all__ = [
+    "frequency_grid", "curve_length", "discretization_sizes", "coupling",
+    "geometry", "kress_weights", "kress_log_table", "assemble",
+    "rhs_plane_wave", "rhs_point_source", "solve_density", "field",
+    "field_full_grid", "eta_window", "window", "window_center",
+    "window_indices", "window_spectra", "fourier_coefficients",
+    "active_windows", "synthesize", "run", "curve_eval",
+]
+
+
+# ---------------------------------------------------------------------------
+# O1. Frequency grid, discretization sizes, coupling parameter
+# ---------------------------------------------------------------------------
+def frequency_grid(W: float, F: int, c: float = 1.0):
+    """Solve frequencies omega_j = j W/F (j = 1..F) and wavenumbers
+    kappa = omega/c (Sec. 2.1, linear dispersion relation kappa = omega/c;
+    the F frequencies feed the 2F-point DFT grid of Sec. 4.1.1, eq. fourier_approx)."""
+    dw = W / F
+    omega = dw * np.arange(1, F + 1, dtype=np.float64)
+    return omega, omega / c
+
+
+def curve_eval(curve, s):
+    """x(s), x'(s), x''(s) of a trigonometric-polynomial curve; shapes (len(s), 2)."""
+    s = np.asarray(s, dtype=np.float64)
+    d = np.arange(curve.degree + 1, dtype=np.float64)[:, None]
+    C, S = np.cos(d * s[None, :]), np.sin(d * s[None, :])
+    out = []
+    for cc, ss in ((curve.cx, curve.sx), (curve.cy, curve.sy)):
+        cc = np.asarray(cc, dtype=np.float64); ss = np.asarray(ss, dtype=np.float64)
+        x = cc @ C + ss @ S
+        dx = (cc * d[:, 0]) @ (-S) + (ss * d[:, 0]) @ C
+        ddx = -(cc * d[:, 0] ** 2) @ C - (ss * d[:, 0] ** 2) @ S
+        out.append((x, dx, ddx))
+    X = np.stack([out[0][0], out[1][0]], axis=1)
+    dX = np.stack([out[0][1], out[1][1]], axis=1)
+    ddX = np.stack([out[0][2], out[1][2]], axis=1)
+    return X, dX, ddX
+
+
+def curve_length(curve, n_quad: int = 4096) -> float:
+    """Perimeter by the trapezoidal rule on the periodic speed |x'(s)|."""
+    s = 2 * np.pi * np.arange(n_quad) / n_quad
+    _, dX, _ = curve_eval(curve, s)
+    return float(2 * np.pi / n_quad * np.sum(np.hypot(dX[:, 0], dX[:, 1])))
+
+
+def discretization_sizes(kappa, length, ppw, n_min, n_mult, n_cap):
+    """N_j = max(n_min, ceil(ppw * L * kappa / (2 pi) / n_mult) * n_mult), capped
+    at n_cap: a fixed number of points per wavelength over the curve."""
+    kappa = np.asarray(kappa, dtype=np.float64)
+    raw = ppw * length * kappa / (2 * np.pi)
+    N = np.ceil(raw / n_mult).astype(np.int64) * n_mult
+    return np.minimum(np.maximum(N, n_min), n_cap)
+
+
+def coupling(kappa):
+    """Coupling parameter eta of the combined field equation (eq. CFIE_direct);
+    any real nonzero value gives unique solvability; we take max(kappa, 1)."""
+    return np.maximum(np.asarray(kappa, dtype=np.float64), 1.0)
+
+
+# ---------------------------------------------------------------------------
+# O2. Boundary nodes (the set C of boundary points, Sec. 5)
+# ---------------------------------------------------------------------------
+def geometry(curve, N: int):
+    """Nodes t_i = 2 pi i / N on [0, 2 pi) with x, x', x'', |x'| and the outward
+    unit normal nu = (x2', -x1')/|x'| (counter-clockwise curve).
+
+    Rejects a clockwise or degenerate curve (signed area <= 0 or |x'| = 0)."""
+    t = 2 * np.pi * np.arange(N) / N
+    X, dX, ddX = curve_eval(curve, t)
+    speed = np.hypot(dX[:, 0], dX[:, 1])
+    if np.any(speed == 0.0) or not np.all(np.isfinite(X)):
+        raise ValueError("degenerate curve")
+    area = 0.5 * np.sum(X[:, 0] * dX[:, 1] - X[:, 1] * dX[:, 0]) * (2 * np.pi / N)
+    if area <= 0:
+        raise ValueError("curve must be counter-clockwise with positive area")
+    nu = np.stack([dX[:, 1], -dX[:, 0]], axis=1) / speed[:, None]
+    return dict(t=t, x=X, dx=dX, ddx=ddX, speed=speed, nu=nu)
+
+
+# ---------------------------------------------------------------------------
+# O3. Kress product-quadrature weights for the logarithmic kernel part
+#     (the 2D Nystrom method cited in Sec. 2.3: Colton & Kress, Sec. 3.5)
+# ---------------------------------------------------------------------------
+def kress_weights(N: int):
+    """R_l, l = 0..N-1 (N = 2n): weights of the rule
+        int_0^{2pi} log(4 sin^2((t_i - tau)/2)) f(tau) dtau ~= sum_j R_{(i-j) mod N} f(t_j),
+    R_l = -(2 pi / n) sum_{m=1}^{n-1} cos(m l pi / n) / m - (-1)^l pi / n^2."""
+    if N % 2:
+        raise ValueError("N must be even")
+    n = N // 2
+    l = np.arange(N)[:, None].astype(np.float64)
+    m = np.arange(1, n)[None, :].astype(np.float64)
+    R = -(2 * np.pi / n) * np.sum(np.cos(m * l * np.pi / n) / m, axis=1)
+    R -= ((-1.0) ** np.arange(N)) * np.pi / n ** 2
+    return R
+
+
+def kress_log_table(N: int):
+    """Lambda_l = log(4 sin^2(l pi / N)) for l = 1..N-1 (entry 0 unused, set 0)."""
+    l = np.arange(N)
+    out = np.zeros(N)
+    out[1:] = np.log(4 * np.sin(l[1:] * np.pi / N) ** 2)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O4/O5. Nystrom matrix and right-hand side of the direct CFIE (eq. CFIE_direct)
+# ---------------------------------------------------------------------------
+def assemble(geom, kappa: float, eta: float):
+    """A_ij for  (1/2) psi + K*psi - i eta S psi  on the parametrized nodes.
+
+    Kernels (parameter t at the target i, tau at the source j), with
+    G = (i/4) H0^(1)(kappa |x - y|) (Sec. 2.3), d = x_j - x_i, r = |d|:
+      M  = (i/4) H0(kappa r)                       (single layer)
+      L  = (i kappa / 4) H1(kappa r) (nu_i . d) / r  (normal derivative at target)
+    split as K = K1 log(4 sin^2((t-tau)/2)) + K2 with
+      M1 = -J0(kappa r)/(4 pi),  L1 = -(kappa/(4 pi)) J1(kappa r) (nu_i . d)/r,
+    and diagonal limits
+      M2_ii = i/4 - (gamma + log(kappa |x'_i| / 2))/(2 pi),  L1_ii = 0,
+      L2_ii = nu_i . x''_i / (4 pi |x'_i|^2).
+    A_ij = delta_ij / 2 + |x'_j| [ R_{i-j} (L1 - i eta M1) + (pi/n) (L2 - i eta M2) ].
+    """
+    x, nu, speed, ddx = geom["x"], geom["nu"], geom["speed"], geom["ddx"]
+    N = len(speed)
+    n = N // 2
+    R = kress_weights(N)
+    Lam = kress_log_table(N)
+    i_idx = np.arange(N)[:, None]
+    j_idx = np.arange(N)[None, :]
+    lidx = (i_idx - j_idx) % N
+    d = x[None, :, :] - x[:, None, :]                 # d[i, j] = x_j - x_i
+    r = np.hypot(d[..., 0], d[..., 1])
+    diag = np.eye(N, dtype=bool)
+    r_safe = np.where(diag, 1.0, r)
+    z = kappa * r_safe
+    J0, Y0, J1, Y1 = special.j0(z), special.y0(z), special.j1(z), special.y1(z)
+    nud = nu[:, None, 0] * d[..., 0] + nu[:, None, 1] * d[..., 1]   # nu_i . d_ij
+    logt = Lam[lidx]
+    M = 0.25j * (J0 + 1j * Y0)
+    M1 = -J0 / (4 * np.pi)
+    M2 = M - M1 * logt
+    L = 0.25j * kappa * (J1 + 1j * Y1) * nud / r_safe
+    L1 = -(kappa / (4 * np.pi)) * J1 * nud / r_safe
+    L2 = L - L1 * logt
+    euler = 0.57721566490153286061
+    M1[diag] = -1.0 / (4 * np.pi)
+    M2[diag] = 0.25j - (euler + np.log(kappa * speed / 2)) / (2 * np.pi)
+    L1[diag] = 0.0
+    L2[diag] = (nu[:, 0] * ddx[:, 0] + nu[:, 1] * ddx[:, 1]) / (4 * np.pi * speed ** 2)
+    K1 = L1 - 1j * eta * M1
+    K2 = L2 - 1j * eta * M2
+    A = (R[lidx] * K1 + (np.pi / n) * K2) * speed[None, :]
+    A[diag] += 0.5
+    return A
+
+
+def rhs_plane_wave(geom, kappa: float, eta: float, p):
+    """g = dB/dn - i eta B with B = exp(i kappa p.x) (eq. CFIE_direct with the
+    boundary data replaced by the plane wave, Sec. 3.2 / eq. psikslow_repr)."""
+    x, nu = geom["x"], geom["nu"]
+    phase = np.exp(1j * kappa * (x @ np.asarray(p, dtype=np.float64)))
+    return 1j * (kappa * (nu @ np.asarray(p, dtype=np.float64)) - eta) * phase
+
+
+def rhs_point_source(geom, kappa: float, eta: float, r0):
+    """g for B = (i/4) H0(kappa |x - r0|), a source r0 outside the closed domain."""
+    x, nu = geom["x"], geom["nu"]
+    dd = x - np.asarray(r0, dtype=np.float64)[None, :]
+    rho = np.hypot(dd[:, 0], dd[:, 1])
+    B = 0.25j * special.hankel1(0, kappa * rho)
+    dB = -0.25j * kappa * special.hankel1(1, kappa * rho) * np.sum(nu * dd, axis=1) / rho
+    return dB - 1j * eta * B
+
+
+# ---------------------------------------------------------------------------
+# O6. Dense solve (step F3)
+# ---------------------------------------------------------------------------
+def solve_density(A, g):
+    """psi = A^{-1} g by LAPACK LU with partial pivoting; returns (psi, relres)
+    with relres = ||g - A psi||_2 / ||g||_2."""
+    lu, piv = linalg.lu_factor(A, check_finite=True)
+    psi = linalg.lu_solve((lu, piv), g)
+    res = np.linalg.norm(g - A @ psi) / np.linalg.norm(g)
+    return psi, float(res)
+
+
+# ---------------------------------------------------------------------------
+# O7. Field evaluation (eq. freq_domain_repr / Ukslow_repr, step F5)
+# ---------------------------------------------------------------------------
+def field(geom, psi, kappa: float, obs):
+    """V(r) = int_Gamma psi G dsigma ~= (pi/n) sum_i (i/4) H0(kappa |r - x_i|) |x'_i| psi_i
+    (trapezoidal rule in the parameter, valid for r away from Gamma)."""
+    x, speed = geom["x"], geom["speed"]
+    N = len(speed)
+    obs = np.asarray(obs, dtype=np.float64)
+    dd = obs[:, None, :] - x[None, :, :]
+    rr = np.hypot(dd[..., 0], dd[..., 1])
+    z = kappa * rr
+    G = 0.25j * (special.j0(z) + 1j * special.y0(z))
+    return (2 * np.pi / N) * (G * speed[None, :]) @ psi
+
+
+def field_full_grid(V_pos, zero_value):
+    """Extend V(r, omega_j), j = 1..F, to the DFT grid omega_l = (l - F) d_omega,
+    l = 0..2F-1, on [-W, W): V(r, -omega) = conj V(r, omega) (real time signals)
+    and V(r, 0) = zero_value."""
+    Nr, F = V_pos.shape
+    out = np.zeros((Nr, 2 * F), dtype=np.complex128)
+    out[:, F] = zero_value
+    out[:, F + 1:] = V_pos[:, : F - 1]
+    out[:, :F] = np.conj(V_pos[:, ::-1])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O8. Partition of unity (Sec. 3.1, eq. window_func)
+# ---------------------------------------------------------------------------
+def eta_window(u):
+    """eta(u) = exp(2 e^{-1/u} / (u - 1)) on (0, 1); eta = 1 for u <= 0, 0 for u >= 1."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.where(u <= 0.0, 1.0, 0.0)
+    m = (u > 0.0) & (u < 1.0)
+    um = u[m]
+    out[m] = np.exp(2.0 * np.exp(-1.0 / um) / (um - 1.0))
+    return out
+
+
+def window(t, H: float):
+    """w(t): 1 - eta((t+H)/(H/2)) on [-H, -H/2], 1 on (-H/2, H/2),
+    eta((t - H/2)/(H/2)) on [H/2, H], 0 for |t| > H (eq. window_func)."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.zeros_like(t)
+    left = (t >= -H) & (t <= -H / 2)
+    mid = (t > -H / 2) & (t < H / 2)
+    right = (t >= H / 2) & (t <= H)
+    out[left] = 1.0 - eta_window((t[left] + H) / (H / 2))
+    out[mid] = 1.0
+    out[right] = eta_window((t[right] - H / 2) / (H / 2))
+    return out
+
+
+def window_center(k, H: float):
+    """s_k = 3 (k - 1) H / 2 (Sec. 3.1)."""
+    return 1.5 * H * (np.asarray(k, dtype=np.float64) - 1.0)
+
+
+def window_indices(t_lo: float, t_hi: float, H: float):
+    """All integers k whose support [s_k - H, s_k + H] meets [t_lo, t_hi]."""
+    k_lo = math.floor((t_lo - H) / (1.5 * H)) + 1
+    k_hi = math.ceil((t_hi + H) / (1.5 * H)) + 1
+    ks = np.arange(k_lo - 1, k_hi + 2)
+    s = window_center(ks, H)
+    keep = (s + H >= t_lo) & (s - H <= t_hi)
+    return ks[keep]
+
+
+# ---------------------------------------------------------------------------
+# O9. Windowed, recentered signal spectra (eq. Bkslow_eqn, steps F1-F2)
+# ---------------------------------------------------------------------------
+def window_spectra(signal, H: float, ks, omega_l):
+    """B_k^slow(omega_l) = int a_k(t + s_k) e^{i omega t} dt with a_k = w_k a and
+    a = -f (sound-soft data b = -u_inc), by the rectangle/trapezoidal rule on the
+    signal samples (the integrand vanishes with all derivatives at the ends)."""
+    t = signal.t
+    a = -np.asarray(signal.f, dtype=np.float64)
+    out = np.zeros((len(ks), len(omega_l)), dtype=np.complex128)
+    for i, k in enumerate(ks):
+        sk = window_center(k, H)
+        tau = t - sk
+        wk = window(tau, H)
+        sel = wk != 0.0
+        out[i] = signal.dt * (np.exp(1j * np.outer(omega_l, tau[sel])) @ (wk[sel] * a[sel]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O10. Fourier-series coefficients on [-W, W) (eq. fourier_approx, DFT case)
+# ---------------------------------------------------------------------------
+def fourier_coefficients(G, W: float):
+    """c_m, m = -F..F-1, of G(omega) ~= sum_m c_m e^{i pi m omega / W} from the
+    2F samples G(omega_l), omega_l = -W + l W/F: direct DFT sum
+    c_m = (1/2F) sum_l G_l e^{-i pi m omega_l / W}.  G has shape (..., 2F)."""
+    M = G.shape[-1]
+    F = M // 2
+    dw = W / F
+    omega_l = -W + dw * np.arange(M)
+    m = np.arange(-F, F)
+    E = np.exp(-1j * np.pi * np.outer(omega_l, m) / W)      # (2F, 2F)
+    return (G @ E) / M
+
+
+# ---------------------------------------------------------------------------
+# O11. Scaled-convolution synthesis and sum over windows (eqs. approx,
+#      discConv, ukW, uk_def, final_u; steps T1a, T2, T5)
+# ---------------------------------------------------------------------------
+def active_windows(t: float, ks, H: float, tau0: float, dw: float):
+    s = window_center(ks, H)
+    return np.abs(t - s - tau0) <= np.pi / dw
+
+
+def synthesize(V_full, Bslow, ks, H, tau0, W, times):
+    """u(r, t) = sum_{k in A(t)} u_k^{W,J}(r, t) with
+        u_k(r, t) = (1/2pi) int_{-W}^{W} B_k^slow(w) V(r, w) e^{-i w (t - s_k)} dw
+                  = Re (W/pi) sum_m c_{k,m}(r) sinc(W (t - s_k - tau0)/pi - m),
+    c_{k,m}(r) the Fourier coefficients of B_k^slow V e^{-i w tau0} on [-W, W).
+    Returns (u, max |Im|) where Im is the imaginary part before taking Re."""
+    Nr, M = V_full.shape
+    F = M // 2
+    dw = W / F
+    omega_l = -W + dw * np.arange(M)
+    m = np.arange(-F, F)
+    u = np.zeros((Nr, len(times)))
+    im_max = 0.0
+    shift = np.exp(-1j * omega_l * tau0)
+    for ik, k in enumerate(ks):
+        sk = window_center(k, H)
+        G = Bslow[ik][None, :] * V_full * shift[None, :]
+        c = fourier_coefficients(G, W)                        # (Nr, 2F)
+        act = np.abs(np.asarray(times) - sk - tau0) <= np.pi / dw
+        if not np.any(act):
+            continue
+        tt = np.asarray(times)[act]
+        S = np.sinc(W * (tt[None, :] - sk - tau0) / np.pi - m[:, None])   # (2F, nt)
+        uk = (W / np.pi) * (c @ S)
+        im_max = max(im_max, float(np.max(np.abs(uk.imag))) if uk.size else 0.0)
+        u[:, act] += uk.real
+    return u, im_max
+
+
+# ---------------------------------------------------------------------------
+# Whole pipeline (F1-F5, T0-T6)
+# ---------------------------------------------------------------------------
+def run(curve, W, F, N_rule, direction, signal, H, tau0, obs, times, c=1.0,
+        incidence="plane", r0=None, return_all=False):
+    """Scattered field u(r, t) on obs x times.  N_rule is an int (fixed N) or a
+    dict(ppw, n_min, n_mult, n_cap)."""
+    omega, kappa = frequency_grid(W, F, c)
+    if isinstance(N_rule, dict):
+        Ns = discretization_sizes(kappa, curve_length(curve), **N_rule)
+    else:
+        Ns = np.full(F, int(N_rule))
+    eta = coupling(kappa)
+    geoms = {}
+    psis, res = [], []
+    Vpos = np.zeros((len(obs), F), dtype=np.complex128)
+    for j in range(F):
+        N = int(Ns[j])
+        if N not in geoms:
+            geoms[N] = geometry(curve, N)
+        gm = geoms[N]
+        A = assemble(gm, kappa[j], eta[j])
+        if incidence == "plane":
+            g = rhs_plane_wave(gm, kappa[j], eta[j], direction)
+        else:
+            g = rhs_point_source(gm, kappa[j], eta[j], r0)
+        psi, rr = solve_density(A, g)
+        psis.append(psi); res.append(rr)
+        Vpos[:, j] = field(gm, psi, kappa[j], obs)
+    V_full = field_full_grid(Vpos, 1.0 if incidence == "plane" else 0.0)
+    dw = W / F
+    omega_l = -W + dw * np.arange(2 * F)
+    t = signal.t
+    ks = window_indices(t[0], t[-1], H)
+    act_any = np.zeros(len(ks), dtype=bool)
+    for tt in np.asarray(times):
+        act_any |= active_windows(tt, ks, H, tau0, dw)
+    ks = ks[act_any]
+    B = window_spectra(signal, H, ks, omega_l)
+    u, im_max = synthesize(V_full, B, ks, H, tau0, W, times)
+    if return_all:
+        return dict(u=u, im_max=im_max, psi=psis, res=res, Vpos=Vpos, V=V_full,
+                    ks=ks, B=B, Ns=Ns, kappa=kappa, eta=eta)
+    return u

@@ -1,0 +1,400 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each compares the oracle with a
+closed form, an identity, a library routine on a special case, a
+high-precision brute-force limit, or a number the paper prints
+(tests/golden/paper_parameters.json).  CPU only.
+"""
+import json
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle as O
+import workloads as Wk
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_parameters.json")))
+
+
+# --------------------------------------------------------------------------
+# P1. Bessel values used by the oracle (scipy) against 30-digit mpmath
+# --------------------------------------------------------------------------
+def test_bessel_values_against_mpmath():
+    mp.mp.dps = 30
+    zs = np.concatenate([np.geomspace(1e-6, 3e3, 60), [2.404825557695773, 3.8317059702075125, 0.8935769662791675]])
+    eps = np.finfo(float).eps
+    for z in zs:
+        # value error allowed: a few ulps plus the argument's own conditioning
+        # |f'(z)| z eps ~ sqrt(2 z / pi) eps for large z
+        cond = 4 * eps * np.sqrt(z) if z > 1 else 0.0
+        for nu, fj, fy in ((0, special.j0, special.y0), (1, special.j1, special.y1)):
+            ej = float(mp.besselj(nu, z)); ey = float(mp.bessely(nu, z))
+            assert abs(fj(z) - ej) <= 4e-15 * max(1.0, abs(ej)) + cond, (nu, z)
+            assert abs(fy(z) - ey) <= 4e-15 * max(1.0, abs(ey)) + cond, (nu, z)
+    # Wronskian J1 Y0 - J0 Y1 = 2/(pi z)
+    z = np.geomspace(1e-3, 2e3, 200)
+    w = special.j1(z) * special.y0(z) - special.j0(z) * special.y1(z)
+    assert np.allclose(w * np.pi * z / 2, 1.0, rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------------------------------
+# P2. Kress weights integrate log(4 sin^2((t-tau)/2)) e^{i m tau} exactly
+#     (log(4 sin^2(s/2)) = -2 sum_{m>=1} cos(m s)/m)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [8, 16, 64, 250])
+def test_kress_weight_moments(N):
+    n = N // 2
+    R = O.kress_weights(N)
+    t = 2 * np.pi * np.arange(N) / N
+    i = 3 % N
+    lidx = (i - np.arange(N)) % N
+    for m in list(range(-(n - 1), n)):
+        got = np.sum(R[lidx] * np.exp(1j * m * t))
+        exact = 0.0 if m == 0 else -(2 * np.pi / abs(m)) * np.exp(1j * m * t[i])
+        assert abs(got - exact) < 1e-12 * max(1, N / 16), (N, m)
+
+
+def test_kress_rule_on_smooth_function():
+    """Product rule applied to f(tau) = exp(cos tau) against adaptive mpmath
+    quadrature of the log-singular integral."""
+    mp.mp.dps = 25
+    N = 64
+    R = O.kress_weights(N)
+    t = 2 * np.pi * np.arange(N) / N
+    ti = t[5]
+    f = lambda tau: mp.e ** mp.cos(tau)
+    g = lambda tau: mp.log(4 * mp.sin((ti - tau) / 2) ** 2) * f(tau)
+    exact = mp.quad(g, [0, ti, 2 * mp.pi])
+    got = np.sum(R[(5 - np.arange(N)) % N] * np.exp(np.cos(t)))
+    assert abs(got - float(exact)) < 1e-13
+
+
+def test_kress_log_table_matches_geometry():
+    N = 32
+    lam = O.kress_log_table(N)
+    t = 2 * np.pi * np.arange(N) / N
+    # |e^{i t} - 1|^2 = 4 sin^2(t/2)
+    assert np.allclose(lam[1:], np.log(np.abs(np.exp(1j * t[1:]) - 1) ** 2), atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# P3/P4. Circle: circulant matrix with known eigenvalues; exact densities and
+#        fields from the Bessel series (jump relations + Jacobi-Anger)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kappa", [0.7, 5.5, 21.0])
+def test_circle_eigenvalues(kappa):
+    N = 96
+    eta = float(O.coupling(kappa))
+    gm = O.geometry(Wk.circle(1.0), N)
+    A = O.assemble(gm, kappa, eta)
+    # circulant: A_ij depends on (i - j) mod N only
+    for s in (1, 7):
+        assert np.allclose(A, np.roll(np.roll(A, s, 0), s, 1), atol=1e-13)
+    for m in (0, 1, 4, 9, 15):
+        v = np.exp(1j * m * gm["t"])
+        lam = (A @ v) / v
+        ex = (1j * np.pi / 2) * special.hankel1(m, kappa) * (kappa * special.jvp(m, kappa) - 1j * eta * special.jv(m, kappa))
+        assert np.max(np.abs(lam - ex)) < 1e-12, m
+
+
+def _circle_exact(R, kappa, thp, theta, robs=None, thobs=None, mmax=None):
+    mmax = mmax or int(kappa * max(R, 1) + 40)
+    ms = np.arange(-mmax, mmax + 1)
+    Hm = special.hankel1(ms, kappa * R)
+    psi = (-(2j / (np.pi * R)) * (1j ** ms)[None, :] * np.exp(1j * np.outer(theta - thp, ms)) / Hm[None, :]).sum(1)
+    if robs is None:
+        return psi
+    V = ((1j ** ms) * special.jv(ms, kappa * R) * special.hankel1(ms, kappa * robs[:, None]) / Hm
+         * np.exp(1j * np.outer(thobs - thp, ms))).sum(1)
+    return psi, V
+
+
+@pytest.mark.parametrize("R,kappa,N", [(1.0, 0.3, 64), (1.0, 6.0, 64), (1.7, 20.0, 256), (1.0, 55.0, 384)])
+def test_circle_density_and_field_exact(R, kappa, N):
+    thp = 0.4
+    p = (np.cos(thp), np.sin(thp))
+    eta = float(O.coupling(kappa))
+    gm = O.geometry(Wk.circle(R), N)
+    A = O.assemble(gm, kappa, eta)
+    g = O.rhs_plane_wave(gm, kappa, eta, p)
+    psi, res = O.solve_density(A, g)
+    assert res < 1e-13
+    obs = Wk.ring(16, 3.0 * R)
+    th = np.arctan2(obs[:, 1], obs[:, 0])
+    psi_ex, V_ex = _circle_exact(R, kappa, thp, gm["t"], np.full(16, 3.0 * R), th)
+    assert np.max(np.abs(psi - psi_ex)) / np.max(np.abs(psi_ex)) < 1e-12
+    V = O.field(gm, psi, kappa, obs)
+    assert np.max(np.abs(V - V_ex)) / np.max(np.abs(V_ex)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P5/P6. Density independent of eta; interior extinction on the kite
+# --------------------------------------------------------------------------
+def _inside_kite(pts):
+    s = np.linspace(0, 2 * np.pi, 4001)
+    X, _, _ = O.curve_eval(Wk.kite(), s)
+    ang = np.zeros(len(pts))
+    for q, pt in enumerate(pts):
+        d = X - pt
+        a = np.unwrap(np.arctan2(d[:, 1], d[:, 0]))
+        ang[q] = (a[-1] - a[0]) / (2 * np.pi)
+    return np.abs(ang - 1) < 1e-6
+
+
+KITE_INTERIOR = np.array([[-0.3, 0.2], [0.0, -0.5], [-0.8, 0.9], [0.2, 0.0], [-0.9, -0.6]])
+
+
+def test_kite_interior_points_are_inside():
+    assert np.all(_inside_kite(KITE_INTERIOR))
+
+
+@pytest.mark.parametrize("kappa", [1.5, 12.0])
+def test_density_independent_of_eta(kappa):
+    gm = O.geometry(Wk.kite(), 256)
+    p = (0.6, 0.8)
+    psis = []
+    for eta in (1.0, kappa, 3.3 * kappa):
+        A = O.assemble(gm, kappa, eta)
+        psis.append(O.solve_density(A, O.rhs_plane_wave(gm, kappa, eta, p))[0])
+    for q in psis[1:]:
+        assert np.max(np.abs(q - psis[0])) / np.max(np.abs(psis[0])) < 1e-12
+
+
+@pytest.mark.parametrize("kappa", [0.9, 15.0, 40.0])
+def test_interior_extinction_plane_wave(kappa):
+    N = 512 if kappa > 20 else 256
+    gm = O.geometry(Wk.kite(), N)
+    eta = float(O.coupling(kappa))
+    p = np.array([0.6, 0.8])
+    psi, _ = O.solve_density(O.assemble(gm, kappa, eta), O.rhs_plane_wave(gm, kappa, eta, p))
+    V = O.field(gm, psi, kappa, KITE_INTERIOR)
+    assert np.max(np.abs(V - np.exp(1j * kappa * KITE_INTERIOR @ p))) < 1e-11
+
+
+def test_interior_extinction_point_source():
+    kappa = 8.0
+    r0 = np.array([2.5, 1.0])
+    gm = O.geometry(Wk.kite(), 256)
+    eta = float(O.coupling(kappa))
+    psi, _ = O.solve_density(O.assemble(gm, kappa, eta), O.rhs_point_source(gm, kappa, eta, r0))
+    V = O.field(gm, psi, kappa, KITE_INTERIOR)
+    G = 0.25j * special.hankel1(0, kappa * np.hypot(*(KITE_INTERIOR - r0).T))
+    assert np.max(np.abs(V - G)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P13. Superalgebraic convergence in N (fixed frequency, exterior field)
+# --------------------------------------------------------------------------
+def test_convergence_in_N():
+    kappa = 10.0
+    eta = float(O.coupling(kappa))
+    obs = np.array(GOLDEN["convergence_experiment"]["obs"])[None, :]
+    p = np.array(GOLDEN["convergence_experiment"]["direction"]); p = p / np.linalg.norm(p)
+    vals = {}
+    for N in (64, 96, 128, 192, 384):
+        gm = O.geometry(Wk.kite(), N)
+        psi, _ = O.solve_density(O.assemble(gm, kappa, eta), O.rhs_plane_wave(gm, kappa, eta, p))
+        vals[N] = O.field(gm, psi, kappa, obs)[0]
+    err = [abs(vals[N] - vals[384]) for N in (64, 96, 128, 192)]
+    assert err[0] > err[1] > err[2] > err[3]
+    assert err[3] < 1e-12 and err[1] / err[3] > 1e4
+
+
+# --------------------------------------------------------------------------
+# P14. Diagonal limits against a 40-digit brute-force limit of the kernels
+# --------------------------------------------------------------------------
+def test_diagonal_limits_brute_force():
+    mp.mp.dps = 40
+    curve = Wk.kite()
+    N = 32
+    kappa, eta = 3.3, 3.3
+    gm = O.geometry(curve, N)
+    A = O.assemble(gm, kappa, eta)
+    R = O.kress_weights(N)
+    i = 5
+    ti = gm["t"][i]
+
+    def xpt(s):
+        d = [mp.mpf(k) for k in range(curve.degree + 1)]
+        x1 = sum(curve.cx[k] * mp.cos(d[k] * s) + curve.sx[k] * mp.sin(d[k] * s) for k in range(len(d)))
+        x2 = sum(curve.cy[k] * mp.cos(d[k] * s) + curve.sy[k] * mp.sin(d[k] * s) for k in range(len(d)))
+        return x1, x2
+
+    def dxpt(s):
+        d = [mp.mpf(k) for k in range(curve.degree + 1)]
+        x1 = sum(d[k] * (-curve.cx[k] * mp.sin(d[k] * s) + curve.sx[k] * mp.cos(d[k] * s)) for k in range(len(d)))
+        x2 = sum(d[k] * (-curve.cy[k] * mp.sin(d[k] * s) + curve.sy[k] * mp.cos(d[k] * s)) for k in range(len(d)))
+        return x1, x2
+
+    t0 = mp.mpf(ti)
+    xi = xpt(t0); dxi = dxpt(t0)
+    sp = mp.sqrt(dxi[0] ** 2 + dxi[1] ** 2)
+    nu = (dxi[1] / sp, -dxi[0] / sp)
+
+    def smooth_parts(tau):
+        y = xpt(tau)
+        d = (y[0] - xi[0], y[1] - xi[1])
+        r = mp.sqrt(d[0] ** 2 + d[1] ** 2)
+        z = kappa * r
+        H0 = mp.besselj(0, z) + 1j * mp.bessely(0, z)
+        H1 = mp.besselj(1, z) + 1j * mp.bessely(1, z)
+        lg = mp.log(4 * mp.sin((t0 - tau) / 2) ** 2)
+        M = 0.25j * H0
+        M1 = -mp.besselj(0, z) / (4 * mp.pi)
+        nd = nu[0] * d[0] + nu[1] * d[1]
+        L = 0.25j * kappa * H1 * nd / r
+        L1 = -(kappa / (4 * mp.pi)) * mp.besselj(1, z) * nd / r
+        return (L - L1 * lg) - 1j * eta * (M - M1 * lg), L1 - 1j * eta * M1
+
+    # Richardson-free: at 40 digits, offset 1e-15 gives the limit to ~1e-14
+    K2, K1 = smooth_parts(t0 + mp.mpf("1e-15"))
+    n = N // 2
+    diag = 0.5 + float(sp) * (R[0] * complex(K1) + (np.pi / n) * complex(K2))
+    assert abs(A[i, i] - diag) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P8. DFT + sinc scaled convolution against the exact transform of the
+#     paper's quadrature test function (Sec. 6.1)
+# --------------------------------------------------------------------------
+def test_synthesis_exact_transform():
+    g = GOLDEN["fourier_quadrature_demo"]
+    a, b = g["interval"]
+    W = b
+    F = 64
+    dw = W / F
+    wl = -W + dw * np.arange(2 * F)
+    G = np.exp(-g["gauss_coeff"] * wl ** 2) * np.exp(1j * g["modulation"] * wl)
+    assert abs(np.exp(-g["gauss_coeff"] * W ** 2)) < 10 * g["endpoint_magnitude_order"]
+    c = O.fourier_coefficients(G[None, :], W)[0]
+    t = np.linspace(-5, 25, 301)
+    m = np.arange(-F, F)
+    f = (W / np.pi) * (c[None, :] * np.sinc(W * t[:, None] / np.pi - m[None, :])).sum(1)
+    exact = np.exp(-(t - g["modulation"]) ** 2) / np.sqrt(np.pi)   # (1/2pi) * 2 sqrt(pi) e^{-(t-10)^2}
+    assert np.max(np.abs(f - exact)) < 1e-14
+
+
+def test_fourier_coefficients_match_fft():
+    rng = np.random.default_rng(7)
+    F, W = 32, 5.0
+    G = rng.standard_normal((3, 2 * F)) + 1j * rng.standard_normal((3, 2 * F))
+    c = O.fourier_coefficients(G, W)
+    m = np.arange(-F, F)
+    ref = ((-1.0) ** m)[None, :] * np.fft.fft(G, axis=1)[:, m % (2 * F)] / (2 * F)
+    assert np.allclose(c, ref, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# P9. Partition of unity (Sec. 3.1 a-d) in time and in frequency
+# --------------------------------------------------------------------------
+def test_window_properties():
+    p = GOLDEN["partition_of_unity"]
+    H = p["H_used_in_paper"]
+    assert np.allclose(np.diff(O.window_center(np.arange(1, 6), H)), p["center_spacing_over_H"] * H)
+    assert O.window_center(1, H) == 0.0
+    t = np.linspace(-1.2 * H, 1.2 * H, 24001)
+    w = O.window(t, H)
+    assert np.all(w[np.abs(t) < p["plateau_halfwidth_over_H"] * H] == 1.0)
+    assert np.all(w[np.abs(t) > p["support_halfwidth_over_H"] * H] == 0.0)
+    # the rising ramp of window k+1 complements the falling ramp of window k
+    tr = np.linspace(0.5 * H, H, 501)
+    assert np.allclose(O.window(tr, H) + O.window(tr - 1.5 * H, H), 1.0, atol=1e-15)
+    assert O.eta_window(0.0) == 1.0 and O.eta_window(1.0) == 0.0
+    e = O.eta_window(np.linspace(0, 1, 1001))
+    assert np.all(np.diff(e) <= 0)
+    tt = np.linspace(-3 * H, 40 * H, 50001)
+    S = sum(O.window(tt - O.window_center(k, H), H) for k in range(-5, 35))
+    assert np.max(np.abs(S - 1.0)) < 1e-15
+
+
+def test_window_spectra_sum_to_signal_transform():
+    """sum_k e^{i w s_k} B_k^slow(w) = A(w), with A the exact transform of
+    a = -exp(-(t-c)^2/s) cos(nu t)."""
+    c0, s, nu = 14.0, 2.0, 6.0
+    sig = Wk.gaussian_pulse(t0=0.0, t1=30.0, dt=1 / 128, center=c0, var2=s, freq=nu)
+    H = 4.0
+    ks = O.window_indices(sig.t[0], sig.t[-1], H)
+    w = np.linspace(-15, 15, 61)
+    B = O.window_spectra(sig, H, ks, w)
+    total = (np.exp(1j * np.outer(O.window_center(ks, H), w)) * B).sum(0)
+    exact = -0.5 * np.sqrt(np.pi * s) * (np.exp(-s * (w + nu) ** 2 / 4 + 1j * (w + nu) * c0)
+                                         + np.exp(-s * (w - nu) ** 2 / 4 + 1j * (w - nu) * c0))
+    assert np.max(np.abs(total - exact)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P7. Whole pipeline: interior points see u = b = -f(t - p.x) (time domain),
+#     P10 Hermitian symmetry, P11 time-leap invariance
+# --------------------------------------------------------------------------
+def _pulse15():
+    return Wk.gaussian_pulse(t0=0.0, t1=30.0, dt=1 / 64, center=15.0, var2=1.0, freq=10.0)
+
+
+def test_interior_time_domain_circle():
+    pts = np.array([[0.2, 0.1], [-0.5, 0.3], [0.0, -0.6]])
+    p = np.array([0.6, 0.8])
+    times = np.linspace(0, 40, 81)
+    out = O.run(Wk.circle(1.0), 24.0, 128, 64, tuple(p), _pulse15(), 10.0, 3.0, pts, times, return_all=True)
+    f = lambda t: np.exp(-(t - 15) ** 2) * np.cos(10 * t)
+    exact = np.array([-f(times - x @ p) for x in pts])
+    assert np.max(np.abs(out["u"] - exact)) < 1e-9
+    assert out["im_max"] < 1e-13
+
+
+@pytest.mark.slow
+def test_interior_time_domain_kite():
+    p = np.array([0.6, 0.8])
+    times = np.linspace(0, 40, 41)
+    out = O.run(Wk.kite(), 20.0, 96, 256, tuple(p), _pulse15(), 10.0, 0.0, KITE_INTERIOR[:3], times, return_all=True)
+    f = lambda t: np.exp(-(t - 15) ** 2) * np.cos(10 * t)
+    exact = np.array([-f(times - x @ p) for x in KITE_INTERIOR[:3]])
+    assert np.max(np.abs(out["u"] - exact)) < 1e-8
+
+
+def test_time_leap_invariance():
+    sig = _pulse15()
+    H = 10.0
+    shift = 1.5 * H * 40
+    sig2 = Wk.Signal(sig.t0 + shift, sig.dt, sig.f.copy())
+    times = np.linspace(0, 40, 21)
+    pts = np.array([[3.0, 0.5], [-2.0, 2.5]])
+    u1 = O.run(Wk.circle(1.0), 16.0, 48, 64, (1.0, 0.0), sig, H, 0.0, pts, times)
+    u2 = O.run(Wk.circle(1.0), 16.0, 48, 64, (1.0, 0.0), sig2, H, 0.0, pts, times + shift)
+    assert np.max(np.abs(u1 - u2)) <= 1e-13 * np.max(np.abs(u1))
+
+
+def test_grid_and_sizes():
+    omega, kappa = O.frequency_grid(200.0, 512)
+    assert omega[0] == 200.0 / 512 and omega[-1] == 200.0
+    L = O.curve_length(Wk.kite())
+    Ns = O.discretization_sizes(kappa, L, 10.0, 64, 32, 4096)
+    assert Ns.min() == 64 and np.all(Ns % 32 == 0) and Ns.max() <= 4096
+    assert abs(L - 9.32402267328496) < 1e-9
+    # perimeter of a circle of radius 1.7
+    assert abs(O.curve_length(Wk.circle(1.7)) - 2 * np.pi * 1.7) < 1e-12
+    d = np.hypot(*(O.curve_eval(Wk.kite(), np.linspace(0, 2 * np.pi, 200001))[0]
+                   - np.array(GOLDEN["convergence_experiment"]["obs"])).T).min()
+    assert abs(d - GOLDEN["convergence_experiment"]["obs_distance_to_boundary_approx"]) < 0.05
+
+
+def test_geometry_rejects_clockwise_and_degenerate():
+    c = Wk.circle(1.0)
+    cw = Wk.Curve("cw", c.cx, c.sx, c.cy, -c.sy)
+    with pytest.raises(ValueError):
+        O.geometry(cw, 32)
+    pt = Wk.Curve("pt", np.array([0.0, 0.0]), np.zeros(2), np.zeros(2), np.zeros(2))
+    with pytest.raises(ValueError):
+        O.geometry(pt, 32)
+
+
+def test_star_curve_is_polar_form():
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0, 0.15 / np.arange(2, 9)); ph = rng.uniform(0, 2 * np.pi, 7)
+    c = Wk.star(a, ph)
+    th = np.linspace(0, 2 * np.pi, 97)
+    r = 1 + sum(a[k - 2] * np.cos(k * th + ph[k - 2]) for k in range(2, 9))
+    X, _, _ = O.curve_eval(c, th)
+    assert np.allclose(X, np.stack([r * np.cos(th), r * np.sin(th)], 1), atol=1e-14)
