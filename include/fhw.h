@@ -1,0 +1,224 @@
+/*
+ * fhw.h -- C ABI of the MI355X (gfx950) hot path of the frequency/time hybrid
+ * wave-equation solver of Anderson, Bruno & Lyon, "High-order, dispersionless
+ * Fast-Hybrid wave equation solver, Part I" (arXiv 1807.02718).
+ *
+ * The path, in the paper's order (Sec. 5, steps F1-F5 and T0-T6):
+ *   fhw_plan             frequency grid, discretization sizes, boundary nodes,
+ *                        Kress weights (Sec. 2.3, Sec. 4.1.1)
+ *   fhw_solve_densities  assemble + factor + solve the direct combined-field
+ *                        equation (eq. CFIE_direct) at every frequency (step F3)
+ *   fhw_eval_field       layer potential U = int psi G (eqs. freq_domain_repr,
+ *                        Ukslow_repr; step F5)
+ *   fhw_synthesize       windowed, recentred signal spectra (eq. Bkslow_eqn,
+ *                        steps F1-F2), Fourier coefficients (eq. fourier_approx,
+ *                        T1a), sinc scaled-convolution synthesis and the sum
+ *                        over windows (eqs. approx, discConv, ukW, final_u;
+ *                        T2, T5)
+ * plus stage entry points for the same steps on caller buffers.
+ *
+ * Conventions shared by every call
+ *  - Return value: FHW_OK (0) or a negative FHW_E_* code; fhw_last_error()
+ *    gives a message.  No call aborts the process.
+ *  - Pointers are DEVICE pointers owned by the caller unless marked [host].
+ *    The library never frees caller memory.
+ *  - Work is enqueued on the HIP stream given to fhw_create and is
+ *    asynchronous unless stated; calls that return host values synchronize
+ *    that stream.  One context per stream; a context is not thread-safe.
+ *  - Complex numbers are interleaved (re, im) pairs: double2 for FP64
+ *    ("complex128"), float2 for FP32 ("complex64").
+ *  - Matrices are row-major, packed (leading dimension N), one after another
+ *    at caller-given element offsets (ragged batches).
+ *  - Frequencies: omega_j = j W / F, j = 1..F; wavenumber kappa = omega / c;
+ *    coupling eta = max(kappa, 1).  The DFT grid is omega_l = (l - F) W / F,
+ *    l = 0..2F-1, on [-W, W).
+ *  - Boundary nodes: t_i = 2 pi i / N, i = 0..N-1 on a counter-clockwise
+ *    curve; normals point out of the scatterer.
+ */
+#ifndef FHW_H
+#define FHW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FHW_OK 0
+#define FHW_E_INVALID (-1)  /* bad argument, clockwise/degenerate curve, NaN input */
+#define FHW_E_NOMEM (-2)    /* device memory or HBM budget exhausted */
+#define FHW_E_HIP (-3)      /* HIP runtime error */
+#define FHW_E_SINGULAR (-4) /* exactly zero pivot met in an LU factorization */
+#define FHW_E_NOCONV (-5)   /* iterative refinement did not reach its tolerance */
+#define FHW_E_STATE (-6)    /* call out of order (e.g. solve before plan) */
+
+#define FHW_FP64 0          /* complex128 LU and solves */
+#define FHW_FP32_REFINE 1   /* complex64 LU on MFMA + FP64-residual refinement */
+
+typedef struct fhw_ctx fhw_ctx;
+
+/* Scatterer boundary as a real trigonometric polynomial in s in [0, 2 pi):
+ *   x1(s) = sum_{d=0}^{degree} cx[d] cos(d s) + sx[d] sin(d s), x2 likewise
+ * with cy, sy.  [host] arrays of degree+1 doubles, counter-clockwise. */
+typedef struct {
+    int32_t degree;
+    const double *cx, *sx, *cy, *sy;
+} fhw_curve;
+
+/* Frequency-domain problem (Sec. 2.1, Remark rem:pwe, Sec. 5 F3). */
+typedef struct {
+    double W;            /* band limit (> 0); solve frequencies j W / F        */
+    int32_t F;           /* number of solve frequencies (>= 1)                 */
+    double c;            /* wave speed (> 0); kappa = omega / c                */
+    int32_t N_fixed;     /* > 0: this even N at every frequency; 0: rule below */
+    double ppw;          /* points per wavelength over the curve length        */
+    int32_t n_min, n_mult, n_cap;   /* N = clamp(ceil(ppw L kappa/(2 pi n_mult)) n_mult) */
+    int32_t precision;   /* FHW_FP64 or FHW_FP32_REFINE                        */
+    double refine_tol;   /* relative residual target ||g-A psi||/||g|| (FP32)  */
+    int32_t refine_max;  /* maximum refinement sweeps (FP32 path)              */
+    double direction[2]; /* plane-wave direction p (unit vector)               */
+} fhw_problem;
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL =
+ * default stream).  hbm_budget_bytes caps the device workspace (0 = 90% of the
+ * free device memory); solves are chunked over frequencies to fit it. */
+int fhw_create(fhw_ctx** ctx, void* hip_stream, size_t hbm_budget_bytes);
+int fhw_destroy(fhw_ctx* ctx);
+const char* fhw_last_error(const fhw_ctx* ctx);
+int fhw_version(void);
+
+/* Plan a problem: frequencies, discretization sizes N_j, boundary nodes and
+ * Kress weights per distinct N (Sec. 2.3), density layout, and the device
+ * workspace (allocated here; later calls of the plan allocate nothing).
+ * Outputs [host], optional (NULL to skip): N_out[F], psi_off_out[F+1]
+ * (element offsets of psi_j in the ragged density buffer).
+ * Errors: FHW_E_INVALID for a clockwise or degenerate curve, odd or
+ * non-positive N, F < 1; FHW_E_NOMEM if one frequency does not fit the budget. */
+int fhw_plan(fhw_ctx* ctx, const fhw_curve* curve, const fhw_problem* prob,
+             int32_t* N_out, int64_t* psi_off_out);
+
+/* Step F3: densities psi_p(., omega_j) of eq. CFIE_direct with boundary data
+ * exp(i kappa p.x), for all planned frequencies.
+ * psi: complex128, psi_off[F] elements (ragged, offsets from fhw_plan).
+ * resid [host, optional]: relative residuals per frequency (FP32 path: after
+ * refinement; FP64 path: filled only when compute_resid != 0, else -1).
+ * sweeps [host, optional]: refinement sweeps used per frequency.
+ * Synchronizes the stream.  FHW_E_SINGULAR on an exactly zero pivot,
+ * FHW_E_NOCONV if refinement misses refine_tol within refine_max sweeps. */
+int fhw_solve_densities(fhw_ctx* ctx, void* psi, double* resid, int32_t* sweeps,
+                        int32_t compute_resid);
+
+/* Step F5 (eqs. freq_domain_repr, Ukslow_repr): V(r, omega_l) on the full DFT
+ * grid, V[r][l], complex128 [N_r][2F]; V(r,-omega) = conj V(r,omega) and
+ * V(r, 0) = zero_value (1 for plane-wave data: the low-frequency limit).
+ * obs: [host] doubles [N_r][2], points off the boundary. */
+int fhw_eval_field(fhw_ctx* ctx, const void* psi, const double* obs, int32_t N_r,
+                   double zero_value, void* V);
+
+/* Incident signal f sampled at t0 + n dt, n = 0..n-1 (device doubles); the
+ * incident field is f(t - p.r/c) and the boundary signal is a = -f.  The
+ * signal must vanish, with its derivatives, at both ends of the range. */
+typedef struct {
+    double t0, dt;
+    int64_t n;
+    const double* f;
+} fhw_signal;
+
+/* Partition of unity (Sec. 3.1): s_k = 1.5 H (k - 1), half-width H; tau0 is an
+ * extra recentring shift (0 = the paper's choice). */
+typedef struct {
+    double H, tau0;
+} fhw_windows;
+
+/* Steps F1-F2 and T0-T6: scattered field u[r][t] (device doubles [N_r][N_t])
+ * from V (device complex128 [N_r][2F], as written by fhw_eval_field) at the
+ * [host] times[N_t].  Active windows: |t - s_k - tau0| <= pi F / W.
+ * Errors: FHW_E_INVALID if 2F is not a power of two or inputs are non-finite. */
+int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
+                   const void* V, int32_t N_r, const double* times, int32_t N_t,
+                   double* u);
+
+/* ---------------- stage entry points (same kernels, caller buffers) -------- */
+
+/* Boundary nodes of the planned curve at N points (Sec. 2.3 Nystrom nodes):
+ * geom doubles [9][N] = x1, x2, x1', x2', x1'', x2'', |x'|, nu1, nu2. */
+int fhw_geometry(fhw_ctx* ctx, int32_t N, double* geom);
+
+/* Kress weights R_l (l = 0..N-1) of the log-kernel product rule and the table
+ * log(4 sin^2(l pi / N)) (entry 0 = 0), doubles [N] each (Sec. 2.3). */
+int fhw_kress_weights(fhw_ctx* ctx, int32_t N, double* R, double* logtab);
+
+/* Nystrom matrix and plane-wave RHS of eq. CFIE_direct for planned frequencies
+ * j0 .. j0+count-1 (0-based): A complex128 at A_off[q] (N_j^2 elements each,
+ * row-major), g complex128 at g_off[q] (N_j elements).  A_off, g_off [host]. */
+int fhw_assemble(fhw_ctx* ctx, int32_t j0, int32_t count, void* A, const int64_t* A_off,
+                 void* g, const int64_t* g_off);
+
+/* In-place batched LU with partial pivoting (max |re|+|im|, first index on
+ * ties) of `batch` row-major square matrices: N[q], A_off[q], piv_off[q]
+ * [host]; A complex128 (precision FHW_FP64) or complex64 (FHW_FP32_REFINE);
+ * piv int32 (global row swapped with row i, applied in order).  Rows of
+ * earlier column panels are not permuted by later pivots (the solve below
+ * replays the pivots panel by panel).  linv: device workspace of
+ * sum_q 4096*ceil(N[q]/64) elements of the same complex type, linv_off[q]
+ * [host]; block p of matrix q (64x64 row-major at linv_off[q] + 4096 p)
+ * receives the inverse of the unit-lower diagonal block p below its diagonal
+ * and the inverse of the upper diagonal block on and above it.
+ * Returns FHW_E_SINGULAR if any exactly zero pivot was met. */
+int fhw_lu_factor(fhw_ctx* ctx, int32_t batch, const int32_t* N, const int64_t* A_off,
+                  void* A, const int64_t* piv_off, int32_t* piv, const int64_t* linv_off,
+                  void* linv, int32_t precision);
+
+/* x = A^{-1} b from fhw_lu_factor output, in place on b (complex128,
+ * b_off[q] [host]).  Factors may be complex64 (precision FHW_FP32_REFINE);
+ * vectors are always complex128. */
+int fhw_lu_solve(fhw_ctx* ctx, int32_t batch, const int32_t* N, const int64_t* A_off,
+                 const void* LU, const int64_t* piv_off, const int32_t* piv,
+                 const int64_t* linv_off, const void* linv, const int64_t* b_off,
+                 void* b, int32_t precision);
+
+/* Window spectra B_k^slow(omega_l) (eq. Bkslow_eqn) for windows k = k_first +
+ * q, q = 0..count-1, on the planned DFT grid: B complex128 [count][2F]. */
+int fhw_window_spectra(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
+                       int64_t k_first, int32_t count, void* B);
+
+/* Fourier coefficients c_{k,m}(r), m = -F..F-1 (eq. fourier_approx; T1a) of
+ * B_k(omega) V(r, omega) exp(-i omega tau0) on [-W, W): c complex128
+ * [count][N_r][2F] (index m + F) from B [count][2F] and V [N_r][2F]. */
+int fhw_fourier_coefficients(fhw_ctx* ctx, const void* B, int32_t count, const void* V,
+                             int32_t N_r, double tau0, void* c);
+
+/* ---------------- diagnostics ------------------------------------------------ */
+
+/* Stage timers: with profiling on, every kernel launch of the context is
+ * bracketed by HIP events on the context's stream.  fhw_profile(ctx, 1) turns
+ * it on and clears the counters, fhw_profile(ctx, 0) turns it off.
+ * fhw_profile_read synchronizes the stream, writes the summed milliseconds and
+ * the launch count per stage into [host] ms[FHW_N_STAGES] and
+ * launches[FHW_N_STAGES], and clears the counters. */
+#define FHW_STAGE_GEOMETRY 0
+#define FHW_STAGE_KRESS 1
+#define FHW_STAGE_ASSEMBLE 2
+#define FHW_STAGE_LU_PANEL 3
+#define FHW_STAGE_LU_SWAP 4
+#define FHW_STAGE_LU_TRSM 5
+#define FHW_STAGE_LU_UPDATE 6
+#define FHW_STAGE_SOLVE 7
+#define FHW_STAGE_RESIDUAL 8
+#define FHW_STAGE_FIELD 9
+#define FHW_STAGE_SPECTRA 10
+#define FHW_STAGE_COEFFS 11
+#define FHW_STAGE_SYNTH 12
+#define FHW_N_STAGES 13
+int fhw_profile(fhw_ctx* ctx, int32_t enable);
+int fhw_profile_read(fhw_ctx* ctx, double* ms, int64_t* launches);
+
+/* Hankel functions H0^(1)(z), H1^(1)(z) at z[n] > 0 (device doubles) into
+ * h complex128 [n][2] (diagnostic of the in-register Bessel evaluation). */
+int fhw_hankel01(fhw_ctx* ctx, const double* z, int64_t n, void* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHW_H */

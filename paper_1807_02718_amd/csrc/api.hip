@@ -1,0 +1,775 @@
+// C ABI of libfhw (declared in include/fhw.h): context, planner and the
+// entry points of the hot path.  Host logic only; every arithmetic step of
+// the method runs in the kernels of geometry/assemble/lu/solve/field/synth.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <new>
+#include <set>
+
+#include "fhw_internal.h"
+
+namespace {
+
+struct zd { double re, im; };   // complex128 element (host view)
+
+struct chunk_t {
+    int32_t j0 = 0, count = 0, maxN = 0;
+    // device metadata (inside ctx->meta)
+    int32_t* d_N = nullptr;
+    int64_t *d_aoff = nullptr, *d_pivoff = nullptr, *d_linvoff = nullptr, *d_voff = nullptr;
+    fhw_assemble_item* d_items = nullptr;
+    int64_t* d_asm_prefix = nullptr;
+    int32_t* d_lu_prefix = nullptr;
+    int64_t asm_blocks = 0;
+    fhw_lu_sched sched;
+    int64_t psi_base = 0;       // element offset of psi_j0
+    int64_t vec_elems = 0;      // sum N over the chunk
+};
+
+struct plan_ext {
+    std::vector<chunk_t> chunks;
+    fhw_field_item* d_field_items = nullptr;
+};
+
+std::map<const fhw_ctx*, plan_ext> g_plans;   // per-context plan extension
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int64_t linv_elems(int32_t N) { return (int64_t)((N + FHW_LU_NB - 1) / FHW_LU_NB) * FHW_LU_NB * FHW_LU_NB; }
+
+size_t freq_bytes(int32_t N, int precision) {
+    size_t NN = (size_t)N * N;
+    size_t b = NN * 16;                                       // FP64 matrix
+    if (precision == FHW_FP32_REFINE) b += NN * 8;             // FP32 factors
+    b += (size_t)linv_elems(N) * (precision == FHW_FP64 ? 16 : 8);
+    b += (size_t)N * 4;                                       // pivots
+    b += (size_t)N * 16 * 2;                                  // g, r
+    b += 256;                                                 // metadata
+    return b;
+}
+
+void curve_eval_host(const fhw_ctx* c, double s, double& x1, double& x2, double& d1, double& d2) {
+    x1 = x2 = d1 = d2 = 0.0;
+    for (int d = 0; d <= c->degree; ++d) {
+        double cs = cos(d * s), sn = sin(d * s);
+        x1 += c->cx[d] * cs + c->sx[d] * sn;
+        x2 += c->cy[d] * cs + c->sy[d] * sn;
+        d1 += d * (c->sx[d] * cs - c->cx[d] * sn);
+        d2 += d * (c->sy[d] * cs - c->cy[d] * sn);
+    }
+}
+
+void free_plan(fhw_ctx* c) {
+    auto it = g_plans.find(c);
+    if (it != g_plans.end()) g_plans.erase(it);
+    for (auto& kv : c->geoms) {
+        (void)hipFree(kv.second.geom);
+        (void)hipFree(kv.second.R);
+        (void)hipFree(kv.second.logtab);
+    }
+    c->geoms.clear();
+    void* ptrs[] = {c->d_curve, c->A64, c->A32, c->linv, c->piv, c->x, c->r, c->meta, c->d_status,
+                    c->d_norms, c->d_done, c->d_sweeps};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    c->d_curve = nullptr; c->A64 = c->A32 = c->linv = nullptr; c->piv = nullptr; c->x = c->r = nullptr;
+    c->meta = nullptr; c->d_status = nullptr; c->d_norms = nullptr; c->d_done = nullptr; c->d_sweeps = nullptr;
+    c->planned = false;
+}
+
+int lds_limit(fhw_ctx* c) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) v = 65536;
+    return v;
+}
+
+}  // namespace
+
+hipEvent_t fhw_prof::take() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void fhw_prof::begin(int stage, hipStream_t s) {
+    open_stage = stage;
+    open_a = take();
+    if (open_a) (void)hipEventRecord(open_a, s);
+}
+
+void fhw_prof::end(hipStream_t s) {
+    if (open_stage < 0 || !open_a) return;
+    hipEvent_t b = take();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    recs.push_back(rec{open_stage, open_a, b});
+    open_stage = -1;
+    open_a = nullptr;
+}
+
+int fhw_fail(fhw_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int fhw_hip_check(fhw_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fhw_fail(ctx, FHW_E_NOMEM, std::string("device memory exhausted: ") + what);
+    return fhw_fail(ctx, FHW_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int fhw_ensure_scratch(fhw_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->scratch_bytes) return FHW_OK;
+    FHW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    size_t nb = align_up(bytes, 1 << 20);
+    FHW_HIP(ctx, hipMalloc(&ctx->scratch, nb));
+    ctx->scratch_bytes = nb;
+    return FHW_OK;
+}
+
+#define STAGE(c, st, call)                                               \
+    do {                                                                 \
+        prof_begin(&(c)->prof, (st), (c)->stream);                       \
+        hipError_t _e = (call);                                          \
+        prof_end(&(c)->prof, (c)->stream);                               \
+        if (_e != hipSuccess) return fhw_hip_check((c), _e, #call);      \
+    } while (0)
+
+extern "C" {
+
+int fhw_version(void) { return 1; }
+
+int fhw_profile(fhw_ctx* c, int32_t enable) {
+    if (!c) return FHW_E_INVALID;
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& r : c->prof.recs) {
+        c->prof.pool.push_back(r.a);
+        c->prof.pool.push_back(r.b);
+    }
+    c->prof.recs.clear();
+    c->prof.on = enable != 0;
+    return FHW_OK;
+}
+
+int fhw_profile_read(fhw_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return FHW_E_INVALID;
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    for (int q = 0; q < FHW_N_STAGES; ++q) {
+        ms[q] = 0.0;
+        launches[q] = 0;
+    }
+    for (auto& r : c->prof.recs) {
+        float t = 0.0f;
+        FHW_HIP(c, hipEventElapsedTime(&t, r.a, r.b));
+        if (r.stage >= 0 && r.stage < FHW_N_STAGES) {
+            ms[r.stage] += (double)t;
+            launches[r.stage] += 1;
+        }
+        c->prof.pool.push_back(r.a);
+        c->prof.pool.push_back(r.b);
+    }
+    c->prof.recs.clear();
+    return FHW_OK;
+}
+
+int fhw_create(fhw_ctx** out, void* hip_stream, size_t hbm_budget_bytes) {
+    if (!out) return FHW_E_INVALID;
+    *out = nullptr;
+    fhw_ctx* c = new (std::nothrow) fhw_ctx();
+    if (!c) return FHW_E_NOMEM;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return FHW_E_HIP;
+    }
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        delete c;
+        return FHW_E_HIP;
+    }
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    *out = c;
+    return FHW_OK;
+}
+
+int fhw_destroy(fhw_ctx* c) {
+    if (!c) return FHW_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_plan(c);
+    if (c->scratch) (void)hipFree(c->scratch);
+    for (auto& r : c->prof.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    delete c;
+    return FHW_OK;
+}
+
+const char* fhw_last_error(const fhw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* N_out, int64_t* psi_off_out) {
+    if (!c) return FHW_E_INVALID;
+    if (!curve || !p || curve->degree < 1 || !curve->cx || !curve->sx || !curve->cy || !curve->sy)
+        return fhw_fail(c, FHW_E_INVALID, "plan: missing curve/problem");
+    if (!(p->W > 0) || p->F < 1 || !(p->c > 0) || !isfinite(p->W) || !isfinite(p->c))
+        return fhw_fail(c, FHW_E_INVALID, "plan: need W > 0, F >= 1, c > 0");
+    if (p->precision != FHW_FP64 && p->precision != FHW_FP32_REFINE)
+        return fhw_fail(c, FHW_E_INVALID, "plan: unknown precision");
+    if (!isfinite(p->direction[0]) || !isfinite(p->direction[1]))
+        return fhw_fail(c, FHW_E_INVALID, "plan: direction not finite");
+    (void)hipStreamSynchronize(c->stream);
+    free_plan(c);
+    c->prob = *p;
+    c->degree = curve->degree;
+    const int D1 = curve->degree + 1;
+    c->cx.assign(curve->cx, curve->cx + D1);
+    c->sx.assign(curve->sx, curve->sx + D1);
+    c->cy.assign(curve->cy, curve->cy + D1);
+    c->sy.assign(curve->sy, curve->sy + D1);
+    for (int d = 0; d < D1; ++d)
+        if (!isfinite(c->cx[d]) || !isfinite(c->sx[d]) || !isfinite(c->cy[d]) || !isfinite(c->sy[d]))
+            return fhw_fail(c, FHW_E_INVALID, "plan: curve coefficients not finite");
+    // curve length (trapezoidal rule on the periodic speed), orientation check
+    const int nq = 4096;
+    double L = 0.0, area = 0.0, minsp = 1e300;
+    for (int q = 0; q < nq; ++q) {
+        double s = 2.0 * M_PI * q / nq, x1, x2, d1, d2;
+        curve_eval_host(c, s, x1, x2, d1, d2);
+        double sp = sqrt(d1 * d1 + d2 * d2);
+        L += sp;
+        area += x1 * d2 - x2 * d1;
+        minsp = std::min(minsp, sp);
+    }
+    L *= 2.0 * M_PI / nq;
+    area *= 0.5 * 2.0 * M_PI / nq;
+    if (!(minsp > 0.0) || !(area > 0.0))
+        return fhw_fail(c, FHW_E_INVALID, "plan: curve must be counter-clockwise, non-degenerate");
+    c->length = L;
+    // frequencies, sizes, coupling
+    const int F = p->F;
+    const double dw = p->W / (double)F;
+    c->kappa.resize(F);
+    c->eta.resize(F);
+    c->Ns.resize(F);
+    for (int j = 0; j < F; ++j) {
+        double om = dw * (double)(j + 1);
+        c->kappa[j] = om / p->c;
+        c->eta[j] = std::max(c->kappa[j], 1.0);
+        int N;
+        if (p->N_fixed > 0) {
+            N = p->N_fixed;
+        } else {
+            if (p->n_mult < 1 || p->n_min < 2 || p->n_cap < p->n_min || !(p->ppw > 0))
+                return fhw_fail(c, FHW_E_INVALID, "plan: bad N rule");
+            double raw = p->ppw * L * c->kappa[j] / (2.0 * M_PI);
+            double m = ceil(raw / (double)p->n_mult) * (double)p->n_mult;
+            N = (int)std::min<double>(std::max<double>(m, p->n_min), p->n_cap);
+        }
+        if (N < 4 || (N & 1) || N > 4096)
+            return fhw_fail(c, FHW_E_INVALID, "plan: N must be even, 4 <= N <= 4096");
+        c->Ns[j] = N;
+    }
+    c->psi_off.assign(F + 1, 0);
+    for (int j = 0; j < F; ++j) c->psi_off[j + 1] = c->psi_off[j] + c->Ns[j];
+    int maxN = *std::max_element(c->Ns.begin(), c->Ns.end());
+    if ((size_t)maxN * 16 + 2048 > (size_t)lds_limit(c))
+        return fhw_fail(c, FHW_E_INVALID, "plan: N too large for the LDS-resident solve vector");
+
+    // curve coefficients on device, geometry + Kress tables per distinct N
+    FHW_HIP(c, hipMalloc(&c->d_curve, sizeof(double) * 4 * D1));
+    std::vector<double> hc(4 * D1);
+    for (int d = 0; d < D1; ++d) {
+        hc[d] = c->cx[d]; hc[D1 + d] = c->sx[d]; hc[2 * D1 + d] = c->cy[d]; hc[3 * D1 + d] = c->sy[d];
+    }
+    FHW_HIP(c, hipMemcpy(c->d_curve, hc.data(), sizeof(double) * 4 * D1, hipMemcpyHostToDevice));
+    std::set<int32_t> distinct(c->Ns.begin(), c->Ns.end());
+    for (int32_t N : distinct) {
+        fhw_geom_entry e{};
+        e.N = N;
+        FHW_HIP(c, hipMalloc(&e.geom, sizeof(double) * 9 * N));
+        FHW_HIP(c, hipMalloc(&e.R, sizeof(double) * N));
+        FHW_HIP(c, hipMalloc(&e.logtab, sizeof(double) * N));
+        STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, c->d_curve, c->degree, N, e.geom));
+        STAGE(c, FHW_STAGE_KRESS, launch_kress(c->stream, N, e.R, e.logtab));
+        c->geoms[N] = e;
+    }
+
+    // chunks over frequencies within the HBM budget
+    const int prec = p->precision;
+    plan_ext& px = g_plans[c];
+    px.chunks.clear();
+    {
+        size_t geo = 0;
+        for (int32_t N : distinct) geo += (size_t)N * 11 * 8;
+        size_t avail = c->budget > geo ? c->budget - geo : 0;
+        int j = 0;
+        while (j < F) {
+            chunk_t ch;
+            ch.j0 = j;
+            size_t used = 0;
+            while (j < F) {
+                size_t fb = freq_bytes(c->Ns[j], prec);
+                if (ch.count > 0 && used + fb > avail) break;
+                if (ch.count == 0 && fb > avail)
+                    return fhw_fail(c, FHW_E_NOMEM, "plan: one frequency does not fit the HBM budget");
+                used += fb;
+                ch.count++;
+                j++;
+            }
+            px.chunks.push_back(ch);
+        }
+    }
+    // workspace sized for the largest chunk
+    size_t wsA64 = 0, wsA32 = 0, wsL = 0, wsP = 0, wsV = 0;
+    int maxcount = 0;
+    for (auto& ch : px.chunks) {
+        size_t a = 0, l = 0, pv = 0, v = 0;
+        ch.maxN = 0;
+        for (int q = 0; q < ch.count; ++q) {
+            int N = c->Ns[ch.j0 + q];
+            a += (size_t)N * N;
+            l += linv_elems(N);
+            pv += N;
+            v += N;
+            ch.maxN = std::max(ch.maxN, N);
+        }
+        ch.psi_base = c->psi_off[ch.j0];
+        ch.vec_elems = (int64_t)v;
+        wsA64 = std::max(wsA64, a);
+        wsL = std::max(wsL, l);
+        wsP = std::max(wsP, pv);
+        wsV = std::max(wsV, v);
+        maxcount = std::max(maxcount, ch.count);
+    }
+    wsA32 = prec == FHW_FP32_REFINE ? wsA64 : 0;
+    c->chunk = maxcount;
+    FHW_HIP(c, hipMalloc(&c->A64, wsA64 * 16));
+    if (wsA32) FHW_HIP(c, hipMalloc(&c->A32, wsA32 * 8));
+    FHW_HIP(c, hipMalloc(&c->linv, wsL * (prec == FHW_FP64 ? 16 : 8)));
+    FHW_HIP(c, hipMalloc((void**)&c->piv, wsP * 4));
+    FHW_HIP(c, hipMalloc(&c->x, wsV * 16));   // g
+    FHW_HIP(c, hipMalloc(&c->r, wsV * 16));   // residual / correction
+    FHW_HIP(c, hipMalloc((void**)&c->d_status, sizeof(int32_t) * 4));
+    FHW_HIP(c, hipMalloc((void**)&c->d_norms, sizeof(double) * 2 * F));
+    FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * F));
+    FHW_HIP(c, hipMalloc((void**)&c->d_sweeps, sizeof(int32_t) * F));
+    c->ws_A64 = wsA64; c->ws_A32 = wsA32; c->ws_linv = wsL; c->ws_piv = wsP;
+
+    // per-chunk metadata, built once and uploaded into one buffer
+    std::vector<char> host;
+    struct fix { chunk_t* ch; size_t oN, oA, oP, oL, oV, oI, oAP, oLP; };
+    std::vector<fix> fixes;
+    auto put = [&](const void* src, size_t bytes) {
+        size_t o = align_up(host.size(), 64);
+        host.resize(o + bytes);
+        memcpy(host.data() + o, src, bytes);
+        return o;
+    };
+    for (auto& ch : px.chunks) {
+        std::vector<int32_t> Nv(ch.count);
+        std::vector<int64_t> ao(ch.count), po(ch.count), lo(ch.count), vo(ch.count), ap(ch.count + 1);
+        std::vector<fhw_assemble_item> items(ch.count);
+        int64_t a = 0, pv = 0, l = 0, v = 0, blk = 0;
+        for (int q = 0; q < ch.count; ++q) {
+            int j = ch.j0 + q;
+            int N = c->Ns[j];
+            Nv[q] = N;
+            ao[q] = a; po[q] = pv; lo[q] = l; vo[q] = v;
+            const fhw_geom_entry& ge = c->geoms[N];
+            items[q].geom = ge.geom;
+            items[q].R = ge.R;
+            items[q].logtab = ge.logtab;
+            items[q].a_off = a;
+            items[q].g_off = v;
+            items[q].N = N;
+            items[q].kappa = c->kappa[j];
+            items[q].eta = c->eta[j];
+            ap[q] = blk;
+            blk += assemble_blocks_for(N);
+            a += (int64_t)N * N; pv += N; l += linv_elems(N); v += N;
+        }
+        ap[ch.count] = blk;
+        ch.asm_blocks = blk;
+        lu_build_schedule(Nv.data(), ch.count, ch.sched);
+        fix f;
+        f.ch = &ch;
+        f.oN = put(Nv.data(), Nv.size() * 4);
+        f.oA = put(ao.data(), ao.size() * 8);
+        f.oP = put(po.data(), po.size() * 8);
+        f.oL = put(lo.data(), lo.size() * 8);
+        f.oV = put(vo.data(), vo.size() * 8);
+        f.oI = put(items.data(), items.size() * sizeof(fhw_assemble_item));
+        f.oAP = put(ap.data(), ap.size() * 8);
+        f.oLP = put(ch.sched.prefix.data(), std::max<size_t>(1, ch.sched.prefix.size()) * 4);
+        fixes.push_back(f);
+    }
+    std::vector<fhw_field_item> fitems(F);
+    for (int j = 0; j < F; ++j) {
+        fitems[j].geom = c->geoms[c->Ns[j]].geom;
+        fitems[j].psi_off = c->psi_off[j];
+        fitems[j].N = c->Ns[j];
+        fitems[j].kappa = c->kappa[j];
+    }
+    size_t oF = put(fitems.data(), fitems.size() * sizeof(fhw_field_item));
+    c->meta_bytes = align_up(host.size(), 64);
+    FHW_HIP(c, hipMalloc(&c->meta, c->meta_bytes));
+    FHW_HIP(c, hipMemcpy(c->meta, host.data(), host.size(), hipMemcpyHostToDevice));
+    char* mb = (char*)c->meta;
+    for (auto& f : fixes) {
+        f.ch->d_N = (int32_t*)(mb + f.oN);
+        f.ch->d_aoff = (int64_t*)(mb + f.oA);
+        f.ch->d_pivoff = (int64_t*)(mb + f.oP);
+        f.ch->d_linvoff = (int64_t*)(mb + f.oL);
+        f.ch->d_voff = (int64_t*)(mb + f.oV);
+        f.ch->d_items = (fhw_assemble_item*)(mb + f.oI);
+        f.ch->d_asm_prefix = (int64_t*)(mb + f.oAP);
+        f.ch->d_lu_prefix = (int32_t*)(mb + f.oLP);
+    }
+    px.d_field_items = (fhw_field_item*)(mb + oF);
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    c->planned = true;
+    if (N_out)
+        for (int j = 0; j < F; ++j) N_out[j] = c->Ns[j];
+    if (psi_off_out)
+        for (int j = 0; j <= F; ++j) psi_off_out[j] = c->psi_off[j];
+    return FHW_OK;
+}
+
+int fhw_solve_densities(fhw_ctx* c, void* psi, double* resid, int32_t* sweeps, int32_t compute_resid) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (!psi) return fhw_fail(c, FHW_E_INVALID, "solve: psi is null");
+    plan_ext& px = g_plans[c];
+    const fhw_problem& p = c->prob;
+    const int F = p.F;
+    const bool fp32 = p.precision == FHW_FP32_REFINE;
+    FHW_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * 4, c->stream));
+    FHW_HIP(c, hipMemsetAsync(c->d_done, 0, sizeof(int32_t) * F, c->stream));
+    FHW_HIP(c, hipMemsetAsync(c->d_sweeps, 0, sizeof(int32_t) * F, c->stream));
+    zd* psid = (zd*)psi;
+    for (auto& ch : px.chunks) {
+        fhw_batch_dev bd{ch.d_N, ch.d_aoff, ch.d_pivoff, ch.d_linvoff, ch.d_voff, ch.count};
+        zd* x = psid + ch.psi_base;          // solution written in place into psi
+        zd* g = (zd*)c->x;
+        zd* r = (zd*)c->r;
+        STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
+                                          p.direction[0], p.direction[1], c->A64, fp32 ? c->A32 : nullptr, g));
+        void* LU = fp32 ? c->A32 : c->A64;
+        FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
+                                    p.precision, &c->prof));
+        FHW_HIP(c, hipMemcpyAsync(x, g, sizeof(zd) * ch.vec_elems, hipMemcpyDeviceToDevice, c->stream));
+        STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, ch.maxN, LU, c->piv, c->linv, x, nullptr, p.precision));
+        double* norms = c->d_norms + 2 * ch.j0;
+        if (fp32) {
+            int32_t* done = c->d_done + ch.j0;
+            int32_t* sw = c->d_sweeps + ch.j0;
+            const int maxs = std::max(0, p.refine_max);
+            for (int it = 0; it <= maxs; ++it) {
+                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, norms, p.refine_tol, done, sw,
+                                             it));
+                if (it == maxs) break;
+                STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, ch.maxN, LU, c->piv, c->linv, r, x, done,
+                                               p.precision));
+            }
+        } else if (compute_resid) {
+            // the factorization overwrote A: assemble it again for the residual
+            STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
+                                              p.direction[0], p.direction[1], c->A64, nullptr, g));
+            STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, norms, 0.0, nullptr, nullptr, 0));
+        }
+    }
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    int32_t st[4];
+    FHW_HIP(c, hipMemcpy(st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    std::vector<double> nrm;
+    std::vector<int32_t> done, sw;
+    const bool have_norms = fp32 || compute_resid;
+    if (have_norms) {
+        nrm.resize(2 * F);
+        FHW_HIP(c, hipMemcpy(nrm.data(), c->d_norms, sizeof(double) * 2 * F, hipMemcpyDeviceToHost));
+    }
+    if (fp32) {
+        done.resize(F);
+        sw.resize(F);
+        FHW_HIP(c, hipMemcpy(done.data(), c->d_done, sizeof(int32_t) * F, hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(sw.data(), c->d_sweeps, sizeof(int32_t) * F, hipMemcpyDeviceToHost));
+    }
+    for (int j = 0; j < F; ++j) {
+        if (resid) resid[j] = have_norms ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
+        if (sweeps) sweeps[j] = fp32 ? (done[j] ? sw[j] : p.refine_max) : 0;
+    }
+    if (st[0]) return fhw_fail(c, FHW_E_SINGULAR, "solve: exactly zero pivot in an LU factorization");
+    if (fp32)
+        for (int j = 0; j < F; ++j)
+            if (!done[j]) return fhw_fail(c, FHW_E_NOCONV, "solve: refinement did not reach refine_tol");
+    return FHW_OK;
+}
+
+int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, double zero_value, void* V) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field: no plan");
+    if (N_r < 0 || (N_r > 0 && (!psi || !obs || !V))) return fhw_fail(c, FHW_E_INVALID, "field: bad arguments");
+    if (N_r == 0) return FHW_OK;
+    for (int q = 0; q < 2 * N_r; ++q)
+        if (!isfinite(obs[q])) return fhw_fail(c, FHW_E_INVALID, "field: observation point not finite");
+    int rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
+    if (rc) return rc;
+    FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
+    STAGE(c, FHW_STAGE_FIELD, launch_field(c->stream, g_plans[c].d_field_items, c->prob.F, psi, (const double*)c->scratch, N_r,
+                            zero_value, V));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V, int32_t N_r,
+                   const double* times, int32_t N_t, double* u) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize: no plan");
+    if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize: bad arguments");
+    if (N_r == 0 || N_t == 0) return FHW_OK;
+    if (!V || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize: bad signal or buffers");
+    const double H = win->H, tau0 = win->tau0;
+    if (!(H > 0) || !isfinite(H) || !isfinite(tau0)) return fhw_fail(c, FHW_E_INVALID, "synthesize: bad windows");
+    const int F = c->prob.F;
+    const int M = 2 * F;
+    if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F must be a power of two");
+    if ((size_t)M * 16 > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F too large");
+    const double W = c->prob.W;
+    // windows meeting the signal's sample range
+    const double tlo = sig->t0, thi = sig->t0 + sig->dt * (double)(sig->n - 1);
+    const double span = 1.5 * H;
+    int64_t k_lo = (int64_t)floor((tlo - H) / span) + 1 - 1;
+    int64_t k_hi = (int64_t)ceil((thi + H) / span) + 1 + 1;
+    while (k_lo <= k_hi && !(1.5 * H * ((double)k_lo - 1.0) + H >= tlo)) ++k_lo;
+    while (k_hi >= k_lo && !(1.5 * H * ((double)k_hi - 1.0) - H <= thi)) --k_hi;
+    const double P = M_PI / (W / (double)F);
+    std::vector<int32_t> slot;
+    std::vector<int64_t> klist;
+    if (k_hi >= k_lo) {
+        slot.assign(k_hi - k_lo + 1, -1);
+        std::vector<char> need(k_hi - k_lo + 1, 0);
+        for (int q = 0; q < N_t; ++q) {
+            const double t = times[q];
+            if (!isfinite(t)) return fhw_fail(c, FHW_E_INVALID, "synthesize: time not finite");
+            int64_t ka = (int64_t)floor((t - tau0 - P) / span) + 1 - 1;
+            int64_t kb = (int64_t)ceil((t - tau0 + P) / span) + 1 + 1;
+            for (int64_t k = std::max(ka, k_lo); k <= std::min(kb, k_hi); ++k) {
+                const double sk = 1.5 * H * ((double)k - 1.0);
+                if (fabs(t - sk - tau0) <= P) need[k - k_lo] = 1;
+            }
+        }
+        for (int64_t k = k_lo; k <= k_hi; ++k)
+            if (need[k - k_lo]) {
+                slot[k - k_lo] = (int32_t)klist.size();
+                klist.push_back(k);
+            }
+    }
+    const int count = (int)klist.size();
+    // scratch layout: times | slot | klist | B | c
+    size_t o_t = 0;
+    size_t o_s = align_up(o_t + (size_t)N_t * 8, 256);
+    size_t o_k = align_up(o_s + std::max<size_t>(1, slot.size()) * 4, 256);
+    size_t o_B = align_up(o_k + std::max<size_t>(1, klist.size()) * 8, 256);
+    size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
+    size_t total = align_up(o_c + (size_t)count * N_r * M * 16, 256);
+    int rc = fhw_ensure_scratch(c, total);
+    if (rc) return rc;
+    char* sb = (char*)c->scratch;
+    FHW_HIP(c, hipMemcpyAsync(sb + o_t, times, (size_t)N_t * 8, hipMemcpyHostToDevice, c->stream));
+    if (!slot.empty())
+        FHW_HIP(c, hipMemcpyAsync(sb + o_s, slot.data(), slot.size() * 4, hipMemcpyHostToDevice, c->stream));
+    if (count > 0)
+        FHW_HIP(c, hipMemcpyAsync(sb + o_k, klist.data(), klist.size() * 8, hipMemcpyHostToDevice, c->stream));
+    STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, H, 0, (const int64_t*)(sb + o_k),
+                                     count, W, F, sb + o_B));
+    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, sb + o_c));
+    if (count == 0) {
+        FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
+    } else {
+        STAGE(c, FHW_STAGE_SYNTH, launch_synth(c->stream, sb + o_c, (const int32_t*)(sb + o_s), k_lo, k_hi, count, N_r,
+                                (const double*)(sb + o_t), N_t, W, F, H, tau0, u));
+    }
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+// ----------------------------- stage entry points ---------------------------
+
+int fhw_geometry(fhw_ctx* c, int32_t N, double* geom) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "geometry: no plan");
+    if (N < 4 || (N & 1) || !geom) return fhw_fail(c, FHW_E_INVALID, "geometry: bad arguments");
+    STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, c->d_curve, c->degree, N, geom));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_kress_weights(fhw_ctx* c, int32_t N, double* R, double* logtab) {
+    if (!c) return FHW_E_INVALID;
+    if (N < 4 || (N & 1) || !R || !logtab) return fhw_fail(c, FHW_E_INVALID, "kress: bad arguments");
+    STAGE(c, FHW_STAGE_KRESS, launch_kress(c->stream, N, R, logtab));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_assemble(fhw_ctx* c, int32_t j0, int32_t count, void* A, const int64_t* A_off, void* g,
+                 const int64_t* g_off) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "assemble: no plan");
+    if (j0 < 0 || count < 0 || j0 + count > c->prob.F || (count > 0 && (!A || !A_off || !g || !g_off)))
+        return fhw_fail(c, FHW_E_INVALID, "assemble: bad arguments");
+    if (count == 0) return FHW_OK;
+    std::vector<fhw_assemble_item> items(count);
+    std::vector<int64_t> pre(count + 1);
+    int64_t blk = 0;
+    for (int q = 0; q < count; ++q) {
+        int j = j0 + q;
+        const fhw_geom_entry& ge = c->geoms[c->Ns[j]];
+        items[q] = fhw_assemble_item{ge.geom, ge.R, ge.logtab, A_off[q], g_off[q], c->Ns[j], c->kappa[j], c->eta[j]};
+        pre[q] = blk;
+        blk += assemble_blocks_for(c->Ns[j]);
+    }
+    pre[count] = blk;
+    size_t oi = 0, op = align_up(sizeof(fhw_assemble_item) * count, 256);
+    int rc = fhw_ensure_scratch(c, op + 8 * (count + 1));
+    if (rc) return rc;
+    char* sb = (char*)c->scratch;
+    FHW_HIP(c, hipMemcpyAsync(sb + oi, items.data(), sizeof(fhw_assemble_item) * count, hipMemcpyHostToDevice,
+                              c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + op, pre.data(), 8 * (count + 1), hipMemcpyHostToDevice, c->stream));
+    STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, (const fhw_assemble_item*)(sb + oi), (const int64_t*)(sb + op), count,
+                                      blk, c->prob.direction[0], c->prob.direction[1], A, nullptr, g));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+static int upload_batch(fhw_ctx* c, int32_t batch, const int32_t* N, const int64_t* a_off, const int64_t* piv_off,
+                        const int64_t* linv_off, const int64_t* v_off, const std::vector<int32_t>* prefix,
+                        fhw_batch_dev& bd, int32_t** d_prefix) {
+    size_t o[7];
+    size_t pos = 0;
+    auto nxt = [&](size_t bytes) { size_t r = align_up(pos, 256); pos = r + bytes; return r; };
+    o[0] = nxt(4 * batch);
+    o[1] = nxt(8 * batch);
+    o[2] = nxt(8 * batch);
+    o[3] = nxt(8 * batch);
+    o[4] = nxt(8 * batch);
+    o[5] = nxt(prefix ? 4 * std::max<size_t>(1, prefix->size()) : 4);
+    o[6] = nxt(16);   // status
+    int rc = fhw_ensure_scratch(c, pos);
+    if (rc) return rc;
+    char* sb = (char*)c->scratch;
+    std::vector<int64_t> zero(batch, 0);
+    FHW_HIP(c, hipMemcpyAsync(sb + o[0], N, 4 * batch, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o[1], a_off, 8 * batch, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o[2], piv_off ? piv_off : zero.data(), 8 * batch, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o[3], linv_off ? linv_off : zero.data(), 8 * batch, hipMemcpyHostToDevice,
+                              c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o[4], v_off ? v_off : zero.data(), 8 * batch, hipMemcpyHostToDevice, c->stream));
+    if (prefix && !prefix->empty())
+        FHW_HIP(c, hipMemcpyAsync(sb + o[5], prefix->data(), 4 * prefix->size(), hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemsetAsync(sb + o[6], 0, 16, c->stream));
+    bd = fhw_batch_dev{(const int32_t*)(sb + o[0]), (const int64_t*)(sb + o[1]), (const int64_t*)(sb + o[2]),
+                       (const int64_t*)(sb + o[3]), (const int64_t*)(sb + o[4]), batch};
+    if (d_prefix) *d_prefix = (int32_t*)(sb + o[5]);
+    // status word at o[6]
+    c->status_len = o[6];
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_lu_factor(fhw_ctx* c, int32_t batch, const int32_t* N, const int64_t* A_off, void* A, const int64_t* piv_off,
+                  int32_t* piv, const int64_t* linv_off, void* linv, int32_t precision) {
+    if (!c) return FHW_E_INVALID;
+    if (batch < 0 || (batch > 0 && (!N || !A_off || !A || !piv_off || !piv || !linv_off || !linv)))
+        return fhw_fail(c, FHW_E_INVALID, "lu_factor: bad arguments");
+    if (precision != FHW_FP64 && precision != FHW_FP32_REFINE)
+        return fhw_fail(c, FHW_E_INVALID, "lu_factor: unknown precision");
+    if (batch == 0) return FHW_OK;
+    for (int q = 0; q < batch; ++q)
+        if (N[q] < 1 || N[q] > 4096) return fhw_fail(c, FHW_E_INVALID, "lu_factor: need 1 <= N <= 4096");
+    fhw_lu_sched sch;
+    lu_build_schedule(N, batch, sch);
+    fhw_batch_dev bd;
+    int32_t* d_prefix = nullptr;
+    int rc = upload_batch(c, batch, N, A_off, piv_off, linv_off, nullptr, &sch.prefix, bd, &d_prefix);
+    if (rc) return rc;
+    int32_t* d_st = (int32_t*)((char*)c->scratch + c->status_len);
+    FHW_HIP(c, launch_lu_factor(c->stream, bd, sch, d_prefix, A, piv, linv, d_st, precision, &c->prof));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    int32_t st = 0;
+    FHW_HIP(c, hipMemcpy(&st, d_st, 4, hipMemcpyDeviceToHost));
+    if (st) return fhw_fail(c, FHW_E_SINGULAR, "lu_factor: exactly zero pivot");
+    return FHW_OK;
+}
+
+int fhw_lu_solve(fhw_ctx* c, int32_t batch, const int32_t* N, const int64_t* A_off, const void* LU,
+                 const int64_t* piv_off, const int32_t* piv, const int64_t* linv_off, const void* linv,
+                 const int64_t* b_off, void* b, int32_t precision) {
+    if (!c) return FHW_E_INVALID;
+    if (batch < 0 || (batch > 0 && (!N || !A_off || !LU || !piv_off || !piv || !linv_off || !linv || !b_off || !b)))
+        return fhw_fail(c, FHW_E_INVALID, "lu_solve: bad arguments");
+    if (precision != FHW_FP64 && precision != FHW_FP32_REFINE)
+        return fhw_fail(c, FHW_E_INVALID, "lu_solve: unknown precision");
+    if (batch == 0) return FHW_OK;
+    int32_t maxN = 0;
+    for (int q = 0; q < batch; ++q) {
+        if (N[q] < 1 || N[q] > 4096) return fhw_fail(c, FHW_E_INVALID, "lu_solve: need 1 <= N <= 4096");
+        maxN = std::max(maxN, N[q]);
+    }
+    if ((size_t)maxN * 16 + 2048 > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "lu_solve: N too large");
+    fhw_batch_dev bd;
+    int rc = upload_batch(c, batch, N, A_off, piv_off, linv_off, b_off, nullptr, bd, nullptr);
+    if (rc) return rc;
+    STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, maxN, LU, piv, linv, b, nullptr, precision));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_window_spectra(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, int64_t k_first, int32_t count,
+                       void* B) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "window_spectra: no plan");
+    if (!sig || !win || count < 0 || (count > 0 && (!B || !sig->f)) || sig->n < 2 || !(sig->dt > 0) || !(win->H > 0))
+        return fhw_fail(c, FHW_E_INVALID, "window_spectra: bad arguments");
+    STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, win->H, k_first, nullptr, count,
+                                     c->prob.W, c->prob.F, B));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_fourier_coefficients(fhw_ctx* c, const void* B, int32_t count, const void* V, int32_t N_r, double tau0,
+                             void* cc) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "fourier_coefficients: no plan");
+    const int M = 2 * c->prob.F;
+    if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: 2F must be a power of two");
+    if (count < 0 || N_r < 0 || ((count > 0 && N_r > 0) && (!B || !V || !cc)) || !isfinite(tau0))
+        return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: bad arguments");
+    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, B, count, V, N_r, c->prob.W, c->prob.F, tau0, cc));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+int fhw_hankel01(fhw_ctx* c, const double* z, int64_t n, void* h) {
+    if (!c) return FHW_E_INVALID;
+    if (n < 0 || (n > 0 && (!z || !h))) return fhw_fail(c, FHW_E_INVALID, "hankel01: bad arguments");
+    FHW_HIP(c, launch_hankel01(c->stream, z, n, h));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Device helpers shared by the gfx950 kernels: complex arithmetic and the
+// in-register FP64 Bessel/Hankel evaluation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bessel_tables.h"
+
+#define FHW_PI 3.14159265358979323846
+#define FHW_INV_SQRT2 0.70710678118654752440
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cpx {
+    T re, im;
+};
+typedef cpx<double> zd;
+typedef cpx<float> zf;
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmk(T r, T i) { cpx<T> z; z.re = r; z.im = i; return z; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return cmk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return cmk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// a - b*c
+template <typename T>
+__device__ __forceinline__ cpx<T> cfms(cpx<T> a, cpx<T> b, cpx<T> c) {
+    return cmk(a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re);
+}
+// a + b*c
+template <typename T>
+__device__ __forceinline__ cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> c) {
+    return cmk(a.re + b.re * c.re - b.im * c.im, a.im + b.re * c.im + b.im * c.re);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return cmk(a.re, -a.im); }
+template <typename T>
+__device__ __forceinline__ T cabs1(cpx<T> a) { return fabs(a.re) + fabs(a.im); }
+// 1/a by scaling (Smith-free: |a| is O(1) for pivots of these systems, but
+// scale anyway to avoid overflow/underflow in |a|^2)
+template <typename T>
+__device__ __forceinline__ cpx<T> crcp(cpx<T> a) {
+    T s = fmax(fabs(a.re), fabs(a.im));
+    T ar = a.re / s, ai = a.im / s;
+    T d = s * (ar * ar + ai * ai);
+    return cmk(ar / d, -ai / d);
+}
+
+// ---------------------------------------------------------------------------
+// J0, Y0, J1, Y1 for z > 0 in FP64 (tables and regions in bessel_tables.h)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fhw_horner(const double* c, int n, double y) {
+    double acc = c[n - 1];
+    for (int k = n - 2; k >= 0; --k) acc = fma(acc, y, c[k]);
+    return acc;
+}
+
+__device__ __forceinline__ double fhw_clenshaw(const double* c, int n, double u) {
+    double b1 = 0.0, b2 = 0.0;
+    double u2 = 2.0 * u;
+    for (int k = n - 1; k >= 1; --k) {
+        double t = fma(u2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = t;
+    }
+    return fma(u, b1, c[0] - b2);
+}
+
+// Auxiliary P_nu, Q_nu (H_nu = sqrt(2/(pi z)) (P + iQ) e^{i(z - nu pi/2 - pi/4)})
+// for z > FHW_BES_Z_SERIES.  want1: also nu = 1.
+template <bool want1>
+__device__ __forceinline__ void fhw_bes_pq(double z, double& P0, double& Q0, double& P1, double& Q1) {
+    if (z >= FHW_BES_Z_ASYM) {
+        double iz = 1.0 / z;
+        double y = iz * iz;
+        P0 = fhw_horner(fhw_bes_asym_p0, FHW_BES_N_ASYM, y);
+        Q0 = iz * fhw_horner(fhw_bes_asym_q0, FHW_BES_N_ASYM, y);
+        if (want1) {
+            P1 = fhw_horner(fhw_bes_asym_p1, FHW_BES_N_ASYM, y);
+            Q1 = iz * fhw_horner(fhw_bes_asym_q1, FHW_BES_N_ASYM, y);
+        }
+        return;
+    }
+    int iv = 0;
+#pragma unroll
+    for (int q = 1; q < FHW_BES_N_INTERVALS; ++q) iv += (z >= fhw_bes_breaks[q]) ? 1 : 0;
+    double xa = 1.0 / fhw_bes_breaks[iv + 1], xb = 1.0 / fhw_bes_breaks[iv];
+    double u = (2.0 / z - (xa + xb)) / (xb - xa);
+    const double* c = fhw_bes_cheb + iv * 4 * FHW_BES_N_CHEB;
+    P0 = fhw_clenshaw(c, FHW_BES_N_CHEB, u);
+    Q0 = fhw_clenshaw(c + FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
+    if (want1) {
+        P1 = fhw_clenshaw(c + 2 * FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
+        Q1 = fhw_clenshaw(c + 3 * FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
+    }
+}
+
+// All four of J0, Y0, J1, Y1 at z > 0.
+__device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, double& J1, double& Y1) {
+    if (z <= FHW_BES_Z_SERIES) {
+        double y = 0.25 * z * z;
+        double j0 = fhw_horner(fhw_bes_series_j0, FHW_BES_N_SERIES, y);
+        double s0 = fhw_horner(fhw_bes_series_s0, FHW_BES_N_SERIES, y);
+        double j1 = 0.5 * z * fhw_horner(fhw_bes_series_j1, FHW_BES_N_SERIES, y);
+        double s1 = fhw_horner(fhw_bes_series_s1, FHW_BES_N_SERIES, y);
+        double lg = log(0.5 * z);
+        J0 = j0;
+        Y0 = (2.0 / FHW_PI) * ((lg + fhw_bes_euler_gamma) * j0 + s0);
+        J1 = j1;
+        Y1 = (2.0 / FHW_PI) * lg * j1 - 2.0 / (FHW_PI * z) - (z / (2.0 * FHW_PI)) * s1;
+        return;
+    }
+    double P0, Q0, P1, Q1;
+    fhw_bes_pq<true>(z, P0, Q0, P1, Q1);
+    double s, c;
+    sincos(z, &s, &c);
+    double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;   // cos, sin of z - pi/4
+    double c1 = s0, s1 = -c0;                                            // cos, sin of z - 3pi/4
+    double amp = sqrt(2.0 / (FHW_PI * z));
+    J0 = amp * (P0 * c0 - Q0 * s0);
+    Y0 = amp * (P0 * s0 + Q0 * c0);
+    J1 = amp * (P1 * c1 - Q1 * s1);
+    Y1 = amp * (P1 * s1 + Q1 * c1);
+}
+
+// J0, Y0 only (H0 = J0 + i Y0).
+__device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0) {
+    if (z <= FHW_BES_Z_SERIES) {
+        double y = 0.25 * z * z;
+        double j0 = fhw_horner(fhw_bes_series_j0, FHW_BES_N_SERIES, y);
+        double s0 = fhw_horner(fhw_bes_series_s0, FHW_BES_N_SERIES, y);
+        J0 = j0;
+        Y0 = (2.0 / FHW_PI) * ((log(0.5 * z) + fhw_bes_euler_gamma) * j0 + s0);
+        return;
+    }
+    double P0, Q0, P1, Q1;
+    fhw_bes_pq<false>(z, P0, Q0, P1, Q1);
+    double s, c;
+    sincos(z, &s, &c);
+    double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;
+    double amp = sqrt(2.0 / (FHW_PI * z));
+    J0 = amp * (P0 * c0 - Q0 * s0);
+    Y0 = amp * (P0 * s0 + Q0 * c0);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level reductions (64 lanes), fixed order => deterministic
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}

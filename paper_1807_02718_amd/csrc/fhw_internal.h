@@ -1,0 +1,173 @@
+// Host-side internals of libfhw: context, plan, and the kernel launchers
+// each .hip translation unit provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fhw.h"
+
+// Outer LU panel width (columns per panel factorization / trailing update).
+#define FHW_LU_NB 64
+
+struct fhw_batch_dev {
+    // device arrays describing a ragged batch of square matrices
+    const int32_t* N;         // [batch]
+    const int64_t* a_off;     // [batch] element offsets of the matrices
+    const int64_t* piv_off;   // [batch]
+    const int64_t* linv_off;  // [batch]
+    const int64_t* v_off;     // [batch] vector offsets
+    int32_t batch;
+};
+
+struct fhw_geom_entry {
+    int32_t N;
+    double* geom;    // [9][N]
+    double* R;       // [N]
+    double* logtab;  // [N]
+};
+
+// Per-stage launch timers (HIP events on the context stream).
+struct fhw_prof {
+    bool on = false;
+    struct rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<rec> recs;
+    std::vector<hipEvent_t> pool;
+    int open_stage = -1;
+    hipEvent_t open_a = nullptr;
+    hipEvent_t take();
+    void begin(int stage, hipStream_t s);
+    void end(hipStream_t s);
+};
+// helpers usable with a null profiler
+inline void prof_begin(fhw_prof* p, int stage, hipStream_t s) {
+    if (p && p->on) p->begin(stage, s);
+}
+inline void prof_end(fhw_prof* p, hipStream_t s) {
+    if (p && p->on) p->end(s);
+}
+
+struct fhw_ctx {
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    std::string err;
+    int device = 0;
+
+    // plan
+    bool planned = false;
+    fhw_problem prob{};
+    std::vector<double> cx, sx, cy, sy;
+    int32_t degree = 0;
+    double length = 0.0;
+    std::vector<double> kappa, eta;
+    std::vector<int32_t> Ns;
+    std::vector<int64_t> psi_off;
+    std::map<int32_t, fhw_geom_entry> geoms;
+    double* d_curve = nullptr;  // [4][degree+1]
+
+    // solve workspace (one chunk of frequencies)
+    int32_t chunk = 0;                 // max frequencies per chunk
+    size_t ws_A64 = 0, ws_A32 = 0, ws_linv = 0, ws_piv = 0;   // element counts
+    void* A64 = nullptr;               // complex128 matrices
+    void* A32 = nullptr;               // complex64 copies (FP32 path)
+    void* linv = nullptr;              // inverse diagonal blocks (factor type)
+    int32_t* piv = nullptr;
+    void* x = nullptr;                 // complex128 work vectors [chunk rhs]
+    void* r = nullptr;                 // complex128 residual vectors
+    void* meta = nullptr;              // per-chunk device metadata
+    size_t meta_bytes = 0;
+    int32_t* d_status = nullptr;       // [0]: singular flag, [1..]: per-matrix flags
+    size_t status_len = 0;
+    double* d_norms = nullptr;         // [chunk][2] residual norms
+    int32_t* d_done = nullptr;         // [chunk]
+    int32_t* d_sweeps = nullptr;       // [chunk]
+
+    fhw_prof prof;
+
+    // generic scratch (synthesis)
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+int fhw_fail(fhw_ctx* ctx, int code, const std::string& msg);
+int fhw_hip_check(fhw_ctx* ctx, hipError_t e, const char* what);
+int fhw_ensure_scratch(fhw_ctx* ctx, size_t bytes);
+#define FHW_HIP(ctx, call)                                                 \
+    do {                                                                   \
+        hipError_t _e = (call);                                            \
+        if (_e != hipSuccess) return fhw_hip_check((ctx), _e, #call);      \
+    } while (0)
+
+// --- geometry.hip -----------------------------------------------------------
+hipError_t launch_geometry(hipStream_t s, const double* curve, int32_t degree, int32_t N, double* geom);
+hipError_t launch_kress(hipStream_t s, int32_t N, double* R, double* logtab);
+
+// --- assemble.hip -----------------------------------------------------------
+struct fhw_assemble_item {
+    const double* geom;    // [9][N]
+    const double* R;       // [N]
+    const double* logtab;  // [N]
+    int64_t a_off, g_off;  // element offsets (complex)
+    int32_t N;
+    double kappa, eta;
+};
+// write complex128 A (and optionally a complex64 copy A32 at the same offsets)
+// and the plane-wave RHS g; d_prefix[q] = first block of item q
+hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_items, const int64_t* d_prefix,
+                                  int32_t n_items, int64_t total_blocks, double p1, double p2, void* A,
+                                  void* A32, void* g);
+int64_t assemble_blocks_for(int32_t N);
+
+// --- lu.hip -----------------------------------------------------------------
+struct fhw_lu_sched {
+    // host-built launch schedule for one batched factorization
+    int32_t nsteps;
+    std::vector<int32_t> R, W;               // per step: rows/thread, sub-panel width
+    std::vector<int64_t> gemm_trsm_off, gemm_upd_off;   // per step: offsets into d_prefix
+    std::vector<int32_t> gemm_trsm_tiles, gemm_upd_tiles, swap_blocks;
+    std::vector<int64_t> swap_off;
+    std::vector<int32_t> prefix;             // concatenated prefix arrays
+};
+void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch);
+hipError_t launch_lu_factor(hipStream_t s, const fhw_batch_dev& b, const fhw_lu_sched& sch,
+                            const int32_t* d_prefix, void* A, int32_t* piv, void* linv,
+                            int32_t* d_status, int precision, fhw_prof* prof);
+hipError_t launch_lu_solve(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU,
+                           const int32_t* piv, const void* linv, void* x, const int32_t* d_skip,
+                           int precision);
+// as launch_lu_solve, but when acc != NULL adds the solution into acc (same
+// offsets) and leaves x holding its input
+hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU,
+                               const int32_t* piv, const void* linv, void* x, void* acc,
+                               const int32_t* d_skip, int precision);
+hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64,
+                             const void* x, const void* g, void* r, double* norms, double tol,
+                             int32_t* done, int32_t* sweeps, int sweep);
+hipError_t launch_convert_c128_c64(hipStream_t s, const void* src, void* dst, int64_t n);
+
+// --- field.hip --------------------------------------------------------------
+struct fhw_field_item {
+    const double* geom;
+    int64_t psi_off;
+    int32_t N;
+    double kappa;
+};
+hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
+                        const double* obs, int32_t N_r, double zero_value, void* V);
+hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
+
+// --- synth.hip --------------------------------------------------------------
+hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, double t0, double dt,
+                                 double H, int64_t k_first, const int64_t* d_klist, int32_t count,
+                                 double W, int32_t F, void* B);
+hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V,
+                                 int32_t N_r, double W, int32_t F, double tau0, void* c);
+hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min,
+                        int64_t k_max, int32_t n_slots, int32_t N_r, const double* times,
+                        int32_t N_t, double W, int32_t F, double H, double tau0, double* u);

@@ -1,0 +1,71 @@
+// Layer-potential evaluation of the frequency-domain field (eqs.
+// freq_domain_repr and Ukslow_repr, step F5):
+//   V(r, omega_j) = int_Gamma psi_j G dsigma
+//               ~= (2 pi / N_j) sum_i (i/4) H0(kappa_j |r - x_i|) |x'_i| psi_j,i
+// written on the full DFT grid with V(r, -omega) = conj V(r, omega) and the
+// omega = 0 entry set by the caller.
+#include "fhw_device.h"
+#include "fhw_internal.h"
+
+// One wave per (observation point, frequency); lanes stride over the nodes,
+// fixed-order wave reduction.
+__global__ __launch_bounds__(256) void k_field(const fhw_field_item* __restrict__ items, int F,
+                                               const zd* __restrict__ psi, const double* __restrict__ obs, int N_r,
+                                               double zero_value, zd* __restrict__ V) {
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= N_r * F) return;
+    const int r = wave / F;
+    const int j = wave - r * F;           // frequency index, omega = (j+1) W/F
+    const fhw_field_item it = items[j];
+    const int N = it.N;
+    const double* x1 = it.geom;
+    const double* x2 = it.geom + N;
+    const double* sp = it.geom + 6 * N;
+    const zd* ps = psi + it.psi_off;
+    const double o1 = obs[2 * r], o2 = obs[2 * r + 1];
+    zd acc = cmk(0.0, 0.0);
+    for (int i = lane; i < N; i += 64) {
+        const double d1 = o1 - x1[i], d2 = o2 - x2[i];
+        const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
+        double J0, Y0;
+        fhw_bessel0(z, J0, Y0);
+        // (i/4) H0 = (-Y0/4, J0/4), weighted by |x'_i|
+        const zd gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
+        acc = cfma(acc, gk, ps[i]);
+    }
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) {
+        const double wq = 2.0 * FHW_PI / (double)N;
+        const zd val = cmk(wq * acc.re, wq * acc.im);
+        zd* Vr = V + (int64_t)r * 2 * F;
+        if (j < F - 1) Vr[F + 1 + j] = val;   // omega = (j+1) dw
+        Vr[F - 1 - j] = cconj(val);          // omega = -(j+1) dw
+        if (j == 0) Vr[F] = cmk(zero_value, 0.0);
+    }
+}
+
+__global__ void k_hankel01(const double* __restrict__ z, int64_t n, zd* __restrict__ h) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double J0, Y0, J1, Y1;
+    fhw_bessel01(z[i], J0, Y0, J1, Y1);
+    h[2 * i] = cmk(J0, Y0);
+    h[2 * i + 1] = cmk(J1, Y1);
+}
+
+hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi, const double* obs,
+                        int32_t N_r, double zero_value, void* V) {
+    const int64_t waves = (int64_t)N_r * F;
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_field, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items, F, (const zd*)psi, obs,
+                       N_r, zero_value, (zd*)V);
+    return hipGetLastError();
+}
+
+hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hankel01, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, (zd*)h);
+    return hipGetLastError();
+}

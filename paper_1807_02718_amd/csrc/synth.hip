@@ -1,0 +1,187 @@
+// Frequency-to-time synthesis with windowing and recentring (Sec. 3, Sec. 4.1):
+//   B_k^slow(omega_l) = int w(t) a(t + s_k) e^{i omega_l t} dt         (eq. Bkslow_eqn)
+//   c_{k,m}(r): Fourier coefficients on [-W, W) of
+//               B_k^slow(omega) V(r, omega) e^{-i omega tau0}         (eq. fourier_approx, T1a)
+//   u(r, t) = Re sum_{k active} (W/pi) sum_m c_{k,m}(r) sinc(W (t - s_k - tau0)/pi - m)
+//                                                  (eqs. approx, discConv, ukW, final_u; T2, T5)
+#include "fhw_device.h"
+#include "fhw_internal.h"
+
+#define SYN_THREADS 256
+#define WS_CHUNK 2048
+
+// Partition-of-unity window (eq. window_func) with eta(u) = exp(2 e^{-1/u}/(u-1)).
+__device__ __forceinline__ double fhw_eta(double u) {
+    if (u <= 0.0) return 1.0;
+    if (u >= 1.0) return 0.0;
+    return exp(2.0 * exp(-1.0 / u) / (u - 1.0));
+}
+__device__ __forceinline__ double fhw_window(double t, double H) {
+    const double h2 = 0.5 * H;
+    if (t >= -H && t <= -h2) return 1.0 - fhw_eta((t + H) / h2);
+    if (t > -h2 && t < h2) return 1.0;
+    if (t >= h2 && t <= H) return fhw_eta((t - h2) / h2);
+    return 0.0;
+}
+
+// grid (count, ceil(2F / 256)); thread = one grid frequency omega_l.
+__global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __restrict__ f, int64_t n, double t0,
+                                                                double dt, double H, int64_t k_first,
+                                                                const int64_t* __restrict__ klist, double W, int F,
+                                                                zd* __restrict__ B) {
+    __shared__ double wa[WS_CHUNK];
+    __shared__ double tau[WS_CHUNK];
+    const int q = blockIdx.x;
+    const int64_t k = klist ? klist[q] : (k_first + q);
+    const double sk = 1.5 * H * ((double)k - 1.0);
+    const int M = 2 * F;
+    const int l = blockIdx.y * SYN_THREADS + threadIdx.x;
+    const double dw = W / (double)F;
+    const double om = -W + dw * (double)l;
+    int64_t n_lo = (int64_t)floor((sk - H - t0) / dt) - 1;
+    int64_t n_hi = (int64_t)ceil((sk + H - t0) / dt) + 1;
+    if (n_lo < 0) n_lo = 0;
+    if (n_hi > n - 1) n_hi = n - 1;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t c0 = n_lo; c0 <= n_hi; c0 += WS_CHUNK) {
+        const int cnt = (int)min<int64_t>(WS_CHUNK, n_hi - c0 + 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += SYN_THREADS) {
+            const int64_t nn = c0 + i;
+            const double tn = t0 + dt * (double)nn;
+            const double tt = tn - sk;
+            tau[i] = tt;
+            wa[i] = fhw_window(tt, H) * (-f[nn]);
+        }
+        __syncthreads();
+        if (l < M) {
+            for (int i = 0; i < cnt; ++i) {
+                const double w = wa[i];
+                if (w != 0.0) {
+                    double s, c;
+                    sincos(om * tau[i], &s, &c);
+                    ar = fma(w, c, ar);
+                    ai = fma(w, s, ai);
+                }
+            }
+        }
+    }
+    if (l < M) B[(int64_t)q * M + l] = cmk(dt * ar, dt * ai);
+}
+
+// One workgroup per (point r, window slot q): LDS radix-2 FFT of length M = 2F
+// of G_l = B_q(omega_l) V(r, omega_l) e^{-i omega_l tau0};
+// c_m = (-1)^m X[m mod M] / M stored at index m + F.
+__global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __restrict__ B, const zd* __restrict__ V,
+                                                                int N_r, double W, int F, int logM, double tau0,
+                                                                zd* __restrict__ c) {
+    extern __shared__ zd X[];
+    const int r = blockIdx.x;
+    const int q = blockIdx.y;
+    const int M = 2 * F;
+    const double dw = W / (double)F;
+    const zd* Bq = B + (int64_t)q * M;
+    const zd* Vr = V + (int64_t)r * M;
+    for (int l = threadIdx.x; l < M; l += SYN_THREADS) {
+        const double om = -W + dw * (double)l;
+        double s, cs;
+        sincos(-om * tau0, &s, &cs);
+        const zd g = cmul(cmul(Bq[l], Vr[l]), cmk(cs, s));
+        const int rev = (int)(__brev((unsigned)l) >> (32 - logM));
+        X[rev] = g;
+    }
+    __syncthreads();
+    for (int len = 2; len <= M; len <<= 1) {
+        const int half = len >> 1;
+        for (int t = threadIdx.x; t < M / 2; t += SYN_THREADS) {
+            const int grp = t / half, pos = t - grp * half;
+            const int i = grp * len + pos, j = i + half;
+            double s, cs;
+            sincospi(-2.0 * (double)pos / (double)len, &s, &cs);
+            const zd u = X[i];
+            const zd v = cmul(X[j], cmk(cs, s));
+            X[i] = cadd(u, v);
+            X[j] = csub(u, v);
+        }
+        __syncthreads();
+    }
+    zd* out = c + ((int64_t)q * N_r + r) * M;
+    const double inv = 1.0 / (double)M;
+    for (int idx = threadIdx.x; idx < M; idx += SYN_THREADS) {
+        const int m = idx - F;
+        const zd x = X[(idx + F) % M];
+        const double sg = (m & 1) ? -inv : inv;
+        out[idx] = cmk(sg * x.re, sg * x.im);
+    }
+}
+
+// One wave per (point r, time t): active windows |t - s_k - tau0| <= pi F / W,
+// lanes stride over m, fixed-order reduction.
+__global__ __launch_bounds__(SYN_THREADS) void k_synth(const zd* __restrict__ c, const int* __restrict__ slot,
+                                                       int64_t k_min, int64_t k_max, int N_r,
+                                                       const double* __restrict__ times, int N_t, double W, int F,
+                                                       double H, double tau0, double* __restrict__ u) {
+    const int64_t wave = (int64_t)blockIdx.x * (SYN_THREADS / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= (int64_t)N_r * N_t) return;
+    const int r = (int)(wave / N_t);
+    const int it = (int)(wave - (int64_t)r * N_t);
+    const double t = times[it];
+    const int M = 2 * F;
+    const double P = FHW_PI / (W / (double)F);
+    const double span = 1.5 * H;
+    const int64_t ka = (int64_t)floor((t - tau0 - P) / span) + 1 - 1;
+    const int64_t kb = (int64_t)ceil((t - tau0 + P) / span) + 1 + 1;
+    double acc = 0.0;
+    for (int64_t k = ka; k <= kb; ++k) {
+        if (k < k_min || k > k_max) continue;
+        const int sl = slot[k - k_min];
+        if (sl < 0) continue;
+        const double sk = 1.5 * H * ((double)k - 1.0);
+        if (!(fabs(t - sk - tau0) <= P)) continue;
+        const double x = W * (t - sk - tau0) / FHW_PI;
+        const double sx = sinpi(x);
+        const zd* ck = c + ((int64_t)sl * N_r + r) * M;
+        for (int idx = lane; idx < M; idx += 64) {
+            const int m = idx - F;
+            const double y = x - (double)m;
+            const double term = (y == 0.0) ? 1.0 : ((m & 1) ? -sx : sx) / (FHW_PI * y);
+            acc = fma(ck[idx].re, term, acc);
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) u[(int64_t)r * N_t + it] = (W / FHW_PI) * acc;
+}
+
+hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, double t0, double dt, double H,
+                                 int64_t k_first, const int64_t* d_klist, int32_t count, double W, int32_t F,
+                                 void* B) {
+    if (count <= 0) return hipSuccess;
+    dim3 grid(count, (2 * F + SYN_THREADS - 1) / SYN_THREADS);
+    hipLaunchKernelGGL(k_window_spectra, grid, dim3(SYN_THREADS), 0, s, f, n, t0, dt, H, k_first, d_klist, W, F,
+                       (zd*)B);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V, int32_t N_r, double W,
+                                 int32_t F, double tau0, void* c) {
+    if (count <= 0 || N_r <= 0) return hipSuccess;
+    const int M = 2 * F;
+    int logM = 0;
+    while ((1 << logM) < M) ++logM;
+    size_t lds = (size_t)M * sizeof(zd);
+    hipLaunchKernelGGL(k_fourier_coeffs, dim3(N_r, count), dim3(SYN_THREADS), lds, s, (const zd*)B, (const zd*)V,
+                       N_r, W, F, logM, tau0, (zd*)c);
+    return hipGetLastError();
+}
+
+hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min, int64_t k_max,
+                        int32_t n_slots, int32_t N_r, const double* times, int32_t N_t, double W, int32_t F, double H,
+                        double tau0, double* u) {
+    (void)n_slots;
+    const int64_t waves = (int64_t)N_r * N_t;
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_synth, dim3((unsigned)((waves + 3) / 4)), dim3(SYN_THREADS), 0, s, (const zd*)c, d_slot,
+                       k_min, k_max, N_r, times, N_t, W, F, H, tau0, u);
+    return hipGetLastError();
+}

@@ -1,0 +1,291 @@
+"""Thin ctypes binding of libfhw (include/fhw.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libfhw.so.  PyTorch supplies device memory and the HIP stream.  Importing this
+module without a built library raises immediately -- there is no fallback.
+
+Module-level functions carry the C names (fhw_plan, fhw_solve_densities, ...);
+`Context` wraps them with tensor allocation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhw.so")
+
+FHW_OK = 0
+FHW_E_INVALID = -1
+FHW_E_NOMEM = -2
+FHW_E_HIP = -3
+FHW_E_SINGULAR = -4
+FHW_E_NOCONV = -5
+FHW_E_STATE = -6
+FHW_FP64 = 0
+FHW_FP32_REFINE = 1
+
+_dp = C.POINTER(C.c_double)
+
+
+class fhw_curve(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("cx", _dp), ("sx", _dp), ("cy", _dp), ("sy", _dp)]
+
+
+class fhw_problem(C.Structure):
+    _fields_ = [("W", C.c_double), ("F", C.c_int32), ("c", C.c_double), ("N_fixed", C.c_int32),
+                ("ppw", C.c_double), ("n_min", C.c_int32), ("n_mult", C.c_int32), ("n_cap", C.c_int32),
+                ("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_max", C.c_int32),
+                ("direction", C.c_double * 2)]
+
+
+class fhw_signal(C.Structure):
+    _fields_ = [("t0", C.c_double), ("dt", C.c_double), ("n", C.c_int64), ("f", C.c_void_p)]
+
+
+class fhw_windows(C.Structure):
+    _fields_ = [("H", C.c_double), ("tau0", C.c_double)]
+
+
+class FhwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libfhw error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfhw.so not built at {LIB_PATH}; run python -m paper_1807_02718_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    p_i32, p_i64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "fhw_create": [C.POINTER(vp), vp, sz],
+        "fhw_destroy": [vp],
+        "fhw_version": [],
+        "fhw_plan": [vp, C.POINTER(fhw_curve), C.POINTER(fhw_problem), p_i32, p_i64],
+        "fhw_solve_densities": [vp, vp, _dp, p_i32, i32],
+        "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
+        "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
+        "fhw_geometry": [vp, i32, vp],
+        "fhw_kress_weights": [vp, i32, vp, vp],
+        "fhw_assemble": [vp, i32, i32, vp, p_i64, vp, p_i64],
+        "fhw_lu_factor": [vp, i32, p_i32, p_i64, vp, p_i64, vp, p_i64, vp, i32],
+        "fhw_lu_solve": [vp, i32, p_i32, p_i64, vp, p_i64, vp, p_i64, vp, p_i64, vp, i32],
+        "fhw_window_spectra": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), i64, i32, vp],
+        "fhw_fourier_coefficients": [vp, vp, i32, vp, i32, C.c_double, vp],
+        "fhw_hankel01": [vp, vp, i64, vp],
+        "fhw_profile": [vp, i32],
+        "fhw_profile_read": [vp, _dp, p_i64],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.fhw_last_error.argtypes = [vp]
+    lib.fhw_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_solve_densities",
+            "fhw_eval_field", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
+            "fhw_profile", "fhw_profile_read")
+STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_swap", "lu_trsm", "lu_update", "solve", "residual",
+          "field", "spectra", "coeffs", "synth")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("device tensor expected")
+        if not t.is_contiguous():
+            raise ValueError("contiguous tensor expected")
+        return C.c_void_p(t.data_ptr())
+    raise TypeError(type(t))
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    return a, a.ctypes.data_as(C.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A libfhw context bound to one HIP stream."""
+
+    def __init__(self, stream=None, hbm_budget_bytes=0, device=None):
+        if device is not None:
+            torch.cuda.set_device(device)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = _lib.fhw_create(C.byref(h), _stream_handle(self.stream), hbm_budget_bytes)
+        if rc != FHW_OK:
+            raise FhwError(rc, "fhw_create failed")
+        self._h = h
+        self.F = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fhw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != FHW_OK:
+            raise FhwError(rc, _lib.fhw_last_error(self._h).decode())
+
+    # -- plan -----------------------------------------------------------------
+    def plan(self, curve, W, F, N=None, c=1.0, ppw=10.0, n_min=64, n_mult=32, n_cap=4096, precision="fp64",
+             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0)):
+        self._cv = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in
+                    (curve.cx, curve.sx, curve.cy, curve.sy)]
+        cs = fhw_curve(len(self._cv[0]) - 1, *[v.ctypes.data_as(_dp) for v in self._cv])
+        pr = fhw_problem()
+        pr.W, pr.F, pr.c = float(W), int(F), float(c)
+        pr.N_fixed = int(N) if N is not None else 0
+        pr.ppw, pr.n_min, pr.n_mult, pr.n_cap = float(ppw), int(n_min), int(n_mult), int(n_cap)
+        pr.precision = {"fp64": FHW_FP64, "fp32_refine": FHW_FP32_REFINE}[precision]
+        pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
+        pr.direction[0], pr.direction[1] = float(direction[0]), float(direction[1])
+        Ns = np.zeros(F, dtype=np.int32)
+        off = np.zeros(F + 1, dtype=np.int64)
+        self._check(_lib.fhw_plan(self._h, C.byref(cs), C.byref(pr), Ns.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  off.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.F, self.W, self.Ns, self.psi_off = int(F), float(W), Ns, off
+        self.precision = precision
+        return Ns, off
+
+    # -- hot path ---------------------------------------------------------------
+    def solve_densities(self, psi=None, compute_resid=False):
+        if psi is None:
+            psi = torch.empty(int(self.psi_off[-1]), dtype=torch.complex128, device=self.device)
+        resid = np.zeros(self.F)
+        sweeps = np.zeros(self.F, dtype=np.int32)
+        self._check(_lib.fhw_solve_densities(self._h, _ptr(psi), resid.ctypes.data_as(_dp),
+                                             sweeps.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(compute_resid))))
+        return psi, resid, sweeps
+
+    def eval_field(self, psi, obs, zero_value=1.0, V=None):
+        obs_h, obs_p = _host(obs, np.float64)
+        Nr = obs_h.shape[0]
+        if V is None:
+            V = torch.empty((Nr, 2 * self.F), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_eval_field(self._h, _ptr(psi), obs_p, Nr, float(zero_value), _ptr(V)))
+        return V
+
+    def synthesize(self, f, t0, dt, H, tau0, V, times, u=None):
+        f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
+        sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
+        wn = fhw_windows(float(H), float(tau0))
+        th, tp = _host(times, np.float64)
+        Nr = V.shape[0]
+        if u is None:
+            u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_synthesize(self._h, C.byref(sg), C.byref(wn), _ptr(V), Nr, tp, len(th), _ptr(u)))
+        return u
+
+    # -- stage entry points -------------------------------------------------------
+    def geometry(self, N):
+        g = torch.empty((9, N), dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_geometry(self._h, int(N), _ptr(g)))
+        return g
+
+    def kress_weights(self, N):
+        R = torch.empty(N, dtype=torch.float64, device=self.device)
+        L = torch.empty(N, dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_kress_weights(self._h, int(N), _ptr(R), _ptr(L)))
+        return R, L
+
+    def assemble(self, j0, count):
+        Ns = self.Ns[j0:j0 + count].astype(np.int64)
+        a_off = np.concatenate([[0], np.cumsum(Ns * Ns)[:-1]]).astype(np.int64)
+        g_off = np.concatenate([[0], np.cumsum(Ns)[:-1]]).astype(np.int64)
+        A = torch.empty(int((Ns * Ns).sum()), dtype=torch.complex128, device=self.device)
+        g = torch.empty(int(Ns.sum()), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_assemble(self._h, int(j0), int(count), _ptr(A), a_off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      _ptr(g), g_off.ctypes.data_as(C.POINTER(C.c_int64))))
+        mats = [A[a_off[q]:a_off[q] + Ns[q] * Ns[q]].view(int(Ns[q]), int(Ns[q])) for q in range(count)]
+        vecs = [g[g_off[q]:g_off[q] + Ns[q]] for q in range(count)]
+        return mats, vecs
+
+    def lu_factor(self, A_flat, Ns, precision="fp64"):
+        """In-place batched LU of matrices packed in A_flat (complex128 or complex64)."""
+        Ns = np.asarray(Ns, dtype=np.int32)
+        a_off = np.concatenate([[0], np.cumsum(Ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
+        p_off = np.concatenate([[0], np.cumsum(Ns.astype(np.int64))[:-1]]).astype(np.int64)
+        l_off = np.concatenate([[0], np.cumsum(4096 * ((Ns.astype(np.int64) + 63) // 64))[:-1]]).astype(np.int64)
+        piv = torch.empty(int(Ns.sum()), dtype=torch.int32, device=self.device)
+        ltot = int((4096 * ((Ns.astype(np.int64) + 63) // 64)).sum())
+        linv = torch.empty(ltot, dtype=A_flat.dtype, device=self.device)
+        prec = {"fp64": FHW_FP64, "fp32_refine": FHW_FP32_REFINE}[precision]
+        self._check(_lib.fhw_lu_factor(self._h, len(Ns), Ns.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       a_off.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(A_flat),
+                                       p_off.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(piv),
+                                       l_off.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(linv), prec))
+        return dict(Ns=Ns, a_off=a_off, p_off=p_off, l_off=l_off, piv=piv, linv=linv, LU=A_flat, prec=prec)
+
+    def lu_solve(self, fac, b_flat):
+        Ns = fac["Ns"]
+        b_off = np.concatenate([[0], np.cumsum(Ns.astype(np.int64))[:-1]]).astype(np.int64)
+        self._check(_lib.fhw_lu_solve(self._h, len(Ns), Ns.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      fac["a_off"].ctypes.data_as(C.POINTER(C.c_int64)), _ptr(fac["LU"]),
+                                      fac["p_off"].ctypes.data_as(C.POINTER(C.c_int64)), _ptr(fac["piv"]),
+                                      fac["l_off"].ctypes.data_as(C.POINTER(C.c_int64)), _ptr(fac["linv"]),
+                                      b_off.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(b_flat), fac["prec"]))
+        return b_flat
+
+    def window_spectra(self, f, t0, dt, H, k_first, count):
+        f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
+        sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
+        wn = fhw_windows(float(H), 0.0)
+        B = torch.empty((count, 2 * self.F), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_window_spectra(self._h, C.byref(sg), C.byref(wn), int(k_first), int(count), _ptr(B)))
+        return B
+
+    def fourier_coefficients(self, B, V, tau0):
+        count, Nr = B.shape[0], V.shape[0]
+        c = torch.empty((count, Nr, 2 * self.F), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_fourier_coefficients(self._h, _ptr(B), count, _ptr(V), Nr, float(tau0), _ptr(c)))
+        return c
+
+    def profile(self, enable=True):
+        self._check(_lib.fhw_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{stage: (milliseconds, launches)} since the last read; clears the counters."""
+        ms = np.zeros(len(STAGES))
+        n = np.zeros(len(STAGES), dtype=np.int64)
+        self._check(_lib.fhw_profile_read(self._h, ms.ctypes.data_as(_dp), n.ctypes.data_as(C.POINTER(C.c_int64))))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
+
+    def hankel01(self, z):
+        z = z if isinstance(z, torch.Tensor) else torch.as_tensor(np.asarray(z, dtype=np.float64), device=self.device)
+        h = torch.empty((z.numel(), 2), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_hankel01(self._h, _ptr(z), int(z.numel()), _ptr(h)))
+        return h
+
+
+def fhw_version():
+    return _lib.fhw_version()
+
+
+def library():
+    """The loaded ctypes library (for symbol checks)."""
+    return _lib

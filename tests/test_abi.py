@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every entry point include/fhw.h declares,
+and the ctypes structs match the header's layout.  CPU only (no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fhw.h")
+LIB = os.path.join(ROOT, "paper_1807_02718_amd", "libfhw.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fhw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for n in ("fhw_create", "fhw_destroy", "fhw_plan", "fhw_solve_densities", "fhw_eval_field", "fhw_synthesize",
+              "fhw_assemble", "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients",
+              "fhw_geometry", "fhw_kress_weights"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfhw.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfhw.so not built")
+def test_binding_loads_and_covers_the_abi():
+    from paper_1807_02718_amd import fhw
+    assert sorted(fhw.EXPORTED) == declared_functions()
+    assert fhw.fhw_version() == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfhw.so not built")
+def test_struct_layouts(tmp_path):
+    """ctypes layouts equal what the C compiler makes of include/fhw.h."""
+    import subprocess
+    from paper_1807_02718_amd import fhw
+    structs = {"fhw_curve": fhw.fhw_curve, "fhw_problem": fhw.fhw_problem, "fhw_signal": fhw.fhw_signal,
+               "fhw_windows": fhw.fhw_windows}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for sname, cls in structs.items():
+        lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{sname} {fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in filter(None, out):
+        sname, field, val = line.split()
+        cls = structs[sname]
+        got = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), line
+
+
+def test_oracle_is_not_imported_by_the_product():
+    pkg = os.path.join(ROOT, "paper_1807_02718_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_bessel_tables_are_current():
+    """The generated table header matches what its generator writes now."""
+    import subprocess
+    import sys
+    import tempfile
+    csrc = os.path.join(ROOT, "paper_1807_02718_amd", "csrc")
+    with tempfile.TemporaryDirectory() as d:
+        src = open(os.path.join(csrc, "gen_bessel_tables.py")).read()
+        gen = os.path.join(d, "gen_bessel_tables.py")
+        open(gen, "w").write(src)
+        subprocess.run([sys.executable, gen], check=True, cwd=d)
+        assert open(os.path.join(d, "bessel_tables.h")).read() == open(os.path.join(csrc, "bessel_tables.h")).read()

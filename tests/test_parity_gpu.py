@@ -1,0 +1,350 @@
+"""GPU-vs-oracle parity for every step of the hot path, through the C ABI.
+
+Tolerances (relative, max norm): matrices 1e-13 (normwise per frequency),
+FP64 densities 1e-11, fields 1e-11, time samples 1e-10; Bessel values a few
+ulps plus the argument's conditioning.  Each test prints the case it runs.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy import special
+
+import oracle as O
+import workloads as Wk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fhw():
+    from paper_1807_02718_amd import fhw as m
+    return m
+
+
+@pytest.fixture
+def ctx(fhw):
+    c = fhw.Context()
+    yield c
+    c.close()
+
+
+def say(*a):
+    print("CASE", *a, flush=True)
+
+
+def relmax(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# ---------------------------------------------------------------- Bessel (a3)
+def test_hankel01_values(ctx):
+    say("hankel01")
+    brk = np.array([3.0, 4.5, 6.75, 10.0, 15.0, 25.0])
+    z = np.concatenate([np.geomspace(1e-5, 3e3, 3000), brk, np.nextafter(brk, 0), np.nextafter(brk, 10)])
+    h = ctx.hankel01(z).cpu().numpy()
+    eps = np.finfo(float).eps
+    cond = 8 * eps * np.sqrt(np.maximum(z, 1.0))
+    for col, (fj, fy) in enumerate(((special.j0, special.y0), (special.j1, special.y1))):
+        J, Y = fj(z), fy(z)
+        errJ = np.abs(h[:, col].real - J) - cond
+        errY = np.abs(h[:, col].imag - Y) - cond
+        assert np.max(errJ / np.maximum(1.0, np.abs(J))) < 6e-15
+        assert np.max(errY / np.maximum(1.0, np.abs(Y))) < 6e-15
+
+
+# ------------------------------------------------------- geometry, Kress (a1, a2)
+@pytest.mark.parametrize("curve,N", [(Wk.circle(1.0), 64), (Wk.kite(), 256), (Wk.star_pool(1, 0)[0], 96)])
+def test_geometry_and_kress(ctx, curve, N):
+    say("geometry", curve.name, N)
+    ctx.plan(curve, 10.0, 4, N=N)
+    g = ctx.geometry(N).cpu().numpy()
+    ref = O.geometry(curve, N)
+    assert np.max(np.abs(g[0:2].T - ref["x"])) < 1e-14
+    assert np.max(np.abs(g[2:4].T - ref["dx"])) < 1e-13
+    assert np.max(np.abs(g[4:6].T - ref["ddx"])) < 1e-12
+    assert np.max(np.abs(g[6] - ref["speed"])) < 1e-13
+    assert np.max(np.abs(g[7:9].T - ref["nu"])) < 1e-14
+    R, L = ctx.kress_weights(N)
+    assert np.max(np.abs(R.cpu().numpy() - O.kress_weights(N))) < 1e-14
+    assert np.max(np.abs(L.cpu().numpy()[1:] - O.kress_log_table(N)[1:])) < 1e-13
+
+
+# ------------------------------------------------------------- assembly (a3)
+@pytest.mark.parametrize("curve,W,F,N", [(Wk.circle(1.0), 20.0, 8, 128), (Wk.kite(), 40.0, 6, 256),
+                                          (Wk.star_pool(2, 0)[1], 30.0, 4, 160)])
+def test_assembly(ctx, curve, W, F, N):
+    say("assembly", curve.name, W, F, N)
+    ctx.plan(curve, W, F, N=N, direction=(0.6, 0.8))
+    mats, vecs = ctx.assemble(0, F)
+    omega, kappa = O.frequency_grid(W, F)
+    eta = O.coupling(kappa)
+    gm = O.geometry(curve, N)
+    for j in range(F):
+        A = O.assemble(gm, kappa[j], eta[j])
+        g = O.rhs_plane_wave(gm, kappa[j], eta[j], (0.6, 0.8))
+        assert relmax(mats[j].cpu().numpy(), A) < 1e-13, j
+        assert relmax(vecs[j].cpu().numpy(), g) < 1e-13, j
+
+
+def test_assembly_ragged(ctx):
+    say("assembly ragged kite")
+    Ns, off = ctx.plan(Wk.kite(), 60.0, 12, ppw=6.0, n_min=32, n_mult=32, n_cap=4096)
+    omega, kappa = O.frequency_grid(60.0, 12)
+    Nref = O.discretization_sizes(kappa, O.curve_length(Wk.kite()), 6.0, 32, 32, 4096)
+    assert np.array_equal(Ns, Nref)
+    mats, vecs = ctx.assemble(3, 9)
+    eta = O.coupling(kappa)
+    for q in range(9):
+        j = 3 + q
+        gm = O.geometry(Wk.kite(), int(Ns[j]))
+        assert relmax(mats[q].cpu().numpy(), O.assemble(gm, kappa[j], eta[j])) < 1e-13
+
+
+# ------------------------------------------------------------------- LU (a4, a5)
+def _rand_batch(Ns, seed, dtype=torch.complex128):
+    rng = np.random.default_rng(seed)
+    mats = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in Ns]
+    rhs = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in Ns]
+    flat = torch.tensor(np.concatenate([m.ravel() for m in mats]), dtype=dtype, device="cuda")
+    b = torch.tensor(np.concatenate(rhs), dtype=torch.complex128, device="cuda")
+    return mats, rhs, flat, b
+
+
+@pytest.mark.parametrize("Ns", [[1, 2, 3, 17, 63, 64, 65, 100, 128, 200, 257], [1100], [2100, 130]])
+def test_lu_random_fp64(ctx, Ns):
+    say("lu fp64", Ns)
+    mats, rhs, flat, b = _rand_batch(Ns, seed=len(Ns) + Ns[0])
+    fac = ctx.lu_factor(flat, Ns)
+    x = ctx.lu_solve(fac, b).cpu().numpy()
+    o = 0
+    for A, g, n in zip(mats, rhs, Ns):
+        ref, _ = O.solve_density(A, g)
+        xs = x[o:o + n]
+        o += n
+        cond = np.linalg.cond(A)
+        assert relmax(xs, ref) < 1e-15 * cond * n + 1e-13, (n, cond)
+        assert np.linalg.norm(A @ xs - g) / np.linalg.norm(g) < 1e-13 * max(1, n / 64)
+
+
+def test_lu_pivots_match_lapack(ctx):
+    say("lu pivots")
+    from scipy import linalg
+    Ns = [5, 64, 130]
+    mats, rhs, flat, b = _rand_batch(Ns, seed=11)
+    fac = ctx.lu_factor(flat, Ns)
+    piv = fac["piv"].cpu().numpy()
+    o = 0
+    for A, n in zip(mats, Ns):
+        _, p_ref = linalg.lu_factor(A)
+        assert np.array_equal(piv[o:o + n], p_ref), n
+        o += n
+
+
+def test_lu_random_fp32(ctx):
+    say("lu fp32")
+    Ns = [16, 64, 200, 300]
+    mats, rhs, flat, b = _rand_batch(Ns, seed=5, dtype=torch.complex64)
+    fac = ctx.lu_factor(flat, Ns, precision="fp32_refine")
+    x = ctx.lu_solve(fac, b).cpu().numpy()
+    o = 0
+    for A, g, n in zip(mats, rhs, Ns):
+        ref = np.linalg.solve(A.astype(np.complex64).astype(np.complex128), g)
+        xs = x[o:o + n]
+        o += n
+        assert relmax(xs, ref) < 3e-7 * np.linalg.cond(A), n
+
+
+def test_lu_singular_reports(ctx, fhw):
+    say("lu singular")
+    flat = torch.zeros(64 * 64, dtype=torch.complex128, device="cuda")
+    with pytest.raises(fhw.FhwError) as e:
+        ctx.lu_factor(flat, [64])
+    assert e.value.code == fhw.FHW_E_SINGULAR
+
+
+# ---------------------------------------------------------- densities (a3-a5)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_densities_circle(ctx, precision):
+    say("densities circle", precision)
+    wl = Wk.circle_pulse()
+    ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=1e-14, refine_max=8)
+    psi, res, sw = ctx.solve_densities(compute_resid=True)
+    psi = psi.cpu().numpy()
+    omega, kappa = O.frequency_grid(wl.W, wl.F)
+    eta = O.coupling(kappa)
+    gm = O.geometry(wl.curve, wl.N)
+    for j in range(wl.F):
+        ref, _ = O.solve_density(O.assemble(gm, kappa[j], eta[j]), O.rhs_plane_wave(gm, kappa[j], eta[j], (1.0, 0.0)))
+        assert relmax(psi[j * wl.N:(j + 1) * wl.N], ref) < 1e-11, j
+    assert np.all(res < 1e-13)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_densities_kite_ragged(ctx, precision):
+    say("densities kite ragged", precision)
+    W, F = 30.0, 16
+    Ns, off = ctx.plan(Wk.kite(), W, F, ppw=10.0, n_min=64, n_mult=32, n_cap=4096, precision=precision,
+                       refine_tol=1e-14, refine_max=8, direction=(0.6, 0.8))
+    psi, res, sw = ctx.solve_densities(compute_resid=True)
+    psi = psi.cpu().numpy()
+    omega, kappa = O.frequency_grid(W, F)
+    eta = O.coupling(kappa)
+    for j in range(F):
+        gm = O.geometry(Wk.kite(), int(Ns[j]))
+        ref, _ = O.solve_density(O.assemble(gm, kappa[j], eta[j]), O.rhs_plane_wave(gm, kappa[j], eta[j], (0.6, 0.8)))
+        assert relmax(psi[off[j]:off[j + 1]], ref) < 1e-11, (j, Ns[j])
+
+
+def test_densities_deterministic(ctx):
+    say("determinism")
+    ctx.plan(Wk.kite(), 20.0, 8, N=256)
+    a = ctx.solve_densities()[0].clone()
+    b = ctx.solve_densities()[0]
+    assert torch.equal(a, b)
+
+
+def test_refinement_noconv(ctx, fhw):
+    say("refine noconv")
+    ctx.plan(Wk.circle(1.0), 10.0, 2, N=64, precision="fp32_refine", refine_tol=1e-30, refine_max=0)
+    with pytest.raises(fhw.FhwError) as e:
+        ctx.solve_densities()
+    assert e.value.code == fhw.FHW_E_NOCONV
+
+
+def test_plan_rejects_bad_curves(ctx, fhw):
+    say("plan errors")
+    c = Wk.circle(1.0)
+    cw = Wk.Curve("cw", c.cx, c.sx, c.cy, -c.sy)
+    with pytest.raises(fhw.FhwError) as e:
+        ctx.plan(cw, 10.0, 4, N=64)
+    assert e.value.code == fhw.FHW_E_INVALID
+    with pytest.raises(fhw.FhwError):
+        ctx.plan(c, 10.0, 4, N=63)
+
+
+# ------------------------------------------------------------------ field (a6)
+def test_field(ctx, fhw):
+    say("field")
+    W, F = 24.0, 16
+    ctx.plan(Wk.kite(), W, F, N=256, direction=(0.6, 0.8))
+    psi, _, _ = ctx.solve_densities()
+    obs = np.concatenate([Wk.ring(12, 3.0), [[2.0, 2.0], [-0.3, 0.2]]])
+    V = ctx.eval_field(psi, obs, zero_value=1.0).cpu().numpy()
+    omega, kappa = O.frequency_grid(W, F)
+    eta = O.coupling(kappa)
+    gm = O.geometry(Wk.kite(), 256)
+    Vpos = np.zeros((len(obs), F), dtype=complex)
+    for j in range(F):
+        ref, _ = O.solve_density(O.assemble(gm, kappa[j], eta[j]), O.rhs_plane_wave(gm, kappa[j], eta[j], (0.6, 0.8)))
+        Vpos[:, j] = O.field(gm, ref, kappa[j], obs)
+    assert relmax(V, O.field_full_grid(Vpos, 1.0)) < 1e-11
+    with pytest.raises(fhw.FhwError):
+        ctx.eval_field(psi, np.array([[np.nan, 0.0]]))
+
+
+# ------------------------------------------------------- synthesis (a7-a9)
+def test_window_spectra(ctx):
+    say("window spectra")
+    sig = Wk.gaussian_pulse(t0=-1.0, t1=30.0, dt=1 / 128, center=12.0, var2=3.0, freq=5.0)
+    W, F, H = 16.0, 64, 4.0
+    ctx.plan(Wk.circle(1.0), W, F, N=32)
+    ks = O.window_indices(sig.t[0], sig.t[-1], H)
+    B = ctx.window_spectra(sig.f, sig.t0, sig.dt, H, int(ks[0]), len(ks)).cpu().numpy()
+    wl = -W + (W / F) * np.arange(2 * F)
+    ref = O.window_spectra(sig, H, ks, wl)
+    assert relmax(B, ref) < 1e-12
+
+
+def test_fourier_coefficients(ctx):
+    say("fourier coefficients")
+    W, F = 12.0, 128
+    ctx.plan(Wk.circle(1.0), W, F, N=32)
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((3, 2 * F)) + 1j * rng.standard_normal((3, 2 * F))
+    V = rng.standard_normal((5, 2 * F)) + 1j * rng.standard_normal((5, 2 * F))
+    tau0 = 1.7
+    c = ctx.fourier_coefficients(torch.tensor(B, device="cuda"), torch.tensor(V, device="cuda"), tau0).cpu().numpy()
+    wl = -W + (W / F) * np.arange(2 * F)
+    shift = np.exp(-1j * wl * tau0)
+    for q in range(3):
+        ref = O.fourier_coefficients(B[q][None, :] * V * shift[None, :], W)
+        assert relmax(c[q], ref) < 1e-13
+
+
+def _pipeline(ctx, wl, precision="fp64", obs=None, zero_value=1.0):
+    N = wl.N if not isinstance(wl.N, dict) else None
+    kw = {} if N is not None else wl.N
+    ctx.plan(wl.curve, wl.W, wl.F, N=N, precision=precision, refine_tol=1e-14, refine_max=8,
+             direction=wl.direction, **kw)
+    psi, _, _ = ctx.solve_densities()
+    obs = wl.obs if obs is None else obs
+    V = ctx.eval_field(psi, obs, zero_value=zero_value)
+    u = ctx.synthesize(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times)
+    return u.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_pipeline_circle_pulse(ctx, precision):
+    say("pipeline circle pulse", precision)
+    wl = Wk.circle_pulse()
+    u = _pipeline(ctx, wl, precision)
+    ref = O.run(wl.curve, wl.W, wl.F, wl.N, wl.direction, wl.signal, wl.H, wl.tau0, wl.obs, wl.times)
+    assert relmax(u, ref) < 1e-10
+
+
+def test_pipeline_interior_identity(ctx):
+    say("pipeline interior identity")
+    sig = Wk.gaussian_pulse(t0=0.0, t1=30.0, dt=1 / 64, center=15.0, var2=1.0, freq=10.0)
+    pts = np.array([[0.2, 0.1], [-0.5, 0.3], [0.0, -0.6]])
+    wl = Wk.Workload("circ_int", Wk.circle(1.0), 24.0, 128, 64, direction=(0.6, 0.8), H=10.0, tau0=3.0,
+                     signal=sig, obs=pts, times=np.linspace(0, 40, 81))
+    u = _pipeline(ctx, wl)
+    f = lambda t: np.exp(-(t - 15) ** 2) * np.cos(10 * t)
+    exact = np.array([-f(wl.times - x @ np.array([0.6, 0.8])) for x in pts])
+    assert np.max(np.abs(u - exact)) < 1e-9
+
+
+def test_pipeline_kite_chirp_small(ctx):
+    say("pipeline kite chirp small")
+    W, F = 25.0, 64
+    sig = Wk.chirp(300.0, np.pi / (4 * W))
+    times = np.concatenate([np.linspace(0, 100, 64), np.linspace(200, 300, 64)])
+    wl = Wk.Workload("kite_chirp_small", Wk.kite(), W, F, dict(ppw=10.0, n_min=64, n_mult=32, n_cap=4096),
+                     direction=(1.0, 0.0), H=3.0, tau0=2.25, signal=sig, obs=Wk.ring(8, 3.0), times=times)
+    u = _pipeline(ctx, wl)
+    ref = O.run(wl.curve, W, F, wl.N, wl.direction, sig, wl.H, wl.tau0, wl.obs, times)
+    assert relmax(u, ref) < 1e-10
+
+
+def test_synthesize_edge_cases(ctx, fhw):
+    say("synthesize edges")
+    wl = Wk.circle_pulse()
+    ctx.plan(wl.curve, wl.W, wl.F, N=wl.N)
+    psi, _, _ = ctx.solve_densities()
+    V = ctx.eval_field(psi, wl.obs)
+    # times far from the signal: no active window -> exactly zero
+    u = ctx.synthesize(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, np.array([1e5, -1e5]))
+    assert torch.count_nonzero(u).item() == 0
+    # one time only, and an empty time list
+    u1 = ctx.synthesize(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, np.array([5.0]))
+    ref = O.run(wl.curve, wl.W, wl.F, wl.N, wl.direction, wl.signal, wl.H, wl.tau0, wl.obs, np.array([5.0]))
+    assert relmax(u1.cpu().numpy(), ref) < 1e-10
+    u0 = ctx.synthesize(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, np.zeros(0))
+    assert u0.numel() == 0
+    # 2F not a power of two
+    ctx.plan(wl.curve, wl.W, 24, N=64)
+    psi, _, _ = ctx.solve_densities()
+    V = ctx.eval_field(psi, wl.obs)
+    with pytest.raises(fhw.FhwError):
+        ctx.synthesize(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times)
+
+
+def test_single_frequency(ctx):
+    say("F = 1")
+    sig = Wk.gaussian_pulse()
+    wl = Wk.Workload("circ_F1", Wk.circle(1.0), 8.0, 1, 64, H=4.0, tau0=0.0, signal=sig, obs=Wk.ring(3, 2.0),
+                     times=np.linspace(0, 10, 5))
+    u = _pipeline(ctx, wl)
+    ref = O.run(wl.curve, wl.W, wl.F, wl.N, wl.direction, sig, wl.H, wl.tau0, wl.obs, wl.times)
+    assert relmax(u, ref) < 1e-10
