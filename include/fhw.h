@@ -27,8 +27,8 @@
  *    that stream.  One context per stream; a context is not thread-safe.
  *  - Complex numbers are interleaved (re, im) pairs: double2 for FP64
  *    ("complex128"), float2 for FP32 ("complex64").
- *  - Matrices are row-major, packed (leading dimension N), one after another
- *    at caller-given element offsets (ragged batches).
+ *  - Matrices are column-major (entry (r, c) at c*N + r), packed, one after
+ *    another at caller-given element offsets (ragged batches).
  *  - Frequencies: omega_j = j W / F, j = 1..F; wavenumber kappa = omega / c;
  *    coupling eta = max(kappa, 1).  The DFT grid is omega_l = (l - F) W / F,
  *    l = 0..2F-1, on [-W, W).
@@ -151,18 +151,18 @@ int fhw_kress_weights(fhw_ctx* ctx, int32_t N, double* R, double* logtab);
 
 /* Nystrom matrix and plane-wave RHS of eq. CFIE_direct for planned frequencies
  * j0 .. j0+count-1 (0-based): A complex128 at A_off[q] (N_j^2 elements each,
- * row-major), g complex128 at g_off[q] (N_j elements).  A_off, g_off [host]. */
+ * column-major), g complex128 at g_off[q] (N_j elements).  A_off, g_off [host]. */
 int fhw_assemble(fhw_ctx* ctx, int32_t j0, int32_t count, void* A, const int64_t* A_off,
                  void* g, const int64_t* g_off);
 
 /* In-place batched LU with partial pivoting (max |re|+|im|, first index on
- * ties) of `batch` row-major square matrices: N[q], A_off[q], piv_off[q]
+ * ties) of `batch` column-major square matrices: N[q], A_off[q], piv_off[q]
  * [host]; A complex128 (precision FHW_FP64) or complex64 (FHW_FP32_REFINE);
  * piv int32 (global row swapped with row i, applied in order).  Rows of
  * earlier column panels are not permuted by later pivots (the solve below
  * replays the pivots panel by panel).  linv: device workspace of
  * sum_q 4096*ceil(N[q]/64) elements of the same complex type, linv_off[q]
- * [host]; block p of matrix q (64x64 row-major at linv_off[q] + 4096 p)
+ * [host]; block p of matrix q (64x64 column-major at linv_off[q] + 4096 p)
  * receives the inverse of the unit-lower diagonal block p below its diagonal
  * and the inverse of the upper diagonal block on and above it.
  * Returns FHW_E_SINGULAR if any exactly zero pivot was met. */
@@ -201,16 +201,17 @@ int fhw_fourier_coefficients(fhw_ctx* ctx, const void* B, int32_t count, const v
 #define FHW_STAGE_KRESS 1
 #define FHW_STAGE_ASSEMBLE 2
 #define FHW_STAGE_LU_PANEL 3
-#define FHW_STAGE_LU_SWAP 4
-#define FHW_STAGE_LU_TRSM 5
-#define FHW_STAGE_LU_UPDATE 6
-#define FHW_STAGE_SOLVE 7
-#define FHW_STAGE_RESIDUAL 8
-#define FHW_STAGE_FIELD 9
-#define FHW_STAGE_SPECTRA 10
-#define FHW_STAGE_COEFFS 11
-#define FHW_STAGE_SYNTH 12
-#define FHW_N_STAGES 13
+#define FHW_STAGE_LU_DIAGINV 4
+#define FHW_STAGE_LU_SWAP 5
+#define FHW_STAGE_LU_TRSM 6
+#define FHW_STAGE_LU_UPDATE 7
+#define FHW_STAGE_SOLVE 8
+#define FHW_STAGE_RESIDUAL 9
+#define FHW_STAGE_FIELD 10
+#define FHW_STAGE_SPECTRA 11
+#define FHW_STAGE_COEFFS 12
+#define FHW_STAGE_SYNTH 13
+#define FHW_N_STAGES 14
 int fhw_profile(fhw_ctx* ctx, int32_t enable);
 int fhw_profile_read(fhw_ctx* ctx, double* ms, int64_t* launches);
 

@@ -46,8 +46,9 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble(const fhw_assemble_ite
     for (int s = 0; s < ASM_PER_THREAD; ++s) {
         const int64_t e = base + (int64_t)s * ASM_THREADS + threadIdx.x;
         if (e >= NN) break;
-        const int i = (int)(e / N);
-        const int j = (int)(e - (int64_t)i * N);
+        // column-major: e = j*N + i (consecutive threads, consecutive rows i)
+        const int j = (int)(e / N);
+        const int i = (int)(e - (int64_t)j * N);
         const int l = (i - j + N) % N;
         const double Rw = it.R[l];
         const double spj = sp[j];

@@ -16,7 +16,7 @@
 struct fhw_batch_dev {
     // device arrays describing a ragged batch of square matrices
     const int32_t* N;         // [batch]
-    const int64_t* a_off;     // [batch] element offsets of the matrices
+    const int64_t* a_off;     // [batch] element offsets of the (column-major) matrices
     const int64_t* piv_off;   // [batch]
     const int64_t* linv_off;  // [batch]
     const int64_t* v_off;     // [batch] vector offsets
@@ -128,7 +128,7 @@ int64_t assemble_blocks_for(int32_t N);
 struct fhw_lu_sched {
     // host-built launch schedule for one batched factorization
     int32_t nsteps;
-    std::vector<int32_t> R, W;               // per step: rows/thread, sub-panel width
+    std::vector<int32_t> R;                  // per step: panel rows per thread
     std::vector<int64_t> gemm_trsm_off, gemm_upd_off;   // per step: offsets into d_prefix
     std::vector<int32_t> gemm_trsm_tiles, gemm_upd_tiles, swap_blocks;
     std::vector<int64_t> swap_off;

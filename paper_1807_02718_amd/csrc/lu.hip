@@ -1,74 +1,81 @@
 // Batched dense complex LU with partial pivoting on gfx950 (step F3: one
-// Nystrom system per frequency), FP64 or FP32, ragged batches of row-major
-// packed matrices.
+// Nystrom system per frequency), FP64 or FP32, ragged batches of
+// column-major packed matrices (element (r, c) of matrix b at a_off[b] + c N + r).
 //
 // Right-looking, blocked by NB = 64 columns.  Per panel k0:
-//   k_lu_panel   one 1024-thread workgroup per matrix factors the (N-k0) x 64
-//                panel in sub-panels of W columns held in registers (pivot
-//                search = wave shuffles + one LDS round, first index on ties),
-//                applies the sub-panel swaps and updates inside the panel, and
-//                writes the inverses of the 64x64 unit-lower and upper
-//                diagonal blocks (used by the trailing TRSM and by the solves).
-//   k_lu_swap    applies the 64 row swaps to the trailing columns.
-//   k_lu_gemm    U12 = L11^{-1} A12 (in place) and A22 -= L21 U12, 64x64 tiles,
-//                complex product as 4 real MFMA 16x16x4 products per k-step.
+//   k_lu_panel    one 256-thread workgroup per matrix (four per CU) factors
+//                 the (N-k0) x 64 panel in sub-panels of W columns held in
+//                 registers, rows owned by threads (coalesced in column-major);
+//                 pivot search = wave shuffles + one LDS round, max |re|+|im|,
+//                 first index on ties; sub-panel swaps and in-panel updates.
+//   k_lu_diaginv  inverses of the 64x64 unit-lower and upper diagonal blocks
+//                 (used by the trailing TRSM and by the solves), in LDS.
+//   k_lu_swap     the panel's row swaps on the trailing columns (no work when
+//                 the panel did not pivot, the usual case for these systems).
+//   k_lu_gemm     U12 = L11^{-1} A12 (in place) and A22 -= L21 U12 on 64x64
+//                 tiles, the complex product as 4 real MFMA 16x16x4 products.
 // Earlier panels' L columns are not permuted by later pivots; the solves
 // replay the pivots panel by panel.
 #include "fhw_device.h"
 #include "fhw_internal.h"
 
 #define NB FHW_LU_NB
-#define PANEL_THREADS 1024
+#define PANEL_THREADS 256
+#define INV_THREADS 1024
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// linv block layout per matrix: panel p at linv_off + p*NB*NB, row-major 64x64:
-// strictly lower part = inverse of the unit-lower L11, upper part incl. the
-// diagonal = inverse of U11.
+// linv block layout per matrix: panel p at linv_off + p*NB*NB, column-major
+// 64x64 (entry (r, c) at c*NB + r): strictly lower part = inverse of the
+// unit-lower L11, upper part including the diagonal = inverse of U11.
 
 template <typename T>
 __device__ __forceinline__ bool piv_better(T v, int i, T bv, int bi) {
     return (v > bv) || (v == bv && i < bi);
 }
 
+template <typename T, int W>
+struct panel_lds {
+    cpx<T> Ublk[W][NB];
+    cpx<T> L11s[W][W];
+    cpx<T> prow[W];
+    cpx<T> rowk[W];
+    T redv[PANEL_THREADS / 64];
+    int redi[PANEL_THREADS / 64];
+    int s_piv[NB];
+    int sing;
+};
+
+// Thread tid owns rows kc + tid + i*256 (i < R) of the current sub-panel.
 template <typename T, int R, int W>
-__global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* __restrict__ Ns,
-                                                            const int64_t* __restrict__ a_off,
-                                                            const int64_t* __restrict__ piv_off,
-                                                            const int64_t* __restrict__ linv_off,
-                                                            cpx<T>* __restrict__ Abase, int* __restrict__ piv,
-                                                            cpx<T>* __restrict__ linv, int* __restrict__ status) {
+__global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int* __restrict__ Ns,
+                                                               const int64_t* __restrict__ a_off,
+                                                               const int64_t* __restrict__ piv_off,
+                                                               cpx<T>* __restrict__ Abase, int* __restrict__ piv,
+                                                               int* __restrict__ status) {
+    __shared__ panel_lds<T, W> S;
     const int b = blockIdx.x;
     const int N = Ns[b];
     if (k0 >= N) return;
     const int nb = min(NB, N - k0);
-    cpx<T>* A = Abase + a_off[b];
+    // P[c*N + r]: entry (k0 + r, k0 + c) of the matrix
+    cpx<T>* P = Abase + a_off[b] + (int64_t)k0 * N + k0;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-
-    __shared__ cpx<T> prow[W];
-    __shared__ cpx<T> rowk[W];
-    __shared__ T redv[PANEL_THREADS / 64];
-    __shared__ int redi[PANEL_THREADS / 64];
-    __shared__ int s_piv[NB];
-    __shared__ cpx<T> L11s[W][W];
-    __shared__ cpx<T> Ublk[W][NB];
-    __shared__ int s_sing;
-    if (tid == 0) s_sing = 0;
+    const cpx<T> zero = cmk((T)0, (T)0);
+    if (tid == 0) S.sing = 0;
 
     cpx<T> a[R][W];
-
     for (int s = 0; s < nb; s += W) {
         const int w = min(W, nb - s);
         const int kc = k0 + s;
-        // rows kc + tid + i*PANEL_THREADS belong to this thread
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int row = kc + tid + i * PANEL_THREADS;
 #pragma unroll
             for (int q = 0; q < W; ++q)
-                a[i][q] = (row < N && q < w) ? A[(int64_t)row * N + kc + q] : cmk((T)0, (T)0);
+                a[i][q] = (row < N && q < w) ? P[(int64_t)(s + q) * N + (row - k0)] : zero;
         }
 #pragma unroll
         for (int j = 0; j < W; ++j) {
@@ -90,14 +97,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
                     int oi = __shfl_xor(bi, off, 64);
                     if (piv_better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
                 }
-                if (lane == 0) { redv[wid] = bv; redi[wid] = bi; }
+                if (lane == 0) { S.redv[wid] = bv; S.redi[wid] = bi; }
                 __syncthreads();
-                bv = redv[0]; bi = redi[0];
+                bv = S.redv[0]; bi = S.redi[0];
 #pragma unroll
                 for (int q = 1; q < PANEL_THREADS / 64; ++q)
-                    if (piv_better(redv[q], redi[q], bv, bi)) { bv = redv[q]; bi = redi[q]; }
+                    if (piv_better(S.redv[q], S.redi[q], bv, bi)) { bv = S.redv[q]; bi = S.redi[q]; }
                 // no candidate (NaN column) or zero column: keep the row, flag it
-                const bool zero = !(bv > (T)0) || bi >= N;
+                const bool zp = !(bv > (T)0) || bi >= N;
                 const int p = (bi >= N) ? col : bi;
                 const int tp = (p - kc) % PANEL_THREADS, ip = (p - kc) / PANEL_THREADS;
                 const int tc = (col - kc) % PANEL_THREADS, ic = (col - kc) / PANEL_THREADS;
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
                     for (int i = 0; i < R; ++i)
                         if (i == ip) {
 #pragma unroll
-                            for (int q = 0; q < W; ++q) prow[q] = a[i][q];
+                            for (int q = 0; q < W; ++q) S.prow[q] = a[i][q];
                         }
                 }
                 if (tid == tc) {
@@ -114,12 +121,12 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
                     for (int i = 0; i < R; ++i)
                         if (i == ic) {
 #pragma unroll
-                            for (int q = 0; q < W; ++q) rowk[q] = a[i][q];
+                            for (int q = 0; q < W; ++q) S.rowk[q] = a[i][q];
                         }
                 }
                 if (tid == 0) {
-                    s_piv[s + j] = p;
-                    if (zero) s_sing = 1;
+                    S.s_piv[s + j] = p;
+                    if (zp) S.sing = 1;
                 }
                 __syncthreads();
                 if (tid == tc) {
@@ -127,7 +134,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
                     for (int i = 0; i < R; ++i)
                         if (i == ic) {
 #pragma unroll
-                            for (int q = 0; q < W; ++q) a[i][q] = prow[q];
+                            for (int q = 0; q < W; ++q) a[i][q] = S.prow[q];
                         }
                 }
                 if (tid == tp && p != col) {
@@ -135,10 +142,10 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
                     for (int i = 0; i < R; ++i)
                         if (i == ip) {
 #pragma unroll
-                            for (int q = 0; q < W; ++q) a[i][q] = rowk[q];
+                            for (int q = 0; q < W; ++q) a[i][q] = S.rowk[q];
                         }
                 }
-                const cpx<T> pinv = zero ? cmk((T)0, (T)0) : crcp(prow[j]);
+                const cpx<T> pinv = zp ? zero : crcp(S.prow[j]);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     const int row = kc + tid + i * PANEL_THREADS;
@@ -146,34 +153,30 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
                         const cpx<T> l = cmul(a[i][j], pinv);
                         a[i][j] = l;
 #pragma unroll
-                        for (int q = j + 1; q < W; ++q) a[i][q] = cfms(a[i][q], l, prow[q]);
+                        for (int q = j + 1; q < W; ++q) a[i][q] = cfms(a[i][q], l, S.prow[q]);
                     }
                 }
-                __syncthreads();
             }
         }
-        // write the factored sub-panel back
+        // the factored sub-panel back
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int row = kc + tid + i * PANEL_THREADS;
             if (row < N) {
 #pragma unroll
                 for (int q = 0; q < W; ++q)
-                    if (q < w) A[(int64_t)row * N + kc + q] = a[i][q];
+                    if (q < w) P[(int64_t)(s + q) * N + (row - k0)] = a[i][q];
             }
         }
-        // this sub-panel's swaps on the other columns of the outer panel
-        if (tid < nb) {
-            const int c = k0 + tid;
-            if (c < kc || c >= kc + w) {
-                for (int jj = 0; jj < w; ++jj) {
-                    const int r1 = kc + jj, r2 = s_piv[s + jj];
-                    if (r1 != r2) {
-                        cpx<T> t1 = A[(int64_t)r1 * N + c];
-                        cpx<T> t2 = A[(int64_t)r2 * N + c];
-                        A[(int64_t)r1 * N + c] = t2;
-                        A[(int64_t)r2 * N + c] = t1;
-                    }
+        // this sub-panel's swaps, in order, on the other columns of the panel
+        if (tid < nb && (tid < s || tid >= s + w)) {
+            cpx<T>* Pc = P + (int64_t)tid * N - k0;   // indexed by absolute row
+            for (int jj = 0; jj < w; ++jj) {
+                const int r1 = kc + jj, r2 = S.s_piv[s + jj];
+                if (r1 != r2) {
+                    const cpx<T> t1 = Pc[r1];
+                    Pc[r1] = Pc[r2];
+                    Pc[r2] = t1;
                 }
             }
         }
@@ -181,69 +184,155 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_lu_panel(int k0, const int* _
         if (ncols > 0) {
             if (tid < w) {
 #pragma unroll
-                for (int q = 0; q < W; ++q) L11s[tid][q] = a[0][q];
+                for (int q = 0; q < W; ++q) S.L11s[tid][q] = a[0][q];
             }
             __syncthreads();
-            // U block rows kc..kc+w-1, columns kc+w .. k0+nb-1: unit-lower solve
+            // U block: rows kc..kc+w-1, columns s+w .. nb-1 (unit-lower solve in LDS)
             if (tid < ncols) {
-                const int c = kc + w + tid;
-                for (int rr = 0; rr < w; ++rr) {
-                    cpx<T> v = A[(int64_t)(kc + rr) * N + c];
-                    for (int q = 0; q < rr; ++q) v = cfms(v, L11s[rr][q], Ublk[q][tid]);
-                    Ublk[rr][tid] = v;
-                    A[(int64_t)(kc + rr) * N + c] = v;
+                cpx<T>* Pc = P + (int64_t)(s + w + tid) * N + s;
+#pragma unroll
+                for (int rr = 0; rr < W; ++rr)
+                    if (rr < w) S.Ublk[rr][tid] = Pc[rr];
+                for (int rr = 1; rr < w; ++rr) {
+                    cpx<T> v = S.Ublk[rr][tid];
+                    for (int q = 0; q < rr; ++q) v = cfms(v, S.L11s[rr][q], S.Ublk[q][tid]);
+                    S.Ublk[rr][tid] = v;
                 }
+#pragma unroll
+                for (int rr = 0; rr < W; ++rr)
+                    if (rr < w) Pc[rr] = S.Ublk[rr][tid];
             }
             __syncthreads();
-            // rows below the sub-panel, columns kc+w .. k0+nb-1
+            // rows below the sub-panel: A22 -= L21 U on the panel's remaining columns
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int row = kc + tid + i * PANEL_THREADS;
                 if (row >= kc + w && row < N) {
-                    cpx<T>* Arow = A + (int64_t)row * N + kc + w;
-                    for (int c = 0; c < ncols; ++c) {
-                        cpx<T> v = Arow[c];
+                    cpx<T>* Pr = P + (int64_t)(s + w) * N + (row - k0);   // column stride N
+                    constexpr int CH = 4;
+                    for (int c0 = 0; c0 < ncols; c0 += CH) {
+                        cpx<T> v[CH];
+#pragma unroll
+                        for (int cc = 0; cc < CH; ++cc)
+                            if (c0 + cc < ncols) v[cc] = Pr[(int64_t)(c0 + cc) * N];
 #pragma unroll
                         for (int q = 0; q < W; ++q)
-                            if (q < w) v = cfms(v, a[i][q], Ublk[q][c]);
-                        Arow[c] = v;
+                            if (q < w) {
+                                const cpx<T> l = a[i][q];
+#pragma unroll
+                                for (int cc = 0; cc < CH; ++cc)
+                                    if (c0 + cc < ncols) v[cc] = cfms(v[cc], l, S.Ublk[q][c0 + cc]);
+                            }
+#pragma unroll
+                        for (int cc = 0; cc < CH; ++cc)
+                            if (c0 + cc < ncols) Pr[(int64_t)(c0 + cc) * N] = v[cc];
                     }
                 }
             }
         }
         __syncthreads();
     }
-    if (tid < nb) piv[piv_off[b] + k0 + tid] = s_piv[tid];
-    if (tid == 0 && s_sing) atomicOr(status, 1);
-    __syncthreads();
+    if (tid < nb) piv[piv_off[b] + k0 + tid] = S.s_piv[tid];
+    if (tid == 0 && S.sing) atomicOr(status, 1);
+}
 
-    // inverses of the diagonal blocks: thread c < nb owns column c of Linv,
-    // thread NB + c owns column c of Uinv.  Values are written to the linv
-    // block and re-read by the same thread only.
+// Inverses of the unit-lower and upper parts of the factored diagonal block
+// of panel k0 (one 1024-thread workgroup per matrix, block in LDS).  16 lanes
+// per column of the inverse: lane t sums the terms q = t mod 16.
+template <typename T>
+struct inv_lds {
+    cpx<T> D[NB][NB + 1];
+    cpx<T> I[NB][NB + 1];
+};
+
+template <typename T>
+__global__ __launch_bounds__(INV_THREADS) void k_lu_diaginv(int k0, const int* __restrict__ Ns,
+                                                           const int64_t* __restrict__ a_off,
+                                                           const int64_t* __restrict__ linv_off,
+                                                           const cpx<T>* __restrict__ Abase,
+                                                           cpx<T>* __restrict__ linv) {
+    extern __shared__ __align__(16) char smem_raw[];
+    inv_lds<T>& S = *reinterpret_cast<inv_lds<T>*>(smem_raw);
+    const int b = blockIdx.x;
+    const int N = Ns[b];
+    if (k0 >= N) return;
+    const int nb = min(NB, N - k0);
+    const cpx<T>* Db = Abase + a_off[b] + (int64_t)k0 * N + k0;
+    const int tid = threadIdx.x;
+    const cpx<T> zero = cmk((T)0, (T)0);
+    for (int e = tid; e < NB * NB; e += INV_THREADS) {
+        const int c = e / NB, r = e - c * NB;
+        S.D[r][c] = (r < nb && c < nb) ? Db[(int64_t)c * N + r] : zero;
+    }
+    __syncthreads();
+    const int c = tid >> 4;   // column of the inverse, 0..63
+    const int t = tid & 15;
+    // ---- Linv column c: x_c = 1, x_r = -sum_{q=c}^{r-1} L_rq x_q
+    cpx<T> xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = (t + 16 * u == c) ? cmk((T)1, (T)0) : zero;
+    for (int r = c + 1; r < nb; ++r) {
+        cpx<T> sacc = zero;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = t + 16 * u;
+            if (q >= c && q < r) sacc = cfma(sacc, S.D[r][q], xv[u]);
+        }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            sacc.re += __shfl_xor(sacc.re, off, 64);
+            sacc.im += __shfl_xor(sacc.im, off, 64);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + 16 * u == r) xv[u] = cmk(-sacc.re, -sacc.im);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = t + 16 * u;
+        if (r > c) S.I[r][c] = xv[u];
+    }
+    // ---- Uinv column c: x_c = 1/U_cc, x_r = -(sum_{q=r+1}^{c} U_rq x_q) / U_rr, r < c
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = zero;
+    if (c < nb) {
+        const cpx<T> dcc = crcp(S.D[c][c]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + 16 * u == c) xv[u] = dcc;
+    }
+    for (int r = min(c, nb) - 1; r >= 0; --r) {
+        cpx<T> sacc = zero;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = t + 16 * u;
+            if (q > r && q <= c) sacc = cfma(sacc, S.D[r][q], xv[u]);
+        }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            sacc.re += __shfl_xor(sacc.re, off, 64);
+            sacc.im += __shfl_xor(sacc.im, off, 64);
+        }
+        const cpx<T> v = cmul(cmk(-sacc.re, -sacc.im), crcp(S.D[r][r]));
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + 16 * u == r) xv[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = t + 16 * u;
+        if (r <= c) S.I[r][c] = xv[u];
+    }
+    __syncthreads();
     cpx<T>* Lb = linv + linv_off[b] + (int64_t)(k0 / NB) * NB * NB;
-    const cpx<T>* D = A + (int64_t)k0 * N + k0;
-    if (tid < nb) {
-        const int c = tid;
-        for (int r = c + 1; r < nb; ++r) {
-            // x_c = 1 implicitly
-            cpx<T> v = csub(cmk((T)0, (T)0), D[(int64_t)r * N + c]);
-            for (int q = c + 1; q < r; ++q) v = cfms(v, D[(int64_t)r * N + q], Lb[q * NB + c]);
-            Lb[r * NB + c] = v;
-        }
-    } else if (tid >= NB && tid < NB + nb) {
-        const int c = tid - NB;
-        // Uinv column c: x_c = 1/U_cc, x_r = -(sum_{q=r+1}^{c} U_rq x_q)/U_rr, r < c
-        Lb[c * NB + c] = crcp(D[(int64_t)c * N + c]);
-        for (int r = c - 1; r >= 0; --r) {
-            cpx<T> v = cmk((T)0, (T)0);
-            for (int q = r + 1; q <= c; ++q) v = cfms(v, D[(int64_t)r * N + q], Lb[q * NB + c]);
-            Lb[r * NB + c] = cmul(v, crcp(D[(int64_t)r * N + r]));
-        }
+    for (int e = tid; e < NB * NB; e += INV_THREADS) {
+        const int cc = e / NB, r = e - cc * NB;
+        Lb[e] = S.I[r][cc];
     }
 }
 
 // Row swaps of panel k0 on columns [k0+nb, N): one thread per column, swaps in
-// order (grid.y blocks of 256 columns).
+// order (grid.y blocks of 256 columns).  Returns at once when no pivot moved.
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_swap(int k0, const int* __restrict__ Ns,
                                                  const int64_t* __restrict__ a_off,
@@ -253,28 +342,37 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, const int* __restrict__
     const int N = Ns[b];
     if (k0 >= N) return;
     const int nb = min(NB, N - k0);
-    const int c = k0 + nb + blockIdx.y * 256 + threadIdx.x;
     __shared__ int sp[NB];
-    if (threadIdx.x < nb) sp[threadIdx.x] = piv[piv_off[b] + k0 + threadIdx.x];
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
     __syncthreads();
+    if (threadIdx.x < nb) {
+        sp[threadIdx.x] = piv[piv_off[b] + k0 + threadIdx.x];
+        if (sp[threadIdx.x] != k0 + (int)threadIdx.x) any = 1;
+    }
+    __syncthreads();
+    if (!any) return;
+    const int c = k0 + nb + blockIdx.y * 256 + threadIdx.x;
     if (c >= N) return;
-    cpx<T>* A = Abase + a_off[b];
+    cpx<T>* Ac = Abase + a_off[b] + (int64_t)c * N;
     for (int jj = 0; jj < nb; ++jj) {
         const int r1 = k0 + jj, r2 = sp[jj];
         if (r1 != r2) {
-            cpx<T> t1 = A[(int64_t)r1 * N + c];
-            cpx<T> t2 = A[(int64_t)r2 * N + c];
-            A[(int64_t)r1 * N + c] = t2;
-            A[(int64_t)r2 * N + c] = t1;
+            const cpx<T> t1 = Ac[r1];
+            Ac[r1] = Ac[r2];
+            Ac[r2] = t1;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Tiled complex GEMM on MFMA for the trailing update.
-//   TRSM mode: C(64 x 64 tile of rows k0..k0+nb, cols k0+nb+64*tc) = Linv * C
-//   SUB  mode: C(rows k0+nb+64*tr, cols k0+nb+64*tc) -= L21 * U12
-// 4 waves; wave (wm, wn) owns a 32x32 quarter = 2x2 MFMA 16x16 blocks.
+// Tiled complex GEMM on MFMA for the trailing update (column-major).
+//   TRSM mode: C(rows k0..k0+nb, cols k0+nb+64*tc ..) = Linv * C (in place)
+//   SUB  mode: C(rows k0+nb+64*tr.., cols k0+nb+64*tc..) -= L21 * U12
+// The MFMA computes the transposed tile, D(j, i) = sum_k U(k, j) L(i, k), so
+// that the 16 consecutive lanes of a result row are 16 consecutive matrix rows
+// (coalesced column-major stores).  4 waves; wave (wj, wi) owns a 32x32
+// quarter = 2x2 MFMA 16x16 blocks.
 // ---------------------------------------------------------------------------
 #define GT 64
 #define GK 16
@@ -282,12 +380,16 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, const int* __restrict__
 
 template <typename T>
 struct mfma_traits;
+// Both take A[i][k] from lane i + 16k and B[k][j] from lane j + 16k.  The
+// 16x16 result lands differently: element v of lane l is row 4v + l/16 for
+// the f64 form and row 4(l/16) + v for the f32 form; column l % 16 in both.
 template <>
 struct mfma_traits<double> {
     typedef v4d acc_t;
     static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 template <>
 struct mfma_traits<float> {
@@ -295,6 +397,7 @@ struct mfma_traits<float> {
     static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 __device__ __forceinline__ int find_prefix(const int* __restrict__ prefix, int n, int blk) {
@@ -325,95 +428,93 @@ __global__ __launch_bounds__(256) void k_lu_gemm(int k0, const int* __restrict__
     const int row0 = SUB ? (k0 + nb + tr * GT) : k0;
     const int nrows = SUB ? min(GT, N - row0) : nb;
     const int ncols = min(GT, N - col0);
-    // A operand: SUB -> A[row0 + i][k0 + k] (ld N); TRSM -> Linv[i][k] (ld NB)
-    const cpx<T>* Aop = SUB ? (A + (int64_t)row0 * N + k0)
-                            : (linv + linv_off[b] + (int64_t)(k0 / NB) * NB * NB);
-    const int lda = SUB ? N : NB;
-    const cpx<T>* Bop = A + (int64_t)k0 * N + col0;   // rows k0.. (U12 / A12), ld N
+    // L operand (i, k): SUB -> A[(k0+k)*N + row0+i]; TRSM -> Linv column-major (i, k) at k*NB + i
+    const cpx<T>* Lop = SUB ? (A + (int64_t)k0 * N + row0) : (linv + linv_off[b] + (int64_t)(k0 / NB) * NB * NB);
+    const int ldl = SUB ? N : NB;
+    const cpx<T>* Uop = A + (int64_t)col0 * N + k0;   // U12 (k, j) at j*N + k
 
-    __shared__ cpx<T> As[GK][GT + GPAD];
-    __shared__ cpx<T> Bs[GK][GT];
+    __shared__ cpx<T> Ls[GK][GT + GPAD];
+    __shared__ cpx<T> Us[GK][GT + GPAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 1, wn = wid & 1;
+    const int wj = wid >> 1, wi = wid & 1;
     acc_t accr[2][2], acci[2][2];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mj = 0; mj < 2; ++mj)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) {
-            accr[mi][ni] = (acc_t)(0);
-            acci[mi][ni] = (acc_t)(0);
+            accr[mj][ni] = (acc_t)(0);
+            acci[mj][ni] = (acc_t)(0);
         }
 
     for (int kb = 0; kb < nb; kb += GK) {
-        // A chunk: 64 rows x 16 k; thread -> (row = tid/16 + 16*pass, k = tid%16)
-#pragma unroll
-        for (int pass = 0; pass < 4; ++pass) {
-            const int i = (tid >> 4) + 16 * pass;
-            const int k = tid & 15;
-            const bool ok = (i < nrows) && (kb + k < nb);
-            // TRSM: Linv is lower-unit + upper(Uinv) packed; use only the unit-lower part
-            cpx<T> v = cmk((T)0, (T)0);
-            if (ok) {
-                if (SUB) {
-                    v = Aop[(int64_t)i * lda + kb + k];
-                } else {
-                    const int kk = kb + k;
-                    if (kk < i) v = Aop[i * lda + kk];
-                    else if (kk == i) v = cmk((T)1, (T)0);
-                }
-            }
-            As[k][i] = v;
-        }
-        // B chunk: 16 k x 64 cols; thread -> (k = tid/64 + 4*pass, col = tid%64)
+        // L chunk: 16 k x 64 i; thread -> (k = tid/64 + 4*pass, i = tid%64), contiguous in i
 #pragma unroll
         for (int pass = 0; pass < 4; ++pass) {
             const int k = (tid >> 6) + 4 * pass;
-            const int j = tid & 63;
+            const int i = tid & 63;
+            const int kk = kb + k;
+            cpx<T> v = cmk((T)0, (T)0);
+            if (i < nrows && kk < nb) {
+                if (SUB) {
+                    v = Lop[(int64_t)kk * ldl + i];
+                } else {
+                    // unit-lower part of the packed inverse block
+                    if (kk < i) v = Lop[kk * ldl + i];
+                    else if (kk == i) v = cmk((T)1, (T)0);
+                }
+            }
+            Ls[k][i] = v;
+        }
+        // U chunk: 16 k x 64 j; thread -> (j = tid/16 + 16*pass, k = tid%16), contiguous in k
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const int j = (tid >> 4) + 16 * pass;
+            const int k = tid & 15;
             const bool ok = (kb + k < nb) && (j < ncols);
-            Bs[k][j] = ok ? Bop[(int64_t)(kb + k) * N + j] : cmk((T)0, (T)0);
+            Us[k][j] = ok ? Uop[(int64_t)j * N + kb + k] : cmk((T)0, (T)0);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < GK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            cpx<T> af[2], bf[2];
+            cpx<T> uf[2], lf[2];
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi) af[mi] = As[kr][wm * 32 + mi * 16 + (lane & 15)];
+            for (int mj = 0; mj < 2; ++mj) uf[mj] = Us[kr][wj * 32 + mj * 16 + (lane & 15)];
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) bf[ni] = Bs[kr][wn * 32 + ni * 16 + (lane & 15)];
+            for (int ni = 0; ni < 2; ++ni) lf[ni] = Ls[kr][wi * 32 + ni * 16 + (lane & 15)];
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi) {
-                const T nai = -af[mi].im;
+            for (int mj = 0; mj < 2; ++mj) {
+                const T nui = -uf[mj].im;
 #pragma unroll
                 for (int ni = 0; ni < 2; ++ni) {
-                    accr[mi][ni] = mfma_traits<T>::mac(af[mi].re, bf[ni].re, accr[mi][ni]);
-                    accr[mi][ni] = mfma_traits<T>::mac(nai, bf[ni].im, accr[mi][ni]);
-                    acci[mi][ni] = mfma_traits<T>::mac(af[mi].re, bf[ni].im, acci[mi][ni]);
-                    acci[mi][ni] = mfma_traits<T>::mac(af[mi].im, bf[ni].re, acci[mi][ni]);
+                    accr[mj][ni] = mfma_traits<T>::mac(uf[mj].re, lf[ni].re, accr[mj][ni]);
+                    accr[mj][ni] = mfma_traits<T>::mac(nui, lf[ni].im, accr[mj][ni]);
+                    acci[mj][ni] = mfma_traits<T>::mac(uf[mj].re, lf[ni].im, acci[mj][ni]);
+                    acci[mj][ni] = mfma_traits<T>::mac(uf[mj].im, lf[ni].re, acci[mj][ni]);
                 }
             }
         }
         __syncthreads();
     }
-    // epilogue: lane holds D[4*(lane/16) + v][lane%16] of each 16x16 block
-    cpx<T>* C = A + (int64_t)row0 * N + col0;
+    // epilogue: element v of this lane is D(j = row(lane, v), i = lane % 16) of each block
+    cpx<T>* C = A + (int64_t)col0 * N + row0;
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mj = 0; mj < 2; ++mj)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
-                const int j = wn * 32 + ni * 16 + (lane & 15);
+                const int j = wj * 32 + mj * 16 + mfma_traits<T>::row(lane, v);
+                const int i = wi * 32 + ni * 16 + (lane & 15);
                 if (i < nrows && j < ncols) {
-                    cpx<T>* p = C + (int64_t)i * N + j;
+                    cpx<T>* p = C + (int64_t)j * N + i;
                     if (SUB) {
-                        cpx<T> o = *p;
-                        *p = cmk(o.re - accr[mi][ni][v], o.im - acci[mi][ni][v]);
+                        const cpx<T> o = *p;
+                        *p = cmk(o.re - accr[mj][ni][v], o.im - acci[mj][ni][v]);
                     } else {
-                        *p = cmk(accr[mi][ni][v], acci[mi][ni][v]);
+                        *p = cmk(accr[mj][ni][v], acci[mj][ni][v]);
                     }
                 }
             }
@@ -426,16 +527,16 @@ void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch) {
     int32_t maxN = 0;
     for (int q = 0; q < batch; ++q) maxN = std::max(maxN, N[q]);
     sch.nsteps = (maxN + NB - 1) / NB;
-    sch.R.clear(); sch.W.clear(); sch.gemm_trsm_off.clear(); sch.gemm_upd_off.clear();
+    sch.R.clear();
+    sch.gemm_trsm_off.clear(); sch.gemm_upd_off.clear();
     sch.gemm_trsm_tiles.clear(); sch.gemm_upd_tiles.clear(); sch.swap_blocks.clear(); sch.prefix.clear();
     for (int p = 0; p < sch.nsteps; ++p) {
         const int k0 = p * NB;
         int rows = 0;
         for (int q = 0; q < batch; ++q) rows = std::max(rows, N[q] - k0);
         int R = (rows + PANEL_THREADS - 1) / PANEL_THREADS;
-        R = R <= 1 ? 1 : (R <= 2 ? 2 : 4);
+        R = R <= 1 ? 1 : (R <= 2 ? 2 : (R <= 4 ? 4 : (R <= 8 ? 8 : 16)));
         sch.R.push_back(R);
-        sch.W.push_back(R == 1 ? 16 : (R == 2 ? 8 : 4));
         int maxrest = 0;
         // TRSM prefix
         sch.gemm_trsm_off.push_back((int64_t)sch.prefix.size());
@@ -462,22 +563,58 @@ void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch) {
 }
 
 template <typename T>
+static void lu_set_lds_limits() {
+    static bool done = false;
+    if (done) return;
+    done = true;
+    (void)hipFuncSetAttribute((const void*)k_lu_diaginv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(inv_lds<T>));
+}
+
+// rows per thread R (from the step's largest panel height) and sub-panel
+// width W of the panel kernel, chosen to keep R*W complex values per thread
+// in registers without spilling
+template <typename T>
+static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, int k0, cpx<T>* A, int32_t* piv,
+                               int32_t* st) {
+#define FHW_PANEL(RR, WW)                                                                                    \
+    hipLaunchKernelGGL((k_lu_panel<T, RR, WW>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N, bd.a_off, \
+                       bd.piv_off, A, piv, st)
+    if constexpr (sizeof(T) == 4) {
+        switch (R) {
+            case 1: FHW_PANEL(1, 16); break;
+            case 2: FHW_PANEL(2, 8); break;
+            case 4: FHW_PANEL(4, 8); break;
+            case 8: FHW_PANEL(8, 4); break;
+            default: FHW_PANEL(16, 2); break;
+        }
+    } else {
+        switch (R) {
+            case 1: FHW_PANEL(1, 8); break;
+            case 2: FHW_PANEL(2, 8); break;
+            case 4: FHW_PANEL(4, 4); break;
+            case 8: FHW_PANEL(8, 2); break;
+            default: FHW_PANEL(16, 1); break;
+        }
+    }
+#undef FHW_PANEL
+    return hipGetLastError();
+}
+
+template <typename T>
 static hipError_t lu_factor_t(hipStream_t s, const fhw_batch_dev& bd, const fhw_lu_sched& sch,
                               const int32_t* d_prefix, cpx<T>* A, int32_t* piv, cpx<T>* linv, int32_t* st,
                               fhw_prof* prof) {
+    lu_set_lds_limits<T>();
     for (int p = 0; p < sch.nsteps; ++p) {
         const int k0 = p * NB;
-        const int R = sch.R[p];
         prof_begin(prof, FHW_STAGE_LU_PANEL, s);
-        if (R == 1)
-            hipLaunchKernelGGL((k_lu_panel<T, 1, 16>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N,
-                               bd.a_off, bd.piv_off, bd.linv_off, A, piv, linv, st);
-        else if (R == 2)
-            hipLaunchKernelGGL((k_lu_panel<T, 2, 8>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N,
-                               bd.a_off, bd.piv_off, bd.linv_off, A, piv, linv, st);
-        else
-            hipLaunchKernelGGL((k_lu_panel<T, 4, 4>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N,
-                               bd.a_off, bd.piv_off, bd.linv_off, A, piv, linv, st);
+        hipError_t e = launch_panel<T>(s, sch.R[p], bd, k0, A, piv, st);
+        prof_end(prof, s);
+        if (e != hipSuccess) return e;
+        prof_begin(prof, FHW_STAGE_LU_DIAGINV, s);
+        hipLaunchKernelGGL((k_lu_diaginv<T>), dim3(bd.batch), dim3(INV_THREADS), sizeof(inv_lds<T>), s, k0, bd.N,
+                           bd.a_off, bd.linv_off, A, linv);
         prof_end(prof, s);
         if (sch.swap_blocks[p] > 0) {
             prof_begin(prof, FHW_STAGE_LU_SWAP, s);
@@ -499,7 +636,7 @@ static hipError_t lu_factor_t(hipStream_t s, const fhw_batch_dev& bd, const fhw_
                                (const cpx<T>*)linv);
             prof_end(prof, s);
         }
-        hipError_t e = hipGetLastError();
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

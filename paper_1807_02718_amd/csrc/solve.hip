@@ -7,11 +7,14 @@
 #define NB FHW_LU_NB
 #define SOLVE_THREADS 256
 
-// One workgroup per matrix; x (complex128, length N) lives in LDS.
+// One workgroup per matrix; x (complex128, length N) lives in LDS.  Factors
+// are column-major (entry (r, c) at c*N + r); linv blocks hold the inverses
+// of the diagonal blocks (column-major 64x64).
 // Forward: per panel, replay the panel's swaps, multiply by the inverse of
-// the unit-lower diagonal block, subtract L21 * y from the rows below.
-// Backward: per panel from the last, subtract U12 * x from the block's rows,
-// multiply by the inverse of U11.
+// the unit-lower diagonal block, subtract L21 * y from the rows below (one
+// thread per row, coalesced down the columns).
+// Backward: per panel from the last, subtract U12 * x from the block's rows
+// (one lane per row, waves over columns), multiply by the inverse of U11.
 template <typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restrict__ Ns,
                                                             const int64_t* __restrict__ a_off,
@@ -23,6 +26,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
                                                             const cpx<T>* __restrict__ linvbase, zd* __restrict__ v,
                                                             zd* __restrict__ acc, const int* __restrict__ skip) {
     extern __shared__ zd xs[];
+    __shared__ zd rhs[NB];
+    __shared__ zd part[SOLVE_THREADS / 64][NB];
     const int b = blockIdx.x;
     if (skip && skip[b]) return;
     const int N = Ns[b];
@@ -55,62 +60,51 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         if (tid < nb) {
             y = xs[k0 + tid];
             for (int c = 0; c < tid; ++c) {
-                cpx<T> l = D[tid * NB + c];
+                const cpx<T> l = D[c * NB + tid];
                 y = cfma(y, cmk((double)l.re, (double)l.im), xs[k0 + c]);
             }
         }
         __syncthreads();
         if (tid < nb) xs[k0 + tid] = y;
         __syncthreads();
-        // rows below: 8 lanes per row, each lane 8 consecutive columns
-        const int grp = tid >> 3, sub = tid & 7;
-        for (int i0 = k0 + nb; i0 < N; i0 += SOLVE_THREADS / 8) {
-            const int i = i0 + grp;
+        for (int i = k0 + nb + tid; i < N; i += SOLVE_THREADS) {
+            const cpx<T>* Li = LU + (int64_t)k0 * N + i;
             zd s = cmk(0.0, 0.0);
-            if (i < N) {
-                const cpx<T>* Lrow = LU + (int64_t)i * N + k0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int c = sub * 8 + q;
-                    if (c < nb) {
-                        cpx<T> l = Lrow[c];
-                        s = cfma(s, cmk((double)l.re, (double)l.im), xs[k0 + c]);
-                    }
-                }
+            for (int c = 0; c < nb; ++c) {
+                const cpx<T> l = Li[(int64_t)c * N];
+                s = cfma(s, cmk((double)l.re, (double)l.im), xs[k0 + c]);
             }
-#pragma unroll
-            for (int off = 1; off < 8; off <<= 1) {
-                s.re += __shfl_xor(s.re, off, 64);
-                s.im += __shfl_xor(s.im, off, 64);
-            }
-            if (i < N && sub == 0) xs[i] = csub(xs[i], s);
+            xs[i] = csub(xs[i], s);
         }
         __syncthreads();
     }
     // ---- backward
-    __shared__ zd rhs[NB];
     for (int p = np - 1; p >= 0; --p) {
         const int k0 = p * NB;
         const int nb = min(NB, N - k0);
         const int c0 = k0 + nb;
-        // rhs_r = x[k0+r] - sum_{c >= c0} U[k0+r][c] x[c]; one wave per row
-        for (int r = wid; r < nb; r += SOLVE_THREADS / 64) {
-            const cpx<T>* Urow = LU + (int64_t)(k0 + r) * N;
-            zd s = cmk(0.0, 0.0);
-            for (int c = c0 + lane; c < N; c += 64) {
-                cpx<T> u = Urow[c];
+        zd s = cmk(0.0, 0.0);
+        if (lane < nb) {
+            const cpx<T>* Ur = LU + k0 + lane;
+            for (int c = c0 + wid; c < N; c += SOLVE_THREADS / 64) {
+                const cpx<T> u = Ur[(int64_t)c * N];
                 s = cfma(s, cmk((double)u.re, (double)u.im), xs[c]);
             }
-            s.re = wave_sum(s.re);
-            s.im = wave_sum(s.im);
-            if (lane == 0) rhs[r] = csub(xs[k0 + r], s);
+        }
+        part[wid][lane] = s;
+        __syncthreads();
+        if (tid < nb) {
+            zd t = xs[k0 + tid];
+#pragma unroll
+            for (int q = 0; q < SOLVE_THREADS / 64; ++q) t = csub(t, part[q][tid]);
+            rhs[tid] = t;
         }
         __syncthreads();
         const cpx<T>* D = Lb + (int64_t)p * NB * NB;
         zd y = cmk(0.0, 0.0);
         if (tid < nb) {
             for (int c = tid; c < nb; ++c) {
-                cpx<T> u = D[tid * NB + c];
+                const cpx<T> u = D[c * NB + tid];
                 y = cfma(y, cmk((double)u.re, (double)u.im), rhs[c]);
             }
         }
@@ -126,9 +120,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
     }
 }
 
-// r = g - A x with the FP64 matrix; norms[2b] = ||r||_2, norms[2b+1] = ||g||_2.
-// Marks done[b] (and sweeps[b] = sweep) once ||r|| <= tol ||g||.  Matrices
-// already done are skipped.  Fixed-order reductions (deterministic).
+// r = g - A x with the FP64 column-major matrix; norms[2b] = ||r||_2,
+// norms[2b+1] = ||g||_2.  Marks done[b] (and sweeps[b] = sweep) once
+// ||r|| <= tol ||g||.  Matrices already done are skipped.  One thread per row,
+// four rows at a time, coalesced down the columns; fixed-order reductions.
 __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restrict__ Ns,
                                                             const int64_t* __restrict__ a_off,
                                                             const int64_t* __restrict__ v_off,
@@ -151,18 +146,32 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
     for (int i = tid; i < N; i += SOLVE_THREADS) xs[i] = xb[i];
     __syncthreads();
     double rr = 0.0, gg = 0.0;
-    for (int i = wid; i < N; i += SOLVE_THREADS / 64) {
-        const zd* Arow = A + (int64_t)i * N;
-        zd s = cmk(0.0, 0.0);
-        for (int c = lane; c < N; c += 64) s = cfma(s, Arow[c], xs[c]);
-        s.re = wave_sum(s.re);
-        s.im = wave_sum(s.im);
-        const zd gi = gb[i];
-        const zd ri = csub(gi, s);
-        if (lane == 0) rb[i] = ri;
-        rr += ri.re * ri.re + ri.im * ri.im;
-        gg += gi.re * gi.re + gi.im * gi.im;
+    constexpr int RB = 4;
+    for (int i0 = 0; i0 < N; i0 += RB * SOLVE_THREADS) {
+        zd s[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) s[q] = cmk(0.0, 0.0);
+        for (int c = 0; c < N; ++c) {
+            const zd xc = xs[c];
+            const zd* Ac = A + (int64_t)c * N + i0 + tid;
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (i0 + tid + q * SOLVE_THREADS < N) s[q] = cfma(s[q], Ac[q * SOLVE_THREADS], xc);
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int i = i0 + tid + q * SOLVE_THREADS;
+            if (i < N) {
+                const zd gi = gb[i];
+                const zd ri = csub(gi, s[q]);
+                rb[i] = ri;
+                rr += ri.re * ri.re + ri.im * ri.im;
+                gg += gi.re * gi.re + gi.im * gi.im;
+            }
+        }
     }
+    rr = wave_sum(rr);
+    gg = wave_sum(gg);
     if (lane == 0) { part[0][wid] = rr; part[1][wid] = gg; }
     __syncthreads();
     if (tid == 0) {

@@ -95,8 +95,8 @@ EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_p
             "fhw_eval_field", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
-STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_swap", "lu_trsm", "lu_update", "solve", "residual",
-          "field", "spectra", "coeffs", "synth")
+STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
+          "residual", "field", "spectra", "coeffs", "synth")
 
 
 def _ptr(t):
@@ -221,12 +221,14 @@ class Context:
         g = torch.empty(int(Ns.sum()), dtype=torch.complex128, device=self.device)
         self._check(_lib.fhw_assemble(self._h, int(j0), int(count), _ptr(A), a_off.ctypes.data_as(C.POINTER(C.c_int64)),
                                       _ptr(g), g_off.ctypes.data_as(C.POINTER(C.c_int64))))
-        mats = [A[a_off[q]:a_off[q] + Ns[q] * Ns[q]].view(int(Ns[q]), int(Ns[q])) for q in range(count)]
+        # column-major storage: the (N, N) row-major view of each block is A^T
+        mats = [A[a_off[q]:a_off[q] + Ns[q] * Ns[q]].view(int(Ns[q]), int(Ns[q])).t() for q in range(count)]
         vecs = [g[g_off[q]:g_off[q] + Ns[q]] for q in range(count)]
         return mats, vecs
 
     def lu_factor(self, A_flat, Ns, precision="fp64"):
-        """In-place batched LU of matrices packed in A_flat (complex128 or complex64)."""
+        """In-place batched LU of column-major matrices packed in A_flat
+        (complex128 or complex64)."""
         Ns = np.asarray(Ns, dtype=np.int32)
         a_off = np.concatenate([[0], np.cumsum(Ns.astype(np.int64) ** 2)[:-1]]).astype(np.int64)
         p_off = np.concatenate([[0], np.cumsum(Ns.astype(np.int64))[:-1]]).astype(np.int64)
