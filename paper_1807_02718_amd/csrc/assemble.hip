@@ -8,8 +8,7 @@
 #include "fhw_internal.h"
 
 #define ASM_THREADS 256
-#define ASM_PER_THREAD 8
-#define ASM_PER_BLOCK (ASM_THREADS * ASM_PER_THREAD)
+#define AT 32   // tile edge
 
 __device__ __forceinline__ int find_item(const int64_t* prefix, int n, int64_t blk) {
     int lo = 0, hi = n - 1;   // largest q with prefix[q] <= blk
@@ -20,16 +19,41 @@ __device__ __forceinline__ int find_item(const int64_t* prefix, int n, int64_t b
     return lo;
 }
 
+// Entry for target node t and source node s from the pair's kernel pieces:
+//   K1 = L1 - i eta M1,  K2 = L2 - i eta M2,  A = |x'_s| (R_l K1 + (pi/n) K2)
+// with L1 = cL n, L2 = (cY n - L1 lam) + i cJ n and n = (nu_t . d)/r.
+__device__ __forceinline__ zd cfie_entry(double n_t, double cL, double cY, double cJ, double M1, double M2r,
+                                         double M2i, double lam, double Rw, double wq, double eta, double sps) {
+    const double L1 = cL * n_t;
+    const double L2r = cY * n_t - L1 * lam;
+    const double L2i = cJ * n_t;
+    const double K1r = L1, K1i = -eta * M1;
+    const double K2r = L2r + eta * M2i, K2i = L2i - eta * M2r;
+    return cmk(sps * (Rw * K1r + wq * K2r), sps * (Rw * K1i + wq * K2i));
+}
+
+// One workgroup per 32x32 tile (I, J), I >= J, of one matrix (column-major).
+// Each thread takes pairs (i, j) = (i0 + tid%32, j0 + tid/32 + 8k), k < 4.
+// The Bessel values of |x_i - x_j| serve A(i, j) (written directly, lanes
+// along i) and A(j, i) (staged in LDS, then written with lanes along j).
+// Diagonal tiles take i >= j only and mirror the strict part.  Tiles with
+// J = 0 also write the RHS.
 __global__ __launch_bounds__(ASM_THREADS) void k_assemble(const fhw_assemble_item* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int n_items,
                                                           double p1, double p2, zd* __restrict__ A,
                                                           zf* __restrict__ A32, zd* __restrict__ g) {
+    __shared__ zd mirror[AT][AT + 1];
     const int q = find_item(prefix, n_items, blockIdx.x);
     const fhw_assemble_item it = items[q];
     const int N = it.N;
     const int n = N >> 1;
-    const int64_t NN = (int64_t)N * N;
-    const int64_t base = (int64_t)(blockIdx.x - prefix[q]) * ASM_PER_BLOCK;
+    // lower-triangular tile index t -> (I, J), I >= J
+    const int t = (int)(blockIdx.x - prefix[q]);
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    const int i0 = I * AT, j0 = J * AT;
     const double* x1 = it.geom;
     const double* x2 = it.geom + N;
     const double* ddx1 = it.geom + 4 * N;
@@ -43,56 +67,74 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble(const fhw_assemble_ite
     zd* Aq = A + it.a_off;
     zf* A32q = A32 ? A32 + it.a_off : nullptr;
 
-    for (int s = 0; s < ASM_PER_THREAD; ++s) {
-        const int64_t e = base + (int64_t)s * ASM_THREADS + threadIdx.x;
-        if (e >= NN) break;
-        // column-major: e = j*N + i (consecutive threads, consecutive rows i)
-        const int j = (int)(e / N);
-        const int i = (int)(e - (int64_t)j * N);
-        const int l = (i - j + N) % N;
-        const double Rw = it.R[l];
+    const int il = threadIdx.x & (AT - 1);
+    const int jg = threadIdx.x >> 5;
+    const int i = i0 + il;
+    const bool iok = i < N;
+    double xi1 = 0, xi2 = 0, ni1 = 0, ni2 = 0, spi = 0;
+    if (iok) { xi1 = x1[i]; xi2 = x2[i]; ni1 = nu1[i]; ni2 = nu2[i]; spi = sp[i]; }
+#pragma unroll
+    for (int k = 0; k < AT / 8; ++k) {
+        const int jl = jg + 8 * k;
+        const int j = j0 + jl;
+        if (!iok || j >= N || (I == J && i < j)) continue;
         const double spj = sp[j];
-        double K1r, K1i, K2r, K2i;
+        int l = i - j;
+        if (l < 0) l += N;
+        zd e_ij, e_ji;
         if (i != j) {
-            const double d1 = x1[j] - x1[i], d2 = x2[j] - x2[i];
+            const double d1 = x1[j] - xi1, d2 = x2[j] - xi2;   // d = x_j - x_i
             const double r = sqrt(d1 * d1 + d2 * d2);
-            const double z = kappa * r;
             double J0, Y0, J1, Y1;
-            fhw_bessel01(z, J0, Y0, J1, Y1);
+            fhw_bessel01(kappa * r, J0, Y0, J1, Y1);
             const double lam = it.logtab[l];
-            const double nud_r = (nu1[i] * d1 + nu2[i] * d2) / r;
-            // M = (i/4)(J0 + i Y0), M1 = -J0/(4pi), M2 = M - M1 lam
             const double M1 = -J0 * inv4pi;
             const double M2r = -0.25 * Y0 - M1 * lam;
             const double M2i = 0.25 * J0;
-            // L = (i kappa/4)(J1 + i Y1) nud/r, L1 = -(kappa/4pi) J1 nud/r, L2 = L - L1 lam
-            const double L1 = -kappa * inv4pi * J1 * nud_r;
-            const double L2r = -0.25 * kappa * Y1 * nud_r - L1 * lam;
-            const double L2i = 0.25 * kappa * J1 * nud_r;
-            K1r = L1;
-            K1i = -eta * M1;
-            K2r = L2r + eta * M2i;
-            K2i = L2i - eta * M2r;
+            const double cL = -kappa * inv4pi * J1;
+            const double cY = -0.25 * kappa * Y1;
+            const double cJ = 0.25 * kappa * J1;
+            const double ir = 1.0 / r;
+            const double n_i = (ni1 * d1 + ni2 * d2) * ir;          // target i: nu_i . (x_j - x_i) / r
+            const double n_j = -(nu1[j] * d1 + nu2[j] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
+            e_ij = cfie_entry(n_i, cL, cY, cJ, M1, M2r, M2i, lam, it.R[l], wq, eta, spj);
+            const int lm = (l == 0) ? 0 : N - l;
+            e_ji = cfie_entry(n_j, cL, cY, cJ, M1, M2r, M2i, it.logtab[lm], it.R[lm], wq, eta, spi);
         } else {
-            const double M2r = -(0.57721566490153286061 + log(0.5 * kappa * spj)) / (2.0 * FHW_PI);
+            const double M2r = -(0.57721566490153286061 + log(0.5 * kappa * spi)) / (2.0 * FHW_PI);
             const double M2i = 0.25;
-            const double L2r = (nu1[i] * ddx1[i] + nu2[i] * ddx2[i]) * inv4pi / (spj * spj);
-            K1r = 0.0;
-            K1i = eta * inv4pi;
-            K2r = L2r + eta * M2i;
-            K2i = -eta * M2r;
+            const double L2r = (ni1 * ddx1[i] + ni2 * ddx2[i]) * inv4pi / (spi * spi);
+            const double K1r = 0.0, K1i = eta * inv4pi;
+            const double K2r = L2r + eta * M2i, K2i = -eta * M2r;
+            const double Rw = it.R[0];
+            e_ij = cmk(spi * (Rw * K1r + wq * K2r) + 0.5, spi * (Rw * K1i + wq * K2i));
+            e_ji = e_ij;
         }
-        double ar = spj * (Rw * K1r + wq * K2r);
-        double ai = spj * (Rw * K1i + wq * K2i);
-        if (i == j) ar += 0.5;
-        Aq[e] = cmk(ar, ai);
-        if (A32q) A32q[e] = cmk((float)ar, (float)ai);
-        if (j == 0) {
-            // g_i = i (kappa p.nu_i - eta) exp(i kappa p.x_i)
-            const double alpha = kappa * (p1 * nu1[i] + p2 * nu2[i]) - eta;
-            double sn, cs;
-            sincos(kappa * (p1 * x1[i] + p2 * x2[i]), &sn, &cs);
-            g[it.g_off + i] = cmk(-alpha * sn, alpha * cs);
+        Aq[(int64_t)j * N + i] = e_ij;
+        if (A32q) A32q[(int64_t)j * N + i] = cmk((float)e_ij.re, (float)e_ij.im);
+        mirror[jl][il] = e_ji;
+    }
+    if (J == 0 && jg == 0 && iok) {
+        // g_i = i (kappa p.nu_i - eta) exp(i kappa p.x_i)
+        const double alpha = kappa * (p1 * ni1 + p2 * ni2) - eta;
+        double sn, cs;
+        sincos(kappa * (p1 * xi1 + p2 * xi2), &sn, &cs);
+        g[it.g_off + i] = cmk(-alpha * sn, alpha * cs);
+    }
+    __syncthreads();
+    // mirrored tile: entry (row j0 + jl, column i0 + il) at (i0 + il) * N + j0 + jl; lanes along jl
+    const int jl2 = threadIdx.x & (AT - 1);
+    const int ig = threadIdx.x >> 5;
+    const int jrow = j0 + jl2;
+#pragma unroll
+    for (int k = 0; k < AT / 8; ++k) {
+        const int il2 = ig + 8 * k;
+        const int icol = i0 + il2;
+        // diagonal tiles computed pairs i >= j only: mirror the strict part
+        if (jrow < N && icol < N && (I != J || icol > jrow)) {
+            const zd v = mirror[jl2][il2];
+            Aq[(int64_t)icol * N + jrow] = v;
+            if (A32q) A32q[(int64_t)icol * N + jrow] = cmk((float)v.re, (float)v.im);
         }
     }
 }
@@ -107,6 +149,6 @@ hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_item
 }
 
 int64_t assemble_blocks_for(int32_t N) {
-    int64_t NN = (int64_t)N * N;
-    return (NN + ASM_PER_BLOCK - 1) / ASM_PER_BLOCK;
+    const int64_t T = (N + AT - 1) / AT;
+    return T * (T + 1) / 2;
 }
