@@ -3,7 +3,7 @@
 // column-major packed matrices (element (r, c) of matrix b at a_off[b] + c N + r).
 //
 // Right-looking, blocked by NB = 64 columns.  Per panel k0:
-//   k_lu_panel    one 256-thread workgroup per matrix (four per CU) factors
+//   k_lu_panel    one 256-thread workgroup per matrix (two to four per CU) factors
 //                 the (N-k0) x 64 panel in sub-panels of W columns held in
 //                 registers, rows owned by threads (coalesced in column-major);
 //                 pivot search = wave shuffles + one LDS round, max |re|+|im|,
@@ -47,9 +47,24 @@ struct panel_lds {
     int sing;
 };
 
-// Thread tid owns rows kc + tid + i*256 (i < R) of the current sub-panel.
-template <typename T, int R, int W>
-__global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int* __restrict__ Ns,
+// Storage of one thread's rows: FP64 rows as W-vectors (a plain R x W array
+// of doubles is demoted to scratch at the widths used), FP32 rows as arrays
+// (measured faster there).
+template <typename T, int W, bool VEC>
+struct panel_row {
+    typedef T type __attribute__((ext_vector_type(W)));
+};
+template <typename T, int W>
+struct panel_row<T, W, false> {
+    typedef T type[W];
+};
+
+// Thread tid owns rows kc + tid + i*256 (i < R) of the current sub-panel,
+// held as separate real and imaginary rows.  WPE (waves per SIMD) sets the
+// register budget: wider sub-panels cut the in-panel update traffic, which
+// costs registers and so occupancy.
+template <typename T, int R, int W, int WPE>
+__global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const int* __restrict__ Ns,
                                                                const int64_t* __restrict__ a_off,
                                                                const int64_t* __restrict__ piv_off,
                                                                cpx<T>* __restrict__ Abase, int* __restrict__ piv,
@@ -63,10 +78,10 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
     cpx<T>* P = Abase + a_off[b] + (int64_t)k0 * N + k0;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const cpx<T> zero = cmk((T)0, (T)0);
     if (tid == 0) S.sing = 0;
 
-    cpx<T> a[R][W];
+    constexpr bool VEC = sizeof(T) == 8;
+    typename panel_row<T, W, VEC>::type ar[R], ai[R];
     for (int s = 0; s < nb; s += W) {
         const int w = min(W, nb - s);
         const int kc = k0 + s;
@@ -74,10 +89,18 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
         for (int i = 0; i < R; ++i) {
             const int row = kc + tid + i * PANEL_THREADS;
 #pragma unroll
-            for (int q = 0; q < W; ++q)
-                a[i][q] = (row < N && q < w) ? P[(int64_t)(s + q) * N + (row - k0)] : zero;
+            for (int q = 0; q < W; ++q) {
+                T vr = (T)0, vi = (T)0;
+                if (row < N && q < w) {
+                    const cpx<T> v = P[(int64_t)(s + q) * N + (row - k0)];
+                    vr = v.re;
+                    vi = v.im;
+                }
+                ar[i][q] = vr;
+                ai[i][q] = vi;
+            }
         }
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int j = 0; j < W; ++j) {
             if (j < w) {
                 const int col = kc + j;
@@ -87,7 +110,7 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
                 for (int i = 0; i < R; ++i) {
                     const int row = kc + tid + i * PANEL_THREADS;
                     if (row >= col && row < N) {
-                        T v = cabs1(a[i][j]);
+                        const T v = fabs(ar[i][j]) + fabs(ai[i][j]);
                         if (piv_better(v, row, bv, bi)) { bv = v; bi = row; }
                     }
                 }
@@ -108,52 +131,83 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
                 const int p = (bi >= N) ? col : bi;
                 const int tp = (p - kc) % PANEL_THREADS, ip = (p - kc) / PANEL_THREADS;
                 const int tc = (col - kc) % PANEL_THREADS, ic = (col - kc) / PANEL_THREADS;
-                if (tid == tp) {
+                if constexpr (VEC) {
+                    // row selection by selects over all R rows (no indexed vector access)
+                    if (tid == tp || tid == tc) {
 #pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (i == ip) {
+                        for (int q = 0; q < W; ++q) {
+                            T pr = (T)0, pi = (T)0, cr = (T)0, ci = (T)0;
 #pragma unroll
-                            for (int q = 0; q < W; ++q) S.prow[q] = a[i][q];
+                            for (int i = 0; i < R; ++i) {
+                                pr = (i == ip) ? ar[i][q] : pr;
+                                pi = (i == ip) ? ai[i][q] : pi;
+                                cr = (i == ic) ? ar[i][q] : cr;
+                                ci = (i == ic) ? ai[i][q] : ci;
+                            }
+                            if (tid == tp) S.prow[q] = cmk(pr, pi);
+                            if (tid == tc) S.rowk[q] = cmk(cr, ci);
                         }
-                }
-                if (tid == tc) {
+                    }
+                } else {
 #pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (i == ic) {
+                    for (int i = 0; i < R; ++i) {
+                        if (tid == tp && i == ip) {
 #pragma unroll
-                            for (int q = 0; q < W; ++q) S.rowk[q] = a[i][q];
+                            for (int q = 0; q < W; ++q) S.prow[q] = cmk(ar[i][q], ai[i][q]);
                         }
+                        if (tid == tc && i == ic) {
+#pragma unroll
+                            for (int q = 0; q < W; ++q) S.rowk[q] = cmk(ar[i][q], ai[i][q]);
+                        }
+                    }
                 }
                 if (tid == 0) {
                     S.s_piv[s + j] = p;
                     if (zp) S.sing = 1;
                 }
                 __syncthreads();
-                if (tid == tc) {
+                if constexpr (VEC) {
+                    if (tid == tc || (tid == tp && p != col)) {
+                        const bool isc = tid == tc, isp = tid == tp && p != col;
 #pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (i == ic) {
+                        for (int q = 0; q < W; ++q) {
+                            const cpx<T> pv = S.prow[q], cv = S.rowk[q];
 #pragma unroll
-                            for (int q = 0; q < W; ++q) a[i][q] = S.prow[q];
+                            for (int i = 0; i < R; ++i) {
+                                const bool tc_i = isc && i == ic, tp_i = isp && i == ip;
+                                ar[i][q] = tc_i ? pv.re : (tp_i ? cv.re : ar[i][q]);
+                                ai[i][q] = tc_i ? pv.im : (tp_i ? cv.im : ai[i][q]);
+                            }
                         }
-                }
-                if (tid == tp && p != col) {
+                    }
+                } else {
 #pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (i == ip) {
+                    for (int i = 0; i < R; ++i) {
+                        if (tid == tc && i == ic) {
 #pragma unroll
-                            for (int q = 0; q < W; ++q) a[i][q] = S.rowk[q];
+                            for (int q = 0; q < W; ++q) { ar[i][q] = S.prow[q].re; ai[i][q] = S.prow[q].im; }
                         }
+                        if (tid == tp && p != col && i == ip) {
+#pragma unroll
+                            for (int q = 0; q < W; ++q) { ar[i][q] = S.rowk[q].re; ai[i][q] = S.rowk[q].im; }
+                        }
+                    }
                 }
-                const cpx<T> pinv = zp ? zero : crcp(S.prow[j]);
+                const cpx<T> pinv = zp ? cmk((T)0, (T)0) : crcp(S.prow[j]);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     const int row = kc + tid + i * PANEL_THREADS;
                     if (row > col && row < N) {
-                        const cpx<T> l = cmul(a[i][j], pinv);
-                        a[i][j] = l;
+                        const T lr = ar[i][j] * pinv.re - ai[i][j] * pinv.im;
+                        const T li = ar[i][j] * pinv.im + ai[i][j] * pinv.re;
+                        ar[i][j] = lr;
+                        ai[i][j] = li;
 #pragma unroll
-                        for (int q = j + 1; q < W; ++q) a[i][q] = cfms(a[i][q], l, S.prow[q]);
+                        for (int q = j + 1; q < W; ++q) {
+                            const cpx<T> u = S.prow[q];
+                            ar[i][q] = ar[i][q] - lr * u.re + li * u.im;
+                            ai[i][q] = ai[i][q] - lr * u.im - li * u.re;
+                        }
                     }
                 }
             }
@@ -165,7 +219,7 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
             if (row < N) {
 #pragma unroll
                 for (int q = 0; q < W; ++q)
-                    if (q < w) P[(int64_t)(s + q) * N + (row - k0)] = a[i][q];
+                    if (q < w) P[(int64_t)(s + q) * N + (row - k0)] = cmk(ar[i][q], ai[i][q]);
             }
         }
         // this sub-panel's swaps, in order, on the other columns of the panel
@@ -184,7 +238,7 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
         if (ncols > 0) {
             if (tid < w) {
 #pragma unroll
-                for (int q = 0; q < W; ++q) S.L11s[tid][q] = a[0][q];
+                for (int q = 0; q < W; ++q) S.L11s[tid][q] = cmk(ar[0][q], ai[0][q]);
             }
             __syncthreads();
             // U block: rows kc..kc+w-1, columns s+w .. nb-1 (unit-lower solve in LDS)
@@ -203,29 +257,49 @@ __global__ __launch_bounds__(PANEL_THREADS, 4) void k_lu_panel(int k0, const int
                     if (rr < w) Pc[rr] = S.Ublk[rr][tid];
             }
             __syncthreads();
-            // rows below the sub-panel: A22 -= L21 U on the panel's remaining columns
+            // rows below the sub-panel: A22 -= L21 U on the panel's remaining columns.
+            // Chunks of CH columns, all R rows of a chunk loaded together.
+            constexpr int CH = (sizeof(T) == 8 ? 8 : 16) / R > 0 ? (sizeof(T) == 8 ? 8 : 16) / R : 1;
+            for (int c0 = 0; c0 < ncols; c0 += CH) {
+                T vr[R][CH], vi[R][CH];
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const int row = kc + tid + i * PANEL_THREADS;
-                if (row >= kc + w && row < N) {
-                    cpx<T>* Pr = P + (int64_t)(s + w) * N + (row - k0);   // column stride N
-                    constexpr int CH = 4;
-                    for (int c0 = 0; c0 < ncols; c0 += CH) {
-                        cpx<T> v[CH];
+                for (int i = 0; i < R; ++i) {
+                    const int row = kc + tid + i * PANEL_THREADS;
+                    const bool ok = row >= kc + w && row < N;
+                    const cpx<T>* Pr = P + (int64_t)(s + w + c0) * N + (row - k0);
 #pragma unroll
-                        for (int cc = 0; cc < CH; ++cc)
-                            if (c0 + cc < ncols) v[cc] = Pr[(int64_t)(c0 + cc) * N];
+                    for (int cc = 0; cc < CH; ++cc) {
+                        T xr = (T)0, xi = (T)0;
+                        if (ok && c0 + cc < ncols) {
+                            const cpx<T> x = Pr[(int64_t)cc * N];
+                            xr = x.re;
+                            xi = x.im;
+                        }
+                        vr[i][cc] = xr;
+                        vi[i][cc] = xi;
+                    }
+                }
 #pragma unroll
-                        for (int q = 0; q < W; ++q)
-                            if (q < w) {
-                                const cpx<T> l = a[i][q];
+                for (int q = 0; q < W; ++q)
+                    if (q < w) {
 #pragma unroll
-                                for (int cc = 0; cc < CH; ++cc)
-                                    if (c0 + cc < ncols) v[cc] = cfms(v[cc], l, S.Ublk[q][c0 + cc]);
+                        for (int cc = 0; cc < CH; ++cc) {
+                            const cpx<T> u = S.Ublk[q][min(c0 + cc, NB - 1)];
+#pragma unroll
+                            for (int i = 0; i < R; ++i) {
+                                vr[i][cc] = vr[i][cc] - ar[i][q] * u.re + ai[i][q] * u.im;
+                                vi[i][cc] = vi[i][cc] - ar[i][q] * u.im - ai[i][q] * u.re;
                             }
+                        }
+                    }
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int row = kc + tid + i * PANEL_THREADS;
+                    if (row >= kc + w && row < N) {
+                        cpx<T>* Pr = P + (int64_t)(s + w + c0) * N + (row - k0);
 #pragma unroll
                         for (int cc = 0; cc < CH; ++cc)
-                            if (c0 + cc < ncols) Pr[(int64_t)(c0 + cc) * N] = v[cc];
+                            if (c0 + cc < ncols) Pr[(int64_t)cc * N] = cmk(vr[i][cc], vi[i][cc]);
                     }
                 }
             }
@@ -635,28 +709,30 @@ static void lu_set_lds_limits() {
 
 // rows per thread R (from the step's largest panel height) and sub-panel
 // width W of the panel kernel, chosen to keep R*W complex values per thread
-// in registers without spilling
+// in registers
 template <typename T>
 static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, int k0, cpx<T>* A, int32_t* piv,
                                int32_t* st) {
-#define FHW_PANEL(RR, WW)                                                                                    \
-    hipLaunchKernelGGL((k_lu_panel<T, RR, WW>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N, bd.a_off, \
+#define FHW_PANEL(RR, WW, EE)                                                                                \
+    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N, bd.a_off, \
                        bd.piv_off, A, piv, st)
+    // (R, W, waves per SIMD), chosen by measurement among the spill-free
+    // register allocations
     if constexpr (sizeof(T) == 4) {
         switch (R) {
-            case 1: FHW_PANEL(1, 16); break;
-            case 2: FHW_PANEL(2, 8); break;
-            case 4: FHW_PANEL(4, 8); break;
-            case 8: FHW_PANEL(8, 4); break;
-            default: FHW_PANEL(16, 2); break;
+            case 1: FHW_PANEL(1, 16, 4); break;
+            case 2: FHW_PANEL(2, 8, 4); break;
+            case 4: FHW_PANEL(4, 8, 4); break;
+            case 8: FHW_PANEL(8, 4, 2); break;
+            default: FHW_PANEL(16, 2, 2); break;
         }
     } else {
         switch (R) {
-            case 1: FHW_PANEL(1, 8); break;
-            case 2: FHW_PANEL(2, 8); break;
-            case 4: FHW_PANEL(4, 4); break;
-            case 8: FHW_PANEL(8, 2); break;
-            default: FHW_PANEL(16, 1); break;
+            case 1: FHW_PANEL(1, 8, 4); break;
+            case 2: FHW_PANEL(2, 8, 2); break;
+            case 4: FHW_PANEL(4, 8, 2); break;
+            case 8: FHW_PANEL(8, 4, 2); break;
+            default: FHW_PANEL(16, 2, 1); break;
         }
     }
 #undef FHW_PANEL
