@@ -109,6 +109,33 @@ int fhw_plan(fhw_ctx* ctx, const fhw_curve* curve, const fhw_problem* prob,
 int fhw_solve_densities(fhw_ctx* ctx, void* psi, double* resid, int32_t* sweeps,
                         int32_t compute_resid);
 
+/* Incident fields for fhw_solve_incidences (Sec. 2.1: any incident field
+ * regular inside the scatterer; its boundary values B enter eq. CFIE_direct
+ * through dB/dnu - i eta B). */
+#define FHW_INC_PLANE 0     /* v = unit direction p: B = exp(i kappa p.x)          */
+#define FHW_INC_POINT 1     /* v = source r0 outside the closed curve:
+                               B = (i/4) H0(kappa |x - r0|); its field at omega = 0
+                               is taken as 0 (eval_field zero_value = 0)          */
+typedef struct {
+    int32_t kind;
+    double v[2];
+} fhw_incidence;
+
+/* Step F3 for several incident fields: each frequency is assembled and
+ * factored once and its factors serve every incidence (the LU reuse of
+ * Sec. 2.3 / Sec. 7 applied to many right-hand sides).
+ * inc [host]: n_inc incidences (n_inc >= 1).
+ * psi: complex128 [n_inc][psi_off[F]], incidence q's densities at
+ * psi + q psi_off[F] in the ragged layout of fhw_plan (so that each block
+ * can be passed to fhw_eval_field).
+ * resid, sweeps [host, optional]: [n_inc][F], as in fhw_solve_densities.
+ * The plan's own direction is not used.  Synchronizes the stream.
+ * Errors: FHW_E_INVALID for an unknown kind, a direction that is not a unit
+ * vector (to 1e-12), a source point on or inside the curve, or non-finite
+ * values; FHW_E_SINGULAR / FHW_E_NOCONV as in fhw_solve_densities. */
+int fhw_solve_incidences(fhw_ctx* ctx, const fhw_incidence* inc, int32_t n_inc, void* psi,
+                         double* resid, int32_t* sweeps, int32_t compute_resid);
+
 /* Step F5 (eqs. freq_domain_repr, Ukslow_repr): V(r, omega_l) on the full DFT
  * grid, V[r][l], complex128 [N_r][2F]; V(r,-omega) = conj V(r,omega) and
  * V(r, 0) = zero_value (1 for plane-wave data: the low-frequency limit).

@@ -447,34 +447,74 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
     return FHW_OK;
 }
 
-int fhw_solve_densities(fhw_ctx* c, void* psi, double* resid, int32_t* sweeps, int32_t compute_resid) {
-    if (!c) return FHW_E_INVALID;
-    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
-    if (!psi) return fhw_fail(c, FHW_E_INVALID, "solve: psi is null");
+// winding number of the planned curve about (a, b): 0 outside
+static int winding_number(const fhw_ctx* c, double a, double b, double* min_dist) {
+    const int M = 4096;
+    double tot = 0.0, prev = 0.0, dmin = INFINITY;
+    for (int k = 0; k <= M; ++k) {
+        double x1, x2, d1, d2;
+        curve_eval_host(c, 2.0 * M_PI * (double)k / M, x1, x2, d1, d2);
+        const double ang = atan2(x2 - b, x1 - a);
+        dmin = std::min(dmin, hypot(x1 - a, x2 - b));
+        if (k > 0) {
+            double da = ang - prev;
+            if (da > M_PI) da -= 2.0 * M_PI;
+            if (da < -M_PI) da += 2.0 * M_PI;
+            tot += da;
+        }
+        prev = ang;
+    }
+    *min_dist = dmin;
+    return (int)lround(tot / (2.0 * M_PI));
+}
+
+// Densities for n_inc incidences (inc == NULL: the plan's plane wave, whose
+// boundary data the assembly kernel writes).  psi holds n_inc blocks of
+// psi_off[F] elements; resid / sweeps [host] are [n_inc][F].
+static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
+                      int32_t* sweeps, int32_t compute_resid) {
     plan_ext& px = g_plans[c];
     const fhw_problem& p = c->prob;
     const int F = p.F;
     const bool fp32 = p.precision == FHW_FP32_REFINE;
+    const int64_t total = c->psi_off[F];
+    // per-(incidence, frequency) status: the plan's arrays for one incidence,
+    // the scratch buffer for several
+    int32_t *d_done = c->d_done, *d_sw = c->d_sweeps;
+    double* d_norms = c->d_norms;
+    if (n_inc > 1) {
+        const size_t nf = (size_t)n_inc * F;
+        const size_t off_sw = align_up(nf * 4, 256), off_nrm = off_sw + align_up(nf * 4, 256);
+        int rc = fhw_ensure_scratch(c, off_nrm + nf * 16);
+        if (rc) return rc;
+        d_done = (int32_t*)c->scratch;
+        d_sw = (int32_t*)((char*)c->scratch + off_sw);
+        d_norms = (double*)((char*)c->scratch + off_nrm);
+    }
     FHW_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * 4, c->stream));
-    FHW_HIP(c, hipMemsetAsync(c->d_done, 0, sizeof(int32_t) * F, c->stream));
-    FHW_HIP(c, hipMemsetAsync(c->d_sweeps, 0, sizeof(int32_t) * F, c->stream));
+    FHW_HIP(c, hipMemsetAsync(d_done, 0, sizeof(int32_t) * F * n_inc, c->stream));
+    FHW_HIP(c, hipMemsetAsync(d_sw, 0, sizeof(int32_t) * F * n_inc, c->stream));
     zd* psid = (zd*)psi;
+    zd* g = (zd*)c->x;
+    zd* r = (zd*)c->r;
     for (auto& ch : px.chunks) {
         fhw_batch_dev bd{ch.d_N, ch.d_aoff, ch.d_pivoff, ch.d_linvoff, ch.d_voff, ch.count};
-        zd* x = psid + ch.psi_base;          // solution written in place into psi
-        zd* g = (zd*)c->x;
-        zd* r = (zd*)c->r;
         STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
                                           p.direction[0], p.direction[1], c->A64, fp32 ? c->A32 : nullptr, g));
         void* LU = fp32 ? c->A32 : c->A64;
         FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
                                     p.precision, &c->prof));
-        FHW_HIP(c, hipMemcpyAsync(x, g, sizeof(zd) * ch.vec_elems, hipMemcpyDeviceToDevice, c->stream));
-        STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, ch.maxN, LU, c->piv, c->linv, x, nullptr, p.precision));
-        double* norms = c->d_norms + 2 * ch.j0;
-        if (fp32) {
-            int32_t* done = c->d_done + ch.j0;
-            int32_t* sw = c->d_sweeps + ch.j0;
+        for (int q = 0; q < n_inc; ++q) {
+            zd* x = psid + q * total + ch.psi_base;     // solution written in place into psi
+            if (inc)
+                STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, inc[q].kind, inc[q].v[0],
+                                                  inc[q].v[1], g));
+            FHW_HIP(c, hipMemcpyAsync(x, g, sizeof(zd) * ch.vec_elems, hipMemcpyDeviceToDevice, c->stream));
+            STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, ch.maxN, LU, c->piv, c->linv, x, nullptr, p.precision));
+            if (!fp32) continue;
+            double* norms = d_norms + 2 * ((int64_t)q * F + ch.j0);
+            int32_t* done = d_done + (int64_t)q * F + ch.j0;
+            int32_t* sw = d_sw + (int64_t)q * F + ch.j0;
             const int maxs = std::max(0, p.refine_max);
             for (int it = 0; it <= maxs; ++it) {
                 STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, norms, p.refine_tol, done, sw,
@@ -483,38 +523,75 @@ int fhw_solve_densities(fhw_ctx* c, void* psi, double* resid, int32_t* sweeps, i
                 STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, ch.maxN, LU, c->piv, c->linv, r, x, done,
                                                p.precision));
             }
-        } else if (compute_resid) {
-            // the factorization overwrote A: assemble it again for the residual
+        }
+        if (!fp32 && compute_resid) {
+            // the factorization overwrote A: assemble it again for the residuals
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
                                               p.direction[0], p.direction[1], c->A64, nullptr, g));
-            STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, norms, 0.0, nullptr, nullptr, 0));
+            for (int q = 0; q < n_inc; ++q) {
+                if (inc)
+                    STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, inc[q].kind, inc[q].v[0],
+                                                      inc[q].v[1], g));
+                double* norms = d_norms + 2 * ((int64_t)q * F + ch.j0);
+                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, psid + q * total + ch.psi_base, g, r,
+                                             norms, 0.0, nullptr, nullptr, 0));
+            }
         }
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     int32_t st[4];
     FHW_HIP(c, hipMemcpy(st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    const size_t nf = (size_t)F * n_inc;
     std::vector<double> nrm;
     std::vector<int32_t> done, sw;
     const bool have_norms = fp32 || compute_resid;
     if (have_norms) {
-        nrm.resize(2 * F);
-        FHW_HIP(c, hipMemcpy(nrm.data(), c->d_norms, sizeof(double) * 2 * F, hipMemcpyDeviceToHost));
+        nrm.resize(2 * nf);
+        FHW_HIP(c, hipMemcpy(nrm.data(), d_norms, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost));
     }
     if (fp32) {
-        done.resize(F);
-        sw.resize(F);
-        FHW_HIP(c, hipMemcpy(done.data(), c->d_done, sizeof(int32_t) * F, hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(sw.data(), c->d_sweeps, sizeof(int32_t) * F, hipMemcpyDeviceToHost));
+        done.resize(nf);
+        sw.resize(nf);
+        FHW_HIP(c, hipMemcpy(done.data(), d_done, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(sw.data(), d_sw, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
     }
-    for (int j = 0; j < F; ++j) {
+    for (size_t j = 0; j < nf; ++j) {
         if (resid) resid[j] = have_norms ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
         if (sweeps) sweeps[j] = fp32 ? (done[j] ? sw[j] : p.refine_max) : 0;
     }
     if (st[0]) return fhw_fail(c, FHW_E_SINGULAR, "solve: exactly zero pivot in an LU factorization");
     if (fp32)
-        for (int j = 0; j < F; ++j)
+        for (size_t j = 0; j < nf; ++j)
             if (!done[j]) return fhw_fail(c, FHW_E_NOCONV, "solve: refinement did not reach refine_tol");
     return FHW_OK;
+}
+
+int fhw_solve_densities(fhw_ctx* c, void* psi, double* resid, int32_t* sweeps, int32_t compute_resid) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (!psi) return fhw_fail(c, FHW_E_INVALID, "solve: psi is null");
+    return solve_impl(c, nullptr, 1, psi, resid, sweeps, compute_resid);
+}
+
+int fhw_solve_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
+                         int32_t* sweeps, int32_t compute_resid) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (!inc || n_inc < 1 || !psi) return fhw_fail(c, FHW_E_INVALID, "solve: need n_inc >= 1 incidences and psi");
+    for (int q = 0; q < n_inc; ++q) {
+        const double a = inc[q].v[0], b = inc[q].v[1];
+        if (!isfinite(a) || !isfinite(b)) return fhw_fail(c, FHW_E_INVALID, "solve: incidence not finite");
+        if (inc[q].kind == FHW_INC_PLANE) {
+            if (fabs(hypot(a, b) - 1.0) > 1e-12) return fhw_fail(c, FHW_E_INVALID, "solve: direction not a unit vector");
+        } else if (inc[q].kind == FHW_INC_POINT) {
+            double dmin;
+            if (winding_number(c, a, b, &dmin) != 0 || !(dmin > 0.0))
+                return fhw_fail(c, FHW_E_INVALID, "solve: point source on or inside the curve");
+        } else {
+            return fhw_fail(c, FHW_E_INVALID, "solve: unknown incidence kind");
+        }
+    }
+    return solve_impl(c, inc, n_inc, psi, resid, sweeps, compute_resid);
 }
 
 int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, double zero_value, void* V) {

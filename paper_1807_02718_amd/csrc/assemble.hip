@@ -152,3 +152,45 @@ int64_t assemble_blocks_for(int32_t N) {
     const int64_t T = (N + AT - 1) / AT;
     return T * (T + 1) / 2;
 }
+
+// Boundary data g = dB/dnu - i eta B of eq. CFIE_direct for one incidence at
+// every node of each frequency (one workgroup per frequency):
+//   plane wave   B = exp(i kappa p.x):  g = i (kappa p.nu - eta) exp(i kappa p.x)
+//   point source B = (i/4) H0(kappa rho), rho = |x - r0|, r0 outside the curve:
+//                dB/dnu = -(i kappa / 4) H1(kappa rho) nu.(x - r0) / rho
+__global__ __launch_bounds__(ASM_THREADS) void k_rhs(const fhw_assemble_item* __restrict__ items, int kind,
+                                                     double v0, double v1, zd* __restrict__ g) {
+    const fhw_assemble_item it = items[blockIdx.x];
+    const int N = it.N;
+    const double kappa = it.kappa, eta = it.eta;
+    const double* x1 = it.geom;
+    const double* x2 = it.geom + N;
+    const double* nu1 = it.geom + 7 * N;
+    const double* nu2 = it.geom + 8 * N;
+    for (int i = threadIdx.x; i < N; i += ASM_THREADS) {
+        zd gi;
+        if (kind == FHW_INC_PLANE) {
+            const double alpha = kappa * (v0 * nu1[i] + v1 * nu2[i]) - eta;
+            double sn, cs;
+            sincos(kappa * (v0 * x1[i] + v1 * x2[i]), &sn, &cs);
+            gi = cmk(-alpha * sn, alpha * cs);
+        } else {
+            const double d1 = x1[i] - v0, d2 = x2[i] - v1;
+            const double rho = sqrt(d1 * d1 + d2 * d2);
+            double J0, Y0, J1, Y1;
+            fhw_bessel01(kappa * rho, J0, Y0, J1, Y1);
+            const double cn = (nu1[i] * d1 + nu2[i] * d2) / rho;
+            const double Br = -0.25 * Y0, Bi = 0.25 * J0;                                 // (i/4) H0
+            const double dBr = 0.25 * kappa * cn * Y1, dBi = -0.25 * kappa * cn * J1;   // -(i kappa/4) H1 cn
+            gi = cmk(dBr + eta * Bi, dBi - eta * Br);
+        }
+        g[it.g_off + i] = gi;
+    }
+}
+
+hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n_items, int32_t kind, double v0,
+                      double v1, void* g) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rhs, dim3(n_items), dim3(ASM_THREADS), 0, s, d_items, kind, v0, v1, (zd*)g);
+    return hipGetLastError();
+}

@@ -123,6 +123,10 @@ hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_item
                                   int32_t n_items, int64_t total_blocks, double p1, double p2, void* A,
                                   void* A32, void* g);
 int64_t assemble_blocks_for(int32_t N);
+// boundary data of one incidence (FHW_INC_PLANE: v = p; FHW_INC_POINT: v = r0)
+// for every item, written at g + g_off
+hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n_items, int32_t kind, double v0,
+                      double v1, void* g);
 
 // --- lu.hip -----------------------------------------------------------------
 struct fhw_lu_sched {

@@ -1,0 +1,209 @@
+"""Parity at the full size of the solve-throughput workload: kite, N = 1024 at
+each of 1024 frequencies on (0, 69], one plane-wave direction, 256 points on
+the radius-3 ring, 1024 times reaching T = 1e4, planned exactly as the
+benchmark plans it (FP32 LU + FP64 refinement to 1e-12, and FP64).
+
+The oracle cannot redo all 1024 solves inside a test, so:
+  * densities and fields are compared at sampled frequencies, each solved by
+    the oracle on its own;
+  * time samples are compared with oracle values written by
+    tests/golden/make_kite_n1024_golden.py (4 of the 256 points, all times);
+  * the synthesis alone runs on a pure-delay spectrum V = exp(i w d_r), whose
+    time-domain field is the delayed boundary signal -f(t - d_r) in closed form;
+  * points inside the kite see the incident signal exactly (extinction).
+Tolerances: FP64 densities 1e-11 (relative, max norm); FP32+refinement
+densities kappa_2(A) times the reported residual; time samples 1e-10 relative
+to the largest sample.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+from scipy import special
+
+import oracle as O
+import workloads as Wk
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SAMPLED = [0, 255, 511, 767, 1023]
+REFINE_TOL = 1e-12
+
+
+def say(*a):
+    print("CASE", *a, flush=True)
+
+
+def relmax(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fhw():
+    from paper_1807_02718_amd import fhw as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def wl():
+    return Wk.kite_n1024()
+
+
+@pytest.fixture(scope="module")
+def oracle_sampled(wl):
+    """Oracle densities, fields, residual-free references and condition numbers
+    at the sampled frequencies."""
+    omega, kappa = O.frequency_grid(wl.W, wl.F)
+    eta = O.coupling(kappa)
+    gm = O.geometry(wl.curve, wl.N)
+    out = {}
+    for j in SAMPLED:
+        A = O.assemble(gm, kappa[j], eta[j])
+        g = O.rhs_plane_wave(gm, kappa[j], eta[j], wl.direction)
+        psi, _ = O.solve_density(A, g)
+        V = O.field(gm, psi, kappa[j], wl.obs)
+        out[j] = dict(A=A, g=g, psi=psi, V=V, cond=float(np.linalg.cond(A)))
+    return out
+
+
+@pytest.fixture(scope="module", params=["fp32_refine", "fp64"])
+def gpu_run(request, fhw, wl):
+    precision = request.param
+    say("full-size kite N=1024 F=1024", precision)
+    ctx = fhw.Context()
+    Ns, off = ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=REFINE_TOL,
+                       refine_max=10, direction=wl.direction)
+    psi, resid, sweeps = ctx.solve_densities(compute_resid=True)
+    V = ctx.eval_field(psi, wl.obs, zero_value=1.0)
+    f = torch.as_tensor(wl.signal.f, device=psi.device)
+    u = ctx.synthesize(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times)
+    res = dict(precision=precision, Ns=np.asarray(Ns), off=np.asarray(off), resid=resid, sweeps=sweeps,
+               psi={j: psi[int(off[j]):int(off[j + 1])].cpu().numpy() for j in SAMPLED},
+               V=V.cpu().numpy(), u=u.cpu().numpy(), ctx=ctx)
+    yield res
+    ctx.close()
+
+
+def test_fullsize_densities_sampled(gpu_run, oracle_sampled, wl):
+    prec = gpu_run["precision"]
+    assert np.all(gpu_run["Ns"] == 1024)
+    if prec == "fp32_refine":
+        assert np.max(gpu_run["resid"]) <= REFINE_TOL
+    for j in SAMPLED:
+        o = oracle_sampled[j]
+        p = gpu_run["psi"][j]
+        err = relmax(p, o["psi"])
+        err2 = float(np.linalg.norm(p - o["psi"]) / np.linalg.norm(o["psi"]))
+        # residual of the GPU density against the oracle's matrix and data
+        r_o = float(np.linalg.norm(o["g"] - o["A"] @ p) / np.linalg.norm(o["g"]))
+        say(prec, "freq", j, "cond", round(o["cond"], 2), "err_inf", err, "err_2", err2, "resid(oracle A)", r_o,
+            "sweeps", int(gpu_run["sweeps"][j]))
+        if prec == "fp64":
+            assert err < 1e-11
+        else:
+            assert r_o <= 1.5 * REFINE_TOL
+            # ||d psi|| <= kappa_2 ||r|| / ||g|| ||psi|| (plus the FP64 floor)
+            assert err2 <= 1.1 * o["cond"] * r_o + 1e-13
+
+
+def test_fullsize_field_sampled(gpu_run, oracle_sampled, wl):
+    prec = gpu_run["precision"]
+    F = wl.F
+    V = gpu_run["V"]
+    assert V.shape == (len(wl.obs), 2 * F)
+    for j in SAMPLED:
+        o = oracle_sampled[j]
+        # omega_{j+1} sits at grid index F + 1 + j; the top frequency W is
+        # held only through its conjugate at -W (index 0) on [-W, W)
+        if F + 1 + j < 2 * F:
+            Vg = V[:, F + 1 + j]
+            assert np.array_equal(V[:, F - 1 - j], np.conj(Vg))   # Hermitian extension
+        else:
+            Vg = np.conj(V[:, 0])
+        err = relmax(Vg, o["V"])
+        say(prec, "field freq", j, "err", err)
+        if prec == "fp64":
+            assert err < 1e-11
+        else:
+            # the field is a fixed linear functional of the density:
+            # |dV_r| <= ||w_r||_2 ||d psi||_2 with w_r = (pi/n) (i/4) H0 |x'|
+            gm = O.geometry(wl.curve, wl.N)
+            _, kappa = O.frequency_grid(wl.W, F)
+            d = np.hypot(wl.obs[:, None, 0] - gm["x"][None, :, 0], wl.obs[:, None, 1] - gm["x"][None, :, 1])
+            w = (np.pi / (wl.N // 2)) * 0.25 * np.abs(special.hankel1(0, kappa[j] * d)) * gm["speed"][None, :]
+            bound = np.linalg.norm(w, axis=1) * np.linalg.norm(gpu_run["psi"][j] - o["psi"])
+            assert np.all(np.abs(Vg - o["V"]) <= 1.1 * bound + 1e-13 * np.max(np.abs(o["V"])))
+    assert np.all(V[:, F] == 1.0)
+
+
+def test_fullsize_time_samples_vs_oracle(gpu_run, wl):
+    meta = json.load(open(os.path.join(HERE, "golden", "kite_n1024_u_sample.json")))
+    ref = np.load(os.path.join(HERE, "golden", "kite_n1024_u_sample.npy"))
+    assert meta["workload"] == wl.name and ref.shape == (len(meta["obs_index"]), len(wl.times))
+    u = gpu_run["u"][meta["obs_index"]]
+    err = relmax(u, ref)
+    say(gpu_run["precision"], "time samples vs oracle (4 points x 1024 times)", err, "max|u|", float(np.max(np.abs(ref))))
+    assert err < 1e-10
+    assert np.all(np.isfinite(gpu_run["u"]))
+
+
+def test_fullsize_synthesis_delay(fhw, wl):
+    """Synthesis of a pure delay V(r, w) = exp(i w d_r) on the full DFT grid:
+    the field is a(t - d_r) = -f(t - d_r), and the oracle's synthesis from the
+    same spectrum agrees on a sample of points."""
+    say("full-size synthesis, delay spectrum")
+    ctx = fhw.Context()
+    try:
+        ctx.plan(wl.curve, wl.W, wl.F, N=wl.N)
+        Nr = len(wl.obs)
+        d = np.linspace(-3.0, 5.0, Nr)
+        dw = wl.W / wl.F
+        omega_l = -wl.W + dw * np.arange(2 * wl.F)
+        Vh = np.exp(1j * omega_l[None, :] * d[:, None])
+        V = torch.as_tensor(Vh, device="cuda")
+        f = torch.as_tensor(wl.signal.f, device="cuda")
+        u = ctx.synthesize(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times).cpu().numpy()
+    finally:
+        ctx.close()
+    exact = -Wk.chirp_value(wl.times[None, :] - d[:, None], 1.0e4 + 5.0, rate=16000.0)
+    err_exact = float(np.max(np.abs(u - exact)))
+    # the oracle's synthesis on 8 of the points
+    sel = np.arange(0, Nr, Nr // 8)
+    t = wl.signal.t
+    ks = O.window_indices(t[0], t[-1], wl.H)
+    act = np.zeros(len(ks), dtype=bool)
+    for tt in wl.times:
+        act |= O.active_windows(tt, ks, wl.H, wl.tau0, dw)
+    ks = ks[act]
+    B = O.window_spectra(wl.signal, wl.H, ks, omega_l)
+    ref, _ = O.synthesize(Vh[sel], B, ks, wl.H, wl.tau0, wl.W, wl.times)
+    err_o = relmax(u[sel], ref)
+    say("delay: |u - exact|", err_exact, "vs oracle", err_o, "windows", len(ks))
+    assert err_o < 1e-10
+    assert err_exact < 1e-9
+
+
+def test_fullsize_interior_extinction(fhw, wl):
+    """Points inside the kite: the scattered field cancels the incident one, so
+    u(x, t) = -f(t - p.x) (plane wave, direction p)."""
+    say("full-size interior extinction")
+    pts = Wk.interior_points(wl.curve, 16, seed=5)
+    ctx = fhw.Context()
+    try:
+        ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision="fp32_refine", refine_tol=REFINE_TOL, refine_max=10,
+                 direction=wl.direction)
+        psi, _, _ = ctx.solve_densities()
+        V = ctx.eval_field(psi, pts, zero_value=1.0)
+        f = torch.as_tensor(wl.signal.f, device=psi.device)
+        u = ctx.synthesize(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times).cpu().numpy()
+    finally:
+        ctx.close()
+    p = np.asarray(wl.direction)
+    exact = -Wk.chirp_value(wl.times[None, :] - (pts @ p)[:, None], 1.0e4 + 5.0, rate=16000.0)
+    err = float(np.max(np.abs(u - exact)))
+    say("interior extinction max error", err)
+    assert err < 1e-9

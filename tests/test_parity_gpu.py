@@ -352,3 +352,90 @@ def test_single_frequency(ctx):
     u = _pipeline(ctx, wl)
     ref = O.run(wl.curve, wl.W, wl.F, wl.N, wl.direction, sig, wl.H, wl.tau0, wl.obs, wl.times)
     assert relmax(u, ref) < 1e-10
+
+
+# ------------------------------------------------- several incidences (a5)
+_INCS = [("plane", (1.0, 0.0)), ("plane", (0.6, -0.8)), ("point", (3.0, 0.5)), ("point", (-0.5, 2.9))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_incidences_kite_ragged(ctx, precision):
+    """One factorization per frequency serves plane waves and exterior point
+    sources; each density matches the oracle's own solve."""
+    say("incidences kite ragged", precision)
+    curve, W, F = Wk.kite(), 40.0, 6
+    rule = dict(ppw=10.0, n_min=64, n_mult=32, n_cap=4096)
+    Ns, off = ctx.plan(curve, W, F, precision=precision, refine_tol=1e-14, refine_max=8, **rule)
+    psi, res, sw = ctx.solve_incidences(_INCS)
+    assert psi.shape == (len(_INCS), int(off[-1]))
+    _, kappa = O.frequency_grid(W, F)
+    eta = O.coupling(kappa)
+    P = psi.cpu().numpy()
+    for j in range(F):
+        gm = O.geometry(curve, int(Ns[j]))
+        A = O.assemble(gm, kappa[j], eta[j])
+        for q, (kind, v) in enumerate(_INCS):
+            g = O.rhs_plane_wave(gm, kappa[j], eta[j], v) if kind == "plane" else O.rhs_point_source(gm, kappa[j], eta[j], v)
+            ref, _ = O.solve_density(A, g)
+            err = relmax(P[q, off[j]:off[j + 1]], ref)
+            assert err < 1e-11, (j, q, err)
+    if precision == "fp32_refine":
+        assert np.all(res <= 1e-14)
+
+
+def test_incidences_single_equals_densities(ctx):
+    say("incidences: one plane wave = solve_densities")
+    wl = Wk.circle_pulse()
+    ctx.plan(wl.curve, wl.W, 16, N=wl.N, direction=(0.6, 0.8))
+    psi1, _, _ = ctx.solve_densities()
+    psi2, _, _ = ctx.solve_incidences([("plane", (0.6, 0.8))])
+    assert relmax(psi2[0].cpu().numpy(), psi1.cpu().numpy()) < 1e-14
+
+
+def test_point_source_interior_extinction(ctx):
+    """Field of the point-source density inside the scatterer equals the free
+    field of the source, G(x, r0) = (i/4) H0(kappa |x - r0|)."""
+    say("point source interior extinction")
+    curve, W, F, N = Wk.kite(), 12.0, 4, 256
+    r0 = (2.5, 1.5)
+    ctx.plan(curve, W, F, N=N)
+    psi, res, _ = ctx.solve_incidences([("point", r0)], compute_resid=True)
+    assert np.all(res < 1e-13)
+    pts = Wk.interior_points(curve, 8, seed=7)
+    V = ctx.eval_field(psi[0], pts, zero_value=0.0).cpu().numpy()
+    _, kappa = O.frequency_grid(W, F)
+    rho = np.hypot(pts[:, 0] - r0[0], pts[:, 1] - r0[1])
+    for j in range(F):
+        exact = 0.25j * special.hankel1(0, kappa[j] * rho)
+        # the top frequency W is stored only as its conjugate at -W (index 0)
+        Vj = V[:, F + 1 + j] if j < F - 1 else np.conj(V[:, 0])
+        assert relmax(Vj, exact) < 1e-10
+    assert np.all(V[:, F] == 0)
+
+
+def test_pipeline_point_source(ctx):
+    """Whole pipeline for an exterior point source vs the oracle's."""
+    say("pipeline point source")
+    sig = Wk.gaussian_pulse(t0=0.0, t1=20.0, dt=1 / 64, center=9.0, var2=2.0, freq=10.0)
+    curve, W, F, N = Wk.circle(1.0), 24.0, 64, 96
+    r0 = (2.0, 1.0)
+    obs, times, H, tau0 = Wk.ring(6, 3.0), np.linspace(0, 30, 61), 6.0, 3.0
+    ctx.plan(curve, W, F, N=N)
+    psi, _, _ = ctx.solve_incidences([("point", r0)])
+    V = ctx.eval_field(psi[0], obs, zero_value=0.0)
+    u = ctx.synthesize(sig.f, sig.t0, sig.dt, H, tau0, V, times).cpu().numpy()
+    ref = O.run(curve, W, F, N, (1.0, 0.0), sig, H, tau0, obs, times, incidence="point", r0=np.array(r0))
+    assert relmax(u, ref) < 1e-10
+
+
+def test_incidences_rejects(ctx, fhw):
+    say("incidences: argument errors")
+    ctx.plan(Wk.kite(), 10.0, 2, N=64)
+    for bad in ([("point", (0.0, 0.0))],            # inside the kite
+                [("plane", (1.0, 1.0))],            # not a unit vector
+                [("plane", (float("nan"), 0.0))],
+                [(7, (1.0, 0.0))],                  # unknown kind
+                []):
+        with pytest.raises(fhw.FhwError) as e:
+            ctx.solve_incidences(bad)
+        assert e.value.code == fhw.FHW_E_INVALID

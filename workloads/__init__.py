@@ -135,17 +135,23 @@ def gaussian_pulse(t0=-1.0, t1=10.0, dt=1.0 / 256, center=4.0, var2=0.5, freq=6.
     return Signal(t0, dt, np.exp(-(t - center) ** 2 / var2) * np.cos(freq * t))
 
 
-def chirp(t_end: float, dt: float, rate: float = 4000.0, ramp: float = 5.0) -> Signal:
+def chirp_value(t, t_end: float, rate: float = 4000.0, ramp: float = 5.0):
     """Chirp sin(g + g^2/rate), g = 4t + 6 cos(t / sqrt 12) (the paper's chirp
     incidence, Sec. 6.3, for rate = 4000), switched on over [0, ramp] and off
     over [t_end, t_end + ramp] with a C-infinity step so that the signal is
-    compactly supported in [0, t_end + ramp]."""
+    compactly supported in [0, t_end + ramp].  Any real t."""
+    t = np.asarray(t, dtype=float)
     T = t_end + ramp
-    n = int(np.ceil(T / dt)) + 1
-    t = dt * np.arange(n)
     g = 4.0 * t + 6.0 * np.cos(t / np.sqrt(12.0))
     env = _smoothstep(t / ramp) * _smoothstep((T - t) / ramp)
-    return Signal(0.0, dt, env * np.sin(g + g * g / rate))
+    return env * np.sin(g + g * g / rate)
+
+
+def chirp(t_end: float, dt: float, rate: float = 4000.0, ramp: float = 5.0) -> Signal:
+    """chirp_value sampled at n dt, n = 0 .. ceil((t_end + ramp)/dt)."""
+    n = int(np.ceil((t_end + ramp) / dt)) + 1
+    t = dt * np.arange(n)
+    return Signal(0.0, dt, chirp_value(t, t_end, rate, ramp))
 
 
 # --------------------------------------------------------------------------
