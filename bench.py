@@ -80,6 +80,43 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
     return dict(seconds=dt, prof=prof, Ns=[int(n) for n in Ns], res=res, sweeps=sw)
 
 
+def latency(fhw, torch, wl, precision, reps):
+    """Latency of one isolated solve at N = 1024 (the top frequency of the
+    band, one plane wave): cold = assembly + LU + solve (+ refinement) with
+    fhw_solve_densities; warm = a new right-hand side on the resident factors
+    with fhw_solve_cached.  Host wall clock around each synchronous call."""
+    ctx = fhw.Context()
+    ctx.plan(wl.curve, wl.W, 1, N=wl.N, precision=precision, refine_tol=1e-12, refine_max=10,
+             direction=wl.direction)
+    psi = torch.empty(wl.N, dtype=torch.complex128, device="cuda")
+    psi2 = torch.empty((1, wl.N), dtype=torch.complex128, device="cuda")
+    inc = [("plane", wl.direction)]
+    cold, warm = [], []
+    for i in range(reps + 2):
+        t0 = time.perf_counter()
+        ctx.solve_densities(psi)
+        t1 = time.perf_counter()
+        ctx.solve_cached(inc, psi2)
+        t2 = time.perf_counter()
+        if i >= 2:
+            cold.append(t1 - t0)
+            warm.append(t2 - t1)
+    ctx.close()
+    q = lambda a, p: float(np.percentile(np.asarray(a) * 1e3, p))
+    return {"cold_p50_ms": q(cold, 50), "cold_p99_ms": q(cold, 99), "warm_p50_ms": q(warm, 50),
+            "warm_p99_ms": q(warm, 99), "reps": reps}
+
+
+def copy_calibration(torch, nbytes, reps):
+    """A plain device copy of nbytes (torch copy_), for scaling HBM counters."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def cpu_baseline(wl, n_freq):
     """The FP64 oracle on a bounded sample: n_freq frequencies spread over the
     band, each = assembly + LAPACK solve + field at all observation points."""
@@ -107,8 +144,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--freqs", type=int, default=1024, help="frequencies in the batch (workload default 1024)")
-    ap.add_argument("--cpu-freqs", type=int, default=8, help="oracle sample size for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-freqs", type=int, default=96, help="oracle sample size for cpu_baseline (0 = skip)")
     ap.add_argument("--modes", default="fp32_refine,fp64")
+    ap.add_argument("--latency-reps", type=int, default=50, help="isolated-solve latency samples (0 = skip)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -116,6 +156,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if a.copy_bytes > 0:
+        copy_calibration(torch, a.copy_bytes, 3)
+        return
     import workloads as Wk
     from paper_1807_02718_amd import fhw
 
@@ -163,6 +206,9 @@ def main():
         rr = results[m]
         out[m] = {"value": wl.F * a.steps / rr["seconds"], "ms_per_step": 1e3 * rr["seconds"] / a.steps,
                   "stages_ms_per_step": {k: v[0] / a.steps for k, v in rr["prof"].items()}}
+    if a.latency_reps > 0:
+        print("bench: latency", file=sys.stderr, flush=True)
+        out["latency"] = {m: latency(fhw, torch, wl, m, a.latency_reps) for m in modes}
     if a.cpu_freqs > 0:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_freqs)

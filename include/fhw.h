@@ -8,6 +8,8 @@
  *                        Kress weights (Sec. 2.3, Sec. 4.1.1)
  *   fhw_solve_densities  assemble + factor + solve the direct combined-field
  *                        equation (eq. CFIE_direct) at every frequency (step F3)
+ *   fhw_solve_incidences the same for several incident fields per factorization
+ *   fhw_solve_cached     further incident fields on factors left resident
  *   fhw_eval_field       layer potential U = int psi G (eqs. freq_domain_repr,
  *                        Ukslow_repr; step F5)
  *   fhw_synthesize       windowed, recentred signal spectra (eq. Bkslow_eqn,
@@ -135,6 +137,17 @@ typedef struct {
  * values; FHW_E_SINGULAR / FHW_E_NOCONV as in fhw_solve_densities. */
 int fhw_solve_incidences(fhw_ctx* ctx, const fhw_incidence* inc, int32_t n_inc, void* psi,
                          double* resid, int32_t* sweeps, int32_t compute_resid);
+
+/* As fhw_solve_incidences, but with the factors left resident by the last
+ * solve call on this plan: no assembly and no factorization, only the
+ * triangular solves (and, in FP32_REFINE, the FP64-residual refinement
+ * against the resident FP64 matrix).  Factors stay resident when the whole
+ * plan fits one workspace chunk and the last solve did not compute FP64
+ * residuals (those re-assemble A over the FP64 factors).
+ * Errors: FHW_E_STATE when no factors are resident; otherwise as
+ * fhw_solve_incidences. */
+int fhw_solve_cached(fhw_ctx* ctx, const fhw_incidence* inc, int32_t n_inc, void* psi,
+                     double* resid, int32_t* sweeps);
 
 /* Step F5 (eqs. freq_domain_repr, Ukslow_repr): V(r, omega_l) on the full DFT
  * grid, V[r][l], complex128 [N_r][2F]; V(r,-omega) = conj V(r,omega) and

@@ -78,6 +78,7 @@ void free_plan(fhw_ctx* c) {
     c->d_curve = nullptr; c->A64 = c->A32 = c->linv = nullptr; c->piv = nullptr; c->x = c->r = nullptr;
     c->meta = nullptr; c->d_status = nullptr; c->d_norms = nullptr; c->d_done = nullptr; c->d_sweeps = nullptr;
     c->planned = false;
+    c->factors_resident = false;
 }
 
 int lds_limit(fhw_ctx* c) {
@@ -472,7 +473,7 @@ static int winding_number(const fhw_ctx* c, double a, double b, double* min_dist
 // boundary data the assembly kernel writes).  psi holds n_inc blocks of
 // psi_off[F] elements; resid / sweeps [host] are [n_inc][F].
 static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
-                      int32_t* sweeps, int32_t compute_resid) {
+                      int32_t* sweeps, int32_t compute_resid, bool reuse) {
     plan_ext& px = g_plans[c];
     const fhw_problem& p = c->prob;
     const int F = p.F;
@@ -499,11 +500,15 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
     zd* r = (zd*)c->r;
     for (auto& ch : px.chunks) {
         fhw_batch_dev bd{ch.d_N, ch.d_aoff, ch.d_pivoff, ch.d_linvoff, ch.d_voff, ch.count};
-        STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
-                                          p.direction[0], p.direction[1], c->A64, fp32 ? c->A32 : nullptr, g));
         void* LU = fp32 ? c->A32 : c->A64;
-        FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
-                                    p.precision, &c->prof));
+        if (!reuse) {
+            c->factors_resident = false;
+            STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count,
+                                                                ch.asm_blocks, p.direction[0], p.direction[1], c->A64,
+                                                                fp32 ? c->A32 : nullptr, g));
+            FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
+                                        p.precision, &c->prof));
+        }
         for (int q = 0; q < n_inc; ++q) {
             zd* x = psid + q * total + ch.psi_base;     // solution written in place into psi
             if (inc)
@@ -526,6 +531,7 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
         }
         if (!fp32 && compute_resid) {
             // the factorization overwrote A: assemble it again for the residuals
+            // (which also ends the residency of the FP64 factors)
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
                                               p.direction[0], p.direction[1], c->A64, nullptr, g));
             for (int q = 0; q < n_inc; ++q) {
@@ -541,6 +547,9 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     int32_t st[4];
     FHW_HIP(c, hipMemcpy(st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    // factors stay usable when the whole plan fits one chunk and nothing
+    // overwrote them (FP64 residuals re-assemble A in place)
+    if (!reuse) c->factors_resident = px.chunks.size() == 1 && !(!fp32 && compute_resid) && !st[0];
     const size_t nf = (size_t)F * n_inc;
     std::vector<double> nrm;
     std::vector<int32_t> done, sw;
@@ -570,13 +579,10 @@ int fhw_solve_densities(fhw_ctx* c, void* psi, double* resid, int32_t* sweeps, i
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
     if (!psi) return fhw_fail(c, FHW_E_INVALID, "solve: psi is null");
-    return solve_impl(c, nullptr, 1, psi, resid, sweeps, compute_resid);
+    return solve_impl(c, nullptr, 1, psi, resid, sweeps, compute_resid, false);
 }
 
-int fhw_solve_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
-                         int32_t* sweeps, int32_t compute_resid) {
-    if (!c) return FHW_E_INVALID;
-    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+static int check_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, const void* psi) {
     if (!inc || n_inc < 1 || !psi) return fhw_fail(c, FHW_E_INVALID, "solve: need n_inc >= 1 incidences and psi");
     for (int q = 0; q < n_inc; ++q) {
         const double a = inc[q].v[0], b = inc[q].v[1];
@@ -591,7 +597,28 @@ int fhw_solve_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, vo
             return fhw_fail(c, FHW_E_INVALID, "solve: unknown incidence kind");
         }
     }
-    return solve_impl(c, inc, n_inc, psi, resid, sweeps, compute_resid);
+    return FHW_OK;
+}
+
+int fhw_solve_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
+                         int32_t* sweeps, int32_t compute_resid) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    int rc = check_incidences(c, inc, n_inc, psi);
+    if (rc) return rc;
+    return solve_impl(c, inc, n_inc, psi, resid, sweeps, compute_resid, false);
+}
+
+int fhw_solve_cached(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
+                     int32_t* sweeps) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (!c->factors_resident)
+        return fhw_fail(c, FHW_E_STATE, "solve_cached: no resident factors (no solve yet, several chunks, "
+                                        "or FP64 residuals overwrote them)");
+    int rc = check_incidences(c, inc, n_inc, psi);
+    if (rc) return rc;
+    return solve_impl(c, inc, n_inc, psi, resid, sweeps, 0, true);
 }
 
 int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, double zero_value, void* V) {

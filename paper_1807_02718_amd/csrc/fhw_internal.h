@@ -61,6 +61,7 @@ struct fhw_ctx {
 
     // plan
     bool planned = false;
+    bool factors_resident = false;     // LU of every planned frequency in the workspace
     fhw_problem prob{};
     std::vector<double> cx, sx, cy, sy;
     int32_t degree = 0;

@@ -75,6 +75,7 @@ def _load():
         "fhw_plan": [vp, C.POINTER(fhw_curve), C.POINTER(fhw_problem), p_i32, p_i64],
         "fhw_solve_densities": [vp, vp, _dp, p_i32, i32],
         "fhw_solve_incidences": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32, i32],
+        "fhw_solve_cached": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
         "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
         "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
         "fhw_geometry": [vp, i32, vp],
@@ -99,7 +100,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_solve_densities",
-            "fhw_solve_incidences", "fhw_eval_field", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
@@ -189,22 +190,32 @@ class Context:
                                              sweeps.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(compute_resid))))
         return psi, resid, sweeps
 
-    def solve_incidences(self, incidences, psi=None, compute_resid=False):
-        """incidences: sequence of ("plane", (p1, p2)) or ("point", (x, y)).
-        Returns (psi [n_inc, psi_off[F]] complex128, resid [n_inc, F], sweeps [n_inc, F])."""
+    def _incidences(self, incidences, psi):
         kinds = {"plane": FHW_INC_PLANE, "point": FHW_INC_POINT}
         n = len(incidences)
         arr = (fhw_incidence * max(n, 1))()
         for q, (kind, v) in enumerate(incidences):
             arr[q].kind = kinds[kind] if isinstance(kind, str) else int(kind)
             arr[q].v[0], arr[q].v[1] = float(v[0]), float(v[1])
-        total = int(self.psi_off[-1])
         if psi is None:
-            psi = torch.empty((max(n, 1), total), dtype=torch.complex128, device=self.device)
+            psi = torch.empty((max(n, 1), int(self.psi_off[-1])), dtype=torch.complex128, device=self.device)
         resid = np.zeros((max(n, 1), self.F))
         sweeps = np.zeros((max(n, 1), self.F), dtype=np.int32)
+        return arr, n, psi, resid, sweeps
+
+    def solve_incidences(self, incidences, psi=None, compute_resid=False):
+        """incidences: sequence of ("plane", (p1, p2)) or ("point", (x, y)).
+        Returns (psi [n_inc, psi_off[F]] complex128, resid [n_inc, F], sweeps [n_inc, F])."""
+        arr, n, psi, resid, sweeps = self._incidences(incidences, psi)
         self._check(_lib.fhw_solve_incidences(self._h, arr, n, _ptr(psi), resid.ctypes.data_as(_dp),
                                               sweeps.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(compute_resid))))
+        return psi, resid, sweeps
+
+    def solve_cached(self, incidences, psi=None):
+        """As solve_incidences, with the factors left resident by the last solve."""
+        arr, n, psi, resid, sweeps = self._incidences(incidences, psi)
+        self._check(_lib.fhw_solve_cached(self._h, arr, n, _ptr(psi), resid.ctypes.data_as(_dp),
+                                          sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
         return psi, resid, sweeps
 
     def eval_field(self, psi, obs, zero_value=1.0, V=None):

@@ -439,3 +439,52 @@ def test_incidences_rejects(ctx, fhw):
         with pytest.raises(fhw.FhwError) as e:
             ctx.solve_incidences(bad)
         assert e.value.code == fhw.FHW_E_INVALID
+
+
+def test_solve_cached(ctx, fhw):
+    """Right-hand sides on resident factors equal a fresh solve; residency
+    rules (no solve yet, FP64 residuals) are reported as FHW_E_STATE."""
+    say("solve_cached")
+    curve, W, F = Wk.kite(), 30.0, 4
+    rule = dict(ppw=10.0, n_min=64, n_mult=32, n_cap=4096)
+    incs = [("plane", (0.0, 1.0)), ("point", (2.5, -2.0))]
+    for precision in ("fp64", "fp32_refine"):
+        ctx.plan(curve, W, F, precision=precision, refine_tol=1e-14, refine_max=8, **rule)
+        with pytest.raises(fhw.FhwError) as e:
+            ctx.solve_cached(incs)
+        assert e.value.code == fhw.FHW_E_STATE
+        ref, _, _ = ctx.solve_incidences(incs)
+        ctx.solve_densities()                        # factors stay resident
+        got, res, _ = ctx.solve_cached(incs)
+        assert relmax(got.cpu().numpy(), ref.cpu().numpy()) < 1e-14
+        if precision == "fp32_refine":
+            assert np.all(res <= 1e-14)
+    ctx.plan(curve, W, F, precision="fp64", **rule)
+    ctx.solve_densities(compute_resid=True)          # FP64 residuals re-assemble A over the factors
+    with pytest.raises(fhw.FhwError) as e:
+        ctx.solve_cached(incs)
+    assert e.value.code == fhw.FHW_E_STATE
+
+
+def test_chunked_plan_matches(fhw):
+    """A small HBM budget splits the frequencies into several workspace
+    chunks; the densities agree with a single-chunk plan to rounding (the
+    panel kernel's sub-panel width follows the tallest matrix of a batch, so
+    the batch composition changes the order of operations)."""
+    say("chunked plan")
+    curve, W, F = Wk.kite(), 40.0, 6
+    rule = dict(ppw=10.0, n_min=64, n_mult=32, n_cap=4096)
+    out = []
+    for budget in (0, 16 << 20):
+        c = fhw.Context(hbm_budget_bytes=budget)
+        try:
+            c.plan(curve, W, F, precision="fp32_refine", refine_tol=1e-14, refine_max=8, **rule)
+            psi, _, _ = c.solve_densities()
+            out.append(psi.cpu().numpy())
+            if budget:
+                with pytest.raises(fhw.FhwError) as e:
+                    c.solve_cached([("plane", (1.0, 0.0))])
+                assert e.value.code == fhw.FHW_E_STATE
+        finally:
+            c.close()
+    assert relmax(out[1], out[0]) < 1e-13
