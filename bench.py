@@ -80,6 +80,21 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
     return dict(seconds=dt, prof=prof, Ns=[int(n) for n in Ns], res=res, sweeps=sw)
 
 
+# HBM bytes per launch of the trailing update on this workload, from rocprofv3
+# FETCH_SIZE (x2: a 1 GiB copy reads as 0.5 GiB, its 128 B requests counted at
+# 64 B) plus WRITE_SIZE; valid only for the lu.hip source with this sha256.
+UPDATE_TRAFFIC = {"lu_sha256": "2d372e258060b056f18fa9c641413fdf47f54ef4bbd8395bfe85a0cd0348f6e8",
+                  "fp32_refine": 6.085e9, "fp64": 12.229e9}
+
+
+def update_traffic(mode):
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1807_02718_amd", "csrc", "lu.hip")
+    with open(src, "rb") as f:
+        same = hashlib.sha256(f.read()).hexdigest() == UPDATE_TRAFFIC["lu_sha256"]
+    return UPDATE_TRAFFIC[mode] if same else None
+
+
 def latency(fhw, torch, wl, precision, reps):
     """Latency of one isolated solve at N = 1024 (the top frequency of the
     band, one plane wave): cold = assembly + LU + solve (+ refinement) with
@@ -195,7 +210,7 @@ def main():
                                f"{len(wl.times)} times, {main_mode}",
                    "global_batch": wl.F, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": update_traffic(main_mode), "traffic_unit": "bytes/launch",
                      "kernel": "k_lu_gemm<SUB> (trailing complex update)",
                      "avg_launch_ms": avg_ms, "launches": upd_n, "flops_per_launch": per_launch},
         "stages_ms_per_step": {k: v[0] / a.steps for k, v in r["prof"].items()},

@@ -483,6 +483,17 @@ __device__ __forceinline__ int find_prefix(const int* __restrict__ prefix, int n
     return lo;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup w runs on
+// XCD w mod 8), and each XCD has its own L2.  Renumber so that XCD x takes
+// one contiguous range of tiles: the tiles of a matrix then share one L2 and
+// its L and U panels are fetched from HBM about once.
+__device__ __forceinline__ int xcd_tile(int w, int G) {
+    constexpr int NX = 8;
+    const int per = G / NX, rem = G % NX;
+    const int x = w % NX, i = w / NX;
+    return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 // Stage one 16-deep chunk of the L and U operands in registers (real and
 // imaginary parts apart): L (k = tid/64 + 4p, i = tid%64), U (j = tid/16 +
 // 16p, k = tid%16).
@@ -554,8 +565,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
                                                  const int64_t* __restrict__ linv_off, cpx<T>* __restrict__ Abase,
                                                  const cpx<T>* __restrict__ linv) {
     typedef typename mfma_traits<T>::acc_t acc_t;
-    const int b = find_prefix(prefix, batch, blockIdx.x);
-    const int tile = blockIdx.x - prefix[b];
+    const int blk = xcd_tile(blockIdx.x, gridDim.x);
+    const int b = find_prefix(prefix, batch, blk);
+    const int tile = blk - prefix[b];
     const int N = Ns[b];
     const int nb = min(NB, N - k0);
     const int rest = N - k0 - nb;
