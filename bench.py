@@ -30,19 +30,17 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32_refine": 157.3}   # MI355X dense MFMA, FP64 /
 
 
 def lu_update_flops(Ns, nb=64):
-    """Algorithmic flops of the trailing complex updates A22 -= L21 U12
-    (8 real flops per complex multiply-add) and the number of launches."""
-    maxN = max(Ns)
-    total, launches = 0.0, 0
-    for k0 in range(0, maxN, nb):
-        any_tile = False
+    """Algorithmic flops of all trailing complex updates A22 -= L21 U12 of one
+    factorization batch (8 real flops per complex multiply-add): the sum over
+    panels of 8 nb rest^2, rest = N - k0 - nb.  The count does not depend on
+    how the updates are grouped into launches."""
+    total = 0.0
+    for k0 in range(0, max(Ns), nb):
         for N in Ns:
             rest = N - k0 - nb
             if rest > 0:
                 total += 8.0 * nb * rest * rest
-                any_tile = True
-        launches += 1 if any_tile else 0
-    return total, launches
+    return total
 
 
 def run_mode(fhw, torch, wl, precision, steps, warmup):
@@ -187,10 +185,10 @@ def main():
     r = results[main_mode]
     ms_step = 1e3 * r["seconds"] / a.steps
     value = wl.F * a.steps / r["seconds"]
-    flops, launches = lu_update_flops(r["Ns"])
+    flops = lu_update_flops(r["Ns"]) * a.steps        # all timed steps
     upd_ms, upd_n = r["prof"]["lu_update"]
     avg_ms = upd_ms / max(upd_n, 1)
-    per_launch = flops / max(launches, 1)
+    per_launch = flops / max(upd_n, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     peak = PEAK_TFLOPS[main_mode]
     out = {

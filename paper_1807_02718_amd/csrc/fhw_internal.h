@@ -130,14 +130,23 @@ hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n
                       double v1, void* g);
 
 // --- lu.hip -----------------------------------------------------------------
+// One launch of the batched factorization.  Panels go in pairs (2q, 2q+1):
+// the pair's trailing block is updated once with depth 128 (see lu.hip).
+enum { FHW_LU_OP_PANEL = 0, FHW_LU_OP_DIAGINV, FHW_LU_OP_SWAP, FHW_LU_OP_TRSM, FHW_LU_OP_SUB };
+struct fhw_lu_op {
+    int32_t kind;
+    int32_t k0;                          // first column of the op's panel
+    int32_t R;                           // PANEL: rows per thread
+    int32_t K, roff, rlim, coff, clim;   // SUB: depth; rows k0+roff.., cols k0+coff..; limits (0 = to N)
+    int32_t cbeg, ccount;                // SWAP: first column and count (0 = to N)
+    int32_t grid;                        // GEMM tiles or SWAP column blocks
+    int64_t prefix_off;                  // GEMM: offset of the op's tile prefix in prefix
+};
 struct fhw_lu_sched {
     // host-built launch schedule for one batched factorization
     int32_t nsteps;
-    std::vector<int32_t> R;                  // per step: panel rows per thread
-    std::vector<int64_t> gemm_trsm_off, gemm_upd_off;   // per step: offsets into d_prefix
-    std::vector<int32_t> gemm_trsm_tiles, gemm_upd_tiles, swap_blocks;
-    std::vector<int64_t> swap_off;
-    std::vector<int32_t> prefix;             // concatenated prefix arrays
+    std::vector<fhw_lu_op> ops;
+    std::vector<int32_t> prefix;         // concatenated per-op tile prefix arrays
 };
 void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch);
 hipError_t launch_lu_factor(hipStream_t s, const fhw_batch_dev& b, const fhw_lu_sched& sch,

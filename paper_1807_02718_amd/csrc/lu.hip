@@ -2,7 +2,8 @@
 // Nystrom system per frequency), FP64 or FP32, ragged batches of
 // column-major packed matrices (element (r, c) of matrix b at a_off[b] + c N + r).
 //
-// Right-looking, blocked by NB = 64 columns.  Per panel k0:
+// Right-looking, blocked by NB = 64 columns, panels in pairs (the schedule
+// at lu_build_schedule).  Per panel k0:
 //   k_lu_panel    one 256-thread workgroup per matrix (two to four per CU) factors
 //                 the (N-k0) x 64 panel in sub-panels of W columns held in
 //                 registers, rows owned by threads (coalesced in column-major);
@@ -10,12 +11,13 @@
 //                 first index on ties; sub-panel swaps and in-panel updates.
 //   k_lu_diaginv  inverses of the 64x64 unit-lower and upper diagonal blocks
 //                 (used by the trailing TRSM and by the solves), in LDS.
-//   k_lu_swap     the panel's row swaps on the trailing columns (no work when
-//                 the panel did not pivot, the usual case for these systems).
+//   k_lu_swap     the panel's row swaps on a column range (no work when the
+//                 panel did not pivot, the usual case for these systems).
 //   k_lu_gemm     U12 = L11^{-1} A12 (in place) and A22 -= L21 U12 on 64x64
-//                 tiles, the complex product as 4 real MFMA 16x16x4 products.
-// Earlier panels' L columns are not permuted by later pivots; the solves
-// replay the pivots panel by panel.
+//                 tiles with depth 64 or 128, the complex product as 4 real
+//                 MFMA 16x16x4 products.
+// A panel's L columns carry the pivots of its pair partner but not those of
+// later pairs; the solves replay the pivots pair by pair.
 #include "fhw_device.h"
 #include "fhw_internal.h"
 
@@ -405,10 +407,11 @@ __global__ __launch_bounds__(INV_THREADS) void k_lu_diaginv(int k0, const int* _
     }
 }
 
-// Row swaps of panel k0 on columns [k0+nb, N): one thread per column, swaps in
-// order (grid.y blocks of 256 columns).  Returns at once when no pivot moved.
+// Row swaps of panel k0 on the columns [cbeg, cbeg + ccount) (ccount = 0: up
+// to N), one thread per column, swaps in order (grid.y blocks of 256
+// columns).  Returns at once when no pivot of the panel moved.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_swap(int k0, const int* __restrict__ Ns,
+__global__ __launch_bounds__(256) void k_lu_swap(int k0, int cbeg, int ccount, const int* __restrict__ Ns,
                                                  const int64_t* __restrict__ a_off,
                                                  const int64_t* __restrict__ piv_off,
                                                  cpx<T>* __restrict__ Abase, const int* __restrict__ piv) {
@@ -426,8 +429,9 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, const int* __restrict__
     }
     __syncthreads();
     if (!any) return;
-    const int c = k0 + nb + blockIdx.y * 256 + threadIdx.x;
-    if (c >= N) return;
+    const int cend = ccount > 0 ? min(N, cbeg + ccount) : N;
+    const int c = cbeg + blockIdx.y * 256 + threadIdx.x;
+    if (c >= cend) return;
     cpx<T>* Ac = Abase + a_off[b] + (int64_t)c * N;
     for (int jj = 0; jj < nb; ++jj) {
         const int r1 = k0 + jj, r2 = sp[jj];
@@ -441,8 +445,10 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, const int* __restrict__
 
 // ---------------------------------------------------------------------------
 // Tiled complex GEMM on MFMA for the trailing update (column-major).
-//   TRSM mode: C(rows k0..k0+nb, cols k0+nb+64*tc ..) = Linv * C (in place)
-//   SUB  mode: C(rows k0+nb+64*tr.., cols k0+nb+64*tc..) -= L21 * U12
+//   TRSM mode: C(rows k0..k0+nb, cols k0+coff+64*tc ..) = Linv * C (in place)
+//   SUB  mode: C(rows k0+roff+64*tr.., cols k0+coff+64*tc..) -= L U with
+//              L = columns k0..k0+K-1 and U = rows k0..k0+K-1 of the matrix
+//              (K = 64: one panel; K = 128: a pair of panels)
 // The MFMA computes the transposed tile, D(j, i) = sum_k U(k, j) L(i, k), so
 // that the 16 consecutive lanes of a result row are 16 consecutive matrix rows
 // (coalesced column-major stores).  4 waves; wave (wj, wi) owns a 32x32
@@ -560,7 +566,8 @@ __device__ __forceinline__ void gemm_store_chunk(cpx<T> (&Ls)[NBUF][GK][GT + GPA
 // the single-buffered form is faster (higher occupancy): 96 vs 91 TFLOP/s in
 // FP32, 53.5 vs 42.9 in FP64 on the largest trailing update.
 template <typename T, bool SUB, bool DBUF = false>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0, const int* __restrict__ prefix, int batch,
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0, int K, int roff, int rlim, int coff,
+                                                 int clim, const int* __restrict__ prefix, int batch,
                                                  const int* __restrict__ Ns, const int64_t* __restrict__ a_off,
                                                  const int64_t* __restrict__ linv_off, cpx<T>* __restrict__ Abase,
                                                  const cpx<T>* __restrict__ linv) {
@@ -569,20 +576,33 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
     const int b = find_prefix(prefix, batch, blk);
     const int tile = blk - prefix[b];
     const int N = Ns[b];
-    const int nb = min(NB, N - k0);
-    const int rest = N - k0 - nb;
-    const int tcols = (rest + GT - 1) / GT;
-    int tr, tc;
-    if (SUB) { tr = tile / tcols; tc = tile - tr * tcols; } else { tr = 0; tc = tile; }
     cpx<T>* A = Abase + a_off[b];
-    const int col0 = k0 + nb + tc * GT;
-    const int row0 = SUB ? (k0 + nb + tr * GT) : k0;
-    const int nrows = SUB ? min(GT, N - row0) : nb;
-    const int ncols = min(GT, N - col0);
-    // L operand (i, k): SUB -> A[(k0+k)*N + row0+i]; TRSM -> Linv column-major (i, k) at k*NB + i
-    const cpx<T>* Lop = SUB ? (A + (int64_t)k0 * N + row0) : (linv + linv_off[b] + (int64_t)(k0 / NB) * NB * NB);
-    const int ldl = SUB ? N : NB;
-    const cpx<T>* Uop = A + (int64_t)col0 * N + k0;   // U12 (k, j) at j*N + k
+    int row0, col0, nrows, ncols, nb;
+    const cpx<T>* Lop;
+    int ldl;
+    if (SUB) {
+        const int rb = k0 + roff, cb = k0 + coff;
+        const int re = rlim > 0 ? min(N, rb + rlim) : N;
+        const int ce = clim > 0 ? min(N, cb + clim) : N;
+        const int tcols = (ce - cb + GT - 1) / GT;
+        const int tr = tile / tcols, tc = tile - tr * tcols;
+        row0 = rb + tr * GT;
+        col0 = cb + tc * GT;
+        nrows = min(GT, re - row0);
+        ncols = min(GT, ce - col0);
+        nb = min(K, N - k0);
+        Lop = A + (int64_t)k0 * N + row0;   // L (i, k) at (k0 + k) N + row0 + i
+        ldl = N;
+    } else {
+        nb = min(NB, N - k0);
+        row0 = k0;
+        col0 = k0 + coff + tile * GT;
+        nrows = nb;
+        ncols = min(GT, N - col0);
+        Lop = linv + linv_off[b] + (int64_t)(k0 / NB) * NB * NB;   // Linv column-major (i, k) at k NB + i
+        ldl = NB;
+    }
+    const cpx<T>* Uop = A + (int64_t)col0 * N + k0;   // U (k, j) at j N + k0 + k
     cpx<T>* C = A + (int64_t)col0 * N + row0;
     constexpr int NBUF = DBUF ? 2 : 1;
     __shared__ cpx<T> Ls[NBUF][GK][GT + GPAD];
@@ -671,42 +691,90 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
 // ---------------------------------------------------------------------------
 // Host side: schedule and launches
 // ---------------------------------------------------------------------------
+// tiles of one GEMM op for a matrix of order N (mirrors the kernel's geometry)
+static int gemm_tiles(int kind, int N, const fhw_lu_op& op) {
+    if (N - op.k0 <= 0) return 0;
+    if (kind == FHW_LU_OP_TRSM) {
+        const int nc = N - (op.k0 + op.coff);
+        return nc > 0 ? (nc + GT - 1) / GT : 0;
+    }
+    const int rb = op.k0 + op.roff, cb = op.k0 + op.coff;
+    const int re = op.rlim > 0 ? std::min(N, rb + op.rlim) : N;
+    const int ce = op.clim > 0 ? std::min(N, cb + op.clim) : N;
+    if (re <= rb || ce <= cb) return 0;
+    return ((re - rb + GT - 1) / GT) * ((ce - cb + GT - 1) / GT);
+}
+
+// Right-looking blocked LU with panels in pairs (p, p+1), k1 = k0 + 64:
+//   panel p; pivots of p on the columns right of it; U = inv(L11) A on
+//   those columns; update of panel p+1's 64 columns only (depth 64);
+//   panel p+1; its pivots on the columns right of it and on panel p's L
+//   columns (rows >= k1); update of the 64-row band k1.. of the trailing
+//   columns (depth 64); U of panel p+1; then ONE update of the trailing block
+//   below and right of the pair with depth 128 (both panels' L and U), which
+//   reads and writes that block once per pair instead of once per panel.
+// The solves replay panel p+1's pivots before panel p's update of the rows
+// below (panel p's L rows carry them).
 void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch) {
     int32_t maxN = 0;
     for (int q = 0; q < batch; ++q) maxN = std::max(maxN, N[q]);
     sch.nsteps = (maxN + NB - 1) / NB;
-    sch.R.clear();
-    sch.gemm_trsm_off.clear(); sch.gemm_upd_off.clear();
-    sch.gemm_trsm_tiles.clear(); sch.gemm_upd_tiles.clear(); sch.swap_blocks.clear(); sch.prefix.clear();
-    for (int p = 0; p < sch.nsteps; ++p) {
-        const int k0 = p * NB;
-        int rows = 0;
-        for (int q = 0; q < batch; ++q) rows = std::max(rows, N[q] - k0);
-        int R = (rows + PANEL_THREADS - 1) / PANEL_THREADS;
-        R = R <= 1 ? 1 : (R <= 2 ? 2 : (R <= 4 ? 4 : (R <= 8 ? 8 : 16)));
-        sch.R.push_back(R);
-        int maxrest = 0;
-        // TRSM prefix
-        sch.gemm_trsm_off.push_back((int64_t)sch.prefix.size());
+    sch.ops.clear();
+    sch.prefix.clear();
+    auto gemm = [&](int kind, int k0, int K, int roff, int rlim, int coff, int clim) {
+        fhw_lu_op op{};
+        op.kind = kind; op.k0 = k0; op.K = K; op.roff = roff; op.rlim = rlim; op.coff = coff; op.clim = clim;
+        op.prefix_off = (int64_t)sch.prefix.size();
         int acc = 0;
         for (int q = 0; q < batch; ++q) {
             sch.prefix.push_back(acc);
-            int rest = N[q] - k0 - NB;
-            if (rest > 0) { acc += (rest + GT - 1) / GT; maxrest = std::max(maxrest, rest); }
+            acc += gemm_tiles(kind, N[q], op);
         }
         sch.prefix.push_back(acc);
-        sch.gemm_trsm_tiles.push_back(acc);
-        // update prefix
-        sch.gemm_upd_off.push_back((int64_t)sch.prefix.size());
-        acc = 0;
+        op.grid = acc;
+        if (acc > 0) sch.ops.push_back(op);
+        else sch.prefix.resize((size_t)op.prefix_off);
+    };
+    auto swap = [&](int k0, int cbeg, int ccount) {
+        int maxc = 0;
         for (int q = 0; q < batch; ++q) {
-            sch.prefix.push_back(acc);
-            int rest = N[q] - k0 - NB;
-            if (rest > 0) { int t = (rest + GT - 1) / GT; acc += t * t; }
+            if (N[q] <= k0) continue;
+            const int ce = ccount > 0 ? std::min(N[q], cbeg + ccount) : N[q];
+            maxc = std::max(maxc, ce - cbeg);
         }
-        sch.prefix.push_back(acc);
-        sch.gemm_upd_tiles.push_back(acc);
-        sch.swap_blocks.push_back(maxrest > 0 ? (maxrest + 255) / 256 : 0);
+        if (maxc <= 0) return;
+        fhw_lu_op op{};
+        op.kind = FHW_LU_OP_SWAP; op.k0 = k0; op.cbeg = cbeg; op.ccount = ccount; op.grid = (maxc + 255) / 256;
+        sch.ops.push_back(op);
+    };
+    auto panel = [&](int k0) {
+        int rows = 0;
+        for (int q = 0; q < batch; ++q) rows = std::max(rows, N[q] - k0);
+        if (rows <= 0) return;
+        int R = (rows + PANEL_THREADS - 1) / PANEL_THREADS;
+        R = R <= 1 ? 1 : (R <= 2 ? 2 : (R <= 4 ? 4 : (R <= 8 ? 8 : 16)));
+        fhw_lu_op op{};
+        op.kind = FHW_LU_OP_PANEL; op.k0 = k0; op.R = R;
+        sch.ops.push_back(op);
+        op.kind = FHW_LU_OP_DIAGINV;
+        sch.ops.push_back(op);
+    };
+    for (int p = 0; p < sch.nsteps; p += 2) {
+        const int k0 = p * NB, k1 = k0 + NB;
+        panel(k0);
+        swap(k0, k1, 0);
+        gemm(FHW_LU_OP_TRSM, k0, 0, 0, 0, NB, 0);
+        if (p + 1 >= sch.nsteps) {
+            gemm(FHW_LU_OP_SUB, k0, NB, NB, 0, NB, 0);
+            continue;
+        }
+        gemm(FHW_LU_OP_SUB, k0, NB, NB, 0, NB, NB);           // panel p+1's columns
+        panel(k1);
+        swap(k1, k1 + NB, 0);                                  // pivots of p+1, right columns
+        swap(k1, k0, NB);                                      // ... and panel p's L columns
+        gemm(FHW_LU_OP_SUB, k0, NB, NB, NB, 2 * NB, 0);       // band rows k1 .. k1+63
+        gemm(FHW_LU_OP_TRSM, k1, 0, 0, 0, NB, 0);
+        gemm(FHW_LU_OP_SUB, k0, 2 * NB, 2 * NB, 0, 2 * NB, 0);   // depth-128 trailing update
     }
 }
 
@@ -756,37 +824,42 @@ static hipError_t lu_factor_t(hipStream_t s, const fhw_batch_dev& bd, const fhw_
                               const int32_t* d_prefix, cpx<T>* A, int32_t* piv, cpx<T>* linv, int32_t* st,
                               fhw_prof* prof) {
     lu_set_lds_limits<T>();
-    for (int p = 0; p < sch.nsteps; ++p) {
-        const int k0 = p * NB;
-        prof_begin(prof, FHW_STAGE_LU_PANEL, s);
-        hipError_t e = launch_panel<T>(s, sch.R[p], bd, k0, A, piv, st);
-        prof_end(prof, s);
-        if (e != hipSuccess) return e;
-        prof_begin(prof, FHW_STAGE_LU_DIAGINV, s);
-        hipLaunchKernelGGL((k_lu_diaginv<T>), dim3(bd.batch), dim3(INV_THREADS), sizeof(inv_lds<T>), s, k0, bd.N,
-                           bd.a_off, bd.linv_off, A, linv);
-        prof_end(prof, s);
-        if (sch.swap_blocks[p] > 0) {
-            prof_begin(prof, FHW_STAGE_LU_SWAP, s);
-            hipLaunchKernelGGL((k_lu_swap<T>), dim3(bd.batch, sch.swap_blocks[p]), dim3(256), 0, s, k0, bd.N,
-                               bd.a_off, bd.piv_off, A, piv);
-            prof_end(prof, s);
+    for (const fhw_lu_op& op : sch.ops) {
+        hipError_t e = hipSuccess;
+        switch (op.kind) {
+            case FHW_LU_OP_PANEL:
+                prof_begin(prof, FHW_STAGE_LU_PANEL, s);
+                e = launch_panel<T>(s, op.R, bd, op.k0, A, piv, st);
+                prof_end(prof, s);
+                break;
+            case FHW_LU_OP_DIAGINV:
+                prof_begin(prof, FHW_STAGE_LU_DIAGINV, s);
+                hipLaunchKernelGGL((k_lu_diaginv<T>), dim3(bd.batch), dim3(INV_THREADS), sizeof(inv_lds<T>), s, op.k0,
+                                   bd.N, bd.a_off, bd.linv_off, A, linv);
+                prof_end(prof, s);
+                break;
+            case FHW_LU_OP_SWAP:
+                prof_begin(prof, FHW_STAGE_LU_SWAP, s);
+                hipLaunchKernelGGL((k_lu_swap<T>), dim3(bd.batch, op.grid), dim3(256), 0, s, op.k0, op.cbeg, op.ccount,
+                                   bd.N, bd.a_off, bd.piv_off, A, piv);
+                prof_end(prof, s);
+                break;
+            case FHW_LU_OP_TRSM:
+                prof_begin(prof, FHW_STAGE_LU_TRSM, s);
+                hipLaunchKernelGGL((k_lu_gemm<T, false>), dim3(op.grid), dim3(256), 0, s, op.k0, 0, 0, 0, op.coff, 0,
+                                   d_prefix + op.prefix_off, bd.batch, bd.N, bd.a_off, bd.linv_off, A,
+                                   (const cpx<T>*)linv);
+                prof_end(prof, s);
+                break;
+            default:
+                prof_begin(prof, FHW_STAGE_LU_UPDATE, s);
+                hipLaunchKernelGGL((k_lu_gemm<T, true>), dim3(op.grid), dim3(256), 0, s, op.k0, op.K, op.roff, op.rlim,
+                                   op.coff, op.clim, d_prefix + op.prefix_off, bd.batch, bd.N, bd.a_off, bd.linv_off,
+                                   A, (const cpx<T>*)linv);
+                prof_end(prof, s);
+                break;
         }
-        if (sch.gemm_trsm_tiles[p] > 0) {
-            prof_begin(prof, FHW_STAGE_LU_TRSM, s);
-            hipLaunchKernelGGL((k_lu_gemm<T, false>), dim3(sch.gemm_trsm_tiles[p]), dim3(256), 0, s, k0,
-                               d_prefix + sch.gemm_trsm_off[p], bd.batch, bd.N, bd.a_off, bd.linv_off, A,
-                               (const cpx<T>*)linv);
-            prof_end(prof, s);
-        }
-        if (sch.gemm_upd_tiles[p] > 0) {
-            prof_begin(prof, FHW_STAGE_LU_UPDATE, s);
-            hipLaunchKernelGGL((k_lu_gemm<T, true>), dim3(sch.gemm_upd_tiles[p]), dim3(256), 0, s, k0,
-                               d_prefix + sch.gemm_upd_off[p], bd.batch, bd.N, bd.a_off, bd.linv_off, A,
-                               (const cpx<T>*)linv);
-            prof_end(prof, s);
-        }
-        e = hipGetLastError();
+        if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -7,12 +7,25 @@
 #define NB FHW_LU_NB
 #define SOLVE_THREADS 256
 
+// row swaps of one panel (LAPACK order: row k0+jj with row piv[k0+jj])
+__device__ __forceinline__ void replay_pivots(zd* xs, const int* piv, int k0, int nb) {
+    for (int jj = 0; jj < nb; ++jj) {
+        const int r2 = piv[k0 + jj];
+        if (r2 != k0 + jj) {
+            const zd t = xs[k0 + jj];
+            xs[k0 + jj] = xs[r2];
+            xs[r2] = t;
+        }
+    }
+}
+
 // One workgroup per matrix; x (complex128, length N) lives in LDS.  Factors
 // are column-major (entry (r, c) at c*N + r); linv blocks hold the inverses
 // of the diagonal blocks (column-major 64x64).
 // Forward: per panel, replay the panel's swaps, multiply by the inverse of
 // the unit-lower diagonal block, subtract L21 * y from the rows below (one
-// thread per row, coalesced down the columns).
+// thread per row, coalesced down the columns); pivot order as the paired
+// factorization left it (below).
 // Backward: per panel from the last, subtract U12 * x from the block's rows
 // (one lane per row, waves over columns), multiply by the inverse of U11.
 template <typename T>
@@ -40,20 +53,13 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
     for (int i = tid; i < N; i += SOLVE_THREADS) xs[i] = vb[i];
     const int np = (N + NB - 1) / NB;
     __syncthreads();
-    // ---- forward
+    // ---- forward.  Panels were factored in pairs (2q, 2q+1) and panel 2q's
+    // L rows below the pair's first panel carry the pivots of panel 2q+1, so
+    // those pivots are replayed before panel 2q's update of the rows below.
     for (int p = 0; p < np; ++p) {
         const int k0 = p * NB;
         const int nb = min(NB, N - k0);
-        if (tid == 0) {
-            for (int jj = 0; jj < nb; ++jj) {
-                const int r2 = piv[k0 + jj];
-                if (r2 != k0 + jj) {
-                    zd t = xs[k0 + jj];
-                    xs[k0 + jj] = xs[r2];
-                    xs[r2] = t;
-                }
-            }
-        }
+        if (tid == 0 && (p & 1) == 0) replay_pivots(xs, piv, k0, nb);
         __syncthreads();
         const cpx<T>* D = Lb + (int64_t)p * NB * NB;
         zd y = cmk(0.0, 0.0);
@@ -67,6 +73,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         __syncthreads();
         if (tid < nb) xs[k0 + tid] = y;
         __syncthreads();
+        if ((p & 1) == 0 && p + 1 < np) {
+            if (tid == 0) replay_pivots(xs, piv, k0 + NB, min(NB, N - k0 - NB));
+            __syncthreads();
+        }
         for (int i = k0 + nb + tid; i < N; i += SOLVE_THREADS) {
             const cpx<T>* Li = LU + (int64_t)k0 * N + i;
             zd s = cmk(0.0, 0.0);
