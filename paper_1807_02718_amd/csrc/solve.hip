@@ -79,11 +79,25 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         }
         for (int i = k0 + nb + tid; i < N; i += SOLVE_THREADS) {
             const cpx<T>* Li = LU + (int64_t)k0 * N + i;
-            zd s = cmk(0.0, 0.0);
-            for (int c = 0; c < nb; ++c) {
-                const cpx<T> l = Li[(int64_t)c * N];
-                s = cfma(s, cmk((double)l.re, (double)l.im), xs[k0 + c]);
+            // eight independent partial sums: eight loads in flight per thread
+            zd s8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s8[u] = cmk(0.0, 0.0);
+            int c = 0;
+            for (; c + 8 <= nb; c += 8) {
+                cpx<T> l8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) l8[u] = Li[(int64_t)(c + u) * N];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s8[u] = cfma(s8[u], cmk((double)l8[u].re, (double)l8[u].im), xs[k0 + c + u]);
             }
+            for (; c < nb; ++c) {
+                const cpx<T> l = Li[(int64_t)c * N];
+                s8[0] = cfma(s8[0], cmk((double)l.re, (double)l.im), xs[k0 + c]);
+            }
+            zd s = s8[0];
+#pragma unroll
+            for (int u = 1; u < 8; ++u) s = cadd(s, s8[u]);
             xs[i] = csub(xs[i], s);
         }
         __syncthreads();
@@ -96,10 +110,24 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         zd s = cmk(0.0, 0.0);
         if (lane < nb) {
             const cpx<T>* Ur = LU + k0 + lane;
-            for (int c = c0 + wid; c < N; c += SOLVE_THREADS / 64) {
-                const cpx<T> u = Ur[(int64_t)c * N];
-                s = cfma(s, cmk((double)u.re, (double)u.im), xs[c]);
+            constexpr int NW = SOLVE_THREADS / 64;
+            // four independent partial sums per lane: four loads in flight
+            zd s4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] = cmk(0.0, 0.0);
+            int c = c0 + wid;
+            for (; c + 3 * NW < N; c += 4 * NW) {
+                cpx<T> u4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) u4[u] = Ur[(int64_t)(c + u * NW) * N];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s4[u] = cfma(s4[u], cmk((double)u4[u].re, (double)u4[u].im), xs[c + u * NW]);
             }
+            for (; c < N; c += NW) {
+                const cpx<T> u = Ur[(int64_t)c * N];
+                s4[0] = cfma(s4[0], cmk((double)u.re, (double)u.im), xs[c]);
+            }
+            s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
         }
         part[wid][lane] = s;
         __syncthreads();

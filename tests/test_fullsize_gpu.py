@@ -1,13 +1,16 @@
-"""Parity at the full size of the solve-throughput workload: kite, N = 1024 at
-each of 1024 frequencies on (0, 69], one plane-wave direction, 256 points on
-the radius-3 ring, 1024 times reaching T = 1e4, planned exactly as the
-benchmark plans it (FP32 LU + FP64 refinement to 1e-12, and FP64).
+"""Parity at full size, in FP32 LU + FP64 refinement to 1e-12 and in FP64:
+  * kite_N1024_F1024: the solve-throughput workload, planned exactly as the
+    benchmark plans it: kite, N = 1024 at each of 1024 frequencies on (0, 69];
+  * kite_chirp_F512_W200: kite, 512 frequencies on (0, 200] with N from 10
+    points per wavelength (64 .. 2976), the paper's chirp;
+both with one plane-wave direction, 256 points on the radius-3 ring and 1024
+times reaching T = 1e4.
 
 The oracle cannot redo all 1024 solves inside a test, so:
   * densities and fields are compared at sampled frequencies, each solved by
     the oracle on its own;
   * time samples are compared with oracle values written by
-    tests/golden/make_kite_n1024_golden.py (4 of the 256 points, all times);
+    tests/golden/make_golden.py (4 of the 256 points, all times);
   * the synthesis alone runs on a pure-delay spectrum V = exp(i w d_r), whose
     time-domain field is the delayed boundary signal -f(t - d_r) in closed form;
   * points inside the kite see the incident signal exactly (extinction).
@@ -29,8 +32,9 @@ import workloads as Wk
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SAMPLED = [0, 255, 511, 767, 1023]
 REFINE_TOL = 1e-12
+WORKLOADS = {"kite_n1024": (Wk.kite_n1024, [0, 255, 511, 767, 1023]),
+             "kite_chirp": (Wk.kite_chirp, [0, 170, 341, 511])}
 
 
 def say(*a):
@@ -48,20 +52,34 @@ def fhw():
     return m
 
 
-@pytest.fixture(scope="module")
-def wl():
-    return Wk.kite_n1024()
+def _plan_kw(wl):
+    return dict(N=wl.N) if not isinstance(wl.N, dict) else dict(wl.N)
+
+
+def _sizes(wl):
+    omega, kappa = O.frequency_grid(wl.W, wl.F)
+    if isinstance(wl.N, dict):
+        return kappa, O.discretization_sizes(kappa, O.curve_length(wl.curve), **wl.N)
+    return kappa, np.full(wl.F, wl.N)
+
+
+@pytest.fixture(scope="module", params=list(WORKLOADS))
+def wl(request):
+    make, sampled = WORKLOADS[request.param]
+    w = make()
+    w.extra["sampled"] = sampled
+    return w
 
 
 @pytest.fixture(scope="module")
 def oracle_sampled(wl):
-    """Oracle densities, fields, residual-free references and condition numbers
-    at the sampled frequencies."""
-    omega, kappa = O.frequency_grid(wl.W, wl.F)
+    """Oracle densities, fields and condition numbers at the sampled
+    frequencies."""
+    kappa, Ns = _sizes(wl)
     eta = O.coupling(kappa)
-    gm = O.geometry(wl.curve, wl.N)
     out = {}
-    for j in SAMPLED:
+    for j in wl.extra["sampled"]:
+        gm = O.geometry(wl.curve, int(Ns[j]))
         A = O.assemble(gm, kappa[j], eta[j])
         g = O.rhs_plane_wave(gm, kappa[j], eta[j], wl.direction)
         psi, _ = O.solve_density(A, g)
@@ -73,16 +91,16 @@ def oracle_sampled(wl):
 @pytest.fixture(scope="module", params=["fp32_refine", "fp64"])
 def gpu_run(request, fhw, wl):
     precision = request.param
-    say("full-size kite N=1024 F=1024", precision)
+    say("full-size", wl.name, precision)
     ctx = fhw.Context()
-    Ns, off = ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=REFINE_TOL,
-                       refine_max=10, direction=wl.direction)
+    Ns, off = ctx.plan(wl.curve, wl.W, wl.F, precision=precision, refine_tol=REFINE_TOL,
+                       refine_max=10, direction=wl.direction, **_plan_kw(wl))
     psi, resid, sweeps = ctx.solve_densities(compute_resid=True)
     V = ctx.eval_field(psi, wl.obs, zero_value=1.0)
     f = torch.as_tensor(wl.signal.f, device=psi.device)
     u = ctx.synthesize(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times)
     res = dict(precision=precision, Ns=np.asarray(Ns), off=np.asarray(off), resid=resid, sweeps=sweeps,
-               psi={j: psi[int(off[j]):int(off[j + 1])].cpu().numpy() for j in SAMPLED},
+               psi={j: psi[int(off[j]):int(off[j + 1])].cpu().numpy() for j in wl.extra["sampled"]},
                V=V.cpu().numpy(), u=u.cpu().numpy(), ctx=ctx)
     yield res
     ctx.close()
@@ -90,17 +108,17 @@ def gpu_run(request, fhw, wl):
 
 def test_fullsize_densities_sampled(gpu_run, oracle_sampled, wl):
     prec = gpu_run["precision"]
-    assert np.all(gpu_run["Ns"] == 1024)
+    assert np.array_equal(gpu_run["Ns"], _sizes(wl)[1])
     if prec == "fp32_refine":
         assert np.max(gpu_run["resid"]) <= REFINE_TOL
-    for j in SAMPLED:
+    for j in wl.extra["sampled"]:
         o = oracle_sampled[j]
         p = gpu_run["psi"][j]
         err = relmax(p, o["psi"])
         err2 = float(np.linalg.norm(p - o["psi"]) / np.linalg.norm(o["psi"]))
         # residual of the GPU density against the oracle's matrix and data
         r_o = float(np.linalg.norm(o["g"] - o["A"] @ p) / np.linalg.norm(o["g"]))
-        say(prec, "freq", j, "cond", round(o["cond"], 2), "err_inf", err, "err_2", err2, "resid(oracle A)", r_o,
+        say(wl.name, prec, "freq", j, "N", len(p), "cond", round(o["cond"], 2), "err_inf", err, "err_2", err2, "resid(oracle A)", r_o,
             "sweeps", int(gpu_run["sweeps"][j]))
         if prec == "fp64":
             assert err < 1e-11
@@ -115,7 +133,8 @@ def test_fullsize_field_sampled(gpu_run, oracle_sampled, wl):
     F = wl.F
     V = gpu_run["V"]
     assert V.shape == (len(wl.obs), 2 * F)
-    for j in SAMPLED:
+    kappa, Ns = _sizes(wl)
+    for j in wl.extra["sampled"]:
         o = oracle_sampled[j]
         # omega_{j+1} sits at grid index F + 1 + j; the top frequency W is
         # held only through its conjugate at -W (index 0) on [-W, W)
@@ -125,37 +144,40 @@ def test_fullsize_field_sampled(gpu_run, oracle_sampled, wl):
         else:
             Vg = np.conj(V[:, 0])
         err = relmax(Vg, o["V"])
-        say(prec, "field freq", j, "err", err)
+        say(wl.name, prec, "field freq", j, "err", err)
         if prec == "fp64":
             assert err < 1e-11
         else:
             # the field is a fixed linear functional of the density:
             # |dV_r| <= ||w_r||_2 ||d psi||_2 with w_r = (pi/n) (i/4) H0 |x'|
-            gm = O.geometry(wl.curve, wl.N)
-            _, kappa = O.frequency_grid(wl.W, F)
+            n_j = int(Ns[j])
+            gm = O.geometry(wl.curve, n_j)
             d = np.hypot(wl.obs[:, None, 0] - gm["x"][None, :, 0], wl.obs[:, None, 1] - gm["x"][None, :, 1])
-            w = (np.pi / (wl.N // 2)) * 0.25 * np.abs(special.hankel1(0, kappa[j] * d)) * gm["speed"][None, :]
+            w = (np.pi / (n_j // 2)) * 0.25 * np.abs(special.hankel1(0, kappa[j] * d)) * gm["speed"][None, :]
             bound = np.linalg.norm(w, axis=1) * np.linalg.norm(gpu_run["psi"][j] - o["psi"])
             assert np.all(np.abs(Vg - o["V"]) <= 1.1 * bound + 1e-13 * np.max(np.abs(o["V"])))
     assert np.all(V[:, F] == 1.0)
 
 
 def test_fullsize_time_samples_vs_oracle(gpu_run, wl):
-    meta = json.load(open(os.path.join(HERE, "golden", "kite_n1024_u_sample.json")))
-    ref = np.load(os.path.join(HERE, "golden", "kite_n1024_u_sample.npy"))
+    meta = json.load(open(os.path.join(HERE, "golden", f"{wl.name}_u_sample.json")))
+    ref = np.load(os.path.join(HERE, "golden", f"{wl.name}_u_sample.npy"))
     assert meta["workload"] == wl.name and ref.shape == (len(meta["obs_index"]), len(wl.times))
     u = gpu_run["u"][meta["obs_index"]]
     err = relmax(u, ref)
-    say(gpu_run["precision"], "time samples vs oracle (4 points x 1024 times)", err, "max|u|", float(np.max(np.abs(ref))))
+    per_t = np.max(np.abs(u - ref), axis=0) / np.max(np.abs(ref))
+    say(wl.name, gpu_run["precision"], "time samples vs oracle (4 points x 1024 times)", err, "max|u|",
+        float(np.max(np.abs(ref))), "per-time error quartiles", np.percentile(per_t, [50, 90, 100]).tolist())
     assert err < 1e-10
     assert np.all(np.isfinite(gpu_run["u"]))
 
 
-def test_fullsize_synthesis_delay(fhw, wl):
+def test_fullsize_synthesis_delay(fhw):
     """Synthesis of a pure delay V(r, w) = exp(i w d_r) on the full DFT grid:
     the field is a(t - d_r) = -f(t - d_r), and the oracle's synthesis from the
     same spectrum agrees on a sample of points."""
     say("full-size synthesis, delay spectrum")
+    wl = Wk.kite_n1024()
     ctx = fhw.Context()
     try:
         ctx.plan(wl.curve, wl.W, wl.F, N=wl.N)
@@ -187,10 +209,11 @@ def test_fullsize_synthesis_delay(fhw, wl):
     assert err_exact < 1e-9
 
 
-def test_fullsize_interior_extinction(fhw, wl):
+def test_fullsize_interior_extinction(fhw):
     """Points inside the kite: the scattered field cancels the incident one, so
     u(x, t) = -f(t - p.x) (plane wave, direction p)."""
     say("full-size interior extinction")
+    wl = Wk.kite_n1024()
     pts = Wk.interior_points(wl.curve, 16, seed=5)
     ctx = fhw.Context()
     try:
