@@ -130,6 +130,36 @@ def copy_calibration(torch, nbytes, reps):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def star_batch_bench(fhw, torch, sb, steps, warmup):
+    """Throughput of one batched FP64 factor + solve of every frequency of
+    every star curve (the batching configuration)."""
+    ctx = fhw.Context()
+    t0 = time.perf_counter()
+    Ns, off = ctx.plan(sb["curves"], sb["W"], sb["F"], precision="fp64", direction=sb["direction"], **sb["rule"])
+    plan_s = time.perf_counter() - t0
+    psi = torch.empty(int(off[-1]), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        ctx.solve_densities(psi)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.solve_densities(psi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.close()
+    flops = lu_update_flops([int(n) for n in Ns]) * steps
+    upd_ms, upd_n = prof["lu_update"]
+    S = len(Ns)
+    print(json.dumps({"metric": "batched FP64 frequency solves/s, 64 star curves x 256 frequencies",
+                      "value": S * steps / dt, "unit": "solves/s", "steps": steps, "warmup": warmup,
+                      "ms_per_step": 1e3 * dt / steps, "systems": S, "N_min": int(min(Ns)), "N_max": int(max(Ns)),
+                      "N_mean": float(np.mean(Ns)), "plan_s": plan_s,
+                      "lu_update_tflops": flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else None,
+                      "stages_ms_per_step": {k: v[0] / steps for k, v in prof.items()}}), flush=True)
+
+
 def cpu_baseline(wl, n_freq):
     """The FP64 oracle on a bounded sample: n_freq frequencies spread over the
     band, each = assembly + LAPACK solve + field at all observation points."""
@@ -162,6 +192,8 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=50, help="isolated-solve latency samples (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
+    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars"],
+                    help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -174,6 +206,9 @@ def main():
         return
     import workloads as Wk
     from paper_1807_02718_amd import fhw
+    if a.workload == "stars":
+        star_batch_bench(fhw, torch, Wk.star_batch(), a.steps, a.warmup)
+        return
 
     wl = Wk.kite_n1024(F=a.freqs)
     modes = a.modes.split(",")

@@ -100,6 +100,16 @@ int fhw_version(void);
 int fhw_plan(fhw_ctx* ctx, const fhw_curve* curve, const fhw_problem* prob,
              int32_t* N_out, int64_t* psi_off_out);
 
+/* Plan several scatterers with one problem (same frequencies, N rule,
+ * precision): the frequency solves of all curves form one batch, so ragged
+ * sizes across curves share every factorization launch.  System s = k F + j
+ * is frequency j of curve k (curve-major); N_out [host] has n_curves F
+ * entries and psi_off_out n_curves F + 1.  Every call below then covers all
+ * systems (psi, resid and sweeps indexed by system); fields are per curve
+ * (fhw_eval_field_curve).  Errors as fhw_plan, for any of the curves. */
+int fhw_plan_curves(fhw_ctx* ctx, const fhw_curve* curves, int32_t n_curves, const fhw_problem* prob,
+                    int32_t* N_out, int64_t* psi_off_out);
+
 /* Step F3: densities psi_p(., omega_j) of eq. CFIE_direct with boundary data
  * exp(i kappa p.x), for all planned frequencies.
  * psi: complex128, psi_off[F] elements (ragged, offsets from fhw_plan).
@@ -155,6 +165,11 @@ int fhw_solve_cached(fhw_ctx* ctx, const fhw_incidence* inc, int32_t n_inc, void
  * obs: [host] doubles [N_r][2], points off the boundary. */
 int fhw_eval_field(fhw_ctx* ctx, const void* psi, const double* obs, int32_t N_r,
                    double zero_value, void* V);
+
+/* As fhw_eval_field for curve k of a plan made by fhw_plan_curves (psi is the
+ * whole density buffer of the plan); fhw_eval_field is curve 0. */
+int fhw_eval_field_curve(fhw_ctx* ctx, int32_t curve, const void* psi, const double* obs,
+                         int32_t N_r, double zero_value, void* V);
 
 /* Incident signal f sampled at t0 + n dt, n = 0..n-1 (device doubles); the
  * incident field is f(t - p.r/c) and the boundary signal is a = -f.  The

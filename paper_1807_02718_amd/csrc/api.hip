@@ -51,14 +51,14 @@ size_t freq_bytes(int32_t N, int precision) {
     return b;
 }
 
-void curve_eval_host(const fhw_ctx* c, double s, double& x1, double& x2, double& d1, double& d2) {
+void curve_eval_host(const fhw_host_curve& cv, double s, double& x1, double& x2, double& d1, double& d2) {
     x1 = x2 = d1 = d2 = 0.0;
-    for (int d = 0; d <= c->degree; ++d) {
+    for (int d = 0; d <= cv.degree; ++d) {
         double cs = cos(d * s), sn = sin(d * s);
-        x1 += c->cx[d] * cs + c->sx[d] * sn;
-        x2 += c->cy[d] * cs + c->sy[d] * sn;
-        d1 += d * (c->sx[d] * cs - c->cx[d] * sn);
-        d2 += d * (c->sy[d] * cs - c->cy[d] * sn);
+        x1 += cv.cx[d] * cs + cv.sx[d] * sn;
+        x2 += cv.cy[d] * cs + cv.sy[d] * sn;
+        d1 += d * (cv.sx[d] * cs - cv.cx[d] * sn);
+        d2 += d * (cv.sy[d] * cs - cv.cy[d] * sn);
     }
 }
 
@@ -71,11 +71,14 @@ void free_plan(fhw_ctx* c) {
         (void)hipFree(kv.second.logtab);
     }
     c->geoms.clear();
-    void* ptrs[] = {c->d_curve, c->A64, c->A32, c->linv, c->piv, c->x, c->r, c->meta, c->d_status,
+    for (auto& cv : c->curves)
+        if (cv.d_curve) (void)hipFree(cv.d_curve);
+    c->curves.clear();
+    void* ptrs[] = {c->A64, c->A32, c->linv, c->piv, c->x, c->r, c->meta, c->d_status,
                     c->d_norms, c->d_done, c->d_sweeps};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    c->d_curve = nullptr; c->A64 = c->A32 = c->linv = nullptr; c->piv = nullptr; c->x = c->r = nullptr;
+    c->A64 = c->A32 = c->linv = nullptr; c->piv = nullptr; c->x = c->r = nullptr;
     c->meta = nullptr; c->d_status = nullptr; c->d_norms = nullptr; c->d_done = nullptr; c->d_sweeps = nullptr;
     c->planned = false;
     c->factors_resident = false;
@@ -220,10 +223,16 @@ int fhw_destroy(fhw_ctx* c) {
 
 const char* fhw_last_error(const fhw_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* N_out, int64_t* psi_off_out) {
+// Plan n_curves scatterers with one problem: system s = curve * F + j.
+static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, const fhw_problem* p, int32_t* N_out,
+                     int64_t* psi_off_out) {
     if (!c) return FHW_E_INVALID;
-    if (!curve || !p || curve->degree < 1 || !curve->cx || !curve->sx || !curve->cy || !curve->sy)
-        return fhw_fail(c, FHW_E_INVALID, "plan: missing curve/problem");
+    if (!curves || n_curves < 1 || !p) return fhw_fail(c, FHW_E_INVALID, "plan: missing curve/problem");
+    for (int k = 0; k < n_curves; ++k) {
+        const fhw_curve* curve = curves + k;
+        if (curve->degree < 1 || !curve->cx || !curve->sx || !curve->cy || !curve->sy)
+            return fhw_fail(c, FHW_E_INVALID, "plan: missing curve coefficients");
+    }
     if (!(p->W > 0) || p->F < 1 || !(p->c > 0) || !isfinite(p->W) || !isfinite(p->c))
         return fhw_fail(c, FHW_E_INVALID, "plan: need W > 0, F >= 1, c > 0");
     if (p->precision != FHW_FP64 && p->precision != FHW_FP32_REFINE)
@@ -233,78 +242,92 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
     (void)hipStreamSynchronize(c->stream);
     free_plan(c);
     c->prob = *p;
-    c->degree = curve->degree;
-    const int D1 = curve->degree + 1;
-    c->cx.assign(curve->cx, curve->cx + D1);
-    c->sx.assign(curve->sx, curve->sx + D1);
-    c->cy.assign(curve->cy, curve->cy + D1);
-    c->sy.assign(curve->sy, curve->sy + D1);
-    for (int d = 0; d < D1; ++d)
-        if (!isfinite(c->cx[d]) || !isfinite(c->sx[d]) || !isfinite(c->cy[d]) || !isfinite(c->sy[d]))
-            return fhw_fail(c, FHW_E_INVALID, "plan: curve coefficients not finite");
-    // curve length (trapezoidal rule on the periodic speed), orientation check
-    const int nq = 4096;
-    double L = 0.0, area = 0.0, minsp = 1e300;
-    for (int q = 0; q < nq; ++q) {
-        double s = 2.0 * M_PI * q / nq, x1, x2, d1, d2;
-        curve_eval_host(c, s, x1, x2, d1, d2);
-        double sp = sqrt(d1 * d1 + d2 * d2);
-        L += sp;
-        area += x1 * d2 - x2 * d1;
-        minsp = std::min(minsp, sp);
-    }
-    L *= 2.0 * M_PI / nq;
-    area *= 0.5 * 2.0 * M_PI / nq;
-    if (!(minsp > 0.0) || !(area > 0.0))
-        return fhw_fail(c, FHW_E_INVALID, "plan: curve must be counter-clockwise, non-degenerate");
-    c->length = L;
-    // frequencies, sizes, coupling
-    const int F = p->F;
-    const double dw = p->W / (double)F;
-    c->kappa.resize(F);
-    c->eta.resize(F);
-    c->Ns.resize(F);
-    for (int j = 0; j < F; ++j) {
-        double om = dw * (double)(j + 1);
-        c->kappa[j] = om / p->c;
-        c->eta[j] = std::max(c->kappa[j], 1.0);
-        int N;
-        if (p->N_fixed > 0) {
-            N = p->N_fixed;
-        } else {
-            if (p->n_mult < 1 || p->n_min < 2 || p->n_cap < p->n_min || !(p->ppw > 0))
-                return fhw_fail(c, FHW_E_INVALID, "plan: bad N rule");
-            double raw = p->ppw * L * c->kappa[j] / (2.0 * M_PI);
-            double m = ceil(raw / (double)p->n_mult) * (double)p->n_mult;
-            N = (int)std::min<double>(std::max<double>(m, p->n_min), p->n_cap);
+    c->curves.resize(n_curves);
+    for (int k = 0; k < n_curves; ++k) {
+        const fhw_curve* curve = curves + k;
+        fhw_host_curve& cv = c->curves[k];
+        cv.degree = curve->degree;
+        const int D1 = curve->degree + 1;
+        cv.cx.assign(curve->cx, curve->cx + D1);
+        cv.sx.assign(curve->sx, curve->sx + D1);
+        cv.cy.assign(curve->cy, curve->cy + D1);
+        cv.sy.assign(curve->sy, curve->sy + D1);
+        for (int d = 0; d < D1; ++d)
+            if (!isfinite(cv.cx[d]) || !isfinite(cv.sx[d]) || !isfinite(cv.cy[d]) || !isfinite(cv.sy[d]))
+                return fhw_fail(c, FHW_E_INVALID, "plan: curve coefficients not finite");
+        // curve length (trapezoidal rule on the periodic speed), orientation check
+        const int nq = 4096;
+        double L = 0.0, area = 0.0, minsp = 1e300;
+        for (int q = 0; q < nq; ++q) {
+            double s = 2.0 * M_PI * q / nq, x1, x2, d1, d2;
+            curve_eval_host(cv, s, x1, x2, d1, d2);
+            double sp = sqrt(d1 * d1 + d2 * d2);
+            L += sp;
+            area += x1 * d2 - x2 * d1;
+            minsp = std::min(minsp, sp);
         }
-        if (N < 4 || (N & 1) || N > 4096)
-            return fhw_fail(c, FHW_E_INVALID, "plan: N must be even, 4 <= N <= 4096");
-        c->Ns[j] = N;
+        L *= 2.0 * M_PI / nq;
+        area *= 0.5 * 2.0 * M_PI / nq;
+        if (!(minsp > 0.0) || !(area > 0.0))
+            return fhw_fail(c, FHW_E_INVALID, "plan: curve must be counter-clockwise, non-degenerate");
+        cv.length = L;
     }
-    c->psi_off.assign(F + 1, 0);
-    for (int j = 0; j < F; ++j) c->psi_off[j + 1] = c->psi_off[j] + c->Ns[j];
+    // frequencies, sizes, coupling per system
+    const int F = p->F;
+    const int S = n_curves * F;
+    const double dw = p->W / (double)F;
+    c->kappa.resize(S);
+    c->eta.resize(S);
+    c->Ns.resize(S);
+    for (int k = 0; k < n_curves; ++k)
+        for (int j = 0; j < F; ++j) {
+            const int sy = k * F + j;
+            double om = dw * (double)(j + 1);
+            c->kappa[sy] = om / p->c;
+            c->eta[sy] = std::max(c->kappa[sy], 1.0);
+            int N;
+            if (p->N_fixed > 0) {
+                N = p->N_fixed;
+            } else {
+                if (p->n_mult < 1 || p->n_min < 2 || p->n_cap < p->n_min || !(p->ppw > 0))
+                    return fhw_fail(c, FHW_E_INVALID, "plan: bad N rule");
+                double raw = p->ppw * c->curves[k].length * c->kappa[sy] / (2.0 * M_PI);
+                double m = ceil(raw / (double)p->n_mult) * (double)p->n_mult;
+                N = (int)std::min<double>(std::max<double>(m, p->n_min), p->n_cap);
+            }
+            if (N < 4 || (N & 1) || N > 4096)
+                return fhw_fail(c, FHW_E_INVALID, "plan: N must be even, 4 <= N <= 4096");
+            c->Ns[sy] = N;
+        }
+    c->psi_off.assign(S + 1, 0);
+    for (int j = 0; j < S; ++j) c->psi_off[j + 1] = c->psi_off[j] + c->Ns[j];
     int maxN = *std::max_element(c->Ns.begin(), c->Ns.end());
     if ((size_t)maxN * 16 + 8192 > (size_t)lds_limit(c))
         return fhw_fail(c, FHW_E_INVALID, "plan: N too large for the LDS-resident solve vector");
 
-    // curve coefficients on device, geometry + Kress tables per distinct N
-    FHW_HIP(c, hipMalloc(&c->d_curve, sizeof(double) * 4 * D1));
-    std::vector<double> hc(4 * D1);
-    for (int d = 0; d < D1; ++d) {
-        hc[d] = c->cx[d]; hc[D1 + d] = c->sx[d]; hc[2 * D1 + d] = c->cy[d]; hc[3 * D1 + d] = c->sy[d];
-    }
-    FHW_HIP(c, hipMemcpy(c->d_curve, hc.data(), sizeof(double) * 4 * D1, hipMemcpyHostToDevice));
-    std::set<int32_t> distinct(c->Ns.begin(), c->Ns.end());
-    for (int32_t N : distinct) {
-        fhw_geom_entry e{};
-        e.N = N;
-        FHW_HIP(c, hipMalloc(&e.geom, sizeof(double) * 9 * N));
-        FHW_HIP(c, hipMalloc(&e.R, sizeof(double) * N));
-        FHW_HIP(c, hipMalloc(&e.logtab, sizeof(double) * N));
-        STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, c->d_curve, c->degree, N, e.geom));
-        STAGE(c, FHW_STAGE_KRESS, launch_kress(c->stream, N, e.R, e.logtab));
-        c->geoms[N] = e;
+    // curve coefficients on device, geometry + Kress tables per (curve, distinct N)
+    size_t geo = 0;
+    for (int k = 0; k < n_curves; ++k) {
+        fhw_host_curve& cv = c->curves[k];
+        const int D1 = cv.degree + 1;
+        FHW_HIP(c, hipMalloc(&cv.d_curve, sizeof(double) * 4 * D1));
+        std::vector<double> hc(4 * D1);
+        for (int d = 0; d < D1; ++d) {
+            hc[d] = cv.cx[d]; hc[D1 + d] = cv.sx[d]; hc[2 * D1 + d] = cv.cy[d]; hc[3 * D1 + d] = cv.sy[d];
+        }
+        FHW_HIP(c, hipMemcpy(cv.d_curve, hc.data(), sizeof(double) * 4 * D1, hipMemcpyHostToDevice));
+        std::set<int32_t> distinct(c->Ns.begin() + k * F, c->Ns.begin() + (k + 1) * F);
+        for (int32_t N : distinct) {
+            fhw_geom_entry e{};
+            e.N = N;
+            FHW_HIP(c, hipMalloc(&e.geom, sizeof(double) * 9 * N));
+            FHW_HIP(c, hipMalloc(&e.R, sizeof(double) * N));
+            FHW_HIP(c, hipMalloc(&e.logtab, sizeof(double) * N));
+            STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, cv.d_curve, cv.degree, N, e.geom));
+            STAGE(c, FHW_STAGE_KRESS, launch_kress(c->stream, N, e.R, e.logtab));
+            c->geoms[fhw_geom_key(k, N)] = e;
+            geo += (size_t)N * 11 * 8;
+        }
     }
 
     // chunks over frequencies within the HBM budget
@@ -312,15 +335,13 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
     plan_ext& px = g_plans[c];
     px.chunks.clear();
     {
-        size_t geo = 0;
-        for (int32_t N : distinct) geo += (size_t)N * 11 * 8;
         size_t avail = c->budget > geo ? c->budget - geo : 0;
         int j = 0;
-        while (j < F) {
+        while (j < S) {
             chunk_t ch;
             ch.j0 = j;
             size_t used = 0;
-            while (j < F) {
+            while (j < S) {
                 size_t fb = freq_bytes(c->Ns[j], prec);
                 if (ch.count > 0 && used + fb > avail) break;
                 if (ch.count == 0 && fb > avail)
@@ -363,9 +384,9 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
     FHW_HIP(c, hipMalloc(&c->x, wsV * 16));   // g
     FHW_HIP(c, hipMalloc(&c->r, wsV * 16));   // residual / correction
     FHW_HIP(c, hipMalloc((void**)&c->d_status, sizeof(int32_t) * 4));
-    FHW_HIP(c, hipMalloc((void**)&c->d_norms, sizeof(double) * 2 * F));
-    FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * F));
-    FHW_HIP(c, hipMalloc((void**)&c->d_sweeps, sizeof(int32_t) * F));
+    FHW_HIP(c, hipMalloc((void**)&c->d_norms, sizeof(double) * 2 * S));
+    FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * S));
+    FHW_HIP(c, hipMalloc((void**)&c->d_sweeps, sizeof(int32_t) * S));
     c->ws_A64 = wsA64; c->ws_A32 = wsA32; c->ws_linv = wsL; c->ws_piv = wsP;
 
     // per-chunk metadata, built once and uploaded into one buffer
@@ -388,7 +409,7 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
             int N = c->Ns[j];
             Nv[q] = N;
             ao[q] = a; po[q] = pv; lo[q] = l; vo[q] = v;
-            const fhw_geom_entry& ge = c->geoms[N];
+            const fhw_geom_entry& ge = c->geoms[fhw_geom_key(j / F, N)];
             items[q].geom = ge.geom;
             items[q].R = ge.R;
             items[q].logtab = ge.logtab;
@@ -416,9 +437,9 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
         f.oLP = put(ch.sched.prefix.data(), std::max<size_t>(1, ch.sched.prefix.size()) * 4);
         fixes.push_back(f);
     }
-    std::vector<fhw_field_item> fitems(F);
-    for (int j = 0; j < F; ++j) {
-        fitems[j].geom = c->geoms[c->Ns[j]].geom;
+    std::vector<fhw_field_item> fitems(S);
+    for (int j = 0; j < S; ++j) {
+        fitems[j].geom = c->geoms[fhw_geom_key(j / F, c->Ns[j])].geom;
         fitems[j].psi_off = c->psi_off[j];
         fitems[j].N = c->Ns[j];
         fitems[j].kappa = c->kappa[j];
@@ -442,19 +463,28 @@ int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* 
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     c->planned = true;
     if (N_out)
-        for (int j = 0; j < F; ++j) N_out[j] = c->Ns[j];
+        for (int j = 0; j < S; ++j) N_out[j] = c->Ns[j];
     if (psi_off_out)
-        for (int j = 0; j <= F; ++j) psi_off_out[j] = c->psi_off[j];
+        for (int j = 0; j <= S; ++j) psi_off_out[j] = c->psi_off[j];
     return FHW_OK;
 }
 
+int fhw_plan(fhw_ctx* c, const fhw_curve* curve, const fhw_problem* p, int32_t* N_out, int64_t* psi_off_out) {
+    return plan_impl(c, curve, 1, p, N_out, psi_off_out);
+}
+
+int fhw_plan_curves(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, const fhw_problem* p, int32_t* N_out,
+                    int64_t* psi_off_out) {
+    return plan_impl(c, curves, n_curves, p, N_out, psi_off_out);
+}
+
 // winding number of the planned curve about (a, b): 0 outside
-static int winding_number(const fhw_ctx* c, double a, double b, double* min_dist) {
+static int winding_number(const fhw_host_curve& cv, double a, double b, double* min_dist) {
     const int M = 4096;
     double tot = 0.0, prev = 0.0, dmin = INFINITY;
     for (int k = 0; k <= M; ++k) {
         double x1, x2, d1, d2;
-        curve_eval_host(c, 2.0 * M_PI * (double)k / M, x1, x2, d1, d2);
+        curve_eval_host(cv, 2.0 * M_PI * (double)k / M, x1, x2, d1, d2);
         const double ang = atan2(x2 - b, x1 - a);
         dmin = std::min(dmin, hypot(x1 - a, x2 - b));
         if (k > 0) {
@@ -476,7 +506,7 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
                       int32_t* sweeps, int32_t compute_resid, bool reuse) {
     plan_ext& px = g_plans[c];
     const fhw_problem& p = c->prob;
-    const int F = p.F;
+    const int F = (int)c->Ns.size();   // systems (curves x frequencies)
     const bool fp32 = p.precision == FHW_FP32_REFINE;
     const int64_t total = c->psi_off[F];
     // per-(incidence, frequency) status: the plan's arrays for one incidence,
@@ -590,9 +620,11 @@ static int check_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc,
         if (inc[q].kind == FHW_INC_PLANE) {
             if (fabs(hypot(a, b) - 1.0) > 1e-12) return fhw_fail(c, FHW_E_INVALID, "solve: direction not a unit vector");
         } else if (inc[q].kind == FHW_INC_POINT) {
-            double dmin;
-            if (winding_number(c, a, b, &dmin) != 0 || !(dmin > 0.0))
-                return fhw_fail(c, FHW_E_INVALID, "solve: point source on or inside the curve");
+            for (const fhw_host_curve& cv : c->curves) {
+                double dmin;
+                if (winding_number(cv, a, b, &dmin) != 0 || !(dmin > 0.0))
+                    return fhw_fail(c, FHW_E_INVALID, "solve: point source on or inside a curve");
+            }
         } else {
             return fhw_fail(c, FHW_E_INVALID, "solve: unknown incidence kind");
         }
@@ -621,9 +653,11 @@ int fhw_solve_cached(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* 
     return solve_impl(c, inc, n_inc, psi, resid, sweeps, 0, true);
 }
 
-int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, double zero_value, void* V) {
+int fhw_eval_field_curve(fhw_ctx* c, int32_t curve, const void* psi, const double* obs, int32_t N_r,
+                         double zero_value, void* V) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field: no plan");
+    if (curve < 0 || curve >= (int)c->curves.size()) return fhw_fail(c, FHW_E_INVALID, "field: no such curve");
     if (N_r < 0 || (N_r > 0 && (!psi || !obs || !V))) return fhw_fail(c, FHW_E_INVALID, "field: bad arguments");
     if (N_r == 0) return FHW_OK;
     for (int q = 0; q < 2 * N_r; ++q)
@@ -631,10 +665,14 @@ int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, 
     int rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
     if (rc) return rc;
     FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
-    STAGE(c, FHW_STAGE_FIELD, launch_field(c->stream, g_plans[c].d_field_items, c->prob.F, psi, (const double*)c->scratch, N_r,
-                            zero_value, V));
+    STAGE(c, FHW_STAGE_FIELD, launch_field(c->stream, g_plans[c].d_field_items + (int64_t)curve * c->prob.F,
+                                           c->prob.F, psi, (const double*)c->scratch, N_r, zero_value, V));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
+}
+
+int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, double zero_value, void* V) {
+    return fhw_eval_field_curve(c, 0, psi, obs, N_r, zero_value, V);
 }
 
 int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V, int32_t N_r,
@@ -688,7 +726,7 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     size_t o_k = align_up(o_s + std::max<size_t>(1, slot.size()) * 4, 256);
     size_t o_B = align_up(o_k + std::max<size_t>(1, klist.size()) * 8, 256);
     size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
-    size_t total = align_up(o_c + (size_t)count * N_r * M * 16, 256);
+    size_t total = align_up(o_c + (size_t)count * N_r * M * 8, 256);   // real parts of c
     int rc = fhw_ensure_scratch(c, total);
     if (rc) return rc;
     char* sb = (char*)c->scratch;
@@ -699,7 +737,8 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
         FHW_HIP(c, hipMemcpyAsync(sb + o_k, klist.data(), klist.size() * 8, hipMemcpyHostToDevice, c->stream));
     STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, H, 0, (const int64_t*)(sb + o_k),
                                      count, W, F, sb + o_B));
-    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, sb + o_c));
+    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
+                                                     (double*)(sb + o_c)));
     if (count == 0) {
         FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
     } else {
@@ -716,7 +755,7 @@ int fhw_geometry(fhw_ctx* c, int32_t N, double* geom) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "geometry: no plan");
     if (N < 4 || (N & 1) || !geom) return fhw_fail(c, FHW_E_INVALID, "geometry: bad arguments");
-    STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, c->d_curve, c->degree, N, geom));
+    STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, c->curves[0].d_curve, c->curves[0].degree, N, geom));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }
@@ -733,7 +772,7 @@ int fhw_assemble(fhw_ctx* c, int32_t j0, int32_t count, void* A, const int64_t* 
                  const int64_t* g_off) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "assemble: no plan");
-    if (j0 < 0 || count < 0 || j0 + count > c->prob.F || (count > 0 && (!A || !A_off || !g || !g_off)))
+    if (j0 < 0 || count < 0 || j0 + count > (int)c->Ns.size() || (count > 0 && (!A || !A_off || !g || !g_off)))
         return fhw_fail(c, FHW_E_INVALID, "assemble: bad arguments");
     if (count == 0) return FHW_OK;
     std::vector<fhw_assemble_item> items(count);
@@ -741,7 +780,7 @@ int fhw_assemble(fhw_ctx* c, int32_t j0, int32_t count, void* A, const int64_t* 
     int64_t blk = 0;
     for (int q = 0; q < count; ++q) {
         int j = j0 + q;
-        const fhw_geom_entry& ge = c->geoms[c->Ns[j]];
+        const fhw_geom_entry& ge = c->geoms[fhw_geom_key(j / c->prob.F, c->Ns[j])];
         items[q] = fhw_assemble_item{ge.geom, ge.R, ge.logtab, A_off[q], g_off[q], c->Ns[j], c->kappa[j], c->eta[j]};
         pre[q] = blk;
         blk += assemble_blocks_for(c->Ns[j]);
@@ -863,7 +902,8 @@ int fhw_fourier_coefficients(fhw_ctx* c, const void* B, int32_t count, const voi
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: 2F must be a power of two");
     if (count < 0 || N_r < 0 || ((count > 0 && N_r > 0) && (!B || !V || !cc)) || !isfinite(tau0))
         return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: bad arguments");
-    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, B, count, V, N_r, c->prob.W, c->prob.F, tau0, cc));
+    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, B, count, V, N_r, c->prob.W, c->prob.F, tau0, cc,
+                                                     nullptr));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }

@@ -53,6 +53,14 @@ inline void prof_end(fhw_prof* p, hipStream_t s) {
     if (p && p->on) p->end(s);
 }
 
+struct fhw_host_curve {
+    int32_t degree = 0;
+    std::vector<double> cx, sx, cy, sy;
+    double length = 0.0;
+    double* d_curve = nullptr;         // [4][degree+1] on the device
+};
+inline int64_t fhw_geom_key(int curve, int N) { return (int64_t)curve * 65536 + N; }
+
 struct fhw_ctx {
     hipStream_t stream = nullptr;
     size_t budget = 0;
@@ -63,14 +71,12 @@ struct fhw_ctx {
     bool planned = false;
     bool factors_resident = false;     // LU of every planned frequency in the workspace
     fhw_problem prob{};
-    std::vector<double> cx, sx, cy, sy;
-    int32_t degree = 0;
-    double length = 0.0;
-    std::vector<double> kappa, eta;
-    std::vector<int32_t> Ns;
-    std::vector<int64_t> psi_off;
-    std::map<int32_t, fhw_geom_entry> geoms;
-    double* d_curve = nullptr;  // [4][degree+1]
+    // systems: curve-major, system s = curve * F + j (frequency j of curve)
+    std::vector<fhw_host_curve> curves;
+    std::vector<double> kappa, eta;    // [systems]
+    std::vector<int32_t> Ns;           // [systems]
+    std::vector<int64_t> psi_off;      // [systems + 1]
+    std::map<int64_t, fhw_geom_entry> geoms;   // key: curve * 65536 + N
 
     // solve workspace (one chunk of frequencies)
     int32_t chunk = 0;                 // max frequencies per chunk
@@ -180,8 +186,9 @@ hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
 hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, double t0, double dt,
                                  double H, int64_t k_first, const int64_t* d_klist, int32_t count,
                                  double W, int32_t F, void* B);
+// c: complex128 [count][N_r][2F]; or, with c == NULL, real parts only into c_re
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V,
-                                 int32_t N_r, double W, int32_t F, double tau0, void* c);
+                                 int32_t N_r, double W, int32_t F, double tau0, void* c, double* c_re);
 hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min,
                         int64_t k_max, int32_t n_slots, int32_t N_r, const double* times,
                         int32_t N_t, double W, int32_t F, double H, double tau0, double* u);

@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, int cbeg, int ccount, c
 // quarter = 2x2 MFMA 16x16 blocks.
 // ---------------------------------------------------------------------------
 #define GT 64
-#define GK 16
+#define GK 32                 // K-chunk staged through LDS
 #define GPAD 1
 
 template <typename T>
@@ -500,12 +500,12 @@ __device__ __forceinline__ int xcd_tile(int w, int G) {
     return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
-// Stage one 16-deep chunk of the L and U operands in registers (real and
-// imaginary parts apart): L (k = tid/64 + 4p, i = tid%64), U (j = tid/16 +
-// 16p, k = tid%16).
+// Stage one GK-deep chunk of the L and U operands in registers (real and
+// imaginary parts apart): L (k = tid/64 + 4p, i = tid%64), U (j = tid/GK +
+// (256/GK) p, k = tid%GK), p < GK/4.
 template <typename T>
 struct gemm_stage {
-    T lr[4], li[4], ur[4], ui[4];
+    T lr[GK / 4], li[GK / 4], ur[GK / 4], ui[GK / 4];
 };
 
 template <typename T, bool SUB>
@@ -513,7 +513,7 @@ __device__ __forceinline__ void gemm_load_chunk(gemm_stage<T>& g, int kb, int ti
                                                 const cpx<T>* __restrict__ Lop, int ldl,
                                                 const cpx<T>* __restrict__ Uop, int N) {
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < GK / 4; ++pass) {
         const int k = (tid >> 6) + 4 * pass;
         const int i = tid & 63;
         const int kk = kb + k;
@@ -538,9 +538,9 @@ __device__ __forceinline__ void gemm_load_chunk(gemm_stage<T>& g, int kb, int ti
         g.li[pass] = vi;
     }
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) {
-        const int j = (tid >> 4) + 16 * pass;
-        const int k = tid & 15;
+    for (int pass = 0; pass < GK / 4; ++pass) {
+        const int j = tid / GK + (256 / GK) * pass;
+        const int k = tid % GK;
         T vr = (T)0, vi = (T)0;
         if ((kb + k < nb) && (j < ncols)) {
             const cpx<T> v = Uop[(int64_t)j * N + kb + k];
@@ -556,9 +556,10 @@ template <typename T, int NBUF>
 __device__ __forceinline__ void gemm_store_chunk(cpx<T> (&Ls)[NBUF][GK][GT + GPAD], cpx<T> (&Us)[NBUF][GK][GT + GPAD],
                                                  const gemm_stage<T>& g, int buf, int tid) {
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) Ls[buf][(tid >> 6) + 4 * pass][tid & 63] = cmk(g.lr[pass], g.li[pass]);
+    for (int pass = 0; pass < GK / 4; ++pass) Ls[buf][(tid >> 6) + 4 * pass][tid & 63] = cmk(g.lr[pass], g.li[pass]);
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) Us[buf][tid & 15][(tid >> 4) + 16 * pass] = cmk(g.ur[pass], g.ui[pass]);
+    for (int pass = 0; pass < GK / 4; ++pass)
+        Us[buf][tid % GK][tid / GK + (256 / GK) * pass] = cmk(g.ur[pass], g.ui[pass]);
 }
 
 // DBUF: double-buffered LDS chunks (next chunk's global loads in flight

@@ -71,10 +71,12 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
 
 // One workgroup per (point r, window slot q): LDS radix-2 FFT of length M = 2F
 // of G_l = B_q(omega_l) V(r, omega_l) e^{-i omega_l tau0};
-// c_m = (-1)^m X[m mod M] / M stored at index m + F.
+// c_m = (-1)^m X[m mod M] / M stored at index m + F: complex128 into c, or,
+// when c_re is given instead, only the real parts (all the synthesis needs:
+// its sinc weights are real and the field is the real part of the sum).
 __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __restrict__ B, const zd* __restrict__ V,
                                                                 int N_r, double W, int F, int logM, double tau0,
-                                                                zd* __restrict__ c) {
+                                                                zd* __restrict__ c, double* __restrict__ c_re) {
     extern __shared__ zd X[];
     const int r = blockIdx.x;
     const int q = blockIdx.y;
@@ -105,52 +107,101 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
         }
         __syncthreads();
     }
-    zd* out = c + ((int64_t)q * N_r + r) * M;
+    const int64_t base = ((int64_t)q * N_r + r) * M;
     const double inv = 1.0 / (double)M;
     for (int idx = threadIdx.x; idx < M; idx += SYN_THREADS) {
         const int m = idx - F;
         const zd x = X[(idx + F) % M];
         const double sg = (m & 1) ? -inv : inv;
-        out[idx] = cmk(sg * x.re, sg * x.im);
+        if (c_re) c_re[base + idx] = sg * x.re;
+        else c[base + idx] = cmk(sg * x.re, sg * x.im);
     }
 }
 
-// One wave per (point r, time t): active windows |t - s_k - tau0| <= pi F / W,
-// lanes stride over m, fixed-order reduction.
-__global__ __launch_bounds__(SYN_THREADS) void k_synth(const zd* __restrict__ c, const int* __restrict__ slot,
+// u(r, t) = (W/pi) sum_{k active} sum_m Re c_{k,m}(r) sinc(x - m), x = W (t - s_k
+// - tau0)/pi, active: |t - s_k - tau0| <= pi F / W.  With sinc(x - m) =
+// (-1)^m sin(pi x) / (pi (x - m)) the sum over m is sin(pi x)/pi times
+// sum_m (-1)^m Re c_m / (x - m); an integer x leaves the single term m = x.
+// One wave per (point r, block of ST consecutive time indices): each lane
+// reads its coefficients of a window once and serves all ST times; fixed-
+// order reductions.
+#define ST 8
+
+// 1/y: the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each squares the relative error), within about an ulp of 1/y.
+__device__ __forceinline__ double synth_recip(double y) {
+    double r = __builtin_amdgcn_rcp(y);
+    double e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-y, r, 1.0);
+    return fma(r, e, r);
+}
+
+__global__ __launch_bounds__(SYN_THREADS) void k_synth(const double* __restrict__ cre, const int* __restrict__ slot,
                                                        int64_t k_min, int64_t k_max, int N_r,
                                                        const double* __restrict__ times, int N_t, double W, int F,
                                                        double H, double tau0, double* __restrict__ u) {
+    const int nblk = (N_t + ST - 1) / ST;
     const int64_t wave = (int64_t)blockIdx.x * (SYN_THREADS / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (wave >= (int64_t)N_r * N_t) return;
-    const int r = (int)(wave / N_t);
-    const int it = (int)(wave - (int64_t)r * N_t);
-    const double t = times[it];
+    if (wave >= (int64_t)N_r * nblk) return;
+    const int r = (int)(wave / nblk);
+    const int it0 = (int)(wave - (int64_t)r * nblk) * ST;
     const int M = 2 * F;
     const double P = FHW_PI / (W / (double)F);
     const double span = 1.5 * H;
-    const int64_t ka = (int64_t)floor((t - tau0 - P) / span) + 1 - 1;
-    const int64_t kb = (int64_t)ceil((t - tau0 + P) / span) + 1 + 1;
-    double acc = 0.0;
+    double tq[ST];
+    int64_t ka = INT64_MAX, kb = INT64_MIN;
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+        tq[q] = (it0 + q < N_t) ? times[it0 + q] : times[it0];
+        ka = min(ka, (int64_t)floor((tq[q] - tau0 - P) / span) + 1 - 1);
+        kb = max(kb, (int64_t)ceil((tq[q] - tau0 + P) / span) + 1 + 1);
+    }
+    ka = max(ka, k_min);
+    kb = min(kb, k_max);
+    double tot[ST];
+#pragma unroll
+    for (int q = 0; q < ST; ++q) tot[q] = 0.0;
     for (int64_t k = ka; k <= kb; ++k) {
-        if (k < k_min || k > k_max) continue;
         const int sl = slot[k - k_min];
         if (sl < 0) continue;
         const double sk = 1.5 * H * ((double)k - 1.0);
-        if (!(fabs(t - sk - tau0) <= P)) continue;
-        const double x = W * (t - sk - tau0) / FHW_PI;
-        const double sx = sinpi(x);
-        const zd* ck = c + ((int64_t)sl * N_r + r) * M;
+        double xq[ST], scale[ST], part[ST];
+        bool use[ST];
+        bool anyk = false;
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            const bool act = (it0 + q < N_t) && fabs(tq[q] - sk - tau0) <= P;
+            xq[q] = W * (tq[q] - sk - tau0) / FHW_PI;
+            const bool integral = act && xq[q] == floor(xq[q]);
+            use[q] = act && !integral;
+            scale[q] = use[q] ? sinpi(xq[q]) / FHW_PI : 0.0;
+            part[q] = 0.0;
+            anyk |= act;
+            if (integral && lane == 0) {
+                // sinc(x - m) = 1 at m = x, 0 at every other m
+                const int idx = (int)xq[q] + F;
+                if (idx >= 0 && idx < M) tot[q] += cre[((int64_t)sl * N_r + r) * M + idx];
+            }
+        }
+        if (!anyk) continue;
+        const double* ck = cre + ((int64_t)sl * N_r + r) * M;
         for (int idx = lane; idx < M; idx += 64) {
             const int m = idx - F;
-            const double y = x - (double)m;
-            const double term = (y == 0.0) ? 1.0 : ((m & 1) ? -sx : sx) / (FHW_PI * y);
-            acc = fma(ck[idx].re, term, acc);
+            const double a = (m & 1) ? -ck[idx] : ck[idx];
+#pragma unroll
+            for (int q = 0; q < ST; ++q)
+                if (use[q]) part[q] = fma(a, synth_recip(xq[q] - (double)m), part[q]);
         }
+#pragma unroll
+        for (int q = 0; q < ST; ++q) tot[q] = fma(scale[q], part[q], tot[q]);
     }
-    acc = wave_sum(acc);
-    if (lane == 0) u[(int64_t)r * N_t + it] = (W / FHW_PI) * acc;
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+        const double v = wave_sum(tot[q]);
+        if (lane == 0 && it0 + q < N_t) u[(int64_t)r * N_t + it0 + q] = (W / FHW_PI) * v;
+    }
 }
 
 hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, double t0, double dt, double H,
@@ -164,14 +215,14 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
 }
 
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V, int32_t N_r, double W,
-                                 int32_t F, double tau0, void* c) {
+                                 int32_t F, double tau0, void* c, double* c_re) {
     if (count <= 0 || N_r <= 0) return hipSuccess;
     const int M = 2 * F;
     int logM = 0;
     while ((1 << logM) < M) ++logM;
     size_t lds = (size_t)M * sizeof(zd);
     hipLaunchKernelGGL(k_fourier_coeffs, dim3(N_r, count), dim3(SYN_THREADS), lds, s, (const zd*)B, (const zd*)V,
-                       N_r, W, F, logM, tau0, (zd*)c);
+                       N_r, W, F, logM, tau0, (zd*)c, c_re);
     return hipGetLastError();
 }
 
@@ -179,9 +230,9 @@ hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int
                         int32_t n_slots, int32_t N_r, const double* times, int32_t N_t, double W, int32_t F, double H,
                         double tau0, double* u) {
     (void)n_slots;
-    const int64_t waves = (int64_t)N_r * N_t;
+    const int64_t waves = (int64_t)N_r * ((N_t + ST - 1) / ST);
     if (waves <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_synth, dim3((unsigned)((waves + 3) / 4)), dim3(SYN_THREADS), 0, s, (const zd*)c, d_slot,
+    hipLaunchKernelGGL(k_synth, dim3((unsigned)((waves + 3) / 4)), dim3(SYN_THREADS), 0, s, (const double*)c, d_slot,
                        k_min, k_max, N_r, times, N_t, W, F, H, tau0, u);
     return hipGetLastError();
 }

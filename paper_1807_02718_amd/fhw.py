@@ -73,10 +73,12 @@ def _load():
         "fhw_destroy": [vp],
         "fhw_version": [],
         "fhw_plan": [vp, C.POINTER(fhw_curve), C.POINTER(fhw_problem), p_i32, p_i64],
+        "fhw_plan_curves": [vp, C.POINTER(fhw_curve), i32, C.POINTER(fhw_problem), p_i32, p_i64],
         "fhw_solve_densities": [vp, vp, _dp, p_i32, i32],
         "fhw_solve_incidences": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32, i32],
         "fhw_solve_cached": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
         "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
+        "fhw_eval_field_curve": [vp, i32, vp, _dp, i32, C.c_double, vp],
         "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
         "fhw_geometry": [vp, i32, vp],
         "fhw_kress_weights": [vp, i32, vp, vp],
@@ -99,8 +101,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_solve_densities",
-            "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
+            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
@@ -162,9 +164,15 @@ class Context:
     # -- plan -----------------------------------------------------------------
     def plan(self, curve, W, F, N=None, c=1.0, ppw=10.0, n_min=64, n_mult=32, n_cap=4096, precision="fp64",
              refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0)):
-        self._cv = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in
-                    (curve.cx, curve.sx, curve.cy, curve.sy)]
-        cs = fhw_curve(len(self._cv[0]) - 1, *[v.ctypes.data_as(_dp) for v in self._cv])
+        """Plan one curve, or several (a list: fhw_plan_curves, system s = k F + j).
+        Returns (N per system, psi offsets)."""
+        many = isinstance(curve, (list, tuple))
+        curves = list(curve) if many else [curve]
+        self._cv = [[np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (cv.cx, cv.sx, cv.cy, cv.sy)]
+                    for cv in curves]
+        arr = (fhw_curve * len(curves))()
+        for k, vs in enumerate(self._cv):
+            arr[k] = fhw_curve(len(vs[0]) - 1, *[v.ctypes.data_as(_dp) for v in vs])
         pr = fhw_problem()
         pr.W, pr.F, pr.c = float(W), int(F), float(c)
         pr.N_fixed = int(N) if N is not None else 0
@@ -172,11 +180,16 @@ class Context:
         pr.precision = {"fp64": FHW_FP64, "fp32_refine": FHW_FP32_REFINE}[precision]
         pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
         pr.direction[0], pr.direction[1] = float(direction[0]), float(direction[1])
-        Ns = np.zeros(F, dtype=np.int32)
-        off = np.zeros(F + 1, dtype=np.int64)
-        self._check(_lib.fhw_plan(self._h, C.byref(cs), C.byref(pr), Ns.ctypes.data_as(C.POINTER(C.c_int32)),
-                                  off.ctypes.data_as(C.POINTER(C.c_int64))))
+        S = len(curves) * int(F)
+        Ns = np.zeros(S, dtype=np.int32)
+        off = np.zeros(S + 1, dtype=np.int64)
+        pN, po = Ns.ctypes.data_as(C.POINTER(C.c_int32)), off.ctypes.data_as(C.POINTER(C.c_int64))
+        if many:
+            self._check(_lib.fhw_plan_curves(self._h, arr, len(curves), C.byref(pr), pN, po))
+        else:
+            self._check(_lib.fhw_plan(self._h, arr, C.byref(pr), pN, po))
         self.F, self.W, self.Ns, self.psi_off = int(F), float(W), Ns, off
+        self.S, self.n_curves = S, len(curves)
         self.precision = precision
         return Ns, off
 
@@ -184,8 +197,8 @@ class Context:
     def solve_densities(self, psi=None, compute_resid=False):
         if psi is None:
             psi = torch.empty(int(self.psi_off[-1]), dtype=torch.complex128, device=self.device)
-        resid = np.zeros(self.F)
-        sweeps = np.zeros(self.F, dtype=np.int32)
+        resid = np.zeros(self.S)
+        sweeps = np.zeros(self.S, dtype=np.int32)
         self._check(_lib.fhw_solve_densities(self._h, _ptr(psi), resid.ctypes.data_as(_dp),
                                              sweeps.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(compute_resid))))
         return psi, resid, sweeps
@@ -199,8 +212,8 @@ class Context:
             arr[q].v[0], arr[q].v[1] = float(v[0]), float(v[1])
         if psi is None:
             psi = torch.empty((max(n, 1), int(self.psi_off[-1])), dtype=torch.complex128, device=self.device)
-        resid = np.zeros((max(n, 1), self.F))
-        sweeps = np.zeros((max(n, 1), self.F), dtype=np.int32)
+        resid = np.zeros((max(n, 1), self.S))
+        sweeps = np.zeros((max(n, 1), self.S), dtype=np.int32)
         return arr, n, psi, resid, sweeps
 
     def solve_incidences(self, incidences, psi=None, compute_resid=False):
@@ -218,12 +231,16 @@ class Context:
                                           sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
         return psi, resid, sweeps
 
-    def eval_field(self, psi, obs, zero_value=1.0, V=None):
+    def eval_field(self, psi, obs, zero_value=1.0, V=None, curve=0):
         obs_h, obs_p = _host(obs, np.float64)
         Nr = obs_h.shape[0]
         if V is None:
             V = torch.empty((Nr, 2 * self.F), dtype=torch.complex128, device=self.device)
-        self._check(_lib.fhw_eval_field(self._h, _ptr(psi), obs_p, Nr, float(zero_value), _ptr(V)))
+        if curve == 0:
+            self._check(_lib.fhw_eval_field(self._h, _ptr(psi), obs_p, Nr, float(zero_value), _ptr(V)))
+        else:
+            self._check(_lib.fhw_eval_field_curve(self._h, int(curve), _ptr(psi), obs_p, Nr, float(zero_value),
+                                                  _ptr(V)))
         return V
 
     def synthesize(self, f, t0, dt, H, tau0, V, times, u=None):

@@ -488,3 +488,40 @@ def test_chunked_plan_matches(fhw):
         finally:
             c.close()
     assert relmax(out[1], out[0]) < 1e-13
+
+
+# ---------------------------------------------- several curves in one plan
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_plan_curves_star_batch(ctx, precision):
+    """Seeded star curves planned together (one batch of ragged systems):
+    every system's density and every curve's field against the oracle."""
+    say("plan_curves star batch", precision)
+    curves = Wk.star_pool(3, seed=0)
+    W, F = 30.0, 8
+    rule = dict(ppw=17.0, n_min=64, n_mult=32, n_cap=2048)
+    Ns, off = ctx.plan(curves, W, F, precision=precision, refine_tol=1e-14, refine_max=8, **rule)
+    assert len(Ns) == 3 * F and off[-1] == np.sum(Ns)
+    psi, res, _ = ctx.solve_densities()
+    P = psi.cpu().numpy()
+    _, kappa = O.frequency_grid(W, F)
+    eta = O.coupling(kappa)
+    obs = Wk.ring(6, 3.0)
+    for k, cv in enumerate(curves):
+        Nk = O.discretization_sizes(kappa, O.curve_length(cv), **rule)
+        assert np.array_equal(Ns[k * F:(k + 1) * F], Nk)
+        V = ctx.eval_field(psi, obs, curve=k).cpu().numpy()
+        for j in range(F):
+            s = k * F + j
+            gm = O.geometry(cv, int(Nk[j]))
+            ref, _ = O.solve_density(O.assemble(gm, kappa[j], eta[j]), O.rhs_plane_wave(gm, kappa[j], eta[j], (1.0, 0.0)))
+            assert relmax(P[off[s]:off[s + 1]], ref) < 1e-11, (k, j)
+            Vj = V[:, F + 1 + j] if j < F - 1 else np.conj(V[:, 0])
+            assert relmax(Vj, O.field(gm, ref, kappa[j], obs)) < 1e-11, (k, j)
+    # incidences and argument checks apply to every curve
+    psi2, _, _ = ctx.solve_incidences([("point", (4.0, 0.5))])
+    for k, cv in enumerate(curves):
+        s = k * F + F - 1
+        gm = O.geometry(cv, int(Ns[s]))
+        ref, _ = O.solve_density(O.assemble(gm, kappa[F - 1], eta[F - 1]),
+                                 O.rhs_point_source(gm, kappa[F - 1], eta[F - 1], (4.0, 0.5)))
+        assert relmax(psi2[0, off[s]:off[s + 1]].cpu().numpy(), ref) < 1e-11

@@ -223,6 +223,14 @@ def kite_n1024(F=1024, n_obs=256, n_times=1024, t_far=1.0e4) -> Workload:
                     H=10.0, tau0=10.0, signal=sig, obs=ring(n_obs, 3.0), times=times)
 
 
+def star_batch(n_curves=64, F=256, W=120.0, seed=0) -> dict:
+    """The batching configuration: n_curves seeded star curves, each with F
+    frequencies on (0, W] and N from 17 points per wavelength (multiple of 32,
+    64 <= N <= 2048), FP64, one plane-wave direction (1, 0)."""
+    return dict(curves=star_pool(n_curves, seed), W=W, F=F,
+                rule=dict(ppw=17.0, n_min=64, n_mult=32, n_cap=2048), direction=(1.0, 0.0))
+
+
 def interior_points(curve: Curve, n: int, seed: int = 3, shrink: float = 0.5) -> np.ndarray:
     """Points well inside a star-shaped-about-its-centroid curve (used for the
     interior-extinction checks): shrink curve points toward the centroid."""
