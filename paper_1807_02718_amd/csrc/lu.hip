@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, int cbeg, int ccount, c
 // quarter = 2x2 MFMA 16x16 blocks.
 // ---------------------------------------------------------------------------
 #define GT 64
-#define GK 32                 // K-chunk staged through LDS
+#define GK 16   // K-chunk staged through LDS (32 measured slower: fewer workgroups fit)
 #define GPAD 1
 
 template <typename T>
