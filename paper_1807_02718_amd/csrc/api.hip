@@ -75,11 +75,12 @@ void free_plan(fhw_ctx* c) {
         if (cv.d_curve) (void)hipFree(cv.d_curve);
     c->curves.clear();
     void* ptrs[] = {c->A64, c->A32, c->linv, c->piv, c->x, c->r, c->meta, c->d_status,
-                    c->d_norms, c->d_done, c->d_sweeps};
+                    c->d_norms, c->d_done, c->d_sweeps, c->d_rpart, c->d_rcount};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->A64 = c->A32 = c->linv = nullptr; c->piv = nullptr; c->x = c->r = nullptr;
     c->meta = nullptr; c->d_status = nullptr; c->d_norms = nullptr; c->d_done = nullptr; c->d_sweeps = nullptr;
+    c->d_rpart = nullptr; c->d_rcount = nullptr;
     c->planned = false;
     c->factors_resident = false;
 }
@@ -387,6 +388,10 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     FHW_HIP(c, hipMalloc((void**)&c->d_norms, sizeof(double) * 2 * S));
     FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * S));
     FHW_HIP(c, hipMalloc((void**)&c->d_sweeps, sizeof(int32_t) * S));
+    // residual: per-block partial norms and per-matrix block counters (zero)
+    FHW_HIP(c, hipMalloc((void**)&c->d_rpart, sizeof(double) * 2 * (size_t)maxcount * ((maxN + 63) / 64)));
+    FHW_HIP(c, hipMalloc((void**)&c->d_rcount, sizeof(int32_t) * (size_t)maxcount));
+    FHW_HIP(c, hipMemset(c->d_rcount, 0, sizeof(int32_t) * (size_t)maxcount));
     c->ws_A64 = wsA64; c->ws_A32 = wsA32; c->ws_linv = wsL; c->ws_piv = wsP;
 
     // per-chunk metadata, built once and uploaded into one buffer
@@ -552,8 +557,8 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             int32_t* sw = d_sw + (int64_t)q * F + ch.j0;
             const int maxs = std::max(0, p.refine_max);
             for (int it = 0; it <= maxs; ++it) {
-                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, norms, p.refine_tol, done, sw,
-                                             it));
+                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, c->d_rpart,
+                                                               c->d_rcount, norms, p.refine_tol, done, sw, it));
                 if (it == maxs) break;
                 STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, ch.maxN, LU, c->piv, c->linv, r, x, done,
                                                p.precision));
@@ -569,8 +574,9 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
                     STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, inc[q].kind, inc[q].v[0],
                                                       inc[q].v[1], g));
                 double* norms = d_norms + 2 * ((int64_t)q * F + ch.j0);
-                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, psid + q * total + ch.psi_base, g, r,
-                                             norms, 0.0, nullptr, nullptr, 0));
+                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, psid + q * total + ch.psi_base,
+                                                               g, r, c->d_rpart, c->d_rcount, norms, 0.0, nullptr,
+                                                               nullptr, 0));
             }
         }
     }

@@ -92,6 +92,8 @@ struct fhw_ctx {
     int32_t* d_status = nullptr;       // [0]: singular flag, [1..]: per-matrix flags
     size_t status_len = 0;
     double* d_norms = nullptr;         // [chunk][2] residual norms
+    double* d_rpart = nullptr;         // residual partial norms [chunk][blocks][2]
+    int32_t* d_rcount = nullptr;       // residual block counters [chunk] (kept zero)
     int32_t* d_done = nullptr;         // [chunk]
     int32_t* d_sweeps = nullptr;       // [chunk]
 
@@ -166,9 +168,11 @@ hipError_t launch_lu_solve(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, 
 hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU,
                                const int32_t* piv, const void* linv, void* x, void* acc,
                                const int32_t* d_skip, int precision);
+// part: 2 * batch * ceil(maxN/64) doubles of scratch; count: batch ints, zero
+// before the first call (each call leaves them zero)
 hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64,
-                             const void* x, const void* g, void* r, double* norms, double tol,
-                             int32_t* done, int32_t* sweeps, int sweep);
+                             const void* x, const void* g, void* r, double* part, int32_t* count,
+                             double* norms, double tol, int32_t* done, int32_t* sweeps, int sweep);
 hipError_t launch_convert_c128_c64(hipStream_t s, const void* src, void* dst, int64_t n);
 
 // --- field.hip --------------------------------------------------------------

@@ -160,61 +160,98 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
 
 // r = g - A x with the FP64 column-major matrix; norms[2b] = ||r||_2,
 // norms[2b+1] = ||g||_2.  Marks done[b] (and sweeps[b] = sweep) once
-// ||r|| <= tol ||g||.  Matrices already done are skipped.  One thread per row,
-// four rows at a time, coalesced down the columns; fixed-order reductions.
+// ||r|| <= tol ||g||.  Matrices already done are skipped.
+// Grid (matrix, row block of 256/PH rows): thread (row, column phase) with PH
+// column phases summed in a fixed order (PH = 4 for small batches, so that
+// one matrix spreads over many workgroups; PH = 1 for large ones, so that x
+// is staged fewer times); per-block partial norms; the last block of a matrix
+// to finish (a counter, reset by that block) adds the partials in block
+// order, so the norms are deterministic.
+template <int PH>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restrict__ Ns,
                                                             const int64_t* __restrict__ a_off,
                                                             const int64_t* __restrict__ v_off,
                                                             const zd* __restrict__ Abase, const zd* __restrict__ x,
                                                             const zd* __restrict__ g, zd* __restrict__ r,
-                                                            double* __restrict__ norms, double tol,
+                                                            double* __restrict__ part, int* __restrict__ count,
+                                                            int nblk_max, double* __restrict__ norms, double tol,
                                                             int* __restrict__ done, int* __restrict__ sweeps,
                                                             int sweep) {
+    constexpr int RES_ROWS = SOLVE_THREADS / PH;
     extern __shared__ zd xs[];
-    __shared__ double part[2][SOLVE_THREADS / 64];
+    __shared__ zd cs[PH][RES_ROWS];
+    __shared__ double wred[2][RES_ROWS / 64];
+    __shared__ int last;
     const int b = blockIdx.x;
     if (done && done[b]) return;
     const int N = Ns[b];
+    const int nblk = (N + RES_ROWS - 1) / RES_ROWS;
+    const int yb = blockIdx.y;
+    if (yb >= nblk) return;
     const zd* A = Abase + a_off[b];
     const zd* xb = x + v_off[b];
     const zd* gb = g + v_off[b];
     zd* rb = r + v_off[b];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wid = tid >> 6;
+    const int il = tid % RES_ROWS, cg = tid / RES_ROWS;
     for (int i = tid; i < N; i += SOLVE_THREADS) xs[i] = xb[i];
     __syncthreads();
-    double rr = 0.0, gg = 0.0;
-    constexpr int RB = 4;
-    for (int i0 = 0; i0 < N; i0 += RB * SOLVE_THREADS) {
-        zd s[RB];
+    const int i = yb * RES_ROWS + il;
+    zd s = cmk(0.0, 0.0);
+    if (i < N) {
+        constexpr int NC = PH;
+        zd s4[4];
 #pragma unroll
-        for (int q = 0; q < RB; ++q) s[q] = cmk(0.0, 0.0);
-        for (int c = 0; c < N; ++c) {
-            const zd xc = xs[c];
-            const zd* Ac = A + (int64_t)c * N + i0 + tid;
+        for (int u = 0; u < 4; ++u) s4[u] = cmk(0.0, 0.0);
+        int c = cg;
+        for (; c + 3 * NC < N; c += 4 * NC) {
+            zd a4[4];
 #pragma unroll
-            for (int q = 0; q < RB; ++q)
-                if (i0 + tid + q * SOLVE_THREADS < N) s[q] = cfma(s[q], Ac[q * SOLVE_THREADS], xc);
+            for (int u = 0; u < 4; ++u) a4[u] = A[(int64_t)(c + u * NC) * N + i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] = cfma(s4[u], a4[u], xs[c + u * NC]);
         }
-#pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            const int i = i0 + tid + q * SOLVE_THREADS;
-            if (i < N) {
-                const zd gi = gb[i];
-                const zd ri = csub(gi, s[q]);
-                rb[i] = ri;
-                rr += ri.re * ri.re + ri.im * ri.im;
-                gg += gi.re * gi.re + gi.im * gi.im;
-            }
-        }
+        for (; c < N; c += NC) s4[0] = cfma(s4[0], A[(int64_t)c * N + i], xs[c]);
+        s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
     }
-    rr = wave_sum(rr);
-    gg = wave_sum(gg);
-    if (lane == 0) { part[0][wid] = rr; part[1][wid] = gg; }
+    cs[cg][il] = s;
+    __syncthreads();
+    if (cg == 0) {
+        double rr = 0.0, gg = 0.0;
+        if (i < N) {
+            zd t = cs[0][il];
+#pragma unroll
+            for (int q = 1; q < PH; ++q) t = cadd(t, cs[q][il]);
+            const zd gi = gb[i];
+            const zd ri = csub(gi, t);
+            rb[i] = ri;
+            rr = ri.re * ri.re + ri.im * ri.im;
+            gg = gi.re * gi.re + gi.im * gi.im;
+        }
+        rr = wave_sum(rr);
+        gg = wave_sum(gg);
+        if ((il & 63) == 0) { wred[0][il >> 6] = rr; wred[1][il >> 6] = gg; }
+    }
     __syncthreads();
     if (tid == 0) {
+        double rr = 0.0, gg = 0.0;
+        for (int q = 0; q < RES_ROWS / 64; ++q) { rr += wred[0][q]; gg += wred[1][q]; }
+        double* pb = part + 2 * ((int64_t)b * nblk_max + yb);
+        pb[0] = rr;
+        pb[1] = gg;
+        __threadfence();
+        last = (atomicAdd(&count[b], 1) == nblk - 1);
+    }
+    __syncthreads();
+    if (last && tid == 0) {
+        __threadfence();
         double R2 = 0.0, G2 = 0.0;
-        for (int q = 0; q < SOLVE_THREADS / 64; ++q) { R2 += part[0][q]; G2 += part[1][q]; }
+        const double* pb = part + 2 * (int64_t)b * nblk_max;
+        for (int q = 0; q < nblk; ++q) {
+            R2 += pb[2 * q];
+            G2 += pb[2 * q + 1];
+        }
+        count[b] = 0;
         norms[2 * b] = sqrt(R2);
         norms[2 * b + 1] = sqrt(G2);
         if (done && R2 <= tol * tol * G2) {
@@ -249,11 +286,21 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
 }
 
 hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64, const void* x,
-                             const void* g, void* r, double* norms, double tol, int32_t* done, int32_t* sweeps,
-                             int sweep) {
+                             const void* g, void* r, double* part, int32_t* count, double* norms, double tol,
+                             int32_t* done, int32_t* sweeps, int sweep) {
     size_t lds = (size_t)maxN * sizeof(zd);
-    hipLaunchKernelGGL(k_residual, dim3(b.batch), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.v_off, (const zd*)A64,
-                       (const zd*)x, (const zd*)g, (zd*)r, norms, tol, done, sweeps, sweep);
+    // 256-row blocks when they alone give >= 1024 workgroups, else 64-row blocks
+    const bool wide = (int64_t)b.batch * ((maxN + 255) / 256) >= 1024;
+    const int rows = wide ? SOLVE_THREADS : SOLVE_THREADS / 4;
+    const int nblk = (maxN + rows - 1) / rows;
+    if (wide)
+        hipLaunchKernelGGL(k_residual<1>, dim3(b.batch, nblk), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.v_off,
+                           (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,
+                           sweeps, sweep);
+    else
+        hipLaunchKernelGGL(k_residual<4>, dim3(b.batch, nblk), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.v_off,
+                           (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,
+                           sweeps, sweep);
     return hipGetLastError();
 }
 
