@@ -37,14 +37,14 @@ __device__ __forceinline__ bool piv_better(T v, int i, T bv, int bi) {
     return (v > bv) || (v == bv && i < bi);
 }
 
-template <typename T, int W>
+template <typename T, int W, int PT>
 struct panel_lds {
     cpx<T> Ublk[W][NB];
     cpx<T> L11s[W][W];
     cpx<T> prow[W];
     cpx<T> rowk[W];
-    T redv[PANEL_THREADS / 64];
-    int redi[PANEL_THREADS / 64];
+    T redv[PT / 64];
+    int redi[PT / 64];
     int s_piv[NB];
     int sing;
 };
@@ -65,13 +65,13 @@ struct panel_row<T, W, false> {
 // held as separate real and imaginary rows.  WPE (waves per SIMD) sets the
 // register budget: wider sub-panels cut the in-panel update traffic, which
 // costs registers and so occupancy.
-template <typename T, int R, int W, int WPE>
-__global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const int* __restrict__ Ns,
+template <typename T, int R, int W, int WPE, int PT = PANEL_THREADS>
+__global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restrict__ Ns,
                                                                const int64_t* __restrict__ a_off,
                                                                const int64_t* __restrict__ piv_off,
                                                                cpx<T>* __restrict__ Abase, int* __restrict__ piv,
                                                                int* __restrict__ status) {
-    __shared__ panel_lds<T, W> S;
+    __shared__ panel_lds<T, W, PT> S;
     const int b = blockIdx.x;
     const int N = Ns[b];
     if (k0 >= N) return;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
         const int kc = k0 + s;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int row = kc + tid + i * PANEL_THREADS;
+            const int row = kc + tid + i * PT;
 #pragma unroll
             for (int q = 0; q < W; ++q) {
                 T vr = (T)0, vi = (T)0;
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
                 int bi = 0x7fffffff;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PANEL_THREADS;
+                    const int row = kc + tid + i * PT;
                     if (row >= col && row < N) {
                         const T v = fabs(ar[i][j]) + fabs(ai[i][j]);
                         if (piv_better(v, row, bv, bi)) { bv = v; bi = row; }
@@ -126,13 +126,13 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
                 __syncthreads();
                 bv = S.redv[0]; bi = S.redi[0];
 #pragma unroll
-                for (int q = 1; q < PANEL_THREADS / 64; ++q)
+                for (int q = 1; q < PT / 64; ++q)
                     if (piv_better(S.redv[q], S.redi[q], bv, bi)) { bv = S.redv[q]; bi = S.redi[q]; }
                 // no candidate (NaN column) or zero column: keep the row, flag it
                 const bool zp = !(bv > (T)0) || bi >= N;
                 const int p = (bi >= N) ? col : bi;
-                const int tp = (p - kc) % PANEL_THREADS, ip = (p - kc) / PANEL_THREADS;
-                const int tc = (col - kc) % PANEL_THREADS, ic = (col - kc) / PANEL_THREADS;
+                const int tp = (p - kc) % PT, ip = (p - kc) / PT;
+                const int tc = (col - kc) % PT, ic = (col - kc) / PT;
                 if constexpr (VEC) {
                     // row selection by selects over all R rows (no indexed vector access)
                     if (tid == tp || tid == tc) {
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
                 const cpx<T> pinv = zp ? cmk((T)0, (T)0) : crcp(S.prow[j]);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PANEL_THREADS;
+                    const int row = kc + tid + i * PT;
                     if (row > col && row < N) {
                         const T lr = ar[i][j] * pinv.re - ai[i][j] * pinv.im;
                         const T li = ar[i][j] * pinv.im + ai[i][j] * pinv.re;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
         // the factored sub-panel back
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int row = kc + tid + i * PANEL_THREADS;
+            const int row = kc + tid + i * PT;
             if (row < N) {
 #pragma unroll
                 for (int q = 0; q < W; ++q)
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
                 T vr[R][CH], vi[R][CH];
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PANEL_THREADS;
+                    const int row = kc + tid + i * PT;
                     const bool ok = row >= kc + w && row < N;
                     const cpx<T>* Pr = P + (int64_t)(s + w + c0) * N + (row - k0);
 #pragma unroll
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(PANEL_THREADS, WPE) void k_lu_panel(int k0, const i
                     }
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PANEL_THREADS;
+                    const int row = kc + tid + i * PT;
                     if (row >= kc + w && row < N) {
                         cpx<T>* Pr = P + (int64_t)(s + w + c0) * N + (row - k0);
 #pragma unroll
@@ -788,32 +788,49 @@ static void lu_set_lds_limits() {
                               (int)sizeof(inv_lds<T>));
 }
 
-// rows per thread R (from the step's largest panel height) and sub-panel
-// width W of the panel kernel, chosen to keep R*W complex values per thread
-// in registers
+// rows per thread R (from the step's largest panel height, for 256 threads)
+// and sub-panel width W of the panel kernel, chosen to keep R*W complex values
+// per thread in registers.  Batches of at most 256 matrices (one per CU or
+// fewer) use 1024 threads per matrix instead: a quarter of the rows per
+// thread, so each matrix's latency-bound panel work is spread wider.
 template <typename T>
 static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, int k0, cpx<T>* A, int32_t* piv,
                                int32_t* st) {
-#define FHW_PANEL(RR, WW, EE)                                                                                \
-    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE>), dim3(bd.batch), dim3(PANEL_THREADS), 0, s, k0, bd.N, bd.a_off, \
+#define FHW_PANEL(RR, WW, EE, PT)                                                                             \
+    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE, PT>), dim3(bd.batch), dim3(PT), 0, s, k0, bd.N, bd.a_off,  \
                        bd.piv_off, A, piv, st)
     // (R, W, waves per SIMD), chosen by measurement among the spill-free
     // register allocations
-    if constexpr (sizeof(T) == 4) {
+    if (bd.batch <= 256) {
+        const int R4 = (R + 3) / 4;   // rows per thread with 1024 threads
+        if constexpr (sizeof(T) == 4) {
+            switch (R4) {
+                case 1: FHW_PANEL(1, 16, 4, 1024); break;
+                case 2: FHW_PANEL(2, 8, 4, 1024); break;
+                default: FHW_PANEL(4, 8, 4, 1024); break;
+            }
+        } else {
+            switch (R4) {
+                case 1: FHW_PANEL(1, 8, 4, 1024); break;
+                case 2: FHW_PANEL(2, 4, 4, 1024); break;
+                default: FHW_PANEL(4, 4, 4, 1024); break;
+            }
+        }
+    } else if constexpr (sizeof(T) == 4) {
         switch (R) {
-            case 1: FHW_PANEL(1, 16, 4); break;
-            case 2: FHW_PANEL(2, 8, 4); break;
-            case 4: FHW_PANEL(4, 8, 4); break;
-            case 8: FHW_PANEL(8, 4, 2); break;
-            default: FHW_PANEL(16, 2, 2); break;
+            case 1: FHW_PANEL(1, 16, 4, 256); break;
+            case 2: FHW_PANEL(2, 8, 4, 256); break;
+            case 4: FHW_PANEL(4, 8, 4, 256); break;
+            case 8: FHW_PANEL(8, 4, 2, 256); break;
+            default: FHW_PANEL(16, 2, 2, 256); break;
         }
     } else {
         switch (R) {
-            case 1: FHW_PANEL(1, 8, 4); break;
-            case 2: FHW_PANEL(2, 8, 2); break;
-            case 4: FHW_PANEL(4, 8, 2); break;
-            case 8: FHW_PANEL(8, 4, 2); break;
-            default: FHW_PANEL(16, 2, 1); break;
+            case 1: FHW_PANEL(1, 8, 4, 256); break;
+            case 2: FHW_PANEL(2, 8, 2, 256); break;
+            case 4: FHW_PANEL(4, 8, 2, 256); break;
+            case 8: FHW_PANEL(8, 4, 2, 256); break;
+            default: FHW_PANEL(16, 2, 1, 256); break;
         }
     }
 #undef FHW_PANEL
