@@ -313,12 +313,20 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
 }
 
 // Inverses of the unit-lower and upper parts of the factored diagonal block
-// of panel k0 (one 1024-thread workgroup per matrix, block in LDS).  16 lanes
-// per column of the inverse: lane t sums the terms q = t mod 16.
+// of panel k0 (one 1024-thread workgroup per matrix, block in LDS), blocked:
+// the four 16x16 diagonal blocks by substitution (16 lanes per column, a
+// 16-lane reduction per step), then 32x32 and 64x64 inverses from
+//   inv([A 0; C B]) = [inv A, 0; -inv B C inv A, inv B]   (unit lower)
+//   inv([A B; 0 D]) = [inv A, -inv A B inv D; 0, inv D]   (upper)
+// with two triangular products per level, one output entry per thread.
+// I holds the result: strict lower = inverse of the unit-lower part,
+// upper with the diagonal = inverse of the upper part.
 template <typename T>
 struct inv_lds {
     cpx<T> D[NB][NB + 1];
     cpx<T> I[NB][NB + 1];
+    cpx<T> Tm[NB / 2][NB / 2 + 1];
+    cpx<T> rd[NB];   // reciprocals of the diagonal of U
 };
 
 template <typename T>
@@ -335,71 +343,87 @@ __global__ __launch_bounds__(INV_THREADS) void k_lu_diaginv(int k0, const int* _
     const int nb = min(NB, N - k0);
     const cpx<T>* Db = Abase + a_off[b] + (int64_t)k0 * N + k0;
     const int tid = threadIdx.x;
-    const cpx<T> zero = cmk((T)0, (T)0);
+    const cpx<T> zero = cmk((T)0, (T)0), one = cmk((T)1, (T)0);
+    // the block, padded to 64 with the identity (whose inverse parts are the identity)
     for (int e = tid; e < NB * NB; e += INV_THREADS) {
         const int c = e / NB, r = e - c * NB;
-        S.D[r][c] = (r < nb && c < nb) ? Db[(int64_t)c * N + r] : zero;
+        S.D[r][c] = (r < nb && c < nb) ? Db[(int64_t)c * N + r] : ((r == c) ? one : zero);
     }
     __syncthreads();
-    const int c = tid >> 4;   // column of the inverse, 0..63
-    const int t = tid & 15;
-    // ---- Linv column c: x_c = 1, x_r = -sum_{q=c}^{r-1} L_rq x_q
-    cpx<T> xv[4];
+    if (tid < NB) S.rd[tid] = crcp(S.D[tid][tid]);
+    __syncthreads();
+    // ---- level 0: 16x16 diagonal blocks; thread = (block bb, column c, lane t)
+    {
+        const int bb = tid >> 8, c = (tid >> 4) & 15, t = tid & 15;
+        const int o = 16 * bb;
+        // unit lower: x_c = 1, x_r = -sum_{q=c}^{r-1} L_rq x_q
+        cpx<T> x = (t == c) ? one : zero;
+        for (int r = c + 1; r < 16; ++r) {
+            cpx<T> acc = (t >= c && t < r) ? cmul(S.D[o + r][o + t], x) : zero;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) xv[u] = (t + 16 * u == c) ? cmk((T)1, (T)0) : zero;
-    for (int r = c + 1; r < nb; ++r) {
-        cpx<T> sacc = zero;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = t + 16 * u;
-            if (q >= c && q < r) sacc = cfma(sacc, S.D[r][q], xv[u]);
+            for (int off = 1; off < 16; off <<= 1) {
+                acc.re += __shfl_xor(acc.re, off, 64);
+                acc.im += __shfl_xor(acc.im, off, 64);
+            }
+            if (t == r) x = cmk(-acc.re, -acc.im);
         }
+        if (t > c) S.I[o + t][o + c] = x;
+        // upper: x_c = 1/U_cc, x_r = -(sum_{q=r+1}^{c} U_rq x_q) / U_rr, r < c
+        x = (t == c) ? S.rd[o + c] : zero;
+        for (int r = c - 1; r >= 0; --r) {
+            cpx<T> acc = (t > r && t <= c) ? cmul(S.D[o + r][o + t], x) : zero;
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            sacc.re += __shfl_xor(sacc.re, off, 64);
-            sacc.im += __shfl_xor(sacc.im, off, 64);
+            for (int off = 1; off < 16; off <<= 1) {
+                acc.re += __shfl_xor(acc.re, off, 64);
+                acc.im += __shfl_xor(acc.im, off, 64);
+            }
+            if (t == r) x = cmul(cmk(-acc.re, -acc.im), S.rd[o + r]);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (t + 16 * u == r) xv[u] = cmk(-sacc.re, -sacc.im);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = t + 16 * u;
-        if (r > c) S.I[r][c] = xv[u];
-    }
-    // ---- Uinv column c: x_c = 1/U_cc, x_r = -(sum_{q=r+1}^{c} U_rq x_q) / U_rr, r < c
-#pragma unroll
-    for (int u = 0; u < 4; ++u) xv[u] = zero;
-    if (c < nb) {
-        const cpx<T> dcc = crcp(S.D[c][c]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (t + 16 * u == c) xv[u] = dcc;
-    }
-    for (int r = min(c, nb) - 1; r >= 0; --r) {
-        cpx<T> sacc = zero;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = t + 16 * u;
-            if (q > r && q <= c) sacc = cfma(sacc, S.D[r][q], xv[u]);
-        }
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            sacc.re += __shfl_xor(sacc.re, off, 64);
-            sacc.im += __shfl_xor(sacc.im, off, 64);
-        }
-        const cpx<T> v = cmul(cmk(-sacc.re, -sacc.im), crcp(S.D[r][r]));
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (t + 16 * u == r) xv[u] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = t + 16 * u;
-        if (r <= c) S.I[r][c] = xv[u];
+        if (t <= c) S.I[o + t][o + c] = x;
     }
     __syncthreads();
+    // ---- levels 1 (m = 16, two pairs) and 2 (m = 32, one pair)
+    for (int m = 16; m < NB; m <<= 1) {
+        const int pairs = NB / (2 * m);
+        const int outs = m * m;                 // per pair
+        const int active = pairs * outs;        // 512 or 1024 threads
+        const int pr = tid / outs, e = tid - pr * outs;
+        const int r = e % m, j = e / m;
+        const int o = pr * 2 * m;               // pair origin: A at (o, o), B at (o+m, o+m)
+        const int tr = pr * m + r;              // this pair's rows of Tm (pairs * m <= 32)
+        // unit lower, step 1: Tm = C inv(A), C = L[o+m.., o..]; inv(A) unit lower
+        if (tid < active) {
+            cpx<T> acc = S.D[o + m + r][o + j];
+            for (int q = j + 1; q < m; ++q) acc = cfma(acc, S.D[o + m + r][o + q], S.I[o + q][o + j]);
+            S.Tm[tr][j] = acc;
+        }
+        __syncthreads();
+        // step 2: X = -inv(B) Tm, inv(B) unit lower
+        cpx<T> xv = zero;
+        if (tid < active) {
+            cpx<T> acc = S.Tm[tr][j];
+            for (int q = 0; q < r; ++q) acc = cfma(acc, S.I[o + m + r][o + m + q], S.Tm[pr * m + q][j]);
+            xv = cmk(-acc.re, -acc.im);
+        }
+        __syncthreads();
+        if (tid < active) S.I[o + m + r][o + j] = xv;
+        // upper, step 1: Tm = B inv(D), B = U[o.., o+m..]; inv(D) upper with diagonal
+        if (tid < active) {
+            cpx<T> acc = zero;
+            for (int q = 0; q <= j; ++q) acc = cfma(acc, S.D[o + r][o + m + q], S.I[o + m + q][o + m + j]);
+            S.Tm[tr][j] = acc;
+        }
+        __syncthreads();
+        // step 2: X = -inv(A) Tm, inv(A) upper with diagonal
+        if (tid < active) {
+            cpx<T> acc = zero;
+            for (int q = r; q < m; ++q) acc = cfma(acc, S.I[o + r][o + q], S.Tm[pr * m + q][j]);
+            xv = cmk(-acc.re, -acc.im);
+        }
+        __syncthreads();
+        if (tid < active) S.I[o + r][o + m + j] = xv;
+        __syncthreads();
+    }
     cpx<T>* Lb = linv + linv_off[b] + (int64_t)(k0 / NB) * NB * NB;
     for (int e = tid; e < NB * NB; e += INV_THREADS) {
         const int cc = e / NB, r = e - cc * NB;
