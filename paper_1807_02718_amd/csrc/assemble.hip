@@ -84,7 +84,9 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble(const fhw_assemble_ite
         zd e_ij, e_ji;
         if (i != j) {
             const double d1 = x1[j] - xi1, d2 = x2[j] - xi2;   // d = x_j - x_i
-            const double r = sqrt(d1 * d1 + d2 * d2);
+            const double r2 = d1 * d1 + d2 * d2;
+            const double ir = fhw_rsqrt(r2);   // 1 / r
+            const double r = r2 * ir;
             double J0, Y0, J1, Y1;
             fhw_bessel01(kappa * r, J0, Y0, J1, Y1);
             const double lam = it.logtab[l];
@@ -94,7 +96,6 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble(const fhw_assemble_ite
             const double cL = -kappa * inv4pi * J1;
             const double cY = -0.25 * kappa * Y1;
             const double cJ = 0.25 * kappa * J1;
-            const double ir = 1.0 / r;
             const double n_i = (ni1 * d1 + ni2 * d2) * ir;          // target i: nu_i . (x_j - x_i) / r
             const double n_j = -(nu1[j] * d1 + nu2[j] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
             e_ij = cfie_entry(n_i, cL, cY, cJ, M1, M2r, M2i, lam, it.R[l], wq, eta, spj);

@@ -8,6 +8,7 @@
 
 #define FHW_PI 3.14159265358979323846
 #define FHW_INV_SQRT2 0.70710678118654752440
+#define FHW_SQRT_2_OVER_PI 0.79788456080286535588   // sqrt(2 / pi)
 
 template <typename T>
 struct __align__(2 * sizeof(T)) cpx {
@@ -70,12 +71,21 @@ __device__ __forceinline__ double fhw_clenshaw(const double* c, int n, double u)
     return fma(u, b1, c[0] - b2);
 }
 
+// 1/sqrt(x), x > 0 finite: the hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2 (each squares the relative error).
+__device__ __forceinline__ double fhw_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 // Auxiliary P_nu, Q_nu (H_nu = sqrt(2/(pi z)) (P + iQ) e^{i(z - nu pi/2 - pi/4)})
-// for z > FHW_BES_Z_SERIES.  want1: also nu = 1.
+// for z > FHW_BES_Z_SERIES, given iz = 1/z.  want1: also nu = 1.
 template <bool want1>
-__device__ __forceinline__ void fhw_bes_pq(double z, double& P0, double& Q0, double& P1, double& Q1) {
+__device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, double& Q0, double& P1, double& Q1) {
     if (z >= FHW_BES_Z_ASYM) {
-        double iz = 1.0 / z;
         double y = iz * iz;
         P0 = fhw_horner(fhw_bes_asym_p0, FHW_BES_N_ASYM, y);
         Q0 = iz * fhw_horner(fhw_bes_asym_q0, FHW_BES_N_ASYM, y);
@@ -88,8 +98,16 @@ __device__ __forceinline__ void fhw_bes_pq(double z, double& P0, double& Q0, dou
     int iv = 0;
 #pragma unroll
     for (int q = 1; q < FHW_BES_N_INTERVALS; ++q) iv += (z >= fhw_bes_breaks[q]) ? 1 : 0;
-    double xa = 1.0 / fhw_bes_breaks[iv + 1], xb = 1.0 / fhw_bes_breaks[iv];
-    double u = (2.0 / z - (xa + xb)) / (xb - xa);
+    // u = (2/z - (xa + xb)) / (xb - xa) on [xa, xb] = [1/break_{iv+1}, 1/break_iv]:
+    // the interval constants are folded at compile time, one select each
+    double shift = 0.0, scale = 0.0;
+#pragma unroll
+    for (int q = 0; q < FHW_BES_N_INTERVALS; ++q) {
+        const double xa = 1.0 / fhw_bes_breaks[q + 1], xb = 1.0 / fhw_bes_breaks[q];
+        shift = (iv == q) ? xa + xb : shift;
+        scale = (iv == q) ? 1.0 / (xb - xa) : scale;
+    }
+    double u = (2.0 * iz - shift) * scale;
     const double* c = fhw_bes_cheb + iv * 4 * FHW_BES_N_CHEB;
     P0 = fhw_clenshaw(c, FHW_BES_N_CHEB, u);
     Q0 = fhw_clenshaw(c + FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
@@ -115,12 +133,13 @@ __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, d
         return;
     }
     double P0, Q0, P1, Q1;
-    fhw_bes_pq<true>(z, P0, Q0, P1, Q1);
+    const double rz = fhw_rsqrt(z);
+    fhw_bes_pq<true>(z, rz * rz, P0, Q0, P1, Q1);
     double s, c;
     sincos(z, &s, &c);
     double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;   // cos, sin of z - pi/4
     double c1 = s0, s1 = -c0;                                            // cos, sin of z - 3pi/4
-    double amp = sqrt(2.0 / (FHW_PI * z));
+    double amp = FHW_SQRT_2_OVER_PI * rz;                                // sqrt(2 / (pi z))
     J0 = amp * (P0 * c0 - Q0 * s0);
     Y0 = amp * (P0 * s0 + Q0 * c0);
     J1 = amp * (P1 * c1 - Q1 * s1);
@@ -138,11 +157,12 @@ __device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0) {
         return;
     }
     double P0, Q0, P1, Q1;
-    fhw_bes_pq<false>(z, P0, Q0, P1, Q1);
+    const double rz = fhw_rsqrt(z);
+    fhw_bes_pq<false>(z, rz * rz, P0, Q0, P1, Q1);
     double s, c;
     sincos(z, &s, &c);
     double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;
-    double amp = sqrt(2.0 / (FHW_PI * z));
+    double amp = FHW_SQRT_2_OVER_PI * rz;
     J0 = amp * (P0 * c0 - Q0 * s0);
     Y0 = amp * (P0 * s0 + Q0 * c0);
 }
