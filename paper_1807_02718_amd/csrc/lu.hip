@@ -14,8 +14,8 @@
 //   k_lu_swap     the panel's row swaps on a column range (no work when the
 //                 panel did not pivot, the usual case for these systems).
 //   k_lu_gemm     U12 = L11^{-1} A12 (in place) and A22 -= L21 U12 on 64x64
-//                 tiles with depth 64 or 128, the complex product as 4 real
-//                 MFMA 16x16x4 products.
+//                 tiles with depth 64 or 128, the complex product as 3 real
+//                 MFMA 16x16x4 products (Gauss's 3M form).
 // A panel's L columns carry the pivots of its pair partner but not those of
 // later pairs; the solves replay the pivots pair by pair.
 #include "fhw_device.h"
@@ -637,13 +637,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
     const int lane = tid & 63, wid = tid >> 6;
     const int wj = wid >> 1, wi = wid & 1;
     const cpx<T> zero = cmk((T)0, (T)0);
-    acc_t accr[2][2], acci[2][2];
+    // complex products by Gauss's three real products (the 3M method):
+    // P1 = Ur Lr, P2 = Ui Li, P3 = (Ur + Ui)(Lr + Li); Re = P1 - P2, Im = P3 - P1 - P2
+    acc_t acc1[2][2], acc2[2][2], acc3[2][2];
 #pragma unroll
     for (int mj = 0; mj < 2; ++mj)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) {
-            accr[mj][ni] = (acc_t)(0);
-            acci[mj][ni] = (acc_t)(0);
+            acc1[mj][ni] = (acc_t)(0);
+            acc2[mj][ni] = (acc_t)(0);
+            acc3[mj][ni] = (acc_t)(0);
         }
     gemm_stage<T> stg;
 
@@ -671,15 +674,19 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
             for (int mj = 0; mj < 2; ++mj) uf[mj] = Us[buf][kr][wj * 32 + mj * 16 + (lane & 15)];
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni) lf[ni] = Ls[buf][kr][wi * 32 + ni * 16 + (lane & 15)];
+            T us[2], ls[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                us[q] = uf[q].re + uf[q].im;
+                ls[q] = lf[q].re + lf[q].im;
+            }
 #pragma unroll
             for (int mj = 0; mj < 2; ++mj) {
-                const T nui = -uf[mj].im;
 #pragma unroll
                 for (int ni = 0; ni < 2; ++ni) {
-                    accr[mj][ni] = mfma_traits<T>::mac(uf[mj].re, lf[ni].re, accr[mj][ni]);
-                    accr[mj][ni] = mfma_traits<T>::mac(nui, lf[ni].im, accr[mj][ni]);
-                    acci[mj][ni] = mfma_traits<T>::mac(uf[mj].re, lf[ni].im, acci[mj][ni]);
-                    acci[mj][ni] = mfma_traits<T>::mac(uf[mj].im, lf[ni].re, acci[mj][ni]);
+                    acc1[mj][ni] = mfma_traits<T>::mac(uf[mj].re, lf[ni].re, acc1[mj][ni]);
+                    acc2[mj][ni] = mfma_traits<T>::mac(uf[mj].im, lf[ni].im, acc2[mj][ni]);
+                    acc3[mj][ni] = mfma_traits<T>::mac(us[mj], ls[ni], acc3[mj][ni]);
                 }
             }
         }
@@ -703,11 +710,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
                 const int i = wi * 32 + ni * 16 + (lane & 15);
                 if (i < nrows && j < ncols) {
                     cpx<T>* p = C + (int64_t)j * N + i;
+                    const T p1 = acc1[mj][ni][v], p2 = acc2[mj][ni][v];
+                    const T dre = p1 - p2, dim = acc3[mj][ni][v] - p1 - p2;
                     if (SUB) {
                         const cpx<T> o = *p;
-                        *p = cmk(o.re - accr[mj][ni][v], o.im - acci[mj][ni][v]);
+                        *p = cmk(o.re - dre, o.im - dim);
                     } else {
-                        *p = cmk(accr[mj][ni][v], acci[mj][ni][v]);
+                        *p = cmk(dre, dim);
                     }
                 }
             }
