@@ -525,3 +525,19 @@ def test_plan_curves_star_batch(ctx, precision):
         ref, _ = O.solve_density(O.assemble(gm, kappa[F - 1], eta[F - 1]),
                                  O.rhs_point_source(gm, kappa[F - 1], eta[F - 1], (4.0, 0.5)))
         assert relmax(psi2[0, off[s]:off[s + 1]].cpu().numpy(), ref) < 1e-11
+
+
+def test_budget_too_small(fhw):
+    """A workspace budget below one frequency's needs is FHW_E_NOMEM at plan
+    time, and the context stays usable."""
+    say("budget too small")
+    c = fhw.Context(hbm_budget_bytes=4 << 20)
+    try:
+        with pytest.raises(fhw.FhwError) as e:
+            c.plan(Wk.kite(), 40.0, 4, N=1024)          # one N = 1024 matrix alone is 16 MiB
+        assert e.value.code == fhw.FHW_E_NOMEM
+        c.plan(Wk.kite(), 10.0, 2, N=64)
+        psi, _, _ = c.solve_densities()
+        assert torch.isfinite(torch.view_as_real(psi)).all()
+    finally:
+        c.close()
