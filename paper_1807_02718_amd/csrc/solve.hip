@@ -28,7 +28,11 @@ __device__ __forceinline__ void replay_pivots(zd* xs, const int* piv, int k0, in
 // factorization left it (below).
 // Backward: per panel from the last, subtract U12 * x from the block's rows
 // (one lane per row, waves over columns), multiply by the inverse of U11.
-template <typename T>
+// WIDE (batches of at most 256 matrices): the diagonal-block products use all
+// 256 threads (4 per row, fully unrolled), shortening each matrix's chain of
+// dependent loads; larger batches keep one thread per row and read only the
+// triangle.
+template <typename T, bool WIDE>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restrict__ Ns,
                                                             const int64_t* __restrict__ a_off,
                                                             const int64_t* __restrict__ piv_off,
@@ -62,17 +66,39 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         if (tid == 0 && (p & 1) == 0) replay_pivots(xs, piv, k0, nb);
         __syncthreads();
         const cpx<T>* D = Lb + (int64_t)p * NB * NB;
-        zd y = cmk(0.0, 0.0);
-        if (tid < nb) {
-            y = xs[k0 + tid];
-            for (int c = 0; c < tid; ++c) {
-                const cpx<T> l = D[c * NB + tid];
-                y = cfma(y, cmk((double)l.re, (double)l.im), xs[k0 + c]);
+        if constexpr (WIDE) {
+            // y = inv(L11) x_block: row lane, 16 columns per wave, all loads in flight
+            {
+                zd sacc = cmk(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < NB / 4; ++u) {
+                    const int c = wid * (NB / 4) + u;
+                    const cpx<T> l = D[c * NB + lane];
+                    if (c < lane && lane < nb) sacc = cfma(sacc, cmk((double)l.re, (double)l.im), xs[k0 + c]);
+                }
+                part[wid][lane] = sacc;
             }
+            __syncthreads();
+            if (tid < nb) {
+                zd y = xs[k0 + tid];
+#pragma unroll
+                for (int q = 0; q < SOLVE_THREADS / 64; ++q) y = cadd(y, part[q][tid]);
+                xs[k0 + tid] = y;
+            }
+            __syncthreads();
+        } else {
+            zd y = cmk(0.0, 0.0);
+            if (tid < nb) {
+                y = xs[k0 + tid];
+                for (int c = 0; c < tid; ++c) {
+                    const cpx<T> l = D[c * NB + tid];
+                    y = cfma(y, cmk((double)l.re, (double)l.im), xs[k0 + c]);
+                }
+            }
+            __syncthreads();
+            if (tid < nb) xs[k0 + tid] = y;
+            __syncthreads();
         }
-        __syncthreads();
-        if (tid < nb) xs[k0 + tid] = y;
-        __syncthreads();
         if ((p & 1) == 0 && p + 1 < np) {
             if (tid == 0) replay_pivots(xs, piv, k0 + NB, min(NB, N - k0 - NB));
             __syncthreads();
@@ -139,16 +165,38 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         }
         __syncthreads();
         const cpx<T>* D = Lb + (int64_t)p * NB * NB;
-        zd y = cmk(0.0, 0.0);
-        if (tid < nb) {
-            for (int c = tid; c < nb; ++c) {
-                const cpx<T> u = D[c * NB + tid];
-                y = cfma(y, cmk((double)u.re, (double)u.im), rhs[c]);
+        if constexpr (WIDE) {
+            // x_block = inv(U11) rhs: row lane, 16 columns per wave
+            {
+                zd sacc = cmk(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < NB / 4; ++u) {
+                    const int c = wid * (NB / 4) + u;
+                    const cpx<T> d = D[c * NB + lane];
+                    if (c >= lane && c < nb) sacc = cfma(sacc, cmk((double)d.re, (double)d.im), rhs[c]);
+                }
+                part[wid][lane] = sacc;
             }
+            __syncthreads();
+            if (tid < nb) {
+                zd y = part[0][tid];
+#pragma unroll
+                for (int q = 1; q < SOLVE_THREADS / 64; ++q) y = cadd(y, part[q][tid]);
+                xs[k0 + tid] = y;
+            }
+            __syncthreads();
+        } else {
+            zd y = cmk(0.0, 0.0);
+            if (tid < nb) {
+                for (int c = tid; c < nb; ++c) {
+                    const cpx<T> u = D[c * NB + tid];
+                    y = cfma(y, cmk((double)u.re, (double)u.im), rhs[c]);
+                }
+            }
+            __syncthreads();
+            if (tid < nb) xs[k0 + tid] = y;
+            __syncthreads();
         }
-        __syncthreads();
-        if (tid < nb) xs[k0 + tid] = y;
-        __syncthreads();
     }
     if (acc) {
         zd* ab = acc + v_off[b];
@@ -276,12 +324,16 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
                                const int32_t* piv, const void* linv, void* x, void* acc, const int32_t* d_skip,
                                int precision) {
     size_t lds = (size_t)maxN * sizeof(zd);
-    if (precision == FHW_FP64)
-        hipLaunchKernelGGL((k_lu_solve<double>), dim3(b.batch), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.piv_off,
-                           b.linv_off, b.v_off, (const zd*)LU, piv, (const zd*)linv, (zd*)x, (zd*)acc, d_skip);
-    else
-        hipLaunchKernelGGL((k_lu_solve<float>), dim3(b.batch), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.piv_off,
-                           b.linv_off, b.v_off, (const zf*)LU, piv, (const zf*)linv, (zd*)x, (zd*)acc, d_skip);
+#define FHW_SOLVE(TT, WW)                                                                                     \
+    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.piv_off, \
+                       b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, d_skip)
+    const bool wide = b.batch <= 256;
+    if (precision == FHW_FP64) {
+        if (wide) FHW_SOLVE(double, true); else FHW_SOLVE(double, false);
+    } else {
+        if (wide) FHW_SOLVE(float, true); else FHW_SOLVE(float, false);
+    }
+#undef FHW_SOLVE
     return hipGetLastError();
 }
 
