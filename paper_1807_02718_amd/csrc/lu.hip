@@ -261,8 +261,8 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
             __syncthreads();
             // rows below the sub-panel: A22 -= L21 U on the panel's remaining columns.
             // Chunks of CH columns, all R rows of a chunk loaded together.
-            // columns per chunk: 16 / R, halved for FP64 at four waves per SIMD (registers)
-            constexpr int CHW = (sizeof(T) == 8 && WPE > 2) ? 8 : 16;
+            // columns per chunk: CHW / R within the register budget of WPE
+            constexpr int CHW = (WPE > 2) ? (sizeof(T) == 8 ? 8 : 16) : (sizeof(T) == 8 ? 16 : 32);
             constexpr int CH = CHW / R > 0 ? CHW / R : 1;
             for (int c0 = 0; c0 < ncols; c0 += CH) {
                 T vr[R][CH], vi[R][CH];
