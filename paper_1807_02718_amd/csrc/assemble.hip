@@ -38,7 +38,7 @@ __device__ __forceinline__ zd cfie_entry(double n_t, double cL, double cY, doubl
 // along i) and A(j, i) (staged in LDS, then written with lanes along j).
 // Diagonal tiles take i >= j only and mirror the strict part.  Tiles with
 // J = 0 also write the RHS.
-__global__ __launch_bounds__(ASM_THREADS) void k_assemble(const fhw_assemble_item* __restrict__ items,
+__global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_item* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int n_items,
                                                           double p1, double p2, zd* __restrict__ A,
                                                           zf* __restrict__ A32, zd* __restrict__ g) {
