@@ -137,7 +137,7 @@ __device__ __forceinline__ double synth_recip(double y) {
     return fma(r, e, r);
 }
 
-__global__ __launch_bounds__(SYN_THREADS) void k_synth(const double* __restrict__ cre, const int* __restrict__ slot,
+__global__ __launch_bounds__(SYN_THREADS, 4) void k_synth(const double* __restrict__ cre, const int* __restrict__ slot,
                                                        int64_t k_min, int64_t k_max, int N_r,
                                                        const double* __restrict__ times, int N_t, double W, int F,
                                                        double H, double tau0, double* __restrict__ u) {
