@@ -24,18 +24,25 @@ __device__ __forceinline__ double fhw_window(double t, double H) {
     return 0.0;
 }
 
-// grid (count, ceil(2F / 256)); thread = one grid frequency omega_l.
+// grid (count, ceil(2F / 32)): a workgroup takes 32 grid frequencies omega_l
+// and splits the window's samples over 8 phases (sample i to phase i mod 8),
+// so that a window's transform spreads over many workgroups; the 8 partial
+// sums of a frequency are added in phase order.
+#define WS_FREQ 32
+#define WS_PH (SYN_THREADS / WS_FREQ)
 __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __restrict__ f, int64_t n, double t0,
                                                                 double dt, double H, int64_t k_first,
                                                                 const int64_t* __restrict__ klist, double W, int F,
                                                                 zd* __restrict__ B) {
     __shared__ double wa[WS_CHUNK];
     __shared__ double tau[WS_CHUNK];
+    __shared__ double red[2][WS_PH][WS_FREQ];
     const int q = blockIdx.x;
     const int64_t k = klist ? klist[q] : (k_first + q);
     const double sk = 1.5 * H * ((double)k - 1.0);
     const int M = 2 * F;
-    const int l = blockIdx.y * SYN_THREADS + threadIdx.x;
+    const int fl = threadIdx.x % WS_FREQ, ph = threadIdx.x / WS_FREQ;
+    const int l = blockIdx.y * WS_FREQ + fl;
     const double dw = W / (double)F;
     const double om = -W + dw * (double)l;
     int64_t n_lo = (int64_t)floor((sk - H - t0) / dt) - 1;
@@ -55,7 +62,7 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
         }
         __syncthreads();
         if (l < M) {
-            for (int i = 0; i < cnt; ++i) {
+            for (int i = ph; i < cnt; i += WS_PH) {
                 const double w = wa[i];
                 if (w != 0.0) {
                     double s, c;
@@ -66,7 +73,18 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
             }
         }
     }
-    if (l < M) B[(int64_t)q * M + l] = cmk(dt * ar, dt * ai);
+    red[0][ph][fl] = ar;
+    red[1][ph][fl] = ai;
+    __syncthreads();
+    if (ph == 0 && l < M) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int p = 0; p < WS_PH; ++p) {
+            sr += red[0][p][fl];
+            si += red[1][p][fl];
+        }
+        B[(int64_t)q * M + l] = cmk(dt * sr, dt * si);
+    }
 }
 
 // One workgroup per (point r, window slot q): LDS radix-2 FFT of length M = 2F
@@ -208,7 +226,7 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
                                  int64_t k_first, const int64_t* d_klist, int32_t count, double W, int32_t F,
                                  void* B) {
     if (count <= 0) return hipSuccess;
-    dim3 grid(count, (2 * F + SYN_THREADS - 1) / SYN_THREADS);
+    dim3 grid(count, (2 * F + WS_FREQ - 1) / WS_FREQ);
     hipLaunchKernelGGL(k_window_spectra, grid, dim3(SYN_THREADS), 0, s, f, n, t0, dt, H, k_first, d_klist, W, F,
                        (zd*)B);
     return hipGetLastError();
