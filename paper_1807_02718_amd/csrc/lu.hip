@@ -6,9 +6,8 @@
 // at lu_build_schedule).  Per panel k0:
 //   k_lu_panel    one 256-thread workgroup per matrix (two to four per CU) factors
 //                 the (N-k0) x 64 panel in sub-panels of W columns held in
-//                 registers, rows owned by threads (coalesced in column-major);
-//                 pivot search = wave shuffles + one LDS round, max |re|+|im|,
-//                 first index on ties; sub-panel swaps and in-panel updates.
+//                 registers, rows owned by threads (coalesced in column-major),
+//                 left-looking across sub-panels so each is read and written once.
 //   k_lu_diaginv  inverses of the 64x64 unit-lower and upper diagonal blocks
 //                 (used by the trailing TRSM and by the solves), in LDS.
 //   k_lu_swap     the panel's row swaps on a column range (no work when the
@@ -37,10 +36,20 @@ __device__ __forceinline__ bool piv_better(T v, int i, T bv, int bi) {
     return (v > bv) || (v == bv && i < bi);
 }
 
+// Panel factorization, left-looking over sub-panels of W columns.  Thread
+// tid owns rows k0 + tid + i*PT of the panel.  Each sub-panel is read once,
+// brought up to date with the factored sub-panels t < s one after the other
+// (U_t = L_tt^{-1} X_t on its W diagonal rows, then X -= L_t U_t on the rows
+// below, L_t streamed from memory), factored in registers (pivot search by
+// wave shuffles and one LDS round, max |re|+|im|, first index on ties) and
+// written back once: the panel's columns are never rewritten between
+// sub-panels.  R rows per thread and W columns per sub-panel set the register
+// budget, WPE the waves per SIMD.
 template <typename T, int W, int PT>
 struct panel_lds {
-    cpx<T> Ublk[W][NB];
-    cpx<T> L11s[W][W];
+    cpx<T> X[W][W];             // rows t*W .. t*W+W-1 of the sub-panel (lazy step t)
+    cpx<T> U[2][W][W];          // U_t, double-buffered across lazy steps
+    cpx<T> Lkeep[NB / W][W][W]; // unit-lower diagonal blocks of the factored sub-panels
     cpx<T> prow[W];
     cpx<T> rowk[W];
     T redv[PT / 64];
@@ -49,52 +58,37 @@ struct panel_lds {
     int sing;
 };
 
-// Storage of one thread's rows: FP64 rows as W-vectors (a plain R x W array
-// of doubles is demoted to scratch at the widths used), FP32 rows as arrays
-// (measured faster there).
-template <typename T, int W, bool VEC>
-struct panel_row {
-    typedef T type __attribute__((ext_vector_type(W)));
-};
-template <typename T, int W>
-struct panel_row<T, W, false> {
-    typedef T type[W];
-};
-
-// Thread tid owns rows kc + tid + i*256 (i < R) of the current sub-panel,
-// held as separate real and imaginary rows.  WPE (waves per SIMD) sets the
-// register budget: wider sub-panels cut the in-panel update traffic, which
-// costs registers and so occupancy.
 template <typename T, int R, int W, int WPE, int PT = PANEL_THREADS>
 __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restrict__ Ns,
-                                                               const int64_t* __restrict__ a_off,
-                                                               const int64_t* __restrict__ piv_off,
-                                                               cpx<T>* __restrict__ Abase, int* __restrict__ piv,
-                                                               int* __restrict__ status) {
+                                                      const int64_t* __restrict__ a_off,
+                                                      const int64_t* __restrict__ piv_off,
+                                                      cpx<T>* __restrict__ Abase, int* __restrict__ piv,
+                                                      int* __restrict__ status) {
+    static_assert(NB % W == 0, "sub-panels tile the panel");
     __shared__ panel_lds<T, W, PT> S;
     const int b = blockIdx.x;
     const int N = Ns[b];
     if (k0 >= N) return;
-    const int nb = min(NB, N - k0);
+    const int m = N - k0;
+    const int nb = min(NB, m);
     // P[c*N + r]: entry (k0 + r, k0 + c) of the matrix
     cpx<T>* P = Abase + a_off[b] + (int64_t)k0 * N + k0;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     if (tid == 0) S.sing = 0;
 
-    constexpr bool VEC = sizeof(T) == 8;
-    typename panel_row<T, W, VEC>::type ar[R], ai[R];
+    T ar[R][W], ai[R][W];
     for (int s = 0; s < nb; s += W) {
         const int w = min(W, nb - s);
         const int kc = k0 + s;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int row = kc + tid + i * PT;
+            const int rho = tid + i * PT;
 #pragma unroll
             for (int q = 0; q < W; ++q) {
                 T vr = (T)0, vi = (T)0;
-                if (row < N && q < w) {
-                    const cpx<T> v = P[(int64_t)(s + q) * N + (row - k0)];
+                if (rho < m && q < w) {
+                    const cpx<T> v = P[(int64_t)(s + q) * N + rho];
                     vr = v.re;
                     vi = v.im;
                 }
@@ -102,6 +96,67 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                 ai[i][q] = vi;
             }
         }
+        // lazy updates by the factored sub-panels (all of full width W)
+        for (int t = 0; t < s / W; ++t) {
+            const int tb = t * W;
+            const int buf = t & 1;
+            if (wid == 0) {
+                // rows tb .. tb+W-1 are rows i = 0 of lanes tb .. tb+W-1
+                if (lane >= tb && lane < tb + W) {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) S.X[lane - tb][q] = cmk(ar[0][q], ai[0][q]);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < W) {
+                    // column lane of U_t = L_tt^{-1} X_t (unit lower, forward substitution)
+                    cpx<T> x[W];
+#pragma unroll
+                    for (int rr = 0; rr < W; ++rr) x[rr] = S.X[rr][lane];
+#pragma unroll
+                    for (int rr = 1; rr < W; ++rr) {
+#pragma unroll
+                        for (int q = 0; q < rr; ++q) x[rr] = cfms(x[rr], S.Lkeep[t][rr][q], x[q]);
+                    }
+#pragma unroll
+                    for (int rr = 0; rr < W; ++rr) S.U[buf][rr][lane] = x[rr];
+                }
+            }
+            __syncthreads();
+            // rows below block t: X -= L_t U_t, one column of L_t at a time
+            // with R loads in flight
+            const cpx<T>* Lt = P + (int64_t)tb * N + tid;
+#pragma unroll 1
+            for (int q = 0; q < W; ++q) {
+                cpx<T> l[R];
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int rho = tid + i * PT;
+                    l[i] = (rho >= tb + W && rho < m) ? Lt[(int64_t)q * N + i * PT] : cmk((T)0, (T)0);
+                }
+#pragma unroll
+                for (int c = 0; c < W; ++c) {
+                    const cpx<T> u = S.U[buf][q][c];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        if (tid + i * PT >= tb + W && tid + i * PT < m) {
+                            ar[i][c] = ar[i][c] - l[i].re * u.re + l[i].im * u.im;
+                            ai[i][c] = ai[i][c] - l[i].re * u.im - l[i].im * u.re;
+                        }
+                    }
+                }
+            }
+            if (tid >= tb && tid < tb + W) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) {
+                    const cpx<T> u = S.U[buf][tid - tb][c];
+                    ar[0][c] = u.re;
+                    ai[0][c] = u.im;
+                }
+            }
+        }
+        // factor the sub-panel: rows kc .. N-1 of its columns
 #pragma clang loop unroll(full)
         for (int j = 0; j < W; ++j) {
             if (j < w) {
@@ -110,7 +165,7 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                 int bi = 0x7fffffff;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PT;
+                    const int row = k0 + tid + i * PT;
                     if (row >= col && row < N) {
                         const T v = fabs(ar[i][j]) + fabs(ai[i][j]);
                         if (piv_better(v, row, bv, bi)) { bv = v; bi = row; }
@@ -131,36 +186,17 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                 // no candidate (NaN column) or zero column: keep the row, flag it
                 const bool zp = !(bv > (T)0) || bi >= N;
                 const int p = (bi >= N) ? col : bi;
-                const int tp = (p - kc) % PT, ip = (p - kc) / PT;
-                const int tc = (col - kc) % PT, ic = (col - kc) / PT;
-                if constexpr (VEC) {
-                    // row selection by selects over all R rows (no indexed vector access)
-                    if (tid == tp || tid == tc) {
+                const int tp = (p - k0) % PT, ip = (p - k0) / PT;
+                const int tc = (col - k0) % PT, ic = (col - k0) / PT;
 #pragma unroll
-                        for (int q = 0; q < W; ++q) {
-                            T pr = (T)0, pi = (T)0, cr = (T)0, ci = (T)0;
+                for (int i = 0; i < R; ++i) {
+                    if (tid == tp && i == ip) {
 #pragma unroll
-                            for (int i = 0; i < R; ++i) {
-                                pr = (i == ip) ? ar[i][q] : pr;
-                                pi = (i == ip) ? ai[i][q] : pi;
-                                cr = (i == ic) ? ar[i][q] : cr;
-                                ci = (i == ic) ? ai[i][q] : ci;
-                            }
-                            if (tid == tp) S.prow[q] = cmk(pr, pi);
-                            if (tid == tc) S.rowk[q] = cmk(cr, ci);
-                        }
+                        for (int q = 0; q < W; ++q) S.prow[q] = cmk(ar[i][q], ai[i][q]);
                     }
-                } else {
+                    if (tid == tc && i == ic) {
 #pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        if (tid == tp && i == ip) {
-#pragma unroll
-                            for (int q = 0; q < W; ++q) S.prow[q] = cmk(ar[i][q], ai[i][q]);
-                        }
-                        if (tid == tc && i == ic) {
-#pragma unroll
-                            for (int q = 0; q < W; ++q) S.rowk[q] = cmk(ar[i][q], ai[i][q]);
-                        }
+                        for (int q = 0; q < W; ++q) S.rowk[q] = cmk(ar[i][q], ai[i][q]);
                     }
                 }
                 if (tid == 0) {
@@ -168,37 +204,21 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                     if (zp) S.sing = 1;
                 }
                 __syncthreads();
-                if constexpr (VEC) {
-                    if (tid == tc || (tid == tp && p != col)) {
-                        const bool isc = tid == tc, isp = tid == tp && p != col;
 #pragma unroll
-                        for (int q = 0; q < W; ++q) {
-                            const cpx<T> pv = S.prow[q], cv = S.rowk[q];
+                for (int i = 0; i < R; ++i) {
+                    if (tid == tc && i == ic) {
 #pragma unroll
-                            for (int i = 0; i < R; ++i) {
-                                const bool tc_i = isc && i == ic, tp_i = isp && i == ip;
-                                ar[i][q] = tc_i ? pv.re : (tp_i ? cv.re : ar[i][q]);
-                                ai[i][q] = tc_i ? pv.im : (tp_i ? cv.im : ai[i][q]);
-                            }
-                        }
+                        for (int q = 0; q < W; ++q) { ar[i][q] = S.prow[q].re; ai[i][q] = S.prow[q].im; }
                     }
-                } else {
+                    if (tid == tp && p != col && i == ip) {
 #pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        if (tid == tc && i == ic) {
-#pragma unroll
-                            for (int q = 0; q < W; ++q) { ar[i][q] = S.prow[q].re; ai[i][q] = S.prow[q].im; }
-                        }
-                        if (tid == tp && p != col && i == ip) {
-#pragma unroll
-                            for (int q = 0; q < W; ++q) { ar[i][q] = S.rowk[q].re; ai[i][q] = S.rowk[q].im; }
-                        }
+                        for (int q = 0; q < W; ++q) { ar[i][q] = S.rowk[q].re; ai[i][q] = S.rowk[q].im; }
                     }
                 }
                 const cpx<T> pinv = zp ? cmk((T)0, (T)0) : crcp(S.prow[j]);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PT;
+                    const int row = k0 + tid + i * PT;
                     if (row > col && row < N) {
                         const T lr = ar[i][j] * pinv.re - ai[i][j] * pinv.im;
                         const T li = ar[i][j] * pinv.im + ai[i][j] * pinv.re;
@@ -214,15 +234,20 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                 }
             }
         }
-        // the factored sub-panel back
+        // the sub-panel back (its U rows above and its factored rows), and its
+        // unit-lower diagonal block kept for the later sub-panels
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int row = kc + tid + i * PT;
-            if (row < N) {
+            const int rho = tid + i * PT;
+            if (rho < m) {
 #pragma unroll
                 for (int q = 0; q < W; ++q)
-                    if (q < w) P[(int64_t)(s + q) * N + (row - k0)] = cmk(ar[i][q], ai[i][q]);
+                    if (q < w) P[(int64_t)(s + q) * N + rho] = cmk(ar[i][q], ai[i][q]);
             }
+        }
+        if (s + w < nb && tid >= s && tid < s + W) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) S.Lkeep[s / W][tid - s][q] = cmk(ar[0][q], ai[0][q]);
         }
         // this sub-panel's swaps, in order, on the other columns of the panel
         if (tid < nb && (tid < s || tid >= s + w)) {
@@ -233,78 +258,6 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                     const cpx<T> t1 = Pc[r1];
                     Pc[r1] = Pc[r2];
                     Pc[r2] = t1;
-                }
-            }
-        }
-        const int ncols = nb - s - w;
-        if (ncols > 0) {
-            if (tid < w) {
-#pragma unroll
-                for (int q = 0; q < W; ++q) S.L11s[tid][q] = cmk(ar[0][q], ai[0][q]);
-            }
-            __syncthreads();
-            // U block: rows kc..kc+w-1, columns s+w .. nb-1 (unit-lower solve in LDS)
-            if (tid < ncols) {
-                cpx<T>* Pc = P + (int64_t)(s + w + tid) * N + s;
-#pragma unroll
-                for (int rr = 0; rr < W; ++rr)
-                    if (rr < w) S.Ublk[rr][tid] = Pc[rr];
-                for (int rr = 1; rr < w; ++rr) {
-                    cpx<T> v = S.Ublk[rr][tid];
-                    for (int q = 0; q < rr; ++q) v = cfms(v, S.L11s[rr][q], S.Ublk[q][tid]);
-                    S.Ublk[rr][tid] = v;
-                }
-#pragma unroll
-                for (int rr = 0; rr < W; ++rr)
-                    if (rr < w) Pc[rr] = S.Ublk[rr][tid];
-            }
-            __syncthreads();
-            // rows below the sub-panel: A22 -= L21 U on the panel's remaining columns.
-            // Chunks of CH columns, all R rows of a chunk loaded together.
-            // columns per chunk: CHW / R within the register budget of WPE
-            constexpr int CHW = (WPE > 2) ? (sizeof(T) == 8 ? 8 : 16) : (sizeof(T) == 8 ? 16 : 32);
-            constexpr int CH = CHW / R > 0 ? CHW / R : 1;
-            for (int c0 = 0; c0 < ncols; c0 += CH) {
-                T vr[R][CH], vi[R][CH];
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PT;
-                    const bool ok = row >= kc + w && row < N;
-                    const cpx<T>* Pr = P + (int64_t)(s + w + c0) * N + (row - k0);
-#pragma unroll
-                    for (int cc = 0; cc < CH; ++cc) {
-                        T xr = (T)0, xi = (T)0;
-                        if (ok && c0 + cc < ncols) {
-                            const cpx<T> x = Pr[(int64_t)cc * N];
-                            xr = x.re;
-                            xi = x.im;
-                        }
-                        vr[i][cc] = xr;
-                        vi[i][cc] = xi;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < W; ++q)
-                    if (q < w) {
-#pragma unroll
-                        for (int cc = 0; cc < CH; ++cc) {
-                            const cpx<T> u = S.Ublk[q][min(c0 + cc, NB - 1)];
-#pragma unroll
-                            for (int i = 0; i < R; ++i) {
-                                vr[i][cc] = vr[i][cc] - ar[i][q] * u.re + ai[i][q] * u.im;
-                                vi[i][cc] = vi[i][cc] - ar[i][q] * u.im - ai[i][q] * u.re;
-                            }
-                        }
-                    }
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const int row = kc + tid + i * PT;
-                    if (row >= kc + w && row < N) {
-                        cpx<T>* Pr = P + (int64_t)(s + w + c0) * N + (row - k0);
-#pragma unroll
-                        for (int cc = 0; cc < CH; ++cc)
-                            if (c0 + cc < ncols) Pr[(int64_t)cc * N] = cmk(vr[i][cc], vi[i][cc]);
-                    }
                 }
             }
         }
