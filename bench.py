@@ -81,8 +81,8 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
 # HBM bytes per launch of the trailing update on this workload, from rocprofv3
 # FETCH_SIZE (x2: a 1 GiB copy reads as 0.5 GiB, its 128 B requests counted at
 # 64 B) plus WRITE_SIZE; valid only for the lu.hip source with this sha256.
-UPDATE_TRAFFIC = {"lu_sha256": "c6cdf124826a37b8ca296e8d5eb61500ec01b16ca43e43c8b6403ea167d087ba",
-                  "fp32_refine": 2.623e9, "fp64": 5.419e9}
+UPDATE_TRAFFIC = {"lu_sha256": "8497d02201a439982214b0b70b400b61bb15ca82546a18bd863ad941c63ecbbb",
+                  "fp32_refine": 2.623e9, "fp64": 5.425e9}
 
 
 def update_traffic(mode):
