@@ -45,6 +45,33 @@ __device__ __forceinline__ bool piv_better(T v, int i, T bv, int bi) {
 // written back once: the panel's columns are never rewritten between
 // sub-panels.  R rows per thread and W columns per sub-panel set the register
 // budget, WPE the waves per SIMD.
+// Column q of L_t for the thread's rows (zero for rows at or above lo).
+template <typename T, int R, int PT>
+__device__ __forceinline__ void lazy_load(cpx<T> (&l)[R], const cpx<T>* Lq, int tid, int lo, int m) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int rho = tid + i * PT;
+        l[i] = (rho >= lo && rho < m) ? Lq[i * PT] : cmk((T)0, (T)0);
+    }
+}
+
+// Rows at or below lo: x(row, :) -= l(row) * u(:)
+template <typename T, int R, int W, int PT>
+__device__ __forceinline__ void lazy_update(T (&ar)[R][W], T (&ai)[R][W], const cpx<T> (&l)[R], const cpx<T>* u,
+                                            int tid, int lo, int m) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const cpx<T> uc = u[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (tid + i * PT >= lo && tid + i * PT < m) {
+                ar[i][c] = ar[i][c] - l[i].re * uc.re + l[i].im * uc.im;
+                ai[i][c] = ai[i][c] - l[i].re * uc.im - l[i].im * uc.re;
+            }
+        }
+    }
+}
+
 template <typename T, int W, int PT>
 struct panel_lds {
     cpx<T> X[W][W];             // rows t*W .. t*W+W-1 of the sub-panel (lazy step t)
@@ -100,6 +127,16 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
         for (int t = 0; t < s / W; ++t) {
             const int tb = t * W;
             const int buf = t & 1;
+            // rows below block t: X -= L_t U_t.  L_t is final, so its loads go
+            // out before U_t is formed: FP32 with one row per thread all W
+            // columns, else FP32 one column ahead of the arithmetic and FP64
+            // the first column only (register budgets, measured)
+            const cpx<T>* Lt = P + (int64_t)tb * N + tid;
+            constexpr bool F32 = sizeof(T) == 4;
+            constexpr int PF = (F32 && R == 1) ? W : 1;
+            cpx<T> l[PF][R];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) lazy_load<T, R, PT>(l[q], Lt + (int64_t)q * N, tid, tb + W, m);
             if (wid == 0) {
                 // rows tb .. tb+W-1 are rows i = 0 of lanes tb .. tb+W-1
                 if (lane >= tb && lane < tb + W) {
@@ -124,26 +161,22 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                 }
             }
             __syncthreads();
-            // rows below block t: X -= L_t U_t, one column of L_t at a time
-            // with R loads in flight
-            const cpx<T>* Lt = P + (int64_t)tb * N + tid;
+            if constexpr (PF == W) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) lazy_update<T, R, W, PT>(ar, ai, l[q], S.U[buf][q], tid, tb + W, m);
+            } else {
 #pragma unroll 1
-            for (int q = 0; q < W; ++q) {
-                cpx<T> l[R];
+                for (int q = 0; q < W; ++q) {
+                    if constexpr (F32) {
+                        // column q + 1 (no rows, so zeros and no loads, after the last)
+                        cpx<T> ln[R];
+                        lazy_load<T, R, PT>(ln, Lt + (int64_t)(q + 1) * N, tid, q + 1 < W ? tb + W : m, m);
+                        lazy_update<T, R, W, PT>(ar, ai, l[0], S.U[buf][q], tid, tb + W, m);
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const int rho = tid + i * PT;
-                    l[i] = (rho >= tb + W && rho < m) ? Lt[(int64_t)q * N + i * PT] : cmk((T)0, (T)0);
-                }
-#pragma unroll
-                for (int c = 0; c < W; ++c) {
-                    const cpx<T> u = S.U[buf][q][c];
-#pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        if (tid + i * PT >= tb + W && tid + i * PT < m) {
-                            ar[i][c] = ar[i][c] - l[i].re * u.re + l[i].im * u.im;
-                            ai[i][c] = ai[i][c] - l[i].re * u.im - l[i].im * u.re;
-                        }
+                        for (int i = 0; i < R; ++i) l[0][i] = ln[i];
+                    } else {
+                        if (q > 0) lazy_load<T, R, PT>(l[0], Lt + (int64_t)q * N, tid, tb + W, m);
+                        lazy_update<T, R, W, PT>(ar, ai, l[0], S.U[buf][q], tid, tb + W, m);
                     }
                 }
             }
