@@ -303,7 +303,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     c->psi_off.assign(S + 1, 0);
     for (int j = 0; j < S; ++j) c->psi_off[j + 1] = c->psi_off[j] + c->Ns[j];
     int maxN = *std::max_element(c->Ns.begin(), c->Ns.end());
-    if ((size_t)maxN * 16 + 8192 > (size_t)lds_limit(c))
+    if ((size_t)maxN * 16 + FHW_SOLVE_STATIC_LDS > (size_t)lds_limit(c))
         return fhw_fail(c, FHW_E_INVALID, "plan: N too large for the LDS-resident solve vector");
 
     // curve coefficients on device, geometry + Kress tables per (curve, distinct N)
@@ -879,7 +879,7 @@ int fhw_lu_solve(fhw_ctx* c, int32_t batch, const int32_t* N, const int64_t* A_o
         if (N[q] < 1 || N[q] > 4096) return fhw_fail(c, FHW_E_INVALID, "lu_solve: need 1 <= N <= 4096");
         maxN = std::max(maxN, N[q]);
     }
-    if ((size_t)maxN * 16 + 8192 > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "lu_solve: N too large");
+    if ((size_t)maxN * 16 + FHW_SOLVE_STATIC_LDS > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "lu_solve: N too large");
     fhw_batch_dev bd;
     int rc = upload_batch(c, batch, N, A_off, piv_off, linv_off, b_off, nullptr, bd, nullptr);
     if (rc) return rc;

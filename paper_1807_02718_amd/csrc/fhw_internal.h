@@ -12,6 +12,8 @@
 
 // Outer LU panel width (columns per panel factorization / trailing update).
 #define FHW_LU_NB 64
+// LDS of the solve kernels beside the N-long solution vector (at most)
+#define FHW_SOLVE_STATIC_LDS 20480
 
 struct fhw_batch_dev {
     // device arrays describing a ragged batch of square matrices

@@ -28,12 +28,12 @@ __device__ __forceinline__ void replay_pivots(zd* xs, const int* piv, int k0, in
 // factorization left it (below).
 // Backward: per panel from the last, subtract U12 * x from the block's rows
 // (one lane per row, waves over columns), multiply by the inverse of U11.
-// WIDE (batches of at most 256 matrices): the diagonal-block products use all
-// 256 threads (4 per row, fully unrolled), shortening each matrix's chain of
-// dependent loads; larger batches keep one thread per row and read only the
-// triangle.
-template <typename T, bool WIDE>
-__global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restrict__ Ns,
+// WIDE (batches of at most 256 matrices): 1024 threads per matrix, and the
+// diagonal-block products use all of them (16 per row, fully unrolled),
+// shortening each matrix's chain of dependent loads; larger batches keep 256
+// threads, one thread per row in the diagonal blocks, reading only the triangle.
+template <typename T, bool WIDE, int TH = WIDE ? 1024 : SOLVE_THREADS>
+__global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
                                                             const int64_t* __restrict__ a_off,
                                                             const int64_t* __restrict__ piv_off,
                                                             const int64_t* __restrict__ linv_off,
@@ -42,9 +42,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
                                                             const int* __restrict__ pivbase,
                                                             const cpx<T>* __restrict__ linvbase, zd* __restrict__ v,
                                                             zd* __restrict__ acc, const int* __restrict__ skip) {
+    static_assert((NB + (TH / 64) * NB) * sizeof(zd) <= FHW_SOLVE_STATIC_LDS, "static LDS of the solve");
     extern __shared__ zd xs[];
     __shared__ zd rhs[NB];
-    __shared__ zd part[SOLVE_THREADS / 64][NB];
+    __shared__ zd part[TH / 64][NB];
     const int b = blockIdx.x;
     if (skip && skip[b]) return;
     const int N = Ns[b];
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
     zd* vb = v + v_off[b];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    for (int i = tid; i < N; i += SOLVE_THREADS) xs[i] = vb[i];
+    for (int i = tid; i < N; i += TH) xs[i] = vb[i];
     const int np = (N + NB - 1) / NB;
     __syncthreads();
     // ---- forward.  Panels were factored in pairs (2q, 2q+1) and panel 2q's
@@ -71,8 +72,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
             {
                 zd sacc = cmk(0.0, 0.0);
 #pragma unroll
-                for (int u = 0; u < NB / 4; ++u) {
-                    const int c = wid * (NB / 4) + u;
+                for (int u = 0; u < NB / (TH / 64); ++u) {
+                    const int c = wid * (NB / (TH / 64)) + u;
                     const cpx<T> l = D[c * NB + lane];
                     if (c < lane && lane < nb) sacc = cfma(sacc, cmk((double)l.re, (double)l.im), xs[k0 + c]);
                 }
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
             if (tid < nb) {
                 zd y = xs[k0 + tid];
 #pragma unroll
-                for (int q = 0; q < SOLVE_THREADS / 64; ++q) y = cadd(y, part[q][tid]);
+                for (int q = 0; q < TH / 64; ++q) y = cadd(y, part[q][tid]);
                 xs[k0 + tid] = y;
             }
             __syncthreads();
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
             if (tid == 0) replay_pivots(xs, piv, k0 + NB, min(NB, N - k0 - NB));
             __syncthreads();
         }
-        for (int i = k0 + nb + tid; i < N; i += SOLVE_THREADS) {
+        for (int i = k0 + nb + tid; i < N; i += TH) {
             const cpx<T>* Li = LU + (int64_t)k0 * N + i;
             // eight independent partial sums: eight loads in flight per thread
             zd s8[8];
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         zd s = cmk(0.0, 0.0);
         if (lane < nb) {
             const cpx<T>* Ur = LU + k0 + lane;
-            constexpr int NW = SOLVE_THREADS / 64;
+            constexpr int NW = TH / 64;
             // four independent partial sums per lane: four loads in flight
             zd s4[4];
 #pragma unroll
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
         if (tid < nb) {
             zd t = xs[k0 + tid];
 #pragma unroll
-            for (int q = 0; q < SOLVE_THREADS / 64; ++q) t = csub(t, part[q][tid]);
+            for (int q = 0; q < TH / 64; ++q) t = csub(t, part[q][tid]);
             rhs[tid] = t;
         }
         __syncthreads();
@@ -170,8 +171,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
             {
                 zd sacc = cmk(0.0, 0.0);
 #pragma unroll
-                for (int u = 0; u < NB / 4; ++u) {
-                    const int c = wid * (NB / 4) + u;
+                for (int u = 0; u < NB / (TH / 64); ++u) {
+                    const int c = wid * (NB / (TH / 64)) + u;
                     const cpx<T> d = D[c * NB + lane];
                     if (c >= lane && c < nb) sacc = cfma(sacc, cmk((double)d.re, (double)d.im), rhs[c]);
                 }
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
             if (tid < nb) {
                 zd y = part[0][tid];
 #pragma unroll
-                for (int q = 1; q < SOLVE_THREADS / 64; ++q) y = cadd(y, part[q][tid]);
+                for (int q = 1; q < TH / 64; ++q) y = cadd(y, part[q][tid]);
                 xs[k0 + tid] = y;
             }
             __syncthreads();
@@ -200,9 +201,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_lu_solve(const int* __restric
     }
     if (acc) {
         zd* ab = acc + v_off[b];
-        for (int i = tid; i < N; i += SOLVE_THREADS) ab[i] = cadd(ab[i], xs[i]);
+        for (int i = tid; i < N; i += TH) ab[i] = cadd(ab[i], xs[i]);
     } else {
-        for (int i = tid; i < N; i += SOLVE_THREADS) vb[i] = xs[i];
+        for (int i = tid; i < N; i += TH) vb[i] = xs[i];
     }
 }
 
@@ -324,9 +325,20 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
                                const int32_t* piv, const void* linv, void* x, void* acc, const int32_t* d_skip,
                                int precision) {
     size_t lds = (size_t)maxN * sizeof(zd);
+    static bool attr = false;
+    if (!attr) {
+        // solution vectors up to N = 4096 (64 KiB) beside the static LDS
+        attr = true;
+        const int dyn = 4096 * (int)sizeof(zd);
+        (void)hipFuncSetAttribute((const void*)k_lu_solve<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        (void)hipFuncSetAttribute((const void*)k_lu_solve<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        (void)hipFuncSetAttribute((const void*)k_lu_solve<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        (void)hipFuncSetAttribute((const void*)k_lu_solve<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    }
 #define FHW_SOLVE(TT, WW)                                                                                     \
-    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.piv_off, \
-                       b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, d_skip)
+    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch), dim3(WW ? 1024 : SOLVE_THREADS), lds, s, b.N, b.a_off,  \
+                       b.piv_off, b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, \
+                       d_skip)
     const bool wide = b.batch <= 256;
     if (precision == FHW_FP64) {
         if (wide) FHW_SOLVE(double, true); else FHW_SOLVE(double, false);
@@ -341,6 +353,13 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
                              const void* g, void* r, double* part, int32_t* count, double* norms, double tol,
                              int32_t* done, int32_t* sweeps, int sweep) {
     size_t lds = (size_t)maxN * sizeof(zd);
+    static bool attr = false;
+    if (!attr) {
+        attr = true;
+        const int dyn = 4096 * (int)sizeof(zd);
+        (void)hipFuncSetAttribute((const void*)k_residual<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        (void)hipFuncSetAttribute((const void*)k_residual<4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    }
     // 256-row blocks when they alone give >= 1024 workgroups, else 64-row blocks
     const bool wide = (int64_t)b.batch * ((maxN + 255) / 256) >= 1024;
     const int rows = wide ? SOLVE_THREADS : SOLVE_THREADS / 4;
