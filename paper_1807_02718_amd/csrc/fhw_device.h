@@ -54,9 +54,20 @@ __device__ __forceinline__ cpx<T> crcp(cpx<T> a) {
 // ---------------------------------------------------------------------------
 // J0, Y0, J1, Y1 for z > 0 in FP64 (tables and regions in bessel_tables.h)
 // ---------------------------------------------------------------------------
+// acc * y + c with the coefficient c as a scalar (SGPR) operand of the
+// three-operand FMA: the compiler's two-operand form needs c in a vector
+// register, which costs two extra vector moves per term for FP64 constants.
+__device__ __forceinline__ double fhw_fma_sc(double acc, double y, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(y), "s"(c));
+    return r;
+}
+
+// Polynomial with compile-time coefficients (fully unrolled)
 __device__ __forceinline__ double fhw_horner(const double* c, int n, double y) {
     double acc = c[n - 1];
-    for (int k = n - 2; k >= 0; --k) acc = fma(acc, y, c[k]);
+#pragma unroll
+    for (int k = n - 2; k >= 0; --k) acc = fhw_fma_sc(acc, y, c[k]);
     return acc;
 }
 
