@@ -111,7 +111,7 @@ def _rand_batch(Ns, seed, dtype=torch.complex128):
     return mats, rhs, flat, b
 
 
-@pytest.mark.parametrize("Ns", [[1, 2, 3, 17, 63, 64, 65, 100, 128, 200, 257], [1100], [2100, 130]])
+@pytest.mark.parametrize("Ns", [[1, 2, 3, 17, 63, 64, 65, 100, 128, 200, 257], [1100], [2100, 130], [4096]])
 def test_lu_random_fp64(ctx, Ns):
     say("lu fp64", Ns)
     mats, rhs, flat, b = _rand_batch(Ns, seed=len(Ns) + Ns[0])
@@ -342,6 +342,24 @@ def test_synthesize_edge_cases(ctx, fhw):
     V = ctx.eval_field(psi, wl.obs)
     with pytest.raises(fhw.FhwError):
         ctx.synthesize(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, wl.times)
+
+
+def test_densities_largest_N(ctx):
+    """N = 4096, the largest order the plan accepts, one frequency: the
+    small-batch solve keeps the whole vector in LDS (64 KiB beside its own
+    17 KiB), in both precisions."""
+    say("densities N = 4096, F = 1")
+    curve, W, N = Wk.kite(), 40.0, 4096
+    omega, kappa = O.frequency_grid(W, 1)
+    eta = O.coupling(kappa)
+    gm = O.geometry(curve, N)
+    ref, _ = O.solve_density(O.assemble(gm, kappa[0], eta[0]), O.rhs_plane_wave(gm, kappa[0], eta[0], (1.0, 0.0)))
+    for precision in ("fp64", "fp32_refine"):
+        ctx.plan(curve, W, 1, N=N, precision=precision, refine_tol=1e-12, refine_max=10)
+        psi, res, sw = ctx.solve_densities(compute_resid=True)
+        err = relmax(psi.cpu().numpy(), ref)
+        say("N = 4096", precision, "err", err, "resid", float(res[0]), "sweeps", int(sw[0]))
+        assert err < 1e-10 and res[0] <= 1e-12
 
 
 def test_single_frequency(ctx):
