@@ -17,6 +17,7 @@
  *                        T1a), sinc scaled-convolution synthesis and the sum
  *                        over windows (eqs. approx, discConv, ukW, final_u;
  *                        T2, T5)
+ *   fhw_run              the three calls above in one
  * plus stage entry points for the same steps on caller buffers.
  *
  * Conventions shared by every call
@@ -193,6 +194,19 @@ typedef struct {
 int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
                    const void* V, int32_t N_r, const double* times, int32_t N_t,
                    double* u);
+
+/* The whole hot path in one call for a plan of one curve (fhw_plan) with its
+ * plane-wave direction: fhw_solve_densities (step F3), fhw_eval_field with
+ * V(r, 0) = 1 (step F5) and fhw_synthesize (F1-F2, T0-T6), in that order on
+ * the context's stream, with the same kernels and results as the three calls.
+ * psi: complex128 [psi_off[F]]; V: complex128 [N_r][2F]; u: doubles [N_r][N_t]
+ * (all device, caller-owned; psi and V are written as by the separate calls).
+ * obs, times, resid, sweeps [host] as in those calls.  Synchronizes.
+ * Errors: FHW_E_STATE without a plan; FHW_E_INVALID for a plan of several
+ * curves or bad arguments; otherwise the first failing step's code. */
+int fhw_run(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win, const double* obs, int32_t N_r,
+            const double* times, int32_t N_t, void* psi, void* V, double* u, double* resid,
+            int32_t* sweeps);
 
 /* ---------------- stage entry points (same kernels, caller buffers) -------- */
 

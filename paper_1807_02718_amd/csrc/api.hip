@@ -755,6 +755,22 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     return FHW_OK;
 }
 
+// The whole hot path of a single-curve plane-wave plan in one call (steps
+// F1-F5, T0-T6): densities, field at the observation points (V(r, 0) = 1,
+// the plane-wave limit) and the time samples, in the order of the separate
+// calls and with the same kernels.
+int fhw_run(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const double* obs, int32_t N_r,
+            const double* times, int32_t N_t, void* psi, void* V, double* u, double* resid, int32_t* sweeps) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "run: no plan");
+    if (c->curves.size() != 1) return fhw_fail(c, FHW_E_INVALID, "run: plans of one curve only");
+    int rc = fhw_solve_densities(c, psi, resid, sweeps, 0);
+    if (rc) return rc;
+    rc = fhw_eval_field(c, psi, obs, N_r, 1.0, V);
+    if (rc) return rc;
+    return fhw_synthesize(c, sig, win, V, N_r, times, N_t, u);
+}
+
 // ----------------------------- stage entry points ---------------------------
 
 int fhw_geometry(fhw_ctx* c, int32_t N, double* geom) {

@@ -80,6 +80,7 @@ def _load():
         "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
         "fhw_eval_field_curve": [vp, i32, vp, _dp, i32, C.c_double, vp],
         "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
+        "fhw_run": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), _dp, i32, _dp, i32, vp, vp, vp, _dp, p_i32],
         "fhw_geometry": [vp, i32, vp],
         "fhw_kress_weights": [vp, i32, vp, vp],
         "fhw_assemble": [vp, i32, i32, vp, p_i64, vp, p_i64],
@@ -102,7 +103,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
-            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
@@ -255,6 +256,27 @@ class Context:
         return u
 
     # -- stage entry points -------------------------------------------------------
+    def run(self, f, t0, dt, H, tau0, obs, times, psi=None, V=None, u=None):
+        """fhw_run: densities, field (V(r, 0) = 1) and time samples in one call.
+        Returns (u, psi, V, resid, sweeps)."""
+        f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
+        sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
+        wn = fhw_windows(float(H), float(tau0))
+        obs_h, obs_p = _host(obs, np.float64)
+        th, tp = _host(times, np.float64)
+        Nr = obs_h.shape[0]
+        if psi is None:
+            psi = torch.empty(int(self.psi_off[-1]), dtype=torch.complex128, device=self.device)
+        if V is None:
+            V = torch.empty((Nr, 2 * self.F), dtype=torch.complex128, device=self.device)
+        if u is None:
+            u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
+        resid = np.zeros(self.S)
+        sweeps = np.zeros(self.S, dtype=np.int32)
+        self._check(_lib.fhw_run(self._h, C.byref(sg), C.byref(wn), obs_p, Nr, tp, len(th), _ptr(psi), _ptr(V),
+                                 _ptr(u), resid.ctypes.data_as(_dp), sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
+        return u, psi, V, resid, sweeps
+
     def geometry(self, N):
         g = torch.empty((9, N), dtype=torch.float64, device=self.device)
         self._check(_lib.fhw_geometry(self._h, int(N), _ptr(g)))

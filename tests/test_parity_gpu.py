@@ -321,6 +321,26 @@ def test_pipeline_kite_chirp_small(ctx):
     assert relmax(u, ref) < 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_run_one_call(ctx, fhw, precision):
+    """fhw_run gives what the three calls give (same kernels, bit for bit) and
+    the oracle's time samples; it refuses a plan of several curves."""
+    say("fhw_run", precision)
+    wl = Wk.circle_pulse()
+    ref_sep = _pipeline(ctx, wl, precision)
+    u, psi, V, resid, sweeps = ctx.run(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, wl.obs, wl.times)
+    u = u.cpu().numpy()
+    assert np.array_equal(u, ref_sep)
+    ref = O.run(wl.curve, wl.W, wl.F, wl.N, wl.direction, wl.signal, wl.H, wl.tau0, wl.obs, wl.times)
+    assert relmax(u, ref) < 1e-10
+    if precision == "fp32_refine":
+        assert np.all(resid <= 1e-14) and np.all(sweeps >= 1)
+    ctx.plan([Wk.circle(1.0), Wk.kite()], wl.W, wl.F, N=64)
+    with pytest.raises(fhw.FhwError) as e:
+        ctx.run(wl.signal.f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, wl.obs, wl.times)
+    assert e.value.code == fhw.FHW_E_INVALID
+
+
 def test_synthesize_edge_cases(ctx, fhw):
     say("synthesize edges")
     wl = Wk.circle_pulse()
