@@ -81,6 +81,10 @@ typedef struct {
     double refine_tol;   /* relative residual target ||g-A psi||/||g|| (FP32)  */
     int32_t refine_max;  /* maximum refinement sweeps (FP32 path)              */
     double direction[2]; /* plane-wave direction p (unit vector)               */
+    int32_t j_first;     /* 0: frequencies j W / F, j = 1..F (the DFT grid of
+                            fhw_eval_field / fhw_synthesize); > 0: the band
+                            (j_first + j) W / F, j = 1..F, for frequency-domain
+                            work only (solves; field and synthesis refuse it) */
 } fhw_problem;
 
 /* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL =

@@ -74,15 +74,51 @@ void free_plan(fhw_ctx* c) {
     for (auto& cv : c->curves)
         if (cv.d_curve) (void)hipFree(cv.d_curve);
     c->curves.clear();
-    void* ptrs[] = {c->A64, c->A32, c->linv, c->piv, c->x, c->r, c->meta, c->d_status,
-                    c->d_norms, c->d_done, c->d_sweeps, c->d_rpart, c->d_rcount};
+    // the large work buffers stay for the next plan (free_workspace)
+    void* ptrs[] = {c->meta, c->d_status, c->d_norms, c->d_done, c->d_sweeps, c->d_rpart, c->d_rcount};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    c->A64 = c->A32 = c->linv = nullptr; c->piv = nullptr; c->x = c->r = nullptr;
     c->meta = nullptr; c->d_status = nullptr; c->d_norms = nullptr; c->d_done = nullptr; c->d_sweeps = nullptr;
     c->d_rpart = nullptr; c->d_rcount = nullptr;
     c->planned = false;
     c->factors_resident = false;
+}
+
+void** workspace_slot(fhw_ctx* c, int k) {
+    void** slots[6] = {&c->A64, &c->A32, &c->linv, (void**)&c->piv, &c->x, &c->r};
+    return slots[k];
+}
+
+void free_workspace(fhw_ctx* c) {
+    for (int k = 0; k < 6; ++k) {
+        void** p = workspace_slot(c, k);
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        c->ws_cap[k] = 0;
+    }
+}
+
+// The six large work buffers of a plan (bytes in need[]), reusing those of the
+// previous plan that are big enough: a stream of plans (one per request, say)
+// then allocates only when it outgrows them.  If what would be kept plus what
+// must grow exceeds the budget, everything is released and allocated afresh.
+int ensure_workspace(fhw_ctx* c, const size_t need[6]) {
+    size_t keep = 0, grow = 0;
+    for (int k = 0; k < 6; ++k) {
+        if (need[k] <= c->ws_cap[k]) keep += c->ws_cap[k];
+        else grow += need[k];
+    }
+    if (grow > 0 && keep + grow > c->budget) free_workspace(c);
+    for (int k = 0; k < 6; ++k) {
+        if (need[k] == 0 || need[k] <= c->ws_cap[k]) continue;
+        void** p = workspace_slot(c, k);
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        c->ws_cap[k] = 0;
+        FHW_HIP(c, hipMalloc(p, need[k]));
+        c->ws_cap[k] = need[k];
+    }
+    return FHW_OK;
 }
 
 int lds_limit(fhw_ctx* c) {
@@ -212,6 +248,7 @@ int fhw_destroy(fhw_ctx* c) {
     if (!c) return FHW_OK;
     (void)hipStreamSynchronize(c->stream);
     free_plan(c);
+    free_workspace(c);
     if (c->scratch) (void)hipFree(c->scratch);
     for (auto& r : c->prof.recs) {
         (void)hipEventDestroy(r.a);
@@ -240,6 +277,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         return fhw_fail(c, FHW_E_INVALID, "plan: unknown precision");
     if (!isfinite(p->direction[0]) || !isfinite(p->direction[1]))
         return fhw_fail(c, FHW_E_INVALID, "plan: direction not finite");
+    if (p->j_first < 0) return fhw_fail(c, FHW_E_INVALID, "plan: j_first must be >= 0");
     (void)hipStreamSynchronize(c->stream);
     free_plan(c);
     c->prob = *p;
@@ -283,7 +321,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     for (int k = 0; k < n_curves; ++k)
         for (int j = 0; j < F; ++j) {
             const int sy = k * F + j;
-            double om = dw * (double)(j + 1);
+            double om = dw * (double)(p->j_first + j + 1);
             c->kappa[sy] = om / p->c;
             c->eta[sy] = std::max(c->kappa[sy], 1.0);
             int N;
@@ -378,12 +416,13 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     }
     wsA32 = prec == FHW_FP32_REFINE ? wsA64 : 0;
     c->chunk = maxcount;
-    FHW_HIP(c, hipMalloc(&c->A64, wsA64 * 16));
-    if (wsA32) FHW_HIP(c, hipMalloc(&c->A32, wsA32 * 8));
-    FHW_HIP(c, hipMalloc(&c->linv, wsL * (prec == FHW_FP64 ? 16 : 8)));
-    FHW_HIP(c, hipMalloc((void**)&c->piv, wsP * 4));
-    FHW_HIP(c, hipMalloc(&c->x, wsV * 16));   // g
-    FHW_HIP(c, hipMalloc(&c->r, wsV * 16));   // residual / correction
+    {
+        // A64, A32 (FP32 path), linv, piv, x (g), r (residual / correction)
+        const size_t need[6] = {wsA64 * 16, wsA32 * 8, wsL * (prec == FHW_FP64 ? 16 : 8), wsP * 4, wsV * 16,
+                                wsV * 16};
+        int rc = ensure_workspace(c, need);
+        if (rc) return rc;
+    }
     FHW_HIP(c, hipMalloc((void**)&c->d_status, sizeof(int32_t) * 4));
     FHW_HIP(c, hipMalloc((void**)&c->d_norms, sizeof(double) * 2 * S));
     FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * S));
@@ -663,6 +702,7 @@ int fhw_eval_field_curve(fhw_ctx* c, int32_t curve, const void* psi, const doubl
                          double zero_value, void* V) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field: no plan");
+    if (c->prob.j_first != 0) return fhw_fail(c, FHW_E_STATE, "field: the plan is a band (j_first > 0)");
     if (curve < 0 || curve >= (int)c->curves.size()) return fhw_fail(c, FHW_E_INVALID, "field: no such curve");
     if (N_r < 0 || (N_r > 0 && (!psi || !obs || !V))) return fhw_fail(c, FHW_E_INVALID, "field: bad arguments");
     if (N_r == 0) return FHW_OK;
@@ -685,6 +725,7 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
                    const double* times, int32_t N_t, double* u) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize: no plan");
+    if (c->prob.j_first != 0) return fhw_fail(c, FHW_E_STATE, "synthesize: the plan is a band (j_first > 0)");
     if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize: bad arguments");
     if (N_r == 0 || N_t == 0) return FHW_OK;
     if (!V || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))

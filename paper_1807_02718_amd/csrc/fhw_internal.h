@@ -89,6 +89,9 @@ struct fhw_ctx {
     int32_t* piv = nullptr;
     void* x = nullptr;                 // complex128 work vectors [chunk rhs]
     void* r = nullptr;                 // complex128 residual vectors
+    // bytes allocated for A64, A32, linv, piv, x, r: these outlive a plan, and
+    // a new plan reallocates only the ones it outgrows
+    size_t ws_cap[6] = {0, 0, 0, 0, 0, 0};
     void* meta = nullptr;              // per-chunk device metadata
     size_t meta_bytes = 0;
     int32_t* d_status = nullptr;       // [0]: singular flag, [1..]: per-matrix flags

@@ -41,7 +41,7 @@ class fhw_problem(C.Structure):
     _fields_ = [("W", C.c_double), ("F", C.c_int32), ("c", C.c_double), ("N_fixed", C.c_int32),
                 ("ppw", C.c_double), ("n_min", C.c_int32), ("n_mult", C.c_int32), ("n_cap", C.c_int32),
                 ("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_max", C.c_int32),
-                ("direction", C.c_double * 2)]
+                ("direction", C.c_double * 2), ("j_first", C.c_int32)]
 
 
 class fhw_signal(C.Structure):
@@ -164,8 +164,9 @@ class Context:
 
     # -- plan -----------------------------------------------------------------
     def plan(self, curve, W, F, N=None, c=1.0, ppw=10.0, n_min=64, n_mult=32, n_cap=4096, precision="fp64",
-             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0)):
+             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0), j_first=0):
         """Plan one curve, or several (a list: fhw_plan_curves, system s = k F + j).
+        j_first > 0 plans the band (j_first + j) W / F, j = 1..F (solves only).
         Returns (N per system, psi offsets)."""
         many = isinstance(curve, (list, tuple))
         curves = list(curve) if many else [curve]
@@ -181,6 +182,7 @@ class Context:
         pr.precision = {"fp64": FHW_FP64, "fp32_refine": FHW_FP32_REFINE}[precision]
         pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
         pr.direction[0], pr.direction[1] = float(direction[0]), float(direction[1])
+        pr.j_first = int(j_first)
         S = len(curves) * int(F)
         Ns = np.zeros(S, dtype=np.int32)
         off = np.zeros(S + 1, dtype=np.int64)

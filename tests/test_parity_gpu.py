@@ -565,6 +565,51 @@ def test_plan_curves_star_batch(ctx, precision):
         assert relmax(psi2[0, off[s]:off[s + 1]].cpu().numpy(), ref) < 1e-11
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_band_plan(ctx, fhw, precision):
+    """j_first > 0: the band (j_first + j) W/F, j = 1..F, solved for several
+    plane waves; densities against the oracle; field and synthesis refuse it."""
+    say("band plan", precision)
+    curve, N, dw, j_first, F = Wk.kite(), 192, 1.0, 30, 6
+    Ns, off = ctx.plan(curve, F * dw, F, N=N, precision=precision, refine_tol=1e-12, refine_max=10, j_first=j_first)
+    dirs = [(1.0, 0.0), (0.0, 1.0), (0.6, -0.8)]
+    psi, res, sw = ctx.solve_incidences([("plane", d) for d in dirs])
+    psi = psi.cpu().numpy()
+    gm = O.geometry(curve, N)
+    for j in (0, F - 1):
+        kappa = (j_first + j + 1) * dw
+        eta = O.coupling(np.array([kappa]))[0]
+        A = O.assemble(gm, kappa, eta)
+        for q, d in enumerate(dirs):
+            ref, _ = O.solve_density(A, O.rhs_plane_wave(gm, kappa, eta, d))
+            assert relmax(psi[q, off[j]:off[j + 1]], ref) < 1e-11, (j, q)
+    with pytest.raises(fhw.FhwError) as e:
+        ctx.eval_field(torch.as_tensor(psi[0], device="cuda"), Wk.ring(4, 3.0))
+    assert e.value.code == fhw.FHW_E_STATE
+
+
+def test_workspace_reused_across_plans(fhw):
+    """A stream of plans of different sizes and precisions on one context
+    (the workspace kept and regrown) gives what fresh contexts give."""
+    say("workspace reuse across plans")
+    cases = [(Wk.kite(), 30.0, 8, 256, "fp32_refine"), (Wk.circle(1.0), 10.0, 4, 64, "fp64"),
+             (Wk.kite(), 40.0, 12, 384, "fp32_refine"), (Wk.kite(), 20.0, 5, 128, "fp64")]
+    c = fhw.Context()
+    try:
+        for curve, W, F, N, prec in cases:
+            c.plan(curve, W, F, N=N, precision=prec, refine_tol=1e-12, refine_max=10)
+            psi, _, _ = c.solve_densities()
+            f = fhw.Context()
+            try:
+                f.plan(curve, W, F, N=N, precision=prec, refine_tol=1e-12, refine_max=10)
+                psi_f, _, _ = f.solve_densities()
+            finally:
+                f.close()
+            assert torch.equal(psi, psi_f), (W, F, N, prec)
+    finally:
+        c.close()
+
+
 def test_budget_too_small(fhw):
     """A workspace budget below one frequency's needs is FHW_E_NOMEM at plan
     time, and the context stays usable."""
