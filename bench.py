@@ -160,6 +160,61 @@ def star_batch_bench(fhw, torch, sb, steps, warmup):
                       "stages_ms_per_step": {k: v[0] / steps for k, v in prof.items()}}), flush=True)
 
 
+def serve_bench(fhw, torch, Wk, rates, duration, max_wait, precision):
+    """The serving configuration, one request at a time in arrival order
+    (FIFO) on one context: per request a band plan of its curve, N and
+    frequencies (the workspace is reused across plans) and one
+    fhw_solve_incidences for its plane waves.  A request still waiting
+    max_wait seconds after its arrival when it reaches the head of the queue
+    is refused.  Latency = completion - arrival (queueing included); host
+    wall clock, each solve call synchronizes."""
+    out = []
+    ctx = fhw.Context()
+    try:
+        for rate in rates:
+            curves, reqs = Wk.serve_requests(rate, duration)
+            # warm-up outside the clock: the largest plan of the stream, so
+            # that no request pays a workspace allocation
+            big = max(reqs, key=lambda r: r["N"] * r["N"] * r["F"])
+            ctx.plan(curves[big["curve"]], big["F"] * 1.0, big["F"], N=big["N"], precision=precision,
+                     refine_tol=1e-12, refine_max=10, j_first=big["j_first"])
+            ctx.solve_incidences([("plane", d) for d in big["dirs"][:1]])
+            torch.cuda.synchronize()
+            lat, wait, service, refused, solves = [], [], 0.0, 0, 0
+            t0 = time.perf_counter()
+            for r in reqs:
+                arr = t0 + r["t"]
+                while time.perf_counter() < arr:
+                    time.sleep(max(0.0, min(arr - time.perf_counter(), 1e-3)))
+                start = time.perf_counter()
+                if start - arr > max_wait:
+                    refused += 1
+                    continue
+                ctx.plan(curves[r["curve"]], r["F"] * 1.0, r["F"], N=r["N"], precision=precision,
+                         refine_tol=1e-12, refine_max=10, j_first=r["j_first"])
+                ctx.solve_incidences([("plane", d) for d in r["dirs"]])
+                end = time.perf_counter()
+                lat.append(end - arr)
+                wait.append(start - arr)
+                service += end - start
+                solves += r["F"] * len(r["dirs"])
+            wall = time.perf_counter() - t0
+            q = lambda a, p: float(np.percentile(np.asarray(a) * 1e3, p)) if a else None
+            out.append({"rate": rate, "offered": len(reqs), "completed": len(lat), "refused": refused,
+                        "goodput_req_s": len(lat) / wall, "rhs_solves_per_s": solves / wall,
+                        "p50_ms": q(lat, 50), "p99_ms": q(lat, 99), "mean_wait_ms": float(np.mean(wait) * 1e3) if wait else None,
+                        "mean_service_ms": 1e3 * service / max(len(lat), 1), "busy": service / wall, "wall_s": wall})
+            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    finally:
+        ctx.close()
+    print(json.dumps({"metric": "serving: per-request latency (p50/p99) and goodput under Poisson arrivals",
+                      "workload": "16 star curves; bands of 10-50 frequencies on (0, 300], N 256-4096, 1-64 plane "
+                                  "waves per request; FIFO, one request at a time",
+                      "precision": precision, "duration_s": duration, "max_wait_s": max_wait,
+                      "factor_cache": "none (requests repeat a (curve, band, N) with negligible probability)",
+                      "rates": out}), flush=True)
+
+
 def cpu_baseline(wl, n_freq):
     """The FP64 oracle on a bounded sample: n_freq frequencies spread over the
     band, each = assembly + LAPACK solve + field at all observation points."""
@@ -192,8 +247,12 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=50, help="isolated-solve latency samples (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
-    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars"],
-                    help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch")
+    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve"],
+                    help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
+                         "serve: Poisson request stream (per-request latency)")
+    ap.add_argument("--rates", default="5,10,20,50", help="serve: arrival rates (requests/s)")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--max-wait", type=float, default=2.0, help="serve: refuse requests queued longer (s)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -208,6 +267,10 @@ def main():
     from paper_1807_02718_amd import fhw
     if a.workload == "stars":
         star_batch_bench(fhw, torch, Wk.star_batch(), a.steps, a.warmup)
+        return
+    if a.workload == "serve":
+        serve_bench(fhw, torch, Wk, [float(x) for x in a.rates.split(",")], a.duration, a.max_wait,
+                    a.modes.split(",")[0])
         return
 
     wl = Wk.kite_n1024(F=a.freqs)

@@ -46,7 +46,7 @@ size_t freq_bytes(int32_t N, int precision) {
     if (precision == FHW_FP32_REFINE) b += NN * 8;             // FP32 factors
     b += (size_t)linv_elems(N) * (precision == FHW_FP64 ? 16 : 8);
     b += (size_t)N * 4;                                       // pivots
-    b += (size_t)N * 16 * 2;                                  // g, r
+    b += (size_t)N * 16 * 2 * FHW_INC_GROUP;                  // g, r per incidence of a group
     b += 256;                                                 // metadata
     return b;
 }
@@ -418,8 +418,8 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     c->chunk = maxcount;
     {
         // A64, A32 (FP32 path), linv, piv, x (g), r (residual / correction)
-        const size_t need[6] = {wsA64 * 16, wsA32 * 8, wsL * (prec == FHW_FP64 ? 16 : 8), wsP * 4, wsV * 16,
-                                wsV * 16};
+        const size_t need[6] = {wsA64 * 16, wsA32 * 8, wsL * (prec == FHW_FP64 ? 16 : 8), wsP * 4,
+                                wsV * 16 * FHW_INC_GROUP, wsV * 16 * FHW_INC_GROUP};
         int rc = ensure_workspace(c, need);
         if (rc) return rc;
     }
@@ -428,9 +428,11 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * S));
     FHW_HIP(c, hipMalloc((void**)&c->d_sweeps, sizeof(int32_t) * S));
     // residual: per-block partial norms and per-matrix block counters (zero)
-    FHW_HIP(c, hipMalloc((void**)&c->d_rpart, sizeof(double) * 2 * (size_t)maxcount * ((maxN + 63) / 64)));
-    FHW_HIP(c, hipMalloc((void**)&c->d_rcount, sizeof(int32_t) * (size_t)maxcount));
-    FHW_HIP(c, hipMemset(c->d_rcount, 0, sizeof(int32_t) * (size_t)maxcount));
+    c->ws_vec = (int64_t)wsV;
+    c->rpart_stride = 2 * (int64_t)maxcount * ((maxN + 63) / 64);
+    FHW_HIP(c, hipMalloc((void**)&c->d_rpart, sizeof(double) * (size_t)c->rpart_stride * FHW_INC_GROUP));
+    FHW_HIP(c, hipMalloc((void**)&c->d_rcount, sizeof(int32_t) * (size_t)maxcount * FHW_INC_GROUP));
+    FHW_HIP(c, hipMemset(c->d_rcount, 0, sizeof(int32_t) * (size_t)maxcount * FHW_INC_GROUP));
     c->ws_A64 = wsA64; c->ws_A32 = wsA32; c->ws_linv = wsL; c->ws_piv = wsP;
 
     // per-chunk metadata, built once and uploaded into one buffer
@@ -583,24 +585,50 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
                                         p.precision, &c->prof));
         }
-        for (int q = 0; q < n_inc; ++q) {
-            zd* x = psid + q * total + ch.psi_base;     // solution written in place into psi
-            if (inc)
-                STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, inc[q].kind, inc[q].v[0],
-                                                  inc[q].v[1], g));
-            FHW_HIP(c, hipMemcpyAsync(x, g, sizeof(zd) * ch.vec_elems, hipMemcpyDeviceToDevice, c->stream));
-            STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, ch.maxN, LU, c->piv, c->linv, x, nullptr, p.precision));
+        // incidences in groups of up to FHW_INC_GROUP: one launch per step for
+        // the whole group (a second grid dimension), each incidence with its
+        // own slot of g and r and its own densities, norms and flags
+        const int64_t sv = c->ws_vec;
+        const int64_t maxc = c->chunk;
+        for (int q0 = 0; q0 < n_inc; q0 += FHW_INC_GROUP) {
+            const int G = std::min(FHW_INC_GROUP, n_inc - q0);
+            zd* x = psid + q0 * total + ch.psi_base;     // solutions written in place into psi
+            if (inc) {
+                fhw_rhs_group rg{};
+                rg.n = G;
+                for (int q = 0; q < G; ++q) {
+                    rg.kind[q] = inc[q0 + q].kind;
+                    rg.v[q][0] = inc[q0 + q].v[0];
+                    rg.v[q][1] = inc[q0 + q].v[1];
+                }
+                STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, rg, sv, g));
+            }
+            for (int q = 0; q < G; ++q)
+                FHW_HIP(c, hipMemcpyAsync(x + q * total, g + q * sv, sizeof(zd) * ch.vec_elems,
+                                          hipMemcpyDeviceToDevice, c->stream));
+            fhw_grp gs;
+            gs.n = G;
+            gs.sv = total;
+            STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, ch.maxN, LU, c->piv, c->linv, x, nullptr,
+                                                      p.precision, gs));
             if (!fp32) continue;
-            double* norms = d_norms + 2 * ((int64_t)q * F + ch.j0);
-            int32_t* done = d_done + (int64_t)q * F + ch.j0;
-            int32_t* sw = d_sw + (int64_t)q * F + ch.j0;
+            double* norms = d_norms + 2 * ((int64_t)q0 * F + ch.j0);
+            int32_t* done = d_done + (int64_t)q0 * F + ch.j0;
+            int32_t* sw = d_sw + (int64_t)q0 * F + ch.j0;
+            fhw_grp gr;   // residual: x in psi, g and r in their slots
+            gr.n = G;
+            gr.sx = total; gr.sg = sv; gr.sr = sv;
+            gr.spart = c->rpart_stride; gr.scount = maxc; gr.snorm = 2 * (int64_t)F; gr.sflag = F;
+            fhw_grp ga;   // correction: solve r in place, add into x, skip converged
+            ga.n = G;
+            ga.sv = sv; ga.sacc = total; ga.sflag = F;
             const int maxs = std::max(0, p.refine_max);
             for (int it = 0; it <= maxs; ++it) {
                 STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, c->d_rpart,
-                                                               c->d_rcount, norms, p.refine_tol, done, sw, it));
+                                                               c->d_rcount, norms, p.refine_tol, done, sw, it, gr));
                 if (it == maxs) break;
                 STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, ch.maxN, LU, c->piv, c->linv, r, x, done,
-                                               p.precision));
+                                                              p.precision, ga));
             }
         }
         if (!fp32 && compute_resid) {
@@ -608,14 +636,26 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             // (which also ends the residency of the FP64 factors)
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
                                               p.direction[0], p.direction[1], c->A64, nullptr, g));
-            for (int q = 0; q < n_inc; ++q) {
-                if (inc)
-                    STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, inc[q].kind, inc[q].v[0],
-                                                      inc[q].v[1], g));
-                double* norms = d_norms + 2 * ((int64_t)q * F + ch.j0);
-                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, psid + q * total + ch.psi_base,
-                                                               g, r, c->d_rpart, c->d_rcount, norms, 0.0, nullptr,
-                                                               nullptr, 0));
+            for (int q0 = 0; q0 < n_inc; q0 += FHW_INC_GROUP) {
+                const int G = std::min(FHW_INC_GROUP, n_inc - q0);
+                if (inc) {
+                    fhw_rhs_group rg{};
+                    rg.n = G;
+                    for (int q = 0; q < G; ++q) {
+                        rg.kind[q] = inc[q0 + q].kind;
+                        rg.v[q][0] = inc[q0 + q].v[0];
+                        rg.v[q][1] = inc[q0 + q].v[1];
+                    }
+                    STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, rg, sv, g));
+                }
+                double* norms = d_norms + 2 * ((int64_t)q0 * F + ch.j0);
+                fhw_grp gr;
+                gr.n = G;
+                gr.sx = total; gr.sg = sv; gr.sr = sv;
+                gr.spart = c->rpart_stride; gr.scount = maxc; gr.snorm = 2 * (int64_t)F;
+                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64,
+                                                               psid + q0 * total + ch.psi_base, g, r, c->d_rpart,
+                                                               c->d_rcount, norms, 0.0, nullptr, nullptr, 0, gr));
             }
         }
     }

@@ -154,14 +154,19 @@ int64_t assemble_blocks_for(int32_t N) {
     return T * (T + 1) / 2;
 }
 
-// Boundary data g = dB/dnu - i eta B of eq. CFIE_direct for one incidence at
-// every node of each frequency (one workgroup per frequency):
+// Boundary data g = dB/dnu - i eta B of eq. CFIE_direct for a group of
+// incidences at every node of each frequency (one workgroup per frequency and
+// incidence):
 //   plane wave   B = exp(i kappa p.x):  g = i (kappa p.nu - eta) exp(i kappa p.x)
 //   point source B = (i/4) H0(kappa rho), rho = |x - r0|, r0 outside the curve:
 //                dB/dnu = -(i kappa / 4) H1(kappa rho) nu.(x - r0) / rho
-__global__ __launch_bounds__(ASM_THREADS) void k_rhs(const fhw_assemble_item* __restrict__ items, int kind,
-                                                     double v0, double v1, zd* __restrict__ g) {
+__global__ __launch_bounds__(ASM_THREADS) void k_rhs(const fhw_assemble_item* __restrict__ items, fhw_rhs_group rg,
+                                                     int64_t sg, zd* __restrict__ g) {
     const fhw_assemble_item it = items[blockIdx.x];
+    const int q = blockIdx.y;   // incidence of the group
+    const int kind = rg.kind[q];
+    const double v0 = rg.v[q][0], v1 = rg.v[q][1];
+    g += (int64_t)q * sg;
     const int N = it.N;
     const double kappa = it.kappa, eta = it.eta;
     const double* x1 = it.geom;
@@ -189,9 +194,10 @@ __global__ __launch_bounds__(ASM_THREADS) void k_rhs(const fhw_assemble_item* __
     }
 }
 
-hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n_items, int32_t kind, double v0,
-                      double v1, void* g) {
-    if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rhs, dim3(n_items), dim3(ASM_THREADS), 0, s, d_items, kind, v0, v1, (zd*)g);
+hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n_items, const fhw_rhs_group& rg,
+                      int64_t sg, void* g) {
+    if (n_items <= 0 || rg.n <= 0) return hipSuccess;
+    if (rg.n > FHW_INC_GROUP) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rhs, dim3(n_items, rg.n), dim3(ASM_THREADS), 0, s, d_items, rg, sg, (zd*)g);
     return hipGetLastError();
 }

@@ -87,8 +87,10 @@ struct fhw_ctx {
     void* A32 = nullptr;               // complex64 copies (FP32 path)
     void* linv = nullptr;              // inverse diagonal blocks (factor type)
     int32_t* piv = nullptr;
-    void* x = nullptr;                 // complex128 work vectors [chunk rhs]
-    void* r = nullptr;                 // complex128 residual vectors
+    void* x = nullptr;                 // complex128 boundary data g [FHW_INC_GROUP][chunk vectors]
+    void* r = nullptr;                 // complex128 residuals [FHW_INC_GROUP][chunk vectors]
+    int64_t ws_vec = 0;                // elements of one incidence's slot in x and r
+    int64_t rpart_stride = 0;          // doubles of one incidence's residual partial norms
     // bytes allocated for A64, A32, linv, piv, x, r: these outlive a plan, and
     // a new plan reallocates only the ones it outgrows
     size_t ws_cap[6] = {0, 0, 0, 0, 0, 0};
@@ -97,8 +99,8 @@ struct fhw_ctx {
     int32_t* d_status = nullptr;       // [0]: singular flag, [1..]: per-matrix flags
     size_t status_len = 0;
     double* d_norms = nullptr;         // [chunk][2] residual norms
-    double* d_rpart = nullptr;         // residual partial norms [chunk][blocks][2]
-    int32_t* d_rcount = nullptr;       // residual block counters [chunk] (kept zero)
+    double* d_rpart = nullptr;         // residual partial norms [FHW_INC_GROUP][chunk][blocks][2]
+    int32_t* d_rcount = nullptr;       // residual block counters [FHW_INC_GROUP][chunk] (kept zero)
     int32_t* d_done = nullptr;         // [chunk]
     int32_t* d_sweeps = nullptr;       // [chunk]
 
@@ -139,8 +141,24 @@ hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_item
 int64_t assemble_blocks_for(int32_t N);
 // boundary data of one incidence (FHW_INC_PLANE: v = p; FHW_INC_POINT: v = r0)
 // for every item, written at g + g_off
-hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n_items, int32_t kind, double v0,
-                      double v1, void* g);
+// Incidences solved together: one more grid dimension over up to
+// FHW_INC_GROUP incidences, each buffer advanced by its stride (elements).
+#define FHW_INC_GROUP 8
+struct fhw_grp {
+    int32_t n = 1;
+    int64_t sv = 0, sacc = 0, sflag = 0;      // solve: vector, accumulator; skip / done / sweeps flags
+    int64_t sx = 0, sg = 0, sr = 0;           // residual: x, g, r
+    int64_t spart = 0, scount = 0, snorm = 0; // residual: partial norms, block counters, norms
+};
+struct fhw_rhs_group {
+    int32_t n;
+    int32_t kind[FHW_INC_GROUP];
+    double v[FHW_INC_GROUP][2];
+};
+// boundary data of n incidences (FHW_INC_PLANE: v = p; FHW_INC_POINT: v = r0)
+// for every item, incidence q written at g + q sg + g_off
+hipError_t launch_rhs(hipStream_t s, const fhw_assemble_item* d_items, int32_t n_items, const fhw_rhs_group& rg,
+                      int64_t sg, void* g);
 
 // --- lu.hip -----------------------------------------------------------------
 // One launch of the batched factorization.  Panels go in pairs (2q, 2q+1):
@@ -165,19 +183,23 @@ void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch);
 hipError_t launch_lu_factor(hipStream_t s, const fhw_batch_dev& b, const fhw_lu_sched& sch,
                             const int32_t* d_prefix, void* A, int32_t* piv, void* linv,
                             int32_t* d_status, int precision, fhw_prof* prof);
+// grp (default: one incidence) gives the incidence count and the strides
+// sv (x), sacc (acc), sflag (d_skip)
 hipError_t launch_lu_solve(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU,
                            const int32_t* piv, const void* linv, void* x, const int32_t* d_skip,
-                           int precision);
+                           int precision, const fhw_grp& grp = fhw_grp());
 // as launch_lu_solve, but when acc != NULL adds the solution into acc (same
 // offsets) and leaves x holding its input
 hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU,
                                const int32_t* piv, const void* linv, void* x, void* acc,
-                               const int32_t* d_skip, int precision);
+                               const int32_t* d_skip, int precision, const fhw_grp& grp = fhw_grp());
 // part: 2 * batch * ceil(maxN/64) doubles of scratch; count: batch ints, zero
-// before the first call (each call leaves them zero)
+// before the first call (each call leaves them zero); per incidence of grp
+// at strides spart, scount (x, g, r, norms, done/sweeps: sx, sg, sr, snorm, sflag)
 hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64,
                              const void* x, const void* g, void* r, double* part, int32_t* count,
-                             double* norms, double tol, int32_t* done, int32_t* sweeps, int sweep);
+                             double* norms, double tol, int32_t* done, int32_t* sweeps, int sweep,
+                             const fhw_grp& grp = fhw_grp());
 hipError_t launch_convert_c128_c64(hipStream_t s, const void* src, void* dst, int64_t n);
 
 // --- field.hip --------------------------------------------------------------

@@ -41,12 +41,19 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
                                                             const cpx<T>* __restrict__ LUbase,
                                                             const int* __restrict__ pivbase,
                                                             const cpx<T>* __restrict__ linvbase, zd* __restrict__ v,
-                                                            zd* __restrict__ acc, const int* __restrict__ skip) {
+                                                            zd* __restrict__ acc, const int* __restrict__ skip,
+                                                            fhw_grp grp) {
     static_assert((NB + (TH / 64) * NB) * sizeof(zd) <= FHW_SOLVE_STATIC_LDS, "static LDS of the solve");
     extern __shared__ zd xs[];
     __shared__ zd rhs[NB];
     __shared__ zd part[TH / 64][NB];
     const int b = blockIdx.x;
+    {
+        const int q = blockIdx.y;   // incidence of the group
+        v += q * grp.sv;
+        if (acc) acc += q * grp.sacc;
+        if (skip) skip += q * grp.sflag;
+    }
     if (skip && skip[b]) return;
     const int N = Ns[b];
     const cpx<T>* LU = LUbase + a_off[b];
@@ -225,8 +232,19 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
                                                             double* __restrict__ part, int* __restrict__ count,
                                                             int nblk_max, double* __restrict__ norms, double tol,
                                                             int* __restrict__ done, int* __restrict__ sweeps,
-                                                            int sweep) {
+                                                            int sweep, fhw_grp grp) {
     constexpr int RES_ROWS = SOLVE_THREADS / PH;
+    {
+        const int q = blockIdx.z;   // incidence of the group
+        x += q * grp.sx;
+        g += q * grp.sg;
+        r += q * grp.sr;
+        part += q * grp.spart;
+        count += q * grp.scount;
+        norms += q * grp.snorm;
+        if (done) done += q * grp.sflag;
+        if (sweeps) sweeps += q * grp.sflag;
+    }
     extern __shared__ zd xs[];
     __shared__ zd cs[PH][RES_ROWS];
     __shared__ double wred[2][RES_ROWS / 64];
@@ -317,13 +335,14 @@ __global__ void k_c128_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, 
 }
 
 hipError_t launch_lu_solve(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU, const int32_t* piv,
-                           const void* linv, void* x, const int32_t* d_skip, int precision) {
-    return launch_lu_solve_acc(s, b, maxN, LU, piv, linv, x, nullptr, d_skip, precision);
+                           const void* linv, void* x, const int32_t* d_skip, int precision, const fhw_grp& grp) {
+    return launch_lu_solve_acc(s, b, maxN, LU, piv, linv, x, nullptr, d_skip, precision, grp);
 }
 
 hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* LU,
                                const int32_t* piv, const void* linv, void* x, void* acc, const int32_t* d_skip,
-                               int precision) {
+                               int precision, const fhw_grp& grp) {
+    if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
     static bool attr = false;
     if (!attr) {
@@ -336,9 +355,9 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
         (void)hipFuncSetAttribute((const void*)k_lu_solve<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     }
 #define FHW_SOLVE(TT, WW)                                                                                     \
-    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch), dim3(WW ? 1024 : SOLVE_THREADS), lds, s, b.N, b.a_off,  \
-                       b.piv_off, b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, \
-                       d_skip)
+    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch, grp.n), dim3(WW ? 1024 : SOLVE_THREADS), lds, s, b.N,   \
+                       b.a_off, b.piv_off, b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x,  \
+                       (zd*)acc, d_skip, grp)
     const bool wide = b.batch <= 256;
     if (precision == FHW_FP64) {
         if (wide) FHW_SOLVE(double, true); else FHW_SOLVE(double, false);
@@ -351,7 +370,8 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
 
 hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64, const void* x,
                              const void* g, void* r, double* part, int32_t* count, double* norms, double tol,
-                             int32_t* done, int32_t* sweeps, int sweep) {
+                             int32_t* done, int32_t* sweeps, int sweep, const fhw_grp& grp) {
+    if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
     static bool attr = false;
     if (!attr) {
@@ -361,17 +381,17 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
         (void)hipFuncSetAttribute((const void*)k_residual<4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     }
     // 256-row blocks when they alone give >= 1024 workgroups, else 64-row blocks
-    const bool wide = (int64_t)b.batch * ((maxN + 255) / 256) >= 1024;
+    const bool wide = (int64_t)b.batch * grp.n * ((maxN + 255) / 256) >= 1024;
     const int rows = wide ? SOLVE_THREADS : SOLVE_THREADS / 4;
     const int nblk = (maxN + rows - 1) / rows;
     if (wide)
-        hipLaunchKernelGGL(k_residual<1>, dim3(b.batch, nblk), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.v_off,
-                           (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,
-                           sweeps, sweep);
+        hipLaunchKernelGGL(k_residual<1>, dim3(b.batch, nblk, grp.n), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off,
+                           b.v_off, (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol,
+                           done, sweeps, sweep, grp);
     else
-        hipLaunchKernelGGL(k_residual<4>, dim3(b.batch, nblk), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off, b.v_off,
-                           (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,
-                           sweeps, sweep);
+        hipLaunchKernelGGL(k_residual<4>, dim3(b.batch, nblk, grp.n), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off,
+                           b.v_off, (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol,
+                           done, sweeps, sweep, grp);
     return hipGetLastError();
 }
 

@@ -240,3 +240,30 @@ def interior_points(curve: Curve, n: int, seed: int = 3, shrink: float = 0.5) ->
     cen = curve_points(curve, np.linspace(0, 2 * np.pi, 256, endpoint=False)).mean(axis=0)
     lam = rng.uniform(0.0, shrink, n)[:, None]
     return cen + lam * (pts - cen)
+
+
+def serve_requests(rate: float, duration: float, seed: int = 1, pool: int = 16, dw: float = 1.0):
+    """The serving configuration: Poisson arrivals at `rate` per second over
+    `duration` seconds.  Each request names a star curve of a seeded pool (the
+    batching configuration's curves), a band [lo, lo + B] with B ~ U(10, 50)
+    and lo ~ U(0, 300 - B) snapped to the grid dw (so j_first = floor(lo/dw)
+    and F = round(B/dw) frequencies (j_first + j) dw, j = 1..F), one N ~
+    U{256, 288, ..., 4096} and 1..64 plane waves at uniform angles.
+    Returns (curves, requests): requests in arrival order, dicts with
+    t, curve, j_first, F, N, dirs ([n_rhs][2])."""
+    rng = np.random.default_rng(seed)
+    curves = star_pool(pool, 0)
+    reqs = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        B = rng.uniform(10.0, 50.0)
+        lo = rng.uniform(0.0, 300.0 - B)
+        N = 256 + 32 * int(rng.integers(0, 121))
+        n_rhs = int(rng.integers(1, 65))
+        ang = rng.uniform(0.0, 2.0 * np.pi, n_rhs)
+        reqs.append(dict(t=t, curve=int(rng.integers(0, pool)), j_first=int(np.floor(lo / dw)),
+                         F=max(1, int(round(B / dw))), N=N, dirs=np.stack([np.cos(ang), np.sin(ang)], axis=1)))
+    return curves, reqs
