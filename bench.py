@@ -160,6 +160,37 @@ def star_batch_bench(fhw, torch, sb, steps, warmup):
                       "stages_ms_per_step": {k: v[0] / steps for k, v in prof.items()}}), flush=True)
 
 
+def batch_sweep(fhw, torch, Wk, batches, modes, reps):
+    """Solves/s of the frequency solves alone (assembly + LU + solves +
+    refinement, fhw_solve_densities) at N = 1024 on the kite for batches of
+    F frequencies spread over the same band (0, 69]; median of reps timed
+    calls after one warm-up (each call synchronizes)."""
+    out = {}
+    for m in modes:
+        rows = []
+        for F in batches:
+            wl = Wk.kite_n1024(F=F)
+            ctx = fhw.Context()
+            try:
+                ctx.plan(wl.curve, wl.W, F, N=wl.N, precision=m, refine_tol=1e-12, refine_max=10,
+                         direction=wl.direction)
+                psi = torch.empty(int(ctx.psi_off[-1]), dtype=torch.complex128, device="cuda")
+                ctx.solve_densities(psi)
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    ctx.solve_densities(psi)
+                    ts.append(time.perf_counter() - t0)
+            finally:
+                ctx.close()
+            t = float(np.median(ts))
+            rows.append({"batch": F, "ms": 1e3 * t, "solves_per_s": F / t})
+            print(json.dumps({"mode": m, **rows[-1]}), file=sys.stderr, flush=True)
+        out[m] = rows
+    print(json.dumps({"metric": "frequency solves/s at N=1024 (kite) vs batch size", "reps": reps, "modes": out}),
+          flush=True)
+
+
 def serve_bench(fhw, torch, Wk, rates, duration, max_wait, precision):
     """The serving configuration, one request at a time in arrival order
     (FIFO) on one context: per request a band plan of its curve, N and
@@ -247,9 +278,10 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=50, help="isolated-solve latency samples (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
-    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve"],
+    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep"],
                     help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
-                         "serve: Poisson request stream (per-request latency)")
+                         "serve: Poisson request stream (per-request latency); batch_sweep: solves/s at "
+                         "batches of 1, 16, 256, 1024 frequencies")
     ap.add_argument("--rates", default="5,10,20,50", help="serve: arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--max-wait", type=float, default=2.0, help="serve: refuse requests queued longer (s)")
@@ -267,6 +299,9 @@ def main():
     from paper_1807_02718_amd import fhw
     if a.workload == "stars":
         star_batch_bench(fhw, torch, Wk.star_batch(), a.steps, a.warmup)
+        return
+    if a.workload == "batch_sweep":
+        batch_sweep(fhw, torch, Wk, [1, 16, 256, 1024], a.modes.split(","), 10)
         return
     if a.workload == "serve":
         serve_bench(fhw, torch, Wk, [float(x) for x in a.rates.split(",")], a.duration, a.max_wait,
