@@ -2,6 +2,8 @@
 // each .hip translation unit provides.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <stdint.h>
 
 #include <map>
@@ -141,6 +143,15 @@ hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_item
 int64_t assemble_blocks_for(int32_t N);
 // boundary data of one incidence (FHW_INC_PLANE: v = p; FHW_INC_POINT: v = r0)
 // for every item, written at g + g_off
+// True the first time a caller passes `mask` on the current device (kernel
+// attributes such as the dynamic LDS limit are per device).
+inline bool fhw_first_on_device(std::atomic<uint64_t>& mask) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const uint64_t bit = 1ull << (dev & 63);
+    return !(mask.fetch_or(bit) & bit);
+}
+
 // Incidences solved together: one more grid dimension over up to
 // FHW_INC_GROUP incidences, each buffer advanced by its stride (elements).
 #define FHW_INC_GROUP 8

@@ -802,9 +802,8 @@ void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch) {
 
 template <typename T>
 static void lu_set_lds_limits() {
-    static bool done = false;
-    if (done) return;
-    done = true;
+    static std::atomic<uint64_t> done{0};
+    if (!fhw_first_on_device(done)) return;
     (void)hipFuncSetAttribute((const void*)k_lu_diaginv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(inv_lds<T>));
 }
@@ -826,7 +825,7 @@ static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, in
         const int R4 = (R + 3) / 4;   // rows per thread with 1024 threads
         if constexpr (sizeof(T) == 4) {
             switch (R4) {
-                case 1: FHW_PANEL(1, 16, 4, 1024); break;
+                case 1: FHW_PANEL(1, 8, 4, 1024); break;
                 case 2: FHW_PANEL(2, 8, 4, 1024); break;
                 default: FHW_PANEL(4, 8, 4, 1024); break;
             }

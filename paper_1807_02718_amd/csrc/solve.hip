@@ -344,10 +344,9 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
                                int precision, const fhw_grp& grp) {
     if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
-    static bool attr = false;
-    if (!attr) {
+    static std::atomic<uint64_t> attr{0};
+    if (fhw_first_on_device(attr)) {
         // solution vectors up to N = 4096 (64 KiB) beside the static LDS
-        attr = true;
         const int dyn = 4096 * (int)sizeof(zd);
         (void)hipFuncSetAttribute((const void*)k_lu_solve<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_lu_solve<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
@@ -373,9 +372,8 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
                              int32_t* done, int32_t* sweeps, int sweep, const fhw_grp& grp) {
     if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
-    static bool attr = false;
-    if (!attr) {
-        attr = true;
+    static std::atomic<uint64_t> attr{0};
+    if (fhw_first_on_device(attr)) {
         const int dyn = 4096 * (int)sizeof(zd);
         (void)hipFuncSetAttribute((const void*)k_residual<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_residual<4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
