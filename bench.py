@@ -204,6 +204,9 @@ def serve_bench(fhw, torch, Wk, rates, duration, max_wait, precision):
     try:
         for rate in rates:
             curves, reqs = Wk.serve_requests(rate, duration)
+            if not reqs:
+                out.append({"rate": rate, "offered": 0, "completed": 0, "refused": 0})
+                continue
             # warm-up outside the clock: the largest plan of the stream, so
             # that no request pays a workspace allocation
             big = max(reqs, key=lambda r: r["N"] * r["N"] * r["F"])
