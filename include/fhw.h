@@ -10,6 +10,9 @@
  *                        equation (eq. CFIE_direct) at every frequency (step F3)
  *   fhw_solve_incidences the same for several incident fields per factorization
  *   fhw_solve_cached     further incident fields on factors left resident
+ *   fhw_plan_systems,    a batch of requests (any curve, frequency and N per
+ *   fhw_factor,          system) factored together, then solved request by
+ *   fhw_solve_range      request on the resident factors
  *   fhw_eval_field       layer potential U = int psi G (eqs. freq_domain_repr,
  *                        Ukslow_repr; step F5)
  *   fhw_synthesize       windowed, recentred signal spectra (eq. Bkslow_eqn,
@@ -163,6 +166,43 @@ int fhw_solve_incidences(fhw_ctx* ctx, const fhw_incidence* inc, int32_t n_inc, 
  * fhw_solve_incidences. */
 int fhw_solve_cached(fhw_ctx* ctx, const fhw_incidence* inc, int32_t n_inc, void* psi,
                      double* resid, int32_t* sweeps);
+
+/* One frequency-domain system of a request: scatterer `curve` (index into the
+ * plan's curves), frequency omega > 0 (kappa = omega / c) and an even N,
+ * 4 <= N <= 4096 nodes. */
+typedef struct {
+    int32_t curve;
+    double omega;
+    int32_t N;
+} fhw_system;
+
+/* Plan an explicit list of systems (Sec. 2.3 discretization of eq.
+ * CFIE_direct for each), for instance the frequencies of several requests of
+ * different scatterers, bands and sizes, so that their factorizations share
+ * every launch.  prob supplies c, precision, refine_tol, refine_max and the
+ * plane-wave direction (W, F, the N rule and j_first are not used).  Such a
+ * plan serves the solves only (fhw_eval_field, fhw_synthesize and the
+ * DFT-grid stage calls refuse it with FHW_E_STATE).  psi_off_out [host,
+ * optional]: n_systems + 1 offsets.  Errors: FHW_E_INVALID for a curve index
+ * out of range, omega <= 0 or a bad N; otherwise as fhw_plan_curves. */
+int fhw_plan_systems(fhw_ctx* ctx, const fhw_curve* curves, int32_t n_curves, const fhw_system* systems,
+                     int32_t n_systems, const fhw_problem* prob, int64_t* psi_off_out);
+
+/* Assemble and factor every system of the plan and leave the factors
+ * resident (step F3 without a right-hand side), for fhw_solve_range and
+ * fhw_solve_cached.  Synchronizes.  FHW_E_NOMEM if the plan needs more than
+ * one workspace chunk; FHW_E_SINGULAR on an exactly zero pivot. */
+int fhw_factor(fhw_ctx* ctx);
+
+/* Solve systems s0 .. s0 + count - 1 on the resident factors for n_inc
+ * incidences (as fhw_solve_cached, restricted to the range: one request of a
+ * batched plan).  psi: complex128 [n_inc][E] with E = psi_off[s0 + count] -
+ * psi_off[s0] (the range's densities, packed).  resid, sweeps [host,
+ * optional]: [n_inc][count].  Synchronizes.  Errors: FHW_E_STATE without
+ * resident factors; FHW_E_INVALID for a range outside the plan or bad
+ * incidences; FHW_E_NOCONV as in fhw_solve_densities. */
+int fhw_solve_range(fhw_ctx* ctx, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc, void* psi,
+                    double* resid, int32_t* sweeps);
 
 /* Step F5 (eqs. freq_domain_repr, Ukslow_repr): V(r, omega_l) on the full DFT
  * grid, V[r][l], complex128 [N_r][2F]; V(r,-omega) = conj V(r,omega) and

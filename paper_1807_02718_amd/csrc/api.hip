@@ -261,18 +261,31 @@ int fhw_destroy(fhw_ctx* c) {
 
 const char* fhw_last_error(const fhw_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-// Plan n_curves scatterers with one problem: system s = curve * F + j.
+// Plan n_curves scatterers with one problem: system s = curve * F + j; or,
+// with sys != NULL, the n_sys systems listed there (any curve, frequency, N).
 static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, const fhw_problem* p, int32_t* N_out,
-                     int64_t* psi_off_out) {
+                     int64_t* psi_off_out, const fhw_system* sys = nullptr, int32_t n_sys = 0) {
     if (!c) return FHW_E_INVALID;
     if (!curves || n_curves < 1 || !p) return fhw_fail(c, FHW_E_INVALID, "plan: missing curve/problem");
+    if (sys) {
+        if (n_sys < 1) return fhw_fail(c, FHW_E_INVALID, "plan_systems: need at least one system");
+        for (int s = 0; s < n_sys; ++s) {
+            if (sys[s].curve < 0 || sys[s].curve >= n_curves)
+                return fhw_fail(c, FHW_E_INVALID, "plan_systems: curve index out of range");
+            if (!(sys[s].omega > 0) || !isfinite(sys[s].omega))
+                return fhw_fail(c, FHW_E_INVALID, "plan_systems: need a finite omega > 0");
+            if (sys[s].N < 4 || (sys[s].N & 1) || sys[s].N > 4096)
+                return fhw_fail(c, FHW_E_INVALID, "plan_systems: N must be even, 4 <= N <= 4096");
+        }
+    }
     for (int k = 0; k < n_curves; ++k) {
         const fhw_curve* curve = curves + k;
         if (curve->degree < 1 || !curve->cx || !curve->sx || !curve->cy || !curve->sy)
             return fhw_fail(c, FHW_E_INVALID, "plan: missing curve coefficients");
     }
-    if (!(p->W > 0) || p->F < 1 || !(p->c > 0) || !isfinite(p->W) || !isfinite(p->c))
-        return fhw_fail(c, FHW_E_INVALID, "plan: need W > 0, F >= 1, c > 0");
+    if (!(p->c > 0) || !isfinite(p->c)) return fhw_fail(c, FHW_E_INVALID, "plan: need c > 0");
+    if (!sys && (!(p->W > 0) || p->F < 1 || !isfinite(p->W)))
+        return fhw_fail(c, FHW_E_INVALID, "plan: need W > 0, F >= 1");
     if (p->precision != FHW_FP64 && p->precision != FHW_FP32_REFINE)
         return fhw_fail(c, FHW_E_INVALID, "plan: unknown precision");
     if (!isfinite(p->direction[0]) || !isfinite(p->direction[1]))
@@ -312,15 +325,24 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         cv.length = L;
     }
     // frequencies, sizes, coupling per system
-    const int F = p->F;
-    const int S = n_curves * F;
+    const int F = sys ? n_sys : p->F;
+    const int S = sys ? n_sys : n_curves * F;
     const double dw = p->W / (double)F;
     c->kappa.resize(S);
     c->eta.resize(S);
     c->Ns.resize(S);
-    for (int k = 0; k < n_curves; ++k)
+    c->sys_curve.resize(S);
+    c->system_plan = sys != nullptr;
+    for (int s = 0; sys && s < S; ++s) {
+        c->kappa[s] = sys[s].omega / p->c;
+        c->eta[s] = std::max(c->kappa[s], 1.0);
+        c->Ns[s] = sys[s].N;
+        c->sys_curve[s] = sys[s].curve;
+    }
+    for (int k = 0; !sys && k < n_curves; ++k)
         for (int j = 0; j < F; ++j) {
             const int sy = k * F + j;
+            c->sys_curve[sy] = k;
             double om = dw * (double)(p->j_first + j + 1);
             c->kappa[sy] = om / p->c;
             c->eta[sy] = std::max(c->kappa[sy], 1.0);
@@ -355,7 +377,9 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
             hc[d] = cv.cx[d]; hc[D1 + d] = cv.sx[d]; hc[2 * D1 + d] = cv.cy[d]; hc[3 * D1 + d] = cv.sy[d];
         }
         FHW_HIP(c, hipMemcpy(cv.d_curve, hc.data(), sizeof(double) * 4 * D1, hipMemcpyHostToDevice));
-        std::set<int32_t> distinct(c->Ns.begin() + k * F, c->Ns.begin() + (k + 1) * F);
+        std::set<int32_t> distinct;
+        for (int s = 0; s < S; ++s)
+            if (c->sys_curve[s] == k) distinct.insert(c->Ns[s]);
         for (int32_t N : distinct) {
             fhw_geom_entry e{};
             e.N = N;
@@ -455,7 +479,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
             int N = c->Ns[j];
             Nv[q] = N;
             ao[q] = a; po[q] = pv; lo[q] = l; vo[q] = v;
-            const fhw_geom_entry& ge = c->geoms[fhw_geom_key(j / F, N)];
+            const fhw_geom_entry& ge = c->geoms[fhw_geom_key(c->sys_curve[j], N)];
             items[q].geom = ge.geom;
             items[q].R = ge.R;
             items[q].logtab = ge.logtab;
@@ -485,7 +509,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     }
     std::vector<fhw_field_item> fitems(S);
     for (int j = 0; j < S; ++j) {
-        fitems[j].geom = c->geoms[fhw_geom_key(j / F, c->Ns[j])].geom;
+        fitems[j].geom = c->geoms[fhw_geom_key(c->sys_curve[j], c->Ns[j])].geom;
         fitems[j].psi_off = c->psi_off[j];
         fitems[j].N = c->Ns[j];
         fitems[j].kappa = c->kappa[j];
@@ -524,6 +548,13 @@ int fhw_plan_curves(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, const
     return plan_impl(c, curves, n_curves, p, N_out, psi_off_out);
 }
 
+int fhw_plan_systems(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, const fhw_system* systems,
+                     int32_t n_systems, const fhw_problem* p, int64_t* psi_off_out) {
+    if (!c) return FHW_E_INVALID;
+    if (!systems) return fhw_fail(c, FHW_E_INVALID, "plan_systems: no systems");
+    return plan_impl(c, curves, n_curves, p, nullptr, psi_off_out, systems, n_systems);
+}
+
 // winding number of the planned curve about (a, b): 0 outside
 static int winding_number(const fhw_host_curve& cv, double a, double b, double* min_dist) {
     const int M = 4096;
@@ -543,6 +574,67 @@ static int winding_number(const fhw_host_curve& cv, double a, double b, double* 
     }
     *min_dist = dmin;
     return (int)lround(tot / (2.0 * M_PI));
+}
+
+// The incidences on one factored batch, in groups of up to FHW_INC_GROUP
+// (one launch per step for a whole group: a second grid dimension), each
+// with its own slot of g and r: boundary data (inc == NULL: the plan's plane
+// wave, as the assembly left it in slot 0), solves and, on the FP32 path,
+// the refinement sweeps.  Vectors are addressed with the batch's offsets:
+// incidence q's densities at x + q xs + v_off[b], of which the elements
+// [voff0, voff0 + elems) belong to the batch; its norms at norms + 2 q fs
+// and flags at done / sw + q fs (index b within the batch).
+static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const fhw_assemble_item* d_items,
+                        int64_t voff0, int64_t elems, const fhw_incidence* inc, int32_t n_inc, zd* x, int64_t xs,
+                        double* norms, int32_t* done, int32_t* sw, int64_t fs) {
+    const fhw_problem& p = c->prob;
+    const bool fp32 = p.precision == FHW_FP32_REFINE;
+    void* LU = fp32 ? c->A32 : c->A64;
+    zd* g = (zd*)c->x;
+    zd* r = (zd*)c->r;
+    const int64_t sv = c->ws_vec;
+    for (int q0 = 0; q0 < n_inc; q0 += FHW_INC_GROUP) {
+        const int G = std::min(FHW_INC_GROUP, n_inc - q0);
+        zd* xq = x + q0 * xs;     // solutions written in place into psi
+        if (inc) {
+            fhw_rhs_group rg{};
+            rg.n = G;
+            for (int q = 0; q < G; ++q) {
+                rg.kind[q] = inc[q0 + q].kind;
+                rg.v[q][0] = inc[q0 + q].v[0];
+                rg.v[q][1] = inc[q0 + q].v[1];
+            }
+            STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, d_items, bd.batch, rg, sv, g));
+        }
+        for (int q = 0; q < G; ++q)
+            FHW_HIP(c, hipMemcpyAsync(xq + q * xs + voff0, g + q * sv + voff0, sizeof(zd) * elems,
+                                      hipMemcpyDeviceToDevice, c->stream));
+        fhw_grp gs;
+        gs.n = G;
+        gs.sv = xs;
+        STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, maxN, LU, c->piv, c->linv, xq, nullptr,
+                                                  p.precision, gs));
+        if (!fp32) continue;
+        double* nq = norms + 2 * (int64_t)q0 * fs;
+        int32_t* dq = done + (int64_t)q0 * fs;
+        int32_t* wq = sw + (int64_t)q0 * fs;
+        fhw_grp gr;   // residual: x in psi, g and r in their slots
+        gr.n = G;
+        gr.sx = xs; gr.sg = sv; gr.sr = sv;
+        gr.spart = c->rpart_stride; gr.scount = c->chunk; gr.snorm = 2 * fs; gr.sflag = fs;
+        fhw_grp ga;   // correction: solve r in place, add into x, skip converged
+        ga.n = G;
+        ga.sv = sv; ga.sacc = xs; ga.sflag = fs;
+        const int maxs = std::max(0, p.refine_max);
+        for (int it = 0; it <= maxs; ++it) {
+            STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, maxN, c->A64, xq, g, r, c->d_rpart,
+                                                           c->d_rcount, nq, p.refine_tol, dq, wq, it, gr));
+            if (it == maxs) break;
+            STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, maxN, LU, c->piv, c->linv, r, xq, dq,
+                                                          p.precision, ga));
+        }
+    }
+    return FHW_OK;
 }
 
 // Densities for n_inc incidences (inc == NULL: the plan's plane wave, whose
@@ -585,57 +677,17 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
                                         p.precision, &c->prof));
         }
-        // incidences in groups of up to FHW_INC_GROUP: one launch per step for
-        // the whole group (a second grid dimension), each incidence with its
-        // own slot of g and r and its own densities, norms and flags
-        const int64_t sv = c->ws_vec;
-        const int64_t maxc = c->chunk;
-        for (int q0 = 0; q0 < n_inc; q0 += FHW_INC_GROUP) {
-            const int G = std::min(FHW_INC_GROUP, n_inc - q0);
-            zd* x = psid + q0 * total + ch.psi_base;     // solutions written in place into psi
-            if (inc) {
-                fhw_rhs_group rg{};
-                rg.n = G;
-                for (int q = 0; q < G; ++q) {
-                    rg.kind[q] = inc[q0 + q].kind;
-                    rg.v[q][0] = inc[q0 + q].v[0];
-                    rg.v[q][1] = inc[q0 + q].v[1];
-                }
-                STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, ch.d_items, ch.count, rg, sv, g));
-            }
-            for (int q = 0; q < G; ++q)
-                FHW_HIP(c, hipMemcpyAsync(x + q * total, g + q * sv, sizeof(zd) * ch.vec_elems,
-                                          hipMemcpyDeviceToDevice, c->stream));
-            fhw_grp gs;
-            gs.n = G;
-            gs.sv = total;
-            STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve(c->stream, bd, ch.maxN, LU, c->piv, c->linv, x, nullptr,
-                                                      p.precision, gs));
-            if (!fp32) continue;
-            double* norms = d_norms + 2 * ((int64_t)q0 * F + ch.j0);
-            int32_t* done = d_done + (int64_t)q0 * F + ch.j0;
-            int32_t* sw = d_sw + (int64_t)q0 * F + ch.j0;
-            fhw_grp gr;   // residual: x in psi, g and r in their slots
-            gr.n = G;
-            gr.sx = total; gr.sg = sv; gr.sr = sv;
-            gr.spart = c->rpart_stride; gr.scount = maxc; gr.snorm = 2 * (int64_t)F; gr.sflag = F;
-            fhw_grp ga;   // correction: solve r in place, add into x, skip converged
-            ga.n = G;
-            ga.sv = sv; ga.sacc = total; ga.sflag = F;
-            const int maxs = std::max(0, p.refine_max);
-            for (int it = 0; it <= maxs; ++it) {
-                STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64, x, g, r, c->d_rpart,
-                                                               c->d_rcount, norms, p.refine_tol, done, sw, it, gr));
-                if (it == maxs) break;
-                STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, ch.maxN, LU, c->piv, c->linv, r, x, done,
-                                                              p.precision, ga));
-            }
+        {
+            int rc = solve_groups(c, bd, ch.maxN, ch.d_items, 0, ch.vec_elems, inc, n_inc, psid + ch.psi_base, total,
+                                  d_norms + 2 * (int64_t)ch.j0, d_done + ch.j0, d_sw + ch.j0, F);
+            if (rc) return rc;
         }
         if (!fp32 && compute_resid) {
             // the factorization overwrote A: assemble it again for the residuals
             // (which also ends the residency of the FP64 factors)
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
                                               p.direction[0], p.direction[1], c->A64, nullptr, g));
+            const int64_t sv = c->ws_vec;
             for (int q0 = 0; q0 < n_inc; q0 += FHW_INC_GROUP) {
                 const int G = std::min(FHW_INC_GROUP, n_inc - q0);
                 if (inc) {
@@ -652,7 +704,7 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
                 fhw_grp gr;
                 gr.n = G;
                 gr.sx = total; gr.sg = sv; gr.sr = sv;
-                gr.spart = c->rpart_stride; gr.scount = maxc; gr.snorm = 2 * (int64_t)F;
+                gr.spart = c->rpart_stride; gr.scount = c->chunk; gr.snorm = 2 * (int64_t)F;
                 STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64,
                                                                psid + q0 * total + ch.psi_base, g, r, c->d_rpart,
                                                                c->d_rcount, norms, 0.0, nullptr, nullptr, 0, gr));
@@ -738,11 +790,77 @@ int fhw_solve_cached(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* 
     return solve_impl(c, inc, n_inc, psi, resid, sweeps, 0, true);
 }
 
+int fhw_factor(fhw_ctx* c) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "factor: no plan");
+    if (g_plans[c].chunks.size() != 1)
+        return fhw_fail(c, FHW_E_NOMEM, "factor: the plan does not fit one workspace chunk");
+    return solve_impl(c, nullptr, 0, nullptr, nullptr, nullptr, 0, false);
+}
+
+int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc, void* psi,
+                    double* resid, int32_t* sweeps) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve_range: no plan");
+    if (!c->factors_resident)
+        return fhw_fail(c, FHW_E_STATE, "solve_range: no resident factors (fhw_factor first)");
+    const int S = (int)c->Ns.size();
+    if (s0 < 0 || count < 1 || s0 > S - count) return fhw_fail(c, FHW_E_INVALID, "solve_range: systems out of range");
+    int rc = check_incidences(c, inc, n_inc, psi);
+    if (rc) return rc;
+    plan_ext& px = g_plans[c];
+    const chunk_t& ch = px.chunks[0];
+    const fhw_problem& p = c->prob;
+    const bool fp32 = p.precision == FHW_FP32_REFINE;
+    // the range as a sub-batch of the resident chunk: its rows of the
+    // per-matrix device tables, vectors addressed with the chunk's offsets
+    const int b0 = s0 - ch.j0;
+    fhw_batch_dev bd{ch.d_N + b0, ch.d_aoff + b0, ch.d_pivoff + b0, ch.d_linvoff + b0, ch.d_voff + b0, count};
+    int32_t maxN = 0;
+    for (int s = s0; s < s0 + count; ++s) maxN = std::max(maxN, c->Ns[s]);
+    const int64_t voff0 = c->psi_off[s0] - ch.psi_base;
+    const int64_t elems = c->psi_off[s0 + count] - c->psi_off[s0];
+    const size_t nf = (size_t)n_inc * count;
+    const size_t off_sw = align_up(nf * 4, 256), off_nrm = off_sw + align_up(nf * 4, 256);
+    rc = fhw_ensure_scratch(c, off_nrm + nf * 16);
+    if (rc) return rc;
+    int32_t* d_done = (int32_t*)c->scratch;
+    int32_t* d_sw = (int32_t*)((char*)c->scratch + off_sw);
+    double* d_norms = (double*)((char*)c->scratch + off_nrm);
+    FHW_HIP(c, hipMemsetAsync(d_done, 0, sizeof(int32_t) * nf, c->stream));
+    FHW_HIP(c, hipMemsetAsync(d_sw, 0, sizeof(int32_t) * nf, c->stream));
+    // psi holds the range's densities per incidence: element e of incidence q
+    // at psi + q elems + e, i.e. x + q elems + v_off[b] with x = psi - voff0
+    zd* x = (zd*)psi - voff0;
+    rc = solve_groups(c, bd, maxN, ch.d_items + b0, voff0, elems, inc, n_inc, x, elems, d_norms, d_done, d_sw, count);
+    if (rc) return rc;
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    std::vector<double> nrm;
+    std::vector<int32_t> done, sw;
+    if (fp32) {
+        nrm.resize(2 * nf);
+        done.resize(nf);
+        sw.resize(nf);
+        FHW_HIP(c, hipMemcpy(nrm.data(), d_norms, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(done.data(), d_done, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(sw.data(), d_sw, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
+    }
+    for (size_t j = 0; j < nf; ++j) {
+        if (resid) resid[j] = fp32 ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
+        if (sweeps) sweeps[j] = fp32 ? (done[j] ? sw[j] : p.refine_max) : 0;
+    }
+    if (fp32)
+        for (size_t j = 0; j < nf; ++j)
+            if (!done[j]) return fhw_fail(c, FHW_E_NOCONV, "solve_range: refinement did not reach refine_tol");
+    return FHW_OK;
+}
+
 int fhw_eval_field_curve(fhw_ctx* c, int32_t curve, const void* psi, const double* obs, int32_t N_r,
                          double zero_value, void* V) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field: no plan");
-    if (c->prob.j_first != 0) return fhw_fail(c, FHW_E_STATE, "field: the plan is a band (j_first > 0)");
+    if (c->prob.j_first != 0 || c->system_plan)
+        return fhw_fail(c, FHW_E_STATE, "field: the plan is a band or a list of systems (no DFT grid)");
     if (curve < 0 || curve >= (int)c->curves.size()) return fhw_fail(c, FHW_E_INVALID, "field: no such curve");
     if (N_r < 0 || (N_r > 0 && (!psi || !obs || !V))) return fhw_fail(c, FHW_E_INVALID, "field: bad arguments");
     if (N_r == 0) return FHW_OK;
@@ -765,7 +883,8 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
                    const double* times, int32_t N_t, double* u) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize: no plan");
-    if (c->prob.j_first != 0) return fhw_fail(c, FHW_E_STATE, "synthesize: the plan is a band (j_first > 0)");
+    if (c->prob.j_first != 0 || c->system_plan)
+        return fhw_fail(c, FHW_E_STATE, "synthesize: the plan is a band or a list of systems (no DFT grid)");
     if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize: bad arguments");
     if (N_r == 0 || N_t == 0) return FHW_OK;
     if (!V || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
@@ -883,7 +1002,7 @@ int fhw_assemble(fhw_ctx* c, int32_t j0, int32_t count, void* A, const int64_t* 
     int64_t blk = 0;
     for (int q = 0; q < count; ++q) {
         int j = j0 + q;
-        const fhw_geom_entry& ge = c->geoms[fhw_geom_key(j / c->prob.F, c->Ns[j])];
+        const fhw_geom_entry& ge = c->geoms[fhw_geom_key(c->sys_curve[j], c->Ns[j])];
         items[q] = fhw_assemble_item{ge.geom, ge.R, ge.logtab, A_off[q], g_off[q], c->Ns[j], c->kappa[j], c->eta[j]};
         pre[q] = blk;
         blk += assemble_blocks_for(c->Ns[j]);
@@ -989,6 +1108,7 @@ int fhw_window_spectra(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win
                        void* B) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "window_spectra: no plan");
+    if (c->system_plan) return fhw_fail(c, FHW_E_STATE, "window_spectra: the plan is a list of systems (no DFT grid)");
     if (!sig || !win || count < 0 || (count > 0 && (!B || !sig->f)) || sig->n < 2 || !(sig->dt > 0) || !(win->H > 0))
         return fhw_fail(c, FHW_E_INVALID, "window_spectra: bad arguments");
     STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, win->H, k_first, nullptr, count,
@@ -1001,6 +1121,7 @@ int fhw_fourier_coefficients(fhw_ctx* c, const void* B, int32_t count, const voi
                              void* cc) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "fourier_coefficients: no plan");
+    if (c->system_plan) return fhw_fail(c, FHW_E_STATE, "fourier_coefficients: the plan is a list of systems (no DFT grid)");
     const int M = 2 * c->prob.F;
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: 2F must be a power of two");
     if (count < 0 || N_r < 0 || ((count > 0 && N_r > 0) && (!B || !V || !cc)) || !isfinite(tau0))

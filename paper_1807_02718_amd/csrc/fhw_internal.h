@@ -79,6 +79,8 @@ struct fhw_ctx {
     std::vector<fhw_host_curve> curves;
     std::vector<double> kappa, eta;    // [systems]
     std::vector<int32_t> Ns;           // [systems]
+    std::vector<int32_t> sys_curve;    // [systems] curve of each system
+    bool system_plan = false;          // planned by fhw_plan_systems (no DFT grid)
     std::vector<int64_t> psi_off;      // [systems + 1]
     std::map<int64_t, fhw_geom_entry> geoms;   // key: curve * 65536 + N
 

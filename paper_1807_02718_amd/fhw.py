@@ -56,6 +56,10 @@ class fhw_incidence(C.Structure):
     _fields_ = [("kind", C.c_int32), ("v", C.c_double * 2)]
 
 
+class fhw_system(C.Structure):
+    _fields_ = [("curve", C.c_int32), ("omega", C.c_double), ("N", C.c_int32)]
+
+
 class FhwError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libfhw error {code}: {msg}")
@@ -74,6 +78,9 @@ def _load():
         "fhw_version": [],
         "fhw_plan": [vp, C.POINTER(fhw_curve), C.POINTER(fhw_problem), p_i32, p_i64],
         "fhw_plan_curves": [vp, C.POINTER(fhw_curve), i32, C.POINTER(fhw_problem), p_i32, p_i64],
+        "fhw_plan_systems": [vp, C.POINTER(fhw_curve), i32, C.POINTER(fhw_system), i32, C.POINTER(fhw_problem), p_i64],
+        "fhw_factor": [vp],
+        "fhw_solve_range": [vp, i32, i32, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
         "fhw_solve_densities": [vp, vp, _dp, p_i32, i32],
         "fhw_solve_incidences": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32, i32],
         "fhw_solve_cached": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
@@ -103,6 +110,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
+            "fhw_plan_systems", "fhw_factor", "fhw_solve_range",
             "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
@@ -195,6 +203,55 @@ class Context:
         self.S, self.n_curves = S, len(curves)
         self.precision = precision
         return Ns, off
+
+    def plan_systems(self, curves, systems, c=1.0, precision="fp64", refine_tol=1e-12, refine_max=10,
+                     direction=(1.0, 0.0)):
+        """fhw_plan_systems: systems = sequence of (curve index, omega, N).
+        Returns the psi offsets (n_systems + 1)."""
+        self._cv = [[np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (cv.cx, cv.sx, cv.cy, cv.sy)]
+                    for cv in curves]
+        arr = (fhw_curve * len(curves))()
+        for k, vs in enumerate(self._cv):
+            arr[k] = fhw_curve(len(vs[0]) - 1, *[v.ctypes.data_as(_dp) for v in vs])
+        S = len(systems)
+        sy = (fhw_system * max(S, 1))()
+        for s, (k, om, N) in enumerate(systems):
+            sy[s] = fhw_system(int(k), float(om), int(N))
+        pr = fhw_problem()
+        pr.W, pr.F, pr.c = 1.0, 1, float(c)
+        pr.precision = {"fp64": FHW_FP64, "fp32_refine": FHW_FP32_REFINE}[precision]
+        pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
+        pr.direction[0], pr.direction[1] = float(direction[0]), float(direction[1])
+        off = np.zeros(S + 1, dtype=np.int64)
+        self._check(_lib.fhw_plan_systems(self._h, arr, len(curves), sy, S, C.byref(pr),
+                                          off.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.F, self.W, self.Ns, self.psi_off = 0, 0.0, np.array([n for _, _, n in systems], dtype=np.int32), off
+        self.S, self.n_curves = S, len(curves)
+        self.precision = precision
+        return off
+
+    def factor(self):
+        """fhw_factor: assemble and factor every planned system; factors stay resident."""
+        self._check(_lib.fhw_factor(self._h))
+
+    def solve_range(self, s0, count, incidences, psi=None):
+        """fhw_solve_range on systems s0 .. s0+count-1.  Returns (psi [n_inc, E]
+        complex128, resid [n_inc, count], sweeps [n_inc, count])."""
+        kinds = {"plane": FHW_INC_PLANE, "point": FHW_INC_POINT}
+        n = len(incidences)
+        arr = (fhw_incidence * max(n, 1))()
+        for q, (kind, v) in enumerate(incidences):
+            arr[q].kind = kinds[kind] if isinstance(kind, str) else int(kind)
+            arr[q].v[0], arr[q].v[1] = float(v[0]), float(v[1])
+        ok = 0 <= s0 and count >= 1 and s0 + count <= self.S
+        E = int(self.psi_off[s0 + count] - self.psi_off[s0]) if ok else 1   # else the library refuses the range
+        if psi is None:
+            psi = torch.empty((max(n, 1), E), dtype=torch.complex128, device=self.device)
+        resid = np.zeros((max(n, 1), count))
+        sweeps = np.zeros((max(n, 1), count), dtype=np.int32)
+        self._check(_lib.fhw_solve_range(self._h, int(s0), int(count), arr, n, _ptr(psi), resid.ctypes.data_as(_dp),
+                                         sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
+        return psi, resid, sweeps
 
     # -- hot path ---------------------------------------------------------------
     def solve_densities(self, psi=None, compute_resid=False):

@@ -45,7 +45,7 @@ def test_struct_layouts(tmp_path):
     import subprocess
     from paper_1807_02718_amd import fhw
     structs = {"fhw_curve": fhw.fhw_curve, "fhw_problem": fhw.fhw_problem, "fhw_signal": fhw.fhw_signal,
-               "fhw_windows": fhw.fhw_windows, "fhw_incidence": fhw.fhw_incidence}
+               "fhw_windows": fhw.fhw_windows, "fhw_incidence": fhw.fhw_incidence, "fhw_system": fhw.fhw_system}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')

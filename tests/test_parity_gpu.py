@@ -610,6 +610,67 @@ def test_workspace_reused_across_plans(fhw):
         c.close()
 
 
+def _requests():
+    """Three requests: (curve index, frequencies, N, incidences)."""
+    return [(0, [31.0, 32.0, 33.0, 34.0], 192, [("plane", (1.0, 0.0)), ("plane", (0.0, 1.0)), ("plane", (0.6, -0.8))]),
+            (1, [10.0, 11.5, 13.0], 256, [("plane", (-1.0, 0.0)), ("point", (3.5, 0.5))]),
+            (2, [50.0, 51.0], 320, [("plane", (0.8, 0.6))] * 1 + [("plane", (np.cos(a), np.sin(a))) for a in (0.3, 1.1, 2.0, 2.9)])]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_requests_alone_and_in_the_mix(fhw, precision):
+    """Requests of different curves, bands, N and right-hand sides factored in
+    one batched plan (fhw_plan_systems + fhw_factor) and solved request by
+    request (fhw_solve_range) give what each gives alone, and the oracle's
+    densities."""
+    say("requests alone vs in the mix", precision)
+    curves = [Wk.star_pool(1, 3)[0], Wk.kite(), Wk.circle(1.2)]
+    reqs = _requests()
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    alone = []
+    c = fhw.Context()
+    try:
+        for k, oms, N, inc in reqs:
+            c.plan_systems(curves, [(k, om, N) for om in oms], precision=precision)
+            c.factor()
+            psi, res, sw = c.solve_range(0, len(oms), inc)
+            alone.append(psi.cpu().numpy())
+        systems = [(k, om, N) for k, oms, N, _ in reqs for om in oms]
+        off = c.plan_systems(curves, systems, precision=precision)
+        c.factor()
+        s0 = 0
+        for (k, oms, N, inc), a in zip(reqs, alone):
+            psi, res, sw = c.solve_range(s0, len(oms), inc)
+            psi = psi.cpu().numpy()
+            err = relmax(psi, a)
+            say("request", k, "N", N, "mix vs alone", err)
+            assert err < tol
+            if precision == "fp32_refine":
+                assert np.all(res <= 1e-12)
+            # the oracle on the first frequency of the request, every incidence
+            gm = O.geometry(curves[k], N)
+            kappa = oms[0]
+            eta = O.coupling(np.array([kappa]))[0]
+            A = O.assemble(gm, kappa, eta)
+            for q, (kind, v) in enumerate(inc):
+                g = O.rhs_plane_wave(gm, kappa, eta, v) if kind == "plane" else O.rhs_point_source(gm, kappa, eta, v)
+                ref, _ = O.solve_density(A, g)
+                assert relmax(psi[q, :N], ref) < 1e-10, (k, q)
+            s0 += len(oms)
+        with pytest.raises(fhw.FhwError) as e:
+            c.eval_field(torch.zeros(int(off[-1]), dtype=torch.complex128, device="cuda"), Wk.ring(4, 3.0))
+        assert e.value.code == fhw.FHW_E_STATE
+        with pytest.raises(fhw.FhwError) as e:
+            c.solve_range(len(systems) - 1, 2, [("plane", (1.0, 0.0))])
+        assert e.value.code == fhw.FHW_E_INVALID
+        c.plan_systems(curves, systems[:2], precision=precision)
+        with pytest.raises(fhw.FhwError) as e:
+            c.solve_range(0, 1, [("plane", (1.0, 0.0))])
+        assert e.value.code == fhw.FHW_E_STATE
+    finally:
+        c.close()
+
+
 def test_budget_too_small(fhw):
     """A workspace budget below one frequency's needs is FHW_E_NOMEM at plan
     time, and the context stays usable."""
