@@ -191,6 +191,96 @@ def batch_sweep(fhw, torch, Wk, batches, modes, reps):
           flush=True)
 
 
+def serve_batched(fhw, torch, Wk, rates, duration, max_wait, precision, batch_bytes):
+    """The serving configuration with continuous batching: before each round,
+    every request that has arrived (and is not past max_wait in the queue) is
+    admitted while the batch's matrices fit batch_bytes of HBM; the round
+    plans all their systems at once (fhw_plan_systems), factors them in
+    shared launches (fhw_factor) and solves each request on the resident
+    factors (fhw_solve_range), completing it there.  Requests that arrive
+    during a round join the next one.  Latency = completion - arrival."""
+    from collections import deque
+    per_sys = 24 if precision == "fp32_refine" else 16     # bytes per matrix entry (FP64 A + FP32 LU)
+    out = []
+    ctx = fhw.Context()
+    try:
+        for rate in rates:
+            curves, reqs = Wk.serve_requests(rate, duration)
+            if not reqs:
+                out.append({"rate": rate, "offered": 0, "completed": 0, "refused": 0})
+                continue
+            # warm-up outside the clock at the size of a full batch
+            warm, nb = [], 0
+            for r in sorted(reqs, key=lambda r: -r["N"]):
+                b = r["F"] * per_sys * r["N"] * r["N"]
+                if warm and nb + b > batch_bytes:
+                    break
+                warm.append(r)
+                nb += b
+            ctx.plan_systems(curves, [(r["curve"], (r["j_first"] + j + 1) * 1.0, r["N"]) for r in warm
+                                      for j in range(r["F"])], precision=precision)
+            ctx.factor()
+            torch.cuda.synchronize()
+            lat, wait, refused, solves, sizes = [], [], 0, 0, []
+            queue = deque()
+            i = 0
+            t0 = time.perf_counter()
+            busy = 0.0
+            while i < len(reqs) or queue:
+                now = time.perf_counter() - t0
+                while i < len(reqs) and reqs[i]["t"] <= now:
+                    queue.append(reqs[i])
+                    i += 1
+                if not queue:
+                    time.sleep(max(0.0, min(reqs[i]["t"] - now, 1e-3)))
+                    continue
+                admit, nbytes = [], 0
+                while queue:
+                    r = queue[0]
+                    if now - r["t"] > max_wait:
+                        refused += 1
+                        queue.popleft()
+                        continue
+                    b = r["F"] * per_sys * r["N"] * r["N"]
+                    if admit and nbytes + b > batch_bytes:
+                        break
+                    admit.append(queue.popleft())
+                    nbytes += b
+                if not admit:
+                    continue
+                start = time.perf_counter()
+                systems = [(r["curve"], (r["j_first"] + j + 1) * 1.0, r["N"]) for r in admit for j in range(r["F"])]
+                ctx.plan_systems(curves, systems, precision=precision, refine_tol=1e-12, refine_max=10)
+                ctx.factor()
+                s0 = 0
+                for r in admit:
+                    ctx.solve_range(s0, r["F"], [("plane", d) for d in r["dirs"]])
+                    end = time.perf_counter()
+                    lat.append(end - (t0 + r["t"]))
+                    wait.append(start - (t0 + r["t"]))
+                    solves += r["F"] * len(r["dirs"])
+                    s0 += r["F"]
+                busy += time.perf_counter() - start
+                sizes.append(len(admit))
+            wall = time.perf_counter() - t0
+            q = lambda a, p: float(np.percentile(np.asarray(a) * 1e3, p)) if a else None
+            out.append({"rate": rate, "offered": len(reqs), "completed": len(lat), "refused": refused,
+                        "goodput_req_s": len(lat) / wall, "rhs_solves_per_s": solves / wall,
+                        "p50_ms": q(lat, 50), "p99_ms": q(lat, 99),
+                        "mean_wait_ms": float(np.mean(wait) * 1e3) if wait else None,
+                        "rounds": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
+                        "busy": busy / wall, "wall_s": wall})
+            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    finally:
+        ctx.close()
+    print(json.dumps({"metric": "serving: per-request latency (p50/p99) and goodput under Poisson arrivals",
+                      "workload": "16 star curves; bands of 10-50 frequencies on (0, 300], N 256-4096, 1-64 plane "
+                                  "waves per request; continuous batching (all waiting requests per round, "
+                                  "factored together)",
+                      "precision": precision, "duration_s": duration, "max_wait_s": max_wait,
+                      "batch_bytes": batch_bytes, "rates": out}), flush=True)
+
+
 def serve_bench(fhw, torch, Wk, rates, duration, max_wait, precision):
     """The serving configuration, one request at a time in arrival order
     (FIFO) on one context: per request a band plan of its curve, N and
@@ -288,6 +378,9 @@ def main():
     ap.add_argument("--rates", default="5,10,20,50", help="serve: arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--max-wait", type=float, default=2.0, help="serve: refuse requests queued longer (s)")
+    ap.add_argument("--serve-mode", default="batched", choices=["batched", "fifo"],
+                    help="serve: continuous batching of waiting requests, or one request at a time")
+    ap.add_argument("--batch-gb", type=float, default=64.0, help="serve (batched): matrix bytes per round (GB)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -307,8 +400,11 @@ def main():
         batch_sweep(fhw, torch, Wk, [1, 16, 256, 1024], a.modes.split(","), 10)
         return
     if a.workload == "serve":
-        serve_bench(fhw, torch, Wk, [float(x) for x in a.rates.split(",")], a.duration, a.max_wait,
-                    a.modes.split(",")[0])
+        rates = [float(x) for x in a.rates.split(",")]
+        if a.serve_mode == "batched":
+            serve_batched(fhw, torch, Wk, rates, a.duration, a.max_wait, a.modes.split(",")[0], a.batch_gb * 1e9)
+        else:
+            serve_bench(fhw, torch, Wk, rates, a.duration, a.max_wait, a.modes.split(",")[0])
         return
 
     wl = Wk.kite_n1024(F=a.freqs)
