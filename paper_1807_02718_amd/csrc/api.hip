@@ -27,6 +27,7 @@ struct chunk_t {
     fhw_lu_sched sched;
     int64_t psi_base = 0;       // element offset of psi_j0
     int64_t vec_elems = 0;      // sum N over the chunk
+    hipGraphExec_t lu_graph = nullptr;   // the factorization's launches, captured once per plan
 };
 
 struct plan_ext {
@@ -64,7 +65,11 @@ void curve_eval_host(const fhw_host_curve& cv, double s, double& x1, double& x2,
 
 void free_plan(fhw_ctx* c) {
     auto it = g_plans.find(c);
-    if (it != g_plans.end()) g_plans.erase(it);
+    if (it != g_plans.end()) {
+        for (auto& ch : it->second.chunks)
+            if (ch.lu_graph) (void)hipGraphExecDestroy(ch.lu_graph);
+        g_plans.erase(it);
+    }
     for (auto& kv : c->geoms) {
         (void)hipFree(kv.second.geom);
         (void)hipFree(kv.second.R);
@@ -249,6 +254,7 @@ int fhw_destroy(fhw_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     free_plan(c);
     free_workspace(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->scratch) (void)hipFree(c->scratch);
     for (auto& r : c->prof.recs) {
         (void)hipEventDestroy(r.a);
@@ -576,6 +582,34 @@ static int winding_number(const fhw_host_curve& cv, double a, double b, double* 
     return (int)lround(tot / (2.0 * M_PI));
 }
 
+// The factorization of a chunk as one graph launch: its launch sequence (all
+// kernels; no memory set or copy nodes) is captured on the context's capture
+// stream at the first solve of the plan and replayed on the work stream
+// afterwards.  The graph holds the plan's device pointers, so a new plan
+// drops it (free_plan).
+static int launch_factor_graph(fhw_ctx* c, chunk_t& ch, const fhw_batch_dev& bd, void* LU) {
+    if (!ch.lu_graph) {
+        if (!c->cap_stream) FHW_HIP(c, hipStreamCreate(&c->cap_stream));
+        lu_prepare(c->prob.precision);
+        // nothing executes during the capture; the graph runs on the work
+        // stream, in order with the work before and after it
+        FHW_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = launch_lu_factor(c->cap_stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv,
+                                        c->d_status, c->prob.precision, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ch.lu_graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ch.lu_graph = nullptr;
+            return fhw_hip_check(c, e, "factorization graph capture");
+        }
+    }
+    FHW_HIP(c, hipGraphLaunch(ch.lu_graph, c->stream));
+    return FHW_OK;
+}
+
 // The incidences on one factored batch, in groups of up to FHW_INC_GROUP
 // (one launch per step for a whole group: a second grid dimension), each
 // with its own slot of g and r: boundary data (inc == NULL: the plan's plane
@@ -674,8 +708,14 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count,
                                                                 ch.asm_blocks, p.direction[0], p.direction[1], c->A64,
                                                                 fp32 ? c->A32 : nullptr, g));
-            FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv, c->d_status,
-                                        p.precision, &c->prof));
+            if (c->prof.on) {
+                // per-stage timers need the launches one by one
+                FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv,
+                                            c->d_status, p.precision, &c->prof));
+            } else {
+                int rc = launch_factor_graph(c, ch, bd, LU);
+                if (rc) return rc;
+            }
         }
         {
             int rc = solve_groups(c, bd, ch.maxN, ch.d_items, 0, ch.vec_elems, inc, n_inc, psid + ch.psi_base, total,

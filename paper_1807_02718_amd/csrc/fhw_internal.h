@@ -109,6 +109,7 @@ struct fhw_ctx {
     int32_t* d_sweeps = nullptr;       // [chunk]
 
     fhw_prof prof;
+    hipStream_t cap_stream = nullptr;  // graph capture (created on first use, default priority)
 
     // generic scratch (synthesis)
     void* scratch = nullptr;
@@ -193,6 +194,8 @@ struct fhw_lu_sched {
     std::vector<int32_t> prefix;         // concatenated per-op tile prefix arrays
 };
 void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch);
+// kernel attributes the factorization needs, set outside any stream capture
+void lu_prepare(int precision);
 hipError_t launch_lu_factor(hipStream_t s, const fhw_batch_dev& b, const fhw_lu_sched& sch,
                             const int32_t* d_prefix, void* A, int32_t* piv, void* linv,
                             int32_t* d_status, int precision, fhw_prof* prof);

@@ -903,6 +903,11 @@ static hipError_t lu_factor_t(hipStream_t s, const fhw_batch_dev& bd, const fhw_
     return hipSuccess;
 }
 
+void lu_prepare(int precision) {
+    if (precision == FHW_FP64) lu_set_lds_limits<double>();
+    else lu_set_lds_limits<float>();
+}
+
 hipError_t launch_lu_factor(hipStream_t s, const fhw_batch_dev& b, const fhw_lu_sched& sch,
                             const int32_t* d_prefix, void* A, int32_t* piv, void* linv, int32_t* d_status,
                             int precision, fhw_prof* prof) {

@@ -671,6 +671,29 @@ def test_requests_alone_and_in_the_mix(fhw, precision):
         c.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_factorization_graph_replays(ctx, precision):
+    """The factorization runs as one captured graph when the stage timers are
+    off: replayed several times, with eager work and synchronizations between
+    the replays, every result equals the eager (timed, launch by launch) one."""
+    say("factorization graph replays", precision)
+    ctx.plan(Wk.kite(), 30.0, 12, precision=precision, refine_tol=1e-12, refine_max=10,
+             ppw=10.0, n_min=64, n_mult=32, n_cap=4096)
+    ctx.profile(True)
+    psi_e, res_e, _ = ctx.solve_densities()
+    ctx.profile(False)
+    psi_e = psi_e.clone()
+    obs = Wk.ring(8, 3.0)
+    for rep in range(4):
+        psi, res, _ = ctx.solve_densities()
+        V = ctx.eval_field(psi, obs)
+        x = torch.ones(1 << 20, dtype=torch.float64, device="cuda").cumsum(0)
+        torch.cuda.synchronize()
+        assert torch.equal(psi, psi_e), rep
+        assert np.array_equal(res, res_e)
+        assert float(x[-1]) == float(1 << 20) and torch.isfinite(V).all()
+
+
 def test_budget_too_small(fhw):
     """A workspace budget below one frequency's needs is FHW_E_NOMEM at plan
     time, and the context stays usable."""
