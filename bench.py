@@ -81,8 +81,8 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
 # HBM bytes per launch of the trailing update on this workload, from rocprofv3
 # FETCH_SIZE (x2: a 1 GiB copy reads as 0.5 GiB, its 128 B requests counted at
 # 64 B) plus WRITE_SIZE; valid only for the lu.hip source with this sha256.
-UPDATE_TRAFFIC = {"lu_sha256": "ea56a03ad8d82df809614a87cf40e2610c051471f2d765c1257bb8f233a77822",
-                  "fp32_refine": 2.623e9, "fp64": 5.427e9}
+UPDATE_TRAFFIC = {"lu_sha256": "8ff4b3c2fcc1fd50035b01c2a640d9504ac3d045a2e76d28d03321a23187d3df",
+                  "fp32_refine": 2.623e9, "fp64": 5.422e9}
 
 
 def update_traffic(mode):
