@@ -191,6 +191,42 @@ def batch_sweep(fhw, torch, Wk, batches, modes, reps):
           flush=True)
 
 
+def tracking_bench(fhw, torch, Wk, reps):
+    """fhw_synthesize with and without active-partition tracking on a signal
+    that is silent over most of its range: the validation pulse (centre 15,
+    band below 24) sampled to t = 1000, 256 points with delays in [-1, 2]
+    (pure-delay spectrum V = e^{i w d_r}), 4096 times on [0, 990]; W = 24,
+    F = 128, H = 10, tau0 = 3.  Median of reps timed calls each."""
+    W, F, H, tau0 = 24.0, 128, 10.0, 3.0
+    sig = Wk.gaussian_pulse(t0=0.0, t1=1000.0, dt=1.0 / 64, center=15.0, var2=1.0, freq=10.0)
+    ctx = fhw.Context()
+    try:
+        ctx.plan(Wk.circle(1.0), W, F, N=64)
+        omega_l = -W + (W / F) * np.arange(2 * F)
+        d = np.linspace(-1.0, 2.0, 256)
+        V = torch.as_tensor(np.exp(1j * omega_l[None, :] * d[:, None]), device="cuda")
+        times = np.linspace(0.0, 990.0, 4096)
+        f = torch.as_tensor(sig.f, device="cuda")
+        res = {}
+        for tol in (0.0, 1e-14):
+            ts = []
+            for _ in range(reps + 1):
+                t0 = time.perf_counter()
+                u = ctx.synthesize(f, sig.t0, sig.dt, H, tau0, V, times, track_tol=tol)
+                ts.append(time.perf_counter() - t0)
+            pairs, active = ctx.synth_active_pairs()
+            res[tol] = (float(np.median(ts[1:])), pairs, active, u.cpu().numpy())
+        diff = float(np.max(np.abs(res[1e-14][3] - res[0.0][3])) / np.max(np.abs(res[0.0][3])))
+        exact = -np.exp(-(times[None, :] - d[:, None] - 15.0) ** 2) * np.cos(10.0 * (times[None, :] - d[:, None]))
+        err = float(np.max(np.abs(res[1e-14][3] - exact)))
+    finally:
+        ctx.close()
+    print(json.dumps({"metric": "synthesis with active-partition tracking (pulse silent over most of [0, 1000])",
+                      "points": 256, "times": 4096, "untracked_ms": 1e3 * res[0.0][0], "tracked_ms": 1e3 * res[1e-14][0],
+                      "pairs": res[0.0][1], "active_pairs_tracked": res[1e-14][2], "track_tol": 1e-14,
+                      "rel_change": diff, "max_abs_err_vs_exact": err}), flush=True)
+
+
 def serve_batched(fhw, torch, Wk, rates, duration, max_wait, precision, batch_bytes):
     """The serving configuration with continuous batching: before each round,
     every request that has arrived (and is not past max_wait in the queue) is
@@ -371,7 +407,8 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=50, help="isolated-solve latency samples (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
-    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep"],
+    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep",
+                                                                "tracking"],
                     help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
                          "serve: Poisson request stream (per-request latency); batch_sweep: solves/s at "
                          "batches of 1, 16, 256, 1024 frequencies")
@@ -395,6 +432,9 @@ def main():
     from paper_1807_02718_amd import fhw
     if a.workload == "stars":
         star_batch_bench(fhw, torch, Wk.star_batch(), a.steps, a.warmup)
+        return
+    if a.workload == "tracking":
+        tracking_bench(fhw, torch, Wk, 5)
         return
     if a.workload == "batch_sweep":
         batch_sweep(fhw, torch, Wk, [1, 16, 256, 1024], a.modes.split(","), 10)

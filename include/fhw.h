@@ -226,9 +226,15 @@ typedef struct {
 } fhw_signal;
 
 /* Partition of unity (Sec. 3.1): s_k = 1.5 H (k - 1), half-width H; tau0 is an
- * extra recentring shift (0 = the paper's choice). */
+ * extra recentring shift (0 = the paper's choice).  track_tol > 0 turns on
+ * active-partition tracking (Sec. 3.1, remark on tracking): at observation
+ * point r, window k is left out when sum_m |Re c_{k,m}(r)| <= track_tol times
+ * the largest such sum over all (k, r); since |sinc| <= 1 each left-out
+ * window changes u(r, t) by at most W/pi times its sum.  0 = every window of
+ * the fixed rule |t - s_k - tau0| <= pi F / W. */
 typedef struct {
     double H, tau0;
+    double track_tol;
 } fhw_windows;
 
 /* Steps F1-F2 and T0-T6: scattered field u[r][t] (device doubles [N_r][N_t])
@@ -251,6 +257,11 @@ int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
 int fhw_run(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win, const double* obs, int32_t N_r,
             const double* times, int32_t N_t, void* psi, void* V, double* u, double* resid,
             int32_t* sweeps);
+
+/* Tracking statistics of the last fhw_synthesize on this context: pairs =
+ * (window, point) pairs of the fixed rule, active = those kept (= pairs when
+ * tracking was off).  [host] outputs.  FHW_E_STATE before any synthesis. */
+int fhw_synth_active_pairs(fhw_ctx* ctx, int64_t* pairs, int64_t* active);
 
 /* ---------------- stage entry points (same kernels, caller buffers) -------- */
 

@@ -329,32 +329,43 @@ def active_windows(t: float, ks, H: float, tau0: float, dw: float):
     return np.abs(t - s - tau0) <= np.pi / dw
 
 
-def synthesize(V_full, Bslow, ks, H, tau0, W, times):
+def synthesize(V_full, Bslow, ks, H, tau0, W, times, track_tol=0.0):
     """u(r, t) = sum_{k in A(t)} u_k^{W,J}(r, t) with
         u_k(r, t) = (1/2pi) int_{-W}^{W} B_k^slow(w) V(r, w) e^{-i w (t - s_k)} dw
                   = Re (W/pi) sum_m c_{k,m}(r) sinc(W (t - s_k - tau0)/pi - m),
     c_{k,m}(r) the Fourier coefficients of B_k^slow V e^{-i w tau0} on [-W, W).
+    track_tol > 0: active-partition tracking (Sec. 3.1, remark on tracking:
+    a partition enters a region only where it exceeds a tolerance there).
+    Partition k is left out at point r when b_k(r) = sum_m |Re c_{k,m}(r)|,
+    which bounds |u_k(r, .)| / (W/pi) since |sinc| <= 1, is at most track_tol
+    times the largest b over the partitions active at some sample time.
     Returns (u, max |Im|) where Im is the imaginary part before taking Re."""
     Nr, M = V_full.shape
     F = M // 2
     dw = W / F
     omega_l = -W + dw * np.arange(M)
     m = np.arange(-F, F)
+    times = np.asarray(times)
     u = np.zeros((Nr, len(times)))
     im_max = 0.0
     shift = np.exp(-1j * omega_l * tau0)
+    parts = []
     for ik, k in enumerate(ks):
         sk = window_center(k, H)
-        G = Bslow[ik][None, :] * V_full * shift[None, :]
-        c = fourier_coefficients(G, W)                        # (Nr, 2F)
-        act = np.abs(np.asarray(times) - sk - tau0) <= np.pi / dw
+        act = np.abs(times - sk - tau0) <= np.pi / dw
         if not np.any(act):
             continue
-        tt = np.asarray(times)[act]
+        G = Bslow[ik][None, :] * V_full * shift[None, :]
+        c = fourier_coefficients(G, W)                        # (Nr, 2F)
+        parts.append((sk, act, c, np.sum(np.abs(c.real), axis=1)))
+    cut = track_tol * max((float(np.max(b)) for _, _, _, b in parts), default=0.0) if track_tol > 0 else -1.0
+    for sk, act, c, b in parts:
+        keep = b > cut
+        tt = times[act]
         S = np.sinc(W * (tt[None, :] - sk - tau0) / np.pi - m[:, None])   # (2F, nt)
         uk = (W / np.pi) * (c @ S)
         im_max = max(im_max, float(np.max(np.abs(uk.imag))) if uk.size else 0.0)
-        u[:, act] += uk.real
+        u[np.ix_(keep, act)] += uk.real[keep]
     return u, im_max
 
 

@@ -929,8 +929,10 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     if (N_r == 0 || N_t == 0) return FHW_OK;
     if (!V || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
         return fhw_fail(c, FHW_E_INVALID, "synthesize: bad signal or buffers");
-    const double H = win->H, tau0 = win->tau0;
+    const double H = win->H, tau0 = win->tau0, ttol = win->track_tol;
     if (!(H > 0) || !isfinite(H) || !isfinite(tau0)) return fhw_fail(c, FHW_E_INVALID, "synthesize: bad windows");
+    if (!(ttol >= 0) || !isfinite(ttol)) return fhw_fail(c, FHW_E_INVALID, "synthesize: track_tol must be >= 0");
+    const bool track = ttol > 0;
     const int F = c->prob.F;
     const int M = 2 * F;
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F must be a power of two");
@@ -972,7 +974,9 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     size_t o_k = align_up(o_s + std::max<size_t>(1, slot.size()) * 4, 256);
     size_t o_B = align_up(o_k + std::max<size_t>(1, klist.size()) * 8, 256);
     size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
-    size_t total = align_up(o_c + (size_t)count * N_r * M * 8, 256);   // real parts of c
+    size_t o_bnd = align_up(o_c + (size_t)count * N_r * M * 8, 256);   // real parts of c
+    size_t o_max = align_up(o_bnd + (size_t)count * N_r * 8, 256);      // tracking bounds
+    size_t total = align_up(o_max + 8, 256);
     int rc = fhw_ensure_scratch(c, total);
     if (rc) return rc;
     char* sb = (char*)c->scratch;
@@ -983,13 +987,20 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
         FHW_HIP(c, hipMemcpyAsync(sb + o_k, klist.data(), klist.size() * 8, hipMemcpyHostToDevice, c->stream));
     STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, H, 0, (const int64_t*)(sb + o_k),
                                      count, W, F, sb + o_B));
+    double* bnd = track ? (double*)(sb + o_bnd) : nullptr;
+    unsigned long long* gmax = track ? (unsigned long long*)(sb + o_max) : nullptr;
+    if (track) FHW_HIP(c, hipMemsetAsync(gmax, 0, 8, c->stream));
     STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
-                                                     (double*)(sb + o_c)));
+                                                     (double*)(sb + o_c), bnd, gmax));
+    c->trk_pairs = (int64_t)count * N_r;
+    c->trk_bnd_off = o_bnd;
+    c->trk_max_off = o_max;
+    c->trk_tol = ttol;
     if (count == 0) {
         FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
     } else {
         STAGE(c, FHW_STAGE_SYNTH, launch_synth(c->stream, sb + o_c, (const int32_t*)(sb + o_s), k_lo, k_hi, count, N_r,
-                                (const double*)(sb + o_t), N_t, W, F, H, tau0, u));
+                                (const double*)(sb + o_t), N_t, W, F, H, tau0, u, bnd, gmax, ttol));
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
@@ -1009,6 +1020,27 @@ int fhw_run(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const dou
     rc = fhw_eval_field(c, psi, obs, N_r, 1.0, V);
     if (rc) return rc;
     return fhw_synthesize(c, sig, win, V, N_r, times, N_t, u);
+}
+
+int fhw_synth_active_pairs(fhw_ctx* c, int64_t* pairs, int64_t* active) {
+    if (!c) return FHW_E_INVALID;
+    if (!pairs || !active) return fhw_fail(c, FHW_E_INVALID, "synth_active_pairs: null output");
+    if (c->trk_pairs < 0) return fhw_fail(c, FHW_E_STATE, "synth_active_pairs: no synthesis yet");
+    *pairs = c->trk_pairs;
+    *active = c->trk_pairs;
+    if (c->trk_tol > 0 && c->trk_pairs > 0) {
+        std::vector<double> b((size_t)c->trk_pairs);
+        unsigned long long mx = 0;
+        FHW_HIP(c, hipStreamSynchronize(c->stream));
+        FHW_HIP(c, hipMemcpy(b.data(), (char*)c->scratch + c->trk_bnd_off, 8 * b.size(), hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(&mx, (char*)c->scratch + c->trk_max_off, 8, hipMemcpyDeviceToHost));
+        double gm;
+        memcpy(&gm, &mx, 8);
+        int64_t n = 0;
+        for (double v : b) n += v > c->trk_tol * gm ? 1 : 0;
+        *active = n;
+    }
+    return FHW_OK;
 }
 
 // ----------------------------- stage entry points ---------------------------

@@ -110,6 +110,10 @@ struct fhw_ctx {
 
     fhw_prof prof;
     hipStream_t cap_stream = nullptr;  // graph capture (created on first use, default priority)
+    // the last fhw_synthesize's tracking data (in scratch): bounds [count][N_r], max, tolerance
+    int64_t trk_pairs = -1;            // -1: no synthesis yet
+    size_t trk_bnd_off = 0, trk_max_off = 0;
+    double trk_tol = 0.0;
 
     // generic scratch (synthesis)
     void* scratch = nullptr;
@@ -233,9 +237,15 @@ hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
 hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, double t0, double dt,
                                  double H, int64_t k_first, const int64_t* d_klist, int32_t count,
                                  double W, int32_t F, void* B);
-// c: complex128 [count][N_r][2F]; or, with c == NULL, real parts only into c_re
+// c: complex128 [count][N_r][2F]; or, with c == NULL, real parts only into c_re.
+// bnd (optional, tracking): [count][N_r] sums of |Re c_m|, their maximum into
+// *gmax (as the bits of a double; zero before the call)
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V,
-                                 int32_t N_r, double W, int32_t F, double tau0, void* c, double* c_re);
+                                 int32_t N_r, double W, int32_t F, double tau0, void* c, double* c_re,
+                                 double* bnd = nullptr, unsigned long long* gmax = nullptr);
+// bnd != NULL: skip window slot sl at point r when bnd[sl N_r + r] <= tol * (*gmax)
 hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min,
                         int64_t k_max, int32_t n_slots, int32_t N_r, const double* times,
-                        int32_t N_t, double W, int32_t F, double H, double tau0, double* u);
+                        int32_t N_t, double W, int32_t F, double H, double tau0, double* u,
+                        const double* bnd = nullptr, const unsigned long long* gmax = nullptr,
+                        double tol = 0.0);

@@ -92,9 +92,14 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
 // c_m = (-1)^m X[m mod M] / M stored at index m + F: complex128 into c, or,
 // when c_re is given instead, only the real parts (all the synthesis needs:
 // its sinc weights are real and the field is the real part of the sum).
+// With bnd given (tracking): also bnd[q N_r + r] = sum_m |Re c_m| in a fixed
+// order, and the largest such bound into *gmax (the bits of a non-negative
+// double order as an unsigned integer; *gmax starts at 0).
 __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __restrict__ B, const zd* __restrict__ V,
                                                                 int N_r, double W, int F, int logM, double tau0,
-                                                                zd* __restrict__ c, double* __restrict__ c_re) {
+                                                                zd* __restrict__ c, double* __restrict__ c_re,
+                                                                double* __restrict__ bnd,
+                                                                unsigned long long* __restrict__ gmax) {
     extern __shared__ zd X[];
     const int r = blockIdx.x;
     const int q = blockIdx.y;
@@ -127,12 +132,26 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
     }
     const int64_t base = ((int64_t)q * N_r + r) * M;
     const double inv = 1.0 / (double)M;
+    double babs = 0.0;
     for (int idx = threadIdx.x; idx < M; idx += SYN_THREADS) {
         const int m = idx - F;
         const zd x = X[(idx + F) % M];
         const double sg = (m & 1) ? -inv : inv;
         if (c_re) c_re[base + idx] = sg * x.re;
         else c[base + idx] = cmk(sg * x.re, sg * x.im);
+        babs += fabs(x.re) * inv;
+    }
+    if (bnd) {
+        __shared__ double red[SYN_THREADS / 64];
+        babs = wave_sum(babs);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = babs;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < SYN_THREADS / 64; ++w) t += red[w];
+            bnd[(int64_t)q * N_r + r] = t;
+            atomicMax(gmax, (unsigned long long)__double_as_longlong(t));
+        }
     }
 }
 
@@ -155,10 +174,15 @@ __device__ __forceinline__ double synth_recip(double y) {
     return fma(r, e, r);
 }
 
+// Tracking (bnd != NULL): window slot sl is skipped at point r when
+// bnd[sl N_r + r] <= tol * gmax; its whole contribution is bounded by
+// (W/pi) bnd (|sinc| <= 1).
 __global__ __launch_bounds__(SYN_THREADS, 4) void k_synth(const double* __restrict__ cre, const int* __restrict__ slot,
                                                        int64_t k_min, int64_t k_max, int N_r,
                                                        const double* __restrict__ times, int N_t, double W, int F,
-                                                       double H, double tau0, double* __restrict__ u) {
+                                                       double H, double tau0, double* __restrict__ u,
+                                                       const double* __restrict__ bnd,
+                                                       const unsigned long long* __restrict__ gmax, double tol) {
     const int nblk = (N_t + ST - 1) / ST;
     const int64_t wave = (int64_t)blockIdx.x * (SYN_THREADS / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -178,12 +202,14 @@ __global__ __launch_bounds__(SYN_THREADS, 4) void k_synth(const double* __restri
     }
     ka = max(ka, k_min);
     kb = min(kb, k_max);
+    const double cut = bnd ? tol * __longlong_as_double((long long)*gmax) : -1.0;
     double tot[ST];
 #pragma unroll
     for (int q = 0; q < ST; ++q) tot[q] = 0.0;
     for (int64_t k = ka; k <= kb; ++k) {
         const int sl = slot[k - k_min];
         if (sl < 0) continue;
+        if (bnd && bnd[(int64_t)sl * N_r + r] <= cut) continue;   // inactive here
         const double sk = 1.5 * H * ((double)k - 1.0);
         double xq[ST], scale[ST], part[ST];
         bool use[ST];
@@ -233,24 +259,25 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
 }
 
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V, int32_t N_r, double W,
-                                 int32_t F, double tau0, void* c, double* c_re) {
+                                 int32_t F, double tau0, void* c, double* c_re, double* bnd,
+                                 unsigned long long* gmax) {
     if (count <= 0 || N_r <= 0) return hipSuccess;
     const int M = 2 * F;
     int logM = 0;
     while ((1 << logM) < M) ++logM;
     size_t lds = (size_t)M * sizeof(zd);
     hipLaunchKernelGGL(k_fourier_coeffs, dim3(N_r, count), dim3(SYN_THREADS), lds, s, (const zd*)B, (const zd*)V,
-                       N_r, W, F, logM, tau0, (zd*)c, c_re);
+                       N_r, W, F, logM, tau0, (zd*)c, c_re, bnd, gmax);
     return hipGetLastError();
 }
 
 hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min, int64_t k_max,
                         int32_t n_slots, int32_t N_r, const double* times, int32_t N_t, double W, int32_t F, double H,
-                        double tau0, double* u) {
+                        double tau0, double* u, const double* bnd, const unsigned long long* gmax, double tol) {
     (void)n_slots;
     const int64_t waves = (int64_t)N_r * ((N_t + ST - 1) / ST);
     if (waves <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_synth, dim3((unsigned)((waves + 3) / 4)), dim3(SYN_THREADS), 0, s, (const double*)c, d_slot,
-                       k_min, k_max, N_r, times, N_t, W, F, H, tau0, u);
+                       k_min, k_max, N_r, times, N_t, W, F, H, tau0, u, bnd, gmax, tol);
     return hipGetLastError();
 }

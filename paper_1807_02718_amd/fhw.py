@@ -49,7 +49,7 @@ class fhw_signal(C.Structure):
 
 
 class fhw_windows(C.Structure):
-    _fields_ = [("H", C.c_double), ("tau0", C.c_double)]
+    _fields_ = [("H", C.c_double), ("tau0", C.c_double), ("track_tol", C.c_double)]
 
 
 class fhw_incidence(C.Structure):
@@ -87,6 +87,7 @@ def _load():
         "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
         "fhw_eval_field_curve": [vp, i32, vp, _dp, i32, C.c_double, vp],
         "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
+        "fhw_synth_active_pairs": [vp, p_i64, p_i64],
         "fhw_run": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), _dp, i32, _dp, i32, vp, vp, vp, _dp, p_i32],
         "fhw_geometry": [vp, i32, vp],
         "fhw_kress_weights": [vp, i32, vp, vp],
@@ -111,7 +112,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
             "fhw_plan_systems", "fhw_factor", "fhw_solve_range",
-            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
@@ -303,10 +304,10 @@ class Context:
                                                   _ptr(V)))
         return V
 
-    def synthesize(self, f, t0, dt, H, tau0, V, times, u=None):
+    def synthesize(self, f, t0, dt, H, tau0, V, times, u=None, track_tol=0.0):
         f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
         sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
-        wn = fhw_windows(float(H), float(tau0))
+        wn = fhw_windows(float(H), float(tau0), float(track_tol))
         th, tp = _host(times, np.float64)
         Nr = V.shape[0]
         if u is None:
@@ -320,7 +321,7 @@ class Context:
         Returns (u, psi, V, resid, sweeps)."""
         f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
         sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
-        wn = fhw_windows(float(H), float(tau0))
+        wn = fhw_windows(float(H), float(tau0), 0.0)
         obs_h, obs_p = _host(obs, np.float64)
         th, tp = _host(times, np.float64)
         Nr = obs_h.shape[0]
@@ -335,6 +336,12 @@ class Context:
         self._check(_lib.fhw_run(self._h, C.byref(sg), C.byref(wn), obs_p, Nr, tp, len(th), _ptr(psi), _ptr(V),
                                  _ptr(u), resid.ctypes.data_as(_dp), sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
         return u, psi, V, resid, sweeps
+
+    def synth_active_pairs(self):
+        """(window, point) pairs of the last synthesis and how many tracking kept."""
+        p, a = C.c_int64(0), C.c_int64(0)
+        self._check(_lib.fhw_synth_active_pairs(self._h, C.byref(p), C.byref(a)))
+        return int(p.value), int(a.value)
 
     def geometry(self, N):
         g = torch.empty((9, N), dtype=torch.float64, device=self.device)

@@ -366,6 +366,49 @@ def test_time_leap_invariance():
     assert np.max(np.abs(u1 - u2)) <= 1e-13 * np.max(np.abs(u1))
 
 
+def _silent_tail_case():
+    """A Gaussian pulse sampled over a long, mostly silent range, a pure-delay
+    spectrum V = e^{i w d_r} (its time-domain field is -f(t - d_r) exactly)
+    and sample times spread over the whole range."""
+    W, F, H, tau0 = 24.0, 128, 10.0, 3.0
+    sig = Wk.gaussian_pulse(t0=0.0, t1=200.0, dt=1.0 / 64, center=15.0, var2=1.0, freq=10.0)
+    dw = W / F
+    omega_l = -W + dw * np.arange(2 * F)
+    d = np.linspace(-1.0, 2.0, 6)
+    V = np.exp(1j * omega_l[None, :] * d[:, None])
+    times = np.linspace(0.0, 190.0, 240)
+    ks = O.window_indices(sig.t[0], sig.t[-1], H)
+    act = np.zeros(len(ks), dtype=bool)
+    for tt in times:
+        act |= O.active_windows(tt, ks, H, tau0, dw)
+    ks = ks[act]
+    B = O.window_spectra(sig, H, ks, omega_l)
+    return W, F, H, tau0, sig, V, d, times, ks, B
+
+
+def test_tracking_drops_silent_partitions_within_its_bound():
+    """Active-partition tracking (Sec. 3.1 remark): at tolerance 1e-14 the
+    windows over the silent part of the signal leave the sum, and the field
+    changes by no more than the bound (W/pi) sum of the dropped b_k(r); the
+    field stays the exact delayed signal."""
+    W, F, H, tau0, sig, V, d, times, ks, B = _silent_tail_case()
+    u0, _ = O.synthesize(V, B, ks, H, tau0, W, times)
+    u1, _ = O.synthesize(V, B, ks, H, tau0, W, times, track_tol=1e-14)
+    # the bound, recomputed from the coefficients
+    dw = W / F
+    omega_l = -W + dw * np.arange(2 * F)
+    shift = np.exp(-1j * omega_l * tau0)
+    b = np.array([np.sum(np.abs(O.fourier_coefficients(B[i][None, :] * V * shift[None, :], W).real), axis=1)
+                  for i in range(len(ks))])                     # (K, Nr)
+    cut = 1e-14 * b.max()
+    dropped = b <= cut
+    assert dropped.sum() > 0.5 * dropped.size                   # most windows are silent
+    bound = (W / np.pi) * np.where(dropped, b, 0.0).sum(axis=0)   # per point, over all times
+    assert np.all(np.abs(u1 - u0) <= bound[:, None] + 1e-300)
+    exact = -np.exp(-(times[None, :] - d[:, None] - 15.0) ** 2) * np.cos(10.0 * (times[None, :] - d[:, None]))
+    assert np.max(np.abs(u1 - exact)) < 1e-9
+
+
 def test_grid_and_sizes():
     omega, kappa = O.frequency_grid(200.0, 512)
     assert omega[0] == 200.0 / 512 and omega[-1] == 200.0

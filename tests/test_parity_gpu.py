@@ -341,6 +341,43 @@ def test_run_one_call(ctx, fhw, precision):
     assert e.value.code == fhw.FHW_E_INVALID
 
 
+def test_synthesis_tracking(ctx):
+    """Active-partition tracking: a pulse sampled over a long silent range, a
+    pure-delay spectrum; at track_tol = 1e-14 most (window, point) pairs
+    leave the sum, the result equals the oracle's tracked synthesis and the
+    untracked one within the tracking bound, and stays the exact delayed
+    signal."""
+    say("synthesis tracking")
+    W, F, H, tau0 = 24.0, 128, 10.0, 3.0
+    sig = Wk.gaussian_pulse(t0=0.0, t1=200.0, dt=1.0 / 64, center=15.0, var2=1.0, freq=10.0)
+    ctx.plan(Wk.circle(1.0), W, F, N=64)
+    dw = W / F
+    omega_l = -W + dw * np.arange(2 * F)
+    d = np.linspace(-1.0, 2.0, 6)
+    Vh = np.exp(1j * omega_l[None, :] * d[:, None])
+    V = torch.as_tensor(Vh, device="cuda")
+    times = np.linspace(0.0, 190.0, 240)
+    f = torch.as_tensor(sig.f, device="cuda")
+    u0 = ctx.synthesize(f, sig.t0, sig.dt, H, tau0, V, times).cpu().numpy()
+    p0, a0 = ctx.synth_active_pairs()
+    u1 = ctx.synthesize(f, sig.t0, sig.dt, H, tau0, V, times, track_tol=1e-14).cpu().numpy()
+    p1, a1 = ctx.synth_active_pairs()
+    say("pairs", p1, "active untracked", a0, "tracked", a1)
+    assert p0 == a0 == p1 and a1 < 0.5 * p1
+    ks = O.window_indices(sig.t[0], sig.t[-1], H)
+    act = np.zeros(len(ks), dtype=bool)
+    for tt in times:
+        act |= O.active_windows(tt, ks, H, tau0, dw)
+    ks = ks[act]
+    B = O.window_spectra(sig, H, ks, omega_l)
+    ref1, _ = O.synthesize(Vh, B, ks, H, tau0, W, times, track_tol=1e-14)
+    scale = np.max(np.abs(ref1))
+    assert np.max(np.abs(u1 - ref1)) / scale < 1e-10
+    assert np.max(np.abs(u1 - u0)) / scale < 1e-12
+    exact = -np.exp(-(times[None, :] - d[:, None] - 15.0) ** 2) * np.cos(10.0 * (times[None, :] - d[:, None]))
+    assert np.max(np.abs(u1 - exact)) < 1e-9
+
+
 def test_synthesize_edge_cases(ctx, fhw):
     say("synthesize edges")
     wl = Wk.circle_pulse()
