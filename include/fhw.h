@@ -227,11 +227,14 @@ typedef struct {
 
 /* Partition of unity (Sec. 3.1): s_k = 1.5 H (k - 1), half-width H; tau0 is an
  * extra recentring shift (0 = the paper's choice).  track_tol > 0 turns on
- * active-partition tracking (Sec. 3.1, remark on tracking): at observation
- * point r, window k is left out when sum_m |Re c_{k,m}(r)| <= track_tol times
- * the largest such sum over all (k, r); since |sinc| <= 1 each left-out
- * window changes u(r, t) by at most W/pi times its sum.  0 = every window of
- * the fixed rule |t - s_k - tau0| <= pi F / W. */
+ * active-partition tracking (Sec. 3.1, remark on tracking).  Window k is left
+ * out everywhere when max_l (|Re B_k| + |Im B_k|) of its signal spectrum is
+ * at most track_tol times the largest over the windows (its contribution is
+ * then at most (W/pi) 2F max_l |B_k| max_l |V(r, .)|; no coefficients are
+ * computed for it), and at observation point r when sum_m |Re c_{k,m}(r)| is
+ * at most track_tol times the largest such sum over the remaining (k, r)
+ * (|sinc| <= 1: the change is at most W/pi times that sum).  0 = every
+ * window of the fixed rule |t - s_k - tau0| <= pi F / W. */
 typedef struct {
     double H, tau0;
     double track_tol;

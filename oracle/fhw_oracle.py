@@ -336,9 +336,12 @@ def synthesize(V_full, Bslow, ks, H, tau0, W, times, track_tol=0.0):
     c_{k,m}(r) the Fourier coefficients of B_k^slow V e^{-i w tau0} on [-W, W).
     track_tol > 0: active-partition tracking (Sec. 3.1, remark on tracking:
     a partition enters a region only where it exceeds a tolerance there).
-    Partition k is left out at point r when b_k(r) = sum_m |Re c_{k,m}(r)|,
-    which bounds |u_k(r, .)| / (W/pi) since |sinc| <= 1, is at most track_tol
-    times the largest b over the partitions active at some sample time.
+    Partition k is left out everywhere when its spectrum is negligible,
+    max_l (|Re B_k| + |Im B_k|) <= track_tol times the largest such maximum
+    (then |u_k| <= (W/pi) 2F max_l |B_k| max_l |V(r, .)|), and at point r
+    when b_k(r) = sum_m |Re c_{k,m}(r)|, which bounds |u_k(r, .)| / (W/pi)
+    since |sinc| <= 1, is at most track_tol times the largest b over the
+    remaining partitions; only partitions active at some sample time count.
     Returns (u, max |Im|) where Im is the imaginary part before taking Re."""
     Nr, M = V_full.shape
     F = M // 2
@@ -357,9 +360,13 @@ def synthesize(V_full, Bslow, ks, H, tau0, W, times, track_tol=0.0):
             continue
         G = Bslow[ik][None, :] * V_full * shift[None, :]
         c = fourier_coefficients(G, W)                        # (Nr, 2F)
-        parts.append((sk, act, c, np.sum(np.abs(c.real), axis=1)))
-    cut = track_tol * max((float(np.max(b)) for _, _, _, b in parts), default=0.0) if track_tol > 0 else -1.0
-    for sk, act, c, b in parts:
+        wmax = float(np.max(np.abs(Bslow[ik].real) + np.abs(Bslow[ik].imag)))
+        parts.append((sk, act, c, np.sum(np.abs(c.real), axis=1), wmax))
+    if track_tol > 0:
+        wcut = track_tol * max((w for *_, w in parts), default=0.0)
+        parts = [pt for pt in parts if pt[4] > wcut]
+    cut = track_tol * max((float(np.max(pt[3])) for pt in parts), default=0.0) if track_tol > 0 else -1.0
+    for sk, act, c, b, _ in parts:
         keep = b > cut
         tt = times[act]
         S = np.sinc(W * (tt[None, :] - sk - tau0) / np.pi - m[:, None])   # (2F, nt)

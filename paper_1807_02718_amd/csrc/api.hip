@@ -976,7 +976,8 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
     size_t o_bnd = align_up(o_c + (size_t)count * N_r * M * 8, 256);   // real parts of c
     size_t o_max = align_up(o_bnd + (size_t)count * N_r * 8, 256);      // tracking bounds
-    size_t total = align_up(o_max + 8, 256);
+    size_t o_wm = align_up(o_max + 16, 256);                            // window maxima
+    size_t total = align_up(o_wm + (size_t)std::max(count, 1) * 8, 256);
     int rc = fhw_ensure_scratch(c, total);
     if (rc) return rc;
     char* sb = (char*)c->scratch;
@@ -989,9 +990,10 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
                                      count, W, F, sb + o_B));
     double* bnd = track ? (double*)(sb + o_bnd) : nullptr;
     unsigned long long* gmax = track ? (unsigned long long*)(sb + o_max) : nullptr;
-    if (track) FHW_HIP(c, hipMemsetAsync(gmax, 0, 8, c->stream));
+    if (track) FHW_HIP(c, hipMemsetAsync(gmax, 0, 16, c->stream));   // gmax and the window-level max
     STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
-                                                     (double*)(sb + o_c), bnd, gmax));
+                                                     (double*)(sb + o_c), bnd, gmax, (double*)(sb + o_wm),
+                                                     gmax ? gmax + 1 : nullptr, ttol));
     c->trk_pairs = (int64_t)count * N_r;
     c->trk_bnd_off = o_bnd;
     c->trk_max_off = o_max;

@@ -239,10 +239,13 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
                                  double W, int32_t F, void* B);
 // c: complex128 [count][N_r][2F]; or, with c == NULL, real parts only into c_re.
 // bnd (optional, tracking): [count][N_r] sums of |Re c_m|, their maximum into
-// *gmax (as the bits of a double; zero before the call)
+// *gmax (as the bits of a double; zero before the call); windows whose
+// spectrum max wmax[q] (written here, [count]) is at most tol * (*gwmax)
+// (zero before the call) get no coefficients and bound 0
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V,
                                  int32_t N_r, double W, int32_t F, double tau0, void* c, double* c_re,
-                                 double* bnd = nullptr, unsigned long long* gmax = nullptr);
+                                 double* bnd = nullptr, unsigned long long* gmax = nullptr,
+                                 double* wmax = nullptr, unsigned long long* gwmax = nullptr, double tol = 0.0);
 // bnd != NULL: skip window slot sl at point r when bnd[sl N_r + r] <= tol * (*gmax)
 hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min,
                         int64_t k_max, int32_t n_slots, int32_t N_r, const double* times,

@@ -87,6 +87,28 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
     }
 }
 
+// Tracking, window level: wmax[q] = max_l (|Re B_q| + |Im B_q|) over the DFT
+// grid, and the largest over the windows into *gwmax (double bits, zero before).
+__global__ __launch_bounds__(SYN_THREADS) void k_window_max(const zd* __restrict__ B, int M,
+                                                            double* __restrict__ wmax,
+                                                            unsigned long long* __restrict__ gwmax) {
+    __shared__ double red[SYN_THREADS / 64];
+    const int q = blockIdx.x;
+    const zd* Bq = B + (int64_t)q * M;
+    double m = 0.0;
+    for (int l = threadIdx.x; l < M; l += SYN_THREADS) m = fmax(m, fabs(Bq[l].re) + fabs(Bq[l].im));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < SYN_THREADS / 64; ++w) t = fmax(t, red[w]);
+        wmax[q] = t;
+        atomicMax(gwmax, (unsigned long long)__double_as_longlong(t));
+    }
+}
+
 // One workgroup per (point r, window slot q): LDS radix-2 FFT of length M = 2F
 // of G_l = B_q(omega_l) V(r, omega_l) e^{-i omega_l tau0};
 // c_m = (-1)^m X[m mod M] / M stored at index m + F: complex128 into c, or,
@@ -99,10 +121,18 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
                                                                 int N_r, double W, int F, int logM, double tau0,
                                                                 zd* __restrict__ c, double* __restrict__ c_re,
                                                                 double* __restrict__ bnd,
-                                                                unsigned long long* __restrict__ gmax) {
+                                                                unsigned long long* __restrict__ gmax,
+                                                                const double* __restrict__ wmax,
+                                                                const unsigned long long* __restrict__ gwmax,
+                                                                double tol) {
     extern __shared__ zd X[];
     const int r = blockIdx.x;
     const int q = blockIdx.y;
+    if (bnd && wmax[q] <= tol * __longlong_as_double((long long)*gwmax)) {
+        // a silent window: no coefficients, bound 0 (the synthesis skips it)
+        if (threadIdx.x == 0) bnd[(int64_t)q * N_r + r] = 0.0;
+        return;
+    }
     const int M = 2 * F;
     const double dw = W / (double)F;
     const zd* Bq = B + (int64_t)q * M;
@@ -260,14 +290,18 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
 
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V, int32_t N_r, double W,
                                  int32_t F, double tau0, void* c, double* c_re, double* bnd,
-                                 unsigned long long* gmax) {
+                                 unsigned long long* gmax, double* wmax, unsigned long long* gwmax, double tol) {
     if (count <= 0 || N_r <= 0) return hipSuccess;
     const int M = 2 * F;
     int logM = 0;
     while ((1 << logM) < M) ++logM;
     size_t lds = (size_t)M * sizeof(zd);
+    if (bnd) {
+        hipLaunchKernelGGL(k_window_max, dim3(count), dim3(SYN_THREADS), 0, s, (const zd*)B, M, wmax, gwmax);
+    }
     hipLaunchKernelGGL(k_fourier_coeffs, dim3(N_r, count), dim3(SYN_THREADS), lds, s, (const zd*)B, (const zd*)V,
-                       N_r, W, F, logM, tau0, (zd*)c, c_re, bnd, gmax);
+                       N_r, W, F, logM, tau0, (zd*)c, c_re, bnd, gmax, (const double*)wmax,
+                       (const unsigned long long*)gwmax, tol);
     return hipGetLastError();
 }
 
