@@ -995,9 +995,7 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
                                                      (double*)(sb + o_c), bnd, gmax, (double*)(sb + o_wm),
                                                      gmax ? gmax + 1 : nullptr, ttol));
     c->trk_pairs = (int64_t)count * N_r;
-    c->trk_bnd_off = o_bnd;
-    c->trk_max_off = o_max;
-    c->trk_tol = ttol;
+    c->trk_active = c->trk_pairs;
     if (count == 0) {
         FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
     } else {
@@ -1005,6 +1003,18 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
                                 (const double*)(sb + o_t), N_t, W, F, H, tau0, u, bnd, gmax, ttol));
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));
+    if (track && count > 0) {
+        // pairs kept, for fhw_synth_active_pairs
+        std::vector<double> b((size_t)count * N_r);
+        unsigned long long mx = 0;
+        FHW_HIP(c, hipMemcpy(b.data(), bnd, 8 * b.size(), hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(&mx, gmax, 8, hipMemcpyDeviceToHost));
+        double gm;
+        memcpy(&gm, &mx, 8);
+        int64_t n = 0;
+        for (double v : b) n += v > ttol * gm ? 1 : 0;
+        c->trk_active = n;
+    }
     return FHW_OK;
 }
 
@@ -1029,19 +1039,7 @@ int fhw_synth_active_pairs(fhw_ctx* c, int64_t* pairs, int64_t* active) {
     if (!pairs || !active) return fhw_fail(c, FHW_E_INVALID, "synth_active_pairs: null output");
     if (c->trk_pairs < 0) return fhw_fail(c, FHW_E_STATE, "synth_active_pairs: no synthesis yet");
     *pairs = c->trk_pairs;
-    *active = c->trk_pairs;
-    if (c->trk_tol > 0 && c->trk_pairs > 0) {
-        std::vector<double> b((size_t)c->trk_pairs);
-        unsigned long long mx = 0;
-        FHW_HIP(c, hipStreamSynchronize(c->stream));
-        FHW_HIP(c, hipMemcpy(b.data(), (char*)c->scratch + c->trk_bnd_off, 8 * b.size(), hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(&mx, (char*)c->scratch + c->trk_max_off, 8, hipMemcpyDeviceToHost));
-        double gm;
-        memcpy(&gm, &mx, 8);
-        int64_t n = 0;
-        for (double v : b) n += v > c->trk_tol * gm ? 1 : 0;
-        *active = n;
-    }
+    *active = c->trk_active;
     return FHW_OK;
 }
 

@@ -110,10 +110,9 @@ struct fhw_ctx {
 
     fhw_prof prof;
     hipStream_t cap_stream = nullptr;  // graph capture (created on first use, default priority)
-    // the last fhw_synthesize's tracking data (in scratch): bounds [count][N_r], max, tolerance
+    // the last fhw_synthesize's (window, point) pairs, and how many tracking kept
     int64_t trk_pairs = -1;            // -1: no synthesis yet
-    size_t trk_bnd_off = 0, trk_max_off = 0;
-    double trk_tol = 0.0;
+    int64_t trk_active = 0;
 
     // generic scratch (synthesis)
     void* scratch = nullptr;
