@@ -379,21 +379,38 @@ def cpu_baseline(wl, n_freq):
     """The FP64 oracle on a bounded sample: n_freq frequencies spread over the
     band, each = assembly + LAPACK solve + field at all observation points."""
     import oracle as O
+    from threadpoolctl import threadpool_limits
     omega, kappa = O.frequency_grid(wl.W, wl.F)
     eta = O.coupling(kappa)
     gm = O.geometry(wl.curve, wl.N)
+
+    def timed(idx):
+        t0 = time.perf_counter()
+        for j in idx:
+            A = O.assemble(gm, kappa[j], eta[j])
+            g = O.rhs_plane_wave(gm, kappa[j], eta[j], wl.direction)
+            psi, _ = O.solve_density(A, g)
+            O.field(gm, psi, kappa[j], wl.obs)
+        return time.perf_counter() - t0
+
     idx = np.linspace(0, wl.F - 1, n_freq).round().astype(int)
-    t0 = time.perf_counter()
-    for j in idx:
-        A = O.assemble(gm, kappa[j], eta[j])
-        g = O.rhs_plane_wave(gm, kappa[j], eta[j], wl.direction)
-        psi, _ = O.solve_density(A, g)
-        O.field(gm, psi, kappa[j], wl.obs)
-    dt = time.perf_counter() - t0
+    dt = timed(idx)
+    # one BLAS thread, on a smaller sample spread over the same band
+    n1 = max(1, n_freq // 12)
+    with threadpool_limits(limits=1):
+        dt1 = timed(np.linspace(0, wl.F - 1, n1).round().astype(int))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n_freq / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "single_core_value": n1 / dt1,
             "sample": f"{n_freq} of {wl.F} frequencies (N={wl.N}): assembly + LAPACK LU solve + field at "
-                      f"{len(wl.obs)} points each, NumPy/SciPy FP64, {threads} BLAS threads; synthesis excluded"}
+                      f"{len(wl.obs)} points each, NumPy/SciPy FP64, {threads} BLAS threads "
+                      f"({n1} frequencies with one thread for single_core_value); synthesis excluded"}
 
 
 def main():
