@@ -80,16 +80,19 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
 
 # HBM bytes per launch of the trailing update on this workload, from rocprofv3
 # FETCH_SIZE (x2: a 1 GiB copy reads as 0.5 GiB, its 128 B requests counted at
-# 64 B) plus WRITE_SIZE; valid only for the lu.hip source with this sha256.
-UPDATE_TRAFFIC = {"lu_sha256": "8ff4b3c2fcc1fd50035b01c2a640d9504ac3d045a2e76d28d03321a23187d3df",
-                  "fp32_refine": 2.623e9, "fp64": 5.422e9}
+# 64 B) plus WRITE_SIZE; valid only while lu.hip + panel_table.h hash to this.
+UPDATE_TRAFFIC = {"lu_sha256": "b301e4974b12882b09c38cd31db1386f310579e2a62268db6cd999cafb738d54",
+                  "fp32_refine": 2.623e9, "fp64": 5.423e9}
 
 
 def update_traffic(mode):
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1807_02718_amd", "csrc", "lu.hip")
-    with open(src, "rb") as f:
-        same = hashlib.sha256(f.read()).hexdigest() == UPDATE_TRAFFIC["lu_sha256"]
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1807_02718_amd", "csrc")
+    text = b""
+    for name in ("lu.hip", "panel_table.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            text += f.read()
+    same = hashlib.sha256(text).hexdigest() == UPDATE_TRAFFIC["lu_sha256"]
     return UPDATE_TRAFFIC[mode] if same else None
 
 

@@ -19,6 +19,7 @@
 // later pairs; the solves replay the pivots pair by pair.
 #include "fhw_device.h"
 #include "fhw_internal.h"
+#include "panel_table.h"
 
 #define NB FHW_LU_NB
 #define PANEL_THREADS 256
@@ -819,40 +820,44 @@ static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, in
 #define FHW_PANEL(RR, WW, EE, PT)                                                                             \
     hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE, PT>), dim3(bd.batch), dim3(PT), 0, s, k0, bd.N, bd.a_off,  \
                        bd.piv_off, A, piv, st)
-    // (R, W, waves per SIMD), chosen by measurement among the spill-free
-    // register allocations
+#define FHW_PANEL_T(RR, WE, PT) FHW_PANEL_X(RR, WE, PT)
+#define FHW_PANEL_X(...) FHW_PANEL(__VA_ARGS__)
+    // (W, waves per SIMD) per case from panel_table.h, among the spill-free
+    // register allocations; R = 8 and 16 (over 1024 rows) are fixed
     if (bd.batch <= 256) {
         const int R4 = (R + 3) / 4;   // rows per thread with 1024 threads
         if constexpr (sizeof(T) == 4) {
             switch (R4) {
-                case 1: FHW_PANEL(1, 8, 4, 1024); break;
-                case 2: FHW_PANEL(2, 8, 4, 1024); break;
-                default: FHW_PANEL(4, 8, 4, 1024); break;
+                case 1: FHW_PANEL_T(1, FHW_PT_F32_1024_R1, 1024); break;
+                case 2: FHW_PANEL_T(2, FHW_PT_F32_1024_R2, 1024); break;
+                default: FHW_PANEL_T(4, FHW_PT_F32_1024_R4, 1024); break;
             }
         } else {
             switch (R4) {
-                case 1: FHW_PANEL(1, 8, 4, 1024); break;
-                case 2: FHW_PANEL(2, 4, 4, 1024); break;
-                default: FHW_PANEL(4, 4, 4, 1024); break;
+                case 1: FHW_PANEL_T(1, FHW_PT_F64_1024_R1, 1024); break;
+                case 2: FHW_PANEL_T(2, FHW_PT_F64_1024_R2, 1024); break;
+                default: FHW_PANEL_T(4, FHW_PT_F64_1024_R4, 1024); break;
             }
         }
     } else if constexpr (sizeof(T) == 4) {
         switch (R) {
-            case 1: FHW_PANEL(1, 16, 4, 256); break;
-            case 2: FHW_PANEL(2, 8, 4, 256); break;
-            case 4: FHW_PANEL(4, 8, 4, 256); break;
+            case 1: FHW_PANEL_T(1, FHW_PT_F32_256_R1, 256); break;
+            case 2: FHW_PANEL_T(2, FHW_PT_F32_256_R2, 256); break;
+            case 4: FHW_PANEL_T(4, FHW_PT_F32_256_R4, 256); break;
             case 8: FHW_PANEL(8, 4, 2, 256); break;
             default: FHW_PANEL(16, 2, 2, 256); break;
         }
     } else {
         switch (R) {
-            case 1: FHW_PANEL(1, 8, 4, 256); break;
-            case 2: FHW_PANEL(2, 8, 2, 256); break;
-            case 4: FHW_PANEL(4, 8, 2, 256); break;
+            case 1: FHW_PANEL_T(1, FHW_PT_F64_256_R1, 256); break;
+            case 2: FHW_PANEL_T(2, FHW_PT_F64_256_R2, 256); break;
+            case 4: FHW_PANEL_T(4, FHW_PT_F64_256_R4, 256); break;
             case 8: FHW_PANEL(8, 4, 2, 256); break;
             default: FHW_PANEL(16, 2, 1, 256); break;
         }
     }
+#undef FHW_PANEL_X
+#undef FHW_PANEL_T
 #undef FHW_PANEL
     return hipGetLastError();
 }

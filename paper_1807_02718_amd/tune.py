@@ -1,0 +1,200 @@
+"""Autotuner of the LU panel kernel's tile shape (sub-panel width W and waves
+per SIMD) per precision, workgroup size and rows per thread.
+
+    python -m paper_1807_02718_amd.tune build     # CPU: variant libraries
+    python -m paper_1807_02718_amd.tune measure   # GPU: time them
+    python -m paper_1807_02718_amd.tune write     # CPU: csrc/panel_table.h
+
+Each variant differs from the current table (csrc/panel_table.h) in one case,
+set to one candidate whose registers fit without spilling (checked from the
+compiler's resource report). `measure` times the panel stage of
+fhw_solve_densities with the library's own HIP-event timers on the kite: for the
+256-thread cases (batches above 256 matrices) N = 1024 with 1024 frequencies,
+whose shrinking panels pass through R = 4, 2 and 1; for the 1024-thread cases
+the sum of N = 1024 with 64 frequencies (R = 1) and N = 4096 with 16
+frequencies (R = 4, 2, 1).  `write` keeps, per case, the fastest variant if it
+beats the current table by more than 1%.  The R = 8 and 16 shapes (256
+threads, N above 1024) are fixed: one shape per case fits without spilling.
+"""
+from __future__ import annotations
+
+import json
+import os
+import re
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+TUNE = os.path.join(HERE, "_tune")
+TABLE = os.path.join(CSRC, "panel_table.h")
+
+# candidate (W, waves per SIMD) per case; the spill check drops the rest
+CANDIDATES = {
+    256: [(4, 4), (8, 4), (8, 2), (16, 2)],
+    1024: [(4, 4), (8, 4)],
+}
+CASES = [(p, pt, r) for p in ("F32", "F64") for pt in (256, 1024) for r in (1, 2, 4)]
+
+
+def case_name(p, pt, r):
+    return f"FHW_PT_{p}_{pt}_R{r}"
+
+
+def read_table(path=TABLE):
+    tab = {}
+    for m in re.finditer(r"#define (FHW_PT_\w+) (\d+), (\d+)", open(path).read()):
+        tab[m.group(1)] = (int(m.group(2)), int(m.group(3)))
+    return tab
+
+
+def write_table(tab, path=TABLE):
+    src = open(TABLE).read()
+    for name, (w, e) in tab.items():
+        src = re.sub(rf"#define {name} \d+, \d+", f"#define {name} {w}, {e}", src)
+    open(path, "w").write(src)
+
+
+def variants():
+    """name -> (table, changed case or None)."""
+    base = read_table()
+    out = {"base": (dict(base), None)}
+    for p, pt, r in CASES:
+        name = case_name(p, pt, r)
+        for w, e in CANDIDATES[pt]:
+            if (w, e) == base[name]:
+                continue
+            t = dict(base)
+            t[name] = (w, e)
+            out[f"{name}_W{w}_E{e}"] = (t, (p, pt, r))
+    return out
+
+
+def _spill_free(report, p, pt, r, w, e):
+    """The panel instantiation of this case compiled without VGPR spills."""
+    T = "f" if p == "F32" else "d"
+    key = f"k_lu_panelI{T}Li{r}ELi{w}ELi{e}ELi{pt}E"
+    blocks = report.split("Function Name: ")
+    for b in blocks:
+        if b.startswith("_Z10") and key in b.split()[0]:
+            m = re.search(r"VGPRs Spill: (\d+)", b)
+            return m is not None and int(m.group(1)) == 0
+    return False
+
+
+def build(jobs=4):
+    from . import build as B
+    B.build(jobs=jobs)   # the other objects, current table
+    objs = [os.path.join(B.BUILD, s.replace(".hip", ".o")) for s in B.SOURCES if s != "lu.hip"]
+    shutil.rmtree(TUNE, ignore_errors=True)
+    os.makedirs(TUNE)
+    vs = variants()
+
+    def one(item):
+        name, (tab, case) = item
+        d = os.path.join(TUNE, name)
+        os.makedirs(os.path.join(d, "paper_1807_02718_amd"))
+        shutil.copy(os.path.join(CSRC, "lu.hip"), d)
+        shutil.copy(TABLE, d)
+        write_table(tab, os.path.join(d, "panel_table.h"))
+        o = os.path.join(d, "lu.o")
+        r = subprocess.run([B.HIPCC, *B.FLAGS, "-I", CSRC, "-c", os.path.join(d, "lu.hip"), "-o", o,
+                            "-Rpass-analysis=kernel-resource-usage"], capture_output=True, text=True)
+        if r.returncode:
+            return name, False, r.stderr[-500:]
+        ok = case is None or _spill_free(r.stderr, *case, *tab[case_name(*case)])
+        if not ok:
+            shutil.rmtree(d)
+            return name, False, "spills"
+        r = subprocess.run([B.HIPCC, "-shared", "-fPIC", f"--offload-arch={B.ARCH}", *objs, o, "-o",
+                            os.path.join(d, "paper_1807_02718_amd", "libfhw.so")], capture_output=True, text=True)
+        os.remove(o)
+        for f in ("__init__.py", "fhw.py"):
+            shutil.copy(os.path.join(HERE, f), os.path.join(d, "paper_1807_02718_amd", f))
+        json.dump(tab, open(os.path.join(d, "table.json"), "w"))
+        return name, r.returncode == 0, r.stderr[-300:]
+
+    with ThreadPoolExecutor(jobs) as ex:
+        for name, ok, msg in ex.map(one, vs.items()):
+            print(f"{name}: {'ok' if ok else 'skipped (' + msg.strip()[:80] + ')'}", flush=True)
+
+
+_TIMER = r"""
+import json, sys, numpy as np
+sys.path.insert(0, sys.argv[1]); sys.path.insert(1, sys.argv[2])
+import torch
+from paper_1807_02718_amd import fhw
+import workloads as Wk
+out = {}
+for prec in ("fp32_refine", "fp64"):
+    for F, N in ((1024, 1024), (64, 1024), (16, 4096)):
+        wl = Wk.kite_n1024(F=F)
+        ctx = fhw.Context()
+        ctx.plan(wl.curve, wl.W, F, N=N, precision=prec, refine_tol=1e-12, refine_max=10, direction=wl.direction)
+        psi = torch.empty(int(ctx.psi_off[-1]), dtype=torch.complex128, device="cuda")
+        ctx.solve_densities(psi)
+        ts = []
+        for _ in range(3):
+            ctx.profile(True)
+            ctx.solve_densities(psi)
+            ts.append(ctx.profile_read()["lu_panel"][0])
+            ctx.profile(False)
+        ctx.close()
+        out[f"{prec}_{F}_{N}"] = float(np.median(ts))
+print(json.dumps(out), flush=True)
+"""
+
+
+def measure():
+    root = os.path.dirname(HERE)
+    res = {}
+    for name in sorted(os.listdir(TUNE)):
+        d = os.path.join(TUNE, name)
+        if not os.path.isfile(os.path.join(d, "table.json")):
+            continue
+        r = subprocess.run([sys.executable, "-c", _TIMER, d, root], capture_output=True, text=True, timeout=300)
+        line = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+        if r.returncode or not line:
+            print(f"{name}: failed ({r.stderr.strip()[-200:]})", flush=True)
+            continue
+        res[name] = {"table": json.load(open(os.path.join(d, "table.json"))), "ms": json.loads(line[-1])}
+        print(name, res[name]["ms"], flush=True)
+    json.dump(res, open(os.path.join(TUNE, "results.json"), "w"), indent=1)
+
+
+def write():
+    res = json.load(open(os.path.join(TUNE, "results.json")))
+    base = res["base"]
+    tab = {k: tuple(v) for k, v in base["table"].items()}
+    for p, pt, r in CASES:
+        name = case_name(p, pt, r)
+        prec = "fp32_refine" if p == "F32" else "fp64"
+        keys = [f"{prec}_1024_1024"] if pt == 256 else [f"{prec}_64_1024", f"{prec}_16_4096"]
+
+        def cost(v):
+            return sum(v["ms"][k] for k in keys)
+
+        best, best_ms = tab[name], cost(base)
+        for vn, v in res.items():
+            if vn.startswith(name + "_W") and cost(v) < best_ms * 0.99:
+                best, best_ms = tuple(v["table"][name]), cost(v)
+        if best != tab[name]:
+            print(f"{name}: {tab[name]} -> {best} ({cost(base):.3f} -> {best_ms:.3f} ms panel stage)")
+        tab[name] = best
+    write_table(tab)
+    print("wrote", TABLE)
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1] if len(sys.argv) > 1 else ""
+    if cmd == "build":
+        build(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+    elif cmd == "measure":
+        measure()
+    elif cmd == "write":
+        write()
+    else:
+        print(__doc__)
+        sys.exit(2)

@@ -85,3 +85,23 @@ def test_bessel_tables_are_current():
         open(gen, "w").write(src)
         subprocess.run([sys.executable, gen], check=True, cwd=d)
         assert open(os.path.join(d, "bessel_tables.h")).read() == open(os.path.join(csrc, "bessel_tables.h")).read()
+
+
+def test_panel_table_round_trip(tmp_path):
+    """The autotuner's table: every case the panel launcher reads is defined,
+    a rewrite changes only the case asked for, and each variant differs from
+    the table in exactly one case."""
+    from paper_1807_02718_amd import tune
+    tab = tune.read_table()
+    assert set(tab) == {tune.case_name(*c) for c in tune.CASES}
+    lu = open(os.path.join(tune.CSRC, "lu.hip")).read()
+    for name in tab:
+        assert name in lu
+    name = tune.case_name("F64", 1024, 2)
+    out = tmp_path / "panel_table.h"
+    tune.write_table({name: (16, 1)}, str(out))
+    back = tune.read_table(str(out))
+    assert back[name] == (16, 1) and all(back[k] == v for k, v in tab.items() if k != name)
+    for vname, (vt, case) in tune.variants().items():
+        diff = [k for k in vt if vt[k] != tab[k]]
+        assert (case is None and not diff) or diff == [tune.case_name(*case)], vname
