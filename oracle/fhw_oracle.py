@@ -33,6 +33,7 @@ __all__ = [
     "field_full_grid", "eta_window", "window", "window_center",
     "window_indices", "window_spectra", "fourier_coefficients",
     "active_windows", "synthesize", "run", "curve_eval",
+    "scaled_convolution_fast", "synthesize_uniform",
 ]
 
 
@@ -374,6 +375,58 @@ def synthesize(V_full, Bslow, ks, H, tau0, W, times, track_tol=0.0):
         im_max = max(im_max, float(np.max(np.abs(uk.imag))) if uk.size else 0.0)
         u[np.ix_(keep, act)] += uk.real[keep]
     return u, im_max
+
+
+# ---------------------------------------------------------------------------
+# O12. Fast scaled convolution for uniform time grids (Sec. 3.3, FFT
+#      accelerated evaluation of scaled discrete convolutions:
+#      eqs. conv_sum, approx_conv_sum; Table 1)
+# ---------------------------------------------------------------------------
+def scaled_convolution_fast(a, x, L: int):
+    """Approximation of d(x) = sum_m a_m b(x - m), m = -M/2..M/2-1, with the
+    kernel b(q) = sinc(q) of eq. discConv (there 2A = P: the coefficients span
+    the whole period), by eq. approx_conv_sum with gamma = 1:
+        d(x) ~= (1/L) sum_{p=-L/2}^{L/2-1} C_p B_p e^{2 pi i p x / L},
+        C_p = sum_m a_m e^{-2 pi i m p / L},
+        B_p = sum_{q=-L/2}^{L/2-1} b(q) e^{-2 pi i q p / L},
+    that is, b replaced by its L-periodic trigonometric interpolant on the
+    integers, evaluated at the real arguments x - m (the paper's beta n - m on
+    a uniform grid).  Each sum is written out as a matrix product; no FFT.
+    a: shape (..., M), real or complex; x: the real arguments, shape (n,).
+    Returns the real part, shape (..., n)."""
+    M = a.shape[-1]
+    m = np.arange(-(M // 2), M // 2)
+    p = np.arange(-(L // 2), L // 2)
+    q = p
+    C = a @ np.exp(-2j * np.pi * np.outer(m, p) / L)
+    B = np.sinc(q) @ np.exp(-2j * np.pi * np.outer(q, p) / L)
+    E = np.exp(2j * np.pi * np.outer(p, np.asarray(x, dtype=np.float64)) / L)
+    return ((C * B) @ E).real / L
+
+
+def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: int):
+    """u(r, t_n) on the uniform grid t_n = t_first + n t_step, n < n_t, as
+    synthesize (same windows, coefficients and active sets, no tracking) with
+    each window's sum over m, sum_m Re c_{k,m} sinc(x - m), x = W (t_n - s_k -
+    tau0)/pi, replaced by scaled_convolution_fast of size L."""
+    Nr, M = V_full.shape
+    F = M // 2
+    dw = W / F
+    omega_l = -W + dw * np.arange(M)
+    times = t_first + t_step * np.arange(n_t)
+    u = np.zeros((Nr, n_t))
+    shift = np.exp(-1j * omega_l * tau0)
+    for ik, k in enumerate(ks):
+        sk = window_center(k, H)
+        act = np.abs(times - sk - tau0) <= np.pi / dw
+        if not np.any(act):
+            continue
+        G = Bslow[ik][None, :] * V_full * shift[None, :]
+        a = fourier_coefficients(G, W).real
+        idx = np.nonzero(act)[0]
+        x = W * (times[idx] - sk - tau0) / np.pi
+        u[:, idx] += (W / np.pi) * scaled_convolution_fast(a, x, L)
+    return u
 
 
 # ---------------------------------------------------------------------------

@@ -445,3 +445,72 @@ def test_star_curve_is_polar_form():
     r = 1 + sum(a[k - 2] * np.cos(k * th + ph[k - 2]) for k in range(2, 9))
     X, _, _ = O.curve_eval(c, th)
     assert np.allclose(X, np.stack([r * np.cos(th), r * np.sin(th)], 1), atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# O12. Fast scaled convolution (Sec. 3.3, eq. approx_conv_sum): the
+# L-periodic interpolant of the sinc on the integers, against the direct sum
+# --------------------------------------------------------------------------
+def _direct_sinc_sum(a, x):
+    M = a.shape[-1]
+    m = np.arange(-(M // 2), M // 2)
+    return np.sinc(np.asarray(x)[:, None] - m[None, :]) @ a
+
+
+def test_fast_scaled_convolution_exact_at_integer_arguments():
+    """At integer x the periodic interpolant of the sinc is the unit impulse
+    (for |x - m| < L), so the fast form returns a_x exactly."""
+    rng = np.random.default_rng(11)
+    M = 128
+    a = rng.standard_normal(M)
+    x = rng.integers(-M // 2, M // 2, 60).astype(float)
+    d = O.scaled_convolution_fast(a, x, 2 * M)
+    assert np.max(np.abs(d - a[(x + M // 2).astype(int)])) < 1e-12
+
+
+def test_fast_scaled_convolution_error_falls_as_L_squared():
+    """White coefficients (content up to the band edge): the error against the
+    direct sum is O(L^-2), as the paper states: each doubling of L divides it
+    by about 4."""
+    rng = np.random.default_rng(3)
+    M = 128
+    a = rng.standard_normal(M)
+    x = rng.uniform(-M // 2, M // 2, 400)
+    d = _direct_sinc_sum(a, x)
+    err = [np.max(np.abs(O.scaled_convolution_fast(a, x, L) - d)) / np.max(np.abs(d))
+           for L in (2 * M, 4 * M, 8 * M, 16 * M)]
+    assert err[0] < 2e-2
+    for e1, e2 in zip(err[1:], err[2:]):
+        assert 3.5 < e1 / e2 < 5.0
+
+
+def test_fast_scaled_convolution_band_limited_case_at_roundoff():
+    """Coefficients of the paper's Gaussian demo spectrum, negligible at the
+    band edge: the interpolant's error, carried by the spectrum near +-W,
+    vanishes to roundoff already at L = 2M."""
+    g = GOLDEN["fourier_quadrature_demo"]
+    W = g["interval"][1]
+    F = 64
+    M = 2 * F
+    wl = -W + (W / F) * np.arange(M)
+    G = np.exp(-g["gauss_coeff"] * wl ** 2) * np.exp(1j * g["modulation"] * wl)
+    a = O.fourier_coefficients(G[None, :], W)[0].real
+    x = np.random.default_rng(5).uniform(-F, F, 300)
+    d = _direct_sinc_sum(a, x)
+    assert np.max(np.abs(O.scaled_convolution_fast(a, x, 2 * M) - d)) < 1e-13 * np.max(np.abs(d))
+
+
+def test_fast_synthesis_interior_time_domain_circle():
+    """The whole pipeline with the fast synthesis on a uniform grid: inside the
+    circle u(x, t) = -f(t - p.x) (interior extinction), and the fast samples
+    match the direct ones."""
+    pts = np.array([[0.2, 0.1], [-0.5, 0.3], [0.0, -0.6]])
+    p = np.array([0.6, 0.8])
+    t_first, t_step, n = 0.0, 0.05, 801
+    times = t_first + t_step * np.arange(n)
+    out = O.run(Wk.circle(1.0), 24.0, 128, 64, tuple(p), _pulse15(), 10.0, 3.0, pts, times, return_all=True)
+    uf = O.synthesize_uniform(out["V"], out["B"], out["ks"], 10.0, 3.0, 24.0, t_first, t_step, n, 256)
+    f = lambda t: np.exp(-(t - 15) ** 2) * np.cos(10 * t)
+    exact = np.array([-f(times - x @ p) for x in pts])
+    assert np.max(np.abs(uf - exact)) < 1e-9
+    assert np.max(np.abs(uf - out["u"])) < 1e-12 * np.max(np.abs(exact))
