@@ -20,6 +20,9 @@
  *                        T1a), sinc scaled-convolution synthesis and the sum
  *                        over windows (eqs. approx, discConv, ukW, final_u;
  *                        T2, T5)
+ *   fhw_synthesize_uniform  the same on a uniform time grid, each window's
+ *                        sum by the fast scaled convolution (Sec. 3.3, eq.
+ *                        approx_conv_sum)
  *   fhw_run              the three calls above in one
  * plus stage entry points for the same steps on caller buffers.
  *
@@ -247,6 +250,26 @@ typedef struct {
 int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
                    const void* V, int32_t N_r, const double* times, int32_t N_t,
                    double* u);
+
+/* Sec. 3.3 (FFT accelerated evaluation of scaled discrete convolutions, eqs.
+ * conv_sum and approx_conv_sum): as fhw_synthesize, on the uniform grid
+ * t_n = t_first + n t_step, n < N_t, with each window's sum over m replaced
+ * by its L-periodic approximation
+ *   sum_m Re c_{k,m} sinc(x - m) ~= (1/L) sum_{p=-L/2}^{L/2-1} C_p e^{2 pi i p x / L},
+ *   C_p = sum_m Re c_{k,m} e^{-2 pi i m p / L},   x = W (t_n - s_k - tau0) / pi,
+ * evaluated by an L-point FFT and a chirp-z (Bluestein) convolution per
+ * window, point and run of grid times.  The error against fhw_synthesize is
+ * O(L^-2), carried by the spectrum's content near +-W; it vanishes to
+ * roundoff where the spectrum is negligible there.  Same windows and active
+ * sets as fhw_synthesize (no tracking: win->track_tol must be 0).
+ *   u       device doubles [N_r][N_t], overwritten.
+ *   L       0 = 4F; else a power of two with 4F <= L <= 4096 (the chirp-z
+ *           convolution of length 2L <= 8192 lives in LDS).
+ * Errors: FHW_E_INVALID for a bad L, t_step <= 0, non-finite inputs, track_tol
+ * != 0, N_r > 65535 or 2F not a power of two; FHW_E_STATE as fhw_synthesize. */
+int fhw_synthesize_uniform(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
+                           const void* V, int32_t N_r, double t_first, double t_step,
+                           int32_t N_t, int32_t L, double* u);
 
 /* The whole hot path in one call for a plan of one curve (fhw_plan) with its
  * plane-wave direction: fhw_solve_densities (step F3), fhw_eval_field with

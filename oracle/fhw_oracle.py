@@ -404,17 +404,20 @@ def scaled_convolution_fast(a, x, L: int):
     return ((C * B) @ E).real / L
 
 
-def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: int):
+def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: int, t_index=None):
     """u(r, t_n) on the uniform grid t_n = t_first + n t_step, n < n_t, as
     synthesize (same windows, coefficients and active sets, no tracking) with
     each window's sum over m, sum_m Re c_{k,m} sinc(x - m), x = W (t_n - s_k -
-    tau0)/pi, replaced by scaled_convolution_fast of size L."""
+    tau0)/pi, replaced by scaled_convolution_fast of size L.  t_index: only
+    these grid indices (columns of the result, in the given order)."""
     Nr, M = V_full.shape
     F = M // 2
     dw = W / F
     omega_l = -W + dw * np.arange(M)
     times = t_first + t_step * np.arange(n_t)
-    u = np.zeros((Nr, n_t))
+    if t_index is not None:
+        times = times[np.asarray(t_index)]
+    u = np.zeros((Nr, len(times)))
     shift = np.exp(-1j * omega_l * tau0)
     for ik, k in enumerate(ks):
         sk = window_center(k, H)

@@ -919,6 +919,19 @@ int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, 
     return fhw_eval_field_curve(c, 0, psi, obs, N_r, zero_value, V);
 }
 
+// Windows k whose support [s_k - H, s_k + H], s_k = 1.5 H (k - 1), meets the
+// signal's sample range (Sec. 3.1); empty when k_lo > k_hi.
+static void signal_windows(const fhw_signal* sig, double H, int64_t* k_lo_out, int64_t* k_hi_out) {
+    const double tlo = sig->t0, thi = sig->t0 + sig->dt * (double)(sig->n - 1);
+    const double span = 1.5 * H;
+    int64_t k_lo = (int64_t)floor((tlo - H) / span) + 1 - 1;
+    int64_t k_hi = (int64_t)ceil((thi + H) / span) + 1 + 1;
+    while (k_lo <= k_hi && !(1.5 * H * ((double)k_lo - 1.0) + H >= tlo)) ++k_lo;
+    while (k_hi >= k_lo && !(1.5 * H * ((double)k_hi - 1.0) - H <= thi)) --k_hi;
+    *k_lo_out = k_lo;
+    *k_hi_out = k_hi;
+}
+
 int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V, int32_t N_r,
                    const double* times, int32_t N_t, double* u) {
     if (!c) return FHW_E_INVALID;
@@ -938,13 +951,9 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F must be a power of two");
     if ((size_t)M * 16 > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F too large");
     const double W = c->prob.W;
-    // windows meeting the signal's sample range
-    const double tlo = sig->t0, thi = sig->t0 + sig->dt * (double)(sig->n - 1);
+    int64_t k_lo, k_hi;
+    signal_windows(sig, H, &k_lo, &k_hi);
     const double span = 1.5 * H;
-    int64_t k_lo = (int64_t)floor((tlo - H) / span) + 1 - 1;
-    int64_t k_hi = (int64_t)ceil((thi + H) / span) + 1 + 1;
-    while (k_lo <= k_hi && !(1.5 * H * ((double)k_lo - 1.0) + H >= tlo)) ++k_lo;
-    while (k_hi >= k_lo && !(1.5 * H * ((double)k_hi - 1.0) - H <= thi)) --k_hi;
     const double P = M_PI / (W / (double)F);
     std::vector<int32_t> slot;
     std::vector<int64_t> klist;
@@ -1015,6 +1024,123 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
         for (double v : b) n += v > ttol * gm ? 1 : 0;
         c->trk_active = n;
     }
+    return FHW_OK;
+}
+
+// Time samples on the uniform grid t_n = t_first + n t_step by the fast scaled
+// convolution: the windows, spectra, coefficients and active sets of
+// fhw_synthesize, then per window and point the sum over m by an L-point FFT
+// and a chirp-z convolution (frft.hip) instead of the direct sinc sum.
+int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V, int32_t N_r,
+                           double t_first, double t_step, int32_t N_t, int32_t L, double* u) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize_uniform: no plan");
+    if (c->prob.j_first != 0 || c->system_plan)
+        return fhw_fail(c, FHW_E_STATE, "synthesize_uniform: the plan is a band or a list of systems (no DFT grid)");
+    if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad arguments");
+    if (N_r == 0 || N_t == 0) return FHW_OK;
+    if (!V || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad signal or buffers");
+    if (!isfinite(t_first) || !(t_step > 0) || !isfinite(t_step))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad time grid");
+    const double H = win->H, tau0 = win->tau0;
+    if (!(H > 0) || !isfinite(H) || !isfinite(tau0))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad windows");
+    if (win->track_tol != 0.0) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: no tracking (track_tol must be 0)");
+    if (N_r > 65535) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: at most 65535 points");
+    const int F = c->prob.F;
+    const int M = 2 * F;
+    if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: 2F must be a power of two");
+    const int qmax = frft_max_q(lds_limit(c));
+    if (L == 0) L = 2 * M;
+    if (L < 2 * M || (L & (L - 1)) || 2 * L > qmax)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: L must be a power of two with 4F <= L <= " +
+                                              std::to_string(qmax / 2));
+    const double W = c->prob.W;
+    const double span = 1.5 * H;
+    const double P = M_PI / (W / (double)F);
+    const double beta = W * t_step / M_PI;
+    int64_t k_lo, k_hi;
+    signal_windows(sig, H, &k_lo, &k_hi);
+    // active grid range of each window, by the same test as the direct sum
+    struct wrange { int64_t k; int64_t a, b; };
+    std::vector<wrange> wr;
+    auto tn = [&](int64_t n) {
+        const double prod = (double)n * t_step;
+        return t_first + prod;
+    };
+    for (int64_t k = k_lo; k <= k_hi; ++k) {
+        const double sk = 1.5 * H * ((double)k - 1.0);
+        const double lo = (sk + tau0 - P - t_first) / t_step, hi = (sk + tau0 + P - t_first) / t_step;
+        if (!(hi >= -2.0) || !(lo <= (double)N_t + 1.0)) continue;
+        int64_t a = std::max<int64_t>(0, (int64_t)floor(std::max(lo, -2.0)) - 1);
+        int64_t b = std::min<int64_t>(N_t - 1, (int64_t)ceil(std::min(hi, (double)N_t + 1.0)) + 1);
+        while (a <= b && !(fabs(tn(a) - sk - tau0) <= P)) ++a;
+        while (b >= a && !(fabs(tn(b) - sk - tau0) <= P)) --b;
+        if (a <= b) wr.push_back({k, a, b});
+    }
+    const int count = (int)wr.size();
+    int64_t nk_max = 1;
+    for (const wrange& w : wr) nk_max = std::max(nk_max, w.b - w.a + 1);
+    int Q = L;
+    while (Q < qmax && (int64_t)Q < (int64_t)L + nk_max - 1) Q <<= 1;
+    const int NC = Q - L + 1;
+    // windows k and k + j overlap in time iff j span <= 2P: passes of windows
+    // k mod NP hold disjoint time ranges
+    const int64_t NP = (int64_t)floor(2.0 * P / span) + 1;
+    std::vector<fhw_frft_chunk> chunks;
+    std::vector<int32_t> pass_first(NP + 1, 0);
+    for (int64_t ps = 0; ps < NP; ++ps) {
+        pass_first[ps] = (int32_t)chunks.size();
+        for (int q = 0; q < count; ++q) {
+            const wrange& w = wr[q];
+            if (((w.k % NP) + NP) % NP != ps) continue;
+            const double sk = 1.5 * H * ((double)w.k - 1.0);
+            for (int64_t n0 = w.a; n0 <= w.b; n0 += NC) {
+                fhw_frft_chunk ch;
+                ch.slot = q;
+                ch.n0 = (int32_t)n0;
+                ch.n = (int32_t)std::min<int64_t>(NC, w.b - n0 + 1);
+                ch.pad = 0;
+                ch.xs = W * (tn(n0) - sk - tau0) / M_PI;
+                chunks.push_back(ch);
+            }
+        }
+    }
+    pass_first[NP] = (int32_t)chunks.size();
+    // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chunks
+    size_t o_k = 0;
+    size_t o_B = align_up(o_k + (size_t)std::max(count, 1) * 8, 256);
+    size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
+    size_t o_tw = align_up(o_c + (size_t)count * N_r * M * 8, 256);
+    size_t o_hs = align_up(o_tw + (size_t)Q / 2 * 16, 256);
+    size_t o_ch = align_up(o_hs + (size_t)Q * 16, 256);
+    size_t total = align_up(o_ch + std::max<size_t>(1, chunks.size()) * sizeof(fhw_frft_chunk), 256);
+    int rc = fhw_ensure_scratch(c, total);
+    if (rc) return rc;
+    char* sb = (char*)c->scratch;
+    FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
+    c->trk_pairs = (int64_t)count * N_r;
+    c->trk_active = c->trk_pairs;
+    if (count == 0) return FHW_OK;
+    std::vector<int64_t> klist(count);
+    for (int q = 0; q < count; ++q) klist[q] = wr[q].k;
+    FHW_HIP(c, hipMemcpyAsync(sb + o_k, klist.data(), klist.size() * 8, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o_ch, chunks.data(), chunks.size() * sizeof(fhw_frft_chunk), hipMemcpyHostToDevice,
+                              c->stream));
+    STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, H, 0,
+                                                      (const int64_t*)(sb + o_k), count, W, F, sb + o_B));
+    STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
+                                                     (double*)(sb + o_c)));
+    STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_tw, sb + o_hs));
+    const fhw_frft_chunk* d_ch = (const fhw_frft_chunk*)(sb + o_ch);
+    for (int64_t ps = 0; ps < NP; ++ps) {
+        const int32_t n = pass_first[ps + 1] - pass_first[ps];
+        if (n == 0) continue;
+        STAGE(c, FHW_STAGE_SYNTH, launch_frft(c->stream, (const double*)(sb + o_c), d_ch + pass_first[ps], n, N_r, F,
+                                              L, Q, beta, W / M_PI, sb + o_tw, sb + o_hs, u, N_t));
+    }
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }
 

@@ -245,6 +245,26 @@ hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, co
                                  int32_t N_r, double W, int32_t F, double tau0, void* c, double* c_re,
                                  double* bnd = nullptr, unsigned long long* gmax = nullptr,
                                  double* wmax = nullptr, unsigned long long* gwmax = nullptr, double tol = 0.0);
+// Fast scaled convolution on a uniform time grid (frft.hip).  A chunk is a
+// run of n consecutive grid times from index n0 inside one window's active
+// range; xs is the kernel argument W (t_{n0} - s_k - tau0) / pi of its first.
+struct fhw_frft_chunk {
+    int32_t slot;
+    int32_t n0;
+    int32_t n;
+    int32_t pad;
+    double xs;
+};
+// largest power-of-two convolution length Q (<= 8192) whose complex128 buffer
+// fits in lds_bytes
+int frft_max_q(int lds_bytes);
+// twiddles tw[Q/2] and the chirp spectrum Hs[Q] for (L, NC, Q, beta)
+hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* tw, void* Hs);
+// u[r][n0 + i] += scale d(xs + beta i), i < n, for every chunk and point r;
+// chunks of one launch must cover disjoint time ranges
+hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* d_chunks, int32_t n_chunks,
+                       int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* tw,
+                       const void* Hs, double* u, int64_t N_t);
 // bnd != NULL: skip window slot sl at point r when bnd[sl N_r + r] <= tol * (*gmax)
 hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min,
                         int64_t k_max, int32_t n_slots, int32_t N_r, const double* times,

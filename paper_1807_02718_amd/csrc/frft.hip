@@ -1,0 +1,191 @@
+// Fast scaled convolution for time samples on a uniform grid (Sec. 3.3, FFT
+// accelerated evaluation of scaled discrete convolutions, eqs. conv_sum and
+// approx_conv_sum; the fractional DFT of Bailey & Swarztrauber, evaluated in
+// Bluestein's chirp-z form).
+//
+// For window k, point r and a chunk of consecutive grid times whose kernel
+// arguments are x_i = xs + beta i (beta = W dt / pi), with a_m = Re c_{k,m}(r),
+// m = -F..F-1, the sum d(x) = sum_m a_m sinc(x - m) is replaced by
+//   d(x) ~= (1/L) sum_{p=-L/2}^{L/2-1} C_p B_p e^{2 pi i p x / L},
+//   C_p = sum_m a_m e^{-2 pi i m p / L}   (gamma = 1).
+// The coefficients span the whole period of the band, so the kernel samples
+// sinc(q) at the integers form the unit impulse and B_p = 1.  With
+// 2 i p = i^2 + p^2 - (i - p)^2 the sum over p for all i of a chunk is one
+// linear convolution,
+//   d(xs + beta i) = e^{i pi beta i^2 / L} sum_{P=0}^{L-1} z_P h(i - P),
+//   z_P = C_p e^{2 pi i p xs / L} e^{i pi beta p^2 / L} / L,   p = P - L/2,
+//   h(j) = e^{-i pi beta (j + L/2)^2 / L},   j = -(L-1) .. NC-1,
+// taken as a circular convolution of length Q >= NC + L - 1 in LDS.
+#include "fhw_device.h"
+#include "fhw_internal.h"
+
+#define FRFT_THREADS 1024
+#define FRFT_QMAX 8192
+#define FRFT_PER (FRFT_QMAX / FRFT_THREADS)
+
+__device__ __forceinline__ int frft_brev(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
+
+// e^{i pi v s} for an exactly representable s: the rounding error of v s is
+// recovered with an fma and the product reduced modulo 2 (exactly) before
+// sincospi, so large arguments keep full absolute accuracy.
+__device__ __forceinline__ zd frft_expipi(double v, double s) {
+    const double t = v * s;
+    const double e = fma(v, s, -t);
+    const double rdc = t - 2.0 * floor(0.5 * t);
+    double sn, cs;
+    sincospi(rdc + e, &sn, &cs);
+    return cmk(cs, sn);
+}
+
+// In-place radix-2 decimation-in-time FFT of length S (a power of two) of LDS
+// data stored in bit-reversed order: X_k = sum_j x_j e^{-2 pi i j k / S}.
+// tw[j] = e^{-2 pi i j / Q}, j < Q/2, for a multiple Q of S.
+__device__ void frft_lds_fft(zd* X, int S, int logS, const zd* __restrict__ tw, int logQ) {
+    for (int lg = 1; lg <= logS; ++lg) {
+        const int half = 1 << (lg - 1);
+        const int tsh = logQ - lg;   // twiddle stride Q / len
+        for (int t = threadIdx.x; t < (S >> 1); t += FRFT_THREADS) {
+            const int pos = t & (half - 1);
+            const int i = ((t >> (lg - 1)) << lg) + pos;
+            const int j = i + half;
+            const zd w = tw[pos << tsh];
+            const zd a = X[i];
+            const zd b = cmul(X[j], w);
+            X[i] = cadd(a, b);
+            X[j] = csub(a, b);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_frft_twiddles(int Q, zd* __restrict__ tw) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= Q / 2) return;
+    double sn, cs;
+    sincospi(-2.0 * (double)j / (double)Q, &sn, &cs);
+    tw[j] = cmk(cs, sn);
+}
+
+// Spectrum of the chirp h (laid out circularly over Q), divided by Q so that
+// the inverse transform of the product needs no further scaling.
+__global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int Q, int logQ, double beta,
+                                                             const zd* __restrict__ tw, zd* __restrict__ Hs) {
+    extern __shared__ zd X[];
+    for (int pos = threadIdx.x; pos < Q; pos += FRFT_THREADS) {
+        zd v = cmk(0.0, 0.0);
+        int j = 0;
+        bool used = false;
+        if (pos < NC) { j = pos; used = true; }
+        else if (pos >= Q - (L - 1)) { j = pos - Q; used = true; }
+        if (used) {
+            const double jj = (double)(j + L / 2);
+            v = frft_expipi(-beta, jj * jj / (double)L);
+        }
+        X[frft_brev(pos, logQ)] = v;
+    }
+    __syncthreads();
+    frft_lds_fft(X, Q, logQ, tw, logQ);
+    const double iq = 1.0 / (double)Q;
+    for (int k = threadIdx.x; k < Q; k += FRFT_THREADS) Hs[k] = cmk(X[k].re * iq, X[k].im * iq);
+}
+
+// One workgroup per (chunk, point r): adds scale * d(x_i) into u[r][n0 + i],
+// i < n.  The chunks of one launch cover disjoint time ranges.
+__global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict__ cre,
+                                                       const fhw_frft_chunk* __restrict__ chunks, int N_r, int F,
+                                                       int L, int logL, int Q, int logQ, double beta, double scale,
+                                                       const zd* __restrict__ tw, const zd* __restrict__ Hs,
+                                                       double* __restrict__ u, int64_t N_t) {
+    extern __shared__ zd X[];
+    const fhw_frft_chunk ch = chunks[blockIdx.x];
+    const int r = blockIdx.y;
+    const int M = 2 * F;
+    const double* a = cre + ((int64_t)ch.slot * N_r + r) * M;
+    // a_m at index m mod L, zero elsewhere, in bit-reversed order
+    for (int idx = threadIdx.x; idx < L; idx += FRFT_THREADS) {
+        const int m = idx < L / 2 ? idx : idx - L;
+        const double v = (m >= -F && m < F) ? a[m + F] : 0.0;
+        X[frft_brev(idx, logL)] = cmk(v, 0.0);
+    }
+    __syncthreads();
+    frft_lds_fft(X, L, logL, tw, logQ);   // X[p mod L] = C_p
+    zd zv[FRFT_PER];
+    const double il = 1.0 / (double)L;
+#pragma unroll
+    for (int k = 0; k < FRFT_PER; ++k) {
+        const int P = threadIdx.x + k * FRFT_THREADS;
+        zd z = cmk(0.0, 0.0);
+        if (P < L) {
+            const int p = P - L / 2;
+            const zd A = X[(P + L / 2) & (L - 1)];
+            const zd ph = cmul(frft_expipi(ch.xs, 2.0 * (double)p * il), frft_expipi(beta, (double)p * (double)p * il));
+            z = cmul(A, ph);
+            z = cmk(z.re * il, z.im * il);
+        }
+        zv[k] = z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < FRFT_PER; ++k) {
+        const int P = threadIdx.x + k * FRFT_THREADS;
+        if (P < Q) X[frft_brev(P, logQ)] = zv[k];
+    }
+    __syncthreads();
+    frft_lds_fft(X, Q, logQ, tw, logQ);
+    // product with the chirp spectrum; the inverse transform as conj(FFT(conj))
+#pragma unroll
+    for (int k = 0; k < FRFT_PER; ++k) {
+        const int K = threadIdx.x + k * FRFT_THREADS;
+        if (K < Q) zv[k] = cconj(cmul(X[K], Hs[K]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < FRFT_PER; ++k) {
+        const int K = threadIdx.x + k * FRFT_THREADS;
+        if (K < Q) X[frft_brev(K, logQ)] = zv[k];
+    }
+    __syncthreads();
+    frft_lds_fft(X, Q, logQ, tw, logQ);
+    double* ur = u + (int64_t)r * N_t + ch.n0;
+    for (int i = threadIdx.x; i < ch.n; i += FRFT_THREADS) {
+        const zd y = cconj(X[i]);
+        const zd w = frft_expipi(beta, (double)i * (double)i * il);
+        ur[i] += scale * (w.re * y.re - w.im * y.im);
+    }
+}
+
+int frft_max_q(int lds_bytes) {
+    int q = FRFT_QMAX;
+    while (q > 2 && (size_t)q * sizeof(zd) > (size_t)lds_bytes) q >>= 1;
+    return q;
+}
+
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* tw, void* Hs) {
+    if (Q > FRFT_QMAX || Q < 2 || (Q & (Q - 1)) || L > Q || NC < 1 || NC + L - 1 > Q) return hipErrorInvalidValue;
+    static std::atomic<uint64_t> attr{0};
+    if (fhw_first_on_device(attr)) {
+        const int dyn = FRFT_QMAX * (int)sizeof(zd);
+        (void)hipFuncSetAttribute((const void*)k_frft_chirp, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        (void)hipFuncSetAttribute((const void*)k_frft, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    }
+    hipLaunchKernelGGL(k_frft_twiddles, dim3((Q / 2 + 255) / 256), dim3(256), 0, s, Q, (zd*)tw);
+    hipLaunchKernelGGL(k_frft_chirp, dim3(1), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, L, NC, Q, ilog2(Q), beta,
+                       (const zd*)tw, (zd*)Hs);
+    return hipGetLastError();
+}
+
+hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* d_chunks, int32_t n_chunks,
+                       int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* tw,
+                       const void* Hs, double* u, int64_t N_t) {
+    if (n_chunks <= 0 || N_r <= 0) return hipSuccess;
+    if (N_r > 65535 || Q > FRFT_QMAX || L > Q || 2 * F > L) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_frft, dim3(n_chunks, N_r), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, c_re, d_chunks,
+                       N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)tw, (const zd*)Hs, u, N_t);
+    return hipGetLastError();
+}

@@ -87,6 +87,8 @@ def _load():
         "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
         "fhw_eval_field_curve": [vp, i32, vp, _dp, i32, C.c_double, vp],
         "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
+        "fhw_synthesize_uniform": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, C.c_double,
+                                   C.c_double, i32, i32, vp],
         "fhw_synth_active_pairs": [vp, p_i64, p_i64],
         "fhw_run": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), _dp, i32, _dp, i32, vp, vp, vp, _dp, p_i32],
         "fhw_geometry": [vp, i32, vp],
@@ -112,7 +114,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
             "fhw_plan_systems", "fhw_factor", "fhw_solve_range",
-            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
@@ -313,6 +315,19 @@ class Context:
         if u is None:
             u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
         self._check(_lib.fhw_synthesize(self._h, C.byref(sg), C.byref(wn), _ptr(V), Nr, tp, len(th), _ptr(u)))
+        return u
+
+    def synthesize_uniform(self, f, t0, dt, H, tau0, V, t_first, t_step, n_t, L=0, u=None):
+        """fhw_synthesize_uniform: u[r][n] at t_first + n t_step by the fast
+        scaled convolution of size L (0 = 4F)."""
+        f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
+        sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
+        wn = fhw_windows(float(H), float(tau0), 0.0)
+        Nr = V.shape[0]
+        if u is None:
+            u = torch.empty((Nr, int(n_t)), dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_synthesize_uniform(self._h, C.byref(sg), C.byref(wn), _ptr(V), Nr, float(t_first),
+                                                float(t_step), int(n_t), int(L), _ptr(u)))
         return u
 
     # -- stage entry points -------------------------------------------------------
