@@ -230,6 +230,54 @@ def tracking_bench(fhw, torch, Wk, reps):
                       "rel_change": diff, "max_abs_err_vs_exact": err}), flush=True)
 
 
+def uniform_bench(fhw, torch, Wk, reps):
+    """Time samples on long uniform grids (the paper's Table 1 setting) for
+    the solve-throughput workload: kite, N = 1024, F = 1024 on (0, 69], the
+    chirp to T = 1e4, 256 points on the radius-3 ring; grids of 16384 and
+    65536 samples at the signal's step pi/(4W) from t = 9000.  The direct sinc
+    sum (fhw_synthesize on the same times) against the fast scaled
+    convolution (fhw_synthesize_uniform, L = 4F): median wall time of reps
+    calls each, the synthesis stage's HIP-event time, and their largest
+    difference relative to the largest sample."""
+    wl = Wk.kite_n1024()
+    ctx = fhw.Context()
+    out = []
+    try:
+        ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision="fp32_refine", refine_tol=1e-12, refine_max=10,
+                 direction=wl.direction)
+        psi, _, _ = ctx.solve_densities()
+        V = ctx.eval_field(psi, wl.obs, zero_value=1.0)
+        f = torch.as_tensor(wl.signal.f, device="cuda")
+        t_step = np.pi / (4.0 * wl.W)
+        for n_t in (16384, 65536):
+            t_first = 9000.0
+            times = t_first + t_step * np.arange(n_t)
+            res = {}
+            for name, call in (("direct", lambda: ctx.synthesize(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, times)),
+                               ("fast", lambda: ctx.synthesize_uniform(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V,
+                                                                       t_first, t_step, n_t))):
+                ts, st = [], []
+                for i in range(reps + 1):
+                    ctx.profile(True)
+                    t0 = time.perf_counter()
+                    u = call()
+                    ts.append(time.perf_counter() - t0)
+                    st.append(ctx.profile_read()["synth"][0])
+                    ctx.profile(False)
+                res[name] = (float(np.median(ts[1:])), float(np.median(st[1:])), u.cpu().numpy())
+            ud = res["direct"][2]
+            out.append({"times": n_t, "t_range": [t_first, float(times[-1])], "points": len(wl.obs),
+                        "direct_ms": 1e3 * res["direct"][0], "fast_ms": 1e3 * res["fast"][0],
+                        "direct_synth_stage_ms": res["direct"][1], "fast_synth_stage_ms": res["fast"][1],
+                        "speedup": res["direct"][0] / res["fast"][0],
+                        "rel_diff": float(np.max(np.abs(res["fast"][2] - ud)) / np.max(np.abs(ud)))})
+            print("uniform", out[-1], flush=True)
+    finally:
+        ctx.close()
+    print(json.dumps({"metric": "time samples on a uniform grid: direct sinc sum vs fast scaled convolution",
+                      "workload": wl.name, "L": 4 * wl.F, "rows": out}), flush=True)
+
+
 def serve_batched(fhw, torch, Wk, rates, duration, max_wait, precision, batch_bytes):
     """The serving configuration with continuous batching: before each round,
     every request that has arrived (and is not past max_wait in the queue) is
@@ -427,7 +475,7 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=50, help="isolated-solve latency samples (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
-    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep",
+    ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep", "uniform",
                                                                 "tracking"],
                     help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
                          "serve: Poisson request stream (per-request latency); batch_sweep: solves/s at "
@@ -452,6 +500,9 @@ def main():
     from paper_1807_02718_amd import fhw
     if a.workload == "stars":
         star_batch_bench(fhw, torch, Wk.star_batch(), a.steps, a.warmup)
+        return
+    if a.workload == "uniform":
+        uniform_bench(fhw, torch, Wk, max(3, a.steps))
         return
     if a.workload == "tracking":
         tracking_bench(fhw, torch, Wk, 5)

@@ -37,22 +37,63 @@ __device__ __forceinline__ zd frft_expipi(double v, double s) {
     return cmk(cs, sn);
 }
 
-// In-place radix-2 decimation-in-time FFT of length S (a power of two) of LDS
-// data stored in bit-reversed order: X_k = sum_j x_j e^{-2 pi i j k / S}.
-// tw[j] = e^{-2 pi i j / Q}, j < Q/2, for a multiple Q of S.
-__device__ void frft_lds_fft(zd* X, int S, int logS, const zd* __restrict__ tw, int logQ) {
-    for (int lg = 1; lg <= logS; ++lg) {
-        const int half = 1 << (lg - 1);
-        const int tsh = logQ - lg;   // twiddle stride Q / len
-        for (int t = threadIdx.x; t < (S >> 1); t += FRFT_THREADS) {
-            const int pos = t & (half - 1);
-            const int i = ((t >> (lg - 1)) << lg) + pos;
-            const int j = i + half;
-            const zd w = tw[pos << tsh];
-            const zd a = X[i];
-            const zd b = cmul(X[j], w);
-            X[i] = cadd(a, b);
-            X[j] = csub(a, b);
+// Twiddle e^{-2 pi i j / Q}, j < Q/2 <= 4096, as the product of two LDS
+// table entries: thi[a] = e^{-2 pi i 64 a / Q}, tlo[b] = e^{-2 pi i b / Q}.
+__device__ __forceinline__ zd frft_tw(const zd* thi, const zd* tlo, int j) { return cmul(thi[j >> 6], tlo[j & 63]); }
+
+// Fill the two 64-entry tables from the global table tw[Q/2] (the caller
+// synchronizes before use).
+__device__ __forceinline__ void frft_tables(zd* thi, zd* tlo, const zd* __restrict__ tw, int Q) {
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        tlo[t] = t < Q / 2 ? tw[t] : cmk(1.0, 0.0);
+        thi[t] = 64 * t < Q / 2 ? tw[64 * t] : cmk(1.0, 0.0);
+    }
+}
+
+// In-place decimation-in-time FFT of length S = 2^logS (S <= Q) of LDS data
+// stored in bit-reversed order: X_k = sum_j x_j e^{-2 pi i j k / S}.  The
+// radix-2 stages go two at a time (radix 2^2): a thread loads x at i0 + {0,
+// h, 2h, 3h}, applies the stage of half-length h (twiddle W_{2h}^pos on both
+// pairs) and then the stage of half-length 2h (W_{4h}^pos, W_{4h}^{pos+h}) in
+// registers, and stores; an odd logS starts with one plain radix-2 stage.
+__device__ void frft_lds_fft(zd* X, int logS, const zd* thi, const zd* tlo, int logQ) {
+    const int S = 1 << logS;
+    int lg = 1;
+    if (logS & 1) {
+#pragma unroll
+        for (int k = 0; k < FRFT_PER / 2; ++k) {
+            const int t = threadIdx.x + k * FRFT_THREADS;
+            if (t < (S >> 1)) {
+                const zd a = X[2 * t], b = X[2 * t + 1];
+                X[2 * t] = cadd(a, b);
+                X[2 * t + 1] = csub(a, b);
+            }
+        }
+        __syncthreads();
+        lg = 2;
+    }
+    for (; lg < logS; lg += 2) {
+        const int h = 1 << (lg - 1);
+#pragma unroll
+        for (int k = 0; k < FRFT_PER / 4; ++k) {
+            const int t = threadIdx.x + k * FRFT_THREADS;
+            if (t < (S >> 2)) {
+                const int pos = t & (h - 1);
+                const int i0 = ((t >> (lg - 1)) << (lg + 1)) + pos;
+                const zd w1 = frft_tw(thi, tlo, pos << (logQ - lg));
+                const zd w2 = frft_tw(thi, tlo, pos << (logQ - lg - 1));
+                const zd w3 = frft_tw(thi, tlo, (pos + h) << (logQ - lg - 1));
+                const zd x0 = X[i0], x1 = X[i0 + h], x2 = X[i0 + 2 * h], x3 = X[i0 + 3 * h];
+                const zd b1 = cmul(x1, w1), b3 = cmul(x3, w1);
+                const zd y0 = cadd(x0, b1), y1 = csub(x0, b1);
+                const zd y2 = cadd(x2, b3), y3 = csub(x2, b3);
+                const zd c2 = cmul(y2, w2), c3 = cmul(y3, w3);
+                X[i0] = cadd(y0, c2);
+                X[i0 + 2 * h] = csub(y0, c2);
+                X[i0 + h] = cadd(y1, c3);
+                X[i0 + 3 * h] = csub(y1, c3);
+            }
         }
         __syncthreads();
     }
@@ -71,6 +112,8 @@ __global__ __launch_bounds__(256) void k_frft_twiddles(int Q, zd* __restrict__ t
 __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int Q, int logQ, double beta,
                                                              const zd* __restrict__ tw, zd* __restrict__ Hs) {
     extern __shared__ zd X[];
+    __shared__ zd thi[64], tlo[64];
+    frft_tables(thi, tlo, tw, Q);
     for (int pos = threadIdx.x; pos < Q; pos += FRFT_THREADS) {
         zd v = cmk(0.0, 0.0);
         int j = 0;
@@ -84,7 +127,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int 
         X[frft_brev(pos, logQ)] = v;
     }
     __syncthreads();
-    frft_lds_fft(X, Q, logQ, tw, logQ);
+    frft_lds_fft(X, logQ, thi, tlo, logQ);
     const double iq = 1.0 / (double)Q;
     for (int k = threadIdx.x; k < Q; k += FRFT_THREADS) Hs[k] = cmk(X[k].re * iq, X[k].im * iq);
 }
@@ -97,6 +140,8 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
                                                        const zd* __restrict__ tw, const zd* __restrict__ Hs,
                                                        double* __restrict__ u, int64_t N_t) {
     extern __shared__ zd X[];
+    __shared__ zd thi[64], tlo[64];
+    frft_tables(thi, tlo, tw, Q);
     const fhw_frft_chunk ch = chunks[blockIdx.x];
     const int r = blockIdx.y;
     const int M = 2 * F;
@@ -108,7 +153,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         X[frft_brev(idx, logL)] = cmk(v, 0.0);
     }
     __syncthreads();
-    frft_lds_fft(X, L, logL, tw, logQ);   // X[p mod L] = C_p
+    frft_lds_fft(X, logL, thi, tlo, logQ);   // X[p mod L] = C_p
     zd zv[FRFT_PER];
     const double il = 1.0 / (double)L;
 #pragma unroll
@@ -131,7 +176,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         if (P < Q) X[frft_brev(P, logQ)] = zv[k];
     }
     __syncthreads();
-    frft_lds_fft(X, Q, logQ, tw, logQ);
+    frft_lds_fft(X, logQ, thi, tlo, logQ);
     // product with the chirp spectrum; the inverse transform as conj(FFT(conj))
 #pragma unroll
     for (int k = 0; k < FRFT_PER; ++k) {
@@ -145,7 +190,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         if (K < Q) X[frft_brev(K, logQ)] = zv[k];
     }
     __syncthreads();
-    frft_lds_fft(X, Q, logQ, tw, logQ);
+    frft_lds_fft(X, logQ, thi, tlo, logQ);
     double* ur = u + (int64_t)r * N_t + ch.n0;
     for (int i = threadIdx.x; i < ch.n; i += FRFT_THREADS) {
         const zd y = cconj(X[i]);

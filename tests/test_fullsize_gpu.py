@@ -230,3 +230,49 @@ def test_fullsize_interior_extinction(fhw):
     err = float(np.max(np.abs(u - exact)))
     say("interior extinction max error", err)
     assert err < 1e-9
+
+
+def test_fullsize_uniform_synthesis(fhw):
+    """The fast scaled convolution in the configuration the uniform-grid
+    benchmark times (kite workload's band: F = 1024 so L = 4096 and chirp-z
+    length 8192; 256 points; 16384 samples at pi/(4W) from t = 9000), on a
+    pure-delay spectrum: against the oracle's written-out approximation on a
+    sample (4 points x 64 grid times), the direct GPU sum on every sample,
+    and the delayed chirp -f(t - d_r)."""
+    say("full-size uniform synthesis")
+    wl = Wk.kite_n1024()
+    ctx = fhw.Context()
+    Nr = len(wl.obs)
+    d = np.linspace(-3.0, 5.0, Nr)
+    dw = wl.W / wl.F
+    omega_l = -wl.W + dw * np.arange(2 * wl.F)
+    Vh = np.exp(1j * omega_l[None, :] * d[:, None])
+    t_first, t_step, n_t = 9000.0, np.pi / (4.0 * wl.W), 16384
+    times = t_first + t_step * np.arange(n_t)
+    try:
+        ctx.plan(wl.curve, wl.W, wl.F, N=wl.N)
+        V = torch.as_tensor(Vh, device="cuda")
+        f = torch.as_tensor(wl.signal.f, device="cuda")
+        u = ctx.synthesize_uniform(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, t_first, t_step,
+                                   n_t).cpu().numpy()
+        ud = ctx.synthesize(f, wl.signal.t0, wl.signal.dt, wl.H, wl.tau0, V, times).cpu().numpy()
+    finally:
+        ctx.close()
+    rows = np.arange(0, Nr, Nr // 4)
+    cols = np.sort(np.random.default_rng(2).choice(2000, 64, replace=False))
+    t = wl.signal.t
+    ks = O.window_indices(t[0], t[-1], wl.H)
+    act = np.zeros(len(ks), dtype=bool)
+    for tt in times[cols]:
+        act |= O.active_windows(tt, ks, wl.H, wl.tau0, dw)
+    ks = ks[act]
+    B = O.window_spectra(wl.signal, wl.H, ks, omega_l)
+    ref = O.synthesize_uniform(Vh[rows], B, ks, wl.H, wl.tau0, wl.W, t_first, t_step, n_t, 4 * wl.F, t_index=cols)
+    exact = -Wk.chirp_value(times[None, :] - d[:, None], 1.0e4 + 5.0, rate=16000.0)
+    err_o = relmax(u[np.ix_(rows, cols)], ref)
+    err_d = float(np.max(np.abs(u - ud)) / np.max(np.abs(ud)))
+    err_x = float(np.max(np.abs(u - exact)))
+    say("uniform: vs oracle", err_o, "vs direct", err_d, "vs exact", err_x, "windows in the sample", len(ks))
+    assert err_o < 1e-10
+    assert err_d < 1e-10
+    assert err_x < 1e-9
