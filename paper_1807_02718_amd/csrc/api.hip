@@ -1108,13 +1108,15 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
         }
     }
     pass_first[NP] = (int32_t)chunks.size();
-    // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chunks
+    // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chirps | chunks
     size_t o_k = 0;
     size_t o_B = align_up(o_k + (size_t)std::max(count, 1) * 8, 256);
     size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
     size_t o_tw = align_up(o_c + (size_t)count * N_r * M * 8, 256);
     size_t o_hs = align_up(o_tw + (size_t)Q / 2 * 16, 256);
-    size_t o_ch = align_up(o_hs + (size_t)Q * 16, 256);
+    size_t o_ci = align_up(o_hs + (size_t)Q * 16, 256);
+    size_t o_co = align_up(o_ci + (size_t)L * 16, 256);
+    size_t o_ch = align_up(o_co + (size_t)NC * 16, 256);
     size_t total = align_up(o_ch + std::max<size_t>(1, chunks.size()) * sizeof(fhw_frft_chunk), 256);
     int rc = fhw_ensure_scratch(c, total);
     if (rc) return rc;
@@ -1132,13 +1134,14 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
                                                       (const int64_t*)(sb + o_k), count, W, F, sb + o_B));
     STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
                                                      (double*)(sb + o_c)));
-    STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_tw, sb + o_hs));
+    STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co));
     const fhw_frft_chunk* d_ch = (const fhw_frft_chunk*)(sb + o_ch);
     for (int64_t ps = 0; ps < NP; ++ps) {
         const int32_t n = pass_first[ps + 1] - pass_first[ps];
         if (n == 0) continue;
         STAGE(c, FHW_STAGE_SYNTH, launch_frft(c->stream, (const double*)(sb + o_c), d_ch + pass_first[ps], n, N_r, F,
-                                              L, Q, beta, W / M_PI, sb + o_tw, sb + o_hs, u, N_t));
+                                              L, Q, beta, W / M_PI, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co, u,
+                                              N_t));
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;

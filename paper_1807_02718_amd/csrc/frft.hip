@@ -108,10 +108,20 @@ __global__ __launch_bounds__(256) void k_frft_twiddles(int Q, zd* __restrict__ t
 }
 
 // Spectrum of the chirp h (laid out circularly over Q), divided by Q so that
-// the inverse transform of the product needs no further scaling.
+// the inverse transform of the product needs no further scaling; and the
+// chirps shared by every chunk and point: cin[P] = e^{i pi beta p^2 / L} / L,
+// p = P - L/2, P < L, and cout[i] = e^{i pi beta i^2 / L}, i < NC.
 __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int Q, int logQ, double beta,
-                                                             const zd* __restrict__ tw, zd* __restrict__ Hs) {
+                                                             const zd* __restrict__ tw, zd* __restrict__ Hs,
+                                                             zd* __restrict__ cin, zd* __restrict__ cout) {
     extern __shared__ zd X[];
+    const double il = 1.0 / (double)L;
+    for (int P = threadIdx.x; P < L; P += FRFT_THREADS) {
+        const double p = (double)(P - L / 2);
+        const zd w = frft_expipi(beta, p * p * il);
+        cin[P] = cmk(w.re * il, w.im * il);
+    }
+    for (int i = threadIdx.x; i < NC; i += FRFT_THREADS) cout[i] = frft_expipi(beta, (double)i * (double)i * il);
     __shared__ zd thi[64], tlo[64];
     frft_tables(thi, tlo, tw, Q);
     for (int pos = threadIdx.x; pos < Q; pos += FRFT_THREADS) {
@@ -138,6 +148,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
                                                        const fhw_frft_chunk* __restrict__ chunks, int N_r, int F,
                                                        int L, int logL, int Q, int logQ, double beta, double scale,
                                                        const zd* __restrict__ tw, const zd* __restrict__ Hs,
+                                                       const zd* __restrict__ cin, const zd* __restrict__ cout,
                                                        double* __restrict__ u, int64_t N_t) {
     extern __shared__ zd X[];
     __shared__ zd thi[64], tlo[64];
@@ -156,16 +167,18 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
     frft_lds_fft(X, logL, thi, tlo, logQ);   // X[p mod L] = C_p
     zd zv[FRFT_PER];
     const double il = 1.0 / (double)L;
+    // phase ramp e^{2 pi i p xs / L} at p = P - L/2, P = tid + k 1024: the
+    // first by sincospi, the next ones times e^{2 pi i 1024 xs / L}
+    zd ramp = frft_expipi(ch.xs, 2.0 * (double)((int)threadIdx.x - L / 2) * il);
+    const zd step = frft_expipi(ch.xs, 2.0 * (double)FRFT_THREADS * il);
 #pragma unroll
     for (int k = 0; k < FRFT_PER; ++k) {
         const int P = threadIdx.x + k * FRFT_THREADS;
         zd z = cmk(0.0, 0.0);
         if (P < L) {
-            const int p = P - L / 2;
+            if (k > 0) ramp = cmul(ramp, step);
             const zd A = X[(P + L / 2) & (L - 1)];
-            const zd ph = cmul(frft_expipi(ch.xs, 2.0 * (double)p * il), frft_expipi(beta, (double)p * (double)p * il));
-            z = cmul(A, ph);
-            z = cmk(z.re * il, z.im * il);
+            z = cmul(cmul(A, ramp), cin[P]);
         }
         zv[k] = z;
     }
@@ -194,7 +207,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
     double* ur = u + (int64_t)r * N_t + ch.n0;
     for (int i = threadIdx.x; i < ch.n; i += FRFT_THREADS) {
         const zd y = cconj(X[i]);
-        const zd w = frft_expipi(beta, (double)i * (double)i * il);
+        const zd w = cout[i];
         ur[i] += scale * (w.re * y.re - w.im * y.im);
     }
 }
@@ -211,7 +224,8 @@ static int ilog2(int v) {
     return l;
 }
 
-hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* tw, void* Hs) {
+hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* tw, void* Hs, void* cin,
+                             void* cout) {
     if (Q > FRFT_QMAX || Q < 2 || (Q & (Q - 1)) || L > Q || NC < 1 || NC + L - 1 > Q) return hipErrorInvalidValue;
     static std::atomic<uint64_t> attr{0};
     if (fhw_first_on_device(attr)) {
@@ -221,16 +235,17 @@ hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, v
     }
     hipLaunchKernelGGL(k_frft_twiddles, dim3((Q / 2 + 255) / 256), dim3(256), 0, s, Q, (zd*)tw);
     hipLaunchKernelGGL(k_frft_chirp, dim3(1), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, L, NC, Q, ilog2(Q), beta,
-                       (const zd*)tw, (zd*)Hs);
+                       (const zd*)tw, (zd*)Hs, (zd*)cin, (zd*)cout);
     return hipGetLastError();
 }
 
 hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* d_chunks, int32_t n_chunks,
                        int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* tw,
-                       const void* Hs, double* u, int64_t N_t) {
+                       const void* Hs, const void* cin, const void* cout, double* u, int64_t N_t) {
     if (n_chunks <= 0 || N_r <= 0) return hipSuccess;
     if (N_r > 65535 || Q > FRFT_QMAX || L > Q || 2 * F > L) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_frft, dim3(n_chunks, N_r), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, c_re, d_chunks,
-                       N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)tw, (const zd*)Hs, u, N_t);
+                       N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)tw, (const zd*)Hs, (const zd*)cin,
+                       (const zd*)cout, u, N_t);
     return hipGetLastError();
 }
