@@ -1087,27 +1087,30 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     const int NC = Q - L + 1;
     // windows k and k + j overlap in time iff j span <= 2P: passes of windows
     // k mod NP hold disjoint time ranges
-    const int64_t NP = (int64_t)floor(2.0 * P / span) + 1;
+    const double np_d = floor(2.0 * P / span) + 1.0;
+    const int64_t NP = np_d < 4e18 ? (int64_t)np_d : INT64_MAX;
+    std::vector<std::pair<int64_t, int>> order(count);   // (pass, slot), windows of one pass together
+    for (int q = 0; q < count; ++q) order[q] = {((wr[q].k % NP) + NP) % NP, q};
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) { return x.first < y.first; });
     std::vector<fhw_frft_chunk> chunks;
-    std::vector<int32_t> pass_first(NP + 1, 0);
-    for (int64_t ps = 0; ps < NP; ++ps) {
-        pass_first[ps] = (int32_t)chunks.size();
-        for (int q = 0; q < count; ++q) {
-            const wrange& w = wr[q];
-            if (((w.k % NP) + NP) % NP != ps) continue;
-            const double sk = 1.5 * H * ((double)w.k - 1.0);
-            for (int64_t n0 = w.a; n0 <= w.b; n0 += NC) {
-                fhw_frft_chunk ch;
-                ch.slot = q;
-                ch.n0 = (int32_t)n0;
-                ch.n = (int32_t)std::min<int64_t>(NC, w.b - n0 + 1);
-                ch.pad = 0;
-                ch.xs = W * (tn(n0) - sk - tau0) / M_PI;
-                chunks.push_back(ch);
-            }
+    std::vector<int32_t> pass_first;   // first chunk of each non-empty pass, then the total
+    for (int i = 0; i < count; ++i) {
+        if (i == 0 || order[i].first != order[i - 1].first) pass_first.push_back((int32_t)chunks.size());
+        const int q = order[i].second;
+        const wrange& w = wr[q];
+        const double sk = 1.5 * H * ((double)w.k - 1.0);
+        for (int64_t n0 = w.a; n0 <= w.b; n0 += NC) {
+            fhw_frft_chunk ch;
+            ch.slot = q;
+            ch.n0 = (int32_t)n0;
+            ch.n = (int32_t)std::min<int64_t>(NC, w.b - n0 + 1);
+            ch.pad = 0;
+            ch.xs = W * (tn(n0) - sk - tau0) / M_PI;
+            chunks.push_back(ch);
         }
     }
-    pass_first[NP] = (int32_t)chunks.size();
+    pass_first.push_back((int32_t)chunks.size());
     // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chirps | chunks
     size_t o_k = 0;
     size_t o_B = align_up(o_k + (size_t)std::max(count, 1) * 8, 256);
@@ -1136,7 +1139,7 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
                                                      (double*)(sb + o_c)));
     STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co));
     const fhw_frft_chunk* d_ch = (const fhw_frft_chunk*)(sb + o_ch);
-    for (int64_t ps = 0; ps < NP; ++ps) {
+    for (size_t ps = 0; ps + 1 < pass_first.size(); ++ps) {
         const int32_t n = pass_first[ps + 1] - pass_first[ps];
         if (n == 0) continue;
         STAGE(c, FHW_STAGE_SYNTH, launch_frft(c->stream, (const double*)(sb + o_c), d_ch + pass_first[ps], n, N_r, F,

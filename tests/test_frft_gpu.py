@@ -80,6 +80,27 @@ def test_uniform_synthesis_matches_oracle(ctx, L, t_first, t_step, n_t):
     assert gap > 1e3 * err   # the approximation is what was matched
 
 
+def test_uniform_synthesis_many_passes(ctx):
+    """Short windows (H = 0.5): 45 passes of windows with disjoint time
+    ranges, about 80 windows; each pass adds into u in turn."""
+    say("uniform synthesis, H = 0.5")
+    H2 = 0.5
+    ctx.plan(Wk.circle(1.0), W, F, N=64)
+    Vh = _white_V(2, seed=6)
+    V = torch.as_tensor(Vh, device="cuda")
+    f = torch.as_tensor(SIG.f, device="cuda")
+    t_first, t_step, n_t = 10.0, 0.05, 801
+    u = ctx.synthesize_uniform(f, SIG.t0, SIG.dt, H2, TAU0, V, t_first, t_step, n_t).cpu().numpy()
+    times = t_first + t_step * np.arange(n_t)
+    dw = W / F
+    ks = _windows(SIG, H2, TAU0, dw, times)
+    B = O.window_spectra(SIG, H2, ks, -W + dw * np.arange(2 * F))
+    ref = O.synthesize_uniform(Vh, B, ks, H2, TAU0, W, t_first, t_step, n_t, 4 * F)
+    err = np.max(np.abs(u - ref)) / np.max(np.abs(ref))
+    say("windows", len(ks), "err vs oracle", err)
+    assert len(ks) > 60 and err < 1e-10
+
+
 def test_uniform_synthesis_band_limited_equals_direct(ctx):
     """Pure-delay spectra and a pulse whose windowed spectra fall to 1e-8 of
     their peak at +-W (W = 48): the periodic approximation's error follows
