@@ -260,13 +260,13 @@ int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
  * evaluated by an L-point FFT and a chirp-z (Bluestein) convolution per
  * window, point and run of grid times.  The error against fhw_synthesize is
  * O(L^-2), carried by the spectrum's content near +-W; it vanishes to
- * roundoff where the spectrum is negligible there.  Same windows and active
- * sets as fhw_synthesize (no tracking: win->track_tol must be 0).
+ * roundoff where the spectrum is negligible there.  Same windows, active
+ * sets and tracking rules (win->track_tol) as fhw_synthesize.
  *   u       device doubles [N_r][N_t], overwritten.
  *   L       0 = 4F; else a power of two with 4F <= L <= 4096 (the chirp-z
  *           convolution of length 2L <= 8192 lives in LDS).
  * Errors: FHW_E_INVALID for a bad L, t_step <= 0, non-finite inputs, track_tol
- * != 0, N_r > 65535 or 2F not a power of two; FHW_E_STATE as fhw_synthesize. */
+ * < 0, N_r > 65535 or 2F not a power of two; FHW_E_STATE as fhw_synthesize. */
 int fhw_synthesize_uniform(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
                            const void* V, int32_t N_r, double t_first, double t_step,
                            int32_t N_t, int32_t L, double* u);

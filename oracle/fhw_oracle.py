@@ -404,12 +404,13 @@ def scaled_convolution_fast(a, x, L: int):
     return ((C * B) @ E).real / L
 
 
-def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: int, t_index=None):
+def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: int, t_index=None,
+                       track_tol=0.0):
     """u(r, t_n) on the uniform grid t_n = t_first + n t_step, n < n_t, as
-    synthesize (same windows, coefficients and active sets, no tracking) with
-    each window's sum over m, sum_m Re c_{k,m} sinc(x - m), x = W (t_n - s_k -
-    tau0)/pi, replaced by scaled_convolution_fast of size L.  t_index: only
-    these grid indices (columns of the result, in the given order)."""
+    synthesize (same windows, coefficients, active sets and tracking rules)
+    with each window's sum over m, sum_m Re c_{k,m} sinc(x - m), x = W (t_n -
+    s_k - tau0)/pi, replaced by scaled_convolution_fast of size L.  t_index:
+    only these grid indices (columns of the result, in the given order)."""
     Nr, M = V_full.shape
     F = M // 2
     dw = W / F
@@ -419,6 +420,7 @@ def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: i
         times = times[np.asarray(t_index)]
     u = np.zeros((Nr, len(times)))
     shift = np.exp(-1j * omega_l * tau0)
+    parts = []
     for ik, k in enumerate(ks):
         sk = window_center(k, H)
         act = np.abs(times - sk - tau0) <= np.pi / dw
@@ -426,9 +428,17 @@ def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: i
             continue
         G = Bslow[ik][None, :] * V_full * shift[None, :]
         a = fourier_coefficients(G, W).real
+        wmax = float(np.max(np.abs(Bslow[ik].real) + np.abs(Bslow[ik].imag)))
+        parts.append((sk, act, a, np.sum(np.abs(a), axis=1), wmax))
+    if track_tol > 0:
+        wcut = track_tol * max((w for *_, w in parts), default=0.0)
+        parts = [pt for pt in parts if pt[4] > wcut]
+    cut = track_tol * max((float(np.max(pt[3])) for pt in parts), default=0.0) if track_tol > 0 else -1.0
+    for sk, act, a, b, _ in parts:
+        keep = b > cut
         idx = np.nonzero(act)[0]
         x = W * (times[idx] - sk - tau0) / np.pi
-        u[:, idx] += (W / np.pi) * scaled_convolution_fast(a, x, L)
+        u[np.ix_(keep, idx)] += (W / np.pi) * scaled_convolution_fast(a[keep], x, L)
     return u
 
 

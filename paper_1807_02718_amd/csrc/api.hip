@@ -1043,10 +1043,12 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
         return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad signal or buffers");
     if (!isfinite(t_first) || !(t_step > 0) || !isfinite(t_step))
         return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad time grid");
-    const double H = win->H, tau0 = win->tau0;
+    const double H = win->H, tau0 = win->tau0, ttol = win->track_tol;
     if (!(H > 0) || !isfinite(H) || !isfinite(tau0))
         return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: bad windows");
-    if (win->track_tol != 0.0) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: no tracking (track_tol must be 0)");
+    if (!(ttol >= 0) || !isfinite(ttol))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: track_tol must be >= 0");
+    const bool track = ttol > 0;
     if (N_r > 65535) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: at most 65535 points");
     const int F = c->prob.F;
     const int M = 2 * F;
@@ -1111,7 +1113,7 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
         }
     }
     pass_first.push_back((int32_t)chunks.size());
-    // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chirps | chunks
+    // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chirps | chunks | tracking
     size_t o_k = 0;
     size_t o_B = align_up(o_k + (size_t)std::max(count, 1) * 8, 256);
     size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
@@ -1120,7 +1122,10 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     size_t o_ci = align_up(o_hs + (size_t)Q * 16, 256);
     size_t o_co = align_up(o_ci + (size_t)L * 16, 256);
     size_t o_ch = align_up(o_co + (size_t)NC * 16, 256);
-    size_t total = align_up(o_ch + std::max<size_t>(1, chunks.size()) * sizeof(fhw_frft_chunk), 256);
+    size_t o_bnd = align_up(o_ch + std::max<size_t>(1, chunks.size()) * sizeof(fhw_frft_chunk), 256);
+    size_t o_max = align_up(o_bnd + (size_t)count * N_r * 8, 256);   // tracking bounds, their maxima
+    size_t o_wm = align_up(o_max + 16, 256);                           // window maxima
+    size_t total = align_up(o_wm + (size_t)std::max(count, 1) * 8, 256);
     int rc = fhw_ensure_scratch(c, total);
     if (rc) return rc;
     char* sb = (char*)c->scratch;
@@ -1135,8 +1140,12 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
                               c->stream));
     STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra(c->stream, sig->f, sig->n, sig->t0, sig->dt, H, 0,
                                                       (const int64_t*)(sb + o_k), count, W, F, sb + o_B));
+    double* bnd = track ? (double*)(sb + o_bnd) : nullptr;
+    unsigned long long* gmax = track ? (unsigned long long*)(sb + o_max) : nullptr;
+    if (track) FHW_HIP(c, hipMemsetAsync(gmax, 0, 16, c->stream));   // gmax and the window-level max
     STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
-                                                     (double*)(sb + o_c)));
+                                                     (double*)(sb + o_c), bnd, gmax, (double*)(sb + o_wm),
+                                                     gmax ? gmax + 1 : nullptr, ttol));
     STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co));
     const fhw_frft_chunk* d_ch = (const fhw_frft_chunk*)(sb + o_ch);
     for (size_t ps = 0; ps + 1 < pass_first.size(); ++ps) {
@@ -1144,9 +1153,21 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
         if (n == 0) continue;
         STAGE(c, FHW_STAGE_SYNTH, launch_frft(c->stream, (const double*)(sb + o_c), d_ch + pass_first[ps], n, N_r, F,
                                               L, Q, beta, W / M_PI, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co, u,
-                                              N_t));
+                                              N_t, bnd, gmax, ttol));
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));
+    if (track) {
+        // pairs kept, for fhw_synth_active_pairs
+        std::vector<double> b((size_t)count * N_r);
+        unsigned long long mx = 0;
+        FHW_HIP(c, hipMemcpy(b.data(), bnd, 8 * b.size(), hipMemcpyDeviceToHost));
+        FHW_HIP(c, hipMemcpy(&mx, gmax, 8, hipMemcpyDeviceToHost));
+        double gm;
+        memcpy(&gm, &mx, 8);
+        int64_t n = 0;
+        for (double v : b) n += v > ttol * gm ? 1 : 0;
+        c->trk_active = n;
+    }
     return FHW_OK;
 }
 

@@ -190,12 +190,16 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
                                                        int L, int logL, int Q, int logQ, double beta, double scale,
                                                        const zd* __restrict__ tw, const zd* __restrict__ Hs,
                                                        const zd* __restrict__ cin, const zd* __restrict__ cout,
-                                                       double* __restrict__ u, int64_t N_t) {
+                                                       double* __restrict__ u, int64_t N_t,
+                                                       const double* __restrict__ bnd,
+                                                       const unsigned long long* __restrict__ gmax, double tol) {
     extern __shared__ zd X[];
     __shared__ zd thi[64], tlo[64];
-    frft_tables(thi, tlo, tw, Q);
     const fhw_frft_chunk ch = chunks[blockIdx.x];
     const int r = blockIdx.y;
+    // tracking: the whole workgroup leaves before its first barrier
+    if (bnd && bnd[(int64_t)ch.slot * N_r + r] <= tol * __longlong_as_double((long long)*gmax)) return;
+    frft_tables(thi, tlo, tw, Q);
     const int M = 2 * F;
     const double* a = cre + ((int64_t)ch.slot * N_r + r) * M;
     // a_m at index m mod L, zero elsewhere, in bit-reversed order
@@ -282,11 +286,12 @@ hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, v
 
 hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* d_chunks, int32_t n_chunks,
                        int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* tw,
-                       const void* Hs, const void* cin, const void* cout, double* u, int64_t N_t) {
+                       const void* Hs, const void* cin, const void* cout, double* u, int64_t N_t,
+                       const double* bnd, const unsigned long long* gmax, double tol) {
     if (n_chunks <= 0 || N_r <= 0) return hipSuccess;
     if (N_r > 65535 || Q > FRFT_QMAX || L > Q || 2 * F > L) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_frft, dim3(n_chunks, N_r), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, c_re, d_chunks,
                        N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)tw, (const zd*)Hs, (const zd*)cin,
-                       (const zd*)cout, u, N_t);
+                       (const zd*)cout, u, N_t, bnd, gmax, tol);
     return hipGetLastError();
 }

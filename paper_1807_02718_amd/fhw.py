@@ -317,12 +317,12 @@ class Context:
         self._check(_lib.fhw_synthesize(self._h, C.byref(sg), C.byref(wn), _ptr(V), Nr, tp, len(th), _ptr(u)))
         return u
 
-    def synthesize_uniform(self, f, t0, dt, H, tau0, V, t_first, t_step, n_t, L=0, u=None):
+    def synthesize_uniform(self, f, t0, dt, H, tau0, V, t_first, t_step, n_t, L=0, u=None, track_tol=0.0):
         """fhw_synthesize_uniform: u[r][n] at t_first + n t_step by the fast
         scaled convolution of size L (0 = 4F)."""
         f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
         sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
-        wn = fhw_windows(float(H), float(tau0), 0.0)
+        wn = fhw_windows(float(H), float(tau0), float(track_tol))
         Nr = V.shape[0]
         if u is None:
             u = torch.empty((Nr, int(n_t)), dtype=torch.float64, device=self.device)
