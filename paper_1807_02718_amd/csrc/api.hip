@@ -949,7 +949,7 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     const int F = c->prob.F;
     const int M = 2 * F;
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F must be a power of two");
-    if ((size_t)M * 16 > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F too large");
+    if (M > 8192 || (size_t)M * 16 > (size_t)lds_limit(c)) return fhw_fail(c, FHW_E_INVALID, "synthesize: 2F too large");
     const double W = c->prob.W;
     int64_t k_lo, k_hi;
     signal_windows(sig, H, &k_lo, &k_hi);
@@ -1349,6 +1349,8 @@ int fhw_fourier_coefficients(fhw_ctx* c, const void* B, int32_t count, const voi
     if (c->system_plan) return fhw_fail(c, FHW_E_STATE, "fourier_coefficients: the plan is a list of systems (no DFT grid)");
     const int M = 2 * c->prob.F;
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: 2F must be a power of two");
+    if (M > 8192 || (size_t)M * 16 > (size_t)lds_limit(c))
+        return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: 2F too large");
     if (count < 0 || N_r < 0 || ((count > 0 && N_r > 0) && (!B || !V || !cc)) || !isfinite(tau0))
         return fhw_fail(c, FHW_E_INVALID, "fourier_coefficients: bad arguments");
     STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, B, count, V, N_r, c->prob.W, c->prob.F, tau0, cc,

@@ -18,6 +18,7 @@
 // taken as a circular convolution of length Q >= NC + L - 1 in LDS.
 #include "fhw_device.h"
 #include "fhw_internal.h"
+#include "lds_fft.h"
 
 #define FRFT_THREADS 1024
 #define FRFT_QMAX 8192
@@ -35,109 +36,6 @@ __device__ __forceinline__ zd frft_expipi(double v, double s) {
     double sn, cs;
     sincospi(rdc + e, &sn, &cs);
     return cmk(cs, sn);
-}
-
-// Twiddle e^{-2 pi i j / Q}, j < Q/2 <= 4096, as the product of two LDS
-// table entries: thi[a] = e^{-2 pi i 64 a / Q}, tlo[b] = e^{-2 pi i b / Q}.
-__device__ __forceinline__ zd frft_tw(const zd* thi, const zd* tlo, int j) { return cmul(thi[j >> 6], tlo[j & 63]); }
-
-// Fill the two 64-entry tables from the global table tw[Q/2] (the caller
-// synchronizes before use).
-__device__ __forceinline__ void frft_tables(zd* thi, zd* tlo, const zd* __restrict__ tw, int Q) {
-    if (threadIdx.x < 64) {
-        const int t = threadIdx.x;
-        tlo[t] = t < Q / 2 ? tw[t] : cmk(1.0, 0.0);
-        thi[t] = 64 * t < Q / 2 ? tw[64 * t] : cmk(1.0, 0.0);
-    }
-}
-
-// One radix-2 DIT stage of half-length h on two values in registers.
-__device__ __forceinline__ void frft_bfly(zd& a, zd& b, zd w) {
-    const zd t = cmul(b, w);
-    b = csub(a, t);
-    a = cadd(a, t);
-}
-
-// In-place decimation-in-time FFT of length S = 2^logS (S <= Q) of LDS data
-// stored in bit-reversed order: X_k = sum_j x_j e^{-2 pi i j k / S}.  The
-// radix-2 stages go three at a time (radix 2^3): a thread loads x at
-// i0 + e h, e < 8, and applies in registers the stages of half-lengths h
-// (twiddle W_{2h}^pos), 2h (W_{4h}^{pos + e h}, e < 2) and 4h
-// (W_{8h}^{pos + e h}, e < 4), all formed from the one table value
-// W_{8h}^pos; one or two leading stages go two at a time or alone so that
-// the rest divides by three.
-__device__ void frft_lds_fft(zd* X, int logS, const zd* thi, const zd* tlo, int logQ) {
-    const int S = 1 << logS;
-    int lg = 1;
-    const int lead = logS % 3;
-    if (lead == 1) {
-#pragma unroll
-        for (int k = 0; k < FRFT_PER / 2; ++k) {
-            const int t = threadIdx.x + k * FRFT_THREADS;
-            if (t < (S >> 1)) {
-                zd a = X[2 * t], b = X[2 * t + 1];
-                frft_bfly(a, b, cmk(1.0, 0.0));
-                X[2 * t] = a;
-                X[2 * t + 1] = b;
-            }
-        }
-        __syncthreads();
-        lg = 2;
-    } else if (lead == 2) {
-#pragma unroll
-        for (int k = 0; k < FRFT_PER / 4; ++k) {
-            const int t = threadIdx.x + k * FRFT_THREADS;
-            if (t < (S >> 2)) {
-                // stages of half-lengths 1 and 2 on x[4t .. 4t+3]
-                zd x0 = X[4 * t], x1 = X[4 * t + 1], x2 = X[4 * t + 2], x3 = X[4 * t + 3];
-                frft_bfly(x0, x1, cmk(1.0, 0.0));
-                frft_bfly(x2, x3, cmk(1.0, 0.0));
-                frft_bfly(x0, x2, cmk(1.0, 0.0));
-                frft_bfly(x1, x3, frft_tw(thi, tlo, 1 << (logQ - 2)));
-                X[4 * t] = x0;
-                X[4 * t + 1] = x1;
-                X[4 * t + 2] = x2;
-                X[4 * t + 3] = x3;
-            }
-        }
-        __syncthreads();
-        lg = 3;
-    }
-    for (; lg + 2 <= logS; lg += 3) {
-        const int h = 1 << (lg - 1);
-#pragma unroll
-        for (int k = 0; k < FRFT_PER / 8; ++k) {
-            const int t = threadIdx.x + k * FRFT_THREADS;
-            if (t < (S >> 3)) {
-                const int pos = t & (h - 1);
-                const int i0 = ((t >> (lg - 1)) << (lg + 2)) + pos;
-                zd x[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = X[i0 + e * h];
-                // one table twiddle w8 = W_{8h}^pos; the others from it:
-                // W_{4h}^pos = w8^2, W_{2h}^pos = w8^4, W_{4h}^{pos+h} = -i W_{4h}^pos,
-                // W_{8h}^{pos+h} = W_8 w8, W_{8h}^{pos+2h} = -i w8, W_{8h}^{pos+3h} = -i W_{8h}^{pos+h}
-                const zd w8 = frft_tw(thi, tlo, pos << (logQ - lg - 2));
-                const zd w4 = cmul(w8, w8);
-                const zd w2 = cmul(w4, w4);
-#pragma unroll
-                for (int e = 0; e < 8; e += 2) frft_bfly(x[e], x[e + 1], w2);
-                const zd w4b = cmk(w4.im, -w4.re);
-                frft_bfly(x[0], x[2], w4);
-                frft_bfly(x[4], x[6], w4);
-                frft_bfly(x[1], x[3], w4b);
-                frft_bfly(x[5], x[7], w4b);
-                const zd w8b = cmul(w8, cmk(FHW_INV_SQRT2, -FHW_INV_SQRT2));
-                frft_bfly(x[0], x[4], w8);
-                frft_bfly(x[1], x[5], w8b);
-                frft_bfly(x[2], x[6], cmk(w8.im, -w8.re));
-                frft_bfly(x[3], x[7], cmk(w8b.im, -w8b.re));
-#pragma unroll
-                for (int e = 0; e < 8; ++e) X[i0 + e * h] = x[e];
-            }
-        }
-        __syncthreads();
-    }
 }
 
 __global__ __launch_bounds__(256) void k_frft_twiddles(int Q, zd* __restrict__ tw) {
@@ -178,7 +76,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int 
         X[frft_brev(pos, logQ)] = v;
     }
     __syncthreads();
-    frft_lds_fft(X, logQ, thi, tlo, logQ);
+    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logQ, thi, tlo, logQ);
     const double iq = 1.0 / (double)Q;
     for (int k = threadIdx.x; k < Q; k += FRFT_THREADS) Hs[k] = cmk(X[k].re * iq, X[k].im * iq);
 }
@@ -209,7 +107,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         X[frft_brev(idx, logL)] = cmk(v, 0.0);
     }
     __syncthreads();
-    frft_lds_fft(X, logL, thi, tlo, logQ);   // X[p mod L] = C_p
+    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logL, thi, tlo, logQ);   // X[p mod L] = C_p
     zd zv[FRFT_PER];
     const double il = 1.0 / (double)L;
     // phase ramp e^{2 pi i p xs / L} at p = P - L/2, P = tid + k 1024: the
@@ -234,7 +132,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         if (P < Q) X[frft_brev(P, logQ)] = zv[k];
     }
     __syncthreads();
-    frft_lds_fft(X, logQ, thi, tlo, logQ);
+    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logQ, thi, tlo, logQ);
     // product with the chirp spectrum; the inverse transform as conj(FFT(conj))
 #pragma unroll
     for (int k = 0; k < FRFT_PER; ++k) {
@@ -248,7 +146,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         if (K < Q) X[frft_brev(K, logQ)] = zv[k];
     }
     __syncthreads();
-    frft_lds_fft(X, logQ, thi, tlo, logQ);
+    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logQ, thi, tlo, logQ);
     double* ur = u + (int64_t)r * N_t + ch.n0;
     for (int i = threadIdx.x; i < ch.n; i += FRFT_THREADS) {
         const zd y = cconj(X[i]);

@@ -6,8 +6,10 @@
 //                                                  (eqs. approx, discConv, ukW, final_u; T2, T5)
 #include "fhw_device.h"
 #include "fhw_internal.h"
+#include "lds_fft.h"
 
 #define SYN_THREADS 256
+#define SYN_MMAX 8192   // largest 2F: the LDS buffer and the 64 x 64 twiddle tables
 #define WS_CHUNK 2048
 
 // Partition-of-unity window (eq. window_func) with eta(u) = exp(2 e^{-1/u}/(u-1)).
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_max(const zd* __restrict
     }
 }
 
-// One workgroup per (point r, window slot q): LDS radix-2 FFT of length M = 2F
+// One workgroup per (point r, window slot q): LDS radix-2^3 FFT of length M = 2F
 // of G_l = B_q(omega_l) V(r, omega_l) e^{-i omega_l tau0};
 // c_m = (-1)^m X[m mod M] / M stored at index m + F: complex128 into c, or,
 // when c_re is given instead, only the real parts (all the synthesis needs:
@@ -137,6 +139,8 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
     const double dw = W / (double)F;
     const zd* Bq = B + (int64_t)q * M;
     const zd* Vr = V + (int64_t)r * M;
+    __shared__ zd thi[64], tlo[64];
+    frft_tables_direct(thi, tlo, M);
     for (int l = threadIdx.x; l < M; l += SYN_THREADS) {
         const double om = -W + dw * (double)l;
         double s, cs;
@@ -146,20 +150,7 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
         X[rev] = g;
     }
     __syncthreads();
-    for (int len = 2; len <= M; len <<= 1) {
-        const int half = len >> 1;
-        for (int t = threadIdx.x; t < M / 2; t += SYN_THREADS) {
-            const int grp = t / half, pos = t - grp * half;
-            const int i = grp * len + pos, j = i + half;
-            double s, cs;
-            sincospi(-2.0 * (double)pos / (double)len, &s, &cs);
-            const zd u = X[i];
-            const zd v = cmul(X[j], cmk(cs, s));
-            X[i] = cadd(u, v);
-            X[j] = csub(u, v);
-        }
-        __syncthreads();
-    }
+    lds_fft<SYN_THREADS, SYN_MMAX>(X, logM, thi, tlo, logM);
     const int64_t base = ((int64_t)q * N_r + r) * M;
     const double inv = 1.0 / (double)M;
     double babs = 0.0;
@@ -293,6 +284,7 @@ hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, co
                                  unsigned long long* gmax, double* wmax, unsigned long long* gwmax, double tol) {
     if (count <= 0 || N_r <= 0) return hipSuccess;
     const int M = 2 * F;
+    if (M > SYN_MMAX || (M & (M - 1))) return hipErrorInvalidValue;
     int logM = 0;
     while ((1 << logM) < M) ++logM;
     size_t lds = (size_t)M * sizeof(zd);
