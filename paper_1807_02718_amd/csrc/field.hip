@@ -9,7 +9,7 @@
 
 // One wave per (observation point, frequency); lanes stride over the nodes,
 // fixed-order wave reduction.
-__global__ __launch_bounds__(256) void k_field(const fhw_field_item* __restrict__ items, int F,
+__global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restrict__ items, int F,
                                                const zd* __restrict__ psi, const double* __restrict__ obs, int N_r,
                                                double zero_value, zd* __restrict__ V) {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
