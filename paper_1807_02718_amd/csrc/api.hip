@@ -1113,12 +1113,11 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
         }
     }
     pass_first.push_back((int32_t)chunks.size());
-    // scratch layout: klist | B | c (real parts) | twiddles | chirp spectrum | chirps | chunks | tracking
+    // scratch layout: klist | B | c (real parts) | chirp spectrum | chirps | chunks | tracking
     size_t o_k = 0;
     size_t o_B = align_up(o_k + (size_t)std::max(count, 1) * 8, 256);
     size_t o_c = align_up(o_B + (size_t)count * M * 16, 256);
-    size_t o_tw = align_up(o_c + (size_t)count * N_r * M * 8, 256);
-    size_t o_hs = align_up(o_tw + (size_t)Q / 2 * 16, 256);
+    size_t o_hs = align_up(o_c + (size_t)count * N_r * M * 8, 256);
     size_t o_ci = align_up(o_hs + (size_t)Q * 16, 256);
     size_t o_co = align_up(o_ci + (size_t)L * 16, 256);
     size_t o_ch = align_up(o_co + (size_t)NC * 16, 256);
@@ -1146,13 +1145,13 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, sb + o_B, count, V, N_r, W, F, tau0, nullptr,
                                                      (double*)(sb + o_c), bnd, gmax, (double*)(sb + o_wm),
                                                      gmax ? gmax + 1 : nullptr, ttol));
-    STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co));
+    STAGE(c, FHW_STAGE_SYNTH, launch_frft_setup(c->stream, L, NC, Q, beta, sb + o_hs, sb + o_ci, sb + o_co));
     const fhw_frft_chunk* d_ch = (const fhw_frft_chunk*)(sb + o_ch);
     for (size_t ps = 0; ps + 1 < pass_first.size(); ++ps) {
         const int32_t n = pass_first[ps + 1] - pass_first[ps];
         if (n == 0) continue;
         STAGE(c, FHW_STAGE_SYNTH, launch_frft(c->stream, (const double*)(sb + o_c), d_ch + pass_first[ps], n, N_r, F,
-                                              L, Q, beta, W / M_PI, sb + o_tw, sb + o_hs, sb + o_ci, sb + o_co, u,
+                                              L, Q, beta, W / M_PI, sb + o_hs, sb + o_ci, sb + o_co, u,
                                               N_t, bnd, gmax, ttol));
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));

@@ -258,17 +258,15 @@ struct fhw_frft_chunk {
 // largest power-of-two convolution length Q (<= 8192) whose complex128 buffer
 // fits in lds_bytes
 int frft_max_q(int lds_bytes);
-// twiddles tw[Q/2], the chirp spectrum Hs[Q] and the chirps cin[L], cout[NC]
-// for (L, NC, Q, beta)
-hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* tw, void* Hs, void* cin,
-                             void* cout);
+// the chirp spectrum Hs[Q] and the chirps cin[L], cout[NC] for (L, NC, Q, beta)
+hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* Hs, void* cin, void* cout);
 // u[r][n0 + i] += scale d(xs + beta i), i < n, for every chunk and point r;
 // chunks of one launch must cover disjoint time ranges.  bnd != NULL
 // (tracking): window slot sl is skipped at point r when
 // bnd[sl N_r + r] <= tol * (*gmax)
 hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* d_chunks, int32_t n_chunks,
-                       int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* tw,
-                       const void* Hs, const void* cin, const void* cout, double* u, int64_t N_t,
+                       int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* Hs,
+                       const void* cin, const void* cout, double* u, int64_t N_t,
                        const double* bnd = nullptr, const unsigned long long* gmax = nullptr, double tol = 0.0);
 // bnd != NULL: skip window slot sl at point r when bnd[sl N_r + r] <= tol * (*gmax)
 hipError_t launch_synth(hipStream_t s, const void* c, const int32_t* d_slot, int64_t k_min,

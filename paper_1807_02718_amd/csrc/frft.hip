@@ -38,20 +38,12 @@ __device__ __forceinline__ zd frft_expipi(double v, double s) {
     return cmk(cs, sn);
 }
 
-__global__ __launch_bounds__(256) void k_frft_twiddles(int Q, zd* __restrict__ tw) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= Q / 2) return;
-    double sn, cs;
-    sincospi(-2.0 * (double)j / (double)Q, &sn, &cs);
-    tw[j] = cmk(cs, sn);
-}
-
 // Spectrum of the chirp h (laid out circularly over Q), divided by Q so that
 // the inverse transform of the product needs no further scaling; and the
 // chirps shared by every chunk and point: cin[P] = e^{i pi beta p^2 / L} / L,
 // p = P - L/2, P < L, and cout[i] = e^{i pi beta i^2 / L}, i < NC.
 __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int Q, int logQ, double beta,
-                                                             const zd* __restrict__ tw, zd* __restrict__ Hs,
+                                                             zd* __restrict__ Hs,
                                                              zd* __restrict__ cin, zd* __restrict__ cout) {
     extern __shared__ zd X[];
     const double il = 1.0 / (double)L;
@@ -62,7 +54,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int 
     }
     for (int i = threadIdx.x; i < NC; i += FRFT_THREADS) cout[i] = frft_expipi(beta, (double)i * (double)i * il);
     __shared__ zd thi[64], tlo[64];
-    frft_tables(thi, tlo, tw, Q);
+    fft_tables(thi, tlo, Q);
     for (int pos = threadIdx.x; pos < Q; pos += FRFT_THREADS) {
         zd v = cmk(0.0, 0.0);
         int j = 0;
@@ -86,8 +78,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft_chirp(int L, int NC, int 
 __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict__ cre,
                                                        const fhw_frft_chunk* __restrict__ chunks, int N_r, int F,
                                                        int L, int logL, int Q, int logQ, double beta, double scale,
-                                                       const zd* __restrict__ tw, const zd* __restrict__ Hs,
-                                                       const zd* __restrict__ cin, const zd* __restrict__ cout,
+                                                       const zd* __restrict__ Hs, const zd* __restrict__ cin, const zd* __restrict__ cout,
                                                        double* __restrict__ u, int64_t N_t,
                                                        const double* __restrict__ bnd,
                                                        const unsigned long long* __restrict__ gmax, double tol) {
@@ -97,7 +88,7 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
     const int r = blockIdx.y;
     // tracking: the whole workgroup leaves before its first barrier
     if (bnd && bnd[(int64_t)ch.slot * N_r + r] <= tol * __longlong_as_double((long long)*gmax)) return;
-    frft_tables(thi, tlo, tw, Q);
+    fft_tables(thi, tlo, Q);
     const int M = 2 * F;
     const double* a = cre + ((int64_t)ch.slot * N_r + r) * M;
     // a_m at index m mod L, zero elsewhere, in bit-reversed order
@@ -167,8 +158,7 @@ static int ilog2(int v) {
     return l;
 }
 
-hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* tw, void* Hs, void* cin,
-                             void* cout) {
+hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* Hs, void* cin, void* cout) {
     if (Q > FRFT_QMAX || Q < 2 || (Q & (Q - 1)) || L > Q || NC < 1 || NC + L - 1 > Q) return hipErrorInvalidValue;
     static std::atomic<uint64_t> attr{0};
     if (fhw_first_on_device(attr)) {
@@ -176,20 +166,19 @@ hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, v
         (void)hipFuncSetAttribute((const void*)k_frft_chirp, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_frft, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     }
-    hipLaunchKernelGGL(k_frft_twiddles, dim3((Q / 2 + 255) / 256), dim3(256), 0, s, Q, (zd*)tw);
     hipLaunchKernelGGL(k_frft_chirp, dim3(1), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, L, NC, Q, ilog2(Q), beta,
-                       (const zd*)tw, (zd*)Hs, (zd*)cin, (zd*)cout);
+                       (zd*)Hs, (zd*)cin, (zd*)cout);
     return hipGetLastError();
 }
 
 hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* d_chunks, int32_t n_chunks,
-                       int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* tw,
-                       const void* Hs, const void* cin, const void* cout, double* u, int64_t N_t,
+                       int32_t N_r, int32_t F, int32_t L, int32_t Q, double beta, double scale, const void* Hs,
+                       const void* cin, const void* cout, double* u, int64_t N_t,
                        const double* bnd, const unsigned long long* gmax, double tol) {
     if (n_chunks <= 0 || N_r <= 0) return hipSuccess;
     if (N_r > 65535 || Q > FRFT_QMAX || L > Q || 2 * F > L) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_frft, dim3(n_chunks, N_r), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, c_re, d_chunks,
-                       N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)tw, (const zd*)Hs, (const zd*)cin,
+                       N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)Hs, (const zd*)cin,
                        (const zd*)cout, u, N_t, bnd, gmax, tol);
     return hipGetLastError();
 }

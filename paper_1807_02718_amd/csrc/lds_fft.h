@@ -5,20 +5,11 @@
 
 // Twiddle e^{-2 pi i j / Q}, j < Q/2 <= 4096, as the product of two LDS
 // table entries: thi[a] = e^{-2 pi i 64 a / Q}, tlo[b] = e^{-2 pi i b / Q}.
-__device__ __forceinline__ zd frft_tw(const zd* thi, const zd* tlo, int j) { return cmul(thi[j >> 6], tlo[j & 63]); }
+__device__ __forceinline__ zd fft_tw(const zd* thi, const zd* tlo, int j) { return cmul(thi[j >> 6], tlo[j & 63]); }
 
-// Fill the two 64-entry tables from the global table tw[Q/2] (the caller
+// The two 64-entry tables for a transform length Q, by sincospi (the caller
 // synchronizes before use).
-__device__ __forceinline__ void frft_tables(zd* thi, zd* tlo, const zd* __restrict__ tw, int Q) {
-    if (threadIdx.x < 64) {
-        const int t = threadIdx.x;
-        tlo[t] = t < Q / 2 ? tw[t] : cmk(1.0, 0.0);
-        thi[t] = 64 * t < Q / 2 ? tw[64 * t] : cmk(1.0, 0.0);
-    }
-}
-
-// The same tables computed in place (sincospi) for a transform length Q.
-__device__ __forceinline__ void frft_tables_direct(zd* thi, zd* tlo, int Q) {
+__device__ __forceinline__ void fft_tables(zd* thi, zd* tlo, int Q) {
     if (threadIdx.x < 64) {
         const int t = threadIdx.x;
         double sn, cs;
@@ -30,7 +21,7 @@ __device__ __forceinline__ void frft_tables_direct(zd* thi, zd* tlo, int Q) {
 }
 
 // One radix-2 DIT stage of half-length h on two values in registers.
-__device__ __forceinline__ void frft_bfly(zd& a, zd& b, zd w) {
+__device__ __forceinline__ void fft_bfly(zd& a, zd& b, zd w) {
     const zd t = cmul(b, w);
     b = csub(a, t);
     a = cadd(a, t);
@@ -56,7 +47,7 @@ __device__ void lds_fft(zd* X, int logS, const zd* thi, const zd* tlo, int logQ)
             const int t = threadIdx.x + k * TH;
             if (t < (S >> 1)) {
                 zd a = X[2 * t], b = X[2 * t + 1];
-                frft_bfly(a, b, cmk(1.0, 0.0));
+                fft_bfly(a, b, cmk(1.0, 0.0));
                 X[2 * t] = a;
                 X[2 * t + 1] = b;
             }
@@ -70,10 +61,10 @@ __device__ void lds_fft(zd* X, int logS, const zd* thi, const zd* tlo, int logQ)
             if (t < (S >> 2)) {
                 // stages of half-lengths 1 and 2 on x[4t .. 4t+3]
                 zd x0 = X[4 * t], x1 = X[4 * t + 1], x2 = X[4 * t + 2], x3 = X[4 * t + 3];
-                frft_bfly(x0, x1, cmk(1.0, 0.0));
-                frft_bfly(x2, x3, cmk(1.0, 0.0));
-                frft_bfly(x0, x2, cmk(1.0, 0.0));
-                frft_bfly(x1, x3, frft_tw(thi, tlo, 1 << (logQ - 2)));
+                fft_bfly(x0, x1, cmk(1.0, 0.0));
+                fft_bfly(x2, x3, cmk(1.0, 0.0));
+                fft_bfly(x0, x2, cmk(1.0, 0.0));
+                fft_bfly(x1, x3, fft_tw(thi, tlo, 1 << (logQ - 2)));
                 X[4 * t] = x0;
                 X[4 * t + 1] = x1;
                 X[4 * t + 2] = x2;
@@ -97,21 +88,21 @@ __device__ void lds_fft(zd* X, int logS, const zd* thi, const zd* tlo, int logQ)
                 // one table twiddle w8 = W_{8h}^pos; the others from it:
                 // W_{4h}^pos = w8^2, W_{2h}^pos = w8^4, W_{4h}^{pos+h} = -i W_{4h}^pos,
                 // W_{8h}^{pos+h} = W_8 w8, W_{8h}^{pos+2h} = -i w8, W_{8h}^{pos+3h} = -i W_{8h}^{pos+h}
-                const zd w8 = frft_tw(thi, tlo, pos << (logQ - lg - 2));
+                const zd w8 = fft_tw(thi, tlo, pos << (logQ - lg - 2));
                 const zd w4 = cmul(w8, w8);
                 const zd w2 = cmul(w4, w4);
 #pragma unroll
-                for (int e = 0; e < 8; e += 2) frft_bfly(x[e], x[e + 1], w2);
+                for (int e = 0; e < 8; e += 2) fft_bfly(x[e], x[e + 1], w2);
                 const zd w4b = cmk(w4.im, -w4.re);
-                frft_bfly(x[0], x[2], w4);
-                frft_bfly(x[4], x[6], w4);
-                frft_bfly(x[1], x[3], w4b);
-                frft_bfly(x[5], x[7], w4b);
+                fft_bfly(x[0], x[2], w4);
+                fft_bfly(x[4], x[6], w4);
+                fft_bfly(x[1], x[3], w4b);
+                fft_bfly(x[5], x[7], w4b);
                 const zd w8b = cmul(w8, cmk(FHW_INV_SQRT2, -FHW_INV_SQRT2));
-                frft_bfly(x[0], x[4], w8);
-                frft_bfly(x[1], x[5], w8b);
-                frft_bfly(x[2], x[6], cmk(w8.im, -w8.re));
-                frft_bfly(x[3], x[7], cmk(w8b.im, -w8b.re));
+                fft_bfly(x[0], x[4], w8);
+                fft_bfly(x[1], x[5], w8b);
+                fft_bfly(x[2], x[6], cmk(w8.im, -w8.re));
+                fft_bfly(x[3], x[7], cmk(w8b.im, -w8b.re));
 #pragma unroll
                 for (int e = 0; e < 8; ++e) X[i0 + e * h] = x[e];
             }

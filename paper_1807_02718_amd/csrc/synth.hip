@@ -140,7 +140,7 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
     const zd* Bq = B + (int64_t)q * M;
     const zd* Vr = V + (int64_t)r * M;
     __shared__ zd thi[64], tlo[64];
-    frft_tables_direct(thi, tlo, M);
+    fft_tables(thi, tlo, M);
     for (int l = threadIdx.x; l < M; l += SYN_THREADS) {
         const double om = -W + dw * (double)l;
         double s, cs;
