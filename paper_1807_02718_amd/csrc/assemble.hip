@@ -71,25 +71,46 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
     const int jg = threadIdx.x >> 5;
     const int i = i0 + il;
     const bool iok = i < N;
+    // The tile's source-node data and the Kress tables at its 2 AT - 1 index
+    // differences l = (i - j) mod N and N - l, staged once in LDS.
+    __shared__ double sj[5][AT];
+    __shared__ double st[4][2 * AT];
+    if (threadIdx.x < AT) {
+        const int j = j0 + threadIdx.x;
+        const bool ok = j < N;
+        sj[0][threadIdx.x] = ok ? x1[j] : 0.0;
+        sj[1][threadIdx.x] = ok ? x2[j] : 0.0;
+        sj[2][threadIdx.x] = ok ? sp[j] : 0.0;
+        sj[3][threadIdx.x] = ok ? nu1[j] : 0.0;
+        sj[4][threadIdx.x] = ok ? nu2[j] : 0.0;
+    } else if (threadIdx.x < 3 * AT - 1) {
+        const int e = threadIdx.x - AT;   // l = i0 - j0 - (AT - 1) + e (mod N)
+        const int l = ((i0 - j0 - (AT - 1) + e) % N + N) % N;
+        const int lm = (l == 0) ? 0 : N - l;
+        st[0][e] = it.logtab[l];
+        st[1][e] = it.R[l];
+        st[2][e] = it.logtab[lm];
+        st[3][e] = it.R[lm];
+    }
     double xi1 = 0, xi2 = 0, ni1 = 0, ni2 = 0, spi = 0;
     if (iok) { xi1 = x1[i]; xi2 = x2[i]; ni1 = nu1[i]; ni2 = nu2[i]; spi = sp[i]; }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < AT / 8; ++k) {
         const int jl = jg + 8 * k;
         const int j = j0 + jl;
         if (!iok || j >= N || (I == J && i < j)) continue;
-        const double spj = sp[j];
-        int l = i - j;
-        if (l < 0) l += N;
+        const double spj = sj[2][jl];
+        const int dd = il - jl + AT - 1;   // index of l = (i - j) mod N in st
         zd e_ij, e_ji;
         if (i != j) {
-            const double d1 = x1[j] - xi1, d2 = x2[j] - xi2;   // d = x_j - x_i
+            const double d1 = sj[0][jl] - xi1, d2 = sj[1][jl] - xi2;   // d = x_j - x_i
             const double r2 = d1 * d1 + d2 * d2;
             const double ir = fhw_rsqrt(r2);   // 1 / r
             const double r = r2 * ir;
             double J0, Y0, J1, Y1;
             fhw_bessel01(kappa * r, J0, Y0, J1, Y1);
-            const double lam = it.logtab[l];
+            const double lam = st[0][dd];
             const double M1 = -J0 * inv4pi;
             const double M2r = -0.25 * Y0 - M1 * lam;
             const double M2i = 0.25 * J0;
@@ -97,10 +118,9 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
             const double cY = -0.25 * kappa * Y1;
             const double cJ = 0.25 * kappa * J1;
             const double n_i = (ni1 * d1 + ni2 * d2) * ir;          // target i: nu_i . (x_j - x_i) / r
-            const double n_j = -(nu1[j] * d1 + nu2[j] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
-            e_ij = cfie_entry(n_i, cL, cY, cJ, M1, M2r, M2i, lam, it.R[l], wq, eta, spj);
-            const int lm = (l == 0) ? 0 : N - l;
-            e_ji = cfie_entry(n_j, cL, cY, cJ, M1, M2r, M2i, it.logtab[lm], it.R[lm], wq, eta, spi);
+            const double n_j = -(sj[3][jl] * d1 + sj[4][jl] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
+            e_ij = cfie_entry(n_i, cL, cY, cJ, M1, M2r, M2i, lam, st[1][dd], wq, eta, spj);
+            e_ji = cfie_entry(n_j, cL, cY, cJ, M1, M2r, M2i, st[2][dd], st[3][dd], wq, eta, spi);
         } else {
             const double M2r = -(0.57721566490153286061 + log(0.5 * kappa * spi)) / (2.0 * FHW_PI);
             const double M2i = 0.25;
