@@ -276,6 +276,33 @@ def test_fourier_coefficients(ctx):
         assert relmax(c[q], ref) < 1e-13
 
 
+def test_fourier_coefficients_largest(ctx):
+    """2F = 8192, the largest transform: a 128 KiB LDS buffer beside the
+    static tables (one window, two points; the oracle's direct DFT)."""
+    say("fourier coefficients, 2F = 8192")
+    W, F = 40.0, 4096
+    ctx.plan(Wk.circle(1.0), W, F, N=32)
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((1, 2 * F)) + 1j * rng.standard_normal((1, 2 * F))
+    V = rng.standard_normal((2, 2 * F)) + 1j * rng.standard_normal((2, 2 * F))
+    tau0 = 0.7
+    c = ctx.fourier_coefficients(torch.tensor(B, device="cuda"), torch.tensor(V, device="cuda"), tau0).cpu().numpy()
+    wl = -W + (W / F) * np.arange(2 * F)
+    G = B[0][None, :] * V * np.exp(-1j * wl * tau0)[None, :]
+    ref = O.fourier_coefficients(G, W)
+    # the oracle's direct DFT evaluates exp at phases up to pi F: each term
+    # carries a phase rounding of about eps pi F (2.9e-12 here), the FFT's
+    # twiddles about one ulp
+    err = relmax(c[0], ref)
+    say("vs oracle", err)
+    assert err < 8 * np.finfo(float).eps * np.pi * F
+    # the same coefficients by the FFT identity pinned against the oracle on
+    # the CPU: c_m = (-1)^m FFT(G)[m mod 2F] / 2F
+    m = np.arange(-F, F)
+    fft_ref = ((-1.0) ** m)[None, :] * np.fft.fft(G, axis=1)[:, m % (2 * F)] / (2 * F)
+    assert relmax(c[0], fft_ref) < 1e-13
+
+
 def _pipeline(ctx, wl, precision="fp64", obs=None, zero_value=1.0):
     N = wl.N if not isinstance(wl.N, dict) else None
     kw = {} if N is not None else wl.N
