@@ -10,7 +10,7 @@ scipy.special, LU from LAPACK (scipy.linalg), the DFT is a direct O(M^2) sum
 and the sinc is numpy.sinc.  Nothing is blocked, fused or reordered beyond
 what the cited definitions state.
 
-Readings of passages the paper leaves open (all documented in the design doc):
+Readings of passages the paper leaves open:
   * frequencies omega_j = j W / F, j = 1..F; DFT grid of 2F points on [-W, W)
   * coupling eta = max(kappa, 1); wave speed c = 1 unless given
   * incident field u_inc = f(t - p.r/c), so the boundary signal is a = -f
