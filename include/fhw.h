@@ -263,8 +263,8 @@ int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
  * roundoff where the spectrum is negligible there.  Same windows, active
  * sets and tracking rules (win->track_tol) as fhw_synthesize.
  *   u       device doubles [N_r][N_t], overwritten.
- *   L       0 = 4F; else a power of two with 4F <= L <= 4096 (the chirp-z
- *           convolution of length 2L <= 8192 lives in LDS).
+ *   L       0 = max(4F, 8); else a power of two with max(4F, 8) <= L <= 4096
+ *           (the chirp-z convolution of length <= 8192 lives in LDS).
  * Errors: FHW_E_INVALID for a bad L, t_step <= 0, non-finite inputs, track_tol
  * < 0, N_r > 65535 or 2F not a power of two; FHW_E_STATE as fhw_synthesize. */
 int fhw_synthesize_uniform(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,

@@ -1054,9 +1054,9 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     const int M = 2 * F;
     if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: 2F must be a power of two");
     const int qmax = frft_max_q(lds_limit(c));
-    if (L == 0) L = 2 * M;
-    if (L < 2 * M || (L & (L - 1)) || 2 * L > qmax)
-        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: L must be a power of two with 4F <= L <= " +
+    if (L == 0) L = std::max(2 * M, 8);
+    if (L < 2 * M || L < 8 || (L & (L - 1)) || 2 * L > qmax)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_uniform: L must be a power of two with max(4F, 8) <= L <= " +
                                               std::to_string(qmax / 2));
     const double W = c->prob.W;
     const double span = 1.5 * H;

@@ -98,52 +98,46 @@ __global__ __launch_bounds__(FRFT_THREADS) void k_frft(const double* __restrict_
         X[frft_brev(idx, logL)] = cmk(v, 0.0);
     }
     __syncthreads();
-    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logL, thi, tlo, logQ);   // X[p mod L] = C_p
-    zd zv[FRFT_PER];
+    // C_p = FFT(a) lands at K = p mod L in the final pass; z_P, P = p + L/2,
+    // goes straight to the convolution buffer's bit-reversed slot.  A thread's
+    // outputs K = t + e L/8 have p = t + d L/8 with d = e (e < 4) or e - 8,
+    // so the phase ramp e^{2 pi i p xs / L} is r0 st^d, st = e^{i pi xs / 4}.
     const double il = 1.0 / (double)L;
-    // phase ramp e^{2 pi i p xs / L} at p = P - L/2, P = tid + k 1024: the
-    // first by sincospi, the next ones times e^{2 pi i 1024 xs / L}
-    zd ramp = frft_expipi(ch.xs, 2.0 * (double)((int)threadIdx.x - L / 2) * il);
-    const zd step = frft_expipi(ch.xs, 2.0 * (double)FRFT_THREADS * il);
+    const int sh = logL - 3;
+    const zd r0 = frft_expipi(ch.xs, 2.0 * (double)threadIdx.x * il);
+    const zd st = frft_expipi(ch.xs, 0.25);
+    zd pw[8];
+    pw[0] = r0;
 #pragma unroll
-    for (int k = 0; k < FRFT_PER; ++k) {
-        const int P = threadIdx.x + k * FRFT_THREADS;
-        zd z = cmk(0.0, 0.0);
-        if (P < L) {
-            if (k > 0) ramp = cmul(ramp, step);
-            const zd A = X[(P + L / 2) & (L - 1)];
-            z = cmul(cmul(A, ramp), cin[P]);
-        }
-        zv[k] = z;
-    }
-    __syncthreads();
+    for (int e = 1; e < 4; ++e) pw[e] = cmul(pw[e - 1], st);
+    pw[7] = cmul(r0, cconj(st));
 #pragma unroll
-    for (int k = 0; k < FRFT_PER; ++k) {
-        const int P = threadIdx.x + k * FRFT_THREADS;
-        if (P < Q) X[frft_brev(P, logQ)] = zv[k];
-    }
+    for (int e = 6; e >= 4; --e) pw[e] = cmul(pw[e + 1], cconj(st));
+    lds_fft_epi<FRFT_THREADS, FRFT_QMAX, true>(
+        X, logL, thi, tlo, logQ,
+        [&](int K, zd c) {
+            const int P = (K + L / 2) & (L - 1);
+            return cmul(cmul(c, pw[(K - (int)threadIdx.x) >> sh]), cin[P]);
+        },
+        [&](int K, zd z) { X[frft_brev((K + L / 2) & (L - 1), logQ)] = z; });
+    for (int P = L + threadIdx.x; P < Q; P += FRFT_THREADS) X[frft_brev(P, logQ)] = cmk(0.0, 0.0);
     __syncthreads();
-    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logQ, thi, tlo, logQ);
-    // product with the chirp spectrum; the inverse transform as conj(FFT(conj))
-#pragma unroll
-    for (int k = 0; k < FRFT_PER; ++k) {
-        const int K = threadIdx.x + k * FRFT_THREADS;
-        if (K < Q) zv[k] = cconj(cmul(X[K], Hs[K]));
-    }
+    // forward transform; its outputs times the chirp spectrum, conjugated,
+    // go to bit-reversed slots for the inverse as conj(FFT(conj))
+    lds_fft_epi<FRFT_THREADS, FRFT_QMAX, true>(
+        X, logQ, thi, tlo, logQ, [&](int K, zd v) { return cconj(cmul(v, Hs[K])); },
+        [&](int K, zd w) { X[frft_brev(K, logQ)] = w; });
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < FRFT_PER; ++k) {
-        const int K = threadIdx.x + k * FRFT_THREADS;
-        if (K < Q) X[frft_brev(K, logQ)] = zv[k];
-    }
-    __syncthreads();
-    lds_fft<FRFT_THREADS, FRFT_QMAX>(X, logQ, thi, tlo, logQ);
+    // inverse transform; output i = conj(X_i) times the output chirp
     double* ur = u + (int64_t)r * N_t + ch.n0;
-    for (int i = threadIdx.x; i < ch.n; i += FRFT_THREADS) {
-        const zd y = cconj(X[i]);
-        const zd w = cout[i];
-        ur[i] += scale * (w.re * y.re - w.im * y.im);
-    }
+    lds_fft_epi<FRFT_THREADS, FRFT_QMAX, false>(
+        X, logQ, thi, tlo, logQ, [&](int K, zd v) { return v; },
+        [&](int K, zd v) {
+            if (K < ch.n) {
+                const zd w = cout[K];
+                ur[K] += scale * (w.re * v.re + w.im * v.im);
+            }
+        });
 }
 
 int frft_max_q(int lds_bytes) {
@@ -176,7 +170,7 @@ hipError_t launch_frft(hipStream_t s, const double* c_re, const fhw_frft_chunk* 
                        const void* cin, const void* cout, double* u, int64_t N_t,
                        const double* bnd, const unsigned long long* gmax, double tol) {
     if (n_chunks <= 0 || N_r <= 0) return hipSuccess;
-    if (N_r > 65535 || Q > FRFT_QMAX || L > Q || 2 * F > L) return hipErrorInvalidValue;
+    if (N_r > 65535 || Q > FRFT_QMAX || L > Q || L < 8 || 2 * F > L) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_frft, dim3(n_chunks, N_r), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, c_re, d_chunks,
                        N_r, F, L, ilog2(L), Q, ilog2(Q), beta, scale, (const zd*)Hs, (const zd*)cin,
                        (const zd*)cout, u, N_t, bnd, gmax, tol);

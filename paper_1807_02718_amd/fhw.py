@@ -319,7 +319,7 @@ class Context:
 
     def synthesize_uniform(self, f, t0, dt, H, tau0, V, t_first, t_step, n_t, L=0, u=None, track_tol=0.0):
         """fhw_synthesize_uniform: u[r][n] at t_first + n t_step by the fast
-        scaled convolution of size L (0 = 4F)."""
+        scaled convolution of size L (0 = max(4F, 8))."""
         f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
         sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
         wn = fhw_windows(float(H), float(tau0), float(track_tol))

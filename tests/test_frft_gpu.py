@@ -203,3 +203,26 @@ def test_uniform_synthesis_tracking(ctx):
     assert np.max(np.abs(u1 - u0)) / scale < 1e-12
     with pytest.raises(Exception):
         ctx.synthesize_uniform(f, sig.t0, sig.dt, H, TAU0, V, t_first, t_step, 10, track_tol=-1.0)
+
+
+@pytest.mark.parametrize("F1", [1, 2])
+def test_uniform_synthesis_smallest_transforms(ctx, F1):
+    """2F = 2 and 4: L = 8 (the smallest the fast form takes), a chirp-z
+    length of at most 8192, against the oracle."""
+    say("uniform synthesis, F =", F1)
+    W1 = 3.0
+    ctx.plan(Wk.circle(1.0), W1, F1, N=32)
+    rng = np.random.default_rng(12)
+    Vh = rng.standard_normal((2, 2 * F1)) + 1j * rng.standard_normal((2, 2 * F1))
+    V = torch.as_tensor(Vh, device="cuda")
+    f = torch.as_tensor(SIG.f, device="cuda")
+    t_first, t_step, n_t = 0.0, 0.1, 400
+    u = ctx.synthesize_uniform(f, SIG.t0, SIG.dt, H, TAU0, V, t_first, t_step, n_t).cpu().numpy()
+    times = t_first + t_step * np.arange(n_t)
+    dw = W1 / F1
+    ks = _windows(SIG, H, TAU0, dw, times)
+    B = O.window_spectra(SIG, H, ks, -W1 + dw * np.arange(2 * F1))
+    ref = O.synthesize_uniform(Vh, B, ks, H, TAU0, W1, t_first, t_step, n_t, max(4 * F1, 8))
+    err = np.max(np.abs(u - ref)) / np.max(np.abs(ref))
+    say("windows", len(ks), "err vs oracle", err)
+    assert err < 1e-10
