@@ -33,8 +33,8 @@ TABLE = os.path.join(CSRC, "panel_table.h")
 
 # candidate (W, waves per SIMD) per case; the spill check drops the rest
 CANDIDATES = {
-    256: [(4, 4), (8, 4), (8, 2), (16, 2)],
-    1024: [(4, 4), (8, 4)],
+    256: [(4, 4), (4, 2), (8, 4), (8, 2), (16, 2)],
+    1024: [(4, 4), (8, 4), (16, 4)],
 }
 CASES = [(p, pt, r) for p in ("F32", "F64") for pt in (256, 1024) for r in (1, 2, 4)]
 
