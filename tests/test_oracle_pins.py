@@ -11,7 +11,7 @@ import os
 import mpmath as mp
 import numpy as np
 import pytest
-from scipy import special
+from scipy import integrate, special
 
 import oracle as O
 import workloads as Wk
@@ -354,6 +354,79 @@ def test_interior_time_domain_kite():
     assert np.max(np.abs(out["u"] - exact)) < 1e-8
 
 
+def test_point_source_time_domain_closed_form():
+    """Exterior point source r0, observation points inside the scatterer
+    (pin P6 in time): the total field vanishes inside, so the computed field
+    equals the free wave of the source, the boundary signal a = -f convolved
+    with the 2D wave Green's function H(t - rho) / (2 pi sqrt(t^2 - rho^2)):
+        u(x, t) = (1/2 pi) int_0^inf a(t - rho cosh s) ds,  rho = |x - r0|.
+    The signal has no content near omega = 0 (|A(0)| / max |A| ~ 1e-17), so
+    the log singularity of H0 there does not enter; one window (H = 40, the
+    signal inside its flat part) holds the whole signal."""
+    sig = Wk.gaussian_pulse(t0=0.0, t1=20.0, dt=1 / 64, center=9.0, var2=2.0, freq=10.0)
+    a = lambda t: -np.exp(-(t - 9.0) ** 2 / 2.0) * np.cos(10.0 * t)
+    r0 = np.array([2.5, 0.7])
+    pts = np.array([[0.2, 0.1], [-0.5, 0.3], [0.0, -0.6]])
+    times = np.linspace(0.0, 30.0, 16)
+
+    def exact(x, t):
+        rho = float(np.hypot(*(x - r0)))
+        if t - 18.0 >= rho:          # a(t - tau) vanishes (to 1e-35) for t - tau > 18
+            lo = float(np.arccosh((t - 18.0) / rho))
+        else:
+            lo = 0.0
+        if t <= rho:
+            return 0.0
+        hi = float(np.arccosh(t / rho))
+        edges = np.linspace(lo, hi, 41)
+        tot = sum(integrate.quad(lambda s: a(t - rho * np.cosh(s)), e0, e1, epsabs=1e-16, epsrel=1e-13,
+                                 limit=200)[0] for e0, e1 in zip(edges[:-1], edges[1:]))
+        return tot / (2 * np.pi)
+
+    ref = np.array([[exact(x, t) for t in times] for x in pts])
+    u = O.run(Wk.circle(1.0), 20.0, 192, 128, (1.0, 0.0), sig, 40.0, 0.0, pts, times, incidence="point",
+              r0=tuple(r0))
+    assert np.max(np.abs(ref)) > 0.03
+    assert np.max(np.abs(u - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_convergence_in_frequency_spacing():
+    """Pin P13 in frequency (the setting of the paper's Sec. 6.2 experiment):
+    kite, observation point (2, 2) outside it, incidence direction
+    (1, 1/2)/|(1, 1/2)|, a pulse whose spectrum is a Gaussian of width 2
+    centred at 12 (nothing near omega = 0 or at W = 24), N fixed.  Solve
+    frequencies j 24/240 contain the grids of F = 30 .. 120 (Delta omega =
+    24 / F), so every F uses the same frequency solves and the error against
+    the F = 240 trace is the synthesis' own.  A rule of fixed algebraic order
+    p would lose about p log2 decades per halving of Delta omega; here every
+    halving gains at least 14, and F = 120 is at roundoff."""
+    W, Fref, N = 24.0, 240, 192
+    obs = np.array([[2.0, 2.0]])
+    p = np.array([1.0, 0.5]) / np.hypot(1.0, 0.5)
+    sig = Wk.gaussian_pulse(t0=-6.0, t1=10.0, dt=np.pi / (4 * W), center=2.0, var2=1.0, freq=12.0)
+    _, kappa = O.frequency_grid(W, Fref)
+    eta = O.coupling(kappa)
+    gm = O.geometry(Wk.kite(), N)
+    Vpos = np.zeros((1, Fref), dtype=complex)
+    for j in range(Fref):
+        psi, _ = O.solve_density(O.assemble(gm, kappa[j], eta[j]), O.rhs_plane_wave(gm, kappa[j], eta[j], p))
+        Vpos[:, j] = O.field(gm, psi, kappa[j], obs)
+    H, tau0 = 20.0, 4.0
+    times = np.linspace(-4.0, 16.0, 81)
+    ks = O.window_indices(sig.t[0], sig.t[-1], H)
+    u = {}
+    for F in (30, 40, 60, 80, 120, 240):
+        dw = W / F
+        B = O.window_spectra(sig, H, ks, -W + dw * np.arange(2 * F))
+        Vf = O.field_full_grid(Vpos[:, Fref // F - 1::Fref // F], 1.0)
+        u[F] = O.synthesize(Vf, B, ks, H, tau0, W, times)[0]
+    scale = np.max(np.abs(u[240]))
+    e = {F: np.max(np.abs(u[F] - u[240])) / scale for F in (30, 40, 60, 80, 120)}
+    assert e[30] > e[40] > e[60] > e[80] > e[120]
+    assert np.log2(e[30] / e[60]) > 14 and np.log2(e[40] / e[80]) > 14
+    assert e[120] < 1e-13
+
+
 def test_time_leap_invariance():
     sig = _pulse15()
     H = 10.0
@@ -419,12 +492,34 @@ def test_grid_and_sizes():
     L = O.curve_length(Wk.kite())
     Ns = O.discretization_sizes(kappa, L, 10.0, 64, 32, 4096)
     assert Ns.min() == 64 and np.all(Ns % 32 == 0) and Ns.max() <= 4096
-    assert abs(L - 9.32402267328496) < 1e-9
+    # the kite's perimeter, independently by adaptive quadrature of its speed
+    speed = lambda s: np.hypot(-np.sin(s) - 1.3 * np.sin(2 * s), 1.5 * np.cos(s))
+    L_quad = integrate.quad(speed, 0.0, 2 * np.pi, epsabs=1e-13, epsrel=1e-13, limit=200)[0]
+    assert abs(L - L_quad) < 1e-12 and abs(L - 9.32402267328496) < 1e-9
     # perimeter of a circle of radius 1.7
     assert abs(O.curve_length(Wk.circle(1.7)) - 2 * np.pi * 1.7) < 1e-12
     d = np.hypot(*(O.curve_eval(Wk.kite(), np.linspace(0, 2 * np.pi, 200001))[0]
                    - np.array(GOLDEN["convergence_experiment"]["obs"])).T).min()
     assert abs(d - GOLDEN["convergence_experiment"]["obs_distance_to_boundary_approx"]) < 0.05
+
+
+def test_discretization_sizes_literals():
+    """N = max(n_min, ceil(ppw L kappa / (2 pi) / n_mult) n_mult), capped: the
+    rule "10 points per wavelength over the curve length, rounded up to a
+    multiple of 32" evaluated by hand.  Unit circle (L = 2 pi): ppw L kappa /
+    (2 pi) = 10 kappa points.  kappa = 5.05: 50.5 -> 64; 7: 70 -> 96 (a floor
+    or a rounding would give 64); 12.8: exactly 128 -> 128; 12.81: 128.1 ->
+    160.  Kite (L = 9.3240227, pinned above): kappa = 200 gives 2967.9 ->
+    2976 (a floor gives 2944, a missing 2 pi the cap 4096); kappa = 69 gives
+    1023.9 -> 1024, the bench size; kappa = 200/512 gives 5.8 -> n_min = 64;
+    kappa = 500 gives 7420 -> the cap 4096."""
+    circ = O.discretization_sizes([5.05, 7.0, 12.8, 12.81], 2 * np.pi, 10.0, 32, 32, 4096)
+    assert circ.tolist() == [64, 96, 128, 160]
+    L = O.curve_length(Wk.kite())
+    kite = O.discretization_sizes([200.0, 69.0, 200.0 / 512, 500.0], L, 10.0, 64, 32, 4096)
+    assert kite.tolist() == [2976, 1024, 64, 4096]
+    # the configuration with 17 points per wavelength and cap 2048
+    assert O.discretization_sizes([60.0], L, 17.0, 64, 32, 2048).tolist() == [1536]   # 1513.6 -> 1536
 
 
 def test_geometry_rejects_clockwise_and_degenerate():
