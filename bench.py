@@ -9,9 +9,14 @@ T = 1e4, 256 observation points, 1024 sample times.
 
 Prints ONE JSON line.  `value` = frequency solves per second of the whole step
 (F / step time) in the FP32-LU + FP64-refinement mode; the FP64 mode is timed
-beside it.  `roofline` is for the dominant kernel (the trailing complex update
-of the batched LU, on MFMA), with its average launch time measured by the
-library's HIP-event stage timers over the timed steps.
+beside it.  The timed steps run with the stage timers off, so the LU runs as
+its captured HIP graph.  `roofline` is for the dominant kernel (the trailing
+complex update of the batched LU, on MFMA), with its average launch time
+measured by the library's HIP-event stage timers, on the library's stream,
+over the same number of steps run again right after the timed ones
+(`ms_per_step_profiled`: the timers make the launches go one by one).
+`cpu_baseline` times the FP64 oracle on a sample of the frequencies, spread
+over worker processes on the host cores.
 """
 from __future__ import annotations
 
@@ -44,6 +49,12 @@ def lu_update_flops(Ns, nb=64):
 
 
 def run_mode(fhw, torch, wl, precision, steps, warmup):
+    """Times `steps` whole steps with the stage timers off (the factorization
+    runs as its captured HIP graph, as every caller gets it), then the same
+    number of steps again with the library's HIP-event stage timers on (the
+    launches then go one by one, each bracketed by events on the library's
+    stream) for the per-stage times and the dominant kernel's launch
+    durations."""
     ctx = fhw.Context()
     Ns, off = ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=1e-12, refine_max=10,
                        direction=wl.direction)
@@ -65,17 +76,23 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ctx.profile(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         res, sw = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same steps with the stage timers on
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt_prof = time.perf_counter() - t1
     prof = ctx.profile_read()
     ctx.profile(False)
     ctx.close()
-    return dict(seconds=dt, prof=prof, Ns=[int(n) for n in Ns], res=res, sweeps=sw)
+    return dict(seconds=dt, seconds_profiled=dt_prof, prof=prof, Ns=[int(n) for n in Ns], res=res, sweeps=sw)
 
 
 # HBM bytes per launch of the trailing update on this workload, from rocprofv3
@@ -426,16 +443,16 @@ def serve_bench(fhw, torch, Wk, rates, duration, max_wait, precision):
                       "rates": out}), flush=True)
 
 
-def cpu_baseline(wl, n_freq):
-    """The FP64 oracle on a bounded sample: n_freq frequencies spread over the
-    band, each = assembly + LAPACK solve + field at all observation points."""
+def _oracle_frequencies(args):
+    """One worker of the CPU baseline: the oracle's assembly, LAPACK solve and
+    field for the given frequency indices, with one BLAS thread."""
+    wl, idx = args
     import oracle as O
     from threadpoolctl import threadpool_limits
-    omega, kappa = O.frequency_grid(wl.W, wl.F)
-    eta = O.coupling(kappa)
-    gm = O.geometry(wl.curve, wl.N)
-
-    def timed(idx):
+    with threadpool_limits(limits=1):
+        _, kappa = O.frequency_grid(wl.W, wl.F)
+        eta = O.coupling(kappa)
+        gm = O.geometry(wl.curve, wl.N)
         t0 = time.perf_counter()
         for j in idx:
             A = O.assemble(gm, kappa[j], eta[j])
@@ -444,24 +461,40 @@ def cpu_baseline(wl, n_freq):
             O.field(gm, psi, kappa[j], wl.obs)
         return time.perf_counter() - t0
 
+
+def cpu_baseline(wl, n_freq, max_workers=16):
+    """The FP64 oracle on a bounded sample: n_freq frequencies spread over the
+    band, each = assembly + LAPACK solve + field at all observation points.
+    The frequencies are independent, so they run in parallel over worker
+    processes (one BLAS thread each), as many as the host cores this process
+    may use, at most max_workers; single_core_value is one worker alone."""
+    from multiprocessing import get_context
     idx = np.linspace(0, wl.F - 1, n_freq).round().astype(int)
-    dt = timed(idx)
-    # one BLAS thread, on a smaller sample spread over the same band
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(max_workers, cores, n_freq))
+    parts = [idx[w::workers] for w in range(workers)]
+    with get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_frequencies, [(wl, idx[:1])] * workers)      # imports and caches outside the clock
+        t0 = time.perf_counter()
+        pool.map(_oracle_frequencies, [(wl, p) for p in parts])
+        dt = time.perf_counter() - t0
     n1 = max(1, n_freq // 12)
-    with threadpool_limits(limits=1):
-        dt1 = timed(np.linspace(0, wl.F - 1, n1).round().astype(int))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    dt1 = _oracle_frequencies((wl, np.linspace(0, wl.F - 1, n1).round().astype(int)))
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n_freq / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "cpu_model": model, "single_core_value": n1 / dt1,
+    return {"value": n_freq / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "cpu_model": model, "host_cores_available": cores, "single_core_value": n1 / dt1,
             "sample": f"{n_freq} of {wl.F} frequencies (N={wl.N}): assembly + LAPACK LU solve + field at "
-                      f"{len(wl.obs)} points each, NumPy/SciPy FP64, {threads} BLAS threads "
-                      f"({n1} frequencies with one thread for single_core_value); synthesis excluded"}
+                      f"{len(wl.obs)} points each, NumPy/SciPy FP64, spread over {workers} worker processes "
+                      f"with one BLAS thread each ({n1} frequencies in one process for single_core_value); "
+                      f"synthesis excluded"}
 
 
 def main():
@@ -555,12 +588,14 @@ def main():
                      "kernel": "k_lu_gemm<SUB> (trailing complex update)",
                      "avg_launch_ms": avg_ms, "launches": upd_n, "flops_per_launch": per_launch},
         "stages_ms_per_step": {k: v[0] / a.steps for k, v in r["prof"].items()},
+        "ms_per_step_profiled": 1e3 * r["seconds_profiled"] / a.steps,
         "max_relres": float(np.max(r["res"])) if main_mode == "fp32_refine" else None,
         "max_sweeps": int(np.max(r["sweeps"])) if main_mode == "fp32_refine" else None,
     }
     for m in modes[1:]:
         rr = results[m]
         out[m] = {"value": wl.F * a.steps / rr["seconds"], "ms_per_step": 1e3 * rr["seconds"] / a.steps,
+                  "ms_per_step_profiled": 1e3 * rr["seconds_profiled"] / a.steps,
                   "stages_ms_per_step": {k: v[0] / a.steps for k, v in rr["prof"].items()}}
     if a.latency_reps > 0:
         print("bench: latency", file=sys.stderr, flush=True)

@@ -21,7 +21,7 @@
  *                        over windows (eqs. approx, discConv, ukW, final_u;
  *                        T2, T5)
  *   fhw_synthesize_uniform  the same on a uniform time grid, each window's
- *                        sum by the fast scaled convolution (Sec. 3.3, eq.
+ *                        sum by the fast scaled convolution (Sec. 4.1.2, eq.
  *                        approx_conv_sum)
  *   fhw_run              the three calls above in one
  * plus stage entry points for the same steps on caller buffers.
@@ -230,7 +230,7 @@ typedef struct {
 
 /* Partition of unity (Sec. 3.1): s_k = 1.5 H (k - 1), half-width H; tau0 is an
  * extra recentring shift (0 = the paper's choice).  track_tol > 0 turns on
- * active-partition tracking (Sec. 3.1, remark on tracking).  Window k is left
+ * active-partition tracking (Sec. 3.2, remark on tracking).  Window k is left
  * out everywhere when max_l (|Re B_k| + |Im B_k|) of its signal spectrum is
  * at most track_tol times the largest over the windows (its contribution is
  * then at most (W/pi) 2F max_l |B_k| max_l |V(r, .)|; no coefficients are
@@ -251,7 +251,7 @@ int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
                    const void* V, int32_t N_r, const double* times, int32_t N_t,
                    double* u);
 
-/* Sec. 3.3 (FFT accelerated evaluation of scaled discrete convolutions, eqs.
+/* Sec. 4.1.2 (FFT accelerated evaluation of scaled discrete convolutions, eqs.
  * conv_sum and approx_conv_sum): as fhw_synthesize, on the uniform grid
  * t_n = t_first + n t_step, n < N_t, with each window's sum over m replaced
  * by its L-periodic approximation

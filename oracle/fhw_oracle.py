@@ -335,7 +335,7 @@ def synthesize(V_full, Bslow, ks, H, tau0, W, times, track_tol=0.0):
         u_k(r, t) = (1/2pi) int_{-W}^{W} B_k^slow(w) V(r, w) e^{-i w (t - s_k)} dw
                   = Re (W/pi) sum_m c_{k,m}(r) sinc(W (t - s_k - tau0)/pi - m),
     c_{k,m}(r) the Fourier coefficients of B_k^slow V e^{-i w tau0} on [-W, W).
-    track_tol > 0: active-partition tracking (Sec. 3.1, remark on tracking:
+    track_tol > 0: active-partition tracking (Sec. 3.2, remark on tracking:
     a partition enters a region only where it exceeds a tolerance there).
     Partition k is left out everywhere when its spectrum is negligible,
     max_l (|Re B_k| + |Im B_k|) <= track_tol times the largest such maximum
@@ -378,7 +378,7 @@ def synthesize(V_full, Bslow, ks, H, tau0, W, times, track_tol=0.0):
 
 
 # ---------------------------------------------------------------------------
-# O12. Fast scaled convolution for uniform time grids (Sec. 3.3, FFT
+# O12. Fast scaled convolution for uniform time grids (Sec. 4.1.2, FFT
 #      accelerated evaluation of scaled discrete convolutions:
 #      eqs. conv_sum, approx_conv_sum; Table 1)
 # ---------------------------------------------------------------------------

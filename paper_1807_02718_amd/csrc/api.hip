@@ -245,6 +245,12 @@ int fhw_create(fhw_ctx** out, void* hip_stream, size_t hbm_budget_bytes) {
         return FHW_E_HIP;
     }
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    if (hipMalloc((void**)&c->d_pending, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_pending, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        if (c->d_pending) (void)hipFree(c->d_pending);
+        delete c;
+        return FHW_E_NOMEM;
+    }
     *out = c;
     return FHW_OK;
 }
@@ -256,6 +262,8 @@ int fhw_destroy(fhw_ctx* c) {
     free_workspace(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->scratch) (void)hipFree(c->scratch);
+    if (c->d_pending) (void)hipFree(c->d_pending);
+    if (c->h_pending) (void)hipHostFree(c->h_pending);
     for (auto& r : c->prof.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -659,10 +667,21 @@ static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const
         fhw_grp ga;   // correction: solve r in place, add into x, skip converged
         ga.n = G;
         ga.sv = sv; ga.sacc = xs; ga.sflag = fs;
+        // sweep 0 measures the FP32 solution (never within a tight tolerance:
+        // its correction always runs); from sweep 1 on, the number of systems
+        // still above the tolerance comes back to the host, and the sweeps
+        // stop as soon as it is zero, instead of launching idle ones
         const int maxs = std::max(0, p.refine_max);
         for (int it = 0; it <= maxs; ++it) {
+            int32_t* pend = it >= 1 ? c->d_pending : nullptr;
+            if (pend) FHW_HIP(c, hipMemsetAsync(pend, 0, sizeof(int32_t), c->stream));
             STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, maxN, c->A64, xq, g, r, c->d_rpart,
-                                                           c->d_rcount, nq, p.refine_tol, dq, wq, it, gr));
+                                                           c->d_rcount, nq, p.refine_tol, dq, wq, it, pend, gr));
+            if (pend) {
+                FHW_HIP(c, hipMemcpyAsync(c->h_pending, pend, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+                FHW_HIP(c, hipStreamSynchronize(c->stream));
+                if (*c->h_pending == 0) break;
+            }
             if (it == maxs) break;
             STAGE(c, FHW_STAGE_SOLVE, launch_lu_solve_acc(c->stream, bd, maxN, LU, c->piv, c->linv, r, xq, dq,
                                                           p.precision, ga));
@@ -747,7 +766,8 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
                 gr.spart = c->rpart_stride; gr.scount = c->chunk; gr.snorm = 2 * (int64_t)F;
                 STAGE(c, FHW_STAGE_RESIDUAL, launch_residual_t(c->stream, bd, ch.maxN, c->A64,
                                                                psid + q0 * total + ch.psi_base, g, r, c->d_rpart,
-                                                               c->d_rcount, norms, 0.0, nullptr, nullptr, 0, gr));
+                                                               c->d_rcount, norms, 0.0, nullptr, nullptr, 0, nullptr,
+                                                               gr));
             }
         }
     }

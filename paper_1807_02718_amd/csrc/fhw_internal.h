@@ -107,6 +107,8 @@ struct fhw_ctx {
     int32_t* d_rcount = nullptr;       // residual block counters [FHW_INC_GROUP][chunk] (kept zero)
     int32_t* d_done = nullptr;         // [chunk]
     int32_t* d_sweeps = nullptr;       // [chunk]
+    int32_t* d_pending = nullptr;      // systems still above the refinement tolerance after a sweep
+    int32_t* h_pending = nullptr;      // its pinned host copy
 
     fhw_prof prof;
     hipStream_t cap_stream = nullptr;  // graph capture (created on first use, default priority)
@@ -215,10 +217,11 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
 // part: 2 * batch * ceil(maxN/64) doubles of scratch; count: batch ints, zero
 // before the first call (each call leaves them zero); per incidence of grp
 // at strides spart, scount (x, g, r, norms, done/sweeps: sx, sg, sr, snorm, sflag)
+// pending (optional): incremented once per matrix left above tol by this sweep
 hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64,
                              const void* x, const void* g, void* r, double* part, int32_t* count,
                              double* norms, double tol, int32_t* done, int32_t* sweeps, int sweep,
-                             const fhw_grp& grp = fhw_grp());
+                             int32_t* pending = nullptr, const fhw_grp& grp = fhw_grp());
 hipError_t launch_convert_c128_c64(hipStream_t s, const void* src, void* dst, int64_t n);
 
 // --- field.hip --------------------------------------------------------------

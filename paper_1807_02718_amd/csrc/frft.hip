@@ -1,4 +1,4 @@
-// Fast scaled convolution for time samples on a uniform grid (Sec. 3.3, FFT
+// Fast scaled convolution for time samples on a uniform grid (Sec. 4.1.2, FFT
 // accelerated evaluation of scaled discrete convolutions, eqs. conv_sum and
 // approx_conv_sum; the fractional DFT of Bailey & Swarztrauber, evaluated in
 // Bluestein's chirp-z form).

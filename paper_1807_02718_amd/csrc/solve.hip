@@ -216,7 +216,8 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
 
 // r = g - A x with the FP64 column-major matrix; norms[2b] = ||r||_2,
 // norms[2b+1] = ||g||_2.  Marks done[b] (and sweeps[b] = sweep) once
-// ||r|| <= tol ||g||.  Matrices already done are skipped.
+// ||r|| <= tol ||g||.  Matrices already done are skipped.  pending (optional)
+// counts the matrices of this launch that are still above the tolerance.
 // Grid (matrix, row block of 256/PH rows): thread (row, column phase) with PH
 // column phases summed in a fixed order (PH = 4 for small batches, so that
 // one matrix spreads over many workgroups; PH = 1 for large ones, so that x
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
                                                             double* __restrict__ part, int* __restrict__ count,
                                                             int nblk_max, double* __restrict__ norms, double tol,
                                                             int* __restrict__ done, int* __restrict__ sweeps,
-                                                            int sweep, fhw_grp grp) {
+                                                            int sweep, int* __restrict__ pending, fhw_grp grp) {
     constexpr int RES_ROWS = SOLVE_THREADS / PH;
     {
         const int q = blockIdx.z;   // incidence of the group
@@ -324,6 +325,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
         if (done && R2 <= tol * tol * G2) {
             done[b] = 1;
             if (sweeps) sweeps[b] = sweep;
+        } else if (pending) {
+            atomicAdd(pending, 1);
         }
     }
 }
@@ -369,7 +372,7 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
 
 hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN, const void* A64, const void* x,
                              const void* g, void* r, double* part, int32_t* count, double* norms, double tol,
-                             int32_t* done, int32_t* sweeps, int sweep, const fhw_grp& grp) {
+                             int32_t* done, int32_t* sweeps, int sweep, int32_t* pending, const fhw_grp& grp) {
     if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
@@ -385,11 +388,11 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
     if (wide)
         hipLaunchKernelGGL(k_residual<1>, dim3(b.batch, nblk, grp.n), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off,
                            b.v_off, (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol,
-                           done, sweeps, sweep, grp);
+                           done, sweeps, sweep, pending, grp);
     else
         hipLaunchKernelGGL(k_residual<4>, dim3(b.batch, nblk, grp.n), dim3(SOLVE_THREADS), lds, s, b.N, b.a_off,
                            b.v_off, (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol,
-                           done, sweeps, sweep, grp);
+                           done, sweeps, sweep, pending, grp);
     return hipGetLastError();
 }
 

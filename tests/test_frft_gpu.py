@@ -1,4 +1,4 @@
-"""Fast scaled convolution on a uniform time grid (Sec. 3.3, eq.
+"""Fast scaled convolution on a uniform time grid (Sec. 4.1.2, eq.
 approx_conv_sum) through fhw_synthesize_uniform, against the oracle's
 written-out form of the same approximation (matrix products, no FFT):
   * white field spectra, where the approximation differs from the direct sum

@@ -460,7 +460,7 @@ def _silent_tail_case():
 
 
 def test_tracking_drops_silent_partitions_within_its_bound():
-    """Active-partition tracking (Sec. 3.1 remark): at tolerance 1e-14 the
+    """Active-partition tracking (Sec. 3.2 remark): at tolerance 1e-14 the
     windows over the silent part of the signal leave the sum, and the field
     changes by no more than the bound (W/pi) sum of the dropped b_k(r); the
     field stays the exact delayed signal."""
@@ -543,7 +543,7 @@ def test_star_curve_is_polar_form():
 
 
 # --------------------------------------------------------------------------
-# O12. Fast scaled convolution (Sec. 3.3, eq. approx_conv_sum): the
+# O12. Fast scaled convolution (Sec. 4.1.2, eq. approx_conv_sum): the
 # L-periodic interpolant of the sinc on the integers, against the direct sum
 # --------------------------------------------------------------------------
 def _direct_sinc_sum(a, x):

@@ -443,7 +443,7 @@ def test_densities_largest_N(ctx):
         psi, res, sw = ctx.solve_densities(compute_resid=True)
         err = relmax(psi.cpu().numpy(), ref)
         say("N = 4096", precision, "err", err, "resid", float(res[0]), "sweeps", int(sw[0]))
-        assert err < 1e-10 and res[0] <= 1e-12
+        assert err < 1e-11 and res[0] <= 1e-12
 
 
 def test_single_frequency(ctx):
@@ -483,6 +483,93 @@ def test_incidences_kite_ragged(ctx, precision):
             assert err < 1e-11, (j, q, err)
     if precision == "fp32_refine":
         assert np.all(res <= 1e-14)
+
+
+def _many_incidences(n_plane=13, seed=11):
+    """n_plane plane waves at seeded angles and point sources on a ring of
+    radius 3.2 (outside the kite), interleaved so that every group of 8 mixes
+    both kinds."""
+    rng = np.random.default_rng(seed)
+    ang = rng.uniform(0.0, 2.0 * np.pi, n_plane)
+    planes = [("plane", (np.cos(a), np.sin(a))) for a in ang]
+    points = [("point", (3.2 * np.cos(b), 3.2 * np.sin(b))) for b in (0.4, 1.3, 2.2, 3.1, 4.0, 4.9, 5.8)]
+    out = []
+    while planes or points:
+        if planes:
+            out.append(planes.pop(0))
+        if planes:
+            out.append(planes.pop(0))
+        if points:
+            out.append(points.pop(0))
+    return out
+
+
+def _check_many(psi, res, incs, curve, oms, Ns, off, precision, tag):
+    """Every (frequency, incidence) density against the oracle's LAPACK solve:
+    1e-11 in FP64; in FP32 + refinement within kappa_inf(A) sqrt(N) times the
+    reported residual (and the residual within the tolerance asked)."""
+    P = psi.cpu().numpy() if hasattr(psi, "cpu") else psi
+    worst = 0.0
+    for j, om in enumerate(oms):
+        N = int(Ns[j])
+        gm = O.geometry(curve, N)
+        kappa = float(om)
+        eta = float(O.coupling(np.array([kappa]))[0])
+        A = O.assemble(gm, kappa, eta)
+        cond = np.linalg.cond(A, np.inf)
+        for q, (kind, v) in enumerate(incs):
+            g = O.rhs_plane_wave(gm, kappa, eta, v) if kind == "plane" else O.rhs_point_source(gm, kappa, eta, v)
+            ref, _ = O.solve_density(A, g)
+            err = relmax(P[q, off[j]:off[j + 1]], ref)
+            worst = max(worst, err)
+            if precision == "fp64":
+                assert err < 1e-11, (tag, j, q, err)
+            else:
+                assert res[q, j] <= 1e-13, (tag, j, q, res[q, j])
+                assert err <= max(1e-11, cond * np.sqrt(N) * res[q, j]), (tag, j, q, err)
+    say(tag, precision, "incidences", len(incs), "worst err vs oracle", worst)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_many_incidences(fhw, precision):
+    """More than one group of 8 incidences per factorization: 20 incidences
+    (plane waves and exterior point sources, mixed within every group) on a
+    ragged kite plan, through fhw_solve_incidences, then fhw_solve_cached on
+    the resident factors (in another order), then fhw_solve_range on a plan
+    of systems (two requests, 20 and 11 incidences)."""
+    incs = _many_incidences()
+    assert len(incs) == 20 and sum(k == "point" for k, _ in incs) == 7
+    curve, W, F = Wk.kite(), 36.0, 5
+    rule = dict(ppw=10.0, n_min=64, n_mult=32, n_cap=4096)
+    omega, _ = O.frequency_grid(W, F)
+    c = fhw.Context()
+    try:
+        say("many incidences: solve_incidences", precision)
+        Ns, off = c.plan(curve, W, F, precision=precision, refine_tol=1e-13, refine_max=10, **rule)
+        assert len(set(int(n) for n in Ns)) >= 3
+        psi, res, sw = c.solve_incidences(incs)
+        _check_many(psi, res, incs, curve, omega, Ns, off, precision, "solve_incidences")
+        say("many incidences: solve_cached (reversed order)", precision)
+        rev = incs[::-1]
+        psi2, res2, _ = c.solve_cached(rev)
+        _check_many(psi2, res2, rev, curve, omega, Ns, off, precision, "solve_cached")
+        P, P2 = psi.cpu().numpy(), psi2.cpu().numpy()
+        for q in range(len(incs)):
+            assert relmax(P2[len(incs) - 1 - q], P[q]) < 1e-13, q
+        say("many incidences: solve_range", precision)
+        oms_a, oms_b = [omega[1], omega[3]], [omega[0], omega[2], omega[4]]
+        systems = [(0, om, int(Ns[list(omega).index(om)])) for om in oms_a + oms_b]
+        off_s = c.plan_systems([curve], systems, precision=precision, refine_tol=1e-13, refine_max=10)
+        c.factor()
+        pa, ra, _ = c.solve_range(0, 2, incs)
+        _check_many(pa, ra, incs, curve, oms_a, [s[2] for s in systems[:2]], off_s[:3] - off_s[0], precision,
+                    "solve_range A")
+        inc_b = incs[4:15]
+        pb, rb, _ = c.solve_range(2, 3, inc_b)
+        _check_many(pb, rb, inc_b, curve, oms_b, [s[2] for s in systems[2:]], off_s[2:] - off_s[2], precision,
+                    "solve_range B")
+    finally:
+        c.close()
 
 
 def test_incidences_single_equals_densities(ctx):
@@ -675,10 +762,12 @@ def test_workspace_reused_across_plans(fhw):
 
 
 def _requests():
-    """Three requests: (curve index, frequencies, N, incidences)."""
+    """Four requests: (curve index, frequencies, N, incidences)."""
     return [(0, [31.0, 32.0, 33.0, 34.0], 192, [("plane", (1.0, 0.0)), ("plane", (0.0, 1.0)), ("plane", (0.6, -0.8))]),
             (1, [10.0, 11.5, 13.0], 256, [("plane", (-1.0, 0.0)), ("point", (3.5, 0.5))]),
-            (2, [50.0, 51.0], 320, [("plane", (0.8, 0.6))] * 1 + [("plane", (np.cos(a), np.sin(a))) for a in (0.3, 1.1, 2.0, 2.9)])]
+            (2, [50.0, 51.0], 320, [("plane", (0.8, 0.6))] * 1 + [("plane", (np.cos(a), np.sin(a))) for a in (0.3, 1.1, 2.0, 2.9)]),
+            # more than one group of 8 right-hand sides
+            (1, [20.0, 21.0], 224, _many_incidences(n_plane=8, seed=5)[:12])]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
@@ -719,7 +808,12 @@ def test_requests_alone_and_in_the_mix(fhw, precision):
             for q, (kind, v) in enumerate(inc):
                 g = O.rhs_plane_wave(gm, kappa, eta, v) if kind == "plane" else O.rhs_point_source(gm, kappa, eta, v)
                 ref, _ = O.solve_density(A, g)
-                assert relmax(psi[q, :N], ref) < 1e-10, (k, q)
+                err = relmax(psi[q, :N], ref)
+                if precision == "fp64":
+                    assert err < 1e-11, (k, q, err)
+                else:
+                    # ||d psi||_inf / ||psi||_inf <= kappa_inf(A) sqrt(N) ||r||_2 / ||g||_2
+                    assert err <= max(1e-11, np.linalg.cond(A, np.inf) * np.sqrt(N) * res[q, 0]), (k, q, err)
             s0 += len(oms)
         with pytest.raises(fhw.FhwError) as e:
             c.eval_field(torch.zeros(int(off[-1]), dtype=torch.complex128, device="cuda"), Wk.ring(4, 3.0))
