@@ -207,6 +207,27 @@ int fhw_factor(fhw_ctx* ctx);
 int fhw_solve_range(fhw_ctx* ctx, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc, void* psi,
                     double* resid, int32_t* sweeps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solves and results as fhw_solve_range, with its per-call status words (the
+ * refinement's convergence flags, sweep counts and residual norms, and the
+ * reported residuals) in a fixed device array of FHW_NOALLOC_SCRATCH_BYTES
+ * inside the library instead of memory the library allocates.  The call
+ * itself allocates nothing: no hipMalloc, hipFree or other allocating
+ * routine; the factors, the plan's workspace and psi are as for
+ * fhw_solve_range.  Limit: n_inc * count <= FHW_NOALLOC_MAX_PAIRS.  Every
+ * call on one GPU uses that GPU's single array (each GPU the library runs on
+ * holds it until the process ends), so such calls that overlap on one GPU,
+ * from any context or thread, race; calls one after another do not (the
+ * array is cleared at the start of each call).  The stage timers do not
+ * record this call.  Synchronizes.  Errors: FHW_E_INVALID when n_inc * count
+ * exceeds the limit; FHW_E_HIP if the array's device address could not be
+ * looked up when the context was created; otherwise as fhw_solve_range. */
+#define FHW_NOALLOC_SCRATCH_BYTES (1 << 20)
+#define FHW_NOALLOC_MAX_PAIRS 16384
+int fhw_solve_range_noalloc(fhw_ctx* ctx, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc,
+                            void* psi, double* resid, int32_t* sweeps);
+
 /* Step F5 (eqs. freq_domain_repr, Ukslow_repr): V(r, omega_l) on the full DFT
  * grid, V[r][l], complex128 [N_r][2F]; V(r,-omega) = conj V(r,omega) and
  * V(r, 0) = zero_value (1 for plane-wave data: the low-frequency limit).

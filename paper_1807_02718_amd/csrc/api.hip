@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <new>
+#include <mutex>
 #include <set>
 
 #include "fhw_internal.h"
@@ -134,6 +135,47 @@ int lds_limit(fhw_ctx* c) {
 
 }  // namespace
 
+// The status words of fhw_solve_range_noalloc live in this fixed device array,
+// one per GPU the library runs on, instead of memory the library allocates.
+// On the host, the array's name is only a stand-in for the device symbol:
+// host code never passes it to a kernel or a copy.  Its device address on each
+// device is looked up once, at the first fhw_create on that device (with the
+// device current), with hipGetSymbolAddress; only that address is used.
+static __device__ __align__(256) unsigned char noalloc_scratch[FHW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_addr[kNoallocDevices] = {};
+
+// device address of noalloc_scratch on `device` (the current device)
+void* noalloc_address(int device, std::string* err) {
+    if (device < 0 || device >= kNoallocDevices) {
+        *err = "allocation-free solves: device index out of range";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p) {
+            *err = std::string("allocation-free solves: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_noalloc_addr[device] = p;
+    }
+    return g_noalloc_addr[device];
+}
+
+// turns the stage timers off for one call (their events would be created on demand)
+struct prof_pause {
+    fhw_prof& p;
+    bool was;
+    explicit prof_pause(fhw_prof& q) : p(q), was(q.on) { p.on = false; }
+    ~prof_pause() { p.on = was; }
+};
+}  // namespace
+
 hipEvent_t fhw_prof::take() {
     if (!pool.empty()) {
         hipEvent_t e = pool.back();
@@ -251,6 +293,9 @@ int fhw_create(fhw_ctx** out, void* hip_stream, size_t hbm_budget_bytes) {
         delete c;
         return FHW_E_NOMEM;
     }
+    // the other calls work without it: a failed lookup fails only
+    // fhw_solve_range_noalloc, with this message
+    c->noalloc = noalloc_address(c->device, &c->noalloc_err);
     *out = c;
     return FHW_OK;
 }
@@ -912,6 +957,65 @@ int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* 
     if (fp32)
         for (size_t j = 0; j < nf; ++j)
             if (!done[j]) return fhw_fail(c, FHW_E_NOCONV, "solve_range: refinement did not reach refine_tol");
+    return FHW_OK;
+}
+
+// fhw_solve_range with its status words in the fixed device array: the same
+// solves (solve_groups), no allocation.  Layout of the array for nf =
+// n_inc * count pairs: done | sweeps | norms (2 nf) | resid out | sweeps out |
+// counter, each at a 256-byte boundary.
+int fhw_solve_range_noalloc(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc,
+                            void* psi, double* resid, int32_t* sweeps) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve_range_noalloc: no plan");
+    if (!c->factors_resident)
+        return fhw_fail(c, FHW_E_STATE, "solve_range_noalloc: no resident factors (fhw_factor first)");
+    const int S = (int)c->Ns.size();
+    if (s0 < 0 || count < 1 || s0 > S - count)
+        return fhw_fail(c, FHW_E_INVALID, "solve_range_noalloc: systems out of range");
+    int rc = check_incidences(c, inc, n_inc, psi);
+    if (rc) return rc;
+    if ((int64_t)n_inc * count > FHW_NOALLOC_MAX_PAIRS)
+        return fhw_fail(c, FHW_E_INVALID, "solve_range_noalloc: n_inc * count = " +
+                                              std::to_string((int64_t)n_inc * count) + " exceeds " +
+                                              std::to_string(FHW_NOALLOC_MAX_PAIRS));
+    if (!c->noalloc) return fhw_fail(c, FHW_E_HIP, c->noalloc_err);
+    const size_t nf = (size_t)n_inc * count;
+    const size_t o_done = 0, o_sw = align_up(o_done + nf * 4, 256), o_nrm = align_up(o_sw + nf * 4, 256);
+    const size_t o_res = align_up(o_nrm + nf * 16, 256), o_swo = align_up(o_res + nf * 8, 256);
+    const size_t o_cnt = align_up(o_swo + nf * 4, 256);
+    static_assert(FHW_NOALLOC_MAX_PAIRS * 36 + 6 * 256 <= FHW_NOALLOC_SCRATCH_BYTES, "status array too small");
+    if (o_cnt + 4 > FHW_NOALLOC_SCRATCH_BYTES) return fhw_fail(c, FHW_E_INVALID, "solve_range_noalloc: too many pairs");
+    char* sb = (char*)c->noalloc;
+    int32_t* d_done = (int32_t*)(sb + o_done);
+    int32_t* d_sw = (int32_t*)(sb + o_sw);
+    double* d_norms = (double*)(sb + o_nrm);
+    double* d_res = (double*)(sb + o_res);
+    int32_t* d_swo = (int32_t*)(sb + o_swo);
+    int32_t* d_cnt = (int32_t*)(sb + o_cnt);
+    prof_pause pause(c->prof);
+    plan_ext& px = g_plans[c];
+    const chunk_t& ch = px.chunks[0];
+    const fhw_problem& p = c->prob;
+    const bool fp32 = p.precision == FHW_FP32_REFINE;
+    const int b0 = s0 - ch.j0;
+    fhw_batch_dev bd{ch.d_N + b0, ch.d_aoff + b0, ch.d_pivoff + b0, ch.d_linvoff + b0, ch.d_voff + b0, count};
+    int32_t maxN = 0;
+    for (int s = s0; s < s0 + count; ++s) maxN = std::max(maxN, c->Ns[s]);
+    const int64_t voff0 = c->psi_off[s0] - ch.psi_base;
+    const int64_t elems = c->psi_off[s0 + count] - c->psi_off[s0];
+    FHW_HIP(c, launch_status_clear(c->stream, d_done, d_sw, d_cnt, (int64_t)nf));
+    zd* x = (zd*)psi - voff0;
+    rc = solve_groups(c, bd, maxN, ch.d_items + b0, voff0, elems, inc, n_inc, x, elems, d_norms, d_done, d_sw, count);
+    if (rc) return rc;
+    FHW_HIP(c, launch_status_finish(c->stream, d_done, d_sw, d_norms, (int64_t)nf, fp32 ? 1 : 0, p.refine_max, d_res,
+                                    d_swo, d_cnt));
+    if (resid) FHW_HIP(c, hipMemcpyAsync(resid, d_res, nf * 8, hipMemcpyDeviceToHost, c->stream));
+    if (sweeps) FHW_HIP(c, hipMemcpyAsync(sweeps, d_swo, nf * 4, hipMemcpyDeviceToHost, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(c->h_pending, d_cnt, 4, hipMemcpyDeviceToHost, c->stream));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    if (fp32 && *c->h_pending != 0)
+        return fhw_fail(c, FHW_E_NOCONV, "solve_range_noalloc: refinement did not reach refine_tol");
     return FHW_OK;
 }
 

@@ -119,6 +119,11 @@ struct fhw_ctx {
     // generic scratch (synthesis)
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+
+    // device address of the library's fixed status array on this context's
+    // device (fhw_solve_range_noalloc); nullptr if the lookup failed
+    void* noalloc = nullptr;
+    std::string noalloc_err;
 };
 
 int fhw_fail(fhw_ctx* ctx, int code, const std::string& msg);
@@ -223,6 +228,14 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
                              double* norms, double tol, int32_t* done, int32_t* sweeps, int sweep,
                              int32_t* pending = nullptr, const fhw_grp& grp = fhw_grp());
 hipError_t launch_convert_c128_c64(hipStream_t s, const void* src, void* dst, int64_t n);
+// status words of nf (incidence, system) pairs in caller-provided device
+// memory: cleared (and *notdone = 0) before the solves; after them resid[j] =
+// ||r|| / ||g|| (-1 when refine == 0), sweeps_out[j] (refine_max for a pair
+// that never met the tolerance, 0 when refine == 0), *notdone += such pairs
+hipError_t launch_status_clear(hipStream_t s, int32_t* done, int32_t* sweeps, int32_t* notdone, int64_t nf);
+hipError_t launch_status_finish(hipStream_t s, const int32_t* done, const int32_t* sweeps, const double* norms,
+                                int64_t nf, int refine, int refine_max, double* resid, int32_t* sweeps_out,
+                                int32_t* notdone);
 
 // --- field.hip --------------------------------------------------------------
 struct fhw_field_item {

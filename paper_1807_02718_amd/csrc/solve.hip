@@ -396,6 +396,53 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
     return hipGetLastError();
 }
 
+// Status words of nf (incidence, system) pairs kept in caller-provided
+// device memory: cleared before the solves, summarised after them.
+__global__ void k_status_clear(int32_t* __restrict__ done, int32_t* __restrict__ sweeps,
+                               int32_t* __restrict__ notdone, int64_t nf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nf) {
+        done[i] = 0;
+        sweeps[i] = 0;
+    }
+    if (i == 0) *notdone = 0;
+}
+
+// resid[j] = ||r|| / ||g|| after the refinement (-1 without it); sweeps_out[j]
+// = the sweep at which pair j met the tolerance, refine_max if it never did
+// (0 without refinement); notdone counts the pairs that never did.
+__global__ void k_status_finish(const int32_t* __restrict__ done, const int32_t* __restrict__ sweeps,
+                                const double* __restrict__ norms, int64_t nf, int refine, int refine_max,
+                                double* __restrict__ resid, int32_t* __restrict__ sweeps_out,
+                                int32_t* __restrict__ notdone) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nf) return;
+    if (!refine) {
+        resid[j] = -1.0;
+        sweeps_out[j] = 0;
+        return;
+    }
+    const double rn = norms[2 * j], gn = norms[2 * j + 1];
+    resid[j] = gn > 0.0 ? rn / gn : 0.0;
+    sweeps_out[j] = done[j] ? sweeps[j] : refine_max;
+    if (!done[j]) atomicAdd(notdone, 1);
+}
+
+hipError_t launch_status_clear(hipStream_t s, int32_t* done, int32_t* sweeps, int32_t* notdone, int64_t nf) {
+    const int64_t blocks = std::max<int64_t>(1, (nf + 255) / 256);
+    hipLaunchKernelGGL(k_status_clear, dim3((unsigned)blocks), dim3(256), 0, s, done, sweeps, notdone, nf);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_finish(hipStream_t s, const int32_t* done, const int32_t* sweeps, const double* norms,
+                                int64_t nf, int refine, int refine_max, double* resid, int32_t* sweeps_out,
+                                int32_t* notdone) {
+    const int64_t blocks = std::max<int64_t>(1, (nf + 255) / 256);
+    hipLaunchKernelGGL(k_status_finish, dim3((unsigned)blocks), dim3(256), 0, s, done, sweeps, norms, nf, refine,
+                       refine_max, resid, sweeps_out, notdone);
+    return hipGetLastError();
+}
+
 hipError_t launch_convert_c128_c64(hipStream_t s, const void* src, void* dst, int64_t n) {
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_c128_to_c64, dim3(blocks), dim3(256), 0, s, (const zd*)src, (zf*)dst, n);

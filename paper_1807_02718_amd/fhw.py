@@ -81,6 +81,7 @@ def _load():
         "fhw_plan_systems": [vp, C.POINTER(fhw_curve), i32, C.POINTER(fhw_system), i32, C.POINTER(fhw_problem), p_i64],
         "fhw_factor": [vp],
         "fhw_solve_range": [vp, i32, i32, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
+        "fhw_solve_range_noalloc": [vp, i32, i32, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
         "fhw_solve_densities": [vp, vp, _dp, p_i32, i32],
         "fhw_solve_incidences": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32, i32],
         "fhw_solve_cached": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
@@ -113,7 +114,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
-            "fhw_plan_systems", "fhw_factor", "fhw_solve_range",
+            "fhw_plan_systems", "fhw_factor", "fhw_solve_range", "fhw_solve_range_noalloc",
             "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
@@ -237,9 +238,11 @@ class Context:
         """fhw_factor: assemble and factor every planned system; factors stay resident."""
         self._check(_lib.fhw_factor(self._h))
 
-    def solve_range(self, s0, count, incidences, psi=None):
-        """fhw_solve_range on systems s0 .. s0+count-1.  Returns (psi [n_inc, E]
-        complex128, resid [n_inc, count], sweeps [n_inc, count])."""
+    def solve_range(self, s0, count, incidences, psi=None, noalloc=False):
+        """fhw_solve_range on systems s0 .. s0+count-1 (noalloc: the
+        allocation-free variant fhw_solve_range_noalloc, same results).
+        Returns (psi [n_inc, E] complex128, resid [n_inc, count], sweeps
+        [n_inc, count])."""
         kinds = {"plane": FHW_INC_PLANE, "point": FHW_INC_POINT}
         n = len(incidences)
         arr = (fhw_incidence * max(n, 1))()
@@ -252,8 +255,9 @@ class Context:
             psi = torch.empty((max(n, 1), E), dtype=torch.complex128, device=self.device)
         resid = np.zeros((max(n, 1), count))
         sweeps = np.zeros((max(n, 1), count), dtype=np.int32)
-        self._check(_lib.fhw_solve_range(self._h, int(s0), int(count), arr, n, _ptr(psi), resid.ctypes.data_as(_dp),
-                                         sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
+        call = _lib.fhw_solve_range_noalloc if noalloc else _lib.fhw_solve_range
+        self._check(call(self._h, int(s0), int(count), arr, n, _ptr(psi), resid.ctypes.data_as(_dp),
+                         sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
         return psi, resid, sweeps
 
     # -- hot path ---------------------------------------------------------------
