@@ -34,6 +34,9 @@ __all__ = [
     "window_indices", "window_spectra", "fourier_coefficients",
     "active_windows", "synthesize", "run", "curve_eval",
     "scaled_convolution_fast", "synthesize_uniform",
+    "graded_mesh", "clenshaw_curtis_nodes", "lowfreq_frequencies", "chebyshev_moments",
+    "fcc_integral", "gram_basis", "fc_gram_tables", "fc_continuation", "fc_coefficients",
+    "fc_integral", "synthesize_lowfreq",
 ]
 
 
@@ -443,12 +446,224 @@ def synthesize_uniform(V_full, Bslow, ks, H, tau0, W, t_first, t_step, n_t, L: i
 
 
 # ---------------------------------------------------------------------------
+# O13. Low-frequency singular quadrature for 2D (Sec. 4.2, eqs.
+#      fourier_sing_decomp, gradedmesh, gradedmeshIntRule) with Fourier
+#      continuation of the smooth part (Sec. 4.1.1, Remark Fourier-FC;
+#      steps T1b, T2b-T2d)
+# ---------------------------------------------------------------------------
+def graded_mesh(omega_c: float, M: int, q: float):
+    """mu_j = omega_c (j / M)^q, j = 0..M (eq. gradedmesh; mu_0 = 0 is kept, so
+    that the composite rule covers all of (0, omega_c])."""
+    return omega_c * (np.arange(M + 1, dtype=np.float64) / M) ** q
+
+
+def clenshaw_curtis_nodes(a: float, b: float, n: int):
+    """The n + 1 Clenshaw-Curtis (Chebyshev extreme) points of [a, b],
+    (a + b)/2 + (b - a)/2 cos(pi i / n), i = 0..n (descending)."""
+    return 0.5 * (a + b) + 0.5 * (b - a) * np.cos(np.pi * np.arange(n + 1) / n)
+
+
+def lowfreq_frequencies(W: float, F: int, jc: int, M: int, n: int, q: float):
+    """The frequency sets of the 2D method (Sec. 5, F = F^smooth U F^sing):
+    omega_c = jc W / F; F^smooth = the solve grid on [omega_c, W], omega_c +
+    i W / F, i = 0..F - jc; F^sing = the Clenshaw-Curtis points of the M
+    subintervals [mu_{j-1}, mu_j] of the graded mesh, n + 1 per subinterval.
+    Returns (omega_c, smooth grid, mu, nodes[M][n + 1])."""
+    h = W / F
+    omega_c = jc * h
+    smooth = omega_c + h * np.arange(F - jc + 1)
+    mu = graded_mesh(omega_c, M, q)
+    nodes = [clenshaw_curtis_nodes(mu[j], mu[j + 1], n) for j in range(M)]
+    return omega_c, smooth, mu, nodes
+
+
+def chebyshev_moments(n: int, kappa: float):
+    """m_k = int_{-1}^{1} T_k(x) e^{-i kappa x} dx, k = 0..n (the modified
+    moments of the Filon-Clenshaw-Curtis rule), by Gauss-Legendre quadrature
+    with enough nodes (64 + 3|kappa|/4) that the entire integrand is
+    integrated to rounding."""
+    ng = 64 + int(np.ceil(0.75 * abs(kappa)))
+    x, w = np.polynomial.legendre.leggauss(ng)
+    T = np.cos(np.arange(n + 1)[:, None] * np.arccos(np.clip(x, -1.0, 1.0))[None, :])
+    return T @ (w * np.exp(-1j * kappa * x))
+
+
+def fcc_integral(values, a: float, b: float, n: int, t):
+    """Filon-Clenshaw-Curtis rule (Sec. 4.2): int_a^b Q_n F(w) e^{-i w t} dw,
+    Q_n F the degree-n polynomial interpolating F at the Clenshaw-Curtis points
+    of [a, b] (values in the order of clenshaw_curtis_nodes).  The interpolant
+    is written in Chebyshev form, p = sum_k alpha_k T_k(x), w = (a+b)/2 +
+    (b-a)/2 x, by solving the interpolation conditions; each moment is exact
+    (chebyshev_moments).  t: array of times."""
+    x = np.cos(np.pi * np.arange(n + 1) / n)
+    T = np.cos(np.outer(np.arccos(x), np.arange(n + 1)))
+    alpha = np.linalg.solve(T, np.asarray(values, dtype=np.complex128))
+    rho, delta = 0.5 * (b - a), 0.5 * (a + b)
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    return np.array([rho * np.exp(-1j * delta * tt) * (alpha @ chebyshev_moments(n, rho * tt)) for tt in t])
+
+
+def gram_basis(d: int):
+    """Gram polynomials on the d points 0, 1, .., d-1: the columns of Q (d x d,
+    values at the points) are orthonormal in the discrete inner product, the
+    k-th of degree k; G_k(x) = sum_l R^{-1}[l, k] x^l.  High precision
+    (mpmath, 60 digits); returns (Q as float64, R^{-1} as mpmath matrix)."""
+    import mpmath as mp
+    with mp.workdps(60):
+        Vm = mp.matrix(d, d)
+        for j in range(d):
+            for l in range(d):
+                Vm[j, l] = mp.mpf(j) ** l
+        Q, R = mp.qr(Vm)
+        # sign convention: positive leading coefficient of every G_k
+        for k in range(d):
+            if R[k, k] < 0:
+                for j in range(d):
+                    Q[j, k] = -Q[j, k]
+                for l in range(d):
+                    R[k, l] = -R[k, l]
+        Rinv = R ** -1
+        Qf = np.array([[float(Q[i, j]) for j in range(d)] for i in range(d)])
+    return Qf, Rinv
+
+
+_FC_CACHE = {}
+
+
+def fc_gram_tables(d: int = 10, C: int = 25, oversample: int = 10):
+    """FC(Gram) continuation tables (Remark Fourier-FC; the FC(Gram) Fourier
+    continuation cited there).  For each Gram polynomial G_k, its "blend to
+    zero" extension: the trigonometric polynomial phi_k of period 2 (d + C)
+    and degree d + C (in the grid unit), least-squares closest to G_k on [0,
+    d - 1] and to 0 on [d + C, 2d + C - 1], both sampled `oversample` times
+    per unit; A[c, k] = phi_k(d + c), c = 0..C-1.  Full-rank least squares
+    solved in 45-digit arithmetic (mpmath SVD).  Returns (A [C, d], Q [d, d])
+    as float64, cached per (d, C, oversample)."""
+    key = (d, C, oversample)
+    if key in _FC_CACHE:
+        return _FC_CACHE[key]
+    import mpmath as mp
+    Qf, Rinv = gram_basis(d)
+    with mp.workdps(100):
+        P = 2 * (d + C)
+        B = d + C
+        xm = [mp.mpf(i) / oversample for i in range((d - 1) * oversample + 1)]
+        xz = [mp.mpf(d + C) + mp.mpf(i) / oversample for i in range((d - 1) * oversample + 1)]
+
+        def basis(x):
+            row = [mp.mpf(1)]
+            for m in range(1, B + 1):
+                row += [mp.cos(2 * mp.pi * m * x / P), mp.sin(2 * mp.pi * m * x / P)]
+            return row
+
+        # normal equations of the full-rank least-squares problem, in 100
+        # digits (its condition number squared is about 1e48 for d = 10)
+        Mm = mp.matrix([basis(x) for x in xm])
+        Mz = mp.matrix([basis(x) for x in xz])
+        G = Mm.T * Mm + Mz.T * Mz
+        Ginv = G ** -1
+        Ec = mp.matrix([basis(mp.mpf(d + c)) for c in range(C)])
+        A = np.zeros((C, d))
+        for k in range(d):
+            y = mp.matrix([sum(Rinv[l, k] * x ** l for l in range(d)) for x in xm])
+            coef = Ginv * (Mm.T * y)
+            vals = Ec * coef
+            A[:, k] = [float(vals[c]) for c in range(C)]
+    _FC_CACHE[key] = (A, Qf)
+    return A, Qf
+
+
+def fc_continuation(f, A, Q):
+    """The FC(Gram) periodic extension of n samples f (n >= d) of a smooth,
+    non-periodic function on an equispaced grid: the n samples followed by C
+    continuation values, the blend to zero of the last d samples' Gram
+    projection plus the blend from zero (mirrored) of the first d samples'.
+    Returns the n + C values of one period."""
+    f = np.asarray(f, dtype=np.complex128)
+    n = len(f)
+    C, d = A.shape
+    g = np.zeros(n + C, dtype=np.complex128)
+    g[:n] = f
+    g[n:] += A @ (Q.T @ f[n - d:])
+    g[n:] += (A @ (Q.T @ f[:d][::-1]))[::-1]
+    return g
+
+
+def fc_coefficients(f, A, Q):
+    """Coefficients c_m, m = -L/2..L/2-1 (L = n + C, index m + L/2), of the
+    trigonometric polynomial of period L h interpolating the FC(Gram)
+    extension (eq. fourier_approx with P = L h != 2A): direct DFT sum."""
+    g = fc_continuation(f, A, Q)
+    L = len(g)
+    m = np.arange(-(L // 2), L - L // 2)
+    jj = np.arange(L)
+    return (np.exp(-2j * np.pi * np.outer(m, jj) / L) @ g) / L
+
+
+def fc_integral(c, omega_a: float, h: float, n: int, t):
+    """int_{omega_a}^{omega_a + (n-1) h} sum_m c_m e^{2 pi i m (w - omega_a)/P}
+    e^{-i w t} dw, P = L h: term-wise exact integration (eq. approx with
+    A = (n - 1) h / 2, P != 2A), written with the normalized sinc."""
+    L = len(c)
+    P = L * h
+    D = (n - 1) * h
+    m = np.arange(-(L // 2), L - L // 2)
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    nu = 2 * np.pi * m[None, :] / P - t[:, None]
+    ker = np.exp(0.5j * nu * D) * D * np.sinc(nu * D / (2 * np.pi))
+    return np.exp(-1j * omega_a * t) * (ker @ c)
+
+
+def synthesize_lowfreq(V_full, V_sing, signal, H, tau0, W, F, jc, M, n, q, times, fc_d=10, fc_C=25):
+    """Time samples by the 2D low-frequency decomposition (eq.
+    fourier_sing_decomp; steps T1b, T2b-T2d, T5): for every window k whose
+    support meets the signal's range and every point r,
+        u_k(r, t) = (1/pi) Re [ I_0(t') + I_+(t') ],  t' = t - s_k - tau0,
+    with F_k(w) = B_k^slow(w) V(r, w) e^{-i w tau0}; I_+ = int_{omega_c}^{W}
+    F_k e^{-i w t'} dw from the FC(Gram) continuation of F_k on the grid of
+    [omega_c, W] (fc_coefficients, fc_integral), I_0 = int_0^{omega_c} by the
+    composite Filon-Clenshaw-Curtis rule on the graded mesh (eq.
+    gradedmeshIntRule, fcc_integral); the negative frequencies enter as the
+    complex conjugate (real signals), hence (1/2 pi) 2 Re.  Every window with
+    signal content is summed at every time (in 2D the low-frequency part of
+    u_k decays only algebraically in time).
+    V_full: [Nr][2F] on the DFT grid (as field_full_grid); V_sing: [Nr][M][n+1]
+    at the nodes of lowfreq_frequencies."""
+    omega_c, smooth, mu, nodes = lowfreq_frequencies(W, F, jc, M, n, q)
+    A, Q = fc_gram_tables(fc_d, fc_C)
+    Nr = V_full.shape[0]
+    # V at the smooth grid: omega = (jc + i) W/F -> index F + jc + i; +W only as conj at index 0
+    idx = F + jc + np.arange(F - jc + 1)
+    Vs = np.empty((Nr, len(smooth)), dtype=np.complex128)
+    inside = idx < 2 * F
+    Vs[:, inside] = V_full[:, idx[inside]]
+    Vs[:, ~inside] = np.conj(V_full[:, 0])[:, None]
+    times = np.asarray(times, dtype=np.float64)
+    u = np.zeros((Nr, len(times)))
+    ks = window_indices(signal.t[0], signal.t[-1], H)
+    for k in ks:
+        sk = window_center(k, H)
+        tp = times - sk - tau0
+        Bs = window_spectra(signal, H, [k], smooth)[0] * np.exp(-1j * smooth * tau0)
+        Bn = [window_spectra(signal, H, [k], nodes[j])[0] * np.exp(-1j * nodes[j] * tau0) for j in range(M)]
+        for r in range(Nr):
+            c = fc_coefficients(Bs * Vs[r], A, Q)
+            I = fc_integral(c, omega_c, W / F, len(smooth), tp)
+            for j in range(M):
+                I = I + fcc_integral(Bn[j] * V_sing[r, j], mu[j], mu[j + 1], n, tp)
+            u[r] += I.real / np.pi
+    return u
+
+
+# ---------------------------------------------------------------------------
 # Whole pipeline (F1-F5, T0-T6)
 # ---------------------------------------------------------------------------
 def run(curve, W, F, N_rule, direction, signal, H, tau0, obs, times, c=1.0,
-        incidence="plane", r0=None, return_all=False):
+        incidence="plane", r0=None, return_all=False, lowfreq=None):
     """Scattered field u(r, t) on obs x times.  N_rule is an int (fixed N) or a
-    dict(ppw, n_min, n_mult, n_cap)."""
+    dict(ppw, n_min, n_mult, n_cap).  lowfreq = dict(jc, M, n, q) selects the
+    2D low-frequency decomposition (synthesize_lowfreq), with the extra
+    frequency solves at the graded Clenshaw-Curtis points."""
     omega, kappa = frequency_grid(W, F, c)
     if isinstance(N_rule, dict):
         Ns = discretization_sizes(kappa, curve_length(curve), **N_rule)
@@ -472,6 +687,34 @@ def run(curve, W, F, N_rule, direction, signal, H, tau0, obs, times, c=1.0,
         psis.append(psi); res.append(rr)
         Vpos[:, j] = field(gm, psi, kappa[j], obs)
     V_full = field_full_grid(Vpos, 1.0 if incidence == "plane" else 0.0)
+    if lowfreq is not None:
+        lf = dict(lowfreq)
+        omega_c, _, _, nodes = lowfreq_frequencies(W, F, lf["jc"], lf["M"], lf["n"], lf["q"])
+        zero = 1.0 if incidence == "plane" else 0.0
+        V_sing = np.zeros((len(obs), lf["M"], lf["n"] + 1), dtype=np.complex128)
+        for jm in range(lf["M"]):
+            for i, om in enumerate(nodes[jm]):
+                if om == 0.0:
+                    V_sing[:, jm, i] = zero
+                    continue
+                kap = om / c
+                if isinstance(N_rule, dict):
+                    N = int(discretization_sizes([kap], curve_length(curve), **N_rule)[0])
+                else:
+                    N = int(N_rule)
+                if N not in geoms:
+                    geoms[N] = geometry(curve, N)
+                gm = geoms[N]
+                et = float(coupling(kap))
+                A = assemble(gm, kap, et)
+                g = rhs_plane_wave(gm, kap, et, direction) if incidence == "plane" else \
+                    rhs_point_source(gm, kap, et, r0)
+                psi, _ = solve_density(A, g)
+                V_sing[:, jm, i] = field(gm, psi, kap, obs)
+        u = synthesize_lowfreq(V_full, V_sing, signal, H, tau0, W, F, lf["jc"], lf["M"], lf["n"], lf["q"], times)
+        if return_all:
+            return dict(u=u, psi=psis, res=res, Vpos=Vpos, V=V_full, V_sing=V_sing, Ns=Ns, kappa=kappa, eta=eta)
+        return u
     dw = W / F
     omega_l = -W + dw * np.arange(2 * F)
     t = signal.t
