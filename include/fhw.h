@@ -91,6 +91,17 @@ typedef struct {
                             fhw_eval_field / fhw_synthesize); > 0: the band
                             (j_first + j) W / F, j = 1..F, for frequency-domain
                             work only (solves; field and synthesis refuse it) */
+    /* 2D low-frequency decomposition (Sec. 4.2; fhw_eval_field_lowfreq,
+     * fhw_synthesize_lowfreq).  lf_M > 0 adds the graded frequencies: the
+     * mesh mu_j = omega_c (j / lf_M)^lf_q, j = 0..lf_M (eq. gradedmesh),
+     * omega_c = lf_jc W / F, and on each [mu_j, mu_{j+1}] the lf_N + 1
+     * Clenshaw-Curtis points; the distinct ones in (0, omega_c), lf_M lf_N - 1
+     * of them in ascending order, become systems F .. F + lf_M lf_N - 2 of the
+     * plan (omega_c itself is system lf_jc - 1).  One curve, j_first = 0;
+     * 1 <= lf_jc, F - lf_jc + 1 >= 20 (the continuation's matching points),
+     * 1 <= lf_N <= 32, lf_q > 0.  lf_M = 0: none (the smooth-F path only). */
+    int32_t lf_M, lf_N, lf_jc;
+    double lf_q;
 } fhw_problem;
 
 /* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL =
@@ -240,6 +251,15 @@ int fhw_eval_field(fhw_ctx* ctx, const void* psi, const double* obs, int32_t N_r
 int fhw_eval_field_curve(fhw_ctx* ctx, int32_t curve, const void* psi, const double* obs,
                          int32_t N_r, double zero_value, void* V);
 
+/* The field at the graded low-frequency nodes of a plan made with lf_M > 0
+ * (Sec. 4.2): V_sing complex128 [N_r][lf_M lf_N + 1] (device), column g the
+ * g-th node in ascending order: g = 0 is omega = 0 (value zero_value: 1 for
+ * plane-wave data, the low-frequency limit), g = lf_M lf_N is omega_c.
+ * obs [host] as in fhw_eval_field.  Errors: FHW_E_STATE for a plan without
+ * the graded frequencies; FHW_E_INVALID for bad arguments. */
+int fhw_eval_field_lowfreq(fhw_ctx* ctx, const void* psi, const double* obs, int32_t N_r, double zero_value,
+                           void* V_sing);
+
 /* Incident signal f sampled at t0 + n dt, n = 0..n-1 (device doubles); the
  * incident field is f(t - p.r/c) and the boundary signal is a = -f.  The
  * signal must vanish, with its derivatives, at both ends of the range. */
@@ -271,6 +291,28 @@ typedef struct {
 int fhw_synthesize(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win,
                    const void* V, int32_t N_r, const double* times, int32_t N_t,
                    double* u);
+
+/* 2D time samples with the low-frequency decomposition (Sec. 4.2, eq.
+ * fourier_sing_decomp; steps T1b, T2b-T2d, T5), for a plan with lf_M > 0.
+ * For every window k whose support meets the signal's range (all of them at
+ * every time: in 2D the low-frequency part of u_k decays only algebraically)
+ * and t' = t - s_k - tau0, F_k(w) = B_k^slow(w) V(r, w) e^{-i w tau0}:
+ *   u(r, t) = sum_k (1/pi) Re [ I_+ + I_0 ],
+ *   I_+ = int_{omega_c}^{W} F_k e^{-i w t'} dw: F_k on the solve grid of
+ *         [omega_c, W] extended by its FC(Gram) continuation (10 matching
+ *         points, 25 continuation points: Remark Fourier-FC) and integrated
+ *         term by term (eq. approx with period P != 2A);
+ *   I_0 = int_0^{omega_c} F_k e^{-i w t'} dw by the composite
+ *         Filon-Clenshaw-Curtis rule on the graded mesh (eq.
+ *         gradedmeshIntRule), exact moments.
+ * V: complex128 [N_r][2F] as written by fhw_eval_field; V_sing: [N_r][lf_M
+ * lf_N + 1] as written by fhw_eval_field_lowfreq; times [host]; u: device
+ * doubles [N_r][N_t], overwritten.  win->track_tol must be 0.
+ * Errors: FHW_E_STATE without the graded frequencies; FHW_E_INVALID for bad
+ * arguments or a smooth grid beyond the kernel's LDS (F - lf_jc + 1 too
+ * large for the continuation and its coefficients in 64 KiB). */
+int fhw_synthesize_lowfreq(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win, const void* V,
+                           const void* V_sing, int32_t N_r, const double* times, int32_t N_t, double* u);
 
 /* Sec. 4.1.2 (FFT accelerated evaluation of scaled discrete convolutions, eqs.
  * conv_sum and approx_conv_sum): as fhw_synthesize, on the uniform grid

@@ -34,6 +34,7 @@ struct chunk_t {
 struct plan_ext {
     std::vector<chunk_t> chunks;
     fhw_field_item* d_field_items = nullptr;
+    fhw_field_item* d_lf_items = nullptr;   // graded nodes 1 .. lf_M lf_N (the last is omega_c)
 };
 
 std::map<const fhw_ctx*, plan_ext> g_plans;   // per-context plan extension
@@ -350,6 +351,16 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     if (!isfinite(p->direction[0]) || !isfinite(p->direction[1]))
         return fhw_fail(c, FHW_E_INVALID, "plan: direction not finite");
     if (p->j_first < 0) return fhw_fail(c, FHW_E_INVALID, "plan: j_first must be >= 0");
+    const bool lowfreq = p->lf_M > 0;
+    if (p->lf_M < 0) return fhw_fail(c, FHW_E_INVALID, "plan: lf_M must be >= 0");
+    if (lowfreq) {
+        if (sys || n_curves != 1 || p->j_first != 0)
+            return fhw_fail(c, FHW_E_INVALID, "plan: the graded low-frequency nodes need a one-curve plan on the DFT grid");
+        if (p->lf_N < 1 || p->lf_N > 32 || !(p->lf_q > 0) || !isfinite(p->lf_q) || p->lf_jc < 1 ||
+            p->F - p->lf_jc + 1 < 20 || (int64_t)p->lf_M * p->lf_N > 4096)
+            return fhw_fail(c, FHW_E_INVALID, "plan: need 1 <= lf_N <= 32, lf_q > 0, lf_jc >= 1, F - lf_jc + 1 >= 20, "
+                                              "lf_M lf_N <= 4096");
+    }
     (void)hipStreamSynchronize(c->stream);
     free_plan(c);
     c->prob = *p;
@@ -385,8 +396,30 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     }
     // frequencies, sizes, coupling per system
     const int F = sys ? n_sys : p->F;
-    const int S = sys ? n_sys : n_curves * F;
     const double dw = p->W / (double)F;
+    // graded low-frequency nodes (eq. gradedmesh): Clenshaw-Curtis points of
+    // each [mu_j, mu_{j+1}], ascending, shared ends once
+    c->lf_extra = 0;
+    c->lf_mu.clear();
+    c->lf_nodes.clear();
+    if (lowfreq) {
+        const int M = p->lf_M, Nn = p->lf_N;
+        c->lf_omega_c = dw * (double)p->lf_jc;
+        c->lf_mu.resize(M + 1);
+        for (int j = 0; j <= M; ++j) c->lf_mu[j] = c->lf_omega_c * pow((double)j / (double)M, p->lf_q);
+        for (int j = 0; j < M; ++j) {
+            const double a = c->lf_mu[j], b = c->lf_mu[j + 1];
+            for (int i = 0; i < Nn; ++i)   // Clenshaw-Curtis point Nn - i: cos(pi (Nn - i) / Nn) ascends with i
+                c->lf_nodes.push_back(0.5 * (a + b) + 0.5 * (b - a) * cos(M_PI * (double)(Nn - i) / (double)Nn));
+        }
+        c->lf_nodes.push_back(c->lf_omega_c);
+        c->lf_nodes[0] = 0.0;
+        for (size_t g = 1; g < c->lf_nodes.size(); ++g)
+            if (!(c->lf_nodes[g] > c->lf_nodes[g - 1]))
+                return fhw_fail(c, FHW_E_INVALID, "plan: graded nodes not increasing (lf_q too large for lf_M)");
+        c->lf_extra = M * Nn - 1;
+    }
+    const int S = sys ? n_sys : n_curves * F + c->lf_extra;
     c->kappa.resize(S);
     c->eta.resize(S);
     c->Ns.resize(S);
@@ -419,6 +452,25 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
                 return fhw_fail(c, FHW_E_INVALID, "plan: N must be even, 4 <= N <= 4096");
             c->Ns[sy] = N;
         }
+    for (int e = 0; e < c->lf_extra; ++e) {
+        // graded node e + 1 (ascending), on curve 0, N by the same rule
+        const int sy = F + e;
+        c->sys_curve[sy] = 0;
+        c->kappa[sy] = c->lf_nodes[e + 1] / p->c;
+        c->eta[sy] = std::max(c->kappa[sy], 1.0);
+        int N;
+        if (p->N_fixed > 0) {
+            N = p->N_fixed;
+        } else {
+            if (p->n_mult < 1 || p->n_min < 2 || p->n_cap < p->n_min || !(p->ppw > 0))
+                return fhw_fail(c, FHW_E_INVALID, "plan: bad N rule");
+            double raw = p->ppw * c->curves[0].length * c->kappa[sy] / (2.0 * M_PI);
+            double m = ceil(raw / (double)p->n_mult) * (double)p->n_mult;
+            N = (int)std::min<double>(std::max<double>(m, p->n_min), p->n_cap);
+        }
+        if (N < 4 || (N & 1) || N > 4096) return fhw_fail(c, FHW_E_INVALID, "plan: N must be even, 4 <= N <= 4096");
+        c->Ns[sy] = N;
+    }
     c->psi_off.assign(S + 1, 0);
     for (int j = 0; j < S; ++j) c->psi_off[j + 1] = c->psi_off[j] + c->Ns[j];
     int maxN = *std::max_element(c->Ns.begin(), c->Ns.end());
@@ -574,6 +626,14 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         fitems[j].kappa = c->kappa[j];
     }
     size_t oF = put(fitems.data(), fitems.size() * sizeof(fhw_field_item));
+    size_t oLF = 0;
+    if (c->lf_extra > 0) {
+        // graded nodes 1 .. lf_M lf_N: the extra systems, then omega_c (system lf_jc - 1)
+        std::vector<fhw_field_item> lfi(c->lf_extra + 1);
+        for (int e = 0; e < c->lf_extra; ++e) lfi[e] = fitems[F + e];
+        lfi[c->lf_extra] = fitems[p->lf_jc - 1];
+        oLF = put(lfi.data(), lfi.size() * sizeof(fhw_field_item));
+    }
     c->meta_bytes = align_up(host.size(), 64);
     FHW_HIP(c, hipMalloc(&c->meta, c->meta_bytes));
     FHW_HIP(c, hipMemcpy(c->meta, host.data(), host.size(), hipMemcpyHostToDevice));
@@ -589,6 +649,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         f.ch->d_lu_prefix = (int32_t*)(mb + f.oLP);
     }
     px.d_field_items = (fhw_field_item*)(mb + oF);
+    px.d_lf_items = c->lf_extra > 0 ? (fhw_field_item*)(mb + oLF) : nullptr;
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     c->planned = true;
     if (N_out)
@@ -1043,6 +1104,25 @@ int fhw_eval_field(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, 
     return fhw_eval_field_curve(c, 0, psi, obs, N_r, zero_value, V);
 }
 
+int fhw_eval_field_lowfreq(fhw_ctx* c, const void* psi, const double* obs, int32_t N_r, double zero_value,
+                           void* V_sing) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field_lowfreq: no plan");
+    if (c->lf_extra <= 0) return fhw_fail(c, FHW_E_STATE, "field_lowfreq: the plan has no graded low-frequency nodes");
+    if (N_r < 0 || (N_r > 0 && (!psi || !obs || !V_sing)) || !isfinite(zero_value))
+        return fhw_fail(c, FHW_E_INVALID, "field_lowfreq: bad arguments");
+    if (N_r == 0) return FHW_OK;
+    for (int q = 0; q < 2 * N_r; ++q)
+        if (!isfinite(obs[q])) return fhw_fail(c, FHW_E_INVALID, "field_lowfreq: observation point not finite");
+    int rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
+    if (rc) return rc;
+    FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
+    STAGE(c, FHW_STAGE_FIELD, launch_field_list(c->stream, g_plans[c].d_lf_items, c->lf_extra + 1, psi,
+                                                (const double*)c->scratch, N_r, zero_value, V_sing));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
 // Windows k whose support [s_k - H, s_k + H], s_k = 1.5 H (k - 1), meets the
 // signal's sample range (Sec. 3.1); empty when k_lo > k_hi.
 static void signal_windows(const fhw_signal* sig, double H, int64_t* k_lo_out, int64_t* k_hi_out) {
@@ -1148,6 +1228,90 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
         for (double v : b) n += v > ttol * gm ? 1 : 0;
         c->trk_active = n;
     }
+    return FHW_OK;
+}
+
+// 2D time samples with the low-frequency decomposition: window spectra at the
+// smooth grid of [omega_c, W] and at the graded nodes, the continuation's
+// Fourier coefficients and the Filon-Clenshaw-Curtis data per (window,
+// point), then every (point, time) summed over all windows (lowfreq.hip).
+int fhw_synthesize_lowfreq(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V,
+                           const void* V_sing, int32_t N_r, const double* times, int32_t N_t, double* u) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize_lowfreq: no plan");
+    if (c->lf_extra <= 0)
+        return fhw_fail(c, FHW_E_STATE, "synthesize_lowfreq: the plan has no graded low-frequency nodes");
+    if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad arguments");
+    if (N_r == 0 || N_t == 0) return FHW_OK;
+    if (!V || !V_sing || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad signal or buffers");
+    const double H = win->H, tau0 = win->tau0;
+    if (!(H > 0) || !isfinite(H) || !isfinite(tau0) || win->track_tol != 0.0)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad windows (track_tol must be 0)");
+    if (N_r > 65535) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: at most 65535 points");
+    for (int q = 0; q < N_t; ++q)
+        if (!isfinite(times[q])) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: time not finite");
+    const fhw_problem& p = c->prob;
+    const int F = p.F, M = p.lf_M, nc = p.lf_N, jc = p.lf_jc;
+    const int n = F - jc + 1, L = n + lf_fc_points();
+    const size_t lds_coef = (size_t)2 * L * 16, lds_syn = ((size_t)2 * L + (size_t)M * 3 * (nc + 1)) * 16;
+    if (n > lf_max_points() || lds_coef > 65536 || lds_syn > 65536)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: F - lf_jc + 1 too large for the kernels' 64 KiB of LDS");
+    int64_t k_lo, k_hi;
+    signal_windows(sig, H, &k_lo, &k_hi);
+    if (k_hi < k_lo) {
+        FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
+        FHW_HIP(c, hipStreamSynchronize(c->stream));
+        return FHW_OK;
+    }
+    const int K = (int)(k_hi - k_lo + 1);
+    std::vector<int64_t> klist(K);
+    for (int q = 0; q < K; ++q) klist[q] = k_lo + q;
+    const double h = p.W / (double)F;
+    const int n_om = n + M * nc + 1;
+    std::vector<double> om(n_om);
+    for (int i = 0; i < n; ++i) om[i] = c->lf_omega_c + h * (double)i;
+    for (int g = 0; g <= M * nc; ++g) om[n + g] = c->lf_nodes[g];
+    // moments of x^p against T_k on [-1, 1]: row 0 from int T_k = 2/(1 - k^2)
+    // (even k), then x T_k = (T_{k+1} + T_{|k-1|}) / 2
+    const int PT = lf_taylor_terms();
+    const int KT = nc + PT + 1;
+    std::vector<double> Sp(KT, 0.0), Sn(KT, 0.0), tay((size_t)(nc + 1) * PT);
+    for (int k = 0; k < KT; ++k) Sp[k] = (k % 2 == 0) ? 2.0 / (1.0 - (double)k * (double)k) : 0.0;
+    for (int pw = 0; pw < PT; ++pw) {
+        for (int k = 0; k <= nc; ++k) tay[(size_t)k * PT + pw] = Sp[k];
+        for (int k = 0; k + 1 < KT; ++k) Sn[k] = 0.5 * (Sp[k + 1] + Sp[k == 0 ? 1 : k - 1]);
+        std::swap(Sp, Sn);
+    }
+    size_t o_t = 0;
+    size_t o_k = align_up(o_t + (size_t)N_t * 8, 256);
+    size_t o_om = align_up(o_k + (size_t)K * 8, 256);
+    size_t o_mu = align_up(o_om + (size_t)n_om * 8, 256);
+    size_t o_ty = align_up(o_mu + (size_t)(M + 1) * 8, 256);
+    size_t o_B = align_up(o_ty + tay.size() * 8, 256);
+    size_t o_cf = align_up(o_B + (size_t)K * n_om * 16, 256);
+    size_t o_ch = align_up(o_cf + (size_t)K * N_r * L * 16, 256);
+    size_t total = align_up(o_ch + (size_t)K * N_r * M * 3 * (nc + 1) * 16, 256);
+    int rc = fhw_ensure_scratch(c, total);
+    if (rc) return rc;
+    char* sb = (char*)c->scratch;
+    FHW_HIP(c, hipMemcpyAsync(sb + o_t, times, (size_t)N_t * 8, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o_k, klist.data(), (size_t)K * 8, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o_om, om.data(), (size_t)n_om * 8, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o_mu, c->lf_mu.data(), (size_t)(M + 1) * 8, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o_ty, tay.data(), tay.size() * 8, hipMemcpyHostToDevice, c->stream));
+    STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra_at(c->stream, sig->f, sig->n, sig->t0, sig->dt, H,
+                                                         (const int64_t*)(sb + o_k), K, (const double*)(sb + o_om),
+                                                         n_om, sb + o_B));
+    STAGE(c, FHW_STAGE_COEFFS, launch_lf_coeffs(c->stream, sb + o_B, (const double*)(sb + o_om), n_om, V, V_sing, N_r,
+                                                F, jc, n, M, nc, tau0, K, sb + o_cf, sb + o_ch));
+    STAGE(c, FHW_STAGE_SYNTH, launch_lf_synth(c->stream, sb + o_cf, sb + o_ch, (const int64_t*)(sb + o_k), K,
+                                              (const double*)(sb + o_mu), (const double*)(sb + o_ty),
+                                              (const double*)(sb + o_t), N_t, N_r, n, M, nc, h, c->lf_omega_c, H,
+                                              tau0, u));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    c->trk_pairs = (int64_t)K * N_r;
+    c->trk_active = c->trk_pairs;
     return FHW_OK;
 }
 

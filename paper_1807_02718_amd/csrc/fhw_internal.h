@@ -82,6 +82,11 @@ struct fhw_ctx {
     std::vector<int32_t> sys_curve;    // [systems] curve of each system
     bool system_plan = false;          // planned by fhw_plan_systems (no DFT grid)
     std::vector<int64_t> psi_off;      // [systems + 1]
+    // graded low-frequency nodes (plans with lf_M > 0): systems F .. F + lf_extra - 1
+    int32_t lf_extra = 0;              // lf_M lf_N - 1 (0: none)
+    double lf_omega_c = 0.0;
+    std::vector<double> lf_mu;         // [lf_M + 1] graded mesh
+    std::vector<double> lf_nodes;      // [lf_M lf_N + 1] ascending, 0 .. omega_c
     std::map<int64_t, fhw_geom_entry> geoms;   // key: curve * 65536 + N
 
     // solve workspace (one chunk of frequencies)
@@ -247,11 +252,36 @@ struct fhw_field_item {
 hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
                         const double* obs, int32_t N_r, double zero_value, void* V);
 hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
+// V[r][0] = zero_value, V[r][1 + j] = field of item j: complex128 [N_r][n_items + 1]
+hipError_t launch_field_list(hipStream_t s, const fhw_field_item* d_items, int32_t n_items, const void* psi,
+                             const double* obs, int32_t N_r, double zero_value, void* V);
+
+// --- lowfreq.hip --------------------------------------------------------------
+// largest number of smooth-grid frequencies the continuation kernel takes;
+// continuation points; Taylor terms of the small-argument moments
+int lf_max_points(void);
+int lf_fc_points(void);
+int lf_taylor_terms(void);
+// per (window, point): Fourier coefficients of the continued smooth part
+// (cfs [K][N_r][n + FC_C]) and the graded subintervals' Chebyshev data
+// (cheb [K][N_r][M][3][nc + 1]); B [K][n_om] at om = smooth grid then the
+// M nc + 1 graded nodes; V [N_r][2F]; Vs [N_r][M nc + 1]
+hipError_t launch_lf_coeffs(hipStream_t s, const void* B, const double* om, int n_om, const void* V, const void* Vs,
+                            int N_r, int F, int jc, int n, int M, int nc, double tau0, int K, void* cfs, void* cheb);
+// u [N_r][N_t] = sum over the K windows of (1/pi) Re (I_+ + I_0); mu [M + 1]
+// graded mesh; taylor [nc + 1][40] moments of x^p against T_k
+hipError_t launch_lf_synth(hipStream_t s, const void* cfs, const void* cheb, const int64_t* klist, int K,
+                           const double* mu, const double* taylor, const double* times, int N_t, int N_r, int n,
+                           int M, int nc, double h, double omega_c, double H, double tau0, double* u);
 
 // --- synth.hip --------------------------------------------------------------
 hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, double t0, double dt,
                                  double H, int64_t k_first, const int64_t* d_klist, int32_t count,
                                  double W, int32_t F, void* B);
+// the same at the n_om frequencies d_om (device), B [count][n_om]
+hipError_t launch_window_spectra_at(hipStream_t s, const double* f, int64_t n, double t0, double dt, double H,
+                                    const int64_t* d_klist, int32_t count, const double* d_om, int32_t n_om,
+                                    void* B);
 // c: complex128 [count][N_r][2F]; or, with c == NULL, real parts only into c_re.
 // bnd (optional, tracking): [count][N_r] sums of |Re c_m|, their maximum into
 // *gmax (as the bits of a double; zero before the call); windows whose

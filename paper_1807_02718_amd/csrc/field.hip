@@ -46,6 +46,42 @@ __global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restri
     }
 }
 
+// V[r][0] = zero_value, V[r][1 + j] = field of item j (j < n_items): the
+// field at an explicit list of systems (the graded low-frequency nodes).
+__global__ __launch_bounds__(256, 4) void k_field_list(const fhw_field_item* __restrict__ items, int n_items,
+                                                    const zd* __restrict__ psi, const double* __restrict__ obs,
+                                                    int N_r, double zero_value, zd* __restrict__ V) {
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= N_r * n_items) return;
+    const int r = wave / n_items;
+    const int j = wave - r * n_items;
+    const fhw_field_item it = items[j];
+    const int N = it.N;
+    const double* x1 = it.geom;
+    const double* x2 = it.geom + N;
+    const double* sp = it.geom + 6 * N;
+    const zd* ps = psi + it.psi_off;
+    const double o1 = obs[2 * r], o2 = obs[2 * r + 1];
+    zd acc = cmk(0.0, 0.0);
+    for (int i = lane; i < N; i += 64) {
+        const double d1 = o1 - x1[i], d2 = o2 - x2[i];
+        const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
+        double J0, Y0;
+        fhw_bessel0(z, J0, Y0);
+        const zd gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
+        acc = cfma(acc, gk, ps[i]);
+    }
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) {
+        const double wq = 2.0 * FHW_PI / (double)N;
+        zd* Vr = V + (int64_t)r * (n_items + 1);
+        Vr[1 + j] = cmk(wq * acc.re, wq * acc.im);
+        if (j == 0) Vr[0] = cmk(zero_value, 0.0);
+    }
+}
+
 __global__ void k_hankel01(const double* __restrict__ z, int64_t n, zd* __restrict__ h) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -61,6 +97,15 @@ hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F,
     if (waves <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_field, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items, F, (const zd*)psi, obs,
                        N_r, zero_value, (zd*)V);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_list(hipStream_t s, const fhw_field_item* d_items, int32_t n_items, const void* psi,
+                             const double* obs, int32_t N_r, double zero_value, void* V) {
+    const int64_t waves = (int64_t)N_r * n_items;
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_field_list, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items, n_items,
+                       (const zd*)psi, obs, N_r, zero_value, (zd*)V);
     return hipGetLastError();
 }
 

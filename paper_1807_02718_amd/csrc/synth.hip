@@ -32,9 +32,12 @@ __device__ __forceinline__ double fhw_window(double t, double H) {
 // sums of a frequency are added in phase order.
 #define WS_FREQ 32
 #define WS_PH (SYN_THREADS / WS_FREQ)
+// With om_list != NULL the frequencies are om_list[0 .. n_om - 1] instead of
+// the DFT grid (B row length n_om).
 __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __restrict__ f, int64_t n, double t0,
                                                                 double dt, double H, int64_t k_first,
                                                                 const int64_t* __restrict__ klist, double W, int F,
+                                                                const double* __restrict__ om_list, int n_om,
                                                                 zd* __restrict__ B) {
     __shared__ double wa[WS_CHUNK];
     __shared__ double tau[WS_CHUNK];
@@ -42,11 +45,11 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
     const int q = blockIdx.x;
     const int64_t k = klist ? klist[q] : (k_first + q);
     const double sk = 1.5 * H * ((double)k - 1.0);
-    const int M = 2 * F;
+    const int M = om_list ? n_om : 2 * F;
     const int fl = threadIdx.x % WS_FREQ, ph = threadIdx.x / WS_FREQ;
     const int l = blockIdx.y * WS_FREQ + fl;
     const double dw = W / (double)F;
-    const double om = -W + dw * (double)l;
+    const double om = om_list ? (l < M ? om_list[l] : 0.0) : -W + dw * (double)l;
     int64_t n_lo = (int64_t)floor((sk - H - t0) / dt) - 1;
     int64_t n_hi = (int64_t)ceil((sk + H - t0) / dt) + 1;
     if (n_lo < 0) n_lo = 0;
@@ -275,7 +278,17 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
     if (count <= 0) return hipSuccess;
     dim3 grid(count, (2 * F + WS_FREQ - 1) / WS_FREQ);
     hipLaunchKernelGGL(k_window_spectra, grid, dim3(SYN_THREADS), 0, s, f, n, t0, dt, H, k_first, d_klist, W, F,
-                       (zd*)B);
+                       (const double*)nullptr, 0, (zd*)B);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_spectra_at(hipStream_t s, const double* f, int64_t n, double t0, double dt, double H,
+                                    const int64_t* d_klist, int32_t count, const double* d_om, int32_t n_om,
+                                    void* B) {
+    if (count <= 0 || n_om <= 0) return hipSuccess;
+    dim3 grid(count, (n_om + WS_FREQ - 1) / WS_FREQ);
+    hipLaunchKernelGGL(k_window_spectra, grid, dim3(SYN_THREADS), 0, s, f, n, t0, dt, H, (int64_t)0, d_klist, 1.0, 1,
+                       d_om, n_om, (zd*)B);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ class fhw_problem(C.Structure):
     _fields_ = [("W", C.c_double), ("F", C.c_int32), ("c", C.c_double), ("N_fixed", C.c_int32),
                 ("ppw", C.c_double), ("n_min", C.c_int32), ("n_mult", C.c_int32), ("n_cap", C.c_int32),
                 ("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_max", C.c_int32),
-                ("direction", C.c_double * 2), ("j_first", C.c_int32)]
+                ("direction", C.c_double * 2), ("j_first", C.c_int32),
+                ("lf_M", C.c_int32), ("lf_N", C.c_int32), ("lf_jc", C.c_int32), ("lf_q", C.c_double)]
 
 
 class fhw_signal(C.Structure):
@@ -87,6 +88,8 @@ def _load():
         "fhw_solve_cached": [vp, C.POINTER(fhw_incidence), i32, vp, _dp, p_i32],
         "fhw_eval_field": [vp, vp, _dp, i32, C.c_double, vp],
         "fhw_eval_field_curve": [vp, i32, vp, _dp, i32, C.c_double, vp],
+        "fhw_eval_field_lowfreq": [vp, vp, _dp, i32, C.c_double, vp],
+        "fhw_synthesize_lowfreq": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, vp, i32, _dp, i32, vp],
         "fhw_synthesize": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, _dp, i32, vp],
         "fhw_synthesize_uniform": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), vp, i32, C.c_double,
                                    C.c_double, i32, i32, vp],
@@ -115,7 +118,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
             "fhw_plan_systems", "fhw_factor", "fhw_solve_range", "fhw_solve_range_noalloc",
-            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_synthesize", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_eval_field_lowfreq", "fhw_synthesize", "fhw_synthesize_lowfreq", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
@@ -176,9 +179,11 @@ class Context:
 
     # -- plan -----------------------------------------------------------------
     def plan(self, curve, W, F, N=None, c=1.0, ppw=10.0, n_min=64, n_mult=32, n_cap=4096, precision="fp64",
-             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0), j_first=0):
+             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0), j_first=0, lowfreq=None):
         """Plan one curve, or several (a list: fhw_plan_curves, system s = k F + j).
         j_first > 0 plans the band (j_first + j) W / F, j = 1..F (solves only).
+        lowfreq = dict(jc, M, n, q) adds the graded low-frequency systems
+        (M n - 1 of them after the F grid systems; one curve).
         Returns (N per system, psi offsets)."""
         many = isinstance(curve, (list, tuple))
         curves = list(curve) if many else [curve]
@@ -195,7 +200,12 @@ class Context:
         pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
         pr.direction[0], pr.direction[1] = float(direction[0]), float(direction[1])
         pr.j_first = int(j_first)
-        S = len(curves) * int(F)
+        extra = 0
+        if lowfreq is not None:
+            pr.lf_M, pr.lf_N, pr.lf_jc = int(lowfreq["M"]), int(lowfreq["n"]), int(lowfreq["jc"])
+            pr.lf_q = float(lowfreq["q"])
+            extra = pr.lf_M * pr.lf_N - 1
+        S = len(curves) * int(F) + extra
         Ns = np.zeros(S, dtype=np.int32)
         off = np.zeros(S + 1, dtype=np.int64)
         pN, po = Ns.ctypes.data_as(C.POINTER(C.c_int32)), off.ctypes.data_as(C.POINTER(C.c_int64))
@@ -206,6 +216,7 @@ class Context:
         self.F, self.W, self.Ns, self.psi_off = int(F), float(W), Ns, off
         self.S, self.n_curves = S, len(curves)
         self.precision = precision
+        self.lowfreq = dict(lowfreq) if lowfreq is not None else None
         return Ns, off
 
     def plan_systems(self, curves, systems, c=1.0, precision="fp64", refine_tol=1e-12, refine_max=10,
@@ -309,6 +320,31 @@ class Context:
             self._check(_lib.fhw_eval_field_curve(self._h, int(curve), _ptr(psi), obs_p, Nr, float(zero_value),
                                                   _ptr(V)))
         return V
+
+    def eval_field_lowfreq(self, psi, obs, zero_value=1.0, V_sing=None):
+        """fhw_eval_field_lowfreq: the field at the graded nodes (ascending,
+        0 .. omega_c), complex128 [N_r][M n + 1]."""
+        obs_h, obs_p = _host(obs, np.float64)
+        Nr = obs_h.shape[0]
+        if V_sing is None:
+            lf = self.lowfreq or {"M": 0, "n": 0}
+            V_sing = torch.empty((Nr, lf["M"] * lf["n"] + 1), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_eval_field_lowfreq(self._h, _ptr(psi), obs_p, Nr, float(zero_value), _ptr(V_sing)))
+        return V_sing
+
+    def synthesize_lowfreq(self, f, t0, dt, H, tau0, V, V_sing, times, u=None):
+        """fhw_synthesize_lowfreq: time samples with the 2D low-frequency
+        decomposition from V [N_r][2F] and V_sing [N_r][M n + 1]."""
+        f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)
+        sg = fhw_signal(float(t0), float(dt), int(f.numel()), _ptr(f).value)
+        wn = fhw_windows(float(H), float(tau0), 0.0)
+        th, tp = _host(times, np.float64)
+        Nr = V.shape[0]
+        if u is None:
+            u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_synthesize_lowfreq(self._h, C.byref(sg), C.byref(wn), _ptr(V), _ptr(V_sing), Nr, tp,
+                                                len(th), _ptr(u)))
+        return u
 
     def synthesize(self, f, t0, dt, H, tau0, V, times, u=None, track_tol=0.0):
         f = f if isinstance(f, torch.Tensor) else torch.as_tensor(np.asarray(f, dtype=np.float64), device=self.device)

@@ -105,3 +105,17 @@ def test_panel_table_round_trip(tmp_path):
     for vname, (vt, case) in tune.variants().items():
         diff = [k for k in vt if vt[k] != tab[k]]
         assert (case is None and not diff) or diff == [tune.case_name(*case)], vname
+
+
+def test_fc_tables_are_current():
+    """The committed FC(Gram) continuation tables match what their generator
+    writes now (60-digit least squares; about half a minute)."""
+    import subprocess
+    import sys
+    import tempfile
+    csrc = os.path.join(ROOT, "paper_1807_02718_amd", "csrc")
+    with tempfile.TemporaryDirectory() as d:
+        gen = os.path.join(d, "gen_fc_tables.py")
+        open(gen, "w").write(open(os.path.join(csrc, "gen_fc_tables.py")).read())
+        subprocess.run([sys.executable, gen], check=True, cwd=d)
+        assert open(os.path.join(d, "fc_tables.h")).read() == open(os.path.join(csrc, "fc_tables.h")).read()
