@@ -295,94 +295,70 @@ def uniform_bench(fhw, torch, Wk, reps):
                       "workload": wl.name, "L": 4 * wl.F, "rows": out}), flush=True)
 
 
-def serve_batched(fhw, torch, Wk, rates, duration, max_wait, precision, batch_bytes):
-    """The serving configuration with continuous batching: before each round,
-    every request that has arrived (and is not past max_wait in the queue) is
-    admitted while the batch's matrices fit batch_bytes of HBM; the round
-    plans all their systems at once (fhw_plan_systems), factors them in
-    shared launches (fhw_factor) and solves each request on the resident
-    factors (fhw_solve_range), completing it there.  Requests that arrive
-    during a round join the next one.  Latency = completion - arrival."""
-    from collections import deque
-    per_sys = 24 if precision == "fp32_refine" else 16     # bytes per matrix entry (FP64 A + FP32 LU)
+def serve_server(fhw, torch, Wk, rates, duration, precision, slots, queue_gb):
+    """The serving configuration through the library's server (fhw_server_*):
+    requests are submitted at their Poisson arrival times (seed 1); the
+    server's worker slots take the waiting requests as they free up, factor
+    each round's systems together and complete every request on the resident
+    factors; a request submitted while queue_gb of workspace already waits is
+    refused (FHW_E_BUSY).  Latency = time its completion is seen - arrival
+    (the loop polls every pending request about every 0.2 ms)."""
     out = []
-    ctx = fhw.Context()
-    try:
-        for rate in rates:
-            curves, reqs = Wk.serve_requests(rate, duration)
-            if not reqs:
-                out.append({"rate": rate, "offered": 0, "completed": 0, "refused": 0})
-                continue
-            # warm-up outside the clock at the size of a full batch
-            warm, nb = [], 0
-            for r in sorted(reqs, key=lambda r: -r["N"]):
-                b = r["F"] * per_sys * r["N"] * r["N"]
-                if warm and nb + b > batch_bytes:
-                    break
-                warm.append(r)
-                nb += b
-            ctx.plan_systems(curves, [(r["curve"], (r["j_first"] + j + 1) * 1.0, r["N"]) for r in warm
-                                      for j in range(r["F"])], precision=precision)
-            ctx.factor()
-            torch.cuda.synchronize()
-            lat, wait, refused, solves, sizes = [], [], 0, 0, []
-            queue = deque()
+    for rate in rates:
+        curves, reqs = Wk.serve_requests(rate, duration)
+        srv = fhw.Server(curves, precision=precision, refine_tol=1e-12, refine_max=10, slots=slots,
+                         queue_limit_bytes=int(queue_gb * 1e9))
+        try:
+            # warm-up outside the clock: the largest requests of the stream,
+            # so that the slots' workspaces have grown
+            for r in sorted(reqs, key=lambda r: -r["N"] * r["N"] * r["F"])[:2 * slots]:
+                oms = [(r["j_first"] + j + 1) * 1.0 for j in range(r["F"])]
+                t, *_ = srv.submit(r["curve"], oms, r["N"], [("plane", d) for d in r["dirs"][:1]])
+                srv.poll(t, wait=True)
+            base = srv.stats()
+            lat, refused, solves = [], 0, 0
+            pending = {}
             i = 0
             t0 = time.perf_counter()
-            busy = 0.0
-            while i < len(reqs) or queue:
+            while i < len(reqs) or pending:
                 now = time.perf_counter() - t0
                 while i < len(reqs) and reqs[i]["t"] <= now:
-                    queue.append(reqs[i])
+                    r = reqs[i]
                     i += 1
-                if not queue:
-                    time.sleep(max(0.0, min(reqs[i]["t"] - now, 1e-3)))
-                    continue
-                admit, nbytes = [], 0
-                while queue:
-                    r = queue[0]
-                    if now - r["t"] > max_wait:
+                    oms = [(r["j_first"] + j + 1) * 1.0 for j in range(r["F"])]
+                    try:
+                        t, *_ = srv.submit(r["curve"], oms, r["N"], [("plane", d) for d in r["dirs"]])
+                        pending[t] = r
+                    except fhw.FhwError as e:
+                        if e.code != fhw.FHW_E_BUSY:
+                            raise
                         refused += 1
-                        queue.popleft()
-                        continue
-                    b = r["F"] * per_sys * r["N"] * r["N"]
-                    if admit and nbytes + b > batch_bytes:
-                        break
-                    admit.append(queue.popleft())
-                    nbytes += b
-                if not admit:
-                    continue
-                start = time.perf_counter()
-                systems = [(r["curve"], (r["j_first"] + j + 1) * 1.0, r["N"]) for r in admit for j in range(r["F"])]
-                ctx.plan_systems(curves, systems, precision=precision, refine_tol=1e-12, refine_max=10)
-                ctx.factor()
-                s0 = 0
-                for r in admit:
-                    ctx.solve_range(s0, r["F"], [("plane", d) for d in r["dirs"]])
-                    end = time.perf_counter()
-                    lat.append(end - (t0 + r["t"]))
-                    wait.append(start - (t0 + r["t"]))
-                    solves += r["F"] * len(r["dirs"])
-                    s0 += r["F"]
-                busy += time.perf_counter() - start
-                sizes.append(len(admit))
+                for t in list(pending):
+                    st = srv.poll(t)
+                    if st != 1:
+                        r = pending.pop(t)
+                        if st != fhw.FHW_OK:
+                            raise fhw.FhwError(st, "request failed")
+                        lat.append(time.perf_counter() - t0 - r["t"])
+                        solves += r["F"] * len(r["dirs"])
+                time.sleep(2e-4)
             wall = time.perf_counter() - t0
-            q = lambda a, p: float(np.percentile(np.asarray(a) * 1e3, p)) if a else None
-            out.append({"rate": rate, "offered": len(reqs), "completed": len(lat), "refused": refused,
-                        "goodput_req_s": len(lat) / wall, "rhs_solves_per_s": solves / wall,
-                        "p50_ms": q(lat, 50), "p99_ms": q(lat, 99),
-                        "mean_wait_ms": float(np.mean(wait) * 1e3) if wait else None,
-                        "rounds": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
-                        "busy": busy / wall, "wall_s": wall})
-            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
-    finally:
-        ctx.close()
+            st = srv.stats()
+        finally:
+            srv.close()
+        rounds = st["rounds"] - base["rounds"]
+        q = lambda a, p: float(np.percentile(np.asarray(a) * 1e3, p)) if a else None
+        out.append({"rate": rate, "offered": len(reqs), "completed": len(lat), "refused": refused,
+                    "goodput_req_s": len(lat) / wall, "rhs_solves_per_s": solves / wall,
+                    "p50_ms": q(lat, 50), "p99_ms": q(lat, 99), "rounds": rounds,
+                    "mean_requests_per_round": len(lat) / max(rounds, 1),
+                    "slot_busy": (st["busy_s"] - base["busy_s"]) / (slots * wall), "wall_s": wall})
+        print(json.dumps(out[-1]), file=sys.stderr, flush=True)
     print(json.dumps({"metric": "serving: per-request latency (p50/p99) and goodput under Poisson arrivals",
                       "workload": "16 star curves; bands of 10-50 frequencies on (0, 300], N 256-4096, 1-64 plane "
-                                  "waves per request; continuous batching (all waiting requests per round, "
-                                  "factored together)",
-                      "precision": precision, "duration_s": duration, "max_wait_s": max_wait,
-                      "batch_bytes": batch_bytes, "rates": out}), flush=True)
+                                  "waves per request; library server, continuous batching over worker slots",
+                      "precision": precision, "duration_s": duration, "slots": slots, "queue_gb": queue_gb,
+                      "rates": out}), flush=True)
 
 
 def serve_bench(fhw, torch, Wk, rates, duration, max_wait, precision):
@@ -513,12 +489,14 @@ def main():
                     help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
                          "serve: Poisson request stream (per-request latency); batch_sweep: solves/s at "
                          "batches of 1, 16, 256, 1024 frequencies")
-    ap.add_argument("--rates", default="5,10,20,50", help="serve: arrival rates (requests/s)")
-    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals per rate")
-    ap.add_argument("--max-wait", type=float, default=2.0, help="serve: refuse requests queued longer (s)")
-    ap.add_argument("--serve-mode", default="batched", choices=["batched", "fifo"],
-                    help="serve: continuous batching of waiting requests, or one request at a time")
-    ap.add_argument("--batch-gb", type=float, default=64.0, help="serve (batched): matrix bytes per round (GB)")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve: arrival rates (requests/s)")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--max-wait", type=float, default=2.0, help="serve (fifo): refuse requests queued longer (s)")
+    ap.add_argument("--serve-mode", default="server", choices=["server", "fifo"],
+                    help="serve: the library's server (continuous batching over worker slots), or one request "
+                         "at a time from the host")
+    ap.add_argument("--slots", type=int, default=2, help="serve (server): worker slots")
+    ap.add_argument("--queue-gb", type=float, default=64.0, help="serve (server): workspace bytes allowed to wait (GB)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -545,8 +523,8 @@ def main():
         return
     if a.workload == "serve":
         rates = [float(x) for x in a.rates.split(",")]
-        if a.serve_mode == "batched":
-            serve_batched(fhw, torch, Wk, rates, a.duration, a.max_wait, a.modes.split(",")[0], a.batch_gb * 1e9)
+        if a.serve_mode == "server":
+            serve_server(fhw, torch, Wk, rates, a.duration, a.modes.split(",")[0], a.slots, a.queue_gb)
         else:
             serve_bench(fhw, torch, Wk, rates, a.duration, a.max_wait, a.modes.split(",")[0])
         return

@@ -61,6 +61,7 @@ extern "C" {
 #define FHW_E_SINGULAR (-4) /* exactly zero pivot met in an LU factorization */
 #define FHW_E_NOCONV (-5)   /* iterative refinement did not reach its tolerance */
 #define FHW_E_STATE (-6)    /* call out of order (e.g. solve before plan) */
+#define FHW_E_BUSY (-7)     /* serving: the queue is full, the request was not admitted */
 
 #define FHW_FP64 0          /* complex128 LU and solves */
 #define FHW_FP32_REFINE 1   /* complex64 LU on MFMA + FP64-residual refinement */
@@ -238,6 +239,62 @@ int fhw_solve_range(fhw_ctx* ctx, int32_t s0, int32_t count, const fhw_incidence
 #define FHW_NOALLOC_MAX_PAIRS 16384
 int fhw_solve_range_noalloc(fhw_ctx* ctx, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc,
                             void* psi, double* resid, int32_t* sweeps);
+
+/* ---------------- serving (continuous batching of frequency solves) ------- */
+
+/* A solve request: frequencies omega[0 .. n_freq-1] (> 0) of one scatterer at N
+ * nodes, n_inc incident fields (as fhw_solve_incidences).  psi: device
+ * complex128 [n_inc][n_freq N] (incidence q, frequency j at q n_freq N + j N),
+ * caller-owned, written when the request completes; resid, sweeps [host,
+ * optional]: [n_inc][n_freq], written on completion.  The library copies
+ * omegas and inc at submission; psi, resid and sweeps must stay valid until
+ * the request is reported finished. */
+typedef struct {
+    int32_t curve;           /* index into the server's curves            */
+    int32_t n_freq;
+    const double* omegas;    /* [host] n_freq frequencies                  */
+    int32_t N;               /* even, 4 <= N <= 4096                       */
+    int32_t n_inc;
+    const fhw_incidence* inc;/* [host] n_inc incidences                    */
+    void* psi;
+    double* resid;
+    int32_t* sweeps;
+} fhw_request;
+
+typedef struct fhw_server fhw_server;
+
+/* A server for requests on a fixed set of scatterers (Sec. 2.3 solves of eq.
+ * CFIE_direct; the factorizations of a round stay resident for every
+ * right-hand side of its requests, the LU reuse of Appendix A).  n_slots
+ * worker slots on the current device, each a host thread with its own
+ * context, HIP stream (non-blocking, default priority) and hbm_budget_bytes /
+ * n_slots of workspace (0 = 85% of the free memory in all).  A free slot
+ * takes every waiting request in arrival order while their matrices fit its
+ * share, plans all their systems at once (fhw_plan_systems), factors them in
+ * shared launches (fhw_factor) and solves each request on the resident
+ * factors (fhw_solve_range), which completes it.  Requests that arrive while
+ * slots are busy wait for the next free slot; the slots' rounds overlap on
+ * the device.  prob supplies c, precision, refine_tol, refine_max (the other
+ * fields are not used).  queue_limit_bytes (0 = the whole budget): a request
+ * submitted while the waiting requests hold more workspace bytes than this is
+ * refused with FHW_E_BUSY.  curves [host] are copied. */
+int fhw_server_create(fhw_server** server, const fhw_curve* curves, int32_t n_curves, const fhw_problem* prob,
+                      int32_t n_slots, size_t hbm_budget_bytes, size_t queue_limit_bytes);
+/* Queue a request; *ticket identifies it.  FHW_E_BUSY: not admitted (queue
+ * full); FHW_E_NOMEM: larger than one slot's workspace; FHW_E_INVALID: bad
+ * request.  Thread-safe. */
+int fhw_server_submit(fhw_server* server, const fhw_request* req, int64_t* ticket);
+/* Status of a request: *status = 1 while pending, else its result code
+ * (FHW_OK or the solve's error).  wait != 0 blocks until it is finished.  A
+ * finished ticket is reported once and then forgotten (FHW_E_INVALID after).
+ * Thread-safe. */
+int fhw_server_poll(fhw_server* server, int64_t ticket, int32_t wait, int32_t* status);
+/* counts [host] int64[5]: rounds, requests finished, requests refused, systems
+ * solved, requests waiting; busy_s [host, optional]: the slots' summed round
+ * time in seconds. */
+int fhw_server_stats(fhw_server* server, int64_t* counts, double* busy_s);
+/* Finishes the waiting requests, stops the slots and frees everything. */
+int fhw_server_destroy(fhw_server* server);
 
 /* Step F5 (eqs. freq_domain_repr, Ukslow_repr): V(r, omega_l) on the full DFT
  * grid, V[r][l], complex128 [N_r][2F]; V(r,-omega) = conj V(r,omega) and

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfhw.so")
 BUILD = os.path.join(CSRC, "_build")
 SOURCES = ["api.hip", "geometry.hip", "assemble.hip", "lu.hip", "solve.hip", "field.hip", "synth.hip", "frft.hip",
-           "lowfreq.hip"]
+           "lowfreq.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -37,7 +37,15 @@ struct plan_ext {
     fhw_field_item* d_lf_items = nullptr;   // graded nodes 1 .. lf_M lf_N (the last is omega_c)
 };
 
-std::map<const fhw_ctx*, plan_ext> g_plans;   // per-context plan extension
+// per-context plan extension; contexts may live on different host threads
+// (one per stream), so lookups go through one lock (map nodes do not move)
+std::mutex g_plans_mu;
+std::map<const fhw_ctx*, plan_ext> g_plans;
+
+plan_ext& plan_of(const fhw_ctx* c) {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    return g_plans[c];
+}
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -66,29 +74,77 @@ void curve_eval_host(const fhw_host_curve& cv, double s, double& x1, double& x2,
 }
 
 void free_plan(fhw_ctx* c) {
-    auto it = g_plans.find(c);
-    if (it != g_plans.end()) {
-        for (auto& ch : it->second.chunks)
-            if (ch.lu_graph) (void)hipGraphExecDestroy(ch.lu_graph);
-        g_plans.erase(it);
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        auto it = g_plans.find(c);
+        if (it != g_plans.end()) {
+            for (auto& ch : it->second.chunks)
+                if (ch.lu_graph) (void)hipGraphExecDestroy(ch.lu_graph);
+            g_plans.erase(it);
+        }
     }
-    for (auto& kv : c->geoms) {
-        (void)hipFree(kv.second.geom);
-        (void)hipFree(kv.second.R);
-        (void)hipFree(kv.second.logtab);
-    }
+    // geometry, curve coefficients and the small per-plan buffers stay for
+    // the next plan (fhw_destroy frees them): freeing device memory
+    // synchronizes the device, which would stall other streams' work
     c->geoms.clear();
-    for (auto& cv : c->curves)
-        if (cv.d_curve) (void)hipFree(cv.d_curve);
     c->curves.clear();
-    // the large work buffers stay for the next plan (free_workspace)
+    c->planned = false;
+    c->factors_resident = false;
+}
+
+void free_caches(fhw_ctx* c) {
+    for (auto& kv : c->geo_cache) {
+        (void)hipFree(kv.second.e.geom);
+        (void)hipFree(kv.second.e.R);
+        (void)hipFree(kv.second.e.logtab);
+    }
+    c->geo_cache.clear();
+    c->geo_cache_bytes = 0;
+    for (auto& kv : c->curve_cache) (void)hipFree(kv.second.d);
+    c->curve_cache.clear();
     void* ptrs[] = {c->meta, c->d_status, c->d_norms, c->d_done, c->d_sweeps, c->d_rpart, c->d_rcount};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->meta = nullptr; c->d_status = nullptr; c->d_norms = nullptr; c->d_done = nullptr; c->d_sweeps = nullptr;
     c->d_rpart = nullptr; c->d_rcount = nullptr;
-    c->planned = false;
-    c->factors_resident = false;
+    for (size_t& k : c->small_cap) k = 0;
+}
+
+// A small per-plan buffer (index k of small_cap) of at least `bytes`, kept
+// across plans and reallocated only when a plan outgrows it; zero-filled
+// (on the context's stream) when `zero` and newly allocated.
+int grow_small(fhw_ctx* c, void** p, int k, size_t bytes, bool zero = false) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (*p && c->small_cap[k] >= bytes) return FHW_OK;
+    if (*p) {
+        FHW_HIP(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    c->small_cap[k] = 0;
+    const size_t nb = align_up(bytes + bytes / 2, 4096);
+    FHW_HIP(c, hipMalloc(p, nb));
+    c->small_cap[k] = nb;
+    if (zero) FHW_HIP(c, hipMemsetAsync(*p, 0, nb, c->stream));
+    return FHW_OK;
+}
+
+// device-to-host copy on the context's stream, then wait for it
+int copy_d2h(fhw_ctx* c, void* dst, const void* src, size_t bytes) {
+    FHW_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
+uint64_t curve_fingerprint(const fhw_host_curve& cv) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    };
+    mix(&cv.degree, sizeof(cv.degree));
+    for (const std::vector<double>* v : {&cv.cx, &cv.sx, &cv.cy, &cv.sy}) mix(v->data(), v->size() * sizeof(double));
+    return h;
 }
 
 void** workspace_slot(fhw_ctx* c, int k) {
@@ -306,6 +362,7 @@ int fhw_destroy(fhw_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     free_plan(c);
     free_workspace(c);
+    free_caches(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->d_pending) (void)hipFree(c->d_pending);
@@ -478,35 +535,70 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         return fhw_fail(c, FHW_E_INVALID, "plan: N too large for the LDS-resident solve vector");
 
     // curve coefficients on device, geometry + Kress tables per (curve, distinct N)
+    // (kept across plans: a curve's coefficients and its nodes and Kress
+    // tables at each N are computed once per context)
     size_t geo = 0;
+    if (c->geo_cache_bytes > ((size_t)1 << 30)) {
+        FHW_HIP(c, hipStreamSynchronize(c->stream));
+        for (auto& kv : c->geo_cache) {
+            (void)hipFree(kv.second.e.geom);
+            (void)hipFree(kv.second.e.R);
+            (void)hipFree(kv.second.e.logtab);
+        }
+        c->geo_cache.clear();
+        c->geo_cache_bytes = 0;
+    }
     for (int k = 0; k < n_curves; ++k) {
         fhw_host_curve& cv = c->curves[k];
         const int D1 = cv.degree + 1;
-        FHW_HIP(c, hipMalloc(&cv.d_curve, sizeof(double) * 4 * D1));
         std::vector<double> hc(4 * D1);
         for (int d = 0; d < D1; ++d) {
             hc[d] = cv.cx[d]; hc[D1 + d] = cv.sx[d]; hc[2 * D1 + d] = cv.cy[d]; hc[3 * D1 + d] = cv.sy[d];
         }
-        FHW_HIP(c, hipMemcpy(cv.d_curve, hc.data(), sizeof(double) * 4 * D1, hipMemcpyHostToDevice));
+        const uint64_t fp = curve_fingerprint(cv);
+        auto cit = c->curve_cache.find(fp);
+        if (cit == c->curve_cache.end() || cit->second.coef != hc) {
+            if (cit != c->curve_cache.end()) {
+                // a different curve with the same fingerprint: drop the old entry
+                FHW_HIP(c, hipStreamSynchronize(c->stream));
+                (void)hipFree(cit->second.d);
+                c->curve_cache.erase(cit);
+            }
+            fhw_curve_cache_entry ce;
+            ce.coef = hc;
+            FHW_HIP(c, hipMalloc((void**)&ce.d, sizeof(double) * 4 * D1));
+            FHW_HIP(c, hipMemcpyAsync(ce.d, ce.coef.data(), sizeof(double) * 4 * D1, hipMemcpyHostToDevice,
+                                      c->stream));
+            FHW_HIP(c, hipStreamSynchronize(c->stream));
+            cit = c->curve_cache.emplace(fp, std::move(ce)).first;
+        }
+        cv.d_curve = cit->second.d;
+        cv.fingerprint = fp;
         std::set<int32_t> distinct;
         for (int s = 0; s < S; ++s)
             if (c->sys_curve[s] == k) distinct.insert(c->Ns[s]);
         for (int32_t N : distinct) {
-            fhw_geom_entry e{};
-            e.N = N;
-            FHW_HIP(c, hipMalloc(&e.geom, sizeof(double) * 9 * N));
-            FHW_HIP(c, hipMalloc(&e.R, sizeof(double) * N));
-            FHW_HIP(c, hipMalloc(&e.logtab, sizeof(double) * N));
-            STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, cv.d_curve, cv.degree, N, e.geom));
-            STAGE(c, FHW_STAGE_KRESS, launch_kress(c->stream, N, e.R, e.logtab));
-            c->geoms[fhw_geom_key(k, N)] = e;
+            auto git = c->geo_cache.find({fp, N});
+            if (git == c->geo_cache.end()) {
+                fhw_geo_cache_entry ge{};
+                fhw_geom_entry& e = ge.e;
+                e.N = N;
+                FHW_HIP(c, hipMalloc(&e.geom, sizeof(double) * 9 * N));
+                FHW_HIP(c, hipMalloc(&e.R, sizeof(double) * N));
+                FHW_HIP(c, hipMalloc(&e.logtab, sizeof(double) * N));
+                STAGE(c, FHW_STAGE_GEOMETRY, launch_geometry(c->stream, cv.d_curve, cv.degree, N, e.geom));
+                STAGE(c, FHW_STAGE_KRESS, launch_kress(c->stream, N, e.R, e.logtab));
+                git = c->geo_cache.emplace(std::make_pair(fp, N), ge).first;
+                c->geo_cache_bytes += (size_t)N * 11 * 8;
+            }
+            c->geoms[fhw_geom_key(k, N)] = git->second.e;
             geo += (size_t)N * 11 * 8;
         }
     }
 
     // chunks over frequencies within the HBM budget
     const int prec = p->precision;
-    plan_ext& px = g_plans[c];
+    plan_ext& px = plan_of(c);
     px.chunks.clear();
     {
         size_t avail = c->budget > geo ? c->budget - geo : 0;
@@ -558,16 +650,19 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         int rc = ensure_workspace(c, need);
         if (rc) return rc;
     }
-    FHW_HIP(c, hipMalloc((void**)&c->d_status, sizeof(int32_t) * 4));
-    FHW_HIP(c, hipMalloc((void**)&c->d_norms, sizeof(double) * 2 * S));
-    FHW_HIP(c, hipMalloc((void**)&c->d_done, sizeof(int32_t) * S));
-    FHW_HIP(c, hipMalloc((void**)&c->d_sweeps, sizeof(int32_t) * S));
-    // residual: per-block partial norms and per-matrix block counters (zero)
-    c->ws_vec = (int64_t)wsV;
-    c->rpart_stride = 2 * (int64_t)maxcount * ((maxN + 63) / 64);
-    FHW_HIP(c, hipMalloc((void**)&c->d_rpart, sizeof(double) * (size_t)c->rpart_stride * FHW_INC_GROUP));
-    FHW_HIP(c, hipMalloc((void**)&c->d_rcount, sizeof(int32_t) * (size_t)maxcount * FHW_INC_GROUP));
-    FHW_HIP(c, hipMemset(c->d_rcount, 0, sizeof(int32_t) * (size_t)maxcount * FHW_INC_GROUP));
+    {
+        int rc = grow_small(c, (void**)&c->d_status, 0, sizeof(int32_t) * 4);
+        if (!rc) rc = grow_small(c, (void**)&c->d_norms, 1, sizeof(double) * 2 * S);
+        if (!rc) rc = grow_small(c, (void**)&c->d_done, 2, sizeof(int32_t) * S);
+        if (!rc) rc = grow_small(c, (void**)&c->d_sweeps, 3, sizeof(int32_t) * S);
+        // residual: per-block partial norms and per-matrix block counters (zero;
+        // every residual launch leaves them zero)
+        c->ws_vec = (int64_t)wsV;
+        c->rpart_stride = 2 * (int64_t)maxcount * ((maxN + 63) / 64);
+        if (!rc) rc = grow_small(c, (void**)&c->d_rpart, 4, sizeof(double) * (size_t)c->rpart_stride * FHW_INC_GROUP);
+        if (!rc) rc = grow_small(c, (void**)&c->d_rcount, 5, sizeof(int32_t) * (size_t)maxcount * FHW_INC_GROUP, true);
+        if (rc) return rc;
+    }
     c->ws_A64 = wsA64; c->ws_A32 = wsA32; c->ws_linv = wsL; c->ws_piv = wsP;
 
     // per-chunk metadata, built once and uploaded into one buffer
@@ -635,8 +730,11 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         oLF = put(lfi.data(), lfi.size() * sizeof(fhw_field_item));
     }
     c->meta_bytes = align_up(host.size(), 64);
-    FHW_HIP(c, hipMalloc(&c->meta, c->meta_bytes));
-    FHW_HIP(c, hipMemcpy(c->meta, host.data(), host.size(), hipMemcpyHostToDevice));
+    {
+        int rc = grow_small(c, &c->meta, 6, c->meta_bytes);
+        if (rc) return rc;
+    }
+    FHW_HIP(c, hipMemcpyAsync(c->meta, host.data(), host.size(), hipMemcpyHostToDevice, c->stream));
     char* mb = (char*)c->meta;
     for (auto& f : fixes) {
         f.ch->d_N = (int32_t*)(mb + f.oN);
@@ -801,7 +899,7 @@ static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const
 // psi_off[F] elements; resid / sweeps [host] are [n_inc][F].
 static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* psi, double* resid,
                       int32_t* sweeps, int32_t compute_resid, bool reuse) {
-    plan_ext& px = g_plans[c];
+    plan_ext& px = plan_of(c);
     const fhw_problem& p = c->prob;
     const int F = (int)c->Ns.size();   // systems (curves x frequencies)
     const bool fp32 = p.precision == FHW_FP32_REFINE;
@@ -879,7 +977,10 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
     }
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     int32_t st[4];
-    FHW_HIP(c, hipMemcpy(st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    {
+        int rc = copy_d2h(c, st, c->d_status, sizeof(st));
+        if (rc) return rc;
+    }
     // factors stay usable when the whole plan fits one chunk and nothing
     // overwrote them (FP64 residuals re-assemble A in place)
     if (!reuse) c->factors_resident = px.chunks.size() == 1 && !(!fp32 && compute_resid) && !st[0];
@@ -889,13 +990,13 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
     const bool have_norms = fp32 || compute_resid;
     if (have_norms) {
         nrm.resize(2 * nf);
-        FHW_HIP(c, hipMemcpy(nrm.data(), d_norms, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost));
+        if (int rc_ = copy_d2h(c, nrm.data(), d_norms, sizeof(double) * 2 * nf)) return rc_;
     }
     if (fp32) {
         done.resize(nf);
         sw.resize(nf);
-        FHW_HIP(c, hipMemcpy(done.data(), d_done, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(sw.data(), d_sw, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
+        if (int rc_ = copy_d2h(c, done.data(), d_done, sizeof(int32_t) * nf)) return rc_;
+        if (int rc_ = copy_d2h(c, sw.data(), d_sw, sizeof(int32_t) * nf)) return rc_;
     }
     for (size_t j = 0; j < nf; ++j) {
         if (resid) resid[j] = have_norms ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
@@ -959,7 +1060,7 @@ int fhw_solve_cached(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* 
 int fhw_factor(fhw_ctx* c) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "factor: no plan");
-    if (g_plans[c].chunks.size() != 1)
+    if (plan_of(c).chunks.size() != 1)
         return fhw_fail(c, FHW_E_NOMEM, "factor: the plan does not fit one workspace chunk");
     return solve_impl(c, nullptr, 0, nullptr, nullptr, nullptr, 0, false);
 }
@@ -974,7 +1075,7 @@ int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* 
     if (s0 < 0 || count < 1 || s0 > S - count) return fhw_fail(c, FHW_E_INVALID, "solve_range: systems out of range");
     int rc = check_incidences(c, inc, n_inc, psi);
     if (rc) return rc;
-    plan_ext& px = g_plans[c];
+    plan_ext& px = plan_of(c);
     const chunk_t& ch = px.chunks[0];
     const fhw_problem& p = c->prob;
     const bool fp32 = p.precision == FHW_FP32_REFINE;
@@ -1007,9 +1108,9 @@ int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* 
         nrm.resize(2 * nf);
         done.resize(nf);
         sw.resize(nf);
-        FHW_HIP(c, hipMemcpy(nrm.data(), d_norms, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(done.data(), d_done, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(sw.data(), d_sw, sizeof(int32_t) * nf, hipMemcpyDeviceToHost));
+        if (int rc_ = copy_d2h(c, nrm.data(), d_norms, sizeof(double) * 2 * nf)) return rc_;
+        if (int rc_ = copy_d2h(c, done.data(), d_done, sizeof(int32_t) * nf)) return rc_;
+        if (int rc_ = copy_d2h(c, sw.data(), d_sw, sizeof(int32_t) * nf)) return rc_;
     }
     for (size_t j = 0; j < nf; ++j) {
         if (resid) resid[j] = fp32 ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
@@ -1055,7 +1156,7 @@ int fhw_solve_range_noalloc(fhw_ctx* c, int32_t s0, int32_t count, const fhw_inc
     int32_t* d_swo = (int32_t*)(sb + o_swo);
     int32_t* d_cnt = (int32_t*)(sb + o_cnt);
     prof_pause pause(c->prof);
-    plan_ext& px = g_plans[c];
+    plan_ext& px = plan_of(c);
     const chunk_t& ch = px.chunks[0];
     const fhw_problem& p = c->prob;
     const bool fp32 = p.precision == FHW_FP32_REFINE;
@@ -1094,7 +1195,7 @@ int fhw_eval_field_curve(fhw_ctx* c, int32_t curve, const void* psi, const doubl
     int rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
     if (rc) return rc;
     FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
-    STAGE(c, FHW_STAGE_FIELD, launch_field(c->stream, g_plans[c].d_field_items + (int64_t)curve * c->prob.F,
+    STAGE(c, FHW_STAGE_FIELD, launch_field(c->stream, plan_of(c).d_field_items + (int64_t)curve * c->prob.F,
                                            c->prob.F, psi, (const double*)c->scratch, N_r, zero_value, V));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
@@ -1117,7 +1218,7 @@ int fhw_eval_field_lowfreq(fhw_ctx* c, const void* psi, const double* obs, int32
     int rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
     if (rc) return rc;
     FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
-    STAGE(c, FHW_STAGE_FIELD, launch_field_list(c->stream, g_plans[c].d_lf_items, c->lf_extra + 1, psi,
+    STAGE(c, FHW_STAGE_FIELD, launch_field_list(c->stream, plan_of(c).d_lf_items, c->lf_extra + 1, psi,
                                                 (const double*)c->scratch, N_r, zero_value, V_sing));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
@@ -1220,8 +1321,8 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
         // pairs kept, for fhw_synth_active_pairs
         std::vector<double> b((size_t)count * N_r);
         unsigned long long mx = 0;
-        FHW_HIP(c, hipMemcpy(b.data(), bnd, 8 * b.size(), hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(&mx, gmax, 8, hipMemcpyDeviceToHost));
+        if (int rc_ = copy_d2h(c, b.data(), bnd, 8 * b.size())) return rc_;
+        if (int rc_ = copy_d2h(c, &mx, gmax, 8)) return rc_;
         double gm;
         memcpy(&gm, &mx, 8);
         int64_t n = 0;
@@ -1447,8 +1548,8 @@ int fhw_synthesize_uniform(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
         // pairs kept, for fhw_synth_active_pairs
         std::vector<double> b((size_t)count * N_r);
         unsigned long long mx = 0;
-        FHW_HIP(c, hipMemcpy(b.data(), bnd, 8 * b.size(), hipMemcpyDeviceToHost));
-        FHW_HIP(c, hipMemcpy(&mx, gmax, 8, hipMemcpyDeviceToHost));
+        if (int rc_ = copy_d2h(c, b.data(), bnd, 8 * b.size())) return rc_;
+        if (int rc_ = copy_d2h(c, &mx, gmax, 8)) return rc_;
         double gm;
         memcpy(&gm, &mx, 8);
         int64_t n = 0;
@@ -1588,7 +1689,7 @@ int fhw_lu_factor(fhw_ctx* c, int32_t batch, const int32_t* N, const int64_t* A_
     FHW_HIP(c, launch_lu_factor(c->stream, bd, sch, d_prefix, A, piv, linv, d_st, precision, &c->prof));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     int32_t st = 0;
-    FHW_HIP(c, hipMemcpy(&st, d_st, 4, hipMemcpyDeviceToHost));
+    if (int rc_ = copy_d2h(c, &st, d_st, 4)) return rc_;
     if (st) return fhw_fail(c, FHW_E_SINGULAR, "lu_factor: exactly zero pivot");
     return FHW_OK;
 }

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,7 +62,16 @@ struct fhw_host_curve {
     int32_t degree = 0;
     std::vector<double> cx, sx, cy, sy;
     double length = 0.0;
-    double* d_curve = nullptr;         // [4][degree+1] on the device
+    double* d_curve = nullptr;         // [4][degree+1] on the device (owned by the curve cache)
+    uint64_t fingerprint = 0;
+};
+// kept across plans (freed by fhw_destroy)
+struct fhw_curve_cache_entry {
+    std::vector<double> coef;          // cx | sx | cy | sy
+    double* d = nullptr;
+};
+struct fhw_geo_cache_entry {
+    fhw_geom_entry e;
 };
 inline int64_t fhw_geom_key(int curve, int N) { return (int64_t)curve * 65536 + N; }
 
@@ -87,7 +97,11 @@ struct fhw_ctx {
     double lf_omega_c = 0.0;
     std::vector<double> lf_mu;         // [lf_M + 1] graded mesh
     std::vector<double> lf_nodes;      // [lf_M lf_N + 1] ascending, 0 .. omega_c
-    std::map<int64_t, fhw_geom_entry> geoms;   // key: curve * 65536 + N
+    std::map<int64_t, fhw_geom_entry> geoms;   // the plan's view, key: curve * 65536 + N
+    std::map<uint64_t, fhw_curve_cache_entry> curve_cache;                       // by curve fingerprint
+    std::map<std::pair<uint64_t, int32_t>, fhw_geo_cache_entry> geo_cache;       // by (fingerprint, N)
+    size_t geo_cache_bytes = 0;
+    size_t small_cap[7] = {0, 0, 0, 0, 0, 0, 0};   // status, norms, done, sweeps, rpart, rcount, meta
 
     // solve workspace (one chunk of frequencies)
     int32_t chunk = 0;                 // max frequencies per chunk
@@ -161,13 +175,24 @@ hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_item
 int64_t assemble_blocks_for(int32_t N);
 // boundary data of one incidence (FHW_INC_PLANE: v = p; FHW_INC_POINT: v = r0)
 // for every item, written at g + g_off
-// True the first time a caller passes `mask` on the current device (kernel
-// attributes such as the dynamic LDS limit are per device).
-inline bool fhw_first_on_device(std::atomic<uint64_t>& mask) {
+// Runs fn once per device for the given mask (kernel attributes such as the
+// dynamic LDS limit are per device).  Contexts on several host threads may
+// race here: the first caller runs fn under a lock, and the others wait for
+// it before they launch.
+inline std::mutex& fhw_attr_mutex() {
+    static std::mutex m;
+    return m;
+}
+template <class Fn>
+inline void fhw_once_on_device(std::atomic<uint64_t>& mask, Fn&& fn) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     const uint64_t bit = 1ull << (dev & 63);
-    return !(mask.fetch_or(bit) & bit);
+    if (mask.load(std::memory_order_acquire) & bit) return;
+    std::lock_guard<std::mutex> lk(fhw_attr_mutex());
+    if (mask.load(std::memory_order_acquire) & bit) return;
+    fn();
+    mask.fetch_or(bit, std::memory_order_release);
 }
 
 // Incidences solved together: one more grid dimension over up to

@@ -155,11 +155,11 @@ static int ilog2(int v) {
 hipError_t launch_frft_setup(hipStream_t s, int L, int NC, int Q, double beta, void* Hs, void* cin, void* cout) {
     if (Q > FRFT_QMAX || Q < 2 || (Q & (Q - 1)) || L > Q || NC < 1 || NC + L - 1 > Q) return hipErrorInvalidValue;
     static std::atomic<uint64_t> attr{0};
-    if (fhw_first_on_device(attr)) {
+    fhw_once_on_device(attr, [&] {
         const int dyn = FRFT_QMAX * (int)sizeof(zd);
         (void)hipFuncSetAttribute((const void*)k_frft_chirp, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_frft, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    }
+    });
     hipLaunchKernelGGL(k_frft_chirp, dim3(1), dim3(FRFT_THREADS), (size_t)Q * sizeof(zd), s, L, NC, Q, ilog2(Q), beta,
                        (zd*)Hs, (zd*)cin, (zd*)cout);
     return hipGetLastError();

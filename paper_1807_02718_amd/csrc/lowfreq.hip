@@ -239,8 +239,9 @@ hipError_t launch_lf_coeffs(hipStream_t s, const void* B, const double* om, int 
     if (n < FC_D || n + FC_C > 2048 || nc < 1 || nc > 32 || K < 1 || N_r < 1) return hipErrorInvalidValue;
     const size_t lds = (size_t)2 * (n + FC_C) * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
-    if (fhw_first_on_device(attr))
+    fhw_once_on_device(attr, [&] {
         (void)hipFuncSetAttribute((const void*)k_lf_coeffs, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    });
     hipLaunchKernelGGL(k_lf_coeffs, dim3((unsigned)(K * N_r)), dim3(LF_THREADS), lds, s, (const zd*)B, om, n_om,
                        (const zd*)V, (const zd*)Vs, N_r, F, jc, n, M, nc, tau0, (zd*)cfs, (zd*)cheb);
     return hipGetLastError();
@@ -253,8 +254,9 @@ hipError_t launch_lf_synth(hipStream_t s, const void* cfs, const void* cheb, con
     const size_t lds = ((size_t)2 * (n + FC_C) + (size_t)M * 3 * (nc + 1)) * sizeof(zd);
     if (lds > 65536) return hipErrorInvalidValue;
     static std::atomic<uint64_t> attr{0};
-    if (fhw_first_on_device(attr))
+    fhw_once_on_device(attr, [&] {
         (void)hipFuncSetAttribute((const void*)k_lf_synth, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    });
     hipLaunchKernelGGL(k_lf_synth, dim3((unsigned)((N_t + LF_THREADS - 1) / LF_THREADS), (unsigned)N_r),
                        dim3(LF_THREADS), lds, s, (const zd*)cfs, (const zd*)cheb, klist, K, mu, taylor, times, N_t,
                        N_r, n, M, nc, h, omega_c, H, tau0, u);

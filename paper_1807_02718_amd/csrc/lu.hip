@@ -804,9 +804,10 @@ void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch) {
 template <typename T>
 static void lu_set_lds_limits() {
     static std::atomic<uint64_t> done{0};
-    if (!fhw_first_on_device(done)) return;
-    (void)hipFuncSetAttribute((const void*)k_lu_diaginv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(inv_lds<T>));
+    fhw_once_on_device(done, [] {
+        (void)hipFuncSetAttribute((const void*)k_lu_diaginv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sizeof(inv_lds<T>));
+    });
 }
 
 // rows per thread R (from the step's largest panel height, for 256 threads)

@@ -348,14 +348,14 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
     if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
-    if (fhw_first_on_device(attr)) {
+    fhw_once_on_device(attr, [&] {
         // solution vectors up to N = 4096 (64 KiB) beside the static LDS
         const int dyn = 4096 * (int)sizeof(zd);
         (void)hipFuncSetAttribute((const void*)k_lu_solve<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_lu_solve<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_lu_solve<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_lu_solve<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    }
+    });
 #define FHW_SOLVE(TT, WW)                                                                                     \
     hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch, grp.n), dim3(WW ? 1024 : SOLVE_THREADS), lds, s, b.N,   \
                        b.a_off, b.piv_off, b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x,  \
@@ -376,11 +376,11 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
     if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
     size_t lds = (size_t)maxN * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
-    if (fhw_first_on_device(attr)) {
+    fhw_once_on_device(attr, [&] {
         const int dyn = 4096 * (int)sizeof(zd);
         (void)hipFuncSetAttribute((const void*)k_residual<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_residual<4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    }
+    });
     // 256-row blocks when they alone give >= 1024 workgroups, else 64-row blocks
     const bool wide = (int64_t)b.batch * grp.n * ((maxN + 255) / 256) >= 1024;
     const int rows = wide ? SOLVE_THREADS : SOLVE_THREADS / 4;

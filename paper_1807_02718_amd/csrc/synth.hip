@@ -302,11 +302,11 @@ hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, co
     while ((1 << logM) < M) ++logM;
     size_t lds = (size_t)M * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
-    if (fhw_first_on_device(attr)) {
+    fhw_once_on_device(attr, [&] {
         // transforms up to 2F = 8192 (128 KiB) beside the static LDS
         (void)hipFuncSetAttribute((const void*)k_fourier_coeffs, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   SYN_MMAX * (int)sizeof(zd));
-    }
+    });
     if (bnd) {
         hipLaunchKernelGGL(k_window_max, dim3(count), dim3(SYN_THREADS), 0, s, (const zd*)B, M, wmax, gwmax);
     }

@@ -25,6 +25,7 @@ FHW_E_HIP = -3
 FHW_E_SINGULAR = -4
 FHW_E_NOCONV = -5
 FHW_E_STATE = -6
+FHW_E_BUSY = -7
 FHW_FP64 = 0
 FHW_FP32_REFINE = 1
 FHW_INC_PLANE = 0
@@ -59,6 +60,12 @@ class fhw_incidence(C.Structure):
 
 class fhw_system(C.Structure):
     _fields_ = [("curve", C.c_int32), ("omega", C.c_double), ("N", C.c_int32)]
+
+
+class fhw_request(C.Structure):
+    _fields_ = [("curve", C.c_int32), ("n_freq", C.c_int32), ("omegas", _dp), ("N", C.c_int32),
+                ("n_inc", C.c_int32), ("inc", C.POINTER(fhw_incidence)), ("psi", C.c_void_p), ("resid", _dp),
+                ("sweeps", C.POINTER(C.c_int32))]
 
 
 class FhwError(RuntimeError):
@@ -103,6 +110,11 @@ def _load():
         "fhw_window_spectra": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), i64, i32, vp],
         "fhw_fourier_coefficients": [vp, vp, i32, vp, i32, C.c_double, vp],
         "fhw_hankel01": [vp, vp, i64, vp],
+        "fhw_server_create": [C.POINTER(vp), C.POINTER(fhw_curve), i32, C.POINTER(fhw_problem), i32, sz, sz],
+        "fhw_server_submit": [vp, C.POINTER(fhw_request), p_i64],
+        "fhw_server_poll": [vp, i64, i32, p_i32],
+        "fhw_server_stats": [vp, p_i64, _dp],
+        "fhw_server_destroy": [vp],
         "fhw_profile": [vp, i32],
         "fhw_profile_read": [vp, _dp, p_i64],
     }
@@ -120,7 +132,8 @@ EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_p
             "fhw_plan_systems", "fhw_factor", "fhw_solve_range", "fhw_solve_range_noalloc",
             "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_eval_field_lowfreq", "fhw_synthesize", "fhw_synthesize_lowfreq", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
-            "fhw_profile", "fhw_profile_read")
+            "fhw_profile", "fhw_profile_read", "fhw_server_create", "fhw_server_submit", "fhw_server_poll",
+            "fhw_server_stats", "fhw_server_destroy")
 STAGES = ("geometry", "kress", "assemble", "lu_panel", "lu_diaginv", "lu_swap", "lu_trsm", "lu_update", "solve",
           "residual", "field", "spectra", "coeffs", "synth")
 
@@ -478,6 +491,86 @@ class Context:
         h = torch.empty((z.numel(), 2), dtype=torch.complex128, device=self.device)
         self._check(_lib.fhw_hankel01(self._h, _ptr(z), int(z.numel()), _ptr(h)))
         return h
+
+
+class Server:
+    """fhw_server: continuous batching of solve requests over worker slots,
+    each with its own stream and workspace (see include/fhw.h)."""
+
+    def __init__(self, curves, precision="fp32_refine", refine_tol=1e-12, refine_max=10, c=1.0, slots=2,
+                 hbm_budget_bytes=0, queue_limit_bytes=0, device=None):
+        if device is not None:
+            torch.cuda.set_device(device)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._cv = [[np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (cv.cx, cv.sx, cv.cy, cv.sy)]
+                    for cv in curves]
+        arr = (fhw_curve * len(curves))()
+        for k, vs in enumerate(self._cv):
+            arr[k] = fhw_curve(len(vs[0]) - 1, *[v.ctypes.data_as(_dp) for v in vs])
+        pr = fhw_problem()
+        pr.c = float(c)
+        pr.precision = {"fp64": FHW_FP64, "fp32_refine": FHW_FP32_REFINE}[precision]
+        pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
+        h = C.c_void_p()
+        rc = _lib.fhw_server_create(C.byref(h), arr, len(curves), C.byref(pr), int(slots), int(hbm_budget_bytes),
+                                    int(queue_limit_bytes))
+        if rc != FHW_OK:
+            raise FhwError(rc, "fhw_server_create failed")
+        self._h = h
+        self._keep = {}   # ticket -> buffers that must outlive the request
+
+    def submit(self, curve, omegas, N, incidences, psi=None):
+        """Queue a request; returns (ticket, psi [n_inc, n_freq N], resid
+        [n_inc, n_freq], sweeps) with psi and resid filled on completion, or
+        raises FhwError (code FHW_E_BUSY when the queue is full)."""
+        om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+        kinds = {"plane": FHW_INC_PLANE, "point": FHW_INC_POINT}
+        n = len(incidences)
+        inc = (fhw_incidence * max(n, 1))()
+        for q, (kind, v) in enumerate(incidences):
+            inc[q].kind = kinds[kind] if isinstance(kind, str) else int(kind)
+            inc[q].v[0], inc[q].v[1] = float(v[0]), float(v[1])
+        if psi is None:
+            psi = torch.empty((max(n, 1), len(om) * int(N)), dtype=torch.complex128, device=self.device)
+        resid = np.zeros((max(n, 1), len(om)))
+        sweeps = np.zeros((max(n, 1), len(om)), dtype=np.int32)
+        req = fhw_request(int(curve), len(om), om.ctypes.data_as(_dp), int(N), n, inc, _ptr(psi).value,
+                          resid.ctypes.data_as(_dp), sweeps.ctypes.data_as(C.POINTER(C.c_int32)))
+        t = C.c_int64()
+        rc = _lib.fhw_server_submit(self._h, C.byref(req), C.byref(t))
+        if rc != FHW_OK:
+            raise FhwError(rc, "fhw_server_submit refused the request" if rc == FHW_E_BUSY else "bad request")
+        self._keep[t.value] = (psi, resid, sweeps)
+        return t.value, psi, resid, sweeps
+
+    def poll(self, ticket, wait=False):
+        """1 while pending, else the request's result code (reported once)."""
+        st = C.c_int32()
+        rc = _lib.fhw_server_poll(self._h, int(ticket), int(bool(wait)), C.byref(st))
+        if rc != FHW_OK:
+            raise FhwError(rc, "unknown ticket")
+        if st.value != 1:
+            self._keep.pop(int(ticket), None)
+        return st.value
+
+    def stats(self):
+        counts = np.zeros(5, dtype=np.int64)
+        busy = C.c_double()
+        _lib.fhw_server_stats(self._h, counts.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(busy))
+        return dict(rounds=int(counts[0]), done=int(counts[1]), refused=int(counts[2]), systems=int(counts[3]),
+                    waiting=int(counts[4]), busy_s=busy.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fhw_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fhw_version():
