@@ -352,6 +352,7 @@ def serve_server(fhw, torch, Wk, rates, duration, precision, slots, queue_gb):
                     "goodput_req_s": len(lat) / wall, "rhs_solves_per_s": solves / wall,
                     "p50_ms": q(lat, 50), "p99_ms": q(lat, 99), "rounds": rounds,
                     "mean_requests_per_round": len(lat) / max(rounds, 1),
+                    "cache_hits": st["cache_hits"] - base["cache_hits"],
                     "slot_busy": (st["busy_s"] - base["busy_s"]) / (slots * wall), "wall_s": wall})
         print(json.dumps(out[-1]), file=sys.stderr, flush=True)
     print(json.dumps({"metric": "serving: per-request latency (p50/p99) and goodput under Poisson arrivals",

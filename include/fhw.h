@@ -272,7 +272,9 @@ typedef struct fhw_server fhw_server;
  * takes every waiting request in arrival order while their matrices fit its
  * share, plans all their systems at once (fhw_plan_systems), factors them in
  * shared launches (fhw_factor) and solves each request on the resident
- * factors (fhw_solve_range), which completes it.  Requests that arrive while
+ * factors (fhw_solve_range), which completes it; a slot keeps its last
+ * round's factors resident and serves a later round whose systems are all
+ * among them without planning or factoring again.  Requests that arrive while
  * slots are busy wait for the next free slot; the slots' rounds overlap on
  * the device.  prob supplies c, precision, refine_tol, refine_max (the other
  * fields are not used).  queue_limit_bytes (0 = the whole budget): a request
@@ -289,9 +291,12 @@ int fhw_server_submit(fhw_server* server, const fhw_request* req, int64_t* ticke
  * finished ticket is reported once and then forgotten (FHW_E_INVALID after).
  * Thread-safe. */
 int fhw_server_poll(fhw_server* server, int64_t ticket, int32_t wait, int32_t* status);
-/* counts [host] int64[5]: rounds, requests finished, requests refused, systems
- * solved, requests waiting; busy_s [host, optional]: the slots' summed round
- * time in seconds. */
+/* counts [host] int64[6]: rounds, requests finished, requests refused, systems
+ * factored, requests waiting, requests served from a slot's resident factors
+ * (no plan or factorization: every system of their round, (curve, omega, N)
+ * at the server's precision, was among the factors the slot kept from its
+ * previous round); busy_s [host, optional]: the slots' summed round time in
+ * seconds. */
 int fhw_server_stats(fhw_server* server, int64_t* counts, double* busy_s);
 /* Finishes the waiting requests, stops the slots and frees everything. */
 int fhw_server_destroy(fhw_server* server);

@@ -9,14 +9,20 @@
 // While one slot plans, factors or solves, the others take the requests that
 // arrived meanwhile, so rounds overlap on the device.  Submission refuses a
 // request (FHW_E_BUSY) while the waiting requests already hold more matrix
-// bytes than the queue limit.  Host logic only: the arithmetic is the
+// bytes than the queue limit.  Each slot keeps the factors of its last round
+// resident: a round whose requests' systems (curve, frequency, N) are all
+// among them, each request's in order, is solved on them with no new plan or
+// factorization (a one-round factor cache per slot; the precision is the
+// server's).  Host logic only: the arithmetic is the
 // library's kernels, through the same calls as a single caller would make.
 #include <math.h>
+#include <string.h>
 
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -58,7 +64,7 @@ struct fhw_server {
     std::vector<hipStream_t> streams;
     std::vector<fhw_ctx*> ctxs;
     // statistics
-    int64_t rounds = 0, done = 0, refused = 0, systems = 0;
+    int64_t rounds = 0, done = 0, refused = 0, systems = 0, cache_hits = 0;
     double busy_s = 0.0;
 
     ~fhw_server() {
@@ -77,10 +83,31 @@ size_t request_bytes(const fhw_problem& p, int N, size_t n_freq) {
     return b * n_freq;
 }
 
+// key of a system in a slot's resident factors: (curve, frequency bits, N)
+struct sys_key {
+    int32_t curve;
+    uint64_t omega;
+    int32_t N;
+    bool operator<(const sys_key& o) const {
+        if (curve != o.curve) return curve < o.curve;
+        if (omega != o.omega) return omega < o.omega;
+        return N < o.N;
+    }
+};
+sys_key key_of(int32_t curve, double omega, int32_t N) {
+    sys_key k{curve, 0, N};
+    memcpy(&k.omega, &omega, sizeof(double));
+    return k;
+}
+
 void worker(fhw_server* S, fhw_ctx* ctx) {
     (void)hipSetDevice(S->device);
     std::vector<srv_request*> batch;
     std::vector<fhw_system> sys;
+    std::vector<int32_t> first;
+    // the factor cache of this slot: the systems of its last round, whose
+    // factors stay resident until the next round needs a new plan
+    std::map<sys_key, int32_t> resident;
     for (;;) {
         batch.clear();
         {
@@ -98,20 +125,46 @@ void worker(fhw_server* S, fhw_ctx* ctx) {
             }
         }
         const auto t0 = std::chrono::steady_clock::now();
-        sys.clear();
-        for (srv_request* r : batch)
-            for (double om : r->omegas) sys.push_back(fhw_system{r->curve, om, r->N});
-        int rc = fhw_plan_systems(ctx, S->curves.data(), (int32_t)S->curves.size(), sys.data(), (int32_t)sys.size(),
+        // every request's systems already resident, in order: no plan, no factorization
+        first.assign(batch.size(), -1);
+        bool hit = !resident.empty();
+        for (size_t b = 0; hit && b < batch.size(); ++b) {
+            const srv_request* r = batch[b];
+            auto it = resident.find(key_of(r->curve, r->omegas[0], r->N));
+            if (it == resident.end()) { hit = false; break; }
+            first[b] = it->second;
+            for (size_t j = 1; j < r->omegas.size(); ++j) {
+                auto jt = resident.find(key_of(r->curve, r->omegas[j], r->N));
+                if (jt == resident.end() || jt->second != first[b] + (int32_t)j) { hit = false; break; }
+            }
+        }
+        int rc = FHW_OK;
+        int64_t n_sys = 0;
+        if (!hit) {
+            sys.clear();
+            for (srv_request* r : batch)
+                for (double om : r->omegas) sys.push_back(fhw_system{r->curve, om, r->N});
+            resident.clear();
+            rc = fhw_plan_systems(ctx, S->curves.data(), (int32_t)S->curves.size(), sys.data(), (int32_t)sys.size(),
                                   &S->prob, nullptr);
-        if (rc == FHW_OK) rc = fhw_factor(ctx);
-        int32_t s0 = 0;
-        for (srv_request* r : batch) {
+            if (rc == FHW_OK) rc = fhw_factor(ctx);
+            int32_t s0 = 0;
+            for (size_t b = 0; b < batch.size(); ++b) {
+                first[b] = s0;
+                s0 += (int32_t)batch[b]->omegas.size();
+            }
+            if (rc == FHW_OK)
+                for (int32_t q = 0; q < (int32_t)sys.size(); ++q)
+                    resident.emplace(key_of(sys[q].curve, sys[q].omega, sys[q].N), q);
+            n_sys = (int64_t)sys.size();
+        }
+        for (size_t b = 0; b < batch.size(); ++b) {
+            srv_request* r = batch[b];
             const int32_t cnt = (int32_t)r->omegas.size();
             int rr = rc;
             if (rr == FHW_OK)
-                rr = fhw_solve_range(ctx, s0, cnt, r->inc.data(), (int32_t)r->inc.size(), r->psi, r->resid,
+                rr = fhw_solve_range(ctx, first[b], cnt, r->inc.data(), (int32_t)r->inc.size(), r->psi, r->resid,
                                      r->sweeps);
-            s0 += cnt;
             std::lock_guard<std::mutex> lk(S->mu);
             r->status = rr;
             if (rr != FHW_OK) r->err = fhw_last_error(ctx);
@@ -121,7 +174,8 @@ void worker(fhw_server* S, fhw_ctx* ctx) {
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         std::lock_guard<std::mutex> lk(S->mu);
         S->rounds += 1;
-        S->systems += (int64_t)sys.size();
+        S->systems += n_sys;
+        if (hit) S->cache_hits += (int64_t)batch.size();
         S->busy_s += dt;
     }
 }
@@ -241,6 +295,7 @@ int fhw_server_stats(fhw_server* S, int64_t* counts, double* busy_s) {
     counts[2] = S->refused;
     counts[3] = S->systems;
     counts[4] = (int64_t)S->queue.size();
+    counts[5] = S->cache_hits;
     if (busy_s) *busy_s = S->busy_s;
     return FHW_OK;
 }

@@ -554,11 +554,11 @@ class Server:
         return st.value
 
     def stats(self):
-        counts = np.zeros(5, dtype=np.int64)
+        counts = np.zeros(6, dtype=np.int64)
         busy = C.c_double()
         _lib.fhw_server_stats(self._h, counts.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(busy))
         return dict(rounds=int(counts[0]), done=int(counts[1]), refused=int(counts[2]), systems=int(counts[3]),
-                    waiting=int(counts[4]), busy_s=busy.value)
+                    waiting=int(counts[4]), cache_hits=int(counts[5]), busy_s=busy.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -130,3 +130,32 @@ def test_server_busy_when_the_queue_is_full(fhw):
         assert e.value.code == fhw.FHW_E_INVALID
     finally:
         srv.close()
+
+
+def test_server_factor_cache(fhw):
+    """A request repeated after its round (same curve, frequencies and N, new
+    right-hand sides) is served from the slot's resident factors: no new
+    factorization, and the densities equal those of a fresh solve."""
+    say("server: factor cache")
+    k, oms, N = 0, [25.0, 26.0, 27.0], 256
+    inc1, inc2 = _incs(3, 11), _incs(10, 12)
+    c = fhw.Context()
+    try:
+        c.plan_systems(CURVES, [(k, om, N) for om in oms], precision="fp32_refine", refine_tol=1e-13)
+        c.factor()
+        ref2 = c.solve_range(0, len(oms), inc2)[0].cpu().numpy()
+    finally:
+        c.close()
+    srv = fhw.Server(CURVES, precision="fp32_refine", refine_tol=1e-13, slots=1)
+    try:
+        t1, *_ = srv.submit(k, oms, N, inc1)
+        assert srv.poll(t1, wait=True) == fhw.FHW_OK
+        s1 = srv.stats()
+        t2, psi2, res2, _ = srv.submit(k, oms, N, inc2)
+        assert srv.poll(t2, wait=True) == fhw.FHW_OK
+        s2 = srv.stats()
+        say("stats after the first", s1, "after the repeat", s2)
+        assert s2["cache_hits"] == s1["cache_hits"] + 1 and s2["systems"] == s1["systems"]
+        assert relmax(psi2.cpu().numpy(), ref2) < 1e-10 and np.all(res2 <= 1e-13)
+    finally:
+        srv.close()
