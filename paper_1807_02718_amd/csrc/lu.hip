@@ -19,6 +19,7 @@
 // later pairs; the solves replay the pivots pair by pair.
 #include "fhw_device.h"
 #include "fhw_internal.h"
+#include "gemm_table.h"
 #include "panel_table.h"
 
 #define NB FHW_LU_NB
@@ -468,8 +469,22 @@ __global__ __launch_bounds__(256) void k_lu_swap(int k0, int cbeg, int ccount, c
 // quarter = 2x2 MFMA 16x16 blocks.
 // ---------------------------------------------------------------------------
 #define GT 64
-#define GK 16   // K-chunk staged through LDS (32 measured slower: fewer workgroups fit)
 #define GPAD 1
+
+// K-chunk staged through LDS and workgroups per CU (the launch-bounds hint)
+// per precision, from the project's autotuner (gemm_table.h)
+template <typename T>
+struct gemm_cfg;
+template <>
+struct gemm_cfg<float> {
+    static constexpr int GK = FHW_GEMM_GK_F32, OCC = FHW_GEMM_OCC_F32;
+};
+template <>
+struct gemm_cfg<double> {
+    static constexpr int GK = FHW_GEMM_GK_F64, OCC = FHW_GEMM_OCC_F64;
+};
+template <typename T>
+constexpr int gk_v = gemm_cfg<T>::GK;
 
 template <typename T>
 struct mfma_traits;
@@ -513,12 +528,12 @@ __device__ __forceinline__ int xcd_tile(int w, int G) {
     return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
-// Stage one GK-deep chunk of the L and U operands in registers (real and
-// imaginary parts apart): L (k = tid/64 + 4p, i = tid%64), U (j = tid/GK +
-// (256/GK) p, k = tid%GK), p < GK/4.
+// Stage one GK-deep chunk (GK = gk_v<T>) of the L and U operands in registers
+// (real and imaginary parts apart): L (k = tid/64 + 4p, i = tid%64), U (j =
+// tid/GK + (256/GK) p, k = tid%GK), p < GK/4.
 template <typename T>
 struct gemm_stage {
-    T lr[GK / 4], li[GK / 4], ur[GK / 4], ui[GK / 4];
+    T lr[gk_v<T> / 4], li[gk_v<T> / 4], ur[gk_v<T> / 4], ui[gk_v<T> / 4];
 };
 
 template <typename T, bool SUB>
@@ -526,7 +541,7 @@ __device__ __forceinline__ void gemm_load_chunk(gemm_stage<T>& g, int kb, int ti
                                                 const cpx<T>* __restrict__ Lop, int ldl,
                                                 const cpx<T>* __restrict__ Uop, int N) {
 #pragma unroll
-    for (int pass = 0; pass < GK / 4; ++pass) {
+    for (int pass = 0; pass < gk_v<T> / 4; ++pass) {
         const int k = (tid >> 6) + 4 * pass;
         const int i = tid & 63;
         const int kk = kb + k;
@@ -551,9 +566,9 @@ __device__ __forceinline__ void gemm_load_chunk(gemm_stage<T>& g, int kb, int ti
         g.li[pass] = vi;
     }
 #pragma unroll
-    for (int pass = 0; pass < GK / 4; ++pass) {
-        const int j = tid / GK + (256 / GK) * pass;
-        const int k = tid % GK;
+    for (int pass = 0; pass < gk_v<T> / 4; ++pass) {
+        const int j = tid / gk_v<T> + (256 / gk_v<T>) * pass;
+        const int k = tid % gk_v<T>;
         T vr = (T)0, vi = (T)0;
         if ((kb + k < nb) && (j < ncols)) {
             const cpx<T> v = Uop[(int64_t)j * N + kb + k];
@@ -566,13 +581,15 @@ __device__ __forceinline__ void gemm_load_chunk(gemm_stage<T>& g, int kb, int ti
 }
 
 template <typename T, int NBUF>
-__device__ __forceinline__ void gemm_store_chunk(cpx<T> (&Ls)[NBUF][GK][GT + GPAD], cpx<T> (&Us)[NBUF][GK][GT + GPAD],
+__device__ __forceinline__ void gemm_store_chunk(cpx<T> (&Ls)[NBUF][gk_v<T>][GT + GPAD],
+                                                 cpx<T> (&Us)[NBUF][gk_v<T>][GT + GPAD],
                                                  const gemm_stage<T>& g, int buf, int tid) {
 #pragma unroll
-    for (int pass = 0; pass < GK / 4; ++pass) Ls[buf][(tid >> 6) + 4 * pass][tid & 63] = cmk(g.lr[pass], g.li[pass]);
+    for (int pass = 0; pass < gk_v<T> / 4; ++pass)
+        Ls[buf][(tid >> 6) + 4 * pass][tid & 63] = cmk(g.lr[pass], g.li[pass]);
 #pragma unroll
-    for (int pass = 0; pass < GK / 4; ++pass)
-        Us[buf][tid % GK][tid / GK + (256 / GK) * pass] = cmk(g.ur[pass], g.ui[pass]);
+    for (int pass = 0; pass < gk_v<T> / 4; ++pass)
+        Us[buf][tid % gk_v<T>][tid / gk_v<T> + (256 / gk_v<T>) * pass] = cmk(g.ur[pass], g.ui[pass]);
 }
 
 // DBUF: double-buffered LDS chunks (next chunk's global loads in flight
@@ -580,7 +597,7 @@ __device__ __forceinline__ void gemm_store_chunk(cpx<T> (&Ls)[NBUF][GK][GT + GPA
 // the single-buffered form is faster (higher occupancy): 96 vs 91 TFLOP/s in
 // FP32, 53.5 vs 42.9 in FP64 on the largest trailing update.
 template <typename T, bool SUB, bool DBUF = false>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0, int K, int roff, int rlim, int coff,
+__global__ __launch_bounds__(256, gemm_cfg<T>::OCC) void k_lu_gemm(int k0, int K, int roff, int rlim, int coff,
                                                  int clim, const int* __restrict__ prefix, int batch,
                                                  const int* __restrict__ Ns, const int64_t* __restrict__ a_off,
                                                  const int64_t* __restrict__ linv_off, cpx<T>* __restrict__ Abase,
@@ -619,8 +636,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
     const cpx<T>* Uop = A + (int64_t)col0 * N + k0;   // U (k, j) at j N + k0 + k
     cpx<T>* C = A + (int64_t)col0 * N + row0;
     constexpr int NBUF = DBUF ? 2 : 1;
-    __shared__ cpx<T> Ls[NBUF][GK][GT + GPAD];
-    __shared__ cpx<T> Us[NBUF][GK][GT + GPAD];
+    __shared__ cpx<T> Ls[NBUF][gk_v<T>][GT + GPAD];
+    __shared__ cpx<T> Us[NBUF][gk_v<T>][GT + GPAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
@@ -639,7 +656,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
         }
     gemm_stage<T> stg;
 
-    const int nchunks = (nb + GK - 1) / GK;
+    const int nchunks = (nb + gk_v<T> - 1) / gk_v<T>;
     if (DBUF) {
         gemm_load_chunk<T, SUB>(stg, 0, tid, nrows, ncols, nb, Lop, ldl, Uop, N);
         gemm_store_chunk<T, NBUF>(Ls, Us, stg, 0, tid);
@@ -649,14 +666,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void k_lu_gemm(int k0,
         const int buf = DBUF ? (ch & 1) : 0;
         const bool more = ch + 1 < nchunks;
         if (DBUF) {
-            if (more) gemm_load_chunk<T, SUB>(stg, (ch + 1) * GK, tid, nrows, ncols, nb, Lop, ldl, Uop, N);
+            if (more) gemm_load_chunk<T, SUB>(stg, (ch + 1) * gk_v<T>, tid, nrows, ncols, nb, Lop, ldl, Uop, N);
         } else {
-            gemm_load_chunk<T, SUB>(stg, ch * GK, tid, nrows, ncols, nb, Lop, ldl, Uop, N);
+            gemm_load_chunk<T, SUB>(stg, ch * gk_v<T>, tid, nrows, ncols, nb, Lop, ldl, Uop, N);
             gemm_store_chunk<T, NBUF>(Ls, Us, stg, 0, tid);
             __syncthreads();
         }
 #pragma unroll
-        for (int kk = 0; kk < GK; kk += 4) {
+        for (int kk = 0; kk < gk_v<T>; kk += 4) {
             const int kr = kk + (lane >> 4);
             cpx<T> uf[2], lf[2];
 #pragma unroll

@@ -4,6 +4,11 @@ per SIMD) per precision, workgroup size and rows per thread.
     python -m paper_1807_02718_amd.tune build     # CPU: variant libraries
     python -m paper_1807_02718_amd.tune measure   # GPU: time them
     python -m paper_1807_02718_amd.tune write     # CPU: csrc/panel_table.h
+    python -m paper_1807_02718_amd.tune gemm-build | gemm-measure | gemm-write
+        the same for the GEMM kernel (k_lu_gemm): K-chunk and workgroups per CU
+        per precision, timed as the update + TRSM stages of the kite batch at
+        N = 1024 (both precisions) and of 16 star curves x 256 frequencies
+        (FP64), written to csrc/gemm_table.h
 
 Each variant differs from the current table (csrc/panel_table.h) in one case,
 set to one candidate whose registers fit without spilling (checked from the
@@ -187,6 +192,175 @@ def write():
     print("wrote", TABLE)
 
 
+# ---------------------------------------------------------------------------
+# GEMM tile: K-chunk GK and workgroups per CU of k_lu_gemm, per precision
+# ---------------------------------------------------------------------------
+GEMM_TABLE = os.path.join(CSRC, "gemm_table.h")
+GEMM_TUNE = os.path.join(HERE, "_tune_gemm")
+GEMM_CANDIDATES = {"F32": [(gk, occ) for gk in (8, 16, 32) for occ in (2, 3, 4, 5)],
+                   "F64": [(gk, occ) for gk in (8, 16, 32) for occ in (1, 2, 3, 4)]}
+
+
+def read_gemm_table(path=GEMM_TABLE):
+    src = open(path).read()
+    out = {}
+    for p in ("F32", "F64"):
+        gk = int(re.search(rf"#define FHW_GEMM_GK_{p} (\d+)", src).group(1))
+        occ = int(re.search(rf"#define FHW_GEMM_OCC_{p} (\d+)", src).group(1))
+        out[p] = (gk, occ)
+    return out
+
+
+def write_gemm_table(tab, path=GEMM_TABLE):
+    src = open(GEMM_TABLE).read()
+    for p, (gk, occ) in tab.items():
+        src = re.sub(rf"#define FHW_GEMM_GK_{p} \d+", f"#define FHW_GEMM_GK_{p} {gk}", src)
+        src = re.sub(rf"#define FHW_GEMM_OCC_{p} \d+", f"#define FHW_GEMM_OCC_{p} {occ}", src)
+    open(path, "w").write(src)
+
+
+def gemm_variants():
+    base = read_gemm_table()
+    out = {"base": (dict(base), None)}
+    for p, cands in GEMM_CANDIDATES.items():
+        for gk, occ in cands:
+            if (gk, occ) == base[p]:
+                continue
+            t = dict(base)
+            t[p] = (gk, occ)
+            out[f"{p}_GK{gk}_OCC{occ}"] = (t, p)
+    return out
+
+
+def _gemm_spill_free(report, p):
+    T = "f" if p == "F32" else "d"
+    blocks = report.split("Function Name: ")
+    seen = False
+    for b in blocks:
+        if b.startswith(f"_Z9k_lu_gemmI{T}"):
+            seen = True
+            m = re.search(r"VGPRs Spill: (\d+)", b)
+            if m is None or int(m.group(1)) != 0:
+                return False
+    return seen
+
+
+def gemm_build(jobs=4):
+    from . import build as B
+    B.build(jobs=jobs)
+    objs = [os.path.join(B.BUILD, s.replace(".hip", ".o")) for s in B.SOURCES if s != "lu.hip"]
+    shutil.rmtree(GEMM_TUNE, ignore_errors=True)
+    os.makedirs(GEMM_TUNE)
+
+    def one(item):
+        name, (tab, p) = item
+        d = os.path.join(GEMM_TUNE, name)
+        os.makedirs(os.path.join(d, "paper_1807_02718_amd"))
+        shutil.copy(os.path.join(CSRC, "lu.hip"), d)
+        shutil.copy(TABLE, d)
+        shutil.copy(GEMM_TABLE, d)
+        write_gemm_table(tab, os.path.join(d, "gemm_table.h"))
+        o = os.path.join(d, "lu.o")
+        r = subprocess.run([B.HIPCC, *B.FLAGS, "-I", CSRC, "-c", os.path.join(d, "lu.hip"), "-o", o,
+                            "-Rpass-analysis=kernel-resource-usage"], capture_output=True, text=True)
+        if r.returncode:
+            return name, False, r.stderr[-500:]
+        if p is not None and not _gemm_spill_free(r.stderr, p):
+            shutil.rmtree(d)
+            return name, False, "spills"
+        r = subprocess.run([B.HIPCC, "-shared", "-fPIC", f"--offload-arch={B.ARCH}", *objs, o, "-o",
+                            os.path.join(d, "paper_1807_02718_amd", "libfhw.so")], capture_output=True, text=True)
+        os.remove(o)
+        for f in ("__init__.py", "fhw.py"):
+            shutil.copy(os.path.join(HERE, f), os.path.join(d, "paper_1807_02718_amd", f))
+        json.dump(tab, open(os.path.join(d, "table.json"), "w"))
+        return name, r.returncode == 0, r.stderr[-300:]
+
+    with ThreadPoolExecutor(jobs) as ex:
+        for name, ok, msg in ex.map(one, gemm_variants().items()):
+            print(f"{name}: {'ok' if ok else 'skipped (' + msg.strip()[:80] + ')'}", flush=True)
+
+
+_GEMM_TIMER = r"""
+import json, sys, numpy as np
+sys.path.insert(0, sys.argv[1]); sys.path.insert(1, sys.argv[2])
+import torch
+from paper_1807_02718_amd import fhw
+import workloads as Wk
+out = {}
+wl = Wk.kite_n1024()
+for prec in ("fp32_refine", "fp64"):
+    ctx = fhw.Context()
+    ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=prec, refine_tol=1e-12, refine_max=10, direction=wl.direction)
+    psi = torch.empty(int(ctx.psi_off[-1]), dtype=torch.complex128, device="cuda")
+    ctx.solve_densities(psi)
+    ts = []
+    for _ in range(3):
+        ctx.profile(True)
+        ctx.solve_densities(psi)
+        pr = ctx.profile_read()
+        ts.append(pr["lu_update"][0] + pr["lu_trsm"][0])
+        ctx.profile(False)
+    ctx.close()
+    out["kite_" + prec] = float(np.median(ts))
+sb = Wk.star_batch(n_curves=16)
+ctx = fhw.Context()
+ctx.plan(sb["curves"], sb["W"], sb["F"], precision="fp64", direction=sb["direction"], **sb["rule"])
+psi = torch.empty(int(ctx.psi_off[-1]), dtype=torch.complex128, device="cuda")
+ctx.solve_densities(psi)
+ts = []
+for _ in range(2):
+    ctx.profile(True)
+    ctx.solve_densities(psi)
+    pr = ctx.profile_read()
+    ts.append(pr["lu_update"][0] + pr["lu_trsm"][0])
+    ctx.profile(False)
+ctx.close()
+out["stars16_fp64"] = float(np.median(ts))
+print(json.dumps(out), flush=True)
+"""
+
+
+def gemm_measure():
+    root = os.path.dirname(HERE)
+    res = {}
+    for name in sorted(os.listdir(GEMM_TUNE)):
+        d = os.path.join(GEMM_TUNE, name)
+        if not os.path.isfile(os.path.join(d, "table.json")):
+            continue
+        print("measuring", name, flush=True)
+        r = subprocess.run([sys.executable, "-c", _GEMM_TIMER, d, root], capture_output=True, text=True,
+                           timeout=300)
+        line = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+        if r.returncode or not line:
+            print(f"{name}: failed ({r.stderr.strip()[-200:]})", flush=True)
+            continue
+        res[name] = {"table": json.load(open(os.path.join(d, "table.json"))), "ms": json.loads(line[-1])}
+        print(name, res[name]["ms"], flush=True)
+    json.dump(res, open(os.path.join(GEMM_TUNE, "results.json"), "w"), indent=1)
+
+
+def gemm_write(results=None):
+    res = json.load(open(results or os.path.join(GEMM_TUNE, "results.json")))
+    base = res["base"]
+    tab = {k: tuple(v) for k, v in base["table"].items()}
+    for p in ("F32", "F64"):
+        keys = ["kite_fp32_refine"] if p == "F32" else ["kite_fp64", "stars16_fp64"]
+
+        def cost(v):
+            return sum(v["ms"][k] for k in keys)
+
+        best, best_ms = tab[p], cost(base)
+        for vn, v in res.items():
+            if vn.startswith(p + "_GK") and cost(v) < best_ms * 0.99:
+                best, best_ms = tuple(v["table"][p]), cost(v)
+        if best != tab[p]:
+            print(f"{p}: {tab[p]} -> {best} ({cost(base):.3f} -> {best_ms:.3f} ms update + TRSM)")
+        tab[p] = best
+    write_gemm_table(tab)
+    print("wrote", GEMM_TABLE)
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else ""
     if cmd == "build":
@@ -195,6 +369,12 @@ if __name__ == "__main__":
         measure()
     elif cmd == "write":
         write()
+    elif cmd == "gemm-build":
+        gemm_build(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+    elif cmd == "gemm-measure":
+        gemm_measure()
+    elif cmd == "gemm-write":
+        gemm_write(sys.argv[2] if len(sys.argv) > 2 else None)
     else:
         print(__doc__)
         sys.exit(2)
