@@ -36,7 +36,8 @@ __all__ = [
     "scaled_convolution_fast", "synthesize_uniform",
     "graded_mesh", "clenshaw_curtis_nodes", "lowfreq_frequencies", "chebyshev_moments",
     "fcc_integral", "gram_basis", "fc_gram_tables", "fc_continuation", "fc_coefficients",
-    "fc_integral", "synthesize_lowfreq",
+    "fc_integral", "synthesize_lowfreq", "boundary_window_transforms", "synthesize_windowed",
+    "run_general",
 ]
 
 
@@ -653,6 +654,81 @@ def synthesize_lowfreq(V_full, V_sing, signal, H, tau0, W, F, jc, M, n, q, times
                 I = I + fcc_integral(Bn[j] * V_sing[r, j], mu[j], mu[j + 1], n, tp)
             u[r] += I.real / np.pi
     return u
+
+
+# ---------------------------------------------------------------------------
+# O14. General incident fields (eq. bkdef2): windowed boundary data per node
+# ---------------------------------------------------------------------------
+def boundary_window_transforms(samples, t0, dt, H, ks, omega):
+    """The recentred transforms of the windowed boundary data of eq. bkdef2,
+        B_k(x_i, w) = int w(t) b(x_i, t + s_k) e^{i w t} dt,
+    by the rectangle rule on the samples b(x_i, t0 + n dt) (the integrand
+    vanishes with all derivatives at the ends), for windows ks and
+    frequencies omega.  samples: [N][n_t] real.  Returns [K][F][N] complex."""
+    samples = np.asarray(samples, dtype=np.float64)
+    t = t0 + dt * np.arange(samples.shape[1])
+    out = np.zeros((len(ks), len(omega), samples.shape[0]), dtype=np.complex128)
+    for q, k in enumerate(ks):
+        tau = t - window_center(k, H)
+        wk = window(tau, H)
+        sel = wk != 0.0
+        out[q] = dt * (np.exp(1j * np.outer(omega, tau[sel])) @ (wk[sel][:, None] * samples[:, sel].T))
+    return out
+
+
+def synthesize_windowed(V_k, ks, H, tau0, W, times):
+    """u(r, t) = sum_{k in A(t)} Re (W/pi) sum_m c_{k,m}(r) sinc(W (t - s_k -
+    tau0)/pi - m) with c_{k,m}(r) the Fourier coefficients of U_k^slow(r, w)
+    e^{-i w tau0} on [-W, W): the synthesis of synthesize with each window's
+    own frequency-domain field (the windowed boundary data already inside it)
+    instead of B_k^slow(w) V(r, w).  V_k: [K][Nr][2F] on the DFT grid."""
+    K, Nr, M = V_k.shape
+    F = M // 2
+    dw = W / F
+    omega_l = -W + dw * np.arange(M)
+    m = np.arange(-F, F)
+    times = np.asarray(times)
+    u = np.zeros((Nr, len(times)))
+    shift = np.exp(-1j * omega_l * tau0)
+    for q, k in enumerate(ks):
+        sk = window_center(k, H)
+        act = np.abs(times - sk - tau0) <= np.pi / dw
+        if not np.any(act):
+            continue
+        c = fourier_coefficients(V_k[q] * shift[None, :], W)
+        S = np.sinc(W * (times[act][None, :] - sk - tau0) / np.pi - m[:, None])
+        u[:, act] += ((W / np.pi) * (c @ S)).real
+    return u
+
+
+def run_general(curve, W, F, N, b, db, t0, dt, H, tau0, obs, times, c=1.0):
+    """The whole path for a general incident field (eq. bkdef2): boundary
+    data b(x_i, t) = -u_inc and its normal derivative db(x_i, t) = -d_nu
+    u_inc sampled at the N nodes (fixed N at every frequency); per window k
+    the recentred transforms B_k, DB_k at every solve frequency, the density
+    of eq. CFIE_direct with right-hand side DB_k - i eta B_k, its field, and
+    the synthesis of every window's own field (synthesize_windowed).  The
+    zero-frequency sample of each window's field is taken as 0 (the windowed
+    data must have no content at omega = 0).  Returns (u, ks)."""
+    omega, kappa = frequency_grid(W, F, c)
+    eta = coupling(kappa)
+    gm = geometry(curve, N)
+    t_hi = t0 + dt * (np.asarray(b).shape[1] - 1)
+    ks = window_indices(t0, t_hi, H)
+    Bk = boundary_window_transforms(b, t0, dt, H, ks, omega)
+    DBk = boundary_window_transforms(db, t0, dt, H, ks, omega)
+    V_k = np.zeros((len(ks), len(obs), 2 * F), dtype=np.complex128)
+    for j in range(F):
+        A = assemble(gm, kappa[j], eta[j])
+        lu = linalg.lu_factor(A)
+        for q in range(len(ks)):
+            g = DBk[q, j] - 1j * eta[j] * Bk[q, j]
+            psi = linalg.lu_solve(lu, g)
+            Vq = field(gm, psi, kappa[j], obs)
+            if j < F - 1:
+                V_k[q, :, F + 1 + j] = Vq
+            V_k[q, :, F - 1 - j] = np.conj(Vq)
+    return synthesize_windowed(V_k, ks, H, tau0, W, times), ks
 
 
 # ---------------------------------------------------------------------------

@@ -135,6 +135,57 @@ def gaussian_pulse(t0=-1.0, t1=10.0, dt=1.0 / 256, center=4.0, var2=0.5, freq=6.
     return Signal(t0, dt, np.exp(-(t - center) ** 2 / var2) * np.cos(freq * t))
 
 
+def gaussian_pulse_value(t, center=4.0, var2=0.5, freq=6.0):
+    """(f(t), f'(t)) of f(t) = exp(-(t - center)^2 / var2) cos(freq t), any real t."""
+    t = np.asarray(t, dtype=float)
+    e = np.exp(-(t - center) ** 2 / var2)
+    return e * np.cos(freq * t), e * (-2.0 * (t - center) / var2 * np.cos(freq * t) - freq * np.sin(freq * t))
+
+
+def plane_pulses_on_boundary(x, nu, waves, t0, dt, n_t, c=1.0):
+    """Dirichlet data of a general incident field on a boundary: the sum of
+    plane-wave pulses u_inc(r, t) = sum_w amp_w f_w(t - p_w.r / c - delay_w),
+    f_w a gaussian_pulse_value with the wave's (center, var2, freq).  Given
+    points x [N][2] and unit normals nu [N][2], returns the samples
+    b = -u_inc(x_i, t_n) and db = -(nu_i . grad u_inc)(x_i, t_n) at t_n = t0 + n
+    dt, n < n_t, both [n_t][N] (time-major).  waves: sequence of dicts with
+    keys amp, p (unit 2-vector), delay, center, var2, freq."""
+    x = np.asarray(x, dtype=float)
+    nu = np.asarray(nu, dtype=float)
+    t = t0 + dt * np.arange(n_t)
+    b = np.zeros((n_t, len(x)))
+    db = np.zeros((n_t, len(x)))
+    for w in waves:
+        p = np.asarray(w["p"], dtype=float)
+        arg = t[:, None] - (x @ p)[None, :] / c - w["delay"]
+        f, fp = gaussian_pulse_value(arg, w["center"], w["var2"], w["freq"])
+        b -= w["amp"] * f
+        db -= w["amp"] * fp * (-(nu @ p) / c)[None, :]
+    return b, db
+
+
+def two_pulse_field():
+    """A general incident field for tests: two plane pulses from different
+    directions with different carriers and delays (not one plane wave)."""
+    return [dict(amp=1.0, p=(1.0, 0.0), delay=0.0, center=4.0, var2=0.5, freq=12.0),
+            dict(amp=0.7, p=(-0.6, 0.8), delay=5.0, center=4.0, var2=0.3, freq=14.0)]
+
+
+def general_pulses(n_waves: int = 24, t_span: float = 200.0, seed: int = 7):
+    """A long general incident field: n_waves plane pulses with seeded unit
+    directions, delays uniform in [0, t_span], carriers in [8, 30] and
+    envelope widths var2 in [0.2, 1]; sampled on [-3, t_span + 14] (every
+    pulse's envelope is below 1e-20 outside).  Returns dict(waves, t0, t1)."""
+    rng = np.random.default_rng(seed)
+    waves = []
+    for _ in range(n_waves):
+        a = rng.uniform(0.0, 2.0 * np.pi)
+        waves.append(dict(amp=float(rng.uniform(0.5, 1.0)), p=(float(np.cos(a)), float(np.sin(a))),
+                          delay=float(rng.uniform(0.0, t_span)), center=4.0, var2=float(rng.uniform(0.2, 1.0)),
+                          freq=float(rng.uniform(8.0, 30.0))))
+    return dict(waves=waves, t0=-3.0, t1=t_span + 14.0)
+
+
 def chirp_value(t, t_end: float, rate: float = 4000.0, ramp: float = 5.0):
     """Chirp sin(g + g^2/rate), g = 4t + 6 cos(t / sqrt 12) (the paper's chirp
     incidence, Sec. 6.3, for rate = 4000), switched on over [0, ramp] and off
