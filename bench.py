@@ -295,6 +295,79 @@ def uniform_bench(fhw, torch, Wk, reps):
                       "workload": wl.name, "L": 4 * wl.F, "rows": out}), flush=True)
 
 
+def general_bench(fhw, torch, Wk, reps, modes):
+    """General incident fields (eq. bkdef2) on the solve-throughput workload's
+    systems: kite, N = 1024 at F = 1024 frequencies on (0, 69], factored once;
+    24 seeded plane pulses spread over 200 time units (not one plane wave),
+    sampled at the nodes every pi/(4W), H = 10.  Times fhw_solve_general (per
+    window: boundary transforms at every frequency, right-hand sides, solves
+    and refinement on the resident factors; median of reps calls), then the
+    windows' fields at 256 points and their synthesis at 1024 times.  The
+    right-hand-side kernel's roofline: its algorithmic FP64 flops (8 per
+    (window, frequency, node, sample in the window's support): one complex
+    factor times the two real samples of b and its normal derivative) per
+    launch over its average launch time from the stage timers of a profiled
+    call, against the FP64 vector peak."""
+    wl = Wk.kite_n1024()
+    gp = Wk.general_pulses()
+    H, tau0 = wl.H, wl.tau0
+    dt = np.pi / (4.0 * wl.W)
+    n_t = int(np.ceil((gp["t1"] - gp["t0"]) / dt)) + 1
+    k_first, n_win = fhw.window_range(gp["t0"], gp["t0"] + dt * (n_t - 1), H)
+    times = np.linspace(0.0, gp["t1"] + 100.0, 1024)
+    rows = []
+    for precision in modes:
+        ctx = fhw.Context()
+        try:
+            ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=1e-12, refine_max=10)
+            t0 = time.perf_counter()
+            ctx.factor()
+            t_factor = time.perf_counter() - t0
+            g = ctx.geometry(wl.N).cpu().numpy()
+            b, db = Wk.plane_pulses_on_boundary(g[0:2].T, g[7:9].T, gp["waves"], gp["t0"], dt, n_t)
+            b = torch.as_tensor(b, device="cuda")
+            db = torch.as_tensor(db, device="cuda")
+            psi = torch.empty((n_win, int(ctx.psi_off[-1])), dtype=torch.complex128, device="cuda")
+            ts = []
+            for i in range(reps + 1):
+                t0 = time.perf_counter()
+                _, res, sw, _ = ctx.solve_general(b, db, gp["t0"], dt, H, k_first, n_win, psi=psi)
+                if i:
+                    ts.append(time.perf_counter() - t0)
+            ctx.profile(True)
+            ctx.solve_general(b, db, gp["t0"], dt, H, k_first, n_win, psi=psi)
+            pr = ctx.profile_read()
+            ctx.profile(False)
+            t0 = time.perf_counter()
+            V = ctx.eval_field_windows(psi, wl.obs)
+            t_field = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            u = ctx.synthesize_windows(H, tau0, k_first, V, times)
+            t_synth = time.perf_counter() - t0
+            umax = float(u.abs().max())
+        finally:
+            ctx.close()
+        # samples inside each window's support, |t_n - s_k| < H
+        tn = gp["t0"] + dt * np.arange(n_t)
+        n_s = sum(int(np.count_nonzero(np.abs(tn - 1.5 * H * (k - 1.0)) < H))
+                  for k in range(k_first, k_first + n_win))
+        flops = 8.0 * wl.F * wl.N * n_s
+        ms_rhs, launches = pr["assemble"]
+        achieved = flops / launches / (ms_rhs / launches * 1e-3) / 1e12
+        t_solve = float(np.median(ts))
+        rows.append({"precision": precision, "windows": n_win, "samples": n_t, "rhs_per_s": n_win * wl.F / t_solve,
+                     "solve_general_ms": 1e3 * t_solve, "factor_ms": 1e3 * t_factor,
+                     "stage_ms": {k: v[0] for k, v in pr.items() if v[1]},
+                     "rhs_kernel": {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+                                    "frac": achieved / 78.6, "launches": launches, "ms_per_launch": ms_rhs / launches,
+                                    "flops_per_launch": flops / launches},
+                     "max_resid": float(np.max(res)), "max_sweeps": int(np.max(sw)),
+                     "field_ms": 1e3 * t_field, "synth_ms": 1e3 * t_synth, "max_abs_u": umax})
+        print("general", rows[-1], flush=True)
+    print(json.dumps({"metric": "general incident field: right-hand sides solved per second on resident factors",
+                      "workload": f"{wl.name}_general24", "unit": "rhs/s", "rows": rows}), flush=True)
+
+
 def serve_server(fhw, torch, Wk, rates, duration, precision, slots, queue_gb):
     """The serving configuration through the library's server (fhw_server_*):
     requests are submitted at their Poisson arrival times (seed 1); the
@@ -486,7 +559,7 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep", "uniform",
-                                                                "tracking"],
+                                                                "tracking", "general"],
                     help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
                          "serve: Poisson request stream (per-request latency); batch_sweep: solves/s at "
                          "batches of 1, 16, 256, 1024 frequencies")
@@ -515,6 +588,9 @@ def main():
         return
     if a.workload == "uniform":
         uniform_bench(fhw, torch, Wk, max(3, a.steps))
+        return
+    if a.workload == "general":
+        general_bench(fhw, torch, Wk, max(3, a.steps), a.modes.split(","))
         return
     if a.workload == "tracking":
         tracking_bench(fhw, torch, Wk, 5)

@@ -414,6 +414,74 @@ int fhw_run(fhw_ctx* ctx, const fhw_signal* sig, const fhw_windows* win, const d
  * tracking was off).  [host] outputs.  FHW_E_STATE before any synthesis. */
 int fhw_synth_active_pairs(fhw_ctx* ctx, int64_t* pairs, int64_t* active);
 
+/* ---------------- general incident fields (eq. bkdef2) -------------------- */
+
+/* Sampled Dirichlet data of a general incident field on the plan's nodes
+ * (Sec. 3.2, eq. bkdef2: the boundary data of the scattered field is b =
+ * -u_inc): b(x_i, t_n) and its normal derivative db(x_i, t_n) = -d_nu
+ * u_inc(x_i, t_n) at t_n = t0 + n dt, n < n_t, for the N Nystrom nodes x_i of
+ * fhw_geometry(ctx, N, ...) (normal nu as there).  b, db: device doubles
+ * [n_t][N], time-major (one time's nodes contiguous), caller-owned, read
+ * during fhw_solve_general only. */
+typedef struct {
+    const double* b;
+    const double* db;
+    int32_t N;
+    int64_t n_t;
+    double t0, dt;
+} fhw_boundary;
+
+/* The windows k = k_first .. k_first + n_win - 1 of the partition of unity
+ * (Sec. 3.1: s_k = 1.5 H (k - 1), support [s_k - H, s_k + H]) whose support
+ * meets [t_lo, t_hi].  [host] outputs.  FHW_E_INVALID for t_hi < t_lo, H <= 0
+ * or non-finite arguments.  Needs no context. */
+int fhw_window_range(double t_lo, double t_hi, double H, int64_t* k_first, int32_t* n_win);
+
+/* Step F3 for general boundary data (Sec. 3.2, eq. bkdef2 with eq.
+ * Bkslow_eqn applied node by node): for each window k = k_first + q, q <
+ * n_win, and solve frequency omega_j, the recentred transforms
+ *   B_k(x_i, omega) = dt sum_n w(t_n - s_k) b(x_i, t_n) e^{i omega (t_n - s_k)}
+ * (DB_k likewise from db: the rectangle rule, exact to roundoff for data
+ * resolved by the samples since the windowed integrand vanishes with all
+ * derivatives at the support's ends), the right-hand side DB_k - i eta B_k
+ * of eq. CFIE_direct, and its density on the resident factors (fhw_factor
+ * first).  The plan: one curve on the DFT grid (fhw_plan with j_first = 0,
+ * no graded low-frequency systems) with the same N at every frequency.
+ *   psi     device complex128 [n_win][psi_off[F]]; window k_first + q's
+ *           densities at q psi_off[F] (each laid out as fhw_solve_densities).
+ *   resid, sweeps [host, optional]: [n_win][F] as fhw_solve_incidences.
+ * Synchronizes.  Errors: FHW_E_STATE without resident factors or for another
+ * kind of plan; FHW_E_INVALID for null buffers, n_win < 1, bnd->N not the
+ * plan's N, n_t < 2, dt <= 0, non-finite t0 or H <= 0; FHW_E_NOCONV as
+ * fhw_solve_densities. */
+int fhw_solve_general(fhw_ctx* ctx, const fhw_boundary* bnd, double H, int64_t k_first, int32_t n_win,
+                      void* psi, double* resid, int32_t* sweeps);
+
+/* Step F5 for the n_win density blocks of fhw_solve_general (eq.
+ * Ukslow_repr): V device complex128 [n_win][N_r][2F], block q as
+ * fhw_eval_field writes it, with V(r, 0) = 0 (the windowed data are taken to
+ * carry no content at omega = 0; the low-frequency decomposition is not
+ * offered for general data).  obs [host] doubles [N_r][2].  Synchronizes.
+ * Errors as fhw_eval_field, and FHW_E_STATE for a plan fhw_solve_general
+ * does not take. */
+int fhw_eval_field_windows(fhw_ctx* ctx, const void* psi, int32_t n_win, const double* obs, int32_t N_r,
+                           void* V);
+
+/* Steps T1a-T6 with each window's own field (general boundary data): u(r, t)
+ * = sum over the windows k = k_first + q, q < n_win, active at t (|t - s_k -
+ * tau0| <= pi F / W) of
+ *   Re (W/pi) sum_m c_{k,m}(r) sinc(W (t - s_k - tau0)/pi - m),
+ * c_{k,m}(r) the Fourier coefficients on [-W, W) of V_k(r, omega) e^{-i
+ * omega tau0} (eqs. fourier_approx, approx, ukW, final_u; the windowed
+ * boundary data already inside V_k, so there is no spectrum factor).
+ * V: device complex128 [n_win][N_r][2F] (fhw_eval_field_windows); times
+ * [host] N_t; u: device doubles [N_r][N_t], overwritten.  win->H and tau0 as
+ * for fhw_solve_general; win->track_tol must be 0.  Synchronizes.
+ * Errors: FHW_E_INVALID for bad arguments, non-finite times or 2F not a
+ * power of two up to 8192; FHW_E_STATE as fhw_eval_field_windows. */
+int fhw_synthesize_windows(fhw_ctx* ctx, const fhw_windows* win, int64_t k_first, int32_t n_win,
+                           const void* V, int32_t N_r, const double* times, int32_t N_t, double* u);
+
 /* ---------------- stage entry points (same kernels, caller buffers) -------- */
 
 /* Boundary nodes of the planned curve at N points (Sec. 2.3 Nystrom nodes):

@@ -136,6 +136,40 @@ int copy_d2h(fhw_ctx* c, void* dst, const void* src, size_t bytes) {
     return FHW_OK;
 }
 
+// Several device-to-host copies through the context's pinned staging buffer
+// with one wait: the copies are queued on the stream, then the host waits
+// once and unpacks (each pageable copy would wait on its own).
+struct d2h_item {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+int readback(fhw_ctx* c, std::initializer_list<d2h_item> items) {
+    size_t total = 0;
+    for (const d2h_item& it : items) total += align_up(it.bytes, 64);
+    if (total > c->h_stage_bytes) {
+        FHW_HIP(c, hipStreamSynchronize(c->stream));
+        if (c->h_stage) (void)hipHostFree(c->h_stage);
+        c->h_stage = nullptr;
+        c->h_stage_bytes = 0;
+        const size_t nb = align_up(total + total / 2, 4096);
+        FHW_HIP(c, hipHostMalloc(&c->h_stage, nb, hipHostMallocDefault));
+        c->h_stage_bytes = nb;
+    }
+    size_t o = 0;
+    for (const d2h_item& it : items) {
+        if (it.bytes) FHW_HIP(c, hipMemcpyAsync((char*)c->h_stage + o, it.src, it.bytes, hipMemcpyDeviceToHost, c->stream));
+        o += align_up(it.bytes, 64);
+    }
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    o = 0;
+    for (const d2h_item& it : items) {
+        if (it.bytes) memcpy(it.dst, (char*)c->h_stage + o, it.bytes);
+        o += align_up(it.bytes, 64);
+    }
+    return FHW_OK;
+}
+
 uint64_t curve_fingerprint(const fhw_host_curve& cv) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](const void* p, size_t n) {
@@ -367,6 +401,7 @@ int fhw_destroy(fhw_ctx* c) {
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->d_pending) (void)hipFree(c->d_pending);
     if (c->h_pending) (void)hipHostFree(c->h_pending);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
     for (auto& r : c->prof.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -822,6 +857,16 @@ static int launch_factor_graph(fhw_ctx* c, chunk_t& ch, const fhw_batch_dev& bd,
     return FHW_OK;
 }
 
+// Where the right-hand sides of a solve come from: incident fields (inc), the
+// windows of sampled boundary data (bnd: window k_first + q is right-hand
+// side q), or neither (the plan's plane wave, as the assembly left it).
+struct rhs_src {
+    const fhw_incidence* inc = nullptr;
+    const fhw_boundary* bnd = nullptr;
+    double H = 0.0;
+    int64_t k_first = 0;
+};
+
 // The incidences on one factored batch, in groups of up to FHW_INC_GROUP
 // (one launch per step for a whole group: a second grid dimension), each
 // with its own slot of g and r: boundary data (inc == NULL: the plan's plane
@@ -831,8 +876,9 @@ static int launch_factor_graph(fhw_ctx* c, chunk_t& ch, const fhw_batch_dev& bd,
 // [voff0, voff0 + elems) belong to the batch; its norms at norms + 2 q fs
 // and flags at done / sw + q fs (index b within the batch).
 static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const fhw_assemble_item* d_items,
-                        int64_t voff0, int64_t elems, const fhw_incidence* inc, int32_t n_inc, zd* x, int64_t xs,
+                        int64_t voff0, int64_t elems, const rhs_src& src, int32_t n_inc, zd* x, int64_t xs,
                         double* norms, int32_t* done, int32_t* sw, int64_t fs) {
+    const fhw_incidence* inc = src.inc;
     const fhw_problem& p = c->prob;
     const bool fp32 = p.precision == FHW_FP32_REFINE;
     void* LU = fp32 ? c->A32 : c->A64;
@@ -851,6 +897,10 @@ static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const
                 rg.v[q][1] = inc[q0 + q].v[1];
             }
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, d_items, bd.batch, rg, sv, g));
+        } else if (src.bnd) {
+            const fhw_boundary& b = *src.bnd;
+            STAGE(c, FHW_STAGE_ASSEMBLE, launch_boundary_rhs(c->stream, b.b, b.db, b.n_t, b.N, b.t0, b.dt, src.H,
+                                                             src.k_first + q0, G, p.c, d_items, bd.batch, sv, g));
         }
         for (int q = 0; q < G; ++q)
             FHW_HIP(c, hipMemcpyAsync(xq + q * xs + voff0, g + q * sv + voff0, sizeof(zd) * elems,
@@ -941,7 +991,9 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             }
         }
         {
-            int rc = solve_groups(c, bd, ch.maxN, ch.d_items, 0, ch.vec_elems, inc, n_inc, psid + ch.psi_base, total,
+            rhs_src src;
+            src.inc = inc;
+            int rc = solve_groups(c, bd, ch.maxN, ch.d_items, 0, ch.vec_elems, src, n_inc, psid + ch.psi_base, total,
                                   d_norms + 2 * (int64_t)ch.j0, d_done + ch.j0, d_sw + ch.j0, F);
             if (rc) return rc;
         }
@@ -975,29 +1027,21 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             }
         }
     }
-    FHW_HIP(c, hipStreamSynchronize(c->stream));
     int32_t st[4];
+    const size_t nf = (size_t)F * n_inc;
+    const bool have_norms = fp32 || compute_resid;
+    std::vector<double> nrm(have_norms ? 2 * nf : 0);
+    std::vector<int32_t> done(fp32 ? nf : 0), sw(fp32 ? nf : 0);
     {
-        int rc = copy_d2h(c, st, c->d_status, sizeof(st));
+        int rc = readback(c, {{st, c->d_status, sizeof(st)},
+                              {nrm.data(), d_norms, sizeof(double) * nrm.size()},
+                              {done.data(), d_done, sizeof(int32_t) * done.size()},
+                              {sw.data(), d_sw, sizeof(int32_t) * sw.size()}});
         if (rc) return rc;
     }
     // factors stay usable when the whole plan fits one chunk and nothing
     // overwrote them (FP64 residuals re-assemble A in place)
     if (!reuse) c->factors_resident = px.chunks.size() == 1 && !(!fp32 && compute_resid) && !st[0];
-    const size_t nf = (size_t)F * n_inc;
-    std::vector<double> nrm;
-    std::vector<int32_t> done, sw;
-    const bool have_norms = fp32 || compute_resid;
-    if (have_norms) {
-        nrm.resize(2 * nf);
-        if (int rc_ = copy_d2h(c, nrm.data(), d_norms, sizeof(double) * 2 * nf)) return rc_;
-    }
-    if (fp32) {
-        done.resize(nf);
-        sw.resize(nf);
-        if (int rc_ = copy_d2h(c, done.data(), d_done, sizeof(int32_t) * nf)) return rc_;
-        if (int rc_ = copy_d2h(c, sw.data(), d_sw, sizeof(int32_t) * nf)) return rc_;
-    }
     for (size_t j = 0; j < nf; ++j) {
         if (resid) resid[j] = have_norms ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
         if (sweeps) sweeps[j] = fp32 ? (done[j] ? sw[j] : p.refine_max) : 0;
@@ -1065,16 +1109,12 @@ int fhw_factor(fhw_ctx* c) {
     return solve_impl(c, nullptr, 0, nullptr, nullptr, nullptr, 0, false);
 }
 
-int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc, void* psi,
-                    double* resid, int32_t* sweeps) {
-    if (!c) return FHW_E_INVALID;
-    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve_range: no plan");
-    if (!c->factors_resident)
-        return fhw_fail(c, FHW_E_STATE, "solve_range: no resident factors (fhw_factor first)");
-    const int S = (int)c->Ns.size();
-    if (s0 < 0 || count < 1 || s0 > S - count) return fhw_fail(c, FHW_E_INVALID, "solve_range: systems out of range");
-    int rc = check_incidences(c, inc, n_inc, psi);
-    if (rc) return rc;
+// Systems s0 .. s0 + count - 1 on the resident factors for n right-hand
+// sides from src; psi holds the range's densities per right-hand side
+// (element e of right-hand side q at psi + q elems + e).  what names the
+// entry point in messages.
+static int range_solve(fhw_ctx* c, const char* what, int32_t s0, int32_t count, const rhs_src& src, int32_t n,
+                       void* psi, double* resid, int32_t* sweeps) {
     plan_ext& px = plan_of(c);
     const chunk_t& ch = px.chunks[0];
     const fhw_problem& p = c->prob;
@@ -1087,38 +1127,116 @@ int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* 
     for (int s = s0; s < s0 + count; ++s) maxN = std::max(maxN, c->Ns[s]);
     const int64_t voff0 = c->psi_off[s0] - ch.psi_base;
     const int64_t elems = c->psi_off[s0 + count] - c->psi_off[s0];
-    const size_t nf = (size_t)n_inc * count;
+    const size_t nf = (size_t)n * count;
     const size_t off_sw = align_up(nf * 4, 256), off_nrm = off_sw + align_up(nf * 4, 256);
-    rc = fhw_ensure_scratch(c, off_nrm + nf * 16);
+    int rc = fhw_ensure_scratch(c, off_nrm + nf * 16);
     if (rc) return rc;
     int32_t* d_done = (int32_t*)c->scratch;
     int32_t* d_sw = (int32_t*)((char*)c->scratch + off_sw);
     double* d_norms = (double*)((char*)c->scratch + off_nrm);
     FHW_HIP(c, hipMemsetAsync(d_done, 0, sizeof(int32_t) * nf, c->stream));
     FHW_HIP(c, hipMemsetAsync(d_sw, 0, sizeof(int32_t) * nf, c->stream));
-    // psi holds the range's densities per incidence: element e of incidence q
-    // at psi + q elems + e, i.e. x + q elems + v_off[b] with x = psi - voff0
     zd* x = (zd*)psi - voff0;
-    rc = solve_groups(c, bd, maxN, ch.d_items + b0, voff0, elems, inc, n_inc, x, elems, d_norms, d_done, d_sw, count);
+    rc = solve_groups(c, bd, maxN, ch.d_items + b0, voff0, elems, src, n, x, elems, d_norms, d_done, d_sw, count);
     if (rc) return rc;
-    FHW_HIP(c, hipStreamSynchronize(c->stream));
-    std::vector<double> nrm;
-    std::vector<int32_t> done, sw;
-    if (fp32) {
-        nrm.resize(2 * nf);
-        done.resize(nf);
-        sw.resize(nf);
-        if (int rc_ = copy_d2h(c, nrm.data(), d_norms, sizeof(double) * 2 * nf)) return rc_;
-        if (int rc_ = copy_d2h(c, done.data(), d_done, sizeof(int32_t) * nf)) return rc_;
-        if (int rc_ = copy_d2h(c, sw.data(), d_sw, sizeof(int32_t) * nf)) return rc_;
-    }
+    std::vector<double> nrm(fp32 ? 2 * nf : 0);
+    std::vector<int32_t> done(fp32 ? nf : 0), sw(fp32 ? nf : 0);
+    rc = readback(c, {{nrm.data(), d_norms, sizeof(double) * nrm.size()},
+                      {done.data(), d_done, sizeof(int32_t) * done.size()},
+                      {sw.data(), d_sw, sizeof(int32_t) * sw.size()}});
+    if (rc) return rc;
     for (size_t j = 0; j < nf; ++j) {
         if (resid) resid[j] = fp32 ? (nrm[2 * j + 1] > 0 ? nrm[2 * j] / nrm[2 * j + 1] : 0.0) : -1.0;
         if (sweeps) sweeps[j] = fp32 ? (done[j] ? sw[j] : p.refine_max) : 0;
     }
     if (fp32)
         for (size_t j = 0; j < nf; ++j)
-            if (!done[j]) return fhw_fail(c, FHW_E_NOCONV, "solve_range: refinement did not reach refine_tol");
+            if (!done[j]) return fhw_fail(c, FHW_E_NOCONV, std::string(what) + ": refinement did not reach refine_tol");
+    return FHW_OK;
+}
+
+int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* inc, int32_t n_inc, void* psi,
+                    double* resid, int32_t* sweeps) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve_range: no plan");
+    if (!c->factors_resident)
+        return fhw_fail(c, FHW_E_STATE, "solve_range: no resident factors (fhw_factor first)");
+    const int S = (int)c->Ns.size();
+    if (s0 < 0 || count < 1 || s0 > S - count) return fhw_fail(c, FHW_E_INVALID, "solve_range: systems out of range");
+    int rc = check_incidences(c, inc, n_inc, psi);
+    if (rc) return rc;
+    rhs_src src;
+    src.inc = inc;
+    return range_solve(c, "solve_range", s0, count, src, n_inc, psi, resid, sweeps);
+}
+
+int fhw_window_range(double t_lo, double t_hi, double H, int64_t* k_first, int32_t* n_win) {
+    if (!k_first || !n_win || !isfinite(t_lo) || !isfinite(t_hi) || !(t_hi >= t_lo) || !(H > 0) || !isfinite(H))
+        return FHW_E_INVALID;
+    const double span = 1.5 * H;
+    int64_t k_lo = (int64_t)floor((t_lo - H) / span);
+    int64_t k_hi = (int64_t)ceil((t_hi + H) / span) + 2;
+    while (k_lo <= k_hi && !(span * ((double)k_lo - 1.0) + H >= t_lo)) ++k_lo;
+    while (k_hi >= k_lo && !(span * ((double)k_hi - 1.0) - H <= t_hi)) --k_hi;
+    if (k_hi - k_lo + 1 > INT32_MAX) return FHW_E_INVALID;
+    *k_first = k_lo;
+    *n_win = (int32_t)(k_hi - k_lo + 1);
+    return FHW_OK;
+}
+
+// A plan the general-data path takes: one curve, the DFT grid, no graded
+// systems, the same N at every frequency (the boundary samples' nodes).
+static int general_plan_check(fhw_ctx* c, const char* what) {
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, std::string(what) + ": no plan");
+    if (c->prob.j_first != 0 || c->system_plan || c->curves.size() != 1 || c->lf_extra > 0)
+        return fhw_fail(c, FHW_E_STATE, std::string(what) + ": needs a plan of one curve on the DFT grid "
+                                                              "without graded low-frequency systems");
+    for (int32_t N : c->Ns)
+        if (N != c->Ns[0])
+            return fhw_fail(c, FHW_E_STATE, std::string(what) + ": needs the same N at every frequency");
+    return FHW_OK;
+}
+
+int fhw_solve_general(fhw_ctx* c, const fhw_boundary* bnd, double H, int64_t k_first, int32_t n_win, void* psi,
+                      double* resid, int32_t* sweeps) {
+    if (!c) return FHW_E_INVALID;
+    int rc = general_plan_check(c, "solve_general");
+    if (rc) return rc;
+    if (!c->factors_resident)
+        return fhw_fail(c, FHW_E_STATE, "solve_general: no resident factors (fhw_factor first)");
+    if (!bnd || !bnd->b || !bnd->db || !psi || n_win < 1)
+        return fhw_fail(c, FHW_E_INVALID, "solve_general: need boundary data, psi and n_win >= 1");
+    if (bnd->N != c->Ns[0]) return fhw_fail(c, FHW_E_INVALID, "solve_general: boundary data at another N");
+    if (bnd->n_t < 2 || !(bnd->dt > 0) || !isfinite(bnd->dt) || !isfinite(bnd->t0))
+        return fhw_fail(c, FHW_E_INVALID, "solve_general: need n_t >= 2, dt > 0 and a finite t0");
+    if (!(H > 0) || !isfinite(H) || !isfinite(1.5 * H * ((double)k_first - 1.0)) ||
+        !isfinite(1.5 * H * ((double)k_first + n_win)))
+        return fhw_fail(c, FHW_E_INVALID, "solve_general: bad windows");
+    rhs_src src;
+    src.bnd = bnd;
+    src.H = H;
+    src.k_first = k_first;
+    return range_solve(c, "solve_general", 0, (int32_t)c->Ns.size(), src, n_win, psi, resid, sweeps);
+}
+
+int fhw_eval_field_windows(fhw_ctx* c, const void* psi, int32_t n_win, const double* obs, int32_t N_r, void* V) {
+    if (!c) return FHW_E_INVALID;
+    int rc = general_plan_check(c, "field_windows");
+    if (rc) return rc;
+    if (n_win < 0 || N_r < 0 || (n_win > 0 && N_r > 0 && (!psi || !obs || !V)))
+        return fhw_fail(c, FHW_E_INVALID, "field_windows: bad arguments");
+    if (n_win == 0 || N_r == 0) return FHW_OK;
+    if (n_win > 65535 * 8) return fhw_fail(c, FHW_E_INVALID, "field_windows: too many windows");
+    for (int q = 0; q < 2 * N_r; ++q)
+        if (!isfinite(obs[q])) return fhw_fail(c, FHW_E_INVALID, "field_windows: observation point not finite");
+    rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
+    if (rc) return rc;
+    const int F = c->prob.F;
+    FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
+    STAGE(c, FHW_STAGE_FIELD, launch_field_blocks(c->stream, plan_of(c).d_field_items, F, psi, c->psi_off[F], n_win,
+                                                  (const double*)c->scratch, N_r, 0.0, V,
+                                                  (int64_t)N_r * 2 * F));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }
 
@@ -1168,7 +1286,9 @@ int fhw_solve_range_noalloc(fhw_ctx* c, int32_t s0, int32_t count, const fhw_inc
     const int64_t elems = c->psi_off[s0 + count] - c->psi_off[s0];
     FHW_HIP(c, launch_status_clear(c->stream, d_done, d_sw, d_cnt, (int64_t)nf));
     zd* x = (zd*)psi - voff0;
-    rc = solve_groups(c, bd, maxN, ch.d_items + b0, voff0, elems, inc, n_inc, x, elems, d_norms, d_done, d_sw, count);
+    rhs_src src;
+    src.inc = inc;
+    rc = solve_groups(c, bd, maxN, ch.d_items + b0, voff0, elems, src, n_inc, x, elems, d_norms, d_done, d_sw, count);
     if (rc) return rc;
     FHW_HIP(c, launch_status_finish(c->stream, d_done, d_sw, d_norms, (int64_t)nf, fp32 ? 1 : 0, p.refine_max, d_res,
                                     d_swo, d_cnt));
@@ -1329,6 +1449,74 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
         for (double v : b) n += v > ttol * gm ? 1 : 0;
         c->trk_active = n;
     }
+    return FHW_OK;
+}
+
+// Synthesis with each window's own field (general boundary data): the
+// coefficient kernel on V_k e^{-i omega tau0} (no spectra), then the sinc
+// sum over the windows active at each time.
+int fhw_synthesize_windows(fhw_ctx* c, const fhw_windows* win, int64_t k_first, int32_t n_win, const void* V,
+                           int32_t N_r, const double* times, int32_t N_t, double* u) {
+    if (!c) return FHW_E_INVALID;
+    int rc = general_plan_check(c, "synthesize_windows");
+    if (rc) return rc;
+    if (!win || n_win < 0 || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: bad arguments");
+    if (N_r == 0 || N_t == 0) return FHW_OK;
+    if (!times || !u || (n_win > 0 && !V)) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: bad buffers");
+    const double H = win->H, tau0 = win->tau0;
+    if (!(H > 0) || !isfinite(H) || !isfinite(tau0)) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: bad windows");
+    if (win->track_tol != 0.0) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: track_tol must be 0");
+    const int F = c->prob.F;
+    const int M = 2 * F;
+    if (M & (M - 1)) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: 2F must be a power of two");
+    if (M > 8192 || (size_t)M * 16 > (size_t)lds_limit(c))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: 2F too large");
+    const double W = c->prob.W;
+    const double span = 1.5 * H;
+    const double P = M_PI / (W / (double)F);
+    // windows active at some sample time get a coefficient slot
+    std::vector<int32_t> slot((size_t)std::max(n_win, 1), -1);
+    std::vector<char> need((size_t)std::max(n_win, 1), 0);
+    for (int q = 0; q < N_t; ++q) {
+        const double t = times[q];
+        if (!isfinite(t)) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows: time not finite");
+        const int64_t ka = (int64_t)floor((t - tau0 - P) / span), kb = (int64_t)ceil((t - tau0 + P) / span) + 2;
+        for (int64_t k = std::max(ka, k_first); k <= std::min<int64_t>(kb, k_first + n_win - 1); ++k)
+            if (fabs(t - span * ((double)k - 1.0) - tau0) <= P) need[k - k_first] = 1;
+    }
+    // coefficients are computed for the run of windows from the first to the
+    // last active one (contiguous in V), inactive ones inside it included
+    int32_t q_lo = n_win, q_hi = -1;
+    for (int32_t q = 0; q < n_win; ++q)
+        if (need[q]) {
+            q_lo = std::min(q_lo, q);
+            q_hi = q;
+        }
+    const int count = q_hi >= q_lo ? q_hi - q_lo + 1 : 0;
+    for (int32_t q = q_lo; q <= q_hi; ++q) slot[q] = q - q_lo;
+    size_t o_t = 0;
+    size_t o_s = align_up(o_t + (size_t)N_t * 8, 256);
+    size_t o_c = align_up(o_s + slot.size() * 4, 256);
+    size_t total = align_up(o_c + (size_t)count * N_r * M * 8, 256);
+    rc = fhw_ensure_scratch(c, total);
+    if (rc) return rc;
+    char* sb = (char*)c->scratch;
+    FHW_HIP(c, hipMemcpyAsync(sb + o_t, times, (size_t)N_t * 8, hipMemcpyHostToDevice, c->stream));
+    FHW_HIP(c, hipMemcpyAsync(sb + o_s, slot.data(), slot.size() * 4, hipMemcpyHostToDevice, c->stream));
+    c->trk_pairs = (int64_t)count * N_r;
+    c->trk_active = c->trk_pairs;
+    if (count == 0) {
+        FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
+    } else {
+        const int64_t vq = (int64_t)N_r * M;
+        STAGE(c, FHW_STAGE_COEFFS, launch_fourier_coeffs(c->stream, nullptr, count, (const zd*)V + q_lo * vq, N_r, W, F,
+                                                         tau0, nullptr, (double*)(sb + o_c), nullptr, nullptr,
+                                                         nullptr, nullptr, 0.0, vq));
+        STAGE(c, FHW_STAGE_SYNTH, launch_synth(c->stream, sb + o_c, (const int32_t*)(sb + o_s), k_first,
+                                               k_first + n_win - 1, count, N_r, (const double*)(sb + o_t), N_t, W, F,
+                                               H, tau0, u, nullptr, nullptr, 0.0));
+    }
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <initializer_list>
 #include <stdint.h>
 
 #include <map>
@@ -128,6 +129,8 @@ struct fhw_ctx {
     int32_t* d_sweeps = nullptr;       // [chunk]
     int32_t* d_pending = nullptr;      // systems still above the refinement tolerance after a sweep
     int32_t* h_pending = nullptr;      // its pinned host copy
+    void* h_stage = nullptr;           // pinned staging of the status read-backs
+    size_t h_stage_bytes = 0;
 
     fhw_prof prof;
     hipStream_t cap_stream = nullptr;  // graph capture (created on first use, default priority)
@@ -278,6 +281,11 @@ hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F,
                         const double* obs, int32_t N_r, double zero_value, void* V);
 hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
 // V[r][0] = zero_value, V[r][1 + j] = field of item j: complex128 [N_r][n_items + 1]
+// the field of n_blk density blocks (block q at psi + q psi_bstride) into
+// V + q V_bstride, each as launch_field writes it, with V(r, 0) = zero_value
+hipError_t launch_field_blocks(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
+                               int64_t psi_bstride, int32_t n_blk, const double* obs, int32_t N_r,
+                               double zero_value, void* V, int64_t V_bstride);
 hipError_t launch_field_list(hipStream_t s, const fhw_field_item* d_items, int32_t n_items, const void* psi,
                              const double* obs, int32_t N_r, double zero_value, void* V);
 
@@ -311,11 +319,20 @@ hipError_t launch_window_spectra_at(hipStream_t s, const double* f, int64_t n, d
 // bnd (optional, tracking): [count][N_r] sums of |Re c_m|, their maximum into
 // *gmax (as the bits of a double; zero before the call); windows whose
 // spectrum max wmax[q] (written here, [count]) is at most tol * (*gwmax)
-// (zero before the call) get no coefficients and bound 0
+// (zero before the call) get no coefficients and bound 0.  With B == NULL
+// every window has its own field, window q's at V + q v_qstride, and the
+// coefficients are those of V e^{-i omega tau0} (no tracking then).
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V,
                                  int32_t N_r, double W, int32_t F, double tau0, void* c, double* c_re,
                                  double* bnd = nullptr, unsigned long long* gmax = nullptr,
-                                 double* wmax = nullptr, unsigned long long* gwmax = nullptr, double tol = 0.0);
+                                 double* wmax = nullptr, unsigned long long* gwmax = nullptr, double tol = 0.0,
+                                 int64_t v_qstride = 0);
+// Right-hand sides DB - i eta B of eq. CFIE_direct from sampled boundary data
+// b, db [n_t][N] (device, real) for windows k_first .. k_first + n_win - 1
+// (window q at g + q sg) and the n_sys items (omega = kappa c)
+hipError_t launch_boundary_rhs(hipStream_t s, const double* b, const double* db, int64_t n_t, int32_t N, double t0,
+                               double dt, double H, int64_t k_first, int32_t n_win, double c,
+                               const fhw_assemble_item* d_items, int32_t n_sys, int64_t sg, void* g);
 // Fast scaled convolution on a uniform time grid (frft.hip).  A chunk is a
 // run of n consecutive grid times from index n0 inside one window's active
 // range; xs is the kernel argument W (t_{n0} - s_k - tau0) / pi of its first.

@@ -46,6 +46,57 @@ __global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restri
     }
 }
 
+// The field of n_blk density blocks at once (the windows of general boundary
+// data): one wave per (point, frequency) as in k_field; the Hankel kernel of
+// a node is formed once and applied to up to FB_BLK blocks.
+#define FB_BLK 8
+__global__ __launch_bounds__(256, 4) void k_field_blocks(const fhw_field_item* __restrict__ items, int F,
+                                                      const zd* __restrict__ psi, int64_t psi_bstride, int n_blk,
+                                                      const double* __restrict__ obs, int N_r, double zero_value,
+                                                      zd* __restrict__ V, int64_t V_bstride) {
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= N_r * F) return;
+    const int r = wave / F;
+    const int j = wave - r * F;
+    const fhw_field_item it = items[j];
+    const int N = it.N;
+    const double* x1 = it.geom;
+    const double* x2 = it.geom + N;
+    const double* sp = it.geom + 6 * N;
+    const double o1 = obs[2 * r], o2 = obs[2 * r + 1];
+    const double wq = 2.0 * FHW_PI / (double)N;
+    for (int q0 = blockIdx.y * FB_BLK; q0 < n_blk; q0 += gridDim.y * FB_BLK) {
+        const int nb = min(FB_BLK, n_blk - q0);
+        const zd* ps = psi + it.psi_off + (int64_t)q0 * psi_bstride;
+        zd acc[FB_BLK];
+#pragma unroll
+        for (int u = 0; u < FB_BLK; ++u) acc[u] = cmk(0.0, 0.0);
+        for (int i = lane; i < N; i += 64) {
+            const double d1 = o1 - x1[i], d2 = o2 - x2[i];
+            const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
+            double J0, Y0;
+            fhw_bessel0(z, J0, Y0);
+            const zd gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
+#pragma unroll
+            for (int u = 0; u < FB_BLK; ++u)
+                if (u < nb) acc[u] = cfma(acc[u], gk, ps[(int64_t)u * psi_bstride + i]);
+        }
+#pragma unroll
+        for (int u = 0; u < FB_BLK; ++u) {
+            if (u >= nb) break;
+            const double re = wave_sum(acc[u].re), im = wave_sum(acc[u].im);
+            if (lane == 0) {
+                const zd val = cmk(wq * re, wq * im);
+                zd* Vr = V + (int64_t)(q0 + u) * V_bstride + (int64_t)r * 2 * F;
+                if (j < F - 1) Vr[F + 1 + j] = val;
+                Vr[F - 1 - j] = cconj(val);
+                if (j == 0) Vr[F] = cmk(zero_value, 0.0);
+            }
+        }
+    }
+}
+
 // V[r][0] = zero_value, V[r][1 + j] = field of item j (j < n_items): the
 // field at an explicit list of systems (the graded low-frequency nodes).
 __global__ __launch_bounds__(256, 4) void k_field_list(const fhw_field_item* __restrict__ items, int n_items,
@@ -97,6 +148,17 @@ hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F,
     if (waves <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_field, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items, F, (const zd*)psi, obs,
                        N_r, zero_value, (zd*)V);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_blocks(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
+                               int64_t psi_bstride, int32_t n_blk, const double* obs, int32_t N_r,
+                               double zero_value, void* V, int64_t V_bstride) {
+    const int64_t waves = (int64_t)N_r * F;
+    if (waves <= 0 || n_blk <= 0) return hipSuccess;
+    const int gy = (n_blk + FB_BLK - 1) / FB_BLK;
+    hipLaunchKernelGGL(k_field_blocks, dim3((unsigned)((waves + 3) / 4), gy), dim3(256), 0, s, d_items, F,
+                       (const zd*)psi, psi_bstride, n_blk, obs, N_r, zero_value, (zd*)V, V_bstride);
     return hipGetLastError();
 }
 

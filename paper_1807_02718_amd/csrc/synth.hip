@@ -92,6 +92,82 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
     }
 }
 
+// Right-hand sides of eq. CFIE_direct for general boundary data (eq. bkdef2):
+// window k = k_first + q, system j (items[j]: omega = kappa c, eta, offset
+// g_off), node i:
+//   B  = dt sum_n w(t_n - s_k) b(x_i, t_n) e^{i omega (t_n - s_k)},  DB likewise
+//        from db (the normal derivative),  g = DB - i eta B
+// written at g + q sg + g_off + i.  b, db: samples [n_t][N] (time-major, so
+// one time's nodes are contiguous).  Grid (n_win, ceil(n_sys / BW_SYS),
+// ceil(N / SYN_THREADS)): a thread takes one node and BW_SYS systems; the
+// factors w e^{i omega tau} of a run of samples are staged in LDS, so each
+// sample of b and db is read once per BW_SYS systems.
+#define BW_SYS 8
+#define BW_CHUNK 256
+__global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __restrict__ b,
+                                                              const double* __restrict__ db, int64_t n_t, int N,
+                                                              double t0, double dt, double H, int64_t k_first,
+                                                              double c, const fhw_assemble_item* __restrict__ items,
+                                                              int n_sys, int64_t sg, zd* __restrict__ g) {
+    __shared__ zd E[BW_SYS][BW_CHUNK];
+    const int q = blockIdx.x;
+    const int j0 = blockIdx.y * BW_SYS;
+    const int ns = min(BW_SYS, n_sys - j0);
+    const int node = blockIdx.z * SYN_THREADS + threadIdx.x;
+    const double sk = 1.5 * H * ((double)(k_first + q) - 1.0);
+    // samples whose window weight can be nonzero, [sk - H, sk + H]
+    int64_t n_lo = (int64_t)floor((sk - H - t0) / dt);
+    int64_t n_hi = (int64_t)ceil((sk + H - t0) / dt);
+    if (n_lo < 0) n_lo = 0;
+    if (n_hi > n_t - 1) n_hi = n_t - 1;
+    zd aB[BW_SYS], aD[BW_SYS];
+#pragma unroll
+    for (int u = 0; u < BW_SYS; ++u) {
+        aB[u] = cmk(0.0, 0.0);
+        aD[u] = cmk(0.0, 0.0);
+    }
+    for (int64_t c0 = n_lo; c0 <= n_hi; c0 += BW_CHUNK) {
+        const int cnt = (int)min<int64_t>(BW_CHUNK, n_hi - c0 + 1);
+        __syncthreads();
+        for (int e = threadIdx.x; e < BW_SYS * cnt; e += SYN_THREADS) {
+            const int u = e / cnt, i = e - u * cnt;
+            zd v = cmk(0.0, 0.0);
+            if (u < ns) {
+                const double tau = t0 + dt * (double)(c0 + i) - sk;
+                const double w = fhw_window(tau, H);
+                double sn, cs;
+                sincos(items[j0 + u].kappa * c * tau, &sn, &cs);
+                v = cmk(w * cs, w * sn);
+            }
+            E[u][i] = v;
+        }
+        __syncthreads();
+        if (node < N) {
+            const double* bp = b + c0 * (int64_t)N + node;
+            const double* dp = db + c0 * (int64_t)N + node;
+            for (int i = 0; i < cnt; ++i) {
+                const double bv = bp[(int64_t)i * N], dv = dp[(int64_t)i * N];
+#pragma unroll
+                for (int u = 0; u < BW_SYS; ++u) {
+                    const zd e = E[u][i];
+                    aB[u] = cmk(fma(bv, e.re, aB[u].re), fma(bv, e.im, aB[u].im));
+                    aD[u] = cmk(fma(dv, e.re, aD[u].re), fma(dv, e.im, aD[u].im));
+                }
+            }
+        }
+    }
+    if (node >= N) return;
+#pragma unroll
+    for (int u = 0; u < BW_SYS; ++u) {
+        if (u < ns) {
+            const fhw_assemble_item it = items[j0 + u];
+            const double eta = it.eta;
+            const zd B = cmk(dt * aB[u].re, dt * aB[u].im), D = cmk(dt * aD[u].re, dt * aD[u].im);
+            g[(int64_t)q * sg + it.g_off + node] = cmk(D.re + eta * B.im, D.im - eta * B.re);
+        }
+    }
+}
+
 // Tracking, window level: wmax[q] = max_l (|Re B_q| + |Im B_q|) over the DFT
 // grid, and the largest over the windows into *gwmax (double bits, zero before).
 __global__ __launch_bounds__(SYN_THREADS) void k_window_max(const zd* __restrict__ B, int M,
@@ -123,7 +199,8 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_max(const zd* __restrict
 // order, and the largest such bound into *gmax (the bits of a non-negative
 // double order as an unsigned integer; *gmax starts at 0).
 __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __restrict__ B, const zd* __restrict__ V,
-                                                                int N_r, double W, int F, int logM, double tau0,
+                                                                int64_t v_qstride, int N_r, double W, int F,
+                                                                int logM, double tau0,
                                                                 zd* __restrict__ c, double* __restrict__ c_re,
                                                                 double* __restrict__ bnd,
                                                                 unsigned long long* __restrict__ gmax,
@@ -140,15 +217,15 @@ __global__ __launch_bounds__(SYN_THREADS) void k_fourier_coeffs(const zd* __rest
     }
     const int M = 2 * F;
     const double dw = W / (double)F;
-    const zd* Bq = B + (int64_t)q * M;
-    const zd* Vr = V + (int64_t)r * M;
+    const zd* Bq = B ? B + (int64_t)q * M : nullptr;   // NULL: each window has its own V
+    const zd* Vr = V + (int64_t)q * v_qstride + (int64_t)r * M;
     __shared__ zd thi[64], tlo[64];
     fft_tables(thi, tlo, M);
     for (int l = threadIdx.x; l < M; l += SYN_THREADS) {
         const double om = -W + dw * (double)l;
         double s, cs;
         sincos(-om * tau0, &s, &cs);
-        const zd g = cmul(cmul(Bq[l], Vr[l]), cmk(cs, s));
+        const zd g = cmul(Bq ? cmul(Bq[l], Vr[l]) : Vr[l], cmk(cs, s));
         const int rev = (int)(__brev((unsigned)l) >> (32 - logM));
         X[rev] = g;
     }
@@ -282,6 +359,15 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
     return hipGetLastError();
 }
 
+hipError_t launch_boundary_rhs(hipStream_t s, const double* b, const double* db, int64_t n_t, int32_t N, double t0,
+                               double dt, double H, int64_t k_first, int32_t n_win, double c,
+                               const fhw_assemble_item* d_items, int32_t n_sys, int64_t sg, void* g) {
+    if (n_win <= 0 || n_sys <= 0 || N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boundary_rhs, dim3(n_win, (n_sys + BW_SYS - 1) / BW_SYS, (N + SYN_THREADS - 1) / SYN_THREADS),
+                       dim3(SYN_THREADS), 0, s, b, db, n_t, N, t0, dt, H, k_first, c, d_items, n_sys, sg, (zd*)g);
+    return hipGetLastError();
+}
+
 hipError_t launch_window_spectra_at(hipStream_t s, const double* f, int64_t n, double t0, double dt, double H,
                                     const int64_t* d_klist, int32_t count, const double* d_om, int32_t n_om,
                                     void* B) {
@@ -294,8 +380,10 @@ hipError_t launch_window_spectra_at(hipStream_t s, const double* f, int64_t n, d
 
 hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, const void* V, int32_t N_r, double W,
                                  int32_t F, double tau0, void* c, double* c_re, double* bnd,
-                                 unsigned long long* gmax, double* wmax, unsigned long long* gwmax, double tol) {
+                                 unsigned long long* gmax, double* wmax, unsigned long long* gwmax, double tol,
+                                 int64_t v_qstride) {
     if (count <= 0 || N_r <= 0) return hipSuccess;
+    if (!B && bnd) return hipErrorInvalidValue;   // tracking needs the window spectra
     const int M = 2 * F;
     if (M > SYN_MMAX || (M & (M - 1))) return hipErrorInvalidValue;
     int logM = 0;
@@ -311,7 +399,7 @@ hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, co
         hipLaunchKernelGGL(k_window_max, dim3(count), dim3(SYN_THREADS), 0, s, (const zd*)B, M, wmax, gwmax);
     }
     hipLaunchKernelGGL(k_fourier_coeffs, dim3(N_r, count), dim3(SYN_THREADS), lds, s, (const zd*)B, (const zd*)V,
-                       N_r, W, F, logM, tau0, (zd*)c, c_re, bnd, gmax, (const double*)wmax,
+                       v_qstride, N_r, W, F, logM, tau0, (zd*)c, c_re, bnd, gmax, (const double*)wmax,
                        (const unsigned long long*)gwmax, tol);
     return hipGetLastError();
 }

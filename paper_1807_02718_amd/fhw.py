@@ -58,6 +58,11 @@ class fhw_incidence(C.Structure):
     _fields_ = [("kind", C.c_int32), ("v", C.c_double * 2)]
 
 
+class fhw_boundary(C.Structure):
+    _fields_ = [("b", C.c_void_p), ("db", C.c_void_p), ("N", C.c_int32), ("n_t", C.c_int64), ("t0", C.c_double),
+                ("dt", C.c_double)]
+
+
 class fhw_system(C.Structure):
     _fields_ = [("curve", C.c_int32), ("omega", C.c_double), ("N", C.c_int32)]
 
@@ -66,6 +71,15 @@ class fhw_request(C.Structure):
     _fields_ = [("curve", C.c_int32), ("n_freq", C.c_int32), ("omegas", _dp), ("N", C.c_int32),
                 ("n_inc", C.c_int32), ("inc", C.POINTER(fhw_incidence)), ("psi", C.c_void_p), ("resid", _dp),
                 ("sweeps", C.POINTER(C.c_int32))]
+
+
+def window_range(t_lo, t_hi, H):
+    """fhw_window_range: (k_first, n_win) of the windows meeting [t_lo, t_hi]."""
+    k, n = C.c_int64(0), C.c_int32(0)
+    rc = _lib.fhw_window_range(float(t_lo), float(t_hi), float(H), C.byref(k), C.byref(n))
+    if rc:
+        raise FhwError(rc, "window_range: bad arguments")
+    return int(k.value), int(n.value)
 
 
 class FhwError(RuntimeError):
@@ -102,6 +116,10 @@ def _load():
                                    C.c_double, i32, i32, vp],
         "fhw_synth_active_pairs": [vp, p_i64, p_i64],
         "fhw_run": [vp, C.POINTER(fhw_signal), C.POINTER(fhw_windows), _dp, i32, _dp, i32, vp, vp, vp, _dp, p_i32],
+        "fhw_window_range": [C.c_double, C.c_double, C.c_double, p_i64, p_i32],
+        "fhw_solve_general": [vp, C.POINTER(fhw_boundary), C.c_double, i64, i32, vp, _dp, p_i32],
+        "fhw_eval_field_windows": [vp, vp, i32, _dp, i32, vp],
+        "fhw_synthesize_windows": [vp, C.POINTER(fhw_windows), i64, i32, vp, i32, _dp, i32, vp],
         "fhw_geometry": [vp, i32, vp],
         "fhw_kress_weights": [vp, i32, vp, vp],
         "fhw_assemble": [vp, i32, i32, vp, p_i64, vp, p_i64],
@@ -130,7 +148,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
             "fhw_plan_systems", "fhw_factor", "fhw_solve_range", "fhw_solve_range_noalloc",
-            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_eval_field_lowfreq", "fhw_synthesize", "fhw_synthesize_lowfreq", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_eval_field_lowfreq", "fhw_synthesize", "fhw_synthesize_lowfreq", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_window_range", "fhw_solve_general",
+            "fhw_eval_field_windows", "fhw_synthesize_windows", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read", "fhw_server_create", "fhw_server_submit", "fhw_server_poll",
             "fhw_server_stats", "fhw_server_destroy")
@@ -404,6 +423,45 @@ class Context:
         self._check(_lib.fhw_run(self._h, C.byref(sg), C.byref(wn), obs_p, Nr, tp, len(th), _ptr(psi), _ptr(V),
                                  _ptr(u), resid.ctypes.data_as(_dp), sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
         return u, psi, V, resid, sweeps
+
+    # -- general incident fields ---------------------------------------------------
+    def solve_general(self, b, db, t0, dt, H, k_first=None, n_win=None, psi=None):
+        """fhw_solve_general: b, db device float64 [n_t][N] (boundary data
+        -u_inc and its normal derivative at the nodes); windows k_first ..
+        k_first + n_win - 1 (default: all that meet the samples' range).
+        Returns (psi [n_win, psi_off[F]] complex128, resid [n_win, F], sweeps
+        [n_win, F], k_first)."""
+        n_t, N = int(b.shape[0]), int(b.shape[1])
+        if k_first is None or n_win is None:
+            k_first, n_win = window_range(t0, t0 + dt * (n_t - 1), H)
+        bd = fhw_boundary(_ptr(b).value, _ptr(db).value, N, n_t, float(t0), float(dt))
+        if psi is None:
+            psi = torch.empty((max(int(n_win), 1), int(self.psi_off[-1])), dtype=torch.complex128, device=self.device)
+        resid = np.zeros((max(int(n_win), 1), self.S))
+        sweeps = np.zeros((max(int(n_win), 1), self.S), dtype=np.int32)
+        self._check(_lib.fhw_solve_general(self._h, C.byref(bd), float(H), int(k_first), int(n_win), _ptr(psi),
+                                           resid.ctypes.data_as(_dp), sweeps.ctypes.data_as(C.POINTER(C.c_int32))))
+        return psi, resid, sweeps, int(k_first)
+
+    def eval_field_windows(self, psi, obs, V=None):
+        """fhw_eval_field_windows: V [n_win, N_r, 2F] complex128, V(r, 0) = 0."""
+        obs_h, obs_p = _host(obs, np.float64)
+        Nr, nw = obs_h.shape[0], int(psi.shape[0])
+        if V is None:
+            V = torch.empty((nw, Nr, 2 * self.F), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_eval_field_windows(self._h, _ptr(psi), nw, obs_p, Nr, _ptr(V)))
+        return V
+
+    def synthesize_windows(self, H, tau0, k_first, V, times, u=None):
+        """fhw_synthesize_windows: u [N_r, N_t] from each window's own field."""
+        wn = fhw_windows(float(H), float(tau0), 0.0)
+        th, tp = _host(times, np.float64)
+        nw, Nr = int(V.shape[0]), int(V.shape[1])
+        if u is None:
+            u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_synthesize_windows(self._h, C.byref(wn), int(k_first), nw, _ptr(V), Nr, tp, len(th),
+                                                _ptr(u)))
+        return u
 
     def synth_active_pairs(self):
         """(window, point) pairs of the last synthesis and how many tracking kept."""
