@@ -296,7 +296,9 @@ int fhw_server_poll(fhw_server* server, int64_t ticket, int32_t wait, int32_t* s
  * (no plan or factorization: every system of their round, (curve, omega, N)
  * at the server's precision, was among the factors the slot kept from its
  * previous round); busy_s [host, optional]: the slots' summed round time in
- * seconds. */
+ * seconds.  A round's rounds, systems and cache counts are in before any of
+ * its requests is reported finished; its busy time is added when the round
+ * ends. */
 int fhw_server_stats(fhw_server* server, int64_t* counts, double* busy_s);
 /* Finishes the waiting requests, stops the slots and frees everything. */
 int fhw_server_destroy(fhw_server* server);

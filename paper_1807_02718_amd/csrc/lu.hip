@@ -87,7 +87,11 @@ struct panel_lds {
     int sing;
 };
 
-template <typename T, int R, int W, int WPE, int PT = PANEL_THREADS>
+// PD: columns of L_t in flight during a lazy step (a rolling register
+// buffer: column q + PD is requested as soon as column q has been applied);
+// 0 selects the default (all W for FP32 with one row per thread, one column
+// ahead for FP32 otherwise, none for FP64).
+template <typename T, int R, int W, int WPE, int PT = PANEL_THREADS, int PD = 0>
 __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restrict__ Ns,
                                                       const int64_t* __restrict__ a_off,
                                                       const int64_t* __restrict__ piv_off,
@@ -130,12 +134,13 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
             const int tb = t * W;
             const int buf = t & 1;
             // rows below block t: X -= L_t U_t.  L_t is final, so its loads go
-            // out before U_t is formed: FP32 with one row per thread all W
-            // columns, else FP32 one column ahead of the arithmetic and FP64
-            // the first column only (register budgets, measured)
+            // out before U_t is formed: by default FP32 with one row per
+            // thread all W columns, else FP32 one column ahead of the
+            // arithmetic and FP64 the first column only (register budgets,
+            // measured); PD > 0: PD columns in flight, in a rolling buffer
             const cpx<T>* Lt = P + (int64_t)tb * N + tid;
             constexpr bool F32 = sizeof(T) == 4;
-            constexpr int PF = (F32 && R == 1) ? W : 1;
+            constexpr int PF = PD > 0 ? (PD < W ? PD : W) : ((F32 && R == 1) ? W : 1);
             cpx<T> l[PF][R];
 #pragma unroll
             for (int q = 0; q < PF; ++q) lazy_load<T, R, PT>(l[q], Lt + (int64_t)q * N, tid, tb + W, m);
@@ -166,6 +171,17 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
             if constexpr (PF == W) {
 #pragma unroll
                 for (int q = 0; q < W; ++q) lazy_update<T, R, W, PT>(ar, ai, l[q], S.U[buf][q], tid, tb + W, m);
+            } else if constexpr (PD > 0) {
+                // column q0 + k from slot k, which then takes column q0 + k + PF
+#pragma unroll 1
+                for (int q0 = 0; q0 < W; q0 += PF) {
+#pragma unroll
+                    for (int k = 0; k < PF; ++k) {
+                        lazy_update<T, R, W, PT>(ar, ai, l[k], S.U[buf][q0 + k], tid, tb + W, m);
+                        if (q0 + k + PF < W)
+                            lazy_load<T, R, PT>(l[k], Lt + (int64_t)(q0 + k + PF) * N, tid, tb + W, m);
+                    }
+                }
             } else {
 #pragma unroll 1
                 for (int q = 0; q < W; ++q) {
@@ -835,11 +851,15 @@ static void lu_set_lds_limits() {
 template <typename T>
 static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, int k0, cpx<T>* A, int32_t* piv,
                                int32_t* st) {
-#define FHW_PANEL(RR, WW, EE, PT)                                                                             \
-    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE, PT>), dim3(bd.batch), dim3(PT), 0, s, k0, bd.N, bd.a_off,  \
+#define FHW_PANEL(RR, WW, EE, PT) FHW_PANEL_D(RR, WW, EE, PT, 0)
+#define FHW_PANEL_D(RR, WW, EE, PT, DD)                                                                       \
+    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE, PT, DD>), dim3(bd.batch), dim3(PT), 0, s, k0, bd.N, bd.a_off, \
                        bd.piv_off, A, piv, st)
 #define FHW_PANEL_T(RR, WE, PT) FHW_PANEL_X(RR, WE, PT)
 #define FHW_PANEL_X(...) FHW_PANEL(__VA_ARGS__)
+    // large batches: (threads, W, WPE, PD) from the table, ceil(256 R / threads) rows per thread
+#define FHW_PANEL_B(RR, TWE) FHW_PANEL_BX(RR, TWE)
+#define FHW_PANEL_BX(RR, PTB, WW, EE, DD) FHW_PANEL_D((RR * 256 + PTB - 1) / PTB, WW, EE, PTB, DD)
     // (W, waves per SIMD) per case from panel_table.h, among the spill-free
     // register allocations; R = 8 and 16 (over 1024 rows) are fixed
     if (bd.batch <= 256) {
@@ -859,23 +879,26 @@ static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, in
         }
     } else if constexpr (sizeof(T) == 4) {
         switch (R) {
-            case 1: FHW_PANEL_T(1, FHW_PT_F32_256_R1, 256); break;
-            case 2: FHW_PANEL_T(2, FHW_PT_F32_256_R2, 256); break;
-            case 4: FHW_PANEL_T(4, FHW_PT_F32_256_R4, 256); break;
+            case 1: FHW_PANEL_B(1, FHW_PB_F32_R1); break;
+            case 2: FHW_PANEL_B(2, FHW_PB_F32_R2); break;
+            case 4: FHW_PANEL_B(4, FHW_PB_F32_R4); break;
             case 8: FHW_PANEL(8, 4, 2, 256); break;
             default: FHW_PANEL(16, 2, 2, 256); break;
         }
     } else {
         switch (R) {
-            case 1: FHW_PANEL_T(1, FHW_PT_F64_256_R1, 256); break;
-            case 2: FHW_PANEL_T(2, FHW_PT_F64_256_R2, 256); break;
-            case 4: FHW_PANEL_T(4, FHW_PT_F64_256_R4, 256); break;
+            case 1: FHW_PANEL_B(1, FHW_PB_F64_R1); break;
+            case 2: FHW_PANEL_B(2, FHW_PB_F64_R2); break;
+            case 4: FHW_PANEL_B(4, FHW_PB_F64_R4); break;
             case 8: FHW_PANEL(8, 4, 2, 256); break;
             default: FHW_PANEL(16, 2, 1, 256); break;
         }
     }
+#undef FHW_PANEL_BX
+#undef FHW_PANEL_B
 #undef FHW_PANEL_X
 #undef FHW_PANEL_T
+#undef FHW_PANEL_D
 #undef FHW_PANEL
     return hipGetLastError();
 }

@@ -158,6 +158,14 @@ void worker(fhw_server* S, fhw_ctx* ctx) {
                     resident.emplace(key_of(sys[q].curve, sys[q].omega, sys[q].N), q);
             n_sys = (int64_t)sys.size();
         }
+        {
+            // the round's counts go in before any of its requests is reported
+            // complete, so that a caller who saw its request finish sees them
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->rounds += 1;
+            S->systems += n_sys;
+            if (hit) S->cache_hits += (int64_t)batch.size();
+        }
         for (size_t b = 0; b < batch.size(); ++b) {
             srv_request* r = batch[b];
             const int32_t cnt = (int32_t)r->omegas.size();
@@ -173,9 +181,6 @@ void worker(fhw_server* S, fhw_ctx* ctx) {
         }
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         std::lock_guard<std::mutex> lk(S->mu);
-        S->rounds += 1;
-        S->systems += n_sys;
-        if (hit) S->cache_hits += (int64_t)batch.size();
         S->busy_s += dt;
     }
 }

@@ -214,6 +214,197 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
     }
 }
 
+// The solves of NV vectors of a group at once, each factor entry loaded once
+// for all of them (the vectors of a group share the matrix).  One 1024-thread
+// workgroup per (matrix, run of NV vectors); dynamic LDS holds the NV
+// solution vectors [NV][N], the cross-wave partial sums of the backward
+// products [16][NV][NB] and the backward right-hand sides [NV][NB].  Same
+// steps and pivot order as k_lu_solve; a vector whose skip flag is set is
+// carried along but neither written nor accumulated.
+#ifndef FHW_SM_TH
+#define FHW_SM_TH 1024   // threads per workgroup
+#endif
+#ifndef FHW_SM_NV
+#define FHW_SM_NV 4      // vectors per workgroup (halved when their LDS does not fit)
+#endif
+#define SM_TH FHW_SM_TH
+template <typename T, int NV>
+__global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict__ Ns,
+                                                        const int64_t* __restrict__ a_off,
+                                                        const int64_t* __restrict__ piv_off,
+                                                        const int64_t* __restrict__ linv_off,
+                                                        const int64_t* __restrict__ v_off,
+                                                        const cpx<T>* __restrict__ LUbase,
+                                                        const int* __restrict__ pivbase,
+                                                        const cpx<T>* __restrict__ linvbase, zd* __restrict__ v,
+                                                        zd* __restrict__ acc, const int* __restrict__ skip,
+                                                        int ldx, fhw_grp grp) {
+    constexpr int NW = SM_TH / 64;
+    extern __shared__ zd smem[];
+    zd* xs = smem;                                  // [NV][ldx]
+    zd* part = smem + NV * ldx;                     // [NW][NV][NB]
+    zd* rhs = part + NW * NV * NB;                  // [NV][NB]
+    const int b = blockIdx.x;
+    const int q0 = blockIdx.y * NV;
+    const int nv = min(NV, grp.n - q0);
+    bool live[NV];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        live[u] = u < nv && !(skip && skip[(int64_t)(q0 + u) * grp.sflag + b]);
+        any = any || live[u];
+    }
+    if (!any) return;
+    const int N = Ns[b];
+    const cpx<T>* LU = LUbase + a_off[b];
+    const int* piv = pivbase + piv_off[b];
+    const cpx<T>* Lb = linvbase + linv_off[b];
+    const int64_t vo = v_off[b];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int u = 0; u < NV; ++u)
+        for (int i = tid; i < N; i += SM_TH)
+            xs[u * ldx + i] = u < nv ? v[(int64_t)(q0 + u) * grp.sv + vo + i] : cmk(0.0, 0.0);
+    const int np = (N + NB - 1) / NB;
+    __syncthreads();
+    // thread (row = lane, vector = wid + NW k) in the diagonal-block products
+    for (int p = 0; p < np; ++p) {
+        const int k0 = p * NB;
+        const int nb = min(NB, N - k0);
+        if (tid < NV && (p & 1) == 0) replay_pivots(xs + tid * ldx, piv, k0, nb);
+        __syncthreads();
+        const cpx<T>* D = Lb + (int64_t)p * NB * NB;
+        {
+            zd y[(NV + NW - 1) / NW];
+#pragma unroll
+            for (int k = 0; k < (NV + NW - 1) / NW; ++k) {
+                const int u = wid + NW * k;
+                if (u < NV && lane < nb) {
+                    zd t = xs[u * ldx + k0 + lane];
+                    for (int c = 0; c < lane; ++c) {
+                        const cpx<T> l = D[c * NB + lane];
+                        t = cfma(t, cmk((double)l.re, (double)l.im), xs[u * ldx + k0 + c]);
+                    }
+                    y[k] = t;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < (NV + NW - 1) / NW; ++k) {
+                const int u = wid + NW * k;
+                if (u < NV && lane < nb) xs[u * ldx + k0 + lane] = y[k];
+            }
+            __syncthreads();
+        }
+        if ((p & 1) == 0 && p + 1 < np) {
+            if (tid < NV) replay_pivots(xs + tid * ldx, piv, k0 + NB, min(NB, N - k0 - NB));
+            __syncthreads();
+        }
+        for (int i = k0 + nb + tid; i < N; i += SM_TH) {
+            const cpx<T>* Li = LU + (int64_t)k0 * N + i;
+            zd sv[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) sv[u] = cmk(0.0, 0.0);
+            int c = 0;
+            for (; c + 4 <= nb; c += 4) {
+                cpx<T> l4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) l4[e] = Li[(int64_t)(c + e) * N];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const zd l = cmk((double)l4[e].re, (double)l4[e].im);
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) sv[u] = cfma(sv[u], l, xs[u * ldx + k0 + c + e]);
+                }
+            }
+            for (; c < nb; ++c) {
+                const cpx<T> l1 = Li[(int64_t)c * N];
+                const zd l = cmk((double)l1.re, (double)l1.im);
+#pragma unroll
+                for (int u = 0; u < NV; ++u) sv[u] = cfma(sv[u], l, xs[u * ldx + k0 + c]);
+            }
+#pragma unroll
+            for (int u = 0; u < NV; ++u) xs[u * ldx + i] = csub(xs[u * ldx + i], sv[u]);
+        }
+        __syncthreads();
+    }
+    for (int p = np - 1; p >= 0; --p) {
+        const int k0 = p * NB;
+        const int nb = min(NB, N - k0);
+        const int c0 = k0 + nb;
+        {
+            zd sv[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) sv[u] = cmk(0.0, 0.0);
+            if (lane < nb) {
+                const cpx<T>* Ur = LU + k0 + lane;
+                int c = c0 + wid;
+                for (; c + 3 * NW < N; c += 4 * NW) {
+                    cpx<T> u4[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) u4[e] = Ur[(int64_t)(c + e * NW) * N];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const zd uu = cmk((double)u4[e].re, (double)u4[e].im);
+#pragma unroll
+                        for (int u = 0; u < NV; ++u) sv[u] = cfma(sv[u], uu, xs[u * ldx + c + e * NW]);
+                    }
+                }
+                for (; c < N; c += NW) {
+                    const cpx<T> u1 = Ur[(int64_t)c * N];
+                    const zd uu = cmk((double)u1.re, (double)u1.im);
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) sv[u] = cfma(sv[u], uu, xs[u * ldx + c]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NV; ++u) part[(wid * NV + u) * NB + lane] = sv[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < (NV + NW - 1) / NW; ++k) {
+            const int u = wid + NW * k;
+            if (u < NV && lane < nb) {
+                zd t = xs[u * ldx + k0 + lane];
+                for (int w = 0; w < NW; ++w) t = csub(t, part[(w * NV + u) * NB + lane]);
+                rhs[u * NB + lane] = t;
+            }
+        }
+        __syncthreads();
+        const cpx<T>* D = Lb + (int64_t)p * NB * NB;
+#pragma unroll
+        for (int k = 0; k < (NV + NW - 1) / NW; ++k) {
+            const int u = wid + NW * k;
+            if (u < NV && lane < nb) {
+                zd y = cmk(0.0, 0.0);
+                for (int c = lane; c < nb; ++c) {
+                    const cpx<T> d = D[c * NB + lane];
+                    y = cfma(y, cmk((double)d.re, (double)d.im), rhs[u * NB + c]);
+                }
+                xs[u * ldx + k0 + lane] = y;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        if (!live[u]) continue;
+        if (acc) {
+            zd* ab = acc + (int64_t)(q0 + u) * grp.sacc + vo;
+            for (int i = tid; i < N; i += SM_TH) ab[i] = cadd(ab[i], xs[u * ldx + i]);
+        } else {
+            zd* vb = v + (int64_t)(q0 + u) * grp.sv + vo;
+            for (int i = tid; i < N; i += SM_TH) vb[i] = xs[u * ldx + i];
+        }
+    }
+}
+
+template <typename T, int NV>
+static size_t solve_multi_lds(int ldx) {
+    return sizeof(zd) * ((size_t)NV * ldx + (size_t)(SM_TH / 64) * NV * NB + (size_t)NV * NB);
+}
+
 // r = g - A x with the FP64 column-major matrix; norms[2b] = ||r||_2,
 // norms[2b+1] = ||g||_2.  Marks done[b] (and sweeps[b] = sweep) once
 // ||r|| <= tol ||g||.  Matrices already done are skipped.  pending (optional)
@@ -331,6 +522,138 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
     }
 }
 
+// The residuals of a whole group in one pass over A: r_q = g_q - A x_q for
+// the n <= FHW_INC_GROUP vectors of the group (vector q at x + q sx, ...),
+// each matrix entry loaded once for all of them.  Grid (matrix, 256-row
+// block), one row per thread; x staged in LDS RM_CH columns at a time for all
+// vectors.  Norms, flags and the block-counter protocol as k_residual, per
+// vector: a matrix is skipped when every vector of the group is done, and a
+// vector already done keeps its flags (its norms are recomputed from the same
+// x, in the same order, so they are unchanged).
+#define RM_CH 128
+__global__ __launch_bounds__(SOLVE_THREADS) void k_residual_multi(const int* __restrict__ Ns,
+                                                                const int64_t* __restrict__ a_off,
+                                                                const int64_t* __restrict__ v_off,
+                                                                const zd* __restrict__ Abase,
+                                                                const zd* __restrict__ x, const zd* __restrict__ g,
+                                                                zd* __restrict__ r, double* __restrict__ part,
+                                                                int* __restrict__ count, int nblk_max,
+                                                                double* __restrict__ norms, double tol,
+                                                                int* __restrict__ done, int* __restrict__ sweeps,
+                                                                int sweep, int* __restrict__ pending, fhw_grp grp) {
+    constexpr int G = FHW_INC_GROUP;
+    __shared__ zd xs[G][RM_CH];
+    __shared__ double wred[G][2][SOLVE_THREADS / 64];
+    __shared__ int last;
+    const int n = grp.n;
+    const int b = blockIdx.x;
+    if (done) {
+        bool all = true;
+        for (int q = 0; q < n; ++q) all = all && done[q * grp.sflag + b];
+        if (all) return;
+    }
+    const int N = Ns[b];
+    const int nblk = (N + SOLVE_THREADS - 1) / SOLVE_THREADS;
+    const int yb = blockIdx.y;
+    if (yb >= nblk) return;
+    const zd* A = Abase + a_off[b];
+    const int64_t vo = v_off[b];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int i = yb * SOLVE_THREADS + tid;
+    zd s[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) s[q] = cmk(0.0, 0.0);
+    for (int c0 = 0; c0 < N; c0 += RM_CH) {
+        const int cnt = min(RM_CH, N - c0);
+        __syncthreads();
+        for (int e = tid; e < n * cnt; e += SOLVE_THREADS) {
+            const int q = e / cnt, c = e - q * cnt;
+            xs[q][c] = x[q * grp.sx + vo + c0 + c];
+        }
+        __syncthreads();
+        if (i < N) {
+            const zd* Ac = A + (int64_t)c0 * N + i;
+            int c = 0;
+            for (; c + 4 <= cnt; c += 4) {
+                zd a4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a4[u] = Ac[(int64_t)(c + u) * N];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        if (q < n) s[q] = cfma(s[q], a4[u], xs[q][c + u]);
+                }
+            }
+            for (; c < cnt; ++c) {
+                const zd a = Ac[(int64_t)c * N];
+#pragma unroll
+                for (int q = 0; q < G; ++q)
+                    if (q < n) s[q] = cfma(s[q], a, xs[q][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        if (q >= n) break;
+        double rr = 0.0, gg = 0.0;
+        if (i < N) {
+            const zd gi = g[q * grp.sg + vo + i];
+            const zd ri = csub(gi, s[q]);
+            r[q * grp.sr + vo + i] = ri;
+            rr = ri.re * ri.re + ri.im * ri.im;
+            gg = gi.re * gi.re + gi.im * gi.im;
+        }
+        rr = wave_sum(rr);
+        gg = wave_sum(gg);
+        if (lane == 0) {
+            wred[q][0][wid] = rr;
+            wred[q][1][wid] = gg;
+        }
+    }
+    __syncthreads();
+    if (tid < n) {
+        const int q = tid;
+        double rr = 0.0, gg = 0.0;
+        for (int w = 0; w < SOLVE_THREADS / 64; ++w) {
+            rr += wred[q][0][w];
+            gg += wred[q][1][w];
+        }
+        double* pb = part + q * grp.spart + 2 * ((int64_t)b * nblk_max + yb);
+        pb[0] = rr;
+        pb[1] = gg;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        last = (atomicAdd(&count[b], 1) == nblk - 1);
+    }
+    __syncthreads();
+    if (last && tid < n) {
+        __threadfence();
+        const int q = tid;
+        double R2 = 0.0, G2 = 0.0;
+        const double* pb = part + q * grp.spart + 2 * (int64_t)b * nblk_max;
+        for (int k = 0; k < nblk; ++k) {
+            R2 += pb[2 * k];
+            G2 += pb[2 * k + 1];
+        }
+        double* nq = norms + q * grp.snorm;
+        nq[2 * b] = sqrt(R2);
+        nq[2 * b + 1] = sqrt(G2);
+        if (done && !done[q * grp.sflag + b]) {
+            if (R2 <= tol * tol * G2) {
+                done[q * grp.sflag + b] = 1;
+                if (sweeps) sweeps[q * grp.sflag + b] = sweep;
+            } else if (pending) {
+                atomicAdd(pending, 1);
+            }
+        }
+    }
+    if (last && tid == 0) count[b] = 0;
+}
+
 __global__ void k_c128_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -346,6 +669,44 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
                                const int32_t* piv, const void* linv, void* x, void* acc, const int32_t* d_skip,
                                int precision, const fhw_grp& grp) {
     if (grp.n < 1 || grp.n > 65535) return hipErrorInvalidValue;
+    // several vectors on a large batch: one pass over each matrix's factors
+    // per run of FHW_SM_NV vectors (or half as many), when their LDS fits the
+    // device's limit
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 0;
+    constexpr int NV1 = FHW_SM_NV, NV2 = FHW_SM_NV / 2;
+    const int nv_fit = solve_multi_lds<double, NV1>(maxN) <= (size_t)lds_max                ? NV1
+                       : NV2 > 1 && solve_multi_lds<double, NV2>(maxN) <= (size_t)lds_max ? NV2
+                                                                                            : 1;
+    if (grp.n > 1 && b.batch > 256 && nv_fit > 1) {
+        static std::atomic<uint64_t> mattr{0};
+        fhw_once_on_device(mattr, [&] {
+            const int dyn = lds_max;
+            (void)hipFuncSetAttribute((const void*)k_lu_solve_multi<double, NV1>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+            (void)hipFuncSetAttribute((const void*)k_lu_solve_multi<double, NV2>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+            (void)hipFuncSetAttribute((const void*)k_lu_solve_multi<float, NV1>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+            (void)hipFuncSetAttribute((const void*)k_lu_solve_multi<float, NV2>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        });
+        const int ldx = maxN;
+#define FHW_SOLVE_M(TT, NVV)                                                                                   \
+    hipLaunchKernelGGL((k_lu_solve_multi<TT, NVV>), dim3(b.batch, (grp.n + NVV - 1) / NVV), dim3(SM_TH),       \
+                       (solve_multi_lds<TT, NVV>(ldx)), s, b.N, b.a_off, b.piv_off, b.linv_off, b.v_off,        \
+                       (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, d_skip, ldx, grp)
+        const bool full = nv_fit == NV1;
+        if (precision == FHW_FP64) {
+            if (full) FHW_SOLVE_M(double, NV1); else FHW_SOLVE_M(double, NV2);
+        } else {
+            if (full) FHW_SOLVE_M(float, NV1); else FHW_SOLVE_M(float, NV2);
+        }
+#undef FHW_SOLVE_M
+        return hipGetLastError();
+    }
     size_t lds = (size_t)maxN * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
     fhw_once_on_device(attr, [&] {
@@ -381,6 +742,15 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
         (void)hipFuncSetAttribute((const void*)k_residual<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_residual<4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     });
+    // a group of several vectors on a batch wide enough to fill the device:
+    // one pass over each matrix for all of them
+    if (grp.n > 1 && grp.n <= FHW_INC_GROUP && (int64_t)b.batch * ((maxN + 255) / 256) >= 512) {
+        const int nblk = (maxN + SOLVE_THREADS - 1) / SOLVE_THREADS;
+        hipLaunchKernelGGL(k_residual_multi, dim3(b.batch, nblk), dim3(SOLVE_THREADS), 0, s, b.N, b.a_off, b.v_off,
+                           (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,
+                           sweeps, sweep, pending, grp);
+        return hipGetLastError();
+    }
     // 256-row blocks when they alone give >= 1024 workgroups, else 64-row blocks
     const bool wide = (int64_t)b.batch * grp.n * ((maxN + 255) / 256) >= 1024;
     const int rows = wide ? SOLVE_THREADS : SOLVE_THREADS / 4;

@@ -129,23 +129,45 @@ __global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __re
     for (int64_t c0 = n_lo; c0 <= n_hi; c0 += BW_CHUNK) {
         const int cnt = (int)min<int64_t>(BW_CHUNK, n_hi - c0 + 1);
         __syncthreads();
-        for (int e = threadIdx.x; e < BW_SYS * cnt; e += SYN_THREADS) {
-            const int u = e / cnt, i = e - u * cnt;
-            zd v = cmk(0.0, 0.0);
-            if (u < ns) {
-                const double tau = t0 + dt * (double)(c0 + i) - sk;
-                const double w = fhw_window(tau, H);
-                double sn, cs;
-                sincos(items[j0 + u].kappa * c * tau, &sn, &cs);
-                v = cmk(w * cs, w * sn);
+        // one sample per thread: its window weight once, the group's phases
+        for (int i = threadIdx.x; i < cnt; i += SYN_THREADS) {
+            const double tau = t0 + dt * (double)(c0 + i) - sk;
+            const double w = fhw_window(tau, H);
+#pragma unroll
+            for (int u = 0; u < BW_SYS; ++u) {
+                zd v = cmk(0.0, 0.0);
+                if (u < ns && w != 0.0) {
+                    double sn, cs;
+                    sincos(items[j0 + u].kappa * c * tau, &sn, &cs);
+                    v = cmk(w * cs, w * sn);
+                }
+                E[u][i] = v;
             }
-            E[u][i] = v;
         }
         __syncthreads();
         if (node < N) {
             const double* bp = b + c0 * (int64_t)N + node;
             const double* dp = db + c0 * (int64_t)N + node;
-            for (int i = 0; i < cnt; ++i) {
+            int i = 0;
+            // four samples' loads in flight before their products
+            for (; i + 4 <= cnt; i += 4) {
+                double bv[4], dv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bv[k] = bp[(int64_t)(i + k) * N];
+                    dv[k] = dp[(int64_t)(i + k) * N];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                    for (int u = 0; u < BW_SYS; ++u) {
+                        const zd e = E[u][i + k];
+                        aB[u] = cmk(fma(bv[k], e.re, aB[u].re), fma(bv[k], e.im, aB[u].im));
+                        aD[u] = cmk(fma(dv[k], e.re, aD[u].re), fma(dv[k], e.im, aD[u].im));
+                    }
+                }
+            }
+            for (; i < cnt; ++i) {
                 const double bv = bp[(int64_t)i * N], dv = dp[(int64_t)i * N];
 #pragma unroll
                 for (int u = 0; u < BW_SYS; ++u) {

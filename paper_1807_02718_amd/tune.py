@@ -1,9 +1,11 @@
 """Autotuner of the LU panel kernel's tile shape (sub-panel width W and waves
 per SIMD) per precision, workgroup size and rows per thread.
 
-    python -m paper_1807_02718_amd.tune build     # CPU: variant libraries
-    python -m paper_1807_02718_amd.tune measure   # GPU: time them
-    python -m paper_1807_02718_amd.tune write     # CPU: csrc/panel_table.h
+    python -m paper_1807_02718_amd.tune build [jobs] [families]   # CPU: variant libraries
+    python -m paper_1807_02718_amd.tune measure [all|big]          # GPU: time them
+    python -m paper_1807_02718_amd.tune write [results.json]       # CPU: csrc/panel_table.h
+(families: PB, 1024 or both, comma-separated; big times the kite at N = 1024
+with 1024 frequencies only, the shape of the PB cases)
     python -m paper_1807_02718_amd.tune gemm-build | gemm-measure | gemm-write
         the same for the GEMM kernel (k_lu_gemm): K-chunk and workgroups per CU
         per precision, timed as the update + TRSM stages of the kite batch at
@@ -14,8 +16,9 @@ Each variant differs from the current table (csrc/panel_table.h) in one case,
 set to one candidate whose registers fit without spilling (checked from the
 compiler's resource report). `measure` times the panel stage of
 fhw_solve_densities with the library's own HIP-event timers on the kite: for the
-256-thread cases (batches above 256 matrices) N = 1024 with 1024 frequencies,
-whose shrinking panels pass through R = 4, 2 and 1; for the 1024-thread cases
+large-batch cases (batches above 256 matrices: workgroup size 256, 512 or 1024,
+W and waves per SIMD) N = 1024 with 1024 frequencies, whose shrinking panels
+pass through R = 4, 2 and 1 rows per 256 threads; for the 1024-thread cases
 the sum of N = 1024 with 64 frequencies (R = 1) and N = 4096 with 16
 frequencies (R = 4, 2, 1).  `write` keeps, per case, the fastest variant if it
 beats the current table by more than 1%.  The R = 8 and 16 shapes (256
@@ -36,51 +39,64 @@ CSRC = os.path.join(HERE, "csrc")
 TUNE = os.path.join(HERE, "_tune")
 TABLE = os.path.join(CSRC, "panel_table.h")
 
-# candidate (W, waves per SIMD) per case; the spill check drops the rest
+# candidate values per case family; the spill check drops the rest.  1024:
+# batches of at most 256 matrices, (W, waves per SIMD) at 1024 threads; PB:
+# larger batches, (threads, W, waves per SIMD, columns in flight PD).  An
+# earlier sweep of PB over 512 and 1024 threads and W = 4 and 16 found every
+# such shape slower than 256 threads with W = 8 (profiles/), so this one
+# varies the occupancy and the lazy loads in flight.
 CANDIDATES = {
-    256: [(4, 4), (4, 2), (8, 4), (8, 2), (16, 2)],
     1024: [(4, 4), (8, 4), (16, 4)],
+    "PB": [(256, 8, e, d) for e in (4, 3, 2) for d in (0, 1, 2, 4, 8)],
 }
-CASES = [(p, pt, r) for p in ("F32", "F64") for pt in (256, 1024) for r in (1, 2, 4)]
+CASES = [(p, pt, r) for p in ("F32", "F64") for pt in ("PB", 1024) for r in (1, 2, 4)]
 
 
 def case_name(p, pt, r):
-    return f"FHW_PT_{p}_{pt}_R{r}"
+    return f"FHW_PB_{p}_R{r}" if pt == "PB" else f"FHW_PT_{p}_{pt}_R{r}"
 
 
 def read_table(path=TABLE):
     tab = {}
-    for m in re.finditer(r"#define (FHW_PT_\w+) (\d+), (\d+)", open(path).read()):
-        tab[m.group(1)] = (int(m.group(2)), int(m.group(3)))
+    for m in re.finditer(r"#define (FHW_P[TB]_\w+) (\d+(?:, \d+)+)", open(path).read()):
+        tab[m.group(1)] = tuple(int(x) for x in m.group(2).split(", "))
     return tab
 
 
 def write_table(tab, path=TABLE):
     src = open(TABLE).read()
-    for name, (w, e) in tab.items():
-        src = re.sub(rf"#define {name} \d+, \d+", f"#define {name} {w}, {e}", src)
+    for name, vals in tab.items():
+        src = re.sub(rf"#define {name} \d+(?:, \d+)+", f"#define {name} " + ", ".join(str(v) for v in vals), src)
     open(path, "w").write(src)
 
 
-def variants():
-    """name -> (table, changed case or None)."""
+def variants(families=None):
+    """name -> (table, changed case or None); families limits the swept cases."""
     base = read_table()
     out = {"base": (dict(base), None)}
     for p, pt, r in CASES:
+        if families and str(pt) not in families:
+            continue
         name = case_name(p, pt, r)
-        for w, e in CANDIDATES[pt]:
-            if (w, e) == base[name]:
-                continue
+        for cand in CANDIDATES[pt]:
+            if tuple(cand) == base[name] or (pt == "PB" and cand[0] > 256 * r):
+                continue   # the current value, or more threads than panel rows
             t = dict(base)
-            t[name] = (w, e)
-            out[f"{name}_W{w}_E{e}"] = (t, (p, pt, r))
+            t[name] = tuple(cand)
+            out[f"{name}_" + "_".join(str(v) for v in cand)] = (t, (p, pt, r))
     return out
 
 
-def _spill_free(report, p, pt, r, w, e):
+def _spill_free(report, p, pt, r, *vals):
     """The panel instantiation of this case compiled without VGPR spills."""
     T = "f" if p == "F32" else "d"
-    key = f"k_lu_panelI{T}Li{r}ELi{w}ELi{e}ELi{pt}E"
+    if pt == "PB":
+        threads, w, e, d = vals
+        rows = (256 * r + threads - 1) // threads
+        key = f"k_lu_panelI{T}Li{rows}ELi{w}ELi{e}ELi{threads}ELi{d}E"
+    else:
+        w, e = vals
+        key = f"k_lu_panelI{T}Li{r}ELi{w}ELi{e}ELi{pt}ELi0E"
     blocks = report.split("Function Name: ")
     for b in blocks:
         if b.startswith("_Z10") and key in b.split()[0]:
@@ -89,13 +105,13 @@ def _spill_free(report, p, pt, r, w, e):
     return False
 
 
-def build(jobs=4):
+def build(jobs=4, families=None):
     from . import build as B
     B.build(jobs=jobs)   # the other objects, current table
     objs = [os.path.join(B.BUILD, s.replace(".hip", ".o")) for s in B.SOURCES if s != "lu.hip"]
     shutil.rmtree(TUNE, ignore_errors=True)
     os.makedirs(TUNE)
-    vs = variants()
+    vs = variants(families)
 
     def one(item):
         name, (tab, case) = item
@@ -133,8 +149,9 @@ import torch
 from paper_1807_02718_amd import fhw
 import workloads as Wk
 out = {}
+shapes = ((1024, 1024), (64, 1024), (16, 4096)) if sys.argv[3] == "all" else ((1024, 1024),)
 for prec in ("fp32_refine", "fp64"):
-    for F, N in ((1024, 1024), (64, 1024), (16, 4096)):
+    for F, N in shapes:
         wl = Wk.kite_n1024(F=F)
         ctx = fhw.Context()
         ctx.plan(wl.curve, wl.W, F, N=N, precision=prec, refine_tol=1e-12, refine_max=10, direction=wl.direction)
@@ -152,14 +169,17 @@ print(json.dumps(out), flush=True)
 """
 
 
-def measure():
+def measure(shapes="all"):
+    """Time every built variant; shapes = "all" (the three kite shapes) or
+    "big" (N = 1024 at 1024 frequencies only: the large-batch cases)."""
     root = os.path.dirname(HERE)
     res = {}
     for name in sorted(os.listdir(TUNE)):
         d = os.path.join(TUNE, name)
         if not os.path.isfile(os.path.join(d, "table.json")):
             continue
-        r = subprocess.run([sys.executable, "-c", _TIMER, d, root], capture_output=True, text=True, timeout=300)
+        r = subprocess.run([sys.executable, "-c", _TIMER, d, root, shapes], capture_output=True, text=True,
+                           timeout=300)
         line = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
         if r.returncode or not line:
             print(f"{name}: failed ({r.stderr.strip()[-200:]})", flush=True)
@@ -169,21 +189,23 @@ def measure():
     json.dump(res, open(os.path.join(TUNE, "results.json"), "w"), indent=1)
 
 
-def write():
-    res = json.load(open(os.path.join(TUNE, "results.json")))
+def write(results=None):
+    res = json.load(open(results or os.path.join(TUNE, "results.json")))
     base = res["base"]
     tab = {k: tuple(v) for k, v in base["table"].items()}
     for p, pt, r in CASES:
         name = case_name(p, pt, r)
+        if not all(k in base["ms"] for k in (["fp32_refine_1024_1024"] if pt == "PB" else ["fp32_refine_64_1024"])):
+            continue   # not timed in this sweep
         prec = "fp32_refine" if p == "F32" else "fp64"
-        keys = [f"{prec}_1024_1024"] if pt == 256 else [f"{prec}_64_1024", f"{prec}_16_4096"]
+        keys = [f"{prec}_1024_1024"] if pt == "PB" else [f"{prec}_64_1024", f"{prec}_16_4096"]
 
         def cost(v):
             return sum(v["ms"][k] for k in keys)
 
         best, best_ms = tab[name], cost(base)
         for vn, v in res.items():
-            if vn.startswith(name + "_W") and cost(v) < best_ms * 0.99:
+            if vn.startswith(name + "_") and cost(v) < best_ms * 0.99:
                 best, best_ms = tuple(v["table"][name]), cost(v)
         if best != tab[name]:
             print(f"{name}: {tab[name]} -> {best} ({cost(base):.3f} -> {best_ms:.3f} ms panel stage)")
@@ -364,11 +386,11 @@ def gemm_write(results=None):
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else ""
     if cmd == "build":
-        build(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+        build(int(sys.argv[2]) if len(sys.argv) > 2 else 4, sys.argv[3].split(",") if len(sys.argv) > 3 else None)
     elif cmd == "measure":
-        measure()
+        measure(sys.argv[2] if len(sys.argv) > 2 else "all")
     elif cmd == "write":
-        write()
+        write(sys.argv[2] if len(sys.argv) > 2 else None)
     elif cmd == "gemm-build":
         gemm_build(int(sys.argv[2]) if len(sys.argv) > 2 else 4)
     elif cmd == "gemm-measure":
