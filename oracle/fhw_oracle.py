@@ -37,7 +37,7 @@ __all__ = [
     "graded_mesh", "clenshaw_curtis_nodes", "lowfreq_frequencies", "chebyshev_moments",
     "fcc_integral", "gram_basis", "fc_gram_tables", "fc_continuation", "fc_coefficients",
     "fc_integral", "synthesize_lowfreq", "boundary_window_transforms", "synthesize_windowed",
-    "run_general",
+    "synthesize_lowfreq_windowed", "assemble_dirichlet", "field_dirichlet", "run_general",
 ]
 
 
@@ -234,6 +234,62 @@ def field(geom, psi, kappa: float, obs):
     z = kappa * rr
     G = 0.25j * (special.j0(z) + 1j * special.y0(z))
     return (2 * np.pi / N) * (G * speed[None, :]) @ psi
+
+
+def assemble_dirichlet(geom, kappa: float, eta: float):
+    """A_ij for  (1/2) phi + K phi - i eta S phi  (the combined double- and
+    single-layer potential u = int [dG/dnu_y - i eta G] phi dsigma_y for an
+    exterior Dirichlet problem with arbitrary data, Colton & Kress Sec. 3.2,
+    discretized by the same Kress split as assemble): the double-layer kernel
+      L = (i kappa / 4) H1(kappa r) (nu_j . (x_i - x_j)) / r
+    takes the source normal nu_j where the direct equation's adjoint kernel
+    takes the target normal; L1 = -(kappa/(4 pi)) J1(kappa r) (nu_j . (x_i -
+    x_j))/r, and the diagonal limits are those of assemble (L2_ii is the
+    curvature term for both kernels)."""
+    x, nu, speed, ddx = geom["x"], geom["nu"], geom["speed"], geom["ddx"]
+    N = len(speed)
+    n = N // 2
+    R = kress_weights(N)
+    Lam = kress_log_table(N)
+    lidx = (np.arange(N)[:, None] - np.arange(N)[None, :]) % N
+    d = x[None, :, :] - x[:, None, :]                 # d[i, j] = x_j - x_i
+    r = np.hypot(d[..., 0], d[..., 1])
+    diag = np.eye(N, dtype=bool)
+    r_safe = np.where(diag, 1.0, r)
+    z = kappa * r_safe
+    J0, Y0, J1, Y1 = special.j0(z), special.y0(z), special.j1(z), special.y1(z)
+    nud = -(nu[None, :, 0] * d[..., 0] + nu[None, :, 1] * d[..., 1])   # nu_j . (x_i - x_j)
+    logt = Lam[lidx]
+    M = 0.25j * (J0 + 1j * Y0)
+    M1 = -J0 / (4 * np.pi)
+    M2 = M - M1 * logt
+    L = 0.25j * kappa * (J1 + 1j * Y1) * nud / r_safe
+    L1 = -(kappa / (4 * np.pi)) * J1 * nud / r_safe
+    L2 = L - L1 * logt
+    M1[diag] = -1.0 / (4 * np.pi)
+    M2[diag] = 0.25j - (0.57721566490153286061 + np.log(kappa * speed / 2)) / (2 * np.pi)
+    L1[diag] = 0.0
+    L2[diag] = (nu[:, 0] * ddx[:, 0] + nu[:, 1] * ddx[:, 1]) / (4 * np.pi * speed ** 2)
+    A = (R[lidx] * (L1 - 1j * eta * M1) + (np.pi / n) * (L2 - 1j * eta * M2)) * speed[None, :]
+    A[diag] += 0.5
+    return A
+
+
+def field_dirichlet(geom, phi, kappa: float, eta: float, obs):
+    """U(r) = int [dG(r, y)/dnu_y - i eta G(r, y)] phi(y) dsigma_y by the
+    trapezoidal rule in the parameter (r away from Gamma), G = (i/4) H0:
+    (2 pi/N) sum_j |x'_j| [ (i kappa/4) H1(kappa rho) nu_j . (r - x_j)/rho
+    + (eta/4) H0(kappa rho) ] phi_j,  rho = |r - x_j|."""
+    x, nu, speed = geom["x"], geom["nu"], geom["speed"]
+    N = len(speed)
+    obs = np.asarray(obs, dtype=np.float64)
+    dd = obs[:, None, :] - x[None, :, :]
+    rho = np.hypot(dd[..., 0], dd[..., 1])
+    z = kappa * rho
+    H0 = special.j0(z) + 1j * special.y0(z)
+    H1 = special.j1(z) + 1j * special.y1(z)
+    dl = 0.25j * kappa * H1 * (nu[None, :, 0] * dd[..., 0] + nu[None, :, 1] * dd[..., 1]) / rho
+    return (2 * np.pi / N) * ((dl + 0.25 * eta * H0) * speed[None, :]) @ phi
 
 
 def field_full_grid(V_pos, zero_value):
@@ -701,34 +757,80 @@ def synthesize_windowed(V_k, ks, H, tau0, W, times):
     return u
 
 
-def run_general(curve, W, F, N, b, db, t0, dt, H, tau0, obs, times, c=1.0):
-    """The whole path for a general incident field (eq. bkdef2): boundary
-    data b(x_i, t) = -u_inc and its normal derivative db(x_i, t) = -d_nu
-    u_inc sampled at the N nodes (fixed N at every frequency); per window k
-    the recentred transforms B_k, DB_k at every solve frequency, the density
-    of eq. CFIE_direct with right-hand side DB_k - i eta B_k, its field, and
-    the synthesis of every window's own field (synthesize_windowed).  The
-    zero-frequency sample of each window's field is taken as 0 (the windowed
-    data must have no content at omega = 0).  Returns (u, ks)."""
-    omega, kappa = frequency_grid(W, F, c)
-    eta = coupling(kappa)
+def synthesize_lowfreq_windowed(V_k, V_k_sing, ks, H, tau0, W, F, jc, M, n, q, times, fc_d=10, fc_C=25):
+    """synthesize_lowfreq with each window's own field (general boundary
+    data): F_k(w) = V_k(r, w) e^{-i w tau0} (the windowed data already inside
+    V_k, no spectrum factor), I_+ from its FC(Gram) continuation on the grid
+    of [omega_c, W] and I_0 by the graded Filon-Clenshaw-Curtis rule, summed
+    over all windows at every time.  V_k: [K][Nr][2F] on the DFT grid;
+    V_k_sing: [K][Nr][M][n+1] at the nodes of lowfreq_frequencies."""
+    omega_c, smooth, mu, nodes = lowfreq_frequencies(W, F, jc, M, n, q)
+    A, Q = fc_gram_tables(fc_d, fc_C)
+    K, Nr = V_k.shape[0], V_k.shape[1]
+    idx = F + jc + np.arange(F - jc + 1)
+    inside = idx < 2 * F
+    times = np.asarray(times, dtype=np.float64)
+    u = np.zeros((Nr, len(times)))
+    es = np.exp(-1j * smooth * tau0)
+    en = [np.exp(-1j * nodes[j] * tau0) for j in range(M)]
+    for qw, k in enumerate(ks):
+        tp = times - window_center(k, H) - tau0
+        Vs = np.empty((Nr, len(smooth)), dtype=np.complex128)
+        Vs[:, inside] = V_k[qw][:, idx[inside]]
+        Vs[:, ~inside] = np.conj(V_k[qw][:, 0])[:, None]
+        for r in range(Nr):
+            c = fc_coefficients(es * Vs[r], A, Q)
+            I = fc_integral(c, omega_c, W / F, len(smooth), tp)
+            for j in range(M):
+                I = I + fcc_integral(en[j] * V_k_sing[qw, r, j], mu[j], mu[j + 1], n, tp)
+            u[r] += I.real / np.pi
+    return u
+
+
+def run_general(curve, W, F, N, b, t0, dt, H, tau0, obs, times, c=1.0, lowfreq=None):
+    """The whole path for a general incident field (eq. bkdef2): Dirichlet
+    data b(x_i, t) = -u_inc sampled at the N nodes (fixed N at every
+    frequency); per window k the recentred transforms B_k at every solve
+    frequency, the exterior Dirichlet problem with data B_k by the combined
+    potential (assemble_dirichlet, field_dirichlet: the windowed data w_k b
+    are not the trace of a wave, so the direct equation's right-hand side
+    does not apply to them), and the synthesis of every window's own field
+    (synthesize_windowed).  The zero-frequency sample of each window's field
+    is taken as 0.  lowfreq = dict(jc, M, n, q): the same at the graded
+    Clenshaw-Curtis frequencies too, synthesized by
+    synthesize_lowfreq_windowed (the value at omega = 0, the first node,
+    again 0: it enters the rule only through the first subinterval, of width
+    mu_1 ~ 1e-11 omega_c).  b: [N][n_t].  Returns (u, ks)."""
     gm = geometry(curve, N)
     t_hi = t0 + dt * (np.asarray(b).shape[1] - 1)
     ks = window_indices(t0, t_hi, H)
-    Bk = boundary_window_transforms(b, t0, dt, H, ks, omega)
-    DBk = boundary_window_transforms(db, t0, dt, H, ks, omega)
+
+    def window_fields(om):
+        """V_k(r, om) for every window, [K][Nr][len(om)] (0 at om = 0)."""
+        ka = np.asarray(om) / c
+        et = coupling(np.where(ka > 0, ka, 1.0))
+        Bk = boundary_window_transforms(b, t0, dt, H, ks, om)
+        out = np.zeros((len(ks), len(obs), len(om)), dtype=np.complex128)
+        for j in range(len(om)):
+            if ka[j] == 0.0:
+                continue
+            lu = linalg.lu_factor(assemble_dirichlet(gm, ka[j], et[j]))
+            for qw in range(len(ks)):
+                out[qw, :, j] = field_dirichlet(gm, linalg.lu_solve(lu, Bk[qw, j]), ka[j], et[j], obs)
+        return out
+
+    omega, _ = frequency_grid(W, F, c)
+    Vg = window_fields(omega)
     V_k = np.zeros((len(ks), len(obs), 2 * F), dtype=np.complex128)
-    for j in range(F):
-        A = assemble(gm, kappa[j], eta[j])
-        lu = linalg.lu_factor(A)
-        for q in range(len(ks)):
-            g = DBk[q, j] - 1j * eta[j] * Bk[q, j]
-            psi = linalg.lu_solve(lu, g)
-            Vq = field(gm, psi, kappa[j], obs)
-            if j < F - 1:
-                V_k[q, :, F + 1 + j] = Vq
-            V_k[q, :, F - 1 - j] = np.conj(Vq)
-    return synthesize_windowed(V_k, ks, H, tau0, W, times), ks
+    V_k[:, :, F + 1:] = Vg[:, :, : F - 1]
+    V_k[:, :, :F] = np.conj(Vg[:, :, ::-1])
+    if lowfreq is None:
+        return synthesize_windowed(V_k, ks, H, tau0, W, times), ks
+    jc, M, n, q = lowfreq["jc"], lowfreq["M"], lowfreq["n"], lowfreq["q"]
+    _, _, _, nodes = lowfreq_frequencies(W, F, jc, M, n, q)
+    Vn = window_fields(np.concatenate(nodes))
+    V_sing = Vn.reshape(len(ks), len(obs), M, n + 1)
+    return synthesize_lowfreq_windowed(V_k, V_sing, ks, H, tau0, W, F, jc, M, n, q, times), ks
 
 
 # ---------------------------------------------------------------------------

@@ -821,31 +821,61 @@ def test_synthesize_windowed_inverts_a_closed_form_spectrum():
     assert np.max(np.abs(u - ref)) < 1e-9
 
 
+def test_dirichlet_potential_reproduces_an_interior_source_field():
+    """The combined potential solves the exterior Dirichlet problem for any
+    data: with the data of the field of a point source inside the scatterer,
+    B = H0(kappa |x - z|), it must return that field outside, H0(kappa |r -
+    z|), on the kite and the circle at low, middle and high frequency (a
+    wrong normal, sign or weight fails at O(1))."""
+    for curve, N, kappas in ((Wk.kite(), 256, (0.3, 5.0, 12.0)), (Wk.circle(1.0), 128, (0.3, 5.0, 20.0))):
+        gm = O.geometry(curve, N)
+        zs = np.array([0.1, 0.2])
+        obs = Wk.ring(6, 3.0)
+        for kappa in kappas:
+            eta = float(O.coupling(np.array([kappa]))[0])
+            B = special.hankel1(0, kappa * np.hypot(*(gm["x"] - zs).T))
+            phi = np.linalg.solve(O.assemble_dirichlet(gm, kappa, eta), B)
+            U = O.field_dirichlet(gm, phi, kappa, eta, obs)
+            ex = special.hankel1(0, kappa * np.hypot(*(obs - zs).T))
+            assert np.max(np.abs(U - ex)) < 1e-11 * np.max(np.abs(ex)), (curve.name, kappa)
+
+
+def test_dirichlet_matrix_is_the_direct_one_transposed():
+    """In the Nystrom discretization the combined-potential matrix equals
+    D^-1 A^T D, A the direct equation's matrix and D = diag |x'| (the double
+    layer and the adjoint double layer are each other's transposes, with the
+    same diagonal limit; the Kress weights are symmetric in i - j)."""
+    gm = O.geometry(Wk.kite(), 96)
+    D = gm["speed"]
+    for kappa in (0.7, 9.0):
+        eta = float(O.coupling(np.array([kappa]))[0])
+        Ab = O.assemble_dirichlet(gm, kappa, eta)
+        A = O.assemble(gm, kappa, eta)
+        assert np.max(np.abs(Ab - (A.T * D[None, :]) / D[:, None])) < 1e-14 * np.max(np.abs(A))
+
+
 def test_run_general_factorizes_on_separable_data():
-    """Boundary data a(t) beta(x), a(t) delta(x) (separable; beta, delta
-    arbitrary): every window's transform is A_k(w) beta(x), so the path must
-    equal the windowed spectra A_k times the field of the density for the
-    right-hand side delta - i eta beta, synthesized with V(r, 0) = 0.  This
-    fixes the right-hand side (both terms and the sign of eta), the mirrored
-    frequency layout of each window's field and the per-window synthesis."""
+    """Boundary data a(t) beta(x) (separable; beta arbitrary): every window's
+    transform is A_k(w) beta(x), so the path must equal the windowed spectra
+    A_k times the combined potential of the data beta, synthesized with V(r,
+    0) = 0.  This fixes the mirrored frequency layout of each window's field
+    and the per-window synthesis against the plane-path machinery."""
     W, F, N, H, tau0 = 20.0, 64, 24, 3.0, 2.0
     cv = Wk.kite()
     gm = O.geometry(cv, N)
     rng = np.random.default_rng(5)
-    beta, delta = rng.standard_normal(N), rng.standard_normal(N)
+    beta = rng.standard_normal(N)
     sig = Wk.gaussian_pulse(t0=-1.0, t1=10.0, dt=1.0 / 128, freq=5.0)
-    a = -sig.f                                        # the data of the scattered field, b = -f
-    b, db = np.outer(beta, a), np.outer(delta, a)
+    b = np.outer(beta, -sig.f)                        # the data of the scattered field, b = -f beta
     obs = Wk.ring(5, 3.5)
     times = np.linspace(0.0, 30.0, 40)
-    u, ks = O.run_general(cv, W, F, N, b, db, sig.t0, sig.dt, H, tau0, obs, times)
+    u, ks = O.run_general(cv, W, F, N, b, sig.t0, sig.dt, H, tau0, obs, times)
     omega, kappa = O.frequency_grid(W, F)
     eta = O.coupling(kappa)
     Vpos = np.zeros((len(obs), F), dtype=complex)
     for j in range(F):
-        A = O.assemble(gm, kappa[j], eta[j])
-        psi = np.linalg.solve(A, delta - 1j * eta[j] * beta)
-        Vpos[:, j] = O.field(gm, psi, kappa[j], obs)
+        phi = np.linalg.solve(O.assemble_dirichlet(gm, kappa[j], eta[j]), beta)
+        Vpos[:, j] = O.field_dirichlet(gm, phi, kappa[j], eta[j], obs)
     om_l = -W + (W / F) * np.arange(2 * F)
     Bs = O.window_spectra(sig, H, ks, om_l)
     ref, _ = O.synthesize(O.field_full_grid(Vpos, 0.0), Bs, ks, H, tau0, W, times)
@@ -855,20 +885,47 @@ def test_run_general_factorizes_on_separable_data():
 def test_run_general_plane_pulse_matches_the_plane_wave_path():
     """A plane pulse given as general boundary data (windowed at the boundary)
     and the plane-wave path (windowed in the signal) sum to the same field;
-    they differ only by the DFT-grid quadrature near omega = 0 of each
-    window's part (the 2D low-frequency behaviour of Sec. 4.2), here a few
-    1e-5 of max |u| (a dropped term, a sign or a transposed layout is O(1))."""
+    on the DFT grid alone both carry the 2D low-frequency quadrature error of
+    Sec. 4.2 (reading 2's size), so they agree to a few 1e-4 of max |u| (a
+    dropped term, a sign or a transposed layout is O(1))."""
     W, F, N, H, tau0 = 20.0, 256, 64, 4.0, 3.0
     cv = Wk.circle(1.0)
     gm = O.geometry(cv, N)
     wave = dict(amp=1.0, p=(1.0, 0.0), delay=0.0, center=4.0, var2=0.5, freq=12.0)
     t0, dt = -1.0, 1.0 / 256
     n_t = 11 * 256 + 1
-    b, db = Wk.plane_pulses_on_boundary(gm["x"], gm["nu"], [wave], t0, dt, n_t)
+    b, _ = Wk.plane_pulses_on_boundary(gm["x"], gm["nu"], [wave], t0, dt, n_t)
     obs = Wk.ring(8, 3.0)
     times = np.linspace(0.0, 40.0, 64)
-    ug, _ = O.run_general(cv, W, F, N, b.T, db.T, t0, dt, H, tau0, obs, times)
+    ug, _ = O.run_general(cv, W, F, N, b.T, t0, dt, H, tau0, obs, times)
     sig = Wk.Signal(t0, dt, Wk.gaussian_pulse_value(t0 + dt * np.arange(n_t), 4.0, 0.5, 12.0)[0])
     up = O.run(cv, W, F, N, (1.0, 0.0), sig, H, tau0, obs, times)
     err = np.max(np.abs(ug - up)) / np.max(np.abs(up))
-    assert err < 2e-4, err
+    assert err < 5e-4, err
+
+
+def test_run_general_lowfreq_matches_the_exact_circle_series():
+    """The circle configuration's pulse (zero-frequency content 0.014) given
+    as general boundary data, with the low-frequency decomposition (F = 256,
+    omega_c = 1.25, M = 16, n = 8, q = 9.1): every window's exterior
+    Dirichlet problem solved at the grid and graded frequencies (N = 128) and
+    synthesized with synthesize_lowfreq_windowed matches the exact
+    time-domain solution (Bessel series integrated by brute force) to 1e-9
+    relative, where the smooth-only general path is off by ~1e-4."""
+    sig = Wk.gaussian_pulse()
+    obs = Wk.ring(16, 3.0)[::4]
+    robs, thobs = np.hypot(obs[:, 0], obs[:, 1]), np.arctan2(obs[:, 1], obs[:, 0])
+    times = np.linspace(0.0, 40.0, 32)
+    ex = _circle_trace_exact(robs, thobs, times, _pulse_transform)
+    W, F, N, H, tau0 = 20.0, 256, 128, 4.0, 3.0
+    LF = dict(jc=16, M=16, n=8, q=9.1)
+    gm = O.geometry(Wk.circle(1.0), N)
+    wave = dict(amp=1.0, p=(1.0, 0.0), delay=0.0, center=4.0, var2=0.5, freq=6.0)
+    b, _ = Wk.plane_pulses_on_boundary(gm["x"], gm["nu"], [wave], sig.t0, sig.dt, len(sig.f))
+    u_lf, _ = O.run_general(Wk.circle(1.0), W, F, N, b.T, sig.t0, sig.dt, H, tau0, obs, times, lowfreq=LF)
+    u_sm, _ = O.run_general(Wk.circle(1.0), W, F, N, b.T, sig.t0, sig.dt, H, tau0, obs, times)
+    scale = np.max(np.abs(ex))
+    err_lf = np.max(np.abs(u_lf - ex)) / scale
+    err_sm = np.max(np.abs(u_sm - ex)) / scale
+    assert err_lf < 1e-9, err_lf
+    assert err_sm > 1e3 * err_lf, (err_sm, err_lf)
