@@ -299,15 +299,15 @@ def general_bench(fhw, torch, Wk, reps, modes):
     """General incident fields (eq. bkdef2) on the solve-throughput workload's
     systems: kite, N = 1024 at F = 1024 frequencies on (0, 69], factored once;
     24 seeded plane pulses spread over 200 time units (not one plane wave),
-    sampled at the nodes every pi/(4W), H = 10.  Times fhw_solve_general (per
-    window: boundary transforms at every frequency, right-hand sides, solves
-    and refinement on the resident factors; median of reps calls), then the
-    windows' fields at 256 points and their synthesis at 1024 times.  The
-    right-hand-side kernel's roofline: its algorithmic FP64 flops (8 per
-    (window, frequency, node, sample in the window's support): one complex
-    factor times the two real samples of b and its normal derivative) per
-    launch over its average launch time from the stage timers of a profiled
-    call, against the FP64 vector peak."""
+    sampled at the nodes every pi/(4W), H = 10, on a plan of the combined
+    formulation.  Times fhw_solve_general (per window: boundary transforms
+    at every frequency, right-hand sides, solves and refinement on the
+    resident factors; median of reps calls), then the windows' fields at 256
+    points and their synthesis at 1024 times.  The right-hand-side kernel's
+    roofline: its algorithmic FP64 flops (4 per (window, frequency, node,
+    sample in the window's support): one complex factor times one real
+    sample) per launch over its average launch time from the stage timers of
+    a profiled call, against the FP64 vector peak."""
     wl = Wk.kite_n1024()
     gp = Wk.general_pulses()
     H, tau0 = wl.H, wl.tau0
@@ -319,23 +319,23 @@ def general_bench(fhw, torch, Wk, reps, modes):
     for precision in modes:
         ctx = fhw.Context()
         try:
-            ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=1e-12, refine_max=10)
+            ctx.plan(wl.curve, wl.W, wl.F, N=wl.N, precision=precision, refine_tol=1e-12, refine_max=10,
+                     formulation="combined")
             t0 = time.perf_counter()
             ctx.factor()
             t_factor = time.perf_counter() - t0
             g = ctx.geometry(wl.N).cpu().numpy()
-            b, db = Wk.plane_pulses_on_boundary(g[0:2].T, g[7:9].T, gp["waves"], gp["t0"], dt, n_t)
+            b, _ = Wk.plane_pulses_on_boundary(g[0:2].T, g[7:9].T, gp["waves"], gp["t0"], dt, n_t)
             b = torch.as_tensor(b, device="cuda")
-            db = torch.as_tensor(db, device="cuda")
             psi = torch.empty((n_win, int(ctx.psi_off[-1])), dtype=torch.complex128, device="cuda")
             ts = []
             for i in range(reps + 1):
                 t0 = time.perf_counter()
-                _, res, sw, _ = ctx.solve_general(b, db, gp["t0"], dt, H, k_first, n_win, psi=psi)
+                _, res, sw, _ = ctx.solve_general(b, gp["t0"], dt, H, k_first, n_win, psi=psi)
                 if i:
                     ts.append(time.perf_counter() - t0)
             ctx.profile(True)
-            ctx.solve_general(b, db, gp["t0"], dt, H, k_first, n_win, psi=psi)
+            ctx.solve_general(b, gp["t0"], dt, H, k_first, n_win, psi=psi)
             pr = ctx.profile_read()
             ctx.profile(False)
             t0 = time.perf_counter()
@@ -351,7 +351,7 @@ def general_bench(fhw, torch, Wk, reps, modes):
         tn = gp["t0"] + dt * np.arange(n_t)
         n_s = sum(int(np.count_nonzero(np.abs(tn - 1.5 * H * (k - 1.0)) < H))
                   for k in range(k_first, k_first + n_win))
-        flops = 8.0 * wl.F * wl.N * n_s
+        flops = 4.0 * wl.F * wl.N * n_s
         ms_rhs, launches = pr["assemble"]
         achieved = flops / launches / (ms_rhs / launches * 1e-3) / 1e12
         t_solve = float(np.median(ts))

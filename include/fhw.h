@@ -66,6 +66,19 @@ extern "C" {
 #define FHW_FP64 0          /* complex128 LU and solves */
 #define FHW_FP32_REFINE 1   /* complex64 LU on MFMA + FP64-residual refinement */
 
+/* Boundary integral equation of a plan (fhw_problem.formulation). */
+#define FHW_FORM_DIRECT 0   /* the direct combined-field equation (eq.
+                               CFIE_direct): data of an incident wave (plane
+                               waves, point sources); density = normal
+                               derivative of the total field, field = single
+                               layer (eq. freq_domain_repr) */
+#define FHW_FORM_COMBINED 1 /* exterior Dirichlet problem for arbitrary data B:
+                               u = int [dG/dnu_y - i eta G] phi dsigma_y with
+                               (1/2) phi + K phi - i eta S phi = B (K the
+                               double layer; Colton & Kress Sec. 3.2), for the
+                               windowed data of general incident fields (eq.
+                               bkdef2), which are not the trace of a wave */
+
 typedef struct fhw_ctx fhw_ctx;
 
 /* Scatterer boundary as a real trigonometric polynomial in s in [0, 2 pi):
@@ -103,6 +116,13 @@ typedef struct {
      * 1 <= lf_N <= 32, lf_q > 0.  lf_M = 0: none (the smooth-F path only). */
     int32_t lf_M, lf_N, lf_jc;
     double lf_q;
+    /* FHW_FORM_DIRECT (0) or FHW_FORM_COMBINED.  A combined plan (one curve,
+     * j_first = 0, the same N at every frequency; graded low-frequency
+     * systems allowed) serves only fhw_solve_general and the window calls;
+     * the direct calls (fhw_solve_densities, fhw_solve_incidences,
+     * fhw_solve_cached, fhw_solve_range*, fhw_eval_field*, fhw_run) refuse
+     * it with FHW_E_STATE, and the window calls refuse a direct plan. */
+    int32_t formulation;
 } fhw_problem;
 
 /* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL =
@@ -420,14 +440,12 @@ int fhw_synth_active_pairs(fhw_ctx* ctx, int64_t* pairs, int64_t* active);
 
 /* Sampled Dirichlet data of a general incident field on the plan's nodes
  * (Sec. 3.2, eq. bkdef2: the boundary data of the scattered field is b =
- * -u_inc): b(x_i, t_n) and its normal derivative db(x_i, t_n) = -d_nu
- * u_inc(x_i, t_n) at t_n = t0 + n dt, n < n_t, for the N Nystrom nodes x_i of
- * fhw_geometry(ctx, N, ...) (normal nu as there).  b, db: device doubles
- * [n_t][N], time-major (one time's nodes contiguous), caller-owned, read
- * during fhw_solve_general only. */
+ * -u_inc): b(x_i, t_n) at t_n = t0 + n dt, n < n_t, for the N Nystrom nodes
+ * x_i of fhw_geometry(ctx, N, ...).  b: device doubles [n_t][N], time-major
+ * (one time's nodes contiguous), caller-owned, read during
+ * fhw_solve_general only. */
 typedef struct {
     const double* b;
-    const double* db;
     int32_t N;
     int64_t n_t;
     double t0, dt;
@@ -439,35 +457,44 @@ typedef struct {
  * or non-finite arguments.  Needs no context. */
 int fhw_window_range(double t_lo, double t_hi, double H, int64_t* k_first, int32_t* n_win);
 
-/* Step F3 for general boundary data (Sec. 3.2, eq. bkdef2 with eq.
- * Bkslow_eqn applied node by node): for each window k = k_first + q, q <
- * n_win, and solve frequency omega_j, the recentred transforms
+/* Step F3 for general boundary data (Sec. 3.2, eq. bkdef2, with eq.
+ * Bkslow_eqn applied node by node): u_k is the solution whose Dirichlet data
+ * is the windowed b_k = w_k b.  For each window k = k_first + q, q < n_win,
+ * and every system of the plan (solve frequencies, and the graded
+ * low-frequency ones if planned), the recentred transform
  *   B_k(x_i, omega) = dt sum_n w(t_n - s_k) b(x_i, t_n) e^{i omega (t_n - s_k)}
- * (DB_k likewise from db: the rectangle rule, exact to roundoff for data
- * resolved by the samples since the windowed integrand vanishes with all
- * derivatives at the support's ends), the right-hand side DB_k - i eta B_k
- * of eq. CFIE_direct, and its density on the resident factors (fhw_factor
- * first).  The plan: one curve on the DFT grid (fhw_plan with j_first = 0,
- * no graded low-frequency systems) with the same N at every frequency.
- *   psi     device complex128 [n_win][psi_off[F]]; window k_first + q's
- *           densities at q psi_off[F] (each laid out as fhw_solve_densities).
- *   resid, sweeps [host, optional]: [n_win][F] as fhw_solve_incidences.
- * Synchronizes.  Errors: FHW_E_STATE without resident factors or for another
- * kind of plan; FHW_E_INVALID for null buffers, n_win < 1, bnd->N not the
- * plan's N, n_t < 2, dt <= 0, non-finite t0 or H <= 0; FHW_E_NOCONV as
- * fhw_solve_densities. */
+ * (the rectangle rule, exact to roundoff for data resolved by the samples
+ * since the windowed integrand vanishes with all derivatives at the
+ * support's ends) is the right-hand side of the combined-potential equation
+ * (FHW_FORM_COMBINED), solved on the resident factors (fhw_factor first).
+ *   psi     device complex128 [n_win][psi_off[S]] (S systems): the densities
+ *           phi of window k_first + q at q psi_off[S].
+ *   resid, sweeps [host, optional]: [n_win][S] as fhw_solve_incidences.
+ * Synchronizes.  Errors: FHW_E_STATE without resident factors or for a plan
+ * that is not FHW_FORM_COMBINED; FHW_E_INVALID for null buffers, n_win < 1,
+ * bnd->N not the plan's N, n_t < 2, dt <= 0, non-finite t0 or H <= 0;
+ * FHW_E_NOCONV as fhw_solve_densities. */
 int fhw_solve_general(fhw_ctx* ctx, const fhw_boundary* bnd, double H, int64_t k_first, int32_t n_win,
                       void* psi, double* resid, int32_t* sweeps);
 
-/* Step F5 for the n_win density blocks of fhw_solve_general (eq.
- * Ukslow_repr): V device complex128 [n_win][N_r][2F], block q as
- * fhw_eval_field writes it, with V(r, 0) = 0 (the windowed data are taken to
- * carry no content at omega = 0; the low-frequency decomposition is not
- * offered for general data).  obs [host] doubles [N_r][2].  Synchronizes.
- * Errors as fhw_eval_field, and FHW_E_STATE for a plan fhw_solve_general
- * does not take. */
+/* Step F5 for the n_win density blocks of fhw_solve_general: each window's
+ * field by the combined potential, V_k(r, omega) = (2 pi / N) sum_j |x'_j|
+ * [(i kappa/4) H1(kappa rho) nu_j . (r - x_j)/rho + (eta/4) H0(kappa rho)]
+ * phi_j, rho = |r - x_j| (trapezoidal rule; r away from the curve), at the
+ * solve frequencies.  V: device complex128 [n_win][N_r][2F], block q as
+ * fhw_eval_field lays out its field, with V(r, 0) = 0 (the zero-frequency
+ * limit of a window's field, the bounded harmonic extension of its data, is
+ * not computed).  obs [host] doubles [N_r][2].  Synchronizes.  Errors as
+ * fhw_eval_field, and FHW_E_STATE for a plan fhw_solve_general does not take. */
 int fhw_eval_field_windows(fhw_ctx* ctx, const void* psi, int32_t n_win, const double* obs, int32_t N_r,
                            void* V);
+
+/* The same at the graded low-frequency nodes of a plan with lf_M > 0:
+ * V_sing device complex128 [n_win][N_r][lf_M lf_N + 1], block q as
+ * fhw_eval_field_lowfreq lays it out (ascending nodes, V(r, 0) = 0 first).
+ * Errors: FHW_E_STATE without graded nodes; otherwise as above. */
+int fhw_eval_field_windows_lowfreq(fhw_ctx* ctx, const void* psi, int32_t n_win, const double* obs, int32_t N_r,
+                                   void* V_sing);
 
 /* Steps T1a-T6 with each window's own field (general boundary data): u(r, t)
  * = sum over the windows k = k_first + q, q < n_win, active at t (|t - s_k -
@@ -484,6 +511,19 @@ int fhw_eval_field_windows(fhw_ctx* ctx, const void* psi, int32_t n_win, const d
 int fhw_synthesize_windows(fhw_ctx* ctx, const fhw_windows* win, int64_t k_first, int32_t n_win,
                            const void* V, int32_t N_r, const double* times, int32_t N_t, double* u);
 
+/* fhw_synthesize_lowfreq with each window's own field (Sec. 4.2 for general
+ * boundary data): for every window k = k_first + q, q < n_win, at every time
+ * and t' = t - s_k - tau0, F_k(w) = V_k(r, w) e^{-i w tau0}, u(r, t) = sum_k
+ * (1/pi) Re [I_+ + I_0] with I_+ from the FC(Gram) continuation of F_k on
+ * the solve grid of [omega_c, W] and I_0 by the graded Filon-Clenshaw-Curtis
+ * rule.  V: [n_win][N_r][2F] (fhw_eval_field_windows), V_sing: [n_win][N_r]
+ * [lf_M lf_N + 1] (fhw_eval_field_windows_lowfreq); times [host]; u device
+ * doubles [N_r][N_t], overwritten.  win->track_tol must be 0.  Errors as
+ * fhw_synthesize_lowfreq and fhw_synthesize_windows. */
+int fhw_synthesize_windows_lowfreq(fhw_ctx* ctx, const fhw_windows* win, int64_t k_first, int32_t n_win,
+                                   const void* V, const void* V_sing, int32_t N_r, const double* times,
+                                   int32_t N_t, double* u);
+
 /* ---------------- stage entry points (same kernels, caller buffers) -------- */
 
 /* Boundary nodes of the planned curve at N points (Sec. 2.3 Nystrom nodes):
@@ -496,7 +536,8 @@ int fhw_kress_weights(fhw_ctx* ctx, int32_t N, double* R, double* logtab);
 
 /* Nystrom matrix and plane-wave RHS of eq. CFIE_direct for planned frequencies
  * j0 .. j0+count-1 (0-based): A complex128 at A_off[q] (N_j^2 elements each,
- * column-major), g complex128 at g_off[q] (N_j elements).  A_off, g_off [host]. */
+ * column-major), g complex128 at g_off[q] (N_j elements).  A_off, g_off [host].
+ * For a plan of the combined formulation, A is that formulation's matrix. */
 int fhw_assemble(fhw_ctx* ctx, int32_t j0, int32_t count, void* A, const int64_t* A_off,
                  void* g, const int64_t* g_off);
 

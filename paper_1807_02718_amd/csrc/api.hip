@@ -443,6 +443,11 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
     if (!isfinite(p->direction[0]) || !isfinite(p->direction[1]))
         return fhw_fail(c, FHW_E_INVALID, "plan: direction not finite");
     if (p->j_first < 0) return fhw_fail(c, FHW_E_INVALID, "plan: j_first must be >= 0");
+    if (p->formulation != FHW_FORM_DIRECT && p->formulation != FHW_FORM_COMBINED)
+        return fhw_fail(c, FHW_E_INVALID, "plan: unknown formulation");
+    if (p->formulation == FHW_FORM_COMBINED && (sys || n_curves != 1 || p->j_first != 0 || p->N_fixed <= 0))
+        return fhw_fail(c, FHW_E_INVALID, "plan: the combined formulation needs one curve on the DFT grid with "
+                                          "a fixed N");
     const bool lowfreq = p->lf_M > 0;
     if (p->lf_M < 0) return fhw_fail(c, FHW_E_INVALID, "plan: lf_M must be >= 0");
     if (lowfreq) {
@@ -754,6 +759,7 @@ static int plan_impl(fhw_ctx* c, const fhw_curve* curves, int32_t n_curves, cons
         fitems[j].psi_off = c->psi_off[j];
         fitems[j].N = c->Ns[j];
         fitems[j].kappa = c->kappa[j];
+        fitems[j].eta = c->eta[j];
     }
     size_t oF = put(fitems.data(), fitems.size() * sizeof(fhw_field_item));
     size_t oLF = 0;
@@ -899,7 +905,7 @@ static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_rhs(c->stream, d_items, bd.batch, rg, sv, g));
         } else if (src.bnd) {
             const fhw_boundary& b = *src.bnd;
-            STAGE(c, FHW_STAGE_ASSEMBLE, launch_boundary_rhs(c->stream, b.b, b.db, b.n_t, b.N, b.t0, b.dt, src.H,
+            STAGE(c, FHW_STAGE_ASSEMBLE, launch_boundary_rhs(c->stream, b.b, b.n_t, b.N, b.t0, b.dt, src.H,
                                                              src.k_first + q0, G, p.c, d_items, bd.batch, sv, g));
         }
         for (int q = 0; q < G; ++q)
@@ -944,6 +950,15 @@ static int solve_groups(fhw_ctx* c, const fhw_batch_dev& bd, int32_t maxN, const
     return FHW_OK;
 }
 
+// The calls of the direct equation (incident waves, single-layer field)
+// refuse a plan of the combined formulation.
+static int direct_only(fhw_ctx* c, const char* what) {
+    if (c->prob.formulation != FHW_FORM_DIRECT)
+        return fhw_fail(c, FHW_E_STATE, std::string(what) + ": the plan is of the combined formulation (general "
+                                                              "boundary data: fhw_solve_general and the window calls)");
+    return FHW_OK;
+}
+
 // Densities for n_inc incidences (inc == NULL: the plan's plane wave, whose
 // boundary data the assembly kernel writes).  psi holds n_inc blocks of
 // psi_off[F] elements; resid / sweeps [host] are [n_inc][F].
@@ -980,7 +995,7 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             c->factors_resident = false;
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count,
                                                                 ch.asm_blocks, p.direction[0], p.direction[1], c->A64,
-                                                                fp32 ? c->A32 : nullptr, g));
+                                                                fp32 ? c->A32 : nullptr, g, p.formulation == FHW_FORM_COMBINED));
             if (c->prof.on) {
                 // per-stage timers need the launches one by one
                 FHW_HIP(c, launch_lu_factor(c->stream, bd, ch.sched, ch.d_lu_prefix, LU, c->piv, c->linv,
@@ -1001,7 +1016,8 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
             // the factorization overwrote A: assemble it again for the residuals
             // (which also ends the residency of the FP64 factors)
             STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, ch.d_items, ch.d_asm_prefix, ch.count, ch.asm_blocks,
-                                              p.direction[0], p.direction[1], c->A64, nullptr, g));
+                                              p.direction[0], p.direction[1], c->A64, nullptr, g,
+                                              p.formulation == FHW_FORM_COMBINED));
             const int64_t sv = c->ws_vec;
             for (int q0 = 0; q0 < n_inc; q0 += FHW_INC_GROUP) {
                 const int G = std::min(FHW_INC_GROUP, n_inc - q0);
@@ -1056,6 +1072,7 @@ static int solve_impl(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void*
 int fhw_solve_densities(fhw_ctx* c, void* psi, double* resid, int32_t* sweeps, int32_t compute_resid) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (int rc_d = direct_only(c, "solve_densities")) return rc_d;
     if (!psi) return fhw_fail(c, FHW_E_INVALID, "solve: psi is null");
     return solve_impl(c, nullptr, 1, psi, resid, sweeps, compute_resid, false);
 }
@@ -1084,6 +1101,7 @@ int fhw_solve_incidences(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, vo
                          int32_t* sweeps, int32_t compute_resid) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (int rc_d = direct_only(c, "solve_incidences")) return rc_d;
     int rc = check_incidences(c, inc, n_inc, psi);
     if (rc) return rc;
     return solve_impl(c, inc, n_inc, psi, resid, sweeps, compute_resid, false);
@@ -1093,6 +1111,7 @@ int fhw_solve_cached(fhw_ctx* c, const fhw_incidence* inc, int32_t n_inc, void* 
                      int32_t* sweeps) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve: no plan");
+    if (int rc_d = direct_only(c, "solve_cached")) return rc_d;
     if (!c->factors_resident)
         return fhw_fail(c, FHW_E_STATE, "solve_cached: no resident factors (no solve yet, several chunks, "
                                         "or FP64 residuals overwrote them)");
@@ -1159,6 +1178,7 @@ int fhw_solve_range(fhw_ctx* c, int32_t s0, int32_t count, const fhw_incidence* 
                     double* resid, int32_t* sweeps) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve_range: no plan");
+    if (int rc_d = direct_only(c, "solve_range")) return rc_d;
     if (!c->factors_resident)
         return fhw_fail(c, FHW_E_STATE, "solve_range: no resident factors (fhw_factor first)");
     const int S = (int)c->Ns.size();
@@ -1184,13 +1204,13 @@ int fhw_window_range(double t_lo, double t_hi, double H, int64_t* k_first, int32
     return FHW_OK;
 }
 
-// A plan the general-data path takes: one curve, the DFT grid, no graded
-// systems, the same N at every frequency (the boundary samples' nodes).
+// A plan the general-data path takes: the combined formulation, one curve,
+// the DFT grid, the same N at every frequency (the boundary samples' nodes).
 static int general_plan_check(fhw_ctx* c, const char* what) {
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, std::string(what) + ": no plan");
-    if (c->prob.j_first != 0 || c->system_plan || c->curves.size() != 1 || c->lf_extra > 0)
-        return fhw_fail(c, FHW_E_STATE, std::string(what) + ": needs a plan of one curve on the DFT grid "
-                                                              "without graded low-frequency systems");
+    if (c->prob.formulation != FHW_FORM_COMBINED || c->prob.j_first != 0 || c->system_plan || c->curves.size() != 1)
+        return fhw_fail(c, FHW_E_STATE, std::string(what) + ": needs a plan of the combined formulation (one "
+                                                              "curve on the DFT grid)");
     for (int32_t N : c->Ns)
         if (N != c->Ns[0])
             return fhw_fail(c, FHW_E_STATE, std::string(what) + ": needs the same N at every frequency");
@@ -1204,7 +1224,7 @@ int fhw_solve_general(fhw_ctx* c, const fhw_boundary* bnd, double H, int64_t k_f
     if (rc) return rc;
     if (!c->factors_resident)
         return fhw_fail(c, FHW_E_STATE, "solve_general: no resident factors (fhw_factor first)");
-    if (!bnd || !bnd->b || !bnd->db || !psi || n_win < 1)
+    if (!bnd || !bnd->b || !psi || n_win < 1)
         return fhw_fail(c, FHW_E_INVALID, "solve_general: need boundary data, psi and n_win >= 1");
     if (bnd->N != c->Ns[0]) return fhw_fail(c, FHW_E_INVALID, "solve_general: boundary data at another N");
     if (bnd->n_t < 2 || !(bnd->dt > 0) || !isfinite(bnd->dt) || !isfinite(bnd->t0))
@@ -1233,9 +1253,9 @@ int fhw_eval_field_windows(fhw_ctx* c, const void* psi, int32_t n_win, const dou
     if (rc) return rc;
     const int F = c->prob.F;
     FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
-    STAGE(c, FHW_STAGE_FIELD, launch_field_blocks(c->stream, plan_of(c).d_field_items, F, psi, c->psi_off[F], n_win,
-                                                  (const double*)c->scratch, N_r, 0.0, V,
-                                                  (int64_t)N_r * 2 * F));
+    STAGE(c, FHW_STAGE_FIELD, launch_field_blocks(c->stream, plan_of(c).d_field_items, F, psi,
+                                                  c->psi_off[c->Ns.size()], n_win, (const double*)c->scratch, N_r,
+                                                  0.0, V, (int64_t)N_r * 2 * F));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }
@@ -1248,6 +1268,7 @@ int fhw_solve_range_noalloc(fhw_ctx* c, int32_t s0, int32_t count, const fhw_inc
                             void* psi, double* resid, int32_t* sweeps) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "solve_range_noalloc: no plan");
+    if (int rc_d = direct_only(c, "solve_range_noalloc")) return rc_d;
     if (!c->factors_resident)
         return fhw_fail(c, FHW_E_STATE, "solve_range_noalloc: no resident factors (fhw_factor first)");
     const int S = (int)c->Ns.size();
@@ -1305,6 +1326,7 @@ int fhw_eval_field_curve(fhw_ctx* c, int32_t curve, const void* psi, const doubl
                          double zero_value, void* V) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field: no plan");
+    if (int rc_d = direct_only(c, "field")) return rc_d;
     if (c->prob.j_first != 0 || c->system_plan)
         return fhw_fail(c, FHW_E_STATE, "field: the plan is a band or a list of systems (no DFT grid)");
     if (curve < 0 || curve >= (int)c->curves.size()) return fhw_fail(c, FHW_E_INVALID, "field: no such curve");
@@ -1329,6 +1351,7 @@ int fhw_eval_field_lowfreq(fhw_ctx* c, const void* psi, const double* obs, int32
                            void* V_sing) {
     if (!c) return FHW_E_INVALID;
     if (!c->planned) return fhw_fail(c, FHW_E_STATE, "field_lowfreq: no plan");
+    if (int rc_d = direct_only(c, "field_lowfreq")) return rc_d;
     if (c->lf_extra <= 0) return fhw_fail(c, FHW_E_STATE, "field_lowfreq: the plan has no graded low-frequency nodes");
     if (N_r < 0 || (N_r > 0 && (!psi || !obs || !V_sing)) || !isfinite(zero_value))
         return fhw_fail(c, FHW_E_INVALID, "field_lowfreq: bad arguments");
@@ -1339,7 +1362,7 @@ int fhw_eval_field_lowfreq(fhw_ctx* c, const void* psi, const double* obs, int32
     if (rc) return rc;
     FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
     STAGE(c, FHW_STAGE_FIELD, launch_field_list(c->stream, plan_of(c).d_lf_items, c->lf_extra + 1, psi,
-                                                (const double*)c->scratch, N_r, zero_value, V_sing));
+                                                (const double*)c->scratch, N_r, zero_value, V_sing, false));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }
@@ -1452,6 +1475,30 @@ int fhw_synthesize(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, co
     return FHW_OK;
 }
 
+int fhw_eval_field_windows_lowfreq(fhw_ctx* c, const void* psi, int32_t n_win, const double* obs, int32_t N_r,
+                                   void* V_sing) {
+    if (!c) return FHW_E_INVALID;
+    int rc = general_plan_check(c, "field_windows_lowfreq");
+    if (rc) return rc;
+    if (c->lf_extra <= 0)
+        return fhw_fail(c, FHW_E_STATE, "field_windows_lowfreq: the plan has no graded low-frequency nodes");
+    if (n_win < 0 || N_r < 0 || (n_win > 0 && N_r > 0 && (!psi || !obs || !V_sing)))
+        return fhw_fail(c, FHW_E_INVALID, "field_windows_lowfreq: bad arguments");
+    if (n_win == 0 || N_r == 0) return FHW_OK;
+    for (int q = 0; q < 2 * N_r; ++q)
+        if (!isfinite(obs[q])) return fhw_fail(c, FHW_E_INVALID, "field_windows_lowfreq: observation point not finite");
+    rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
+    if (rc) return rc;
+    FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
+    const int64_t ps = c->psi_off[c->Ns.size()], vs = (int64_t)N_r * (c->lf_extra + 2);
+    for (int32_t q = 0; q < n_win; ++q)
+        STAGE(c, FHW_STAGE_FIELD, launch_field_list(c->stream, plan_of(c).d_lf_items, c->lf_extra + 1,
+                                                    (const zd*)psi + q * ps, (const double*)c->scratch, N_r, 0.0,
+                                                    (zd*)V_sing + q * vs, true));
+    FHW_HIP(c, hipStreamSynchronize(c->stream));
+    return FHW_OK;
+}
+
 // Synthesis with each window's own field (general boundary data): the
 // coefficient kernel on V_k e^{-i omega tau0} (no spectra), then the sinc
 // sum over the windows active at each time.
@@ -1524,36 +1571,25 @@ int fhw_synthesize_windows(fhw_ctx* c, const fhw_windows* win, int64_t k_first, 
 // smooth grid of [omega_c, W] and at the graded nodes, the continuation's
 // Fourier coefficients and the Filon-Clenshaw-Curtis data per (window,
 // point), then every (point, time) summed over all windows (lowfreq.hip).
-int fhw_synthesize_lowfreq(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V,
-                           const void* V_sing, int32_t N_r, const double* times, int32_t N_t, double* u) {
-    if (!c) return FHW_E_INVALID;
-    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize_lowfreq: no plan");
-    if (c->lf_extra <= 0)
-        return fhw_fail(c, FHW_E_STATE, "synthesize_lowfreq: the plan has no graded low-frequency nodes");
-    if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad arguments");
-    if (N_r == 0 || N_t == 0) return FHW_OK;
-    if (!V || !V_sing || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
-        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad signal or buffers");
-    const double H = win->H, tau0 = win->tau0;
-    if (!(H > 0) || !isfinite(H) || !isfinite(tau0) || win->track_tol != 0.0)
-        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad windows (track_tol must be 0)");
-    if (N_r > 65535) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: at most 65535 points");
-    for (int q = 0; q < N_t; ++q)
-        if (!isfinite(times[q])) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: time not finite");
+// The low-frequency synthesis for windows k_lo .. k_lo + K - 1: the
+// continuation coefficients and Filon-Clenshaw-Curtis data per (window,
+// point), then every (point, time) summed over all windows.  sig != NULL: the
+// plane-path form, F_k = B_k V with the window spectra of the signal; sig ==
+// NULL: each window's own fields (V + q vq, Vs + q vsq), F_k = V_k.
+static int lowfreq_synth_impl(fhw_ctx* c, const char* what, const fhw_signal* sig, int64_t k_lo, int K, double H,
+                              double tau0, const void* V, const void* V_sing, int64_t vq, int64_t vsq, int32_t N_r,
+                              const double* times, int32_t N_t, double* u) {
     const fhw_problem& p = c->prob;
     const int F = p.F, M = p.lf_M, nc = p.lf_N, jc = p.lf_jc;
     const int n = F - jc + 1, L = n + lf_fc_points();
     const size_t lds_coef = (size_t)2 * L * 16, lds_syn = ((size_t)2 * L + (size_t)M * 3 * (nc + 1)) * 16;
     if (n > lf_max_points() || lds_coef > 65536 || lds_syn > 65536)
-        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: F - lf_jc + 1 too large for the kernels' 64 KiB of LDS");
-    int64_t k_lo, k_hi;
-    signal_windows(sig, H, &k_lo, &k_hi);
-    if (k_hi < k_lo) {
+        return fhw_fail(c, FHW_E_INVALID, std::string(what) + ": F - lf_jc + 1 too large for the kernels' 64 KiB of LDS");
+    if (K <= 0) {
         FHW_HIP(c, hipMemsetAsync(u, 0, sizeof(double) * (size_t)N_r * N_t, c->stream));
         FHW_HIP(c, hipStreamSynchronize(c->stream));
         return FHW_OK;
     }
-    const int K = (int)(k_hi - k_lo + 1);
     std::vector<int64_t> klist(K);
     for (int q = 0; q < K; ++q) klist[q] = k_lo + q;
     const double h = p.W / (double)F;
@@ -1578,7 +1614,7 @@ int fhw_synthesize_lowfreq(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     size_t o_mu = align_up(o_om + (size_t)n_om * 8, 256);
     size_t o_ty = align_up(o_mu + (size_t)(M + 1) * 8, 256);
     size_t o_B = align_up(o_ty + tay.size() * 8, 256);
-    size_t o_cf = align_up(o_B + (size_t)K * n_om * 16, 256);
+    size_t o_cf = align_up(o_B + (sig ? (size_t)K * n_om * 16 : 0), 256);
     size_t o_ch = align_up(o_cf + (size_t)K * N_r * L * 16, 256);
     size_t total = align_up(o_ch + (size_t)K * N_r * M * 3 * (nc + 1) * 16, 256);
     int rc = fhw_ensure_scratch(c, total);
@@ -1589,11 +1625,13 @@ int fhw_synthesize_lowfreq(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     FHW_HIP(c, hipMemcpyAsync(sb + o_om, om.data(), (size_t)n_om * 8, hipMemcpyHostToDevice, c->stream));
     FHW_HIP(c, hipMemcpyAsync(sb + o_mu, c->lf_mu.data(), (size_t)(M + 1) * 8, hipMemcpyHostToDevice, c->stream));
     FHW_HIP(c, hipMemcpyAsync(sb + o_ty, tay.data(), tay.size() * 8, hipMemcpyHostToDevice, c->stream));
-    STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra_at(c->stream, sig->f, sig->n, sig->t0, sig->dt, H,
-                                                         (const int64_t*)(sb + o_k), K, (const double*)(sb + o_om),
-                                                         n_om, sb + o_B));
-    STAGE(c, FHW_STAGE_COEFFS, launch_lf_coeffs(c->stream, sb + o_B, (const double*)(sb + o_om), n_om, V, V_sing, N_r,
-                                                F, jc, n, M, nc, tau0, K, sb + o_cf, sb + o_ch));
+    if (sig)
+        STAGE(c, FHW_STAGE_SPECTRA, launch_window_spectra_at(c->stream, sig->f, sig->n, sig->t0, sig->dt, H,
+                                                             (const int64_t*)(sb + o_k), K, (const double*)(sb + o_om),
+                                                             n_om, sb + o_B));
+    STAGE(c, FHW_STAGE_COEFFS, launch_lf_coeffs(c->stream, sig ? sb + o_B : nullptr, (const double*)(sb + o_om), n_om,
+                                                V, V_sing, N_r, F, jc, n, M, nc, tau0, K, sb + o_cf, sb + o_ch, vq,
+                                                vsq));
     STAGE(c, FHW_STAGE_SYNTH, launch_lf_synth(c->stream, sb + o_cf, sb + o_ch, (const int64_t*)(sb + o_k), K,
                                               (const double*)(sb + o_mu), (const double*)(sb + o_ty),
                                               (const double*)(sb + o_t), N_t, N_r, n, M, nc, h, c->lf_omega_c, H,
@@ -1602,6 +1640,52 @@ int fhw_synthesize_lowfreq(fhw_ctx* c, const fhw_signal* sig, const fhw_windows*
     c->trk_pairs = (int64_t)K * N_r;
     c->trk_active = c->trk_pairs;
     return FHW_OK;
+}
+
+int fhw_synthesize_lowfreq(fhw_ctx* c, const fhw_signal* sig, const fhw_windows* win, const void* V,
+                           const void* V_sing, int32_t N_r, const double* times, int32_t N_t, double* u) {
+    if (!c) return FHW_E_INVALID;
+    if (!c->planned) return fhw_fail(c, FHW_E_STATE, "synthesize_lowfreq: no plan");
+    if (c->lf_extra <= 0)
+        return fhw_fail(c, FHW_E_STATE, "synthesize_lowfreq: the plan has no graded low-frequency nodes");
+    if (!sig || !win || N_r < 0 || N_t < 0) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad arguments");
+    if (N_r == 0 || N_t == 0) return FHW_OK;
+    if (!V || !V_sing || !times || !u || !sig->f || sig->n < 2 || !(sig->dt > 0) || !isfinite(sig->t0))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad signal or buffers");
+    const double H = win->H, tau0 = win->tau0;
+    if (!(H > 0) || !isfinite(H) || !isfinite(tau0) || win->track_tol != 0.0)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: bad windows (track_tol must be 0)");
+    if (N_r > 65535) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: at most 65535 points");
+    for (int q = 0; q < N_t; ++q)
+        if (!isfinite(times[q])) return fhw_fail(c, FHW_E_INVALID, "synthesize_lowfreq: time not finite");
+    int64_t k_lo, k_hi;
+    signal_windows(sig, H, &k_lo, &k_hi);
+    const int K = k_hi >= k_lo ? (int)(k_hi - k_lo + 1) : 0;
+    return lowfreq_synth_impl(c, "synthesize_lowfreq", sig, k_lo, K, H, tau0, V, V_sing, 0, 0, N_r, times, N_t, u);
+}
+
+int fhw_synthesize_windows_lowfreq(fhw_ctx* c, const fhw_windows* win, int64_t k_first, int32_t n_win,
+                                   const void* V, const void* V_sing, int32_t N_r, const double* times, int32_t N_t,
+                                   double* u) {
+    if (!c) return FHW_E_INVALID;
+    int rc = general_plan_check(c, "synthesize_windows_lowfreq");
+    if (rc) return rc;
+    if (c->lf_extra <= 0)
+        return fhw_fail(c, FHW_E_STATE, "synthesize_windows_lowfreq: the plan has no graded low-frequency nodes");
+    if (!win || n_win < 0 || N_r < 0 || N_t < 0)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_windows_lowfreq: bad arguments");
+    if (N_r == 0 || N_t == 0) return FHW_OK;
+    if (!times || !u || (n_win > 0 && (!V || !V_sing)))
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_windows_lowfreq: bad buffers");
+    const double H = win->H, tau0 = win->tau0;
+    if (!(H > 0) || !isfinite(H) || !isfinite(tau0) || win->track_tol != 0.0)
+        return fhw_fail(c, FHW_E_INVALID, "synthesize_windows_lowfreq: bad windows (track_tol must be 0)");
+    if (N_r > 65535) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows_lowfreq: at most 65535 points");
+    for (int q = 0; q < N_t; ++q)
+        if (!isfinite(times[q])) return fhw_fail(c, FHW_E_INVALID, "synthesize_windows_lowfreq: time not finite");
+    const int64_t vq = (int64_t)N_r * 2 * c->prob.F, vsq = (int64_t)N_r * (c->lf_extra + 2);
+    return lowfreq_synth_impl(c, "synthesize_windows_lowfreq", nullptr, k_first, n_win, H, tau0, V, V_sing, vq, vsq,
+                              N_r, times, N_t, u);
 }
 
 // Time samples on the uniform grid t_n = t_first + n t_step by the fast scaled
@@ -1817,7 +1901,8 @@ int fhw_assemble(fhw_ctx* c, int32_t j0, int32_t count, void* A, const int64_t* 
                               c->stream));
     FHW_HIP(c, hipMemcpyAsync(sb + op, pre.data(), 8 * (count + 1), hipMemcpyHostToDevice, c->stream));
     STAGE(c, FHW_STAGE_ASSEMBLE, launch_assemble_blocks(c->stream, (const fhw_assemble_item*)(sb + oi), (const int64_t*)(sb + op), count,
-                                      blk, c->prob.direction[0], c->prob.direction[1], A, nullptr, g));
+                                      blk, c->prob.direction[0], c->prob.direction[1], A, nullptr, g,
+                                      c->prob.formulation == FHW_FORM_COMBINED));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }

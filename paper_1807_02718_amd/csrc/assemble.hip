@@ -32,12 +32,17 @@ __device__ __forceinline__ zd cfie_entry(double n_t, double cL, double cY, doubl
     return cmk(sps * (Rw * K1r + wq * K2r), sps * (Rw * K1i + wq * K2i));
 }
 
+// COMB: the combined potential's matrix (1/2) phi + K phi - i eta S phi, K
+// the double layer: the normal factor of entry (i, j) is nu_j . (x_i - x_j)/r
+// (the source's) where the direct equation's adjoint kernel has nu_i . (x_j -
+// x_i)/r (the target's); everything else, diagonal limits included, is shared.
 // One workgroup per 32x32 tile (I, J), I >= J, of one matrix (column-major).
 // Each thread takes pairs (i, j) = (i0 + tid%32, j0 + tid/32 + 8k), k < 4.
 // The Bessel values of |x_i - x_j| serve A(i, j) (written directly, lanes
 // along i) and A(j, i) (staged in LDS, then written with lanes along j).
 // Diagonal tiles take i >= j only and mirror the strict part.  Tiles with
 // J = 0 also write the RHS.
+template <bool COMB>
 __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_item* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int n_items,
                                                           double p1, double p2, zd* __restrict__ A,
@@ -119,8 +124,8 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
             const double cJ = 0.25 * kappa * J1;
             const double n_i = (ni1 * d1 + ni2 * d2) * ir;          // target i: nu_i . (x_j - x_i) / r
             const double n_j = -(sj[3][jl] * d1 + sj[4][jl] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
-            e_ij = cfie_entry(n_i, cL, cY, cJ, M1, M2r, M2i, lam, st[1][dd], wq, eta, spj);
-            e_ji = cfie_entry(n_j, cL, cY, cJ, M1, M2r, M2i, st[2][dd], st[3][dd], wq, eta, spi);
+            e_ij = cfie_entry(COMB ? n_j : n_i, cL, cY, cJ, M1, M2r, M2i, lam, st[1][dd], wq, eta, spj);
+            e_ji = cfie_entry(COMB ? n_i : n_j, cL, cY, cJ, M1, M2r, M2i, st[2][dd], st[3][dd], wq, eta, spi);
         } else {
             const double M2r = -(0.57721566490153286061 + log(0.5 * kappa * spi)) / (2.0 * FHW_PI);
             const double M2i = 0.25;
@@ -162,10 +167,14 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
 
 hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_items, const int64_t* d_prefix,
                                   int32_t n_items, int64_t total_blocks, double p1, double p2, void* A,
-                                  void* A32, void* g) {
+                                  void* A32, void* g, bool combined) {
     if (total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)total_blocks), dim3(ASM_THREADS), 0, s, d_items, d_prefix,
-                       n_items, p1, p2, (zd*)A, (zf*)A32, (zd*)g);
+    if (combined)
+        hipLaunchKernelGGL(k_assemble<true>, dim3((unsigned)total_blocks), dim3(ASM_THREADS), 0, s, d_items,
+                           d_prefix, n_items, p1, p2, (zd*)A, (zf*)A32, (zd*)g);
+    else
+        hipLaunchKernelGGL(k_assemble<false>, dim3((unsigned)total_blocks), dim3(ASM_THREADS), 0, s, d_items,
+                           d_prefix, n_items, p1, p2, (zd*)A, (zf*)A32, (zd*)g);
     return hipGetLastError();
 }
 

@@ -171,10 +171,11 @@ struct fhw_assemble_item {
     double kappa, eta;
 };
 // write complex128 A (and optionally a complex64 copy A32 at the same offsets)
-// and the plane-wave RHS g; d_prefix[q] = first block of item q
+// and the plane-wave RHS g; d_prefix[q] = first block of item q; combined:
+// the combined potential's matrix instead of the direct equation's
 hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_items, const int64_t* d_prefix,
                                   int32_t n_items, int64_t total_blocks, double p1, double p2, void* A,
-                                  void* A32, void* g);
+                                  void* A32, void* g, bool combined = false);
 int64_t assemble_blocks_for(int32_t N);
 // boundary data of one incidence (FHW_INC_PLANE: v = p; FHW_INC_POINT: v = r0)
 // for every item, written at g + g_off
@@ -276,6 +277,7 @@ struct fhw_field_item {
     int64_t psi_off;
     int32_t N;
     double kappa;
+    double eta;   // coupling of the system (the combined potential's single-layer weight)
 };
 hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
                         const double* obs, int32_t N_r, double zero_value, void* V);
@@ -285,9 +287,10 @@ hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
 // V + q V_bstride, each as launch_field writes it, with V(r, 0) = zero_value
 hipError_t launch_field_blocks(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
                                int64_t psi_bstride, int32_t n_blk, const double* obs, int32_t N_r,
-                               double zero_value, void* V, int64_t V_bstride);
+                               double zero_value, void* V, int64_t V_bstride);   // combined potential
+// (combined: the combined potential instead of the single layer)
 hipError_t launch_field_list(hipStream_t s, const fhw_field_item* d_items, int32_t n_items, const void* psi,
-                             const double* obs, int32_t N_r, double zero_value, void* V);
+                             const double* obs, int32_t N_r, double zero_value, void* V, bool combined = false);
 
 // --- lowfreq.hip --------------------------------------------------------------
 // largest number of smooth-grid frequencies the continuation kernel takes;
@@ -299,8 +302,11 @@ int lf_taylor_terms(void);
 // (cfs [K][N_r][n + FC_C]) and the graded subintervals' Chebyshev data
 // (cheb [K][N_r][M][3][nc + 1]); B [K][n_om] at om = smooth grid then the
 // M nc + 1 graded nodes; V [N_r][2F]; Vs [N_r][M nc + 1]
+// With B == NULL each window has its own fields, window q's at V + q v_qstride
+// and Vs + q vs_qstride (general boundary data), and no spectrum factor.
 hipError_t launch_lf_coeffs(hipStream_t s, const void* B, const double* om, int n_om, const void* V, const void* Vs,
-                            int N_r, int F, int jc, int n, int M, int nc, double tau0, int K, void* cfs, void* cheb);
+                            int N_r, int F, int jc, int n, int M, int nc, double tau0, int K, void* cfs, void* cheb,
+                            int64_t v_qstride = 0, int64_t vs_qstride = 0);
 // u [N_r][N_t] = sum over the K windows of (1/pi) Re (I_+ + I_0); mu [M + 1]
 // graded mesh; taylor [nc + 1][40] moments of x^p against T_k
 hipError_t launch_lf_synth(hipStream_t s, const void* cfs, const void* cheb, const int64_t* klist, int K,
@@ -327,12 +333,12 @@ hipError_t launch_fourier_coeffs(hipStream_t s, const void* B, int32_t count, co
                                  double* bnd = nullptr, unsigned long long* gmax = nullptr,
                                  double* wmax = nullptr, unsigned long long* gwmax = nullptr, double tol = 0.0,
                                  int64_t v_qstride = 0);
-// Right-hand sides DB - i eta B of eq. CFIE_direct from sampled boundary data
-// b, db [n_t][N] (device, real) for windows k_first .. k_first + n_win - 1
-// (window q at g + q sg) and the n_sys items (omega = kappa c)
-hipError_t launch_boundary_rhs(hipStream_t s, const double* b, const double* db, int64_t n_t, int32_t N, double t0,
-                               double dt, double H, int64_t k_first, int32_t n_win, double c,
-                               const fhw_assemble_item* d_items, int32_t n_sys, int64_t sg, void* g);
+// Right-hand sides B of the combined-potential equation from sampled
+// Dirichlet data b [n_t][N] (device, real) for windows k_first .. k_first +
+// n_win - 1 (window q at g + q sg) and the n_sys items (omega = kappa c)
+hipError_t launch_boundary_rhs(hipStream_t s, const double* b, int64_t n_t, int32_t N, double t0, double dt,
+                               double H, int64_t k_first, int32_t n_win, double c, const fhw_assemble_item* d_items,
+                               int32_t n_sys, int64_t sg, void* g);
 // Fast scaled convolution on a uniform time grid (frft.hip).  A chunk is a
 // run of n consecutive grid times from index n0 inside one window's active
 // range; xs is the kernel argument W (t_{n0} - s_k - tau0) / pi of its first.

@@ -46,9 +46,24 @@ __global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restri
     }
 }
 
+// Kernel of the combined potential at observation point (o1, o2) for node i:
+//   |x'_i| [ (i kappa/4) H1(kappa rho) nu_i . (r - x_i)/rho + (eta/4) H0(kappa rho) ]
+__device__ __forceinline__ zd combined_kernel(const double* geom, int N, int i, double o1, double o2, double kappa,
+                                             double eta) {
+    const double d1 = o1 - geom[i], d2 = o2 - geom[N + i];
+    const double rho = sqrt(d1 * d1 + d2 * d2);
+    double J0, Y0, J1, Y1;
+    fhw_bessel01(kappa * rho, J0, Y0, J1, Y1);
+    const double cn = (geom[7 * N + i] * d1 + geom[8 * N + i] * d2) / rho;
+    const double sp = geom[6 * N + i];
+    const double a = 0.25 * kappa * cn, e = 0.25 * eta;
+    return cmk(sp * (e * J0 - a * Y1), sp * (e * Y0 + a * J1));
+}
+
 // The field of n_blk density blocks at once (the windows of general boundary
-// data): one wave per (point, frequency) as in k_field; the Hankel kernel of
-// a node is formed once and applied to up to FB_BLK blocks.
+// data, by the combined potential): one wave per (point, frequency) as in
+// k_field; the kernel of a node is formed once and applied to up to FB_BLK
+// blocks.
 #define FB_BLK 8
 __global__ __launch_bounds__(256, 4) void k_field_blocks(const fhw_field_item* __restrict__ items, int F,
                                                       const zd* __restrict__ psi, int64_t psi_bstride, int n_blk,
@@ -61,9 +76,6 @@ __global__ __launch_bounds__(256, 4) void k_field_blocks(const fhw_field_item* _
     const int j = wave - r * F;
     const fhw_field_item it = items[j];
     const int N = it.N;
-    const double* x1 = it.geom;
-    const double* x2 = it.geom + N;
-    const double* sp = it.geom + 6 * N;
     const double o1 = obs[2 * r], o2 = obs[2 * r + 1];
     const double wq = 2.0 * FHW_PI / (double)N;
     for (int q0 = blockIdx.y * FB_BLK; q0 < n_blk; q0 += gridDim.y * FB_BLK) {
@@ -73,11 +85,7 @@ __global__ __launch_bounds__(256, 4) void k_field_blocks(const fhw_field_item* _
 #pragma unroll
         for (int u = 0; u < FB_BLK; ++u) acc[u] = cmk(0.0, 0.0);
         for (int i = lane; i < N; i += 64) {
-            const double d1 = o1 - x1[i], d2 = o2 - x2[i];
-            const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
-            double J0, Y0;
-            fhw_bessel0(z, J0, Y0);
-            const zd gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
+            const zd gk = combined_kernel(it.geom, N, i, o1, o2, it.kappa, it.eta);
 #pragma unroll
             for (int u = 0; u < FB_BLK; ++u)
                 if (u < nb) acc[u] = cfma(acc[u], gk, ps[(int64_t)u * psi_bstride + i]);
@@ -98,7 +106,9 @@ __global__ __launch_bounds__(256, 4) void k_field_blocks(const fhw_field_item* _
 }
 
 // V[r][0] = zero_value, V[r][1 + j] = field of item j (j < n_items): the
-// field at an explicit list of systems (the graded low-frequency nodes).
+// field at an explicit list of systems (the graded low-frequency nodes); COMB:
+// by the combined potential instead of the single layer.
+template <bool COMB>
 __global__ __launch_bounds__(256, 4) void k_field_list(const fhw_field_item* __restrict__ items, int n_items,
                                                     const zd* __restrict__ psi, const double* __restrict__ obs,
                                                     int N_r, double zero_value, zd* __restrict__ V) {
@@ -116,11 +126,16 @@ __global__ __launch_bounds__(256, 4) void k_field_list(const fhw_field_item* __r
     const double o1 = obs[2 * r], o2 = obs[2 * r + 1];
     zd acc = cmk(0.0, 0.0);
     for (int i = lane; i < N; i += 64) {
-        const double d1 = o1 - x1[i], d2 = o2 - x2[i];
-        const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
-        double J0, Y0;
-        fhw_bessel0(z, J0, Y0);
-        const zd gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
+        zd gk;
+        if constexpr (COMB) {
+            gk = combined_kernel(it.geom, N, i, o1, o2, it.kappa, it.eta);
+        } else {
+            const double d1 = o1 - x1[i], d2 = o2 - x2[i];
+            const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
+            double J0, Y0;
+            fhw_bessel0(z, J0, Y0);
+            gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
+        }
         acc = cfma(acc, gk, ps[i]);
     }
     acc.re = wave_sum(acc.re);
@@ -163,11 +178,15 @@ hipError_t launch_field_blocks(hipStream_t s, const fhw_field_item* d_items, int
 }
 
 hipError_t launch_field_list(hipStream_t s, const fhw_field_item* d_items, int32_t n_items, const void* psi,
-                             const double* obs, int32_t N_r, double zero_value, void* V) {
+                             const double* obs, int32_t N_r, double zero_value, void* V, bool combined) {
     const int64_t waves = (int64_t)N_r * n_items;
     if (waves <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_field_list, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items, n_items,
-                       (const zd*)psi, obs, N_r, zero_value, (zd*)V);
+    if (combined)
+        hipLaunchKernelGGL(k_field_list<true>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items, n_items,
+                           (const zd*)psi, obs, N_r, zero_value, (zd*)V);
+    else
+        hipLaunchKernelGGL(k_field_list<false>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d_items,
+                           n_items, (const zd*)psi, obs, N_r, zero_value, (zd*)V);
     return hipGetLastError();
 }
 

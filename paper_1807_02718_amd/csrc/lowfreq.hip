@@ -28,7 +28,8 @@
 // V: [N_r][2F] on the DFT grid; Vs: [N_r][M n + 1] at the graded nodes.
 __global__ __launch_bounds__(LF_THREADS) void k_lf_coeffs(const zd* __restrict__ B, const double* __restrict__ om,
                                                          int n_om, const zd* __restrict__ V, const zd* __restrict__ Vs,
-                                                         int N_r, int F, int jc, int n, int M, int nc, double tau0,
+                                                         int64_t v_qstride, int64_t vs_qstride, int N_r, int F,
+                                                         int jc, int n, int M, int nc, double tau0,
                                                          zd* __restrict__ cfs, zd* __restrict__ cheb) {
     extern __shared__ zd lds[];
     const int L = n + FC_C;
@@ -36,15 +37,16 @@ __global__ __launch_bounds__(LF_THREADS) void k_lf_coeffs(const zd* __restrict__
     zd* tw = lds + L;     // [L] e^{-2 pi i j / L}
     __shared__ zd aR[FC_D], aL[FC_D];
     const int q = blockIdx.x / N_r, r = blockIdx.x - q * N_r;
-    const zd* Bq = B + (int64_t)q * n_om;
-    const zd* Vr = V + (int64_t)r * 2 * F;
+    const zd* Bq = B ? B + (int64_t)q * n_om : nullptr;   // NULL: each window has its own field
+    const zd* Vr = V + (int64_t)q * v_qstride + (int64_t)r * 2 * F;
+    Vs += (int64_t)q * vs_qstride;
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += LF_THREADS) {
         const int l = F + jc + i;   // grid index of omega = (jc + i) W / F; +W is stored as conj at l = 0
         const zd v = l < 2 * F ? Vr[l] : cconj(Vr[0]);
         double s, c;
         sincos(om[i] * tau0, &s, &c);
-        g[i] = cmul(cmul(Bq[i], v), cmk(c, -s));
+        g[i] = cmul(Bq ? cmul(Bq[i], v) : v, cmk(c, -s));
     }
     for (int j = tid; j < L; j += LF_THREADS) {
         double s, c;
@@ -98,7 +100,8 @@ __global__ __launch_bounds__(LF_THREADS) void k_lf_coeffs(const zd* __restrict__
             const int gidx = j * nc + nc - i;
             double s, c;
             sincos(om[n + gidx] * tau0, &s, &c);
-            G[i] = cmul(cmul(Bq[n + gidx], Vs[(int64_t)r * (M * nc + 1) + gidx]), cmk(c, -s));
+            const zd vs = Vs[(int64_t)r * (M * nc + 1) + gidx];
+            G[i] = cmul(Bq ? cmul(Bq[n + gidx], vs) : vs, cmk(c, -s));
         }
         zd* out = cheb + ((int64_t)blockIdx.x * M + j) * 3 * (nc + 1);
         for (int k = 0; k <= nc; ++k) {
@@ -235,7 +238,8 @@ int lf_fc_points(void) { return FC_C; }
 int lf_taylor_terms(void) { return LF_TAYLOR; }
 
 hipError_t launch_lf_coeffs(hipStream_t s, const void* B, const double* om, int n_om, const void* V, const void* Vs,
-                            int N_r, int F, int jc, int n, int M, int nc, double tau0, int K, void* cfs, void* cheb) {
+                            int N_r, int F, int jc, int n, int M, int nc, double tau0, int K, void* cfs, void* cheb,
+                            int64_t v_qstride, int64_t vs_qstride) {
     if (n < FC_D || n + FC_C > 2048 || nc < 1 || nc > 32 || K < 1 || N_r < 1) return hipErrorInvalidValue;
     const size_t lds = (size_t)2 * (n + FC_C) * sizeof(zd);
     static std::atomic<uint64_t> attr{0};
@@ -243,7 +247,8 @@ hipError_t launch_lf_coeffs(hipStream_t s, const void* B, const double* om, int 
         (void)hipFuncSetAttribute((const void*)k_lf_coeffs, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
     });
     hipLaunchKernelGGL(k_lf_coeffs, dim3((unsigned)(K * N_r)), dim3(LF_THREADS), lds, s, (const zd*)B, om, n_om,
-                       (const zd*)V, (const zd*)Vs, N_r, F, jc, n, M, nc, tau0, (zd*)cfs, (zd*)cheb);
+                       (const zd*)V, (const zd*)Vs, v_qstride, vs_qstride, N_r, F, jc, n, M, nc, tau0, (zd*)cfs,
+                       (zd*)cheb);
     return hipGetLastError();
 }
 

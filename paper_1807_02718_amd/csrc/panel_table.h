@@ -10,11 +10,11 @@
 // a thread takes ceil(256 R / threads) rows; PD columns of each factored
 // sub-panel in flight during the lazy updates (0: the kernel's default)
 #define FHW_PB_F32_R1 256, 8, 4, 0
-#define FHW_PB_F32_R2 256, 8, 4, 0
+#define FHW_PB_F32_R2 256, 8, 2, 2
 #define FHW_PB_F32_R4 256, 8, 4, 0
-#define FHW_PB_F64_R1 256, 8, 4, 0
-#define FHW_PB_F64_R2 256, 8, 2, 0
-#define FHW_PB_F64_R4 256, 8, 2, 0
+#define FHW_PB_F64_R1 256, 8, 2, 2
+#define FHW_PB_F64_R2 256, 8, 2, 1
+#define FHW_PB_F64_R4 256, 8, 2, 1
 // 1024 threads (batches of at most 256 matrices), rows per thread R
 #define FHW_PT_F32_1024_R1 8, 4
 #define FHW_PT_F32_1024_R2 8, 4

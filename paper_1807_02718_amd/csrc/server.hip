@@ -205,6 +205,7 @@ int fhw_server_create(fhw_server** out, const fhw_curve* curves, int32_t n_curve
     S->prob = *prob;
     S->prob.lf_M = 0;
     S->prob.j_first = 0;
+    S->prob.formulation = FHW_FORM_DIRECT;
     S->coef.resize(n_curves);
     S->curves.resize(n_curves);
     for (int k = 0; k < n_curves; ++k) {

@@ -92,20 +92,18 @@ __global__ __launch_bounds__(SYN_THREADS) void k_window_spectra(const double* __
     }
 }
 
-// Right-hand sides of eq. CFIE_direct for general boundary data (eq. bkdef2):
-// window k = k_first + q, system j (items[j]: omega = kappa c, eta, offset
-// g_off), node i:
-//   B  = dt sum_n w(t_n - s_k) b(x_i, t_n) e^{i omega (t_n - s_k)},  DB likewise
-//        from db (the normal derivative),  g = DB - i eta B
-// written at g + q sg + g_off + i.  b, db: samples [n_t][N] (time-major, so
-// one time's nodes are contiguous).  Grid (n_win, ceil(n_sys / BW_SYS),
+// Right-hand sides of the combined-potential equation for general boundary
+// data (eq. bkdef2): window k = k_first + q, system j (items[j]: omega =
+// kappa c, offset g_off), node i:
+//   B = dt sum_n w(t_n - s_k) b(x_i, t_n) e^{i omega (t_n - s_k)}
+// written at g + q sg + g_off + i.  b: samples [n_t][N] (time-major, so one
+// time's nodes are contiguous).  Grid (n_win, ceil(n_sys / BW_SYS),
 // ceil(N / SYN_THREADS)): a thread takes one node and BW_SYS systems; the
 // factors w e^{i omega tau} of a run of samples are staged in LDS, so each
-// sample of b and db is read once per BW_SYS systems.
+// sample is read once per BW_SYS systems.
 #define BW_SYS 8
 #define BW_CHUNK 256
-__global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __restrict__ b,
-                                                              const double* __restrict__ db, int64_t n_t, int N,
+__global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __restrict__ b, int64_t n_t, int N,
                                                               double t0, double dt, double H, int64_t k_first,
                                                               double c, const fhw_assemble_item* __restrict__ items,
                                                               int n_sys, int64_t sg, zd* __restrict__ g) {
@@ -120,12 +118,9 @@ __global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __re
     int64_t n_hi = (int64_t)ceil((sk + H - t0) / dt);
     if (n_lo < 0) n_lo = 0;
     if (n_hi > n_t - 1) n_hi = n_t - 1;
-    zd aB[BW_SYS], aD[BW_SYS];
+    zd aB[BW_SYS];
 #pragma unroll
-    for (int u = 0; u < BW_SYS; ++u) {
-        aB[u] = cmk(0.0, 0.0);
-        aD[u] = cmk(0.0, 0.0);
-    }
+    for (int u = 0; u < BW_SYS; ++u) aB[u] = cmk(0.0, 0.0);
     for (int64_t c0 = n_lo; c0 <= n_hi; c0 += BW_CHUNK) {
         const int cnt = (int)min<int64_t>(BW_CHUNK, n_hi - c0 + 1);
         __syncthreads();
@@ -147,33 +142,27 @@ __global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __re
         __syncthreads();
         if (node < N) {
             const double* bp = b + c0 * (int64_t)N + node;
-            const double* dp = db + c0 * (int64_t)N + node;
             int i = 0;
-            // four samples' loads in flight before their products
-            for (; i + 4 <= cnt; i += 4) {
-                double bv[4], dv[4];
+            // eight samples' loads in flight before their products
+            for (; i + 8 <= cnt; i += 8) {
+                double bv[8];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    bv[k] = bp[(int64_t)(i + k) * N];
-                    dv[k] = dp[(int64_t)(i + k) * N];
-                }
+                for (int k = 0; k < 8; ++k) bv[k] = bp[(int64_t)(i + k) * N];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < 8; ++k) {
 #pragma unroll
                     for (int u = 0; u < BW_SYS; ++u) {
                         const zd e = E[u][i + k];
                         aB[u] = cmk(fma(bv[k], e.re, aB[u].re), fma(bv[k], e.im, aB[u].im));
-                        aD[u] = cmk(fma(dv[k], e.re, aD[u].re), fma(dv[k], e.im, aD[u].im));
                     }
                 }
             }
             for (; i < cnt; ++i) {
-                const double bv = bp[(int64_t)i * N], dv = dp[(int64_t)i * N];
+                const double bv = bp[(int64_t)i * N];
 #pragma unroll
                 for (int u = 0; u < BW_SYS; ++u) {
                     const zd e = E[u][i];
                     aB[u] = cmk(fma(bv, e.re, aB[u].re), fma(bv, e.im, aB[u].im));
-                    aD[u] = cmk(fma(dv, e.re, aD[u].re), fma(dv, e.im, aD[u].im));
                 }
             }
         }
@@ -183,9 +172,7 @@ __global__ __launch_bounds__(SYN_THREADS) void k_boundary_rhs(const double* __re
     for (int u = 0; u < BW_SYS; ++u) {
         if (u < ns) {
             const fhw_assemble_item it = items[j0 + u];
-            const double eta = it.eta;
-            const zd B = cmk(dt * aB[u].re, dt * aB[u].im), D = cmk(dt * aD[u].re, dt * aD[u].im);
-            g[(int64_t)q * sg + it.g_off + node] = cmk(D.re + eta * B.im, D.im - eta * B.re);
+            g[(int64_t)q * sg + it.g_off + node] = cmk(dt * aB[u].re, dt * aB[u].im);
         }
     }
 }
@@ -381,12 +368,12 @@ hipError_t launch_window_spectra(hipStream_t s, const double* f, int64_t n, doub
     return hipGetLastError();
 }
 
-hipError_t launch_boundary_rhs(hipStream_t s, const double* b, const double* db, int64_t n_t, int32_t N, double t0,
-                               double dt, double H, int64_t k_first, int32_t n_win, double c,
-                               const fhw_assemble_item* d_items, int32_t n_sys, int64_t sg, void* g) {
+hipError_t launch_boundary_rhs(hipStream_t s, const double* b, int64_t n_t, int32_t N, double t0, double dt,
+                               double H, int64_t k_first, int32_t n_win, double c, const fhw_assemble_item* d_items,
+                               int32_t n_sys, int64_t sg, void* g) {
     if (n_win <= 0 || n_sys <= 0 || N <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_boundary_rhs, dim3(n_win, (n_sys + BW_SYS - 1) / BW_SYS, (N + SYN_THREADS - 1) / SYN_THREADS),
-                       dim3(SYN_THREADS), 0, s, b, db, n_t, N, t0, dt, H, k_first, c, d_items, n_sys, sg, (zd*)g);
+                       dim3(SYN_THREADS), 0, s, b, n_t, N, t0, dt, H, k_first, c, d_items, n_sys, sg, (zd*)g);
     return hipGetLastError();
 }
 

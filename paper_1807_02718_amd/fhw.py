@@ -28,6 +28,8 @@ FHW_E_STATE = -6
 FHW_E_BUSY = -7
 FHW_FP64 = 0
 FHW_FP32_REFINE = 1
+FHW_FORM_DIRECT = 0
+FHW_FORM_COMBINED = 1
 FHW_INC_PLANE = 0
 FHW_INC_POINT = 1
 
@@ -43,7 +45,8 @@ class fhw_problem(C.Structure):
                 ("ppw", C.c_double), ("n_min", C.c_int32), ("n_mult", C.c_int32), ("n_cap", C.c_int32),
                 ("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_max", C.c_int32),
                 ("direction", C.c_double * 2), ("j_first", C.c_int32),
-                ("lf_M", C.c_int32), ("lf_N", C.c_int32), ("lf_jc", C.c_int32), ("lf_q", C.c_double)]
+                ("lf_M", C.c_int32), ("lf_N", C.c_int32), ("lf_jc", C.c_int32), ("lf_q", C.c_double),
+                ("formulation", C.c_int32)]
 
 
 class fhw_signal(C.Structure):
@@ -59,8 +62,7 @@ class fhw_incidence(C.Structure):
 
 
 class fhw_boundary(C.Structure):
-    _fields_ = [("b", C.c_void_p), ("db", C.c_void_p), ("N", C.c_int32), ("n_t", C.c_int64), ("t0", C.c_double),
-                ("dt", C.c_double)]
+    _fields_ = [("b", C.c_void_p), ("N", C.c_int32), ("n_t", C.c_int64), ("t0", C.c_double), ("dt", C.c_double)]
 
 
 class fhw_system(C.Structure):
@@ -119,7 +121,9 @@ def _load():
         "fhw_window_range": [C.c_double, C.c_double, C.c_double, p_i64, p_i32],
         "fhw_solve_general": [vp, C.POINTER(fhw_boundary), C.c_double, i64, i32, vp, _dp, p_i32],
         "fhw_eval_field_windows": [vp, vp, i32, _dp, i32, vp],
+        "fhw_eval_field_windows_lowfreq": [vp, vp, i32, _dp, i32, vp],
         "fhw_synthesize_windows": [vp, C.POINTER(fhw_windows), i64, i32, vp, i32, _dp, i32, vp],
+        "fhw_synthesize_windows_lowfreq": [vp, C.POINTER(fhw_windows), i64, i32, vp, vp, i32, _dp, i32, vp],
         "fhw_geometry": [vp, i32, vp],
         "fhw_kress_weights": [vp, i32, vp, vp],
         "fhw_assemble": [vp, i32, i32, vp, p_i64, vp, p_i64],
@@ -149,7 +153,8 @@ _lib = _load()
 EXPORTED = ("fhw_create", "fhw_destroy", "fhw_last_error", "fhw_version", "fhw_plan", "fhw_plan_curves",
             "fhw_plan_systems", "fhw_factor", "fhw_solve_range", "fhw_solve_range_noalloc",
             "fhw_solve_densities", "fhw_solve_incidences", "fhw_solve_cached", "fhw_eval_field", "fhw_eval_field_curve", "fhw_eval_field_lowfreq", "fhw_synthesize", "fhw_synthesize_lowfreq", "fhw_synthesize_uniform", "fhw_synth_active_pairs", "fhw_run", "fhw_window_range", "fhw_solve_general",
-            "fhw_eval_field_windows", "fhw_synthesize_windows", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
+            "fhw_eval_field_windows", "fhw_eval_field_windows_lowfreq", "fhw_synthesize_windows",
+            "fhw_synthesize_windows_lowfreq", "fhw_geometry", "fhw_kress_weights", "fhw_assemble",
             "fhw_lu_factor", "fhw_lu_solve", "fhw_window_spectra", "fhw_fourier_coefficients", "fhw_hankel01",
             "fhw_profile", "fhw_profile_read", "fhw_server_create", "fhw_server_submit", "fhw_server_poll",
             "fhw_server_stats", "fhw_server_destroy")
@@ -211,11 +216,13 @@ class Context:
 
     # -- plan -----------------------------------------------------------------
     def plan(self, curve, W, F, N=None, c=1.0, ppw=10.0, n_min=64, n_mult=32, n_cap=4096, precision="fp64",
-             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0), j_first=0, lowfreq=None):
+             refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0), j_first=0, lowfreq=None, formulation="direct"):
         """Plan one curve, or several (a list: fhw_plan_curves, system s = k F + j).
         j_first > 0 plans the band (j_first + j) W / F, j = 1..F (solves only).
         lowfreq = dict(jc, M, n, q) adds the graded low-frequency systems
-        (M n - 1 of them after the F grid systems; one curve).
+        (M n - 1 of them after the F grid systems; one curve).  formulation
+        "combined": the exterior Dirichlet problem for arbitrary data (general
+        boundary data, fhw_solve_general; one curve, fixed N).
         Returns (N per system, psi offsets)."""
         many = isinstance(curve, (list, tuple))
         curves = list(curve) if many else [curve]
@@ -232,6 +239,7 @@ class Context:
         pr.refine_tol, pr.refine_max = float(refine_tol), int(refine_max)
         pr.direction[0], pr.direction[1] = float(direction[0]), float(direction[1])
         pr.j_first = int(j_first)
+        pr.formulation = {"direct": FHW_FORM_DIRECT, "combined": FHW_FORM_COMBINED}[formulation]
         extra = 0
         if lowfreq is not None:
             pr.lf_M, pr.lf_N, pr.lf_jc = int(lowfreq["M"]), int(lowfreq["n"]), int(lowfreq["jc"])
@@ -425,16 +433,16 @@ class Context:
         return u, psi, V, resid, sweeps
 
     # -- general incident fields ---------------------------------------------------
-    def solve_general(self, b, db, t0, dt, H, k_first=None, n_win=None, psi=None):
-        """fhw_solve_general: b, db device float64 [n_t][N] (boundary data
-        -u_inc and its normal derivative at the nodes); windows k_first ..
-        k_first + n_win - 1 (default: all that meet the samples' range).
-        Returns (psi [n_win, psi_off[F]] complex128, resid [n_win, F], sweeps
-        [n_win, F], k_first)."""
+    def solve_general(self, b, t0, dt, H, k_first=None, n_win=None, psi=None):
+        """fhw_solve_general on a plan of the combined formulation: b device
+        float64 [n_t][N] (Dirichlet data -u_inc at the nodes); windows k_first
+        .. k_first + n_win - 1 (default: all that meet the samples' range).
+        Returns (psi [n_win, psi_off[S]] complex128, resid [n_win, S], sweeps
+        [n_win, S], k_first)."""
         n_t, N = int(b.shape[0]), int(b.shape[1])
         if k_first is None or n_win is None:
             k_first, n_win = window_range(t0, t0 + dt * (n_t - 1), H)
-        bd = fhw_boundary(_ptr(b).value, _ptr(db).value, N, n_t, float(t0), float(dt))
+        bd = fhw_boundary(_ptr(b).value, N, n_t, float(t0), float(dt))
         if psi is None:
             psi = torch.empty((max(int(n_win), 1), int(self.psi_off[-1])), dtype=torch.complex128, device=self.device)
         resid = np.zeros((max(int(n_win), 1), self.S))
@@ -452,6 +460,16 @@ class Context:
         self._check(_lib.fhw_eval_field_windows(self._h, _ptr(psi), nw, obs_p, Nr, _ptr(V)))
         return V
 
+    def eval_field_windows_lowfreq(self, psi, obs, V_sing=None):
+        """fhw_eval_field_windows_lowfreq: V_sing [n_win, N_r, M n + 1] complex128."""
+        obs_h, obs_p = _host(obs, np.float64)
+        Nr, nw = obs_h.shape[0], int(psi.shape[0])
+        if V_sing is None:
+            lf = self.lowfreq or {"M": 0, "n": 0}
+            V_sing = torch.empty((nw, Nr, lf["M"] * lf["n"] + 1), dtype=torch.complex128, device=self.device)
+        self._check(_lib.fhw_eval_field_windows_lowfreq(self._h, _ptr(psi), nw, obs_p, Nr, _ptr(V_sing)))
+        return V_sing
+
     def synthesize_windows(self, H, tau0, k_first, V, times, u=None):
         """fhw_synthesize_windows: u [N_r, N_t] from each window's own field."""
         wn = fhw_windows(float(H), float(tau0), 0.0)
@@ -461,6 +479,18 @@ class Context:
             u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
         self._check(_lib.fhw_synthesize_windows(self._h, C.byref(wn), int(k_first), nw, _ptr(V), Nr, tp, len(th),
                                                 _ptr(u)))
+        return u
+
+    def synthesize_windows_lowfreq(self, H, tau0, k_first, V, V_sing, times, u=None):
+        """fhw_synthesize_windows_lowfreq: u [N_r, N_t] with the low-frequency
+        decomposition from each window's own fields."""
+        wn = fhw_windows(float(H), float(tau0), 0.0)
+        th, tp = _host(times, np.float64)
+        nw, Nr = int(V.shape[0]), int(V.shape[1])
+        if u is None:
+            u = torch.empty((Nr, len(th)), dtype=torch.float64, device=self.device)
+        self._check(_lib.fhw_synthesize_windows_lowfreq(self._h, C.byref(wn), int(k_first), nw, _ptr(V),
+                                                        _ptr(V_sing), Nr, tp, len(th), _ptr(u)))
         return u
 
     def synth_active_pairs(self):
