@@ -227,7 +227,11 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
 #ifndef FHW_SM_NV
 #define FHW_SM_NV 4      // vectors per workgroup (halved when their LDS does not fit)
 #endif
+#ifndef FHW_SM_LD
+#define FHW_SM_LD 8      // factor loads in flight per thread
+#endif
 #define SM_TH FHW_SM_TH
+#define SM_LD FHW_SM_LD
 template <typename T, int NV>
 __global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict__ Ns,
                                                         const int64_t* __restrict__ a_off,
@@ -307,12 +311,13 @@ __global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict_
 #pragma unroll
             for (int u = 0; u < NV; ++u) sv[u] = cmk(0.0, 0.0);
             int c = 0;
-            for (; c + 4 <= nb; c += 4) {
-                cpx<T> l4[4];
+            // SM_LD columns' loads in flight before their products
+            for (; c + SM_LD <= nb; c += SM_LD) {
+                cpx<T> l4[SM_LD];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) l4[e] = Li[(int64_t)(c + e) * N];
+                for (int e = 0; e < SM_LD; ++e) l4[e] = Li[(int64_t)(c + e) * N];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                for (int e = 0; e < SM_LD; ++e) {
                     const zd l = cmk((double)l4[e].re, (double)l4[e].im);
 #pragma unroll
                     for (int u = 0; u < NV; ++u) sv[u] = cfma(sv[u], l, xs[u * ldx + k0 + c + e]);
@@ -340,12 +345,12 @@ __global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict_
             if (lane < nb) {
                 const cpx<T>* Ur = LU + k0 + lane;
                 int c = c0 + wid;
-                for (; c + 3 * NW < N; c += 4 * NW) {
-                    cpx<T> u4[4];
+                for (; c + (SM_LD - 1) * NW < N; c += SM_LD * NW) {
+                    cpx<T> u4[SM_LD];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) u4[e] = Ur[(int64_t)(c + e * NW) * N];
+                    for (int e = 0; e < SM_LD; ++e) u4[e] = Ur[(int64_t)(c + e * NW) * N];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
+                    for (int e = 0; e < SM_LD; ++e) {
                         const zd uu = cmk((double)u4[e].re, (double)u4[e].im);
 #pragma unroll
                         for (int u = 0; u < NV; ++u) sv[u] = cfma(sv[u], uu, xs[u * ldx + c + e * NW]);
