@@ -17,6 +17,8 @@
 //                 MFMA 16x16x4 products (Gauss's 3M form).
 // A panel's L columns carry the pivots of its pair partner but not those of
 // later pairs; the solves replay the pivots pair by pair.
+#include <algorithm>
+
 #include "fhw_device.h"
 #include "fhw_internal.h"
 #include "gemm_table.h"
@@ -96,10 +98,10 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                                                       const int64_t* __restrict__ a_off,
                                                       const int64_t* __restrict__ piv_off,
                                                       cpx<T>* __restrict__ Abase, int* __restrict__ piv,
-                                                      int* __restrict__ status) {
+                                                      int* __restrict__ status, const int32_t* __restrict__ ids) {
     static_assert(NB % W == 0, "sub-panels tile the panel");
     __shared__ panel_lds<T, W, PT> S;
-    const int b = blockIdx.x;
+    const int b = ids ? ids[blockIdx.x] : (int)blockIdx.x;
     const int N = Ns[b];
     if (k0 >= N) return;
     const int m = N - k0;
@@ -803,16 +805,54 @@ void lu_build_schedule(const int32_t* N, int32_t batch, fhw_lu_sched& sch) {
         op.kind = FHW_LU_OP_SWAP; op.k0 = k0; op.cbeg = cbeg; op.ccount = ccount; op.grid = (maxc + 255) / 256;
         sch.ops.push_back(op);
     };
+    // One panel launch per rows-per-thread class (R = 1, 2, 4, 8, 16 for
+    // 256 threads): each matrix still being factored runs the register shape
+    // of its own panel height, not of the tallest panel in the batch.  A class
+    // of fewer matrices than CUs is folded into the next taller class (it
+    // would run alone as one under-filled wave of workgroups), and so is every
+    // class of a batch of at most 256 matrices (one workgroup per CU or fewer:
+    // each launch costs a full panel latency).  The matrices of a launch are
+    // listed largest first, so the longest workgroups start first; a launch
+    // over every matrix of an equal-order batch needs no list.
+    bool uniform = true;
+    for (int q = 1; q < batch; ++q) uniform = uniform && N[q] == N[0];
     auto panel = [&](int k0) {
-        int rows = 0;
-        for (int q = 0; q < batch; ++q) rows = std::max(rows, N[q] - k0);
-        if (rows <= 0) return;
-        int R = (rows + PANEL_THREADS - 1) / PANEL_THREADS;
-        R = R <= 1 ? 1 : (R <= 2 ? 2 : (R <= 4 ? 4 : (R <= 8 ? 8 : 16)));
+        std::vector<int32_t> cls[5];
+        for (int q = 0; q < batch; ++q) {
+            const int rows = N[q] - k0;
+            if (rows <= 0) continue;
+            const int r = (rows + PANEL_THREADS - 1) / PANEL_THREADS;
+            cls[r <= 1 ? 0 : (r <= 2 ? 1 : (r <= 4 ? 2 : (r <= 8 ? 3 : 4)))].push_back(q);
+        }
+        for (int c = 0; c < 4; ++c) {
+            if (cls[c].empty()) continue;
+            int up = c + 1;
+            while (up < 5 && cls[up].empty()) ++up;
+            if (up < 5 && (batch <= 256 || (int)cls[c].size() < 256)) {
+                cls[up].insert(cls[up].end(), cls[c].begin(), cls[c].end());
+                cls[c].clear();
+            }
+        }
+        bool any = false;
+        for (int c = 4; c >= 0; --c) {
+            std::vector<int32_t>& ids = cls[c];
+            if (ids.empty()) continue;
+            any = true;
+            fhw_lu_op op{};
+            op.kind = FHW_LU_OP_PANEL; op.k0 = k0; op.R = 1 << c;
+            op.grid = (int32_t)ids.size();
+            if (uniform && (int32_t)ids.size() == batch) {
+                op.prefix_off = -1;
+            } else {
+                std::stable_sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) { return N[x] > N[y]; });
+                op.prefix_off = (int64_t)sch.prefix.size();
+                sch.prefix.insert(sch.prefix.end(), ids.begin(), ids.end());
+            }
+            sch.ops.push_back(op);
+        }
+        if (!any) return;
         fhw_lu_op op{};
-        op.kind = FHW_LU_OP_PANEL; op.k0 = k0; op.R = R;
-        sch.ops.push_back(op);
-        op.kind = FHW_LU_OP_DIAGINV;
+        op.kind = FHW_LU_OP_DIAGINV; op.k0 = k0;
         sch.ops.push_back(op);
     };
     for (int p = 0; p < sch.nsteps; p += 2) {
@@ -843,18 +883,18 @@ static void lu_set_lds_limits() {
     });
 }
 
-// rows per thread R (from the step's largest panel height, for 256 threads)
+// rows per thread R (from the tallest panel of the launch, for 256 threads)
 // and sub-panel width W of the panel kernel, chosen to keep R*W complex values
 // per thread in registers.  Batches of at most 256 matrices (one per CU or
 // fewer) use 1024 threads per matrix instead: a quarter of the rows per
 // thread, so each matrix's latency-bound panel work is spread wider.
 template <typename T>
 static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, int k0, cpx<T>* A, int32_t* piv,
-                               int32_t* st) {
+                               int32_t* st, int grid, const int32_t* ids) {
 #define FHW_PANEL(RR, WW, EE, PT) FHW_PANEL_D(RR, WW, EE, PT, 0)
 #define FHW_PANEL_D(RR, WW, EE, PT, DD)                                                                       \
-    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE, PT, DD>), dim3(bd.batch), dim3(PT), 0, s, k0, bd.N, bd.a_off, \
-                       bd.piv_off, A, piv, st)
+    hipLaunchKernelGGL((k_lu_panel<T, RR, WW, EE, PT, DD>), dim3(grid), dim3(PT), 0, s, k0, bd.N, bd.a_off, \
+                       bd.piv_off, A, piv, st, ids)
 #define FHW_PANEL_T(RR, WE, PT) FHW_PANEL_X(RR, WE, PT)
 #define FHW_PANEL_X(...) FHW_PANEL(__VA_ARGS__)
     // large batches: (threads, W, WPE, PD) from the table, ceil(256 R / threads) rows per thread
@@ -913,7 +953,8 @@ static hipError_t lu_factor_t(hipStream_t s, const fhw_batch_dev& bd, const fhw_
         switch (op.kind) {
             case FHW_LU_OP_PANEL:
                 prof_begin(prof, FHW_STAGE_LU_PANEL, s);
-                e = launch_panel<T>(s, op.R, bd, op.k0, A, piv, st);
+                e = launch_panel<T>(s, op.R, bd, op.k0, A, piv, st, op.grid,
+                                    op.prefix_off < 0 ? nullptr : d_prefix + op.prefix_off);
                 prof_end(prof, s);
                 break;
             case FHW_LU_OP_DIAGINV:
