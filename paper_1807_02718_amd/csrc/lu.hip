@@ -59,19 +59,21 @@ __device__ __forceinline__ void lazy_load(cpx<T> (&l)[R], const cpx<T>* Lq, int 
     }
 }
 
-// Rows at or below lo: x(row, :) -= l(row) * u(:)
-template <typename T, int R, int W, int PT>
-__device__ __forceinline__ void lazy_update(T (&ar)[R][W], T (&ai)[R][W], const cpx<T> (&l)[R], const cpx<T>* u,
-                                            int tid, int lo, int m) {
+// Rows at or below lo: x(row, :) -= l(row) * u(:).  l is zero outside rows
+// [lo, m) (lazy_load), so every row takes the update unguarded: rows above
+// lo (final U rows, or rows about to be replaced by U_t) and rows past m
+// (never written back) are left as they are, up to the sign of a zero.  A
+// guard per row would cost a select per updated value (the compiler
+// if-converts it), half again the four FMAs of the complex update.
+template <typename T, int R, int W>
+__device__ __forceinline__ void lazy_update(T (&ar)[R][W], T (&ai)[R][W], const cpx<T> (&l)[R], const cpx<T>* u) {
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         const cpx<T> uc = u[c];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            if (tid + i * PT >= lo && tid + i * PT < m) {
-                ar[i][c] = ar[i][c] - l[i].re * uc.re + l[i].im * uc.im;
-                ai[i][c] = ai[i][c] - l[i].re * uc.im - l[i].im * uc.re;
-            }
+            ar[i][c] = ar[i][c] - l[i].re * uc.re + l[i].im * uc.im;
+            ai[i][c] = ai[i][c] - l[i].re * uc.im - l[i].im * uc.re;
         }
     }
 }
@@ -172,14 +174,14 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
             __syncthreads();
             if constexpr (PF == W) {
 #pragma unroll
-                for (int q = 0; q < W; ++q) lazy_update<T, R, W, PT>(ar, ai, l[q], S.U[buf][q], tid, tb + W, m);
+                for (int q = 0; q < W; ++q) lazy_update<T, R, W>(ar, ai, l[q], S.U[buf][q]);
             } else if constexpr (PD > 0) {
                 // column q0 + k from slot k, which then takes column q0 + k + PF
 #pragma unroll 1
                 for (int q0 = 0; q0 < W; q0 += PF) {
 #pragma unroll
                     for (int k = 0; k < PF; ++k) {
-                        lazy_update<T, R, W, PT>(ar, ai, l[k], S.U[buf][q0 + k], tid, tb + W, m);
+                        lazy_update<T, R, W>(ar, ai, l[k], S.U[buf][q0 + k]);
                         if (q0 + k + PF < W)
                             lazy_load<T, R, PT>(l[k], Lt + (int64_t)(q0 + k + PF) * N, tid, tb + W, m);
                     }
@@ -191,12 +193,12 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                         // column q + 1 (no rows, so zeros and no loads, after the last)
                         cpx<T> ln[R];
                         lazy_load<T, R, PT>(ln, Lt + (int64_t)(q + 1) * N, tid, q + 1 < W ? tb + W : m, m);
-                        lazy_update<T, R, W, PT>(ar, ai, l[0], S.U[buf][q], tid, tb + W, m);
+                        lazy_update<T, R, W>(ar, ai, l[0], S.U[buf][q]);
 #pragma unroll
                         for (int i = 0; i < R; ++i) l[0][i] = ln[i];
                     } else {
                         if (q > 0) lazy_load<T, R, PT>(l[0], Lt + (int64_t)q * N, tid, tb + W, m);
-                        lazy_update<T, R, W, PT>(ar, ai, l[0], S.U[buf][q], tid, tb + W, m);
+                        lazy_update<T, R, W>(ar, ai, l[0], S.U[buf][q]);
                     }
                 }
             }
