@@ -556,6 +556,153 @@ def cpu_baseline(wl, n_freq, max_workers=16):
                       f"synthesis excluded"}
 
 
+def _oracle_systems(args):
+    """One worker of the per-configuration CPU timing: the oracle's geometry,
+    assembly, LAPACK solve and (with observation points) field for each listed
+    system (curve index, kappa, N), with one BLAS thread; returns seconds."""
+    curves, systems, direction, obs = args
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        geoms = {}
+        t0 = time.perf_counter()
+        for k, kap, N in systems:
+            if (k, N) not in geoms:
+                geoms[(k, N)] = O.geometry(curves[k], N)
+            gm = geoms[(k, N)]
+            eta = float(O.coupling(np.array([kap]))[0])
+            A = O.assemble(gm, kap, eta)
+            psi, _ = O.solve_density(A, O.rhs_plane_wave(gm, kap, eta, direction))
+            if obs is not None:
+                O.field(gm, psi, kap, obs)
+        return time.perf_counter() - t0
+
+
+def configs_bench(fhw, torch, Wk, reps, cpu_sample, max_workers=16):
+    """Each configuration of the paper's experiments end to end: the GPU path
+    (median of reps whole passes after one warm-up, stage timers off, plan
+    apart) against the FP64 oracle's frequency solves on the host (assembly +
+    LAPACK solve + field per system, synthesis excluded) timed on an evenly
+    spaced sample of at most cpu_sample systems and scaled to all of them, both
+    spread over worker processes (all-core) and in one process (single-core,
+    an eighth of the sample)."""
+    import oracle as O
+    from multiprocessing import get_context
+    dev = torch.device("cuda")
+    LF = dict(jc=16, M=16, n=8, q=9.1)
+    kc = Wk.kite_chirp()
+    sb = Wk.star_batch()
+    cases = [
+        ("circle, low-frequency decomposition (unit circle N = 128, 256 + 127 graded frequencies on (0, 20])",
+         "circle_lowfreq", [Wk.circle(1.0)], "fp64", dict(W=20.0, F=256, N=128, lowfreq=LF)),
+        ("kite chirp, FP64 (512 frequencies on (0, 200], N 64-2976)", "kite_chirp", [kc.curve], "fp64",
+         dict(W=kc.W, F=kc.F, **kc.N)),
+        ("kite chirp, FP32 LU + FP64 refinement to 1e-12", "kite_chirp", [kc.curve], "fp32_refine",
+         dict(W=kc.W, F=kc.F, **kc.N)),
+        ("star batch, FP64 solves (64 star curves x 256 frequencies on (0, 120], N 64-2048)", "stars",
+         sb["curves"], "fp64", dict(W=sb["W"], F=sb["F"], **sb["rule"])),
+    ]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(max_workers, cores))
+    rows = []
+    with get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_systems, [([Wk.circle(1.0)], [(0, 1.0, 64)], (1.0, 0.0), None)] * workers)
+        for title, kind, curves, prec, kw in cases:
+            print(f"bench: configs: {title}", file=sys.stderr, flush=True)
+            kw = dict(kw)
+            W, F = kw.pop("W"), kw.pop("F")
+            ctx = fhw.Context()
+            try:
+                t0 = time.perf_counter()
+                Ns, off = ctx.plan(curves if len(curves) > 1 else curves[0], W, F, precision=prec,
+                                   refine_tol=1e-12, refine_max=10, direction=(1.0, 0.0), **kw)
+                torch.cuda.synchronize()
+                plan_s = time.perf_counter() - t0
+                psi = torch.empty(int(off[-1]), dtype=torch.complex128, device=dev)
+                if kind == "circle_lowfreq":
+                    wl = Wk.circle_pulse()
+                    obs, times, H, tau0 = wl.obs, wl.times, wl.H, wl.tau0
+                elif kind == "kite_chirp":
+                    obs, times, H, tau0 = kc.obs, kc.times, kc.H, kc.tau0
+                else:
+                    obs = None
+                sig = Wk.gaussian_pulse() if kind == "circle_lowfreq" else kc.signal
+                f = torch.as_tensor(sig.f, device=dev)
+                V = None if obs is None else torch.empty((len(obs), 2 * F), dtype=torch.complex128, device=dev)
+
+                def one_pass():
+                    ctx.solve_densities(psi)
+                    if kind == "circle_lowfreq":
+                        ctx.eval_field(psi, obs, zero_value=1.0, V=V)
+                        Vs = ctx.eval_field_lowfreq(psi, obs, zero_value=1.0)
+                        ctx.synthesize_lowfreq(f, sig.t0, sig.dt, H, tau0, V, Vs, times)
+                    elif kind == "kite_chirp":
+                        ctx.eval_field(psi, obs, zero_value=1.0, V=V)
+                        ctx.synthesize(f, sig.t0, sig.dt, H, tau0, V, times)
+
+                one_pass()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(reps):
+                    t1 = time.perf_counter()
+                    one_pass()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t1)
+            finally:
+                ctx.close()
+            gpu_s = float(np.median(ts))
+            # the same systems for the oracle: (curve index, kappa, N)
+            if kind == "stars":
+                _, kap = O.frequency_grid(W, F)
+                systems = [(k, float(kap[j]), int(n)) for k, cv in enumerate(curves)
+                           for j, n in enumerate(O.discretization_sizes(kap, O.curve_length(cv), **kw))]
+            elif kind == "kite_chirp":
+                _, kap = O.frequency_grid(W, F)
+                systems = [(0, float(kap[j]), int(n))
+                           for j, n in enumerate(O.discretization_sizes(kap, O.curve_length(curves[0]), **kw))]
+            else:
+                _, kap = O.frequency_grid(W, F)
+                om_c, _, _, nodes = O.lowfreq_frequencies(W, F, LF["jc"], LF["M"], LF["n"], LF["q"])
+                graded = []                                     # subintervals share their ends
+                for om in np.sort(np.concatenate(nodes)):
+                    if om > 0.0 and not np.isclose(om, om_c, rtol=1e-9, atol=0.0) and \
+                            not (graded and np.isclose(om, graded[-1], rtol=1e-9, atol=0.0)):
+                        graded.append(float(om))
+                ks = list(kap) + graded
+                systems = [(0, float(k), 128) for k in ks]
+            assert len(systems) == len(Ns), (kind, len(systems), len(Ns))
+            idx = np.unique(np.linspace(0, len(systems) - 1, min(cpu_sample, len(systems))).round().astype(int))
+            sample = [systems[i] for i in idx]
+            parts = [sample[w::workers] for w in range(workers)]
+            t1 = time.perf_counter()
+            pool.map(_oracle_systems, [(curves, p, (1.0, 0.0), obs) for p in parts if p])
+            cpu_all = (time.perf_counter() - t1) * len(systems) / len(sample)
+            sub = sample[::8]
+            cpu_one = _oracle_systems((curves, sub, (1.0, 0.0), obs)) * len(systems) / len(sub)
+            rows.append({"config": title, "precision": prec, "systems": len(Ns), "N_min": int(min(Ns)),
+                         "N_max": int(max(Ns)), "gpu_s": gpu_s, "gpu_solves_per_s": len(Ns) / gpu_s,
+                         "plan_s": plan_s, "cpu_all_core_s": cpu_all, "cpu_single_core_s": cpu_one,
+                         "cpu_workers": workers, "cpu_sample_systems": len(sample),
+                         "gpu_vs_cpu_all_core": cpu_all / gpu_s,
+                         "gpu_path": "solves + fields + synthesis" if obs is not None else "solves"})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    print(json.dumps({"metric": "per-configuration wall time: the GPU path against the FP64 oracle on the host",
+                      "cpu_model": model, "host_cores_available": cores,
+                      "cpu_note": "oracle frequency solves only (geometry, assembly, LAPACK solve, field at the "
+                                  "observation points; synthesis excluded), timed on an evenly spaced sample and "
+                                  "scaled to every system",
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -568,7 +715,7 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     ap.add_argument("--workload", default="kite_n1024", choices=["kite_n1024", "stars", "serve", "batch_sweep", "uniform",
-                                                                "tracking", "general"],
+                                                                "tracking", "general", "configs"],
                     help="kite_n1024: the headline metric; stars: 64 star curves x 256 frequencies in one batch; "
                          "serve: Poisson request stream (per-request latency); batch_sweep: solves/s at "
                          "batches of 1, 16, 256, 1024 frequencies")
@@ -594,6 +741,9 @@ def main():
     from paper_1807_02718_amd import fhw
     if a.workload == "stars":
         star_batch_bench(fhw, torch, Wk.star_batch(), a.steps, a.warmup)
+        return
+    if a.workload == "configs":
+        configs_bench(fhw, torch, Wk, max(3, a.steps), a.cpu_freqs if a.cpu_freqs > 0 else 96)
         return
     if a.workload == "uniform":
         uniform_bench(fhw, torch, Wk, max(3, a.steps))
