@@ -347,12 +347,15 @@ def general_bench(fhw, torch, Wk, reps, modes):
             ctx.solve_general(b, gp["t0"], dt, H, k_first, n_win, psi=psi)
             pr = ctx.profile_read()
             ctx.profile(False)
-            t0 = time.perf_counter()
-            V = ctx.eval_field_windows(psi, wl.obs)
-            t_field = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            u = ctx.synthesize_windows(H, tau0, k_first, V, times)
-            t_synth = time.perf_counter() - t0
+            tf, tsy = [], []
+            for _ in range(reps):            # median of reps calls each (each call synchronizes)
+                t0 = time.perf_counter()
+                V = ctx.eval_field_windows(psi, wl.obs)
+                tf.append(time.perf_counter() - t0)
+                t0 = time.perf_counter()
+                u = ctx.synthesize_windows(H, tau0, k_first, V, times)
+                tsy.append(time.perf_counter() - t0)
+            t_field, t_synth = float(np.median(tf)), float(np.median(tsy))
             umax = float(u.abs().max())
         finally:
             ctx.close()
