@@ -1485,16 +1485,15 @@ int fhw_eval_field_windows_lowfreq(fhw_ctx* c, const void* psi, int32_t n_win, c
     if (n_win < 0 || N_r < 0 || (n_win > 0 && N_r > 0 && (!psi || !obs || !V_sing)))
         return fhw_fail(c, FHW_E_INVALID, "field_windows_lowfreq: bad arguments");
     if (n_win == 0 || N_r == 0) return FHW_OK;
+    if (n_win > 65535 * 8) return fhw_fail(c, FHW_E_INVALID, "field_windows_lowfreq: too many windows");
     for (int q = 0; q < 2 * N_r; ++q)
         if (!isfinite(obs[q])) return fhw_fail(c, FHW_E_INVALID, "field_windows_lowfreq: observation point not finite");
     rc = fhw_ensure_scratch(c, (size_t)N_r * 16);
     if (rc) return rc;
     FHW_HIP(c, hipMemcpyAsync(c->scratch, obs, (size_t)N_r * 16, hipMemcpyHostToDevice, c->stream));
     const int64_t ps = c->psi_off[c->Ns.size()], vs = (int64_t)N_r * (c->lf_extra + 2);
-    for (int32_t q = 0; q < n_win; ++q)
-        STAGE(c, FHW_STAGE_FIELD, launch_field_list(c->stream, plan_of(c).d_lf_items, c->lf_extra + 1,
-                                                    (const zd*)psi + q * ps, (const double*)c->scratch, N_r, 0.0,
-                                                    (zd*)V_sing + q * vs, true));
+    STAGE(c, FHW_STAGE_FIELD, launch_field_blocks(c->stream, plan_of(c).d_lf_items, c->lf_extra + 1, psi, ps, n_win,
+                                                  (const double*)c->scratch, N_r, 0.0, V_sing, vs, true));
     FHW_HIP(c, hipStreamSynchronize(c->stream));
     return FHW_OK;
 }

@@ -283,11 +283,13 @@ hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F,
                         const double* obs, int32_t N_r, double zero_value, void* V);
 hipError_t launch_hankel01(hipStream_t s, const double* z, int64_t n, void* h);
 // V[r][0] = zero_value, V[r][1 + j] = field of item j: complex128 [N_r][n_items + 1]
-// the field of n_blk density blocks (block q at psi + q psi_bstride) into
-// V + q V_bstride, each as launch_field writes it, with V(r, 0) = zero_value
+// the field of n_blk density blocks by the combined potential (block q at
+// psi + q psi_bstride; every item at the same N) into V + q V_bstride, each as
+// launch_field writes it with V(r, 0) = zero_value, or with list = true as
+// launch_field_list writes it (the F items an explicit list)
 hipError_t launch_field_blocks(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
                                int64_t psi_bstride, int32_t n_blk, const double* obs, int32_t N_r,
-                               double zero_value, void* V, int64_t V_bstride);   // combined potential
+                               double zero_value, void* V, int64_t V_bstride, bool list = false);   // combined potential
 // (combined: the combined potential instead of the single layer)
 hipError_t launch_field_list(hipStream_t s, const fhw_field_item* d_items, int32_t n_items, const void* psi,
                              const double* obs, int32_t N_r, double zero_value, void* V, bool combined = false);

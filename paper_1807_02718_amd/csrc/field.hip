@@ -78,7 +78,9 @@ __device__ __forceinline__ zd combined_kernel(const double* geom, int N, int i, 
 // the end.  Kernel evaluation and accumulation never hold registers at the
 // same time, and a kernel value serves every window of the group.  LDS rows
 // are padded by one entry so that the rows read side by side fall in
-// different banks.
+// different banks.  LIST: the F systems are an explicit list (the graded
+// low-frequency nodes) written as V[r][1 + j] with V[r][0] = zero_value,
+// instead of the full DFT grid.
 #ifndef FHW_FB_P
 #define FHW_FB_P 16      // observation points per workgroup (8: 4.2 ms, 4: 4.8 ms against 3.7 ms for 16)
 #endif
@@ -89,6 +91,7 @@ __device__ __forceinline__ zd combined_kernel(const double* geom, int N, int i, 
 #define FB_BLK 16
 #define FB_CH 64
 static_assert(FB_P * FB_BLK <= 256, "one (point, window) pair per thread at least");
+template <bool LIST>
 __global__ __launch_bounds__(256, FHW_FB_WPE) void k_field_blocks(const fhw_field_item* __restrict__ items, int F,
                                                       const zd* __restrict__ psi, int64_t psi_bstride, int n_blk,
                                                       const double* __restrict__ obs, int N_r, double zero_value,
@@ -147,10 +150,16 @@ __global__ __launch_bounds__(256, FHW_FB_WPE) void k_field_blocks(const fhw_fiel
         if (r < N_r) {
             const double wq = 2.0 * FHW_PI / (double)N;
             const zd val = cmk(wq * sum.re, wq * sum.im);
-            zd* Vr = V + (int64_t)(q0 + u) * V_bstride + (int64_t)r * 2 * F;
-            if (j < F - 1) Vr[F + 1 + j] = val;
-            Vr[F - 1 - j] = cconj(val);
-            if (j == 0) Vr[F] = cmk(zero_value, 0.0);
+            if constexpr (LIST) {
+                zd* Vr = V + (int64_t)(q0 + u) * V_bstride + (int64_t)r * (F + 1);
+                Vr[1 + j] = val;
+                if (j == 0) Vr[0] = cmk(zero_value, 0.0);
+            } else {
+                zd* Vr = V + (int64_t)(q0 + u) * V_bstride + (int64_t)r * 2 * F;
+                if (j < F - 1) Vr[F + 1 + j] = val;
+                Vr[F - 1 - j] = cconj(val);
+                if (j == 0) Vr[F] = cmk(zero_value, 0.0);
+            }
         }
     }
 }
@@ -218,13 +227,17 @@ hipError_t launch_field(hipStream_t s, const fhw_field_item* d_items, int32_t F,
 
 hipError_t launch_field_blocks(hipStream_t s, const fhw_field_item* d_items, int32_t F, const void* psi,
                                int64_t psi_bstride, int32_t n_blk, const double* obs, int32_t N_r,
-                               double zero_value, void* V, int64_t V_bstride) {
+                               double zero_value, void* V, int64_t V_bstride, bool list) {
     if (N_r <= 0 || F <= 0 || n_blk <= 0) return hipSuccess;
     const int64_t blocks = (int64_t)F * ((N_r + FB_P - 1) / FB_P);
     const int64_t gy = (n_blk + FB_BLK - 1) / FB_BLK;
     if (blocks > 0x7fffffff || gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_field_blocks, dim3((unsigned)blocks, (unsigned)gy), dim3(256), 0, s, d_items, F,
-                       (const zd*)psi, psi_bstride, n_blk, obs, N_r, zero_value, (zd*)V, V_bstride);
+    if (list)
+        hipLaunchKernelGGL(k_field_blocks<true>, dim3((unsigned)blocks, (unsigned)gy), dim3(256), 0, s, d_items, F,
+                           (const zd*)psi, psi_bstride, n_blk, obs, N_r, zero_value, (zd*)V, V_bstride);
+    else
+        hipLaunchKernelGGL(k_field_blocks<false>, dim3((unsigned)blocks, (unsigned)gy), dim3(256), 0, s, d_items, F,
+                           (const zd*)psi, psi_bstride, n_blk, obs, N_r, zero_value, (zd*)V, V_bstride);
     return hipGetLastError();
 }
 
