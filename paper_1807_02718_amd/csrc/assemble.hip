@@ -42,7 +42,7 @@ __device__ __forceinline__ zd cfie_entry(double n_t, double cL, double cY, doubl
 // along i) and A(j, i) (staged in LDS, then written with lanes along j).
 // Diagonal tiles take i >= j only and mirror the strict part.  Tiles with
 // J = 0 also write the RHS.
-template <bool COMB>
+template <bool COMB, bool NT>
 __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_item* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int n_items,
                                                           double p1, double p2, zd* __restrict__ A,
@@ -136,8 +136,8 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
             e_ij = cmk(spi * (Rw * K1r + wq * K2r) + 0.5, spi * (Rw * K1i + wq * K2i));
             e_ji = e_ij;
         }
-        Aq[(int64_t)j * N + i] = e_ij;
-        if (A32q) A32q[(int64_t)j * N + i] = cmk((float)e_ij.re, (float)e_ij.im);
+        st_maybe_stream<NT>(&Aq[(int64_t)j * N + i], e_ij);
+        if (A32q) st_maybe_stream<NT>(&A32q[(int64_t)j * N + i], cmk((float)e_ij.re, (float)e_ij.im));
         mirror[jl][il] = e_ji;
     }
     if (J == 0 && jg == 0 && iok) {
@@ -159,8 +159,8 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
         // diagonal tiles computed pairs i >= j only: mirror the strict part
         if (jrow < N && icol < N && (I != J || icol > jrow)) {
             const zd v = mirror[jl2][il2];
-            Aq[(int64_t)icol * N + jrow] = v;
-            if (A32q) A32q[(int64_t)icol * N + jrow] = cmk((float)v.re, (float)v.im);
+            st_maybe_stream<NT>(&Aq[(int64_t)icol * N + jrow], v);
+            if (A32q) st_maybe_stream<NT>(&A32q[(int64_t)icol * N + jrow], cmk((float)v.re, (float)v.im));
         }
     }
 }
@@ -169,12 +169,20 @@ hipError_t launch_assemble_blocks(hipStream_t s, const fhw_assemble_item* d_item
                                   int32_t n_items, int64_t total_blocks, double p1, double p2, void* A,
                                   void* A32, void* g, bool combined) {
     if (total_blocks <= 0) return hipSuccess;
-    if (combined)
-        hipLaunchKernelGGL(k_assemble<true>, dim3((unsigned)total_blocks), dim3(ASM_THREADS), 0, s, d_items,
-                           d_prefix, n_items, p1, p2, (zd*)A, (zf*)A32, (zd*)g);
-    else
-        hipLaunchKernelGGL(k_assemble<false>, dim3((unsigned)total_blocks), dim3(ASM_THREADS), 0, s, d_items,
-                           d_prefix, n_items, p1, p2, (zd*)A, (zf*)A32, (zd*)g);
+    // stores with the nontemporal hint once the matrices (32 KB of FP64
+    // entries per tile pair) outgrow the 256 MB last-level cache
+#define FHW_ASM(CB, NTB)                                                                                     \
+    hipLaunchKernelGGL((k_assemble<CB, NTB>), dim3((unsigned)total_blocks), dim3(ASM_THREADS), 0, s, d_items, \
+                       d_prefix, n_items, p1, p2, (zd*)A, (zf*)A32, (zd*)g)
+    const bool nt = total_blocks > 8192;
+    if (combined) {
+        if (nt) FHW_ASM(true, true);
+        else FHW_ASM(true, false);
+    } else {
+        if (nt) FHW_ASM(false, true);
+        else FHW_ASM(false, false);
+    }
+#undef FHW_ASM
     return hipGetLastError();
 }
 

@@ -51,6 +51,40 @@ __device__ __forceinline__ cpx<T> crcp(cpx<T> a) {
     return cmk(ar / d, -ai / d);
 }
 
+// Streaming accesses with the nontemporal hint, for data touched once per
+// kernel (a matrix read once by a residual, written once by the assembly):
+// one 16- or 8-byte access each, as the plain ones.
+typedef double fhw_v2d __attribute__((ext_vector_type(2)));
+typedef float fhw_v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ zd ld_stream(const zd* p) {
+    const fhw_v2d t = __builtin_nontemporal_load((const fhw_v2d*)p);
+    return cmk(t.x, t.y);
+}
+__device__ __forceinline__ zf ld_stream(const zf* p) {
+    const fhw_v2f t = __builtin_nontemporal_load((const fhw_v2f*)p);
+    return cmk(t.x, t.y);
+}
+__device__ __forceinline__ void st_stream(zd* p, zd v) {
+    const fhw_v2d t = {v.re, v.im};
+    __builtin_nontemporal_store(t, (fhw_v2d*)p);
+}
+__device__ __forceinline__ void st_stream(zf* p, zf v) {
+    const fhw_v2f t = {v.re, v.im};
+    __builtin_nontemporal_store(t, (fhw_v2f*)p);
+}
+// The hint only where the data cannot stay cached anyway (large batches):
+// a repeated solve of one system finds its matrix in the last-level cache.
+template <bool STREAM, typename V>
+__device__ __forceinline__ V ld_maybe_stream(const V* p) {
+    if constexpr (STREAM) return ld_stream(p);
+    else return *p;
+}
+template <bool STREAM, typename V>
+__device__ __forceinline__ void st_maybe_stream(V* p, V v) {
+    if constexpr (STREAM) st_stream(p, v);
+    else *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // J0, Y0, J1, Y1 for z > 0 in FP64 (tables and regions in bessel_tables.h)
 // ---------------------------------------------------------------------------

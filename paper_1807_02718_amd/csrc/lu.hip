@@ -112,6 +112,7 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
     cpx<T>* P = Abase + a_off[b] + (int64_t)k0 * N + k0;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
+    const bool wave_live = __builtin_amdgcn_readfirstlane(wid) * 64 < m;   // row tid + i PT >= wid 64
     if (tid == 0) S.sing = 0;
 
     T ar[R][W], ai[R][W];
@@ -172,7 +173,10 @@ __global__ __launch_bounds__(PT, WPE) void k_lu_panel(int k0, const int* __restr
                 }
             }
             __syncthreads();
-            if constexpr (PF == W) {
+            // a wave whose rows all lie past the panel's end skips the update
+            // (a wave-uniform branch, no barrier inside)
+            if (!wave_live) {
+            } else if constexpr (PF == W) {
 #pragma unroll
                 for (int q = 0; q < W; ++q) lazy_update<T, R, W>(ar, ai, l[q], S.U[buf][q]);
             } else if constexpr (PD > 0) {

@@ -121,12 +121,12 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
             for (; c + 8 <= nb; c += 8) {
                 cpx<T> l8[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) l8[u] = Li[(int64_t)(c + u) * N];
+                for (int u = 0; u < 8; ++u) l8[u] = ld_maybe_stream<!WIDE>(&Li[(int64_t)(c + u) * N]);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) s8[u] = cfma(s8[u], cmk((double)l8[u].re, (double)l8[u].im), xs[k0 + c + u]);
             }
             for (; c < nb; ++c) {
-                const cpx<T> l = Li[(int64_t)c * N];
+                const cpx<T> l = ld_maybe_stream<!WIDE>(&Li[(int64_t)c * N]);
                 s8[0] = cfma(s8[0], cmk((double)l.re, (double)l.im), xs[k0 + c]);
             }
             zd s = s8[0];
@@ -153,12 +153,12 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
             for (; c + 3 * NW < N; c += 4 * NW) {
                 cpx<T> u4[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) u4[u] = Ur[(int64_t)(c + u * NW) * N];
+                for (int u = 0; u < 4; ++u) u4[u] = ld_maybe_stream<!WIDE>(&Ur[(int64_t)(c + u * NW) * N]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) s4[u] = cfma(s4[u], cmk((double)u4[u].re, (double)u4[u].im), xs[c + u * NW]);
             }
             for (; c < N; c += NW) {
-                const cpx<T> u = Ur[(int64_t)c * N];
+                const cpx<T> u = ld_maybe_stream<!WIDE>(&Ur[(int64_t)c * N]);
                 s4[0] = cfma(s4[0], cmk((double)u.re, (double)u.im), xs[c]);
             }
             s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
@@ -471,11 +471,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
         for (; c + 3 * NC < N; c += 4 * NC) {
             zd a4[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a4[u] = A[(int64_t)(c + u * NC) * N + i];
+            for (int u = 0; u < 4; ++u) a4[u] = ld_maybe_stream<PH == 1>(&A[(int64_t)(c + u * NC) * N + i]);
 #pragma unroll
             for (int u = 0; u < 4; ++u) s4[u] = cfma(s4[u], a4[u], xs[c + u * NC]);
         }
-        for (; c < N; c += NC) s4[0] = cfma(s4[0], A[(int64_t)c * N + i], xs[c]);
+        for (; c < N; c += NC) s4[0] = cfma(s4[0], ld_maybe_stream<PH == 1>(&A[(int64_t)c * N + i]), xs[c]);
         s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
     }
     cs[cg][il] = s;
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual_multi(const int* __r
             for (; c + 4 <= cnt; c += 4) {
                 zd a4[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a4[u] = Ac[(int64_t)(c + u) * N];
+                for (int u = 0; u < 4; ++u) a4[u] = ld_stream(&Ac[(int64_t)(c + u) * N]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual_multi(const int* __r
                 }
             }
             for (; c < cnt; ++c) {
-                const zd a = Ac[(int64_t)c * N];
+                const zd a = ld_stream(&Ac[(int64_t)c * N]);
 #pragma unroll
                 for (int q = 0; q < G; ++q)
                     if (q < n) s[q] = cfma(s[q], a, xs[q][c]);
