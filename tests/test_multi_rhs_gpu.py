@@ -5,8 +5,9 @@ group instead of once per vector.  20 incidences (plane waves and exterior
 point sources, mixed in every group of 8) on the kite at 520 frequencies,
 both precisions, through fhw_solve_incidences, against the oracle's LAPACK
 solves at sampled frequencies and against the same incidences solved one at
-a time (single-vector kernels); plus N = 1536 (two vectors per workgroup) on
-a band of 264 frequencies with the FP64 residuals of fhw_solve_incidences."""
+a time (single-vector kernels); plus N = 2560 (two vectors per workgroup: four
+would outgrow the LDS) on a band of 264 frequencies with the FP64 residuals of
+fhw_solve_incidences."""
 import numpy as np
 import pytest
 
@@ -86,10 +87,11 @@ def test_group_kernels_wide_batch(fhw, precision):
 
 
 def test_group_kernels_two_per_workgroup_fp64_residuals(fhw):
-    """N = 1536 puts two vectors in each solve workgroup; FP64 residuals
-    (compute_resid) go through the group residual kernel."""
+    """N = 2560 puts two vectors in each solve workgroup (four would need
+    more LDS than a workgroup may have); FP64 residuals (compute_resid) go
+    through the group residual kernel."""
     incs = incidences(n_plane=7, seed=3)[:9]
-    curve, W, F, N = Wk.kite(), 30.0, 264, 1536
+    curve, W, F, N = Wk.kite(), 30.0, 264, 2560
     omega, _ = O.frequency_grid(W, F)
     c = fhw.Context()
     try:
