@@ -201,7 +201,7 @@ inline void fhw_once_on_device(std::atomic<uint64_t>& mask, Fn&& fn) {
 
 // Incidences solved together: one more grid dimension over up to
 // FHW_INC_GROUP incidences, each buffer advanced by its stride (elements).
-#define FHW_INC_GROUP 8
+#define FHW_INC_GROUP 16
 struct fhw_grp {
     int32_t n = 1;
     int64_t sv = 0, sacc = 0, sflag = 0;      // solve: vector, accumulator; skip / done / sweeps flags

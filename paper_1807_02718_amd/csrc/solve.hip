@@ -532,7 +532,12 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual(const int* __restric
 // vector: a matrix is skipped when every vector of the group is done, and a
 // vector already done keeps its flags (its norms are recomputed from the same
 // x, in the same order, so they are unchanged).
+// GT: the group width the kernel is built for (2, 4, 8 or 16, the group's n
+// rounded up): x of the absent vectors q >= n is staged as zeros and every
+// vector accumulates unconditionally, so the inner loop is branch-free.
 #define RM_CH 128
+#define RM_LD 4          // matrix loads in flight per thread (8 and 16 measured slower)
+template <int GT>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_residual_multi(const int* __restrict__ Ns,
                                                                 const int64_t* __restrict__ a_off,
                                                                 const int64_t* __restrict__ v_off,
@@ -543,7 +548,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual_multi(const int* __r
                                                                 double* __restrict__ norms, double tol,
                                                                 int* __restrict__ done, int* __restrict__ sweeps,
                                                                 int sweep, int* __restrict__ pending, fhw_grp grp) {
-    constexpr int G = FHW_INC_GROUP;
+    constexpr int G = GT;
+    static_assert(GT <= FHW_INC_GROUP, "a group holds at most FHW_INC_GROUP vectors");
     __shared__ zd xs[G][RM_CH];
     __shared__ double wred[G][2][SOLVE_THREADS / 64];
     __shared__ int last;
@@ -569,49 +575,49 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_residual_multi(const int* __r
     for (int c0 = 0; c0 < N; c0 += RM_CH) {
         const int cnt = min(RM_CH, N - c0);
         __syncthreads();
-        for (int e = tid; e < n * cnt; e += SOLVE_THREADS) {
+        for (int e = tid; e < G * cnt; e += SOLVE_THREADS) {
             const int q = e / cnt, c = e - q * cnt;
-            xs[q][c] = x[q * grp.sx + vo + c0 + c];
+            xs[q][c] = q < n ? x[q * grp.sx + vo + c0 + c] : cmk(0.0, 0.0);
         }
         __syncthreads();
         if (i < N) {
             const zd* Ac = A + (int64_t)c0 * N + i;
             int c = 0;
-            for (; c + 4 <= cnt; c += 4) {
-                zd a4[4];
+            for (; c + RM_LD <= cnt; c += RM_LD) {
+                zd a4[RM_LD];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a4[u] = ld_stream(&Ac[(int64_t)(c + u) * N]);
+                for (int u = 0; u < RM_LD; ++u) a4[u] = ld_stream(&Ac[(int64_t)(c + u) * N]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < RM_LD; ++u) {
 #pragma unroll
-                    for (int q = 0; q < G; ++q)
-                        if (q < n) s[q] = cfma(s[q], a4[u], xs[q][c + u]);
+                    for (int q = 0; q < G; ++q) s[q] = cfma(s[q], a4[u], xs[q][c + u]);
                 }
             }
             for (; c < cnt; ++c) {
                 const zd a = ld_stream(&Ac[(int64_t)c * N]);
 #pragma unroll
-                for (int q = 0; q < G; ++q)
-                    if (q < n) s[q] = cfma(s[q], a, xs[q][c]);
+                for (int q = 0; q < G; ++q) s[q] = cfma(s[q], a, xs[q][c]);
             }
         }
     }
+    // (a single-exit loop, so that it unrolls and s stays in registers)
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-        if (q >= n) break;
-        double rr = 0.0, gg = 0.0;
-        if (i < N) {
-            const zd gi = g[q * grp.sg + vo + i];
-            const zd ri = csub(gi, s[q]);
-            r[q * grp.sr + vo + i] = ri;
-            rr = ri.re * ri.re + ri.im * ri.im;
-            gg = gi.re * gi.re + gi.im * gi.im;
-        }
-        rr = wave_sum(rr);
-        gg = wave_sum(gg);
-        if (lane == 0) {
-            wred[q][0][wid] = rr;
-            wred[q][1][wid] = gg;
+        if (q < n) {
+            double rr = 0.0, gg = 0.0;
+            if (i < N) {
+                const zd gi = g[q * grp.sg + vo + i];
+                const zd ri = csub(gi, s[q]);
+                r[q * grp.sr + vo + i] = ri;
+                rr = ri.re * ri.re + ri.im * ri.im;
+                gg = gi.re * gi.re + gi.im * gi.im;
+            }
+            rr = wave_sum(rr);
+            gg = wave_sum(gg);
+            if (lane == 0) {
+                wred[q][0][wid] = rr;
+                wred[q][1][wid] = gg;
+            }
         }
     }
     __syncthreads();
@@ -748,9 +754,15 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
     // one pass over each matrix for all of them
     if (grp.n > 1 && grp.n <= FHW_INC_GROUP && (int64_t)b.batch * ((maxN + 255) / 256) >= 512) {
         const int nblk = (maxN + SOLVE_THREADS - 1) / SOLVE_THREADS;
-        hipLaunchKernelGGL(k_residual_multi, dim3(b.batch, nblk), dim3(SOLVE_THREADS), 0, s, b.N, b.a_off, b.v_off,
-                           (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,
-                           sweeps, sweep, pending, grp);
+#define FHW_RES_M(GG)                                                                                           \
+    hipLaunchKernelGGL(k_residual_multi<GG>, dim3(b.batch, nblk), dim3(SOLVE_THREADS), 0, s, b.N, b.a_off, b.v_off, \
+                       (const zd*)A64, (const zd*)x, (const zd*)g, (zd*)r, part, count, nblk, norms, tol, done,    \
+                       sweeps, sweep, pending, grp)
+        if (grp.n <= 2) FHW_RES_M(2);
+        else if (grp.n <= 4) FHW_RES_M(4);
+        else if (grp.n <= 8) FHW_RES_M(8);
+        else FHW_RES_M(16);
+#undef FHW_RES_M
         return hipGetLastError();
     }
     // 256-row blocks when they alone give >= 1024 workgroups, else 64-row blocks
