@@ -907,7 +907,8 @@ static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, in
 #define FHW_PANEL_B(RR, TWE) FHW_PANEL_BX(RR, TWE)
 #define FHW_PANEL_BX(RR, PTB, WW, EE, DD) FHW_PANEL_D((RR * 256 + PTB - 1) / PTB, WW, EE, PTB, DD)
     // (W, waves per SIMD) per case from panel_table.h, among the spill-free
-    // register allocations; R = 8 and 16 (over 1024 rows) are fixed
+    // register allocations; tall panels (R = 8 and 16, over 1024 rows) take
+    // their workgroup size from the table too
     if (bd.batch <= 256) {
         const int R4 = (R + 3) / 4;   // rows per thread with 1024 threads
         if constexpr (sizeof(T) == 4) {
@@ -928,16 +929,16 @@ static hipError_t launch_panel(hipStream_t s, int R, const fhw_batch_dev& bd, in
             case 1: FHW_PANEL_B(1, FHW_PB_F32_R1); break;
             case 2: FHW_PANEL_B(2, FHW_PB_F32_R2); break;
             case 4: FHW_PANEL_B(4, FHW_PB_F32_R4); break;
-            case 8: FHW_PANEL(8, 4, 2, 256); break;
-            default: FHW_PANEL(16, 2, 2, 256); break;
+            case 8: FHW_PANEL_B(8, FHW_PB_F32_R8); break;
+            default: FHW_PANEL_B(16, FHW_PB_F32_R16); break;
         }
     } else {
         switch (R) {
             case 1: FHW_PANEL_B(1, FHW_PB_F64_R1); break;
             case 2: FHW_PANEL_B(2, FHW_PB_F64_R2); break;
             case 4: FHW_PANEL_B(4, FHW_PB_F64_R4); break;
-            case 8: FHW_PANEL(8, 4, 2, 256); break;
-            default: FHW_PANEL(16, 2, 1, 256); break;
+            case 8: FHW_PANEL_B(8, FHW_PB_F64_R8); break;
+            default: FHW_PANEL_B(16, FHW_PB_F64_R16); break;
         }
     }
 #undef FHW_PANEL_BX

@@ -2,10 +2,12 @@
 per SIMD) per precision, workgroup size and rows per thread.
 
     python -m paper_1807_02718_amd.tune build [jobs] [families]   # CPU: variant libraries
-    python -m paper_1807_02718_amd.tune measure [all|big]          # GPU: time them
+    python -m paper_1807_02718_amd.tune measure [all|big|tall]     # GPU: time them
     python -m paper_1807_02718_amd.tune write [results.json]       # CPU: csrc/panel_table.h
-(families: PB, 1024 or both, comma-separated; big times the kite at N = 1024
-with 1024 frequencies only, the shape of the PB cases)
+(families: PB, PBT, 1024, comma-separated; big times the kite at N = 1024
+with 1024 frequencies only, the shape of the PB cases; tall times star-curve
+batches with panels of 1025-2048 rows (N = 1536) and 2049-4096 rows
+(N = 4096), the PBT cases)
     python -m paper_1807_02718_amd.tune gemm-build | gemm-measure | gemm-write
         the same for the GEMM kernel (k_lu_gemm): K-chunk and workgroups per CU
         per precision, timed as the update + TRSM stages of the kite batch at
@@ -20,9 +22,11 @@ large-batch cases (batches above 256 matrices: workgroup size 256, 512 or 1024,
 W and waves per SIMD) N = 1024 with 1024 frequencies, whose shrinking panels
 pass through R = 4, 2 and 1 rows per 256 threads; for the 1024-thread cases
 the sum of N = 1024 with 64 frequencies (R = 1) and N = 4096 with 16
-frequencies (R = 4, 2, 1).  `write` keeps, per case, the fastest variant if it
-beats the current table by more than 1%.  The R = 8 and 16 shapes (256
-threads, N above 1024) are fixed: one shape per case fits without spilling.
+frequencies (R = 4, 2, 1); for the tall panels of large batches (R = 8 and
+16 rows per 256 threads: workgroup size, W and waves per SIMD) 512 systems at
+N = 1536 and 300 at N = 4096 on four star curves, factored by fhw_factor.
+`write` keeps, per case, the fastest variant if it beats the current table by
+more than 1%.
 """
 from __future__ import annotations
 
@@ -48,12 +52,15 @@ TABLE = os.path.join(CSRC, "panel_table.h")
 CANDIDATES = {
     1024: [(4, 4), (8, 4), (16, 4)],
     "PB": [(256, 8, e, d) for e in (4, 3, 2) for d in (0, 1, 2, 4, 8)],
+    "PBT": [(256, 4, 2, 0), (256, 2, 2, 0), (256, 2, 1, 0), (512, 8, 4, 0), (512, 8, 2, 0), (512, 4, 4, 0),
+            (512, 4, 2, 0), (1024, 8, 4, 0), (1024, 8, 2, 0), (1024, 4, 4, 0)],
 }
-CASES = [(p, pt, r) for p in ("F32", "F64") for pt in ("PB", 1024) for r in (1, 2, 4)]
+CASES = ([(p, pt, r) for p in ("F32", "F64") for pt in ("PB", 1024) for r in (1, 2, 4)] +
+         [(p, "PBT", r) for p in ("F32", "F64") for r in (8, 16)])
 
 
 def case_name(p, pt, r):
-    return f"FHW_PB_{p}_R{r}" if pt == "PB" else f"FHW_PT_{p}_{pt}_R{r}"
+    return f"FHW_PB_{p}_R{r}" if pt in ("PB", "PBT") else f"FHW_PT_{p}_{pt}_R{r}"
 
 
 def read_table(path=TABLE):
@@ -79,7 +86,7 @@ def variants(families=None):
             continue
         name = case_name(p, pt, r)
         for cand in CANDIDATES[pt]:
-            if tuple(cand) == base[name] or (pt == "PB" and cand[0] > 256 * r):
+            if tuple(cand) == base[name] or (pt in ("PB", "PBT") and cand[0] > 256 * r):
                 continue   # the current value, or more threads than panel rows
             t = dict(base)
             t[name] = tuple(cand)
@@ -90,7 +97,7 @@ def variants(families=None):
 def _spill_free(report, p, pt, r, *vals):
     """The panel instantiation of this case compiled without VGPR spills."""
     T = "f" if p == "F32" else "d"
-    if pt == "PB":
+    if pt in ("PB", "PBT"):
         threads, w, e, d = vals
         rows = (256 * r + threads - 1) // threads
         key = f"k_lu_panelI{T}Li{rows}ELi{w}ELi{e}ELi{threads}ELi{d}E"
@@ -150,6 +157,22 @@ from paper_1807_02718_amd import fhw
 import workloads as Wk
 out = {}
 shapes = ((1024, 1024), (64, 1024), (16, 4096)) if sys.argv[3] == "all" else ((1024, 1024),)
+if sys.argv[3] == "tall":
+    shapes = ()
+    curves = Wk.star_pool(4, 0)
+    for prec in ("fp32_refine", "fp64"):
+        for N, n_sys in ((1536, 512), (4096, 300)):
+            ctx = fhw.Context()
+            ctx.plan_systems(curves, [(q % 4, 100.0 + 0.5 * q, N) for q in range(n_sys)], precision=prec)
+            ctx.factor()
+            ts = []
+            for _ in range(3):
+                ctx.profile(True)
+                ctx.factor()
+                ts.append(ctx.profile_read()["lu_panel"][0])
+                ctx.profile(False)
+            ctx.close()
+            out[f"{prec}_tall{N}"] = float(np.median(ts))
 for prec in ("fp32_refine", "fp64"):
     for F, N in shapes:
         wl = Wk.kite_n1024(F=F)
@@ -170,8 +193,9 @@ print(json.dumps(out), flush=True)
 
 
 def measure(shapes="all"):
-    """Time every built variant; shapes = "all" (the three kite shapes) or
-    "big" (N = 1024 at 1024 frequencies only: the large-batch cases)."""
+    """Time every built variant; shapes = "all" (the three kite shapes),
+    "big" (N = 1024 at 1024 frequencies only: the large-batch cases) or
+    "tall" (the star-curve batches at N = 1536 and 4096: the tall panels)."""
     root = os.path.dirname(HERE)
     res = {}
     for name in sorted(os.listdir(TUNE)):
@@ -195,10 +219,15 @@ def write(results=None):
     tab = {k: tuple(v) for k, v in base["table"].items()}
     for p, pt, r in CASES:
         name = case_name(p, pt, r)
-        if not all(k in base["ms"] for k in (["fp32_refine_1024_1024"] if pt == "PB" else ["fp32_refine_64_1024"])):
-            continue   # not timed in this sweep
         prec = "fp32_refine" if p == "F32" else "fp64"
-        keys = [f"{prec}_1024_1024"] if pt == "PB" else [f"{prec}_64_1024", f"{prec}_16_4096"]
+        if pt == "PB":
+            keys = [f"{prec}_1024_1024"]
+        elif pt == "PBT":
+            keys = [f"{prec}_tall1536" if r == 8 else f"{prec}_tall4096"]
+        else:
+            keys = [f"{prec}_64_1024", f"{prec}_16_4096"]
+        if not all(k in base["ms"] for k in keys):
+            continue   # not timed in this sweep
 
         def cost(v):
             return sum(v["ms"][k] for k in keys)
