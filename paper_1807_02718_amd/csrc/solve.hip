@@ -232,6 +232,9 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
 #ifndef FHW_SM_LD
 #define FHW_SM_LD 8      // factor loads in flight per thread
 #endif
+#ifndef FHW_SM_MIN_BATCH
+#define FHW_SM_MIN_BATCH 256   // smaller batches solve vector by vector (more workgroups)
+#endif
 #define SM_TH FHW_SM_TH
 #define SM_LD FHW_SM_LD
 template <typename T, int NV>
@@ -688,7 +691,7 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
     const int nv_fit = solve_multi_lds<double, NV1>(maxN) <= (size_t)lds_max                ? NV1
                        : NV2 > 1 && solve_multi_lds<double, NV2>(maxN) <= (size_t)lds_max ? NV2
                                                                                             : 1;
-    if (grp.n > 1 && b.batch > 256 && nv_fit > 1) {
+    if (grp.n > 1 && b.batch > FHW_SM_MIN_BATCH && nv_fit > 1) {
         static std::atomic<uint64_t> mattr{0};
         fhw_once_on_device(mattr, [&] {
             const int dyn = lds_max;
@@ -750,9 +753,11 @@ hipError_t launch_residual_t(hipStream_t s, const fhw_batch_dev& b, int32_t maxN
         (void)hipFuncSetAttribute((const void*)k_residual<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         (void)hipFuncSetAttribute((const void*)k_residual<4>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     });
-    // a group of several vectors on a batch wide enough to fill the device:
-    // one pass over each matrix for all of them
-    if (grp.n > 1 && grp.n <= FHW_INC_GROUP && (int64_t)b.batch * ((maxN + 255) / 256) >= 512) {
+    // a group of several vectors: one pass over each matrix for all of them,
+    // at any batch size (the per-vector kernel reads each matrix once per
+    // vector; a serving round of 30 systems with 16 vectors each took 6 ms of
+    // per-vector residuals per launch)
+    if (grp.n > 1 && grp.n <= FHW_INC_GROUP) {
         const int nblk = (maxN + SOLVE_THREADS - 1) / SOLVE_THREADS;
 #define FHW_RES_M(GG)                                                                                           \
     hipLaunchKernelGGL(k_residual_multi<GG>, dim3(b.batch, nblk), dim3(SOLVE_THREADS), 0, s, b.N, b.a_off, b.v_off, \
