@@ -99,8 +99,8 @@ def run_mode(fhw, torch, wl, precision, steps, warmup):
 # FETCH_SIZE (x2: a 1 GiB copy reads as 0.5 GiB, its 128 B requests counted at
 # 64 B) plus WRITE_SIZE; valid only while lu.hip + panel_table.h + gemm_table.h
 # hash to this.
-UPDATE_TRAFFIC = {"lu_sha256": "0e1de2468dc1dfd0e0eab5921fca706adfe932597c21ba839eda20c595eef5af",
-                  "fp32_refine": 2.623e9, "fp64": 5.424e9}
+UPDATE_TRAFFIC = {"lu_sha256": "ef0e7096bd237979896e7f1d143c541f05c6a9cd49d89e88f899be30c25a5a1a",
+                  "fp32_refine": 2.623e9, "fp64": 5.418e9}
 
 
 def update_traffic(mode):
