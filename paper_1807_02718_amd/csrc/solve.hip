@@ -42,14 +42,20 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
                                                             const int* __restrict__ pivbase,
                                                             const cpx<T>* __restrict__ linvbase, zd* __restrict__ v,
                                                             zd* __restrict__ acc, const int* __restrict__ skip,
-                                                            fhw_grp grp) {
+                                                            int batch, fhw_grp grp) {
     static_assert((NB + (TH / 64) * NB) * sizeof(zd) <= FHW_SOLVE_STATIC_LDS, "static LDS of the solve");
     extern __shared__ zd xs[];
     __shared__ zd rhs[NB];
     __shared__ zd part[TH / 64][NB];
-    const int b = blockIdx.x;
+    // (matrix b, vector q) of this workgroup from the 1D grid of 8 ceil(batch
+    // / 8) grp.n workgroups: workgroups go to the XCDs round-robin by linear
+    // index, so matrix b's vectors all run on XCD b mod 8, where their reads
+    // of its factors meet in one L2 (one vector per matrix: b = index)
+    const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+    const int jb = k / grp.n, q = k - jb * grp.n;
+    const int b = xcd + 8 * jb;
+    if (b >= batch) return;
     {
-        const int q = blockIdx.y;   // incidence of the group
         v += q * grp.sv;
         if (acc) acc += q * grp.sacc;
         if (skip) skip += q * grp.sflag;
@@ -729,9 +735,9 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
         (void)hipFuncSetAttribute((const void*)k_lu_solve<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     });
 #define FHW_SOLVE(TT, WW)                                                                                     \
-    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3(b.batch, grp.n), dim3(WW ? 1024 : SOLVE_THREADS), lds, s, b.N,   \
-                       b.a_off, b.piv_off, b.linv_off, b.v_off, (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x,  \
-                       (zd*)acc, d_skip, grp)
+    hipLaunchKernelGGL((k_lu_solve<TT, WW>), dim3((unsigned)(8 * ((b.batch + 7) / 8) * grp.n)),                    \
+                       dim3(WW ? 1024 : SOLVE_THREADS), lds, s, b.N, b.a_off, b.piv_off, b.linv_off, b.v_off,           \
+                       (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, d_skip, b.batch, grp)
     const bool wide = b.batch <= 256;
     if (precision == FHW_FP64) {
         if (wide) FHW_SOLVE(double, true); else FHW_SOLVE(double, false);
