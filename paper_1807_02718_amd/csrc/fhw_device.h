@@ -127,9 +127,13 @@ __device__ __forceinline__ double fhw_rsqrt(double x) {
 }
 
 // Auxiliary P_nu, Q_nu (H_nu = sqrt(2/(pi z)) (P + iQ) e^{i(z - nu pi/2 - pi/4)})
-// for z > FHW_BES_Z_SERIES, given iz = 1/z.  want1: also nu = 1.
+// for z > FHW_BES_Z_SERIES, given iz = 1/z.  want1: also nu = 1.  cheb: the
+// Chebyshev coefficients fhw_bes_cheb, or a copy of them in LDS (each lane
+// gathers its own interval's coefficients; from LDS the gathers are short).
+#define FHW_BES_CHEB_LEN (FHW_BES_N_INTERVALS * 4 * FHW_BES_N_CHEB)
 template <bool want1>
-__device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, double& Q0, double& P1, double& Q1) {
+__device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, double& Q0, double& P1, double& Q1,
+                                           const double* cheb) {
     if (z >= FHW_BES_Z_ASYM) {
         double y = iz * iz;
         P0 = fhw_horner(fhw_bes_asym_p0, FHW_BES_N_ASYM, y);
@@ -153,7 +157,7 @@ __device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, doub
         scale = (iv == q) ? 1.0 / (xb - xa) : scale;
     }
     double u = (2.0 * iz - shift) * scale;
-    const double* c = fhw_bes_cheb + iv * 4 * FHW_BES_N_CHEB;
+    const double* c = cheb + iv * 4 * FHW_BES_N_CHEB;
     P0 = fhw_clenshaw(c, FHW_BES_N_CHEB, u);
     Q0 = fhw_clenshaw(c + FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
     if (want1) {
@@ -163,7 +167,8 @@ __device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, doub
 }
 
 // All four of J0, Y0, J1, Y1 at z > 0.
-__device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, double& J1, double& Y1) {
+__device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, double& J1, double& Y1,
+                                             const double* cheb = fhw_bes_cheb) {
     if (z <= FHW_BES_Z_SERIES) {
         double y = 0.25 * z * z;
         double j0 = fhw_horner(fhw_bes_series_j0, FHW_BES_N_SERIES, y);
@@ -179,7 +184,7 @@ __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, d
     }
     double P0, Q0, P1, Q1;
     const double rz = fhw_rsqrt(z);
-    fhw_bes_pq<true>(z, rz * rz, P0, Q0, P1, Q1);
+    fhw_bes_pq<true>(z, rz * rz, P0, Q0, P1, Q1, cheb);
     double s, c;
     sincos(z, &s, &c);
     double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;   // cos, sin of z - pi/4
@@ -192,7 +197,7 @@ __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, d
 }
 
 // J0, Y0 only (H0 = J0 + i Y0).
-__device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0) {
+__device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0, const double* cheb = fhw_bes_cheb) {
     if (z <= FHW_BES_Z_SERIES) {
         double y = 0.25 * z * z;
         double j0 = fhw_horner(fhw_bes_series_j0, FHW_BES_N_SERIES, y);
@@ -203,7 +208,7 @@ __device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0) {
     }
     double P0, Q0, P1, Q1;
     const double rz = fhw_rsqrt(z);
-    fhw_bes_pq<false>(z, rz * rz, P0, Q0, P1, Q1);
+    fhw_bes_pq<false>(z, rz * rz, P0, Q0, P1, Q1, cheb);
     double s, c;
     sincos(z, &s, &c);
     double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;
