@@ -346,21 +346,24 @@ __global__ __launch_bounds__(SYN_THREADS, 4) void k_synth(const double* __restri
         if (sl < 0) continue;
         if (bnd && bnd[(int64_t)sl * N_r + r] <= cut) continue;   // inactive here
         const double sk = 1.5 * H * ((double)k - 1.0);
+        // a time that does not use this window's sum (inactive, or at an
+        // integer x) takes x = 1/2: its terms stay finite and its weight is 0,
+        // so the sum over m needs no per-term guard
         double xq[ST], scale[ST], part[ST];
-        bool use[ST];
         bool anyk = false;
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
             const bool act = (it0 + q < N_t) && fabs(tq[q] - sk - tau0) <= P;
-            xq[q] = W * (tq[q] - sk - tau0) / FHW_PI;
-            const bool integral = act && xq[q] == floor(xq[q]);
-            use[q] = act && !integral;
-            scale[q] = use[q] ? sinpi(xq[q]) / FHW_PI : 0.0;
+            const double x = W * (tq[q] - sk - tau0) / FHW_PI;
+            const bool integral = act && x == floor(x);
+            const bool use = act && !integral;
+            scale[q] = use ? sinpi(x) / FHW_PI : 0.0;
+            xq[q] = use ? x : 0.5;
             part[q] = 0.0;
             anyk |= act;
             if (integral && lane == 0) {
                 // sinc(x - m) = 1 at m = x, 0 at every other m
-                const int idx = (int)xq[q] + F;
+                const int idx = (int)x + F;
                 if (idx >= 0 && idx < M) tot[q] += cre[((int64_t)sl * N_r + r) * M + idx];
             }
         }
@@ -370,8 +373,7 @@ __global__ __launch_bounds__(SYN_THREADS, 4) void k_synth(const double* __restri
             const int m = idx - F;
             const double a = (m & 1) ? -ck[idx] : ck[idx];
 #pragma unroll
-            for (int q = 0; q < ST; ++q)
-                if (use[q]) part[q] = fma(a, synth_recip(xq[q] - (double)m), part[q]);
+            for (int q = 0; q < ST; ++q) part[q] = fma(a, synth_recip(xq[q] - (double)m), part[q]);
         }
 #pragma unroll
         for (int q = 0; q < ST; ++q) tot[q] = fma(scale[q], part[q], tot[q]);
