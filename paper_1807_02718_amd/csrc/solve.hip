@@ -253,13 +253,20 @@ __global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict_
                                                         const int* __restrict__ pivbase,
                                                         const cpx<T>* __restrict__ linvbase, zd* __restrict__ v,
                                                         zd* __restrict__ acc, const int* __restrict__ skip,
-                                                        int ldx, fhw_grp grp) {
+                                                        int ldx, int batch, fhw_grp grp) {
     constexpr int NW = SM_TH / 64;
     extern __shared__ zd smem[];
     zd* xs = smem;                                  // [NV][ldx]
     zd* rhs = smem + NV * ldx;                      // [NV][NB]
-    const int b = blockIdx.x;
-    const int q0 = blockIdx.y * NV;
+    // (matrix b, run of NV vectors) from the 1D grid of 8 ceil(batch / 8)
+    // runs workgroups, numbered as in k_lu_solve: a matrix's runs go out one
+    // after another on XCD b mod 8, so they stream its factors together
+    const int runs = (grp.n + NV - 1) / NV;
+    const int xcd = blockIdx.x & 7, kq = blockIdx.x >> 3;
+    const int jb = kq / runs;
+    const int b = xcd + 8 * jb;
+    if (b >= batch) return;
+    const int q0 = (kq - jb * runs) * NV;
     const int nv = min(NV, grp.n - q0);
     bool live[NV];
     bool any = false;
@@ -712,9 +719,9 @@ hipError_t launch_lu_solve_acc(hipStream_t s, const fhw_batch_dev& b, int32_t ma
         });
         const int ldx = maxN;
 #define FHW_SOLVE_M(TT, NVV)                                                                                   \
-    hipLaunchKernelGGL((k_lu_solve_multi<TT, NVV>), dim3(b.batch, (grp.n + NVV - 1) / NVV), dim3(SM_TH),       \
-                       (solve_multi_lds<TT, NVV>(ldx)), s, b.N, b.a_off, b.piv_off, b.linv_off, b.v_off,        \
-                       (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, d_skip, ldx, grp)
+    hipLaunchKernelGGL((k_lu_solve_multi<TT, NVV>), dim3((unsigned)(8 * ((b.batch + 7) / 8) * ((grp.n + NVV - 1) / NVV))), \
+                       dim3(SM_TH), (solve_multi_lds<TT, NVV>(ldx)), s, b.N, b.a_off, b.piv_off, b.linv_off, b.v_off,  \
+                       (const cpx<TT>*)LU, piv, (const cpx<TT>*)linv, (zd*)x, (zd*)acc, d_skip, ldx, b.batch, grp)
         const bool full = nv_fit == NV1;
         if (precision == FHW_FP64) {
             if (full) FHW_SOLVE_M(double, NV1); else FHW_SOLVE_M(double, NV2);
