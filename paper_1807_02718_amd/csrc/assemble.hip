@@ -97,9 +97,9 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
         st[2][e] = it.logtab[lm];
         st[3][e] = it.R[lm];
     }
-    // the Bessel Chebyshev coefficients too (assembly 7.3 -> 6.5 ms per FP32-mode step)
-    __shared__ double s_cheb[FHW_BES_CHEB_LEN];
-    for (int e = threadIdx.x; e < FHW_BES_CHEB_LEN; e += ASM_THREADS) s_cheb[e] = fhw_bes_cheb[e];
+    // the Bessel interval polynomials too (assembly 7.3 -> 6.5 ms per FP32-mode step)
+    __shared__ double s_poly[FHW_BES_POLY_LEN];
+    for (int e = threadIdx.x; e < FHW_BES_POLY_LEN; e += ASM_THREADS) s_poly[e] = fhw_bes_poly[e];
     double xi1 = 0, xi2 = 0, ni1 = 0, ni2 = 0, spi = 0;
     if (iok) { xi1 = x1[i]; xi2 = x2[i]; ni1 = nu1[i]; ni2 = nu2[i]; spi = sp[i]; }
     __syncthreads();
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
             const double ir = fhw_rsqrt(r2);   // 1 / r
             const double r = r2 * ir;
             double J0, Y0, J1, Y1;
-            fhw_bessel01(kappa * r, J0, Y0, J1, Y1, s_cheb);
+            fhw_bessel01(kappa * r, J0, Y0, J1, Y1, s_poly);
             const double lam = st[0][dd];
             const double M1 = -J0 * inv4pi;
             const double M2r = -0.25 * Y0 - M1 * lam;

@@ -105,15 +105,12 @@ __device__ __forceinline__ double fhw_horner(const double* c, int n, double y) {
     return acc;
 }
 
-__device__ __forceinline__ double fhw_clenshaw(const double* c, int n, double u) {
-    double b1 = 0.0, b2 = 0.0;
-    double u2 = 2.0 * u;
-    for (int k = n - 1; k >= 1; --k) {
-        double t = fma(u2, b1, c[k] - b2);
-        b2 = b1;
-        b1 = t;
-    }
-    return fma(u, b1, c[0] - b2);
+// Polynomial whose coefficients each lane reads itself (per-lane interval)
+__device__ __forceinline__ double fhw_horner_v(const double* c, int n, double u) {
+    double acc = c[n - 1];
+#pragma unroll
+    for (int k = n - 2; k >= 0; --k) acc = fma(acc, u, c[k]);
+    return acc;
 }
 
 // 1/sqrt(x), x > 0 finite: the hardware estimate refined by two Newton steps
@@ -126,14 +123,59 @@ __device__ __forceinline__ double fhw_rsqrt(double x) {
     return y;
 }
 
+// sin and cos of w = z - pi/4 for z >= 0 (the Hankel phase): Cody and Waite's
+// additive reduction w = k pi/2 + r, written as r = z - m pi/4 with m = 2k + 1
+// odd, pi/4 split in two doubles (the leading one pi/4 rounded, the second the
+// rounded remainder; with fused products the reduction error stays near one
+// ulp of r up to z ~ 1e15), then the Taylor series of sin r and cos r on
+// |r| <= pi/4 through r^17 and r^16 (first omitted terms below 1e-17) and the
+// quadrant k mod 4.  About half the instructions of the general sincos.
+#define FHW_PIO4_HI 0x1.921fb54442d18p-1
+#define FHW_PIO4_LO 0x1.1a62633145c07p-55
+#define FHW_2_OVER_PI 0x1.45f306dc9c883p-1
+__device__ __forceinline__ void fhw_sincos_shift(double z, double& sw, double& cw) {
+    const double k = __builtin_rint(fma(z, FHW_2_OVER_PI, -0.5));
+    const double m = fma(2.0, k, 1.0);
+    double r = fma(-m, FHW_PIO4_HI, z);
+    r = fma(-m, FHW_PIO4_LO, r);
+    const double x = r * r;
+    // sin r = r + r x (-1/3! + x (1/5! - ...)),  cos r = 1 - x/2 + x^2 (1/4! - x (1/6! - ...))
+    double ps = 0x1.952c77030ad4ap-49;                 //  1/17!
+    ps = fhw_fma_sc(ps, x, -0x1.ae7f3e733b81fp-41);   // -1/15!
+    ps = fhw_fma_sc(ps, x, 0x1.6124613a86d09p-33);    //  1/13!
+    ps = fhw_fma_sc(ps, x, -0x1.ae64567f544e4p-26);   // -1/11!
+    ps = fhw_fma_sc(ps, x, 0x1.71de3a556c734p-19);    //  1/9!
+    ps = fhw_fma_sc(ps, x, -0x1.a01a01a01a01ap-13);   // -1/7!
+    ps = fhw_fma_sc(ps, x, 0x1.1111111111111p-7);     //  1/5!
+    ps = fhw_fma_sc(ps, x, -0x1.5555555555555p-3);    // -1/3!
+    double pc = 0x1.ae7f3e733b81fp-45;                 //  1/16!
+    pc = fhw_fma_sc(pc, x, -0x1.93974a8c07c9dp-37);   // -1/14!
+    pc = fhw_fma_sc(pc, x, 0x1.1eed8eff8d898p-29);    //  1/12!
+    pc = fhw_fma_sc(pc, x, -0x1.27e4fb7789f5cp-22);   // -1/10!
+    pc = fhw_fma_sc(pc, x, 0x1.a01a01a01a01ap-16);    //  1/8!
+    pc = fhw_fma_sc(pc, x, -0x1.6c16c16c16c17p-10);   // -1/6!
+    pc = fhw_fma_sc(pc, x, 0x1.5555555555555p-5);     //  1/4!
+    const double sr = fma(r * x, ps, r);
+    const double cr = fma(x * x, pc, fma(-0.5, x, 1.0));
+    // (sin, cos)(k pi/2 + r): k odd swaps them (cos, -sin); k = 2, 3 mod 4 negates both
+    const int q = (int)k;
+    const bool odd = (q & 1) != 0;
+    double a = odd ? cr : sr;
+    double b = odd ? -sr : cr;
+    if (q & 2) { a = -a; b = -b; }
+    sw = a;
+    cw = b;
+}
+
 // Auxiliary P_nu, Q_nu (H_nu = sqrt(2/(pi z)) (P + iQ) e^{i(z - nu pi/2 - pi/4)})
-// for z > FHW_BES_Z_SERIES, given iz = 1/z.  want1: also nu = 1.  cheb: the
-// Chebyshev coefficients fhw_bes_cheb, or a copy of them in LDS (each lane
-// gathers its own interval's coefficients; from LDS the gathers are short).
-#define FHW_BES_CHEB_LEN (FHW_BES_N_INTERVALS * 4 * FHW_BES_N_CHEB)
+// for z > FHW_BES_Z_SERIES, given iz = 1/z.  want1: also nu = 1.  poly: the
+// interval polynomials fhw_bes_poly (Chebyshev fits in 1/z, in power form in
+// the interval's u), or a copy of them in LDS (each lane gathers its own
+// interval's coefficients; from LDS the gathers are short).
+#define FHW_BES_POLY_LEN (FHW_BES_N_INTERVALS * 4 * FHW_BES_N_POLY)
 template <bool want1>
 __device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, double& Q0, double& P1, double& Q1,
-                                           const double* cheb) {
+                                           const double* poly) {
     if (z >= FHW_BES_Z_ASYM) {
         double y = iz * iz;
         P0 = fhw_horner(fhw_bes_asym_p0, FHW_BES_N_ASYM, y);
@@ -157,18 +199,18 @@ __device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, doub
         scale = (iv == q) ? 1.0 / (xb - xa) : scale;
     }
     double u = (2.0 * iz - shift) * scale;
-    const double* c = cheb + iv * 4 * FHW_BES_N_CHEB;
-    P0 = fhw_clenshaw(c, FHW_BES_N_CHEB, u);
-    Q0 = fhw_clenshaw(c + FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
+    const double* c = poly + iv * 4 * FHW_BES_N_POLY;
+    P0 = fhw_horner_v(c, FHW_BES_N_POLY, u);
+    Q0 = fhw_horner_v(c + FHW_BES_N_POLY, FHW_BES_N_POLY, u);
     if (want1) {
-        P1 = fhw_clenshaw(c + 2 * FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
-        Q1 = fhw_clenshaw(c + 3 * FHW_BES_N_CHEB, FHW_BES_N_CHEB, u);
+        P1 = fhw_horner_v(c + 2 * FHW_BES_N_POLY, FHW_BES_N_POLY, u);
+        Q1 = fhw_horner_v(c + 3 * FHW_BES_N_POLY, FHW_BES_N_POLY, u);
     }
 }
 
 // All four of J0, Y0, J1, Y1 at z > 0.
 __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, double& J1, double& Y1,
-                                             const double* cheb = fhw_bes_cheb) {
+                                             const double* poly = fhw_bes_poly) {
     if (z <= FHW_BES_Z_SERIES) {
         double y = 0.25 * z * z;
         double j0 = fhw_horner(fhw_bes_series_j0, FHW_BES_N_SERIES, y);
@@ -184,10 +226,9 @@ __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, d
     }
     double P0, Q0, P1, Q1;
     const double rz = fhw_rsqrt(z);
-    fhw_bes_pq<true>(z, rz * rz, P0, Q0, P1, Q1, cheb);
-    double s, c;
-    sincos(z, &s, &c);
-    double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;   // cos, sin of z - pi/4
+    fhw_bes_pq<true>(z, rz * rz, P0, Q0, P1, Q1, poly);
+    double s0, c0;
+    fhw_sincos_shift(z, s0, c0);                                         // sin, cos of z - pi/4
     double c1 = s0, s1 = -c0;                                            // cos, sin of z - 3pi/4
     double amp = FHW_SQRT_2_OVER_PI * rz;                                // sqrt(2 / (pi z))
     J0 = amp * (P0 * c0 - Q0 * s0);
@@ -197,7 +238,7 @@ __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, d
 }
 
 // J0, Y0 only (H0 = J0 + i Y0).
-__device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0, const double* cheb = fhw_bes_cheb) {
+__device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0, const double* poly = fhw_bes_poly) {
     if (z <= FHW_BES_Z_SERIES) {
         double y = 0.25 * z * z;
         double j0 = fhw_horner(fhw_bes_series_j0, FHW_BES_N_SERIES, y);
@@ -208,10 +249,9 @@ __device__ __forceinline__ void fhw_bessel0(double z, double& J0, double& Y0, co
     }
     double P0, Q0, P1, Q1;
     const double rz = fhw_rsqrt(z);
-    fhw_bes_pq<false>(z, rz * rz, P0, Q0, P1, Q1, cheb);
-    double s, c;
-    sincos(z, &s, &c);
-    double c0 = (c + s) * FHW_INV_SQRT2, s0 = (s - c) * FHW_INV_SQRT2;
+    fhw_bes_pq<false>(z, rz * rz, P0, Q0, P1, Q1, poly);
+    double s0, c0;
+    fhw_sincos_shift(z, s0, c0);
     double amp = FHW_SQRT_2_OVER_PI * rz;
     J0 = amp * (P0 * c0 - Q0 * s0);
     Y0 = amp * (P0 * s0 + Q0 * c0);

@@ -12,8 +12,8 @@
 __global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restrict__ items, int F,
                                                const zd* __restrict__ psi, const double* __restrict__ obs, int N_r,
                                                double zero_value, zd* __restrict__ V) {
-    __shared__ double s_cheb[FHW_BES_CHEB_LEN];   // Bessel Chebyshev coefficients, gathered per lane
-    for (int e = threadIdx.x; e < FHW_BES_CHEB_LEN; e += blockDim.x) s_cheb[e] = fhw_bes_cheb[e];
+    __shared__ double s_poly[FHW_BES_POLY_LEN];   // Bessel interval polynomials, gathered per lane
+    for (int e = threadIdx.x; e < FHW_BES_POLY_LEN; e += blockDim.x) s_poly[e] = fhw_bes_poly[e];
     __syncthreads();
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restri
         const double d1 = o1 - x1[i], d2 = o2 - x2[i];
         const double z = it.kappa * sqrt(d1 * d1 + d2 * d2);
         double J0, Y0;
-        fhw_bessel0(z, J0, Y0, s_cheb);
+        fhw_bessel0(z, J0, Y0, s_poly);
         // (i/4) H0 = (-Y0/4, J0/4), weighted by |x'_i|
         const zd gk = cmk(-0.25 * Y0 * sp[i], 0.25 * J0 * sp[i]);
         acc = cfma(acc, gk, ps[i]);
@@ -54,11 +54,11 @@ __global__ __launch_bounds__(256, 4) void k_field(const fhw_field_item* __restri
 //   |x'| [ (i kappa/4) H1(kappa rho) nu . (r - x)/rho + (eta/4) H0(kappa rho) ]
 __device__ __forceinline__ zd combined_kernel_at(double x1, double x2, double sp, double n1, double n2, double o1,
                                                 double o2, double kappa, double eta,
-                                                const double* cheb = fhw_bes_cheb) {
+                                                const double* poly = fhw_bes_poly) {
     const double d1 = o1 - x1, d2 = o2 - x2;
     const double rho = sqrt(d1 * d1 + d2 * d2);
     double J0, Y0, J1, Y1;
-    fhw_bessel01(kappa * rho, J0, Y0, J1, Y1, cheb);
+    fhw_bessel01(kappa * rho, J0, Y0, J1, Y1, poly);
     const double cn = (n1 * d1 + n2 * d2) / rho;
     const double a = 0.25 * kappa * cn, e = 0.25 * eta;
     return cmk(sp * (e * J0 - a * Y1), sp * (e * Y0 + a * J1));
@@ -66,9 +66,9 @@ __device__ __forceinline__ zd combined_kernel_at(double x1, double x2, double sp
 
 // The same for node i of a geometry array (x1, x2, ..., |x'| at 6N, nu at 7N, 8N).
 __device__ __forceinline__ zd combined_kernel(const double* geom, int N, int i, double o1, double o2, double kappa,
-                                             double eta, const double* cheb = fhw_bes_cheb) {
+                                             double eta, const double* poly = fhw_bes_poly) {
     return combined_kernel_at(geom[i], geom[N + i], geom[6 * N + i], geom[7 * N + i], geom[8 * N + i], o1, o2,
-                              kappa, eta, cheb);
+                              kappa, eta, poly);
 }
 
 // The field of n_blk density blocks at once (the windows of general boundary
@@ -103,9 +103,9 @@ __global__ __launch_bounds__(256, FHW_FB_WPE) void k_field_blocks(const fhw_fiel
     __shared__ zd G[FB_P][FB_CH + 1];
     __shared__ zd Ps[FB_BLK][FB_CH + 1];
     __shared__ zd part[256];
-    __shared__ double s_cheb[FHW_BES_CHEB_LEN];
+    __shared__ double s_poly[FHW_BES_POLY_LEN];
     const int tid = threadIdx.x;
-    for (int e = tid; e < FHW_BES_CHEB_LEN; e += 256) s_cheb[e] = fhw_bes_cheb[e];
+    for (int e = tid; e < FHW_BES_POLY_LEN; e += 256) s_poly[e] = fhw_bes_poly[e];
     __syncthreads();
     const int lane = tid & 63, wid = tid >> 6;
     const int n_rg = (N_r + FB_P - 1) / FB_P;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256, FHW_FB_WPE) void k_field_blocks(const fhw_fiel
             for (int p = wid; p < FB_P; p += 4) {
                 const int r = r0 + p;
                 G[p][lane] = r < N_r ? combined_kernel_at(x1, x2, sp, n1, n2, obs[2 * r], obs[2 * r + 1], it.kappa,
-                                                          it.eta, s_cheb)
+                                                          it.eta, s_poly)
                                      : cmk(0.0, 0.0);
             }
         } else {

@@ -41,7 +41,7 @@ def relmax(a, b):
 def test_hankel01_values(ctx):
     say("hankel01")
     brk = np.array([3.0, 4.5, 6.75, 10.0, 15.0, 25.0])
-    z = np.concatenate([np.geomspace(1e-5, 3e3, 3000), brk, np.nextafter(brk, 0), np.nextafter(brk, 10)])
+    z = np.concatenate([np.geomspace(1e-5, 1e5, 4000), brk, np.nextafter(brk, 0), np.nextafter(brk, 10)])
     h = ctx.hankel01(z).cpu().numpy()
     eps = np.finfo(float).eps
     cond = 8 * eps * np.sqrt(np.maximum(z, 1.0))
