@@ -40,8 +40,9 @@ __device__ __forceinline__ zd cfie_entry(double n_t, double cL, double cY, doubl
 // Each thread takes pairs (i, j) = (i0 + tid%32, j0 + tid/32 + 8k), k < 4.
 // The Bessel values of |x_i - x_j| serve A(i, j) (written directly, lanes
 // along i) and A(j, i) (staged in LDS, then written with lanes along j).
-// Diagonal tiles take i >= j only and mirror the strict part.  Tiles with
-// J = 0 also write the RHS.
+// Diagonal tiles take i > j in the pair loop, mirror the strict part and
+// write their diagonal entries after it (so that no other tile evaluates the
+// diagonal limits).  Tiles with J = 0 also write the RHS.
 template <bool COMB, bool NT>
 __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_item* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int n_items,
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
     const int n = N >> 1;
     // lower-triangular tile index t -> (I, J), I >= J
     const int t = (int)(blockIdx.x - prefix[q]);
-    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    int I = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     while (I * (I + 1) / 2 > t) --I;
     const int J = t - I * (I + 1) / 2;
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
     const double* nu2 = it.geom + 8 * N;
     const double kappa = it.kappa, eta = it.eta;
     const double inv4pi = 1.0 / (4.0 * FHW_PI);
-    const double wq = FHW_PI / (double)n;
+    const double wq = FHW_PI * fhw_rcp((double)n);
     zd* Aq = A + it.a_off;
     zf* A32q = A32 ? A32 + it.a_off : nullptr;
 
@@ -89,8 +90,9 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
         sj[3][threadIdx.x] = ok ? nu1[j] : 0.0;
         sj[4][threadIdx.x] = ok ? nu2[j] : 0.0;
     } else if (threadIdx.x < 3 * AT - 1) {
-        const int e = threadIdx.x - AT;   // l = i0 - j0 - (AT - 1) + e (mod N)
-        const int l = ((i0 - j0 - (AT - 1) + e) % N + N) % N;
+        const int e = threadIdx.x - AT;   // l = i0 - j0 - (AT - 1) + e (mod N), in [-(AT - 1), N) as i0 >= j0
+        const int l0 = i0 - j0 - (AT - 1) + e;
+        const int l = l0 < 0 ? l0 + N : l0;
         const int lm = (l == 0) ? 0 : N - l;
         st[0][e] = it.logtab[l];
         st[1][e] = it.R[l];
@@ -107,41 +109,41 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
     for (int k = 0; k < AT / 8; ++k) {
         const int jl = jg + 8 * k;
         const int j = j0 + jl;
-        if (!iok || j >= N || (I == J && i < j)) continue;
+        if (!iok || j >= N || (I == J && i <= j)) continue;
         const double spj = sj[2][jl];
         const int dd = il - jl + AT - 1;   // index of l = (i - j) mod N in st
-        zd e_ij, e_ji;
-        if (i != j) {
-            const double d1 = sj[0][jl] - xi1, d2 = sj[1][jl] - xi2;   // d = x_j - x_i
-            const double r2 = d1 * d1 + d2 * d2;
-            const double ir = fhw_rsqrt(r2);   // 1 / r
-            const double r = r2 * ir;
-            double J0, Y0, J1, Y1;
-            fhw_bessel01(kappa * r, J0, Y0, J1, Y1, s_poly);
-            const double lam = st[0][dd];
-            const double M1 = -J0 * inv4pi;
-            const double M2r = -0.25 * Y0 - M1 * lam;
-            const double M2i = 0.25 * J0;
-            const double cL = -kappa * inv4pi * J1;
-            const double cY = -0.25 * kappa * Y1;
-            const double cJ = 0.25 * kappa * J1;
-            const double n_i = (ni1 * d1 + ni2 * d2) * ir;          // target i: nu_i . (x_j - x_i) / r
-            const double n_j = -(sj[3][jl] * d1 + sj[4][jl] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
-            e_ij = cfie_entry(COMB ? n_j : n_i, cL, cY, cJ, M1, M2r, M2i, lam, st[1][dd], wq, eta, spj);
-            e_ji = cfie_entry(COMB ? n_i : n_j, cL, cY, cJ, M1, M2r, M2i, st[2][dd], st[3][dd], wq, eta, spi);
-        } else {
-            const double M2r = -(0.57721566490153286061 + log(0.5 * kappa * spi)) / (2.0 * FHW_PI);
-            const double M2i = 0.25;
-            const double L2r = (ni1 * ddx1[i] + ni2 * ddx2[i]) * inv4pi / (spi * spi);
-            const double K1r = 0.0, K1i = eta * inv4pi;
-            const double K2r = L2r + eta * M2i, K2i = -eta * M2r;
-            const double Rw = it.R[0];
-            e_ij = cmk(spi * (Rw * K1r + wq * K2r) + 0.5, spi * (Rw * K1i + wq * K2i));
-            e_ji = e_ij;
-        }
+        const double d1 = sj[0][jl] - xi1, d2 = sj[1][jl] - xi2;   // d = x_j - x_i
+        const double r2 = d1 * d1 + d2 * d2;
+        const double ir = fhw_rsqrt(r2);   // 1 / r
+        const double r = r2 * ir;
+        double J0, Y0, J1, Y1;
+        fhw_bessel01(kappa * r, J0, Y0, J1, Y1, s_poly);
+        const double lam = st[0][dd];
+        const double M1 = -J0 * inv4pi;
+        const double M2r = -0.25 * Y0 - M1 * lam;
+        const double M2i = 0.25 * J0;
+        const double cL = -kappa * inv4pi * J1;
+        const double cY = -0.25 * kappa * Y1;
+        const double cJ = 0.25 * kappa * J1;
+        const double n_i = (ni1 * d1 + ni2 * d2) * ir;          // target i: nu_i . (x_j - x_i) / r
+        const double n_j = -(sj[3][jl] * d1 + sj[4][jl] * d2) * ir;   // target j: nu_j . (x_i - x_j) / r
+        const zd e_ij = cfie_entry(COMB ? n_j : n_i, cL, cY, cJ, M1, M2r, M2i, lam, st[1][dd], wq, eta, spj);
+        const zd e_ji = cfie_entry(COMB ? n_i : n_j, cL, cY, cJ, M1, M2r, M2i, st[2][dd], st[3][dd], wq, eta, spi);
         st_maybe_stream<NT>(&Aq[(int64_t)j * N + i], e_ij);
         if (A32q) st_maybe_stream<NT>(&A32q[(int64_t)j * N + i], cmk((float)e_ij.re, (float)e_ij.im));
         mirror[jl][il] = e_ji;
+    }
+    if (I == J && iok && (il & 7) == jg) {
+        // diagonal entry (i, i): the kernels' limits as x_j -> x_i (one thread per row)
+        const double M2r = -(0.57721566490153286061 + log(0.5 * kappa * spi)) * (0.5 / FHW_PI);
+        const double M2i = 0.25;
+        const double L2r = (ni1 * ddx1[i] + ni2 * ddx2[i]) * inv4pi * fhw_rcp(spi * spi);
+        const double K1r = 0.0, K1i = eta * inv4pi;
+        const double K2r = L2r + eta * M2i, K2i = -eta * M2r;
+        const double Rw = it.R[0];
+        const zd e = cmk(spi * (Rw * K1r + wq * K2r) + 0.5, spi * (Rw * K1i + wq * K2i));
+        st_maybe_stream<NT>(&Aq[(int64_t)i * N + i], e);
+        if (A32q) st_maybe_stream<NT>(&A32q[(int64_t)i * N + i], cmk((float)e.re, (float)e.im));
     }
     if (J == 0 && jg == 0 && iok) {
         // g_i = i (kappa p.nu_i - eta) exp(i kappa p.x_i)
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(ASM_THREADS, 4) void k_assemble(const fhw_assemble_
     for (int k = 0; k < AT / 8; ++k) {
         const int il2 = ig + 8 * k;
         const int icol = i0 + il2;
-        // diagonal tiles computed pairs i >= j only: mirror the strict part
+        // diagonal tiles computed pairs i > j only: mirror the strict part
         if (jrow < N && icol < N && (I != J || icol > jrow)) {
             const zd v = mirror[jl2][il2];
             st_maybe_stream<NT>(&Aq[(int64_t)icol * N + jrow], v);

@@ -167,12 +167,21 @@ __device__ __forceinline__ void fhw_sincos_shift(double z, double& sw, double& c
     cw = b;
 }
 
+// 1/x, x finite and nonzero: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y) (each squares the relative error).
+__device__ __forceinline__ double fhw_rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
 // Auxiliary P_nu, Q_nu (H_nu = sqrt(2/(pi z)) (P + iQ) e^{i(z - nu pi/2 - pi/4)})
 // for z > FHW_BES_Z_SERIES, given iz = 1/z.  want1: also nu = 1.  poly: the
 // interval polynomials fhw_bes_poly (Chebyshev fits in 1/z, in power form in
 // the interval's u), or a copy of them in LDS (each lane gathers its own
 // interval's coefficients; from LDS the gathers are short).
-#define FHW_BES_POLY_LEN (FHW_BES_N_INTERVALS * 4 * FHW_BES_N_POLY)
+#define FHW_BES_POLY_LEN (FHW_BES_N_INTERVALS * FHW_BES_INTERVAL_LEN)
 template <bool want1>
 __device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, double& Q0, double& P1, double& Q1,
                                            const double* poly) {
@@ -189,17 +198,11 @@ __device__ __forceinline__ void fhw_bes_pq(double z, double iz, double& P0, doub
     int iv = 0;
 #pragma unroll
     for (int q = 1; q < FHW_BES_N_INTERVALS; ++q) iv += (z >= fhw_bes_breaks[q]) ? 1 : 0;
-    // u = (2/z - (xa + xb)) / (xb - xa) on [xa, xb] = [1/break_{iv+1}, 1/break_iv]:
-    // the interval constants are folded at compile time, one select each
-    double shift = 0.0, scale = 0.0;
-#pragma unroll
-    for (int q = 0; q < FHW_BES_N_INTERVALS; ++q) {
-        const double xa = 1.0 / fhw_bes_breaks[q + 1], xb = 1.0 / fhw_bes_breaks[q];
-        shift = (iv == q) ? xa + xb : shift;
-        scale = (iv == q) ? 1.0 / (xb - xa) : scale;
-    }
-    double u = (2.0 * iz - shift) * scale;
-    const double* c = poly + iv * 4 * FHW_BES_N_POLY;
+    // u = (2/z - (xa + xb)) / (xb - xa) on [xa, xb] = [1/break_{iv+1}, 1/break_iv],
+    // with the interval's shift and scale read ahead of its coefficients
+    const double* c = poly + iv * FHW_BES_INTERVAL_LEN;
+    const double u = (2.0 * iz - c[0]) * c[1];
+    c += 2;
     P0 = fhw_horner_v(c, FHW_BES_N_POLY, u);
     Q0 = fhw_horner_v(c + FHW_BES_N_POLY, FHW_BES_N_POLY, u);
     if (want1) {
@@ -221,7 +224,7 @@ __device__ __forceinline__ void fhw_bessel01(double z, double& J0, double& Y0, d
         J0 = j0;
         Y0 = (2.0 / FHW_PI) * ((lg + fhw_bes_euler_gamma) * j0 + s0);
         J1 = j1;
-        Y1 = (2.0 / FHW_PI) * lg * j1 - 2.0 / (FHW_PI * z) - (z / (2.0 * FHW_PI)) * s1;
+        Y1 = (2.0 / FHW_PI) * (lg * j1 - fhw_rcp(z)) - (z * (0.5 / FHW_PI)) * s1;
         return;
     }
     double P0, Q0, P1, Q1;
