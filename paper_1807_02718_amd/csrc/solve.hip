@@ -19,6 +19,14 @@ __device__ __forceinline__ void replay_pivots(zd* xs, const int* piv, int k0, in
     }
 }
 
+// Whether any row of a panel was exchanged (one wave, lane per row): most
+// panels of these systems pivot on their diagonal, and the serial replay
+// (one dependent pivot load per row) is then skipped.
+__device__ __forceinline__ bool panel_pivots(const int* piv, int k0, int nb, int lane) {
+    const bool sw = lane < nb && piv[k0 + lane] != k0 + lane;
+    return __ballot(sw) != 0;
+}
+
 // One workgroup per matrix; x (complex128, length N) lives in LDS.  Factors
 // are column-major (entry (r, c) at c*N + r); linv blocks hold the inverses
 // of the diagonal blocks (column-major 64x64).
@@ -77,7 +85,9 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
     for (int p = 0; p < np; ++p) {
         const int k0 = p * NB;
         const int nb = min(NB, N - k0);
-        if (tid == 0 && (p & 1) == 0) replay_pivots(xs, piv, k0, nb);
+        if (wid == 0 && (p & 1) == 0 && panel_pivots(piv, k0, nb, lane)) {
+            if (lane == 0) replay_pivots(xs, piv, k0, nb);
+        }
         __syncthreads();
         const cpx<T>* D = Lb + (int64_t)p * NB * NB;
         if constexpr (WIDE) {
@@ -114,31 +124,53 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
             __syncthreads();
         }
         if ((p & 1) == 0 && p + 1 < np) {
-            if (tid == 0) replay_pivots(xs, piv, k0 + NB, min(NB, N - k0 - NB));
+            const int nb2 = min(NB, N - k0 - NB);
+            if (wid == 0 && panel_pivots(piv, k0 + NB, nb2, lane)) {
+                if (lane == 0) replay_pivots(xs, piv, k0 + NB, nb2);
+            }
             __syncthreads();
         }
-        for (int i = k0 + nb + tid; i < N; i += TH) {
+        // rows below: RP rows per thread and pass, eight columns each (FP32
+        // factors: two rows, sixteen 8-byte loads in flight; FP64: one row)
+        constexpr int RP = sizeof(T) == 4 ? 2 : 1;
+        for (int i = k0 + nb + tid; i < N; i += RP * TH) {
             const cpx<T>* Li = LU + (int64_t)k0 * N + i;
-            // eight independent partial sums: eight loads in flight per thread
-            zd s8[8];
+            bool live[RP];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s8[u] = cmk(0.0, 0.0);
+            for (int rr = 0; rr < RP; ++rr) live[rr] = i + rr * TH < N;
+            zd sa[RP][4];
+#pragma unroll
+            for (int rr = 0; rr < RP; ++rr)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sa[rr][u] = cmk(0.0, 0.0);
             int c = 0;
             for (; c + 8 <= nb; c += 8) {
-                cpx<T> l8[8];
+                cpx<T> la[RP][8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) l8[u] = ld_maybe_stream<!WIDE>(&Li[(int64_t)(c + u) * N]);
+                for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s8[u] = cfma(s8[u], cmk((double)l8[u].re, (double)l8[u].im), xs[k0 + c + u]);
+                    for (int rr = 0; rr < RP; ++rr)
+                        la[rr][u] = live[rr] ? ld_maybe_stream<!WIDE>(&Li[(int64_t)(c + u) * N + rr * TH])
+                                             : cmk((T)0, (T)0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const zd xc = xs[k0 + c + u];
+#pragma unroll
+                    for (int rr = 0; rr < RP; ++rr)
+                        sa[rr][u & 3] = cfma(sa[rr][u & 3], cmk((double)la[rr][u].re, (double)la[rr][u].im), xc);
+                }
             }
             for (; c < nb; ++c) {
-                const cpx<T> l = ld_maybe_stream<!WIDE>(&Li[(int64_t)c * N]);
-                s8[0] = cfma(s8[0], cmk((double)l.re, (double)l.im), xs[k0 + c]);
-            }
-            zd s = s8[0];
 #pragma unroll
-            for (int u = 1; u < 8; ++u) s = cadd(s, s8[u]);
-            xs[i] = csub(xs[i], s);
+                for (int rr = 0; rr < RP; ++rr) {
+                    const cpx<T> l = live[rr] ? ld_maybe_stream<!WIDE>(&Li[(int64_t)c * N + rr * TH]) : cmk((T)0, (T)0);
+                    sa[rr][0] = cfma(sa[rr][0], cmk((double)l.re, (double)l.im), xs[k0 + c]);
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < RP; ++rr)
+                if (live[rr])
+                    xs[i + rr * TH] = csub(xs[i + rr * TH], cadd(cadd(sa[rr][0], sa[rr][1]), cadd(sa[rr][2], sa[rr][3])));
         }
         __syncthreads();
     }
@@ -151,17 +183,18 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
         if (lane < nb) {
             const cpx<T>* Ur = LU + k0 + lane;
             constexpr int NW = TH / 64;
-            // four independent partial sums per lane: four loads in flight
+            // four independent partial sums per lane, eight loads in flight
             zd s4[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) s4[u] = cmk(0.0, 0.0);
             int c = c0 + wid;
-            for (; c + 3 * NW < N; c += 4 * NW) {
-                cpx<T> u4[4];
+            for (; c + 7 * NW < N; c += 8 * NW) {
+                cpx<T> u8[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) u4[u] = ld_maybe_stream<!WIDE>(&Ur[(int64_t)(c + u * NW) * N]);
+                for (int u = 0; u < 8; ++u) u8[u] = ld_maybe_stream<!WIDE>(&Ur[(int64_t)(c + u * NW) * N]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s4[u] = cfma(s4[u], cmk((double)u4[u].re, (double)u4[u].im), xs[c + u * NW]);
+                for (int u = 0; u < 8; ++u)
+                    s4[u & 3] = cfma(s4[u & 3], cmk((double)u8[u].re, (double)u8[u].im), xs[c + u * NW]);
             }
             for (; c < N; c += NW) {
                 const cpx<T> u = ld_maybe_stream<!WIDE>(&Ur[(int64_t)c * N]);
