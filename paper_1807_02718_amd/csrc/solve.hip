@@ -326,7 +326,9 @@ __global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict_
     for (int p = 0; p < np; ++p) {
         const int k0 = p * NB;
         const int nb = min(NB, N - k0);
-        if (tid < NV && (p & 1) == 0) replay_pivots(xs + tid * ldx, piv, k0, nb);
+        if (wid == 0 && (p & 1) == 0 && panel_pivots(piv, k0, nb, lane)) {
+            if (tid < NV) replay_pivots(xs + tid * ldx, piv, k0, nb);
+        }
         __syncthreads();
         const cpx<T>* D = Lb + (int64_t)p * NB * NB;
         {
@@ -352,7 +354,10 @@ __global__ __launch_bounds__(SM_TH) void k_lu_solve_multi(const int* __restrict_
             __syncthreads();
         }
         if ((p & 1) == 0 && p + 1 < np) {
-            if (tid < NV) replay_pivots(xs + tid * ldx, piv, k0 + NB, min(NB, N - k0 - NB));
+            const int nb2 = min(NB, N - k0 - NB);
+            if (wid == 0 && panel_pivots(piv, k0 + NB, nb2, lane)) {
+                if (tid < NV) replay_pivots(xs + tid * ldx, piv, k0 + NB, nb2);
+            }
             __syncthreads();
         }
         for (int i = k0 + nb + tid; i < N; i += SM_TH) {
