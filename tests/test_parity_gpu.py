@@ -159,6 +159,43 @@ def test_lu_random_fp32(ctx):
         assert relmax(xs, ref) < 3e-7 * np.linalg.cond(A), n
 
 
+def test_lu_random_wide_batch_pivoting(ctx):
+    """More than 256 matrices (the 256-thread panels and solves of large
+    batches), random and so pivoting in most columns, ragged orders across
+    several panels: the solves' pivot replays run with real exchanges (the
+    BIE systems of the other large-batch tests rarely exchange rows).  FP64
+    against LAPACK with its pivots, FP32 factors against the FP32-rounded
+    matrices."""
+    from scipy import linalg
+    rng = np.random.default_rng(23)
+    Ns = [int(n) for n in rng.integers(60, 200, size=300)]
+    say("lu wide batch pivoting", len(Ns), min(Ns), max(Ns))
+    mats, rhs, flat, b = _rand_batch(Ns, seed=29)
+    fac = ctx.lu_factor(flat, Ns)
+    x = ctx.lu_solve(fac, b).cpu().numpy()
+    piv = fac["piv"].cpu().numpy()
+    o = 0
+    moved = 0
+    for q, (A, g, n) in enumerate(zip(mats, rhs, Ns)):
+        xs = x[o:o + n]
+        ref, _ = O.solve_density(A, g)
+        assert relmax(xs, ref) < 1e-15 * np.linalg.cond(A) * n + 1e-13, (q, n)
+        if q % 25 == 0:
+            _, p_ref = linalg.lu_factor(A)
+            assert np.array_equal(piv[o:o + n], p_ref), (q, n)
+        moved += int(np.count_nonzero(piv[o:o + n] != np.arange(n)))
+        o += n
+    assert moved > sum(Ns) // 2   # the replays really exchange rows
+    mats32, rhs32, flat32, b32 = _rand_batch(Ns, seed=31, dtype=torch.complex64)
+    fac32 = ctx.lu_factor(flat32, Ns, precision="fp32_refine")
+    x32 = ctx.lu_solve(fac32, b32).cpu().numpy()
+    o = 0
+    for q, (A, g, n) in enumerate(zip(mats32, rhs32, Ns)):
+        ref = np.linalg.solve(A.astype(np.complex64).astype(np.complex128), g)
+        assert relmax(x32[o:o + n], ref) < 3e-7 * np.linalg.cond(A), (q, n)
+        o += n
+
+
 def test_lu_singular_reports(ctx, fhw):
     say("lu singular")
     flat = torch.zeros(64 * 64, dtype=torch.complex128, device="cuda")
