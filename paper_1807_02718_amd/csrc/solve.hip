@@ -130,9 +130,15 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
             }
             __syncthreads();
         }
-        // rows below: RP rows per thread and pass, eight columns each (FP32
-        // factors: two rows, sixteen 8-byte loads in flight; FP64: one row)
-        constexpr int RP = sizeof(T) == 4 ? 2 : 1;
+        // rows below: RP rows per thread and pass.  Large batches: eight
+        // columns per round trip (FP32 factors: two rows, sixteen 8-byte
+        // loads in flight; FP64: one row).  A lone matrix on its CU is bound
+        // by the round trips of this sweep, not by bytes: one row per thread
+        // with CH = 16 columns per round trip, then the eight-column steps
+        // and the tail as before, so each column meets the same partial sum
+        // in the same order either way
+        constexpr int RP = (sizeof(T) == 4 && !WIDE) ? 2 : 1;
+        constexpr int CH = WIDE ? 16 : 8;
         for (int i = k0 + nb + tid; i < N; i += RP * TH) {
             const cpx<T>* Li = LU + (int64_t)k0 * N + i;
             bool live[RP];
@@ -144,6 +150,16 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
 #pragma unroll
                 for (int u = 0; u < 4; ++u) sa[rr][u] = cmk(0.0, 0.0);
             int c = 0;
+            if constexpr (CH > 8) {
+                for (; c + CH <= nb; c += CH) {
+                    cpx<T> lw[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) lw[u] = Li[(int64_t)(c + u) * N];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u)
+                        sa[0][u & 3] = cfma(sa[0][u & 3], cmk((double)lw[u].re, (double)lw[u].im), xs[k0 + c + u]);
+                }
+            }
             for (; c + 8 <= nb; c += 8) {
                 cpx<T> la[RP][8];
 #pragma unroll
