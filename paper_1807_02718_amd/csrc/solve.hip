@@ -133,12 +133,13 @@ __global__ __launch_bounds__(TH) void k_lu_solve(const int* __restrict__ Ns,
         // rows below: RP rows per thread and pass.  Large batches: eight
         // columns per round trip (FP32 factors: two rows, sixteen 8-byte
         // loads in flight; FP64: one row).  A lone matrix on its CU is bound
-        // by the round trips of this sweep, not by bytes: one row per thread
-        // with CH = 16 columns per round trip, then the eight-column steps
-        // and the tail as before, so each column meets the same partial sum
-        // in the same order either way
+        // by the round trips of this sweep, not by bytes: with FP32 factors,
+        // one row per thread and CH = 16 columns per round trip, then the
+        // eight-column steps and the tail as before, so each column meets the
+        // same partial sum in the same order either way (FP64 factors keep
+        // eight: sixteen measured slower there, with more register pressure)
         constexpr int RP = (sizeof(T) == 4 && !WIDE) ? 2 : 1;
-        constexpr int CH = WIDE ? 16 : 8;
+        constexpr int CH = (WIDE && sizeof(T) == 4) ? 16 : 8;
         for (int i = k0 + nb + tid; i < N; i += RP * TH) {
             const cpx<T>* Li = LU + (int64_t)k0 * N + i;
             bool live[RP];
